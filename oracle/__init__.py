@@ -1,0 +1,227 @@
+"""RASTER CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+ctypes wrapper around ``raster_oracle.cpp``, a plain single-threaded
+implementation of Algorithm 1 of the RASTER paper (contraction, then
+agglomeration) with the chunked input of Section 3.6.  Only the tests, the
+package smoke check and the benchmark's CPU-baseline leg may import this
+module; the product library neither imports nor links it, and they share no
+code.
+
+Results come back as numpy arrays sorted by tile: ``kx``, ``ky`` (int64),
+``count`` (uint64) and the label tile ``label_x``, ``label_y`` (the
+lexicographically smallest tile of the cluster).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "raster_oracle.cpp")
+_DEFAULT_LIB = os.path.join(_HERE, "liboracle.so")
+# A test may point the wrapper at a deliberately broken build of the oracle
+# (see tests/test_oracle_mutants.py) to show that the pins catch the mistake.
+_LIB = os.environ.get("RASTER_ORACLE_LIB") or _DEFAULT_LIB
+
+OK, E_INVAL, E_RANGE, E_STATE = 0, -1, -2, -5
+F32, F64 = 1, 2
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (-O2, no FMA contraction, no fast-math)."""
+    if force or not os.path.exists(_DEFAULT_LIB):
+        compile_oracle(_SRC, _DEFAULT_LIB)
+    return _DEFAULT_LIB
+
+
+def compile_oracle(src: str, out: str) -> str:
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off",
+                           "-fno-fast-math", "-fPIC", "-shared", "-o", tmp, src])
+    os.replace(tmp, out)
+    return out
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    vp, i64, i32, u64, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
+    lib.oracle_scale_for_precision.argtypes = [i32]
+    lib.oracle_scale_for_precision.restype = dbl
+    lib.oracle_project.argtypes = [vp, i64, i32, dbl, vp, vp]
+    lib.oracle_project.restype = ctypes.c_int
+    lib.oracle_begin.argtypes = [dbl, u64, u64]
+    lib.oracle_begin.restype = vp
+    lib.oracle_feed.argtypes = [vp, vp, i64, i32]
+    lib.oracle_feed.restype = ctypes.c_int
+    lib.oracle_num_tiles.argtypes = [vp]
+    lib.oracle_num_tiles.restype = i64
+    lib.oracle_tile_counts.argtypes = [vp, vp, vp, vp]
+    lib.oracle_tile_counts.restype = ctypes.c_int
+    lib.oracle_finish.argtypes = [vp]
+    lib.oracle_finish.restype = ctypes.c_int
+    lib.oracle_stats.argtypes = [vp, vp]
+    lib.oracle_stats.restype = ctypes.c_int
+    lib.oracle_result.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.oracle_result.restype = ctypes.c_int
+    lib.oracle_free.argtypes = [vp]
+    lib.oracle_free.restype = None
+    _lib = lib
+    return lib
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: oracle status {code}")
+        self.code = code
+
+
+def scale_for_precision(p: int) -> float:
+    return float(_load().oracle_scale_for_precision(int(p)))
+
+
+def _as_points(points):
+    a = np.asarray(points)
+    if a.dtype == np.float32:
+        dt = F32
+    else:
+        a = a.astype(np.float64, copy=False)
+        dt = F64
+    a = np.ascontiguousarray(a.reshape(-1, 2))
+    return a, dt
+
+
+def project(points, scale: float):
+    """Tile coordinates (kx, ky) of every point (Section 3.2)."""
+    a, dt = _as_points(points)
+    n = a.shape[0]
+    kx = np.empty(n, np.int64)
+    ky = np.empty(n, np.int64)
+    rc = _load().oracle_project(a.ctypes.data, n, dt, float(scale), kx.ctypes.data, ky.ctypes.data)
+    if rc != OK:
+        raise OracleError(rc, "project")
+    return kx, ky
+
+
+@dataclass
+class OracleResult:
+    kx: np.ndarray
+    ky: np.ndarray
+    count: np.ndarray
+    label_x: np.ndarray
+    label_y: np.ndarray
+    stats: dict = field(default_factory=dict)
+
+    @property
+    def num_tiles(self) -> int:
+        return int(self.kx.shape[0])
+
+    @property
+    def num_clusters(self) -> int:
+        return int(self.stats.get("clusters", 0))
+
+
+class OracleStream:
+    """Chunked contraction (Section 3.6) followed by one agglomeration."""
+
+    def __init__(self, scale: float, tau: int, mu: int):
+        self._lib = _load()
+        self._h = self._lib.oracle_begin(float(scale), int(tau), int(mu))
+        if not self._h:
+            raise OracleError(E_INVAL, "begin")
+
+    def feed(self, points) -> None:
+        a, dt = _as_points(points)
+        rc = self._lib.oracle_feed(self._h, a.ctypes.data, a.shape[0], dt)
+        if rc != OK:
+            raise OracleError(rc, "feed")
+
+    def num_tiles(self) -> int:
+        return int(self._lib.oracle_num_tiles(self._h))
+
+    def tile_counts(self):
+        """All (kx, ky, count) of the accumulator, sorted by tile."""
+        m = self.num_tiles()
+        kx = np.empty(m, np.int64)
+        ky = np.empty(m, np.int64)
+        c = np.empty(m, np.uint64)
+        rc = self._lib.oracle_tile_counts(self._h, kx.ctypes.data, ky.ctypes.data, c.ctypes.data)
+        if rc != OK:
+            raise OracleError(rc, "tile_counts")
+        return kx, ky, c
+
+    def stats(self) -> dict:
+        st = np.zeros(7, np.int64)
+        self._lib.oracle_stats(self._h, st.ctypes.data)
+        return dict(n=int(st[0]), distinct=int(st[1]), significant=int(st[2]),
+                    components=int(st[3]), clusters=int(st[4]), tiles=int(st[5]),
+                    failed=bool(st[6]))
+
+    def finish(self) -> OracleResult:
+        rc = self._lib.oracle_finish(self._h)
+        if rc != OK:
+            raise OracleError(rc, "finish")
+        st = self.stats()
+        t = st["tiles"]
+        kx = np.empty(t, np.int64)
+        ky = np.empty(t, np.int64)
+        c = np.empty(t, np.uint64)
+        lx = np.empty(t, np.int64)
+        ly = np.empty(t, np.int64)
+        rc = self._lib.oracle_result(self._h, kx.ctypes.data, ky.ctypes.data, c.ctypes.data,
+                                     lx.ctypes.data, ly.ctypes.data)
+        if rc != OK:
+            raise OracleError(rc, "result")
+        return OracleResult(kx, ky, c, lx, ly, st)
+
+    def close(self) -> None:
+        if self._h:
+            self._lib.oracle_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _scale(precision, scale):
+    if scale is None:
+        if precision is None:
+            raise ValueError("give precision or scale")
+        return scale_for_precision(precision)
+    return float(scale)
+
+
+def cluster(points, tau: int, mu: int, precision: int | None = None,
+            scale: float | None = None) -> OracleResult:
+    """RASTER on one in-memory point set."""
+    st = OracleStream(_scale(precision, scale), tau, mu)
+    try:
+        st.feed(points)
+        return st.finish()
+    finally:
+        st.close()
+
+
+def cluster_chunks(chunks, tau: int, mu: int, precision: int | None = None,
+                   scale: float | None = None) -> OracleResult:
+    """RASTER over an iterable of point chunks (Section 3.6)."""
+    st = OracleStream(_scale(precision, scale), tau, mu)
+    try:
+        for c in chunks:
+            st.feed(c)
+        return st.finish()
+    finally:
+        st.close()

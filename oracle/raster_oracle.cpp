@@ -1,0 +1,282 @@
+// RASTER CPU oracle -- TEST INFRASTRUCTURE ONLY.
+//
+// A plain, slow, single-threaded implementation of contraction clustering
+// (Ulm et al., "Contraction Clustering (RASTER)", Algorithm 1 with Section 3.2
+// for the projection and Section 3.6 for chunked input).  It exists to check
+// the GPU path, and only the test suite, the package smoke check and the
+// benchmark's CPU-baseline leg may load it.  The product library never links
+// or calls it, and the two share no source: this file has its own projection,
+// its own tile representation (a pair of signed 64-bit integers rather than a
+// packed 64-bit key), its own std::unordered_map accumulator and a stack-based
+// depth-first agglomeration in the order Algorithm 1 gives.
+//
+// Readings taken where the paper is silent or loose (each also listed in the
+// design notes):
+//   * project(x, y) = (trunc(fl(x*s)), trunc(fl(y*s))): one IEEE-754 binary64
+//     product, rounded to nearest, truncated toward zero (Section 3.2 speaks of
+//     truncating, and of scaling up and converting to integers).  FP32 input is
+//     widened to binary64 exactly before the product.
+//   * A point whose product is not finite or whose magnitude is at least
+//     2^31 - 1 is a range error (tile coordinates must fit |k| <= 2^31 - 2);
+//     the whole chunk is then rejected and the stream fails.
+//   * Significant means count >= tau (Algorithm 1 removes tiles whose count is
+//     below tau).  tau = 0 and mu = 0 are invalid arguments.
+//   * neighbors(u, delta) is the Chebyshev-1 neighbourhood (Section 3.2: all
+//     eight adjacent tiles); only significant tiles are taken into a cluster.
+//   * A cluster is kept when it holds at least mu tiles.
+//   * Each kept tile is reported with its count and the lexicographically
+//     smallest (kx, ky) of its cluster as the cluster's label; output is sorted
+//     by (kx, ky).
+//
+// Build: g++ -O2 -ffp-contract=off -fPIC -shared (no fast-math).
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <unordered_map>
+#include <unordered_set>
+#include <utility>
+#include <vector>
+
+namespace {
+
+constexpr int kOK = 0;
+constexpr int kInval = -1;
+constexpr int kRange = -2;
+constexpr int kState = -5;
+
+struct Tile {
+    int64_t x, y;
+    bool operator==(const Tile& o) const { return x == o.x && y == o.y; }
+    bool operator<(const Tile& o) const { return x < o.x || (x == o.x && y < o.y); }
+};
+
+struct TileHash {
+    size_t operator()(const Tile& t) const {
+        // std::hash of each coordinate, combined; any hash gives the same result.
+        size_t a = std::hash<int64_t>()(t.x);
+        size_t b = std::hash<int64_t>()(t.y);
+        return a ^ (b + 0x9e3779b97f4a7c15ULL + (a << 6) + (a >> 2));
+    }
+};
+
+// Section 3.2: scale the coordinate and truncate it to an integer.
+int project_coord(double v, double scale, int64_t* k) {
+    double p = v * scale;
+    if (!(std::fabs(p) < 2147483647.0)) return kRange;  // also rejects NaN and Inf
+    *k = (int64_t)std::trunc(p);
+    return kOK;
+}
+
+struct OracleStream {
+    double scale;
+    uint64_t tau, mu;
+    bool failed = false;
+    bool finished = false;
+    uint64_t n_points = 0;
+    // acc: tile -> number of points projected onto it (Algorithm 1, contraction).
+    std::unordered_map<Tile, uint64_t, TileHash> acc;
+    // results filled by finish()
+    uint64_t distinct = 0, significant = 0, components = 0, clusters = 0;
+    std::vector<Tile> out_tile;
+    std::vector<uint64_t> out_count;
+    std::vector<Tile> out_label;
+};
+
+double point_coord(const void* pts, int dtype, int64_t i, int c) {
+    if (dtype == 1) return (double)((const float*)pts)[2 * i + c];
+    return ((const double*)pts)[2 * i + c];
+}
+
+}  // namespace
+
+extern "C" {
+
+// s = 10^p for an integer precision p in [0, 15]; every intermediate is an
+// integer below 2^53, so the product is exact.
+double oracle_scale_for_precision(int32_t p) {
+    double s = 1.0;
+    for (int i = 0; i < p; ++i) s *= 10.0;
+    return s;
+}
+
+// Projection alone, for pinning the tile keys: writes kx[i], ky[i].
+// dtype: 1 = float32 pairs, 2 = float64 pairs (row-major (n, 2)).
+int oracle_project(const void* pts, int64_t n, int32_t dtype, double scale,
+                   int64_t* kx, int64_t* ky) {
+    if (n < 0 || (dtype != 1 && dtype != 2) || (n > 0 && (!pts || !kx || !ky))) return kInval;
+    for (int64_t i = 0; i < n; ++i) {
+        if (project_coord(point_coord(pts, dtype, i, 0), scale, &kx[i]) != kOK) return kRange;
+        if (project_coord(point_coord(pts, dtype, i, 1), scale, &ky[i]) != kOK) return kRange;
+    }
+    return kOK;
+}
+
+void* oracle_begin(double scale, uint64_t tau, uint64_t mu) {
+    if (!(scale > 0.0) || !std::isfinite(scale) || tau == 0 || mu == 0) return nullptr;
+    OracleStream* s = new OracleStream();
+    s->scale = scale;
+    s->tau = tau;
+    s->mu = mu;
+    return s;
+}
+
+// Contraction over one chunk of points (Algorithm 1, first loop).  Chunks may
+// come in any number and order (Section 3.6).  The chunk is checked first, so a
+// range error leaves the accumulator untouched and marks the stream failed.
+int oracle_feed(void* h, const void* pts, int64_t n, int32_t dtype) {
+    OracleStream* s = (OracleStream*)h;
+    if (!s) return kInval;
+    if (s->failed || s->finished) return kState;
+    if (n < 0 || (dtype != 1 && dtype != 2) || (n > 0 && !pts)) return kInval;
+    std::vector<Tile> keys((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        Tile t;
+        if (project_coord(point_coord(pts, dtype, i, 0), s->scale, &t.x) != kOK ||
+            project_coord(point_coord(pts, dtype, i, 1), s->scale, &t.y) != kOK) {
+            s->failed = true;
+            return kRange;
+        }
+        keys[(size_t)i] = t;
+    }
+    for (const Tile& t : keys) {
+        auto it = s->acc.find(t);
+        if (it == s->acc.end()) s->acc.emplace(t, 1);
+        else it->second += 1;
+    }
+    s->n_points += (uint64_t)n;
+    return kOK;
+}
+
+// Number of distinct tiles seen so far (before the significance filter).
+int64_t oracle_num_tiles(void* h) {
+    OracleStream* s = (OracleStream*)h;
+    return s ? (int64_t)s->acc.size() : -1;
+}
+
+// Every (kx, ky, count) of the accumulator, sorted by (kx, ky); call before
+// finish().  Arrays must hold oracle_num_tiles() entries.
+int oracle_tile_counts(void* h, int64_t* kx, int64_t* ky, uint64_t* count) {
+    OracleStream* s = (OracleStream*)h;
+    if (!s) return kInval;
+    if (s->finished) return kState;
+    std::vector<std::pair<Tile, uint64_t>> all(s->acc.begin(), s->acc.end());
+    std::sort(all.begin(), all.end(),
+              [](const std::pair<Tile, uint64_t>& a, const std::pair<Tile, uint64_t>& b) {
+                  return a.first < b.first;
+              });
+    for (size_t i = 0; i < all.size(); ++i) {
+        kx[i] = all[i].first.x;
+        ky[i] = all[i].first.y;
+        count[i] = all[i].second;
+    }
+    return kOK;
+}
+
+// Significance filter and agglomeration (Algorithm 1, second loop and the
+// while-loop), then the mu filter.
+int oracle_finish(void* h) {
+    OracleStream* s = (OracleStream*)h;
+    if (!s) return kInval;
+    if (s->failed || s->finished) return kState;
+    s->finished = true;
+    s->distinct = s->acc.size();
+
+    // Remove every tile whose count is below tau.
+    for (auto it = s->acc.begin(); it != s->acc.end();) {
+        if (it->second < s->tau) it = s->acc.erase(it);
+        else ++it;
+    }
+    s->significant = s->acc.size();
+
+    // sigma := keys of acc (the significant tiles).
+    std::unordered_set<Tile, TileHash> sigma;
+    sigma.reserve(s->acc.size());
+    for (const auto& kv : s->acc) sigma.insert(kv.first);
+
+    std::vector<std::vector<Tile>> kept;
+    while (!sigma.empty()) {
+        Tile t = *sigma.begin();
+        sigma.erase(sigma.begin());
+        std::vector<Tile> cluster;
+        std::vector<Tile> visit{t};
+        while (!visit.empty()) {
+            Tile u = visit.back();
+            visit.pop_back();
+            cluster.push_back(u);
+            // ns = neighbours of u that are still in sigma; drop them from
+            // sigma and queue them for the visit.
+            for (int64_t dx = -1; dx <= 1; ++dx) {
+                for (int64_t dy = -1; dy <= 1; ++dy) {
+                    if (dx == 0 && dy == 0) continue;
+                    Tile v{u.x + dx, u.y + dy};
+                    auto it = sigma.find(v);
+                    if (it != sigma.end()) {
+                        sigma.erase(it);
+                        visit.push_back(v);
+                    }
+                }
+            }
+        }
+        s->components += 1;
+        if (cluster.size() >= s->mu) kept.push_back(std::move(cluster));
+    }
+    s->clusters = kept.size();
+
+    std::vector<std::pair<Tile, Tile>> rows;  // (tile, label)
+    for (const auto& c : kept) {
+        Tile lab = c[0];
+        for (const Tile& t : c)
+            if (t < lab) lab = t;
+        for (const Tile& t : c) rows.emplace_back(t, lab);
+    }
+    std::sort(rows.begin(), rows.end(),
+              [](const std::pair<Tile, Tile>& a, const std::pair<Tile, Tile>& b) {
+                  return a.first < b.first;
+              });
+    s->out_tile.resize(rows.size());
+    s->out_label.resize(rows.size());
+    s->out_count.resize(rows.size());
+    for (size_t i = 0; i < rows.size(); ++i) {
+        s->out_tile[i] = rows[i].first;
+        s->out_label[i] = rows[i].second;
+        s->out_count[i] = s->acc.at(rows[i].first);
+    }
+    return kOK;
+}
+
+// stats[0..6] = n points, distinct tiles, significant tiles, components of the
+// significant tiles, kept clusters, output tiles, failed flag.
+int oracle_stats(void* h, int64_t* stats) {
+    OracleStream* s = (OracleStream*)h;
+    if (!s) return kInval;
+    stats[0] = (int64_t)s->n_points;
+    stats[1] = (int64_t)(s->finished ? s->distinct : s->acc.size());
+    stats[2] = (int64_t)s->significant;
+    stats[3] = (int64_t)s->components;
+    stats[4] = (int64_t)s->clusters;
+    stats[5] = (int64_t)s->out_tile.size();
+    stats[6] = s->failed ? 1 : 0;
+    return kOK;
+}
+
+// Output rows after finish(): tile, count and label tile, sorted by tile.
+int oracle_result(void* h, int64_t* kx, int64_t* ky, uint64_t* count,
+                  int64_t* label_x, int64_t* label_y) {
+    OracleStream* s = (OracleStream*)h;
+    if (!s) return kInval;
+    if (!s->finished) return kState;
+    for (size_t i = 0; i < s->out_tile.size(); ++i) {
+        kx[i] = s->out_tile[i].x;
+        ky[i] = s->out_tile[i].y;
+        count[i] = s->out_count[i];
+        label_x[i] = s->out_label[i].x;
+        label_y[i] = s->out_label[i].y;
+    }
+    return kOK;
+}
+
+void oracle_free(void* h) { delete (OracleStream*)h; }
+
+}  // extern "C"
