@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""RASTER benchmark on one MI355X.
+
+One step = the whole hot path over one batch of synthetic input: begin a
+stream, feed the paper-scale workload (500M FP64 points, 1M centres in
+[0, 10000]^2, sigma 0.01, precision 2, tau 5, mu 4) as ten resident 50M-point
+chunks, finish (significance scan, union-find agglomeration, mu filter).
+
+Prints one JSON line with points/s, the counting kernel's roofline (HIP-event
+duration per launch against the 8 TB/s HBM peak, algorithmic bytes = 16 bytes
+of FP64 coordinates per point) and the CPU oracle timed on a bounded sample
+of the same workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "points/s + HBM GB/s at 500M pts; batched/served vs plain, p50/p99 latency"
+HBM_PEAK_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "count_kernel_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1907_03620_amd", "csrc", "raster_kernels.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(per_launch_points: int):
+    """HBM bytes per counting launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    if int(kv.get("points_per_launch", -1)) != per_launch_points:
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
+def gen_paper_scale(n_chunks: int, chunk: int):
+    import synth
+    centres = synth.paper_scale_centres(3)
+    with ThreadPoolExecutor(min(16, n_chunks)) as ex:
+        return list(ex.map(lambda c: synth.paper_scale_chunk(c, centres=centres, chunk=chunk,
+                                                             n_chunks=n_chunks), range(n_chunks)))
+
+
+def cpu_baseline(host_chunks, strip: float, precision: int, tau: int, mu: int):
+    """Times the oracle, single-threaded and pinned to one core, on the points
+    of every chunk whose x lies in [0, strip): a strip of the canvas with the
+    full workload's density."""
+    import numpy as np
+    import oracle
+    sample = np.concatenate([h[h[:, 0] < strip] for h in host_chunks])
+    try:
+        cpu = sorted(os.sched_getaffinity(0))[0]
+        os.sched_setaffinity(0, {cpu})
+    except (AttributeError, OSError):
+        pass
+    t0 = time.perf_counter()
+    res = oracle.cluster(sample, tau=tau, mu=mu, precision=precision)
+    dt = time.perf_counter() - t0
+    try:
+        os.sched_setaffinity(0, set(range(os.cpu_count() or 1)))
+    except (AttributeError, OSError):
+        pass
+    return dict(value=sample.shape[0] / dt, unit="points/s", cores=1, kind="oracle",
+                sample=(f"x in [0, {strip:g}) strip of all chunks: {sample.shape[0]} points "
+                        f"({res.stats['clusters']} clusters), full Algorithm 1, {dt:.1f} s"),
+                seconds=dt, points=int(sample.shape[0]))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--chunks", type=int, default=10)
+    ap.add_argument("--chunk", type=int, default=50_000_000)
+    ap.add_argument("--tile-hint", type=int, default=0,
+                    help="expected distinct tiles passed to raster_begin (0: let the table grow)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-strip", type=float, default=400.0)
+    ap.add_argument("--tuning", default="", help="JSON object of raster_tuning fields")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the multi-GPU path is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1907_03620_amd as raster
+
+    raster.load()
+    if args.tuning:
+        raster.set_tuning(**json.loads(args.tuning))
+    precision, tau, mu = 2, 5, 4
+    n_total = args.chunks * args.chunk
+
+    log(f"generating {args.chunks} x {args.chunk} points")
+    host = gen_paper_scale(args.chunks, args.chunk)
+    dev = [torch.from_numpy(h).to("cuda") for h in host]
+    torch.cuda.synchronize()
+
+    def step():
+        st = raster.Stream(tau=tau, mu=mu, precision=precision, tile_hint=args.tile_hint)
+        for d in dev:
+            st.feed(d)
+        res = st.finish()
+        st.close()
+        return res
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        res = step()
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1000.0 * elapsed / args.steps
+    value = n_total * args.steps / elapsed
+
+    st = results[-1].stats
+    launches = sum(r.stats["count_launches"] for r in results)
+    us_kernel = sum(r.stats["us_count_kernel"] for r in results)
+    avg_us = us_kernel / max(1, launches)
+    bytes_per_launch = 16.0 * args.chunk
+    achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9
+    traffic = measured_traffic(args.chunk)
+    m, s, t = st["distinct_tiles"], st["significant_tiles"], st["tiles"]
+    alg_bytes = 16.0 * n_total + 2 * 12.0 * m + 20.0 * s + 20.0 * t
+    phases = {k: round(float(np.mean([r.stats[k] for r in results])), 1)
+              for k in ("us_contract", "us_threshold", "us_agglomerate", "us_filter")}
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"paper-scale stream: {n_total} FP64 points, 1M centres in [0,10000]^2, "
+                         f"sigma 0.01, p=2, tau=5, mu=4, {args.chunks} resident chunks of {args.chunk} "
+                         "through begin/feed_chunk/finish"),
+            "points": n_total, "chunks": args.chunks, "precision": precision, "tau": tau, "mu": mu,
+            "tile_hint": args.tile_hint, "tuning": raster.get_tuning().__dict__,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "project_count (k_count_direct)" if raster.get_tuning().preagg_slots == 0
+                      else "project_count (k_count_preagg)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": traffic,
+            "avg_launch_us": avg_us,
+            "bytes_per_launch": bytes_per_launch,
+        },
+        "hbm_gbps_algorithmic_step": alg_bytes / (ms_per_step * 1e-3) / 1e9,
+        "phases_us": phases,
+        "result": {"distinct_tiles": m, "significant_tiles": s, "clusters": st["clusters"], "tiles": t,
+                   "table_capacity": st["table_capacity"], "grow_events": st["grow_events"]},
+        "cpu_baseline": None,
+    }
+    del dev
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, one core)")
+        line["cpu_baseline"] = cpu_baseline(host, args.cpu_strip, precision, tau, mu)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * raster.h -- C ABI of the MI355X (gfx950) RASTER library.
+ *
+ * RASTER ("Contraction Clustering", Ulm et al.) clusters 2-D points in two
+ * steps (Algorithm 1):
+ *   contraction   -- project every point onto an integer tile by scaling by
+ *                    10^p and truncating (Section 3.2), count the points per
+ *                    tile, keep the tiles holding at least tau points;
+ *   agglomeration -- join significant tiles that touch (Chebyshev distance 1,
+ *                    all eight neighbours, Section 3.2) into clusters and keep
+ *                    the clusters of at least mu tiles.
+ * The input may be cut into chunks fed in any order without changing the
+ * result (Section 3.6), which the streaming calls below expose.
+ *
+ * Conventions shared by every call:
+ *   - Points are caller-owned DEVICE memory, row-major (n, 2): x then y of
+ *     each point, RASTER_F64 (16 bytes per point, 16-byte aligned) or
+ *     RASTER_F32 (8 bytes per point, 8-byte aligned).  FP32 coordinates are
+ *     widened to FP64 exactly before the product, so an FP32 point and its
+ *     FP64 widening land on the same tile.
+ *   - Tile of a point: kx = trunc(fl64(x * s)), ky = trunc(fl64(y * s)), one
+ *     IEEE binary64 product rounded to nearest, truncated toward zero.  With an
+ *     integer precision p in [0, 15], s = 10^p exactly.  A coordinate whose
+ *     product is not finite or has magnitude >= 2^31 - 1 makes the whole call
+ *     fail with RASTER_E_RANGE.
+ *   - Tile key: the 64-bit "biased key" (uint64)(kx + 2^31) << 32 |
+ *     (uint32)(ky + 2^31).  Unsigned order of keys is lexicographic (kx, ky)
+ *     order.  A cluster's label is the smallest key among its tiles.
+ *   - Significant means count >= tau (tau >= 1).  A cluster is kept when it
+ *     holds at least mu tiles (mu >= 1).
+ *   - Every call returns a raster_status; 0 is success.  On failure no
+ *     result is produced (*out stays NULL) and raster_last_error() gives a
+ *     one-line reason for the calling thread.
+ *   - Work is enqueued on the caller's HIP stream (0 = the null stream).  Calls
+ *     that return a result synchronise that stream, because output sizes depend
+ *     on the data.
+ *   - The library allocates its own device memory (tables, scratch, results);
+ *     results are owned by the library until raster_result_free().
+ */
+#ifndef RASTER_H
+#define RASTER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum raster_dtype { RASTER_F32 = 1, RASTER_F64 = 2 } raster_dtype;
+
+typedef enum raster_status {
+    RASTER_OK = 0,
+    RASTER_E_INVAL = -1,  /* bad argument: tau or mu 0, NULL pointer with n > 0,
+                             unknown dtype, misaligned points, precision outside
+                             [0, 15], non-finite or non-positive scale        */
+    RASTER_E_RANGE = -2,  /* a coordinate is NaN/Inf or its tile is out of range,
+                             or more than 2^32 - 1 points went into one table */
+    RASTER_E_NOMEM = -3,  /* device allocation failed                          */
+    RASTER_E_DEVICE = -4, /* a HIP call failed                                 */
+    RASTER_E_STATE = -5,  /* streaming call in the wrong state                 */
+    RASTER_E_BUDGET = -6  /* server: a single job exceeds the memory budget    */
+} raster_status;
+
+typedef struct raster_result raster_result; /* opaque; arrays live on the device */
+typedef struct raster_stream raster_stream; /* opaque streaming state; owns the tile table */
+typedef struct raster_server raster_server; /* opaque serving loop */
+
+/* Counters and per-phase device times of one clustering run. */
+typedef struct raster_stats {
+    int64_t n_points;          /* points counted                                  */
+    int64_t distinct_tiles;    /* m: tiles holding at least one point             */
+    int64_t significant_tiles; /* s: tiles holding at least tau points            */
+    int64_t components;        /* connected components of the significant tiles   */
+    int64_t clusters;          /* components with at least mu tiles               */
+    int64_t tiles;             /* tiles of the kept clusters (rows of the result) */
+    int64_t table_capacity;    /* slots of the device tile table                  */
+    int64_t grow_events;       /* times the table was enlarged and rehashed       */
+    float us_contract;         /* projection + counting (all chunks), microseconds */
+    float us_threshold;        /* significance scan and compaction                */
+    float us_agglomerate;      /* neighbour union-find                            */
+    float us_filter;           /* mu filter, labels and output compaction         */
+    int64_t count_launches;    /* launches of the projection + counting kernel    */
+    float us_count_kernel;     /* their summed device time, microseconds          */
+    float reserved;
+} raster_stats;
+
+/* Launch knobs of the contraction kernels.  Any value gives the same result;
+ * they trade speed only.  raster_set_tuning(NULL) restores the defaults. */
+typedef struct raster_tuning {
+    int32_t block;        /* threads per workgroup of the counting kernel: 64..1024, multiple of 64 */
+    int32_t items;        /* points per thread per sweep: 1..16                                   */
+    int32_t preagg_slots; /* LDS pre-aggregation slots per workgroup (0 = off, else power of two
+                             in [256, 4096]): duplicate tiles within a workgroup's points are
+                             combined in LDS before touching the device table               */
+    float load_factor;    /* target occupancy of the device table in (0.05, 0.9]               */
+} raster_tuning;
+
+/* ---- plain form (Algorithm 1 on one resident point set) -------------------- */
+
+/* Cluster n points with integer precision p in [0, 15] (tile side 10^-p).
+ * d_points: device pointer, borrowed until the call returns.  n may be 0. */
+raster_status raster_cluster(const void* d_points, int64_t n, raster_dtype dt, int32_t precision,
+                             uint32_t tau, uint32_t mu, hipStream_t stream, raster_result** out);
+
+/* Same with an arbitrary positive finite scale s (tile side 1/s), e.g.
+ * s = 10^3.5 for the paper's non-integer precisions (Section 3.2). */
+raster_status raster_cluster_scaled(const void* d_points, int64_t n, raster_dtype dt, double scale,
+                                    uint32_t tau, uint32_t mu, hipStream_t stream,
+                                    raster_result** out);
+
+/* ---- results --------------------------------------------------------------- */
+
+int64_t raster_result_num_tiles(const raster_result* r);    /* rows t, or -1 if r is NULL */
+int64_t raster_result_num_clusters(const raster_result* r); /* kept clusters, or -1      */
+/* Borrowed device arrays of t rows each: tile kx, ky, its point count and its
+ * cluster label (biased key of the cluster's smallest tile).  Rows are in no
+ * particular order; any NULL out-pointer is skipped.  Valid until the free. */
+raster_status raster_result_arrays(const raster_result* r, const int32_t** d_kx,
+                                   const int32_t** d_ky, const uint32_t** d_count,
+                                   const uint64_t** d_label);
+/* Copy the t rows into caller-owned device buffers (each of at least t
+ * elements; NULL skips an array), enqueued on `stream` without waiting. */
+raster_status raster_result_copy(const raster_result* r, int32_t* d_kx, int32_t* d_ky, uint32_t* d_count,
+                                 uint64_t* d_label, hipStream_t stream);
+raster_status raster_result_stats(const raster_result* r, raster_stats* out);
+void raster_result_free(raster_result* r);
+
+/* ---- streaming form (chunked input, Section 3.6) ---------------------------- */
+
+/* Start a stream.  tile_hint: expected number of distinct tiles (0 = unknown);
+ * the table grows by rehashing when it fills, so the hint only saves time.
+ * The stream owns one device tile table for its whole life (constant memory). */
+raster_status raster_begin(int32_t precision, uint32_t tau, uint32_t mu, int64_t tile_hint,
+                           hipStream_t stream, raster_stream** st);
+raster_status raster_begin_scaled(double scale, uint32_t tau, uint32_t mu, int64_t tile_hint,
+                                  hipStream_t stream, raster_stream** st);
+/* Count one chunk.  d_points is borrowed until the stream has passed the
+ * enqueued work (the next raster_* call on this stream object, or a
+ * synchronisation of its HIP stream).  Returns without waiting for this chunk;
+ * it may wait for the previous chunk's counters to decide whether the table
+ * must grow.  A range error moves the stream to a failed state, reported by
+ * this or a later call; every later call then returns RASTER_E_STATE or the
+ * recorded error. */
+raster_status raster_feed_chunk(raster_stream* st, const void* d_points, int64_t n,
+                                raster_dtype dt);
+/* Significance filter and agglomeration over everything fed so far.  The
+ * stream is finished afterwards: further feeds return RASTER_E_STATE. */
+raster_status raster_finish(raster_stream* st, raster_result** out);
+/* Tiles counted so far (before the tau filter), for checking the contraction.
+ * Writes up to cap (key, count) pairs into caller device buffers and the true
+ * number of tiles into *m; synchronises the stream. */
+raster_status raster_stream_tiles(raster_stream* st, uint64_t* d_keys, uint32_t* d_counts,
+                                  int64_t cap, int64_t* m);
+/* Free the stream and its table; allowed in any state. */
+void raster_stream_destroy(raster_stream* st);
+
+/* ---- batched form ------------------------------------------------------------ */
+
+typedef struct raster_job {
+    const void* d_points; /* device (n, 2) array, borrowed until the call returns */
+    int64_t n;
+    raster_dtype dt;
+    int32_t precision; /* used when scale <= 0 */
+    double scale;      /* > 0: use this scale instead of 10^precision */
+    uint32_t tau, mu;
+} raster_job;
+
+/* Cluster many independent point sets together: one fused contraction over
+ * all jobs' points, then segmented threshold / agglomeration / filter passes,
+ * replayed from a captured HIP graph when the batch fits the captured shape.
+ * outs[i] receives job i's result, identical to raster_cluster on that job
+ * alone.  On failure every outs[i] is NULL. */
+raster_status raster_cluster_batch(const raster_job* jobs, int32_t n_jobs, hipStream_t stream,
+                                   raster_result** outs);
+
+/* ---- served form ------------------------------------------------------------- */
+
+/* A serving loop on its own host thread: jobs are admitted while their device
+ * memory fits budget_bytes, grouped into batches as they arrive, and run on up
+ * to max_slots HIP streams at once, so that new jobs overlap jobs already on
+ * the GPU.  Tables stay resident and are reused across jobs. */
+raster_status raster_server_create(size_t budget_bytes, int32_t max_slots, raster_server** srv);
+/* Queue a job.  Its points are borrowed until raster_server_wait returns it.
+ * Returns RASTER_E_BUDGET for a job that cannot fit the budget even alone. */
+raster_status raster_server_submit(raster_server* srv, const raster_job* job, uint64_t* ticket);
+/* Block until the job behind ticket is done; *latency_s receives submit-to-
+ * completion wall time.  Each ticket may be waited on once. */
+raster_status raster_server_wait(raster_server* srv, uint64_t ticket, raster_result** out,
+                                 double* latency_s);
+/* Drain queued work, stop the loop and release the server's memory. */
+void raster_server_destroy(raster_server* srv);
+
+/* ---- misc ------------------------------------------------------------------- */
+
+raster_status raster_set_tuning(const raster_tuning* t); /* NULL restores defaults */
+raster_status raster_get_tuning(raster_tuning* t);
+const char* raster_status_string(raster_status s);
+const char* raster_last_error(void); /* thread-local detail of the last failure */
+const char* raster_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RASTER_H */

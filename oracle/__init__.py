@@ -74,6 +74,8 @@ def _load():
     lib.oracle_stats.restype = ctypes.c_int
     lib.oracle_result.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.oracle_result.restype = ctypes.c_int
+    lib.oracle_count_tiles.argtypes = [vp, i64, i32, dbl, vp, vp, i64, vp]
+    lib.oracle_count_tiles.restype = ctypes.c_int
     lib.oracle_free.argtypes = [vp]
     lib.oracle_free.restype = None
     _lib = lib
@@ -111,6 +113,21 @@ def project(points, scale: float):
     if rc != OK:
         raise OracleError(rc, "project")
     return kx, ky
+
+
+def count_tiles(points, scale: float, qx, qy, out=None):
+    """Adds to ``out`` (uint64, one per query tile) the number of points of
+    ``points`` on each query tile (qx[i], qy[i]); returns ``out``."""
+    a, dt = _as_points(points)
+    qx = np.ascontiguousarray(qx, dtype=np.int64)
+    qy = np.ascontiguousarray(qy, dtype=np.int64)
+    if out is None:
+        out = np.zeros(qx.shape[0], np.uint64)
+    rc = _load().oracle_count_tiles(a.ctypes.data, a.shape[0], dt, float(scale), qx.ctypes.data,
+                                    qy.ctypes.data, qx.shape[0], out.ctypes.data)
+    if rc != OK:
+        raise OracleError(rc, "count_tiles")
+    return out
 
 
 @dataclass

@@ -277,6 +277,27 @@ int oracle_result(void* h, int64_t* kx, int64_t* ky, uint64_t* count,
     return kOK;
 }
 
+// Point counts of chosen tiles only: count[q] = number of points whose tile
+// (Section 3.2) is (qx[q], qy[q]).  Lets a test check single tiles of an input
+// far too large for the full accumulator.  Accumulates into `count`, so it can
+// be called once per chunk.
+int oracle_count_tiles(const void* pts, int64_t n, int32_t dtype, double scale, const int64_t* qx,
+                       const int64_t* qy, int64_t nq, uint64_t* count) {
+    if (n < 0 || nq < 0 || (dtype != 1 && dtype != 2)) return kInval;
+    std::unordered_map<Tile, int64_t, TileHash> where;
+    where.reserve((size_t)nq * 2);
+    for (int64_t q = 0; q < nq; ++q) where.emplace(Tile{qx[q], qy[q]}, q);
+    for (int64_t i = 0; i < n; ++i) {
+        Tile t;
+        if (project_coord(point_coord(pts, dtype, i, 0), scale, &t.x) != kOK ||
+            project_coord(point_coord(pts, dtype, i, 1), scale, &t.y) != kOK)
+            return kRange;
+        auto it = where.find(t);
+        if (it != where.end()) count[it->second] += 1;
+    }
+    return kOK;
+}
+
 void oracle_free(void* h) { delete (OracleStream*)h; }
 
 }  // extern "C"

@@ -1,0 +1,365 @@
+"""Python binding of the MI355X RASTER library (``libraster.so``).
+
+Argument marshalling only: every step of the clustering runs in the library's
+HIP kernels.  PyTorch supplies device memory (point tensors, output tensors)
+and the HIP stream; nothing here computes tiles, counts or clusters.
+
+    import paper_1907_03620_amd as raster
+    res = raster.cluster(points_cuda_f64, precision=2, tau=5, mu=4)
+    kx, ky, count, label = res.tensors()       # device tensors, one row per tile
+
+If the library is not built, every call raises ``RasterNotBuilt``: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+__all__ = [
+    "cluster", "Stream", "cluster_batch", "Server", "Result", "RasterError", "RasterNotBuilt",
+    "set_tuning", "get_tuning", "library_path", "load", "biased_key", "F32", "F64",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libraster.so")
+
+F32, F64 = 1, 2
+STATUS = {0: "RASTER_OK", -1: "RASTER_E_INVAL", -2: "RASTER_E_RANGE", -3: "RASTER_E_NOMEM",
+          -4: "RASTER_E_DEVICE", -5: "RASTER_E_STATE", -6: "RASTER_E_BUDGET"}
+E_INVAL, E_RANGE, E_NOMEM, E_DEVICE, E_STATE, E_BUDGET = -1, -2, -3, -4, -5, -6
+
+
+class RasterNotBuilt(RuntimeError):
+    pass
+
+
+class RasterError(RuntimeError):
+    def __init__(self, code: int, what: str, detail: str = ""):
+        super().__init__(f"{what}: {STATUS.get(code, code)}" + (f" ({detail})" if detail else ""))
+        self.code = code
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("n_points", ctypes.c_int64), ("distinct_tiles", ctypes.c_int64),
+                ("significant_tiles", ctypes.c_int64), ("components", ctypes.c_int64),
+                ("clusters", ctypes.c_int64), ("tiles", ctypes.c_int64),
+                ("table_capacity", ctypes.c_int64), ("grow_events", ctypes.c_int64),
+                ("us_contract", ctypes.c_float), ("us_threshold", ctypes.c_float),
+                ("us_agglomerate", ctypes.c_float), ("us_filter", ctypes.c_float),
+                ("count_launches", ctypes.c_int64), ("us_count_kernel", ctypes.c_float),
+                ("reserved", ctypes.c_float)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("items", ctypes.c_int32),
+                ("preagg_slots", ctypes.c_int32), ("load_factor", ctypes.c_float)]
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [("d_points", ctypes.c_void_p), ("n", ctypes.c_int64), ("dt", ctypes.c_int),
+                ("precision", ctypes.c_int32), ("scale", ctypes.c_double),
+                ("tau", ctypes.c_uint32), ("mu", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load libraster.so (raises RasterNotBuilt if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RasterNotBuilt(f"{_LIB_PATH} is missing; build it with paper_1907_03620_amd.build.build()")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i64, i32, u32, dbl, st = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
+                                  ctypes.c_double, ctypes.c_int)
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "raster_cluster": (st, [vp, i64, ctypes.c_int, i32, u32, u32, vp, pp]),
+        "raster_cluster_scaled": (st, [vp, i64, ctypes.c_int, dbl, u32, u32, vp, pp]),
+        "raster_result_num_tiles": (i64, [vp]),
+        "raster_result_num_clusters": (i64, [vp]),
+        "raster_result_arrays": (st, [vp, pp, pp, pp, pp]),
+        "raster_result_copy": (st, [vp, vp, vp, vp, vp, vp]),
+        "raster_result_stats": (st, [vp, ctypes.POINTER(_Stats)]),
+        "raster_result_free": (None, [vp]),
+        "raster_begin": (st, [i32, u32, u32, i64, vp, pp]),
+        "raster_begin_scaled": (st, [dbl, u32, u32, i64, vp, pp]),
+        "raster_feed_chunk": (st, [vp, vp, i64, ctypes.c_int]),
+        "raster_finish": (st, [vp, pp]),
+        "raster_stream_tiles": (st, [vp, vp, vp, i64, ctypes.POINTER(i64)]),
+        "raster_stream_destroy": (None, [vp]),
+        "raster_cluster_batch": (st, [ctypes.POINTER(_Job), i32, vp, pp]),
+        "raster_server_create": (st, [ctypes.c_size_t, i32, pp]),
+        "raster_server_submit": (st, [vp, ctypes.POINTER(_Job), ctypes.POINTER(ctypes.c_uint64)]),
+        "raster_server_wait": (st, [vp, ctypes.c_uint64, pp, ctypes.POINTER(dbl)]),
+        "raster_server_destroy": (None, [vp]),
+        "raster_set_tuning": (st, [ctypes.POINTER(_Tuning)]),
+        "raster_get_tuning": (st, [ctypes.POINTER(_Tuning)]),
+        "raster_status_string": (ctypes.c_char_p, [st]),
+        "raster_last_error": (ctypes.c_char_p, []),
+        "raster_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        detail = load().raster_last_error()
+        raise RasterError(rc, what, detail.decode() if detail else "")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _points(points):
+    """(pointer, n, dtype) of a CUDA tensor of shape (n, 2)."""
+    torch = _torch()
+    if not isinstance(points, torch.Tensor):
+        raise TypeError("points must be a torch tensor on the GPU")
+    if points.device.type != "cuda":
+        raise ValueError("points must be on the GPU (device memory)")
+    if points.dim() != 2 or points.shape[1] != 2:
+        raise ValueError("points must have shape (n, 2)")
+    if not points.is_contiguous():
+        raise ValueError("points must be contiguous (row-major (n, 2))")
+    if points.dtype == torch.float64:
+        dt = F64
+    elif points.dtype == torch.float32:
+        dt = F32
+    else:
+        raise ValueError("points must be float32 or float64")
+    return ctypes.c_void_p(points.data_ptr()), int(points.shape[0]), dt
+
+
+def biased_key(kx, ky):
+    """Biased 64-bit tile key of integer arrays kx, ky (numpy): (kx + 2^31) << 32 | (ky + 2^31)."""
+    import numpy as np
+    kx = np.asarray(kx, dtype=np.int64)
+    ky = np.asarray(ky, dtype=np.int64)
+    return (((kx + (1 << 31)).astype(np.uint64) << np.uint64(32)) | (ky + (1 << 31)).astype(np.uint64))
+
+
+class Result:
+    """One clustering result; the rows live in library-owned device memory."""
+
+    def __init__(self, handle: ctypes.c_void_p, stream=None):
+        self._h = handle
+        self._stream = stream
+        s = _Stats()
+        _check(load().raster_result_stats(self._h, ctypes.byref(s)), "raster_result_stats")
+        self.stats = {name: getattr(s, name) for name, _ in _Stats._fields_}
+
+    @property
+    def num_tiles(self) -> int:
+        return int(self.stats["tiles"])
+
+    @property
+    def num_clusters(self) -> int:
+        return int(self.stats["clusters"])
+
+    def tensors(self, device=None):
+        """(kx int32, ky int32, count uint32, label uint64) device tensors."""
+        torch = _torch()
+        t = self.num_tiles
+        device = device or torch.device("cuda", torch.cuda.current_device())
+        kx = torch.empty(t, dtype=torch.int32, device=device)
+        ky = torch.empty(t, dtype=torch.int32, device=device)
+        cnt = torch.empty(t, dtype=torch.uint32, device=device)
+        lab = torch.empty(t, dtype=torch.uint64, device=device)
+        if t:
+            st = _stream_handle(self._stream)
+            _check(load().raster_result_copy(self._h, ctypes.c_void_p(kx.data_ptr()), ctypes.c_void_p(ky.data_ptr()),
+                                             ctypes.c_void_p(cnt.data_ptr()), ctypes.c_void_p(lab.data_ptr()), st),
+                   "raster_result_copy")
+        return kx, ky, cnt, lab
+
+    def numpy(self, sort: bool = True):
+        """Host copies (kx, ky, count, label) as numpy arrays, sorted by tile if ``sort``."""
+        import numpy as np
+        kx, ky, cnt, lab = (a.cpu().numpy() for a in self.tensors())
+        if sort and kx.shape[0]:
+            order = np.lexsort((ky, kx))
+            kx, ky, cnt, lab = kx[order], ky[order], cnt[order], lab[order]
+        return kx, ky, cnt, lab
+
+    def free(self):
+        if self._h:
+            load().raster_result_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def cluster(points, tau: int, mu: int, precision: int | None = None, scale: float | None = None,
+            stream=None) -> Result:
+    """RASTER on one resident point tensor (Algorithm 1)."""
+    lib = load()
+    p, n, dt = _points(points)
+    out = ctypes.c_void_p()
+    st = _stream_handle(stream)
+    if scale is not None:
+        rc = lib.raster_cluster_scaled(p, n, dt, float(scale), int(tau), int(mu), st, ctypes.byref(out))
+    else:
+        rc = lib.raster_cluster(p, n, dt, int(precision), int(tau), int(mu), st, ctypes.byref(out))
+    _check(rc, "raster_cluster")
+    return Result(out, stream)
+
+
+class Stream:
+    """Chunked contraction with a device-resident table (Section 3.6)."""
+
+    def __init__(self, tau: int, mu: int, precision: int | None = None, scale: float | None = None,
+                 tile_hint: int = 0, stream=None):
+        self._lib = load()
+        self._stream = stream
+        self._h = ctypes.c_void_p()
+        self._keep = []  # chunks stay referenced until the stream has consumed them
+        st = _stream_handle(stream)
+        if scale is not None:
+            rc = self._lib.raster_begin_scaled(float(scale), int(tau), int(mu), int(tile_hint), st,
+                                               ctypes.byref(self._h))
+        else:
+            rc = self._lib.raster_begin(int(precision), int(tau), int(mu), int(tile_hint), st, ctypes.byref(self._h))
+        _check(rc, "raster_begin")
+
+    def feed(self, points) -> None:
+        p, n, dt = _points(points)
+        self._keep.append(points)
+        _check(self._lib.raster_feed_chunk(self._h, p, n, dt), "raster_feed_chunk")
+
+    def tiles(self):
+        """All (key uint64, count uint32) pairs counted so far, as device tensors."""
+        torch = _torch()
+        m = ctypes.c_int64()
+        _check(self._lib.raster_stream_tiles(self._h, None, None, 0, ctypes.byref(m)), "raster_stream_tiles")
+        dev = torch.device("cuda", torch.cuda.current_device())
+        keys = torch.empty(m.value, dtype=torch.uint64, device=dev)
+        cnts = torch.empty(m.value, dtype=torch.uint32, device=dev)
+        _check(self._lib.raster_stream_tiles(self._h, ctypes.c_void_p(keys.data_ptr()),
+                                             ctypes.c_void_p(cnts.data_ptr()), m.value, ctypes.byref(m)),
+               "raster_stream_tiles")
+        return keys, cnts
+
+    def finish(self) -> Result:
+        out = ctypes.c_void_p()
+        _check(self._lib.raster_finish(self._h, ctypes.byref(out)), "raster_finish")
+        self._keep.clear()
+        return Result(out, self._stream)
+
+    def close(self) -> None:
+        if self._h:
+            self._lib.raster_stream_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _job(points, precision=None, tau=5, mu=4, scale=None) -> _Job:
+    p, n, dt = _points(points)
+    return _Job(p, n, dt, int(precision if precision is not None else 0),
+                float(scale) if scale is not None else 0.0, int(tau), int(mu))
+
+
+def cluster_batch(jobs, stream=None) -> list:
+    """jobs: iterable of dicts with keys points, tau, mu and precision or scale."""
+    lib = load()
+    jobs = list(jobs)
+    arr = (_Job * max(1, len(jobs)))(*[_job(**j) for j in jobs])
+    outs = (ctypes.c_void_p * max(1, len(jobs)))()
+    _check(lib.raster_cluster_batch(arr, len(jobs), _stream_handle(stream), outs), "raster_cluster_batch")
+    return [Result(ctypes.c_void_p(outs[i]), stream) for i in range(len(jobs))]
+
+
+class Server:
+    """Serving loop with memory-budget admission and continuous batching."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 4):
+        self._lib = load()
+        self._h = ctypes.c_void_p()
+        self._keep = {}
+        _check(self._lib.raster_server_create(int(budget_bytes), int(max_slots), ctypes.byref(self._h)),
+               "raster_server_create")
+
+    def submit(self, points, tau: int, mu: int, precision: int | None = None, scale: float | None = None) -> int:
+        job = _job(points, precision, tau, mu, scale)
+        t = ctypes.c_uint64()
+        _check(self._lib.raster_server_submit(self._h, ctypes.byref(job), ctypes.byref(t)), "raster_server_submit")
+        self._keep[t.value] = points
+        return t.value
+
+    def wait(self, ticket: int):
+        out = ctypes.c_void_p()
+        lat = ctypes.c_double()
+        rc = self._lib.raster_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(out), ctypes.byref(lat))
+        self._keep.pop(ticket, None)
+        _check(rc, "raster_server_wait")
+        return Result(out), lat.value
+
+    def close(self):
+        if self._h:
+            self._lib.raster_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Tuning:
+    block: int = 256
+    items: int = 4
+    preagg_slots: int = 0
+    load_factor: float = 0.5
+
+
+def set_tuning(t: Tuning | None = None, **kw) -> None:
+    lib = load()
+    if t is None and not kw:
+        _check(lib.raster_set_tuning(None), "raster_set_tuning")
+        return
+    t = t or Tuning()
+    for k, v in kw.items():
+        setattr(t, k, v)
+    c = _Tuning(int(t.block), int(t.items), int(t.preagg_slots), float(t.load_factor))
+    _check(lib.raster_set_tuning(ctypes.byref(c)), "raster_set_tuning")
+
+
+def get_tuning() -> Tuning:
+    c = _Tuning()
+    _check(load().raster_get_tuning(ctypes.byref(c)), "raster_get_tuning")
+    return Tuning(c.block, c.items, c.preagg_slots, c.load_factor)

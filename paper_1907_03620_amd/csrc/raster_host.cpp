@@ -1,0 +1,650 @@
+// Host runtime of the RASTER library: argument checks, device memory, the
+// table life cycle (size, grow, rehash), the streaming state machine and the
+// result objects behind the C ABI of include/raster.h.
+//
+// Every step of the clustering runs in the kernels of raster_kernels.hip; this
+// file only sizes buffers, enqueues launches and reads back a few counters.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "raster.h"
+#include "raster_internal.h"
+#include "raster_runtime.h"
+
+using namespace rst;
+
+// ============================================================ errors =======
+
+namespace rst {
+
+thread_local std::string g_last_error;
+
+raster_status fail(raster_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+raster_status hip_fail(hipError_t e, const char* what) {
+    if (e == hipErrorOutOfMemory) return fail(RASTER_E_NOMEM, "%s: out of device memory", what);
+    return fail(RASTER_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ========================================================= tuning ==========
+
+static std::mutex g_tuning_mu;
+static raster_tuning g_tuning = {256, 4, 0, 0.5f};
+
+raster_tuning current_tuning() {
+    std::lock_guard<std::mutex> g(g_tuning_mu);
+    return g_tuning;
+}
+
+KernelTuning kernel_tuning(const raster_tuning& t) {
+    KernelTuning k;
+    k.block = t.block;
+    k.items = t.items;
+    k.preagg_slots = t.preagg_slots;
+    k.preagg_tiles = 4;
+    return k;
+}
+
+// =================================================== device memory pool ====
+//
+// A caching allocator per device.  Blocks are rounded to size classes and
+// returned to a free list on release.  A block may only be released once the
+// work that used it is complete (the callers synchronise first), so reuse
+// never races with queued kernels.
+
+static size_t size_class(size_t bytes) {
+    if (bytes <= 256) return 256;
+    if (bytes <= (size_t)2 << 20) {
+        size_t c = 256;
+        while (c < bytes) c <<= 1;
+        return c;
+    }
+    const size_t g = (size_t)2 << 20;
+    return (bytes + g - 1) / g * g;
+}
+
+DevicePool& DevicePool::get(int device) {
+    static std::mutex mu;
+    static std::map<int, DevicePool*> pools;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = pools.find(device);
+    if (it != pools.end()) return *it->second;
+    DevicePool* p = new DevicePool();  // lives until process exit
+    p->device_ = device;
+    pools[device] = p;
+    return *p;
+}
+
+hipError_t DevicePool::alloc(void** out, size_t bytes) {
+    const size_t c = size_class(bytes == 0 ? 1 : bytes);
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        auto it = free_.lower_bound(c);
+        // reuse a cached block of the same class, or one at most 2x larger
+        if (it != free_.end() && it->first <= c * 2) {
+            *out = it->second;
+            cached_ -= it->first;
+            used_ += it->first;
+            free_.erase(it);
+            return hipSuccess;
+        }
+    }
+    hipError_t e = hipMalloc(out, c);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        trim();
+        e = hipMalloc(out, c);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *out = nullptr;
+        return e;
+    }
+    std::lock_guard<std::mutex> g(mu_);
+    sizes_[*out] = c;
+    used_ += c;
+    return hipSuccess;
+}
+
+void DevicePool::release(void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = sizes_.find(p);
+    if (it == sizes_.end()) return;
+    free_.emplace(it->second, p);
+    cached_ += it->second;
+    used_ -= it->second;
+}
+
+void DevicePool::trim() {
+    std::multimap<size_t, void*> drop;
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        drop.swap(free_);
+        for (auto& kv : drop) sizes_.erase(kv.second);
+        cached_ = 0;
+    }
+    for (auto& kv : drop) (void)hipFree(kv.second);
+}
+
+size_t DevicePool::used_bytes() {
+    std::lock_guard<std::mutex> g(mu_);
+    return used_;
+}
+
+// A set of pool blocks released together.
+Buffers::~Buffers() { release_all(); }
+
+void Buffers::release_all() {
+    if (!pool) return;
+    for (void* p : blocks) pool->release(p);
+    blocks.clear();
+}
+
+hipError_t Buffers::take(void** out, size_t bytes) {
+    hipError_t e = pool->alloc(out, bytes);
+    if (e == hipSuccess) blocks.push_back(*out);
+    return e;
+}
+
+void Buffers::give_back(void* p) {
+    auto it = std::find(blocks.begin(), blocks.end(), p);
+    if (it != blocks.end()) {
+        blocks.erase(it);
+        pool->release(p);
+    }
+}
+
+// ================================================================ helpers ==
+
+bool scale_for_precision(int32_t p, double* s) {
+    if (p < 0 || p > 15) return false;
+    double v = 1.0;
+    for (int i = 0; i < p; ++i) v *= 10.0;  // every step exact below 2^53
+    *s = v;
+    return true;
+}
+
+uint64_t next_pow2(uint64_t v) {
+    uint64_t c = 1;
+    while (c < v) c <<= 1;
+    return c;
+}
+
+raster_status check_points(const void* p, int64_t n, raster_dtype dt) {
+    if (dt != RASTER_F32 && dt != RASTER_F64) return fail(RASTER_E_INVAL, "unknown dtype %d", (int)dt);
+    if (n < 0) return fail(RASTER_E_INVAL, "negative point count %lld", (long long)n);
+    if (n > 0 && !p) return fail(RASTER_E_INVAL, "NULL points with n = %lld", (long long)n);
+    const uintptr_t a = (uintptr_t)p;
+    if (n > 0 && (a % (dt == RASTER_F64 ? 16 : 8)) != 0)
+        return fail(RASTER_E_INVAL, "points must be %d-byte aligned", dt == RASTER_F64 ? 16 : 8);
+    return RASTER_OK;
+}
+
+raster_status check_params(double scale, uint32_t tau, uint32_t mu) {
+    if (tau == 0) return fail(RASTER_E_INVAL, "tau must be >= 1");
+    if (mu == 0) return fail(RASTER_E_INVAL, "mu must be >= 1");
+    if (!(scale > 0.0) || !std::isfinite(scale)) return fail(RASTER_E_INVAL, "scale must be finite and > 0");
+    return RASTER_OK;
+}
+
+// ============================================================ table run ====
+
+#define HIP_TRY(expr, what)                          \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+TableRun::~TableRun() {
+    for (hipEvent_t& e : ev) if (e) (void)hipEventDestroy(e);
+    if (ev_chunk) (void)hipEventDestroy(ev_chunk);
+    if (ev_k0) (void)hipEventDestroy(ev_k0);
+    if (ev_k1) (void)hipEventDestroy(ev_k1);
+    if (h_ctr) (void)hipHostFree(h_ctr);
+}
+
+raster_status TableRun::init(double scale_, uint32_t tau_, uint32_t mu_, int64_t tile_hint,
+                             hipStream_t stream_) {
+    scale = scale_;
+    tau = tau_;
+    mu = mu_;
+    stream = stream_;
+    HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+    bufs.pool = &DevicePool::get(device);
+    tuning = current_tuning();
+    HIP_TRY(hipHostMalloc((void**)&h_ctr, kCounterWords * sizeof(unsigned long long), hipHostMallocDefault),
+            "hipHostMalloc");
+    std::memset(h_ctr, 0, kCounterWords * sizeof(unsigned long long));
+    for (hipEvent_t& e : ev) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+    HIP_TRY(hipEventCreateWithFlags(&ev_chunk, hipEventDisableTiming), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&ev_k0), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&ev_k1), "hipEventCreate");
+    HIP_TRY(bufs.take((void**)&ctr, kCounterWords * sizeof(unsigned long long)), "counters");
+    HIP_TRY(bufs.take((void**)&partials, kScanBlocks * sizeof(uint32_t)), "scan partials");
+    HIP_TRY(launch_zero_u64((uint64_t*)ctr, kCounterWords, stream), "zero counters");
+    const double lf = tuning.load_factor;
+    const uint64_t want = (uint64_t)std::max<double>(4096.0, (double)std::max<int64_t>(tile_hint, 1) / lf);
+    return alloc_table(next_pow2(want), &tab, &cap);
+}
+
+raster_status TableRun::alloc_table(uint64_t c, Slot** t, uint64_t* c_out) {
+    if (c > ((uint64_t)1 << 31)) return fail(RASTER_E_NOMEM, "table of %llu slots is too large", (unsigned long long)c);
+    HIP_TRY(bufs.take((void**)t, c * sizeof(Slot)), "tile table");
+    HIP_TRY(launch_fill_table(*t, c, stream), "fill table");
+    *c_out = c;
+    return RASTER_OK;
+}
+
+raster_status TableRun::ensure_spill(uint64_t need) {
+    if (spill_cap >= need) return RASTER_OK;
+    const uint64_t c = std::max<uint64_t>(need, 1 << 16);
+    for (int b = 0; b < 2; ++b) {
+        if (spill_keys[b]) bufs.give_back(spill_keys[b]);
+        if (spill_counts[b]) bufs.give_back(spill_counts[b]);
+        spill_keys[b] = nullptr;
+        spill_counts[b] = nullptr;
+        HIP_TRY(bufs.take((void**)&spill_keys[b], c * sizeof(uint64_t)), "spill keys");
+        HIP_TRY(bufs.take((void**)&spill_counts[b], c * sizeof(uint32_t)), "spill counts");
+    }
+    spill_cap = c;
+    return RASTER_OK;
+}
+
+raster_status TableRun::pull_counters() {
+    HIP_TRY(hipMemcpyAsync(h_ctr, ctr, kCounterWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream),
+            "counter copy");
+    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    return RASTER_OK;
+}
+
+// Moves everything into a table of new_cap slots, then re-adds the `pending`
+// spilled records held in spill buffer `src`.  Repeats with a larger table
+// in the (unlikely) case the new table spills again.
+raster_status TableRun::grow(uint64_t new_cap, uint64_t pending, int src) {
+    while (true) {
+        Slot* nt = nullptr;
+        uint64_t nc = 0;
+        raster_status st = alloc_table(new_cap, &nt, &nc);
+        if (st != RASTER_OK) return st;
+        const int dst = src ^ 1;
+        st = ensure_spill(std::max<uint64_t>(cap + pending, spill_cap));
+        if (st != RASTER_OK) return st;
+        HIP_TRY(launch_zero_u64((uint64_t*)ctr + C_INSERTED, 2, stream), "reset counters");
+        SpillBuf sp{spill_keys[dst], spill_counts[dst], spill_cap};
+        HIP_TRY(launch_rehash(tab, cap, nt, nc, sp, ctr, stream), "rehash");
+        HIP_TRY(launch_insert_records(spill_keys[src], spill_counts[src], pending, nt, nc, sp, ctr, stream),
+                "reinsert");
+        raster_status ps = pull_counters();
+        if (ps != RASTER_OK) return ps;
+        bufs.give_back(tab);
+        tab = nt;
+        cap = nc;
+        grow_events += 1;
+        if (h_ctr[C_ERROR] & kErrSpillOverflow) return fail(RASTER_E_DEVICE, "spill buffer overflow while growing");
+        pending = h_ctr[C_SPILLED];
+        if (pending == 0) return RASTER_OK;
+        src = dst;
+        new_cap = cap * 2;
+    }
+}
+
+// Reads the previous chunk's counters and repairs the table if it spilled.
+raster_status TableRun::settle() {
+    if (!chunk_pending) return RASTER_OK;
+    chunk_pending = false;
+    HIP_TRY(hipEventSynchronize(ev_chunk), "hipEventSynchronize");
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev_k0, ev_k1) == hipSuccess) us_count_kernel += 1000.0 * ms;
+    count_launches += 1;
+    if (h_ctr[C_ERROR] & kErrRange) {
+        failed = RASTER_E_RANGE;
+        return fail(RASTER_E_RANGE, "a coordinate is not finite or its tile is outside +-(2^31 - 2)");
+    }
+    if (h_ctr[C_ERROR] & kErrSpillOverflow) {
+        failed = RASTER_E_DEVICE;
+        return fail(RASTER_E_DEVICE, "spill buffer overflow");
+    }
+    const uint64_t spilled = h_ctr[C_SPILLED];
+    if (spilled > 0) {
+        const double lf = tuning.load_factor;
+        const uint64_t want = next_pow2((uint64_t)((double)(h_ctr[C_INSERTED] + spilled) / lf) + 1);
+        raster_status st = grow(std::max<uint64_t>(want, cap * 2), spilled, 0);
+        if (st != RASTER_OK) {
+            failed = st;
+            return st;
+        }
+    }
+    return RASTER_OK;
+}
+
+raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
+    raster_status st = settle();
+    if (st != RASTER_OK) return st;
+    if (n == 0) return RASTER_OK;
+    if ((uint64_t)n_points + (uint64_t)n > 0xFFFFFFFFull)
+        return fail(RASTER_E_RANGE, "more than 2^32 - 1 points in one table");
+    // keep the table under its target load: grow before the chunk if the
+    // previous chunks already filled it past the target
+    const double lf = tuning.load_factor;
+    if ((double)h_ctr[C_INSERTED] > lf * (double)cap) {
+        st = grow(next_pow2((uint64_t)(2.0 * (double)h_ctr[C_INSERTED] / lf)), 0, 0);
+        if (st != RASTER_OK) {
+            failed = st;
+            return st;
+        }
+    }
+    st = ensure_spill((uint64_t)n);
+    if (st != RASTER_OK) return st;
+    if (!timing_started) {
+        HIP_TRY(hipEventRecord(ev[0], stream), "hipEventRecord");
+        timing_started = true;
+    }
+    SpillBuf sp{spill_keys[0], spill_counts[0], spill_cap};
+    HIP_TRY(hipEventRecord(ev_k0, stream), "hipEventRecord");
+    HIP_TRY(launch_project_count(pts, n, (int)dt, scale, tab, cap, sp, ctr, kernel_tuning(tuning), stream),
+            "project_count");
+    HIP_TRY(hipEventRecord(ev_k1, stream), "hipEventRecord");
+    HIP_TRY(hipMemcpyAsync(h_ctr, ctr, kCounterWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream),
+            "counter copy");
+    HIP_TRY(hipEventRecord(ev_chunk, stream), "hipEventRecord");
+    chunk_pending = true;
+    n_points += n;
+    return RASTER_OK;
+}
+
+raster_status TableRun::finish(raster_result** out) {
+    raster_status st = settle();
+    if (st != RASTER_OK) return st;
+    if (!timing_started) {
+        HIP_TRY(hipEventRecord(ev[0], stream), "hipEventRecord");
+        timing_started = true;
+    }
+    HIP_TRY(hipEventRecord(ev[1], stream), "hipEventRecord");
+    const uint64_t m = std::max<uint64_t>(h_ctr[C_INSERTED], 1);
+    uint64_t* s_key = nullptr;
+    uint32_t *s_count = nullptr, *parent = nullptr, *size = nullptr;
+    HIP_TRY(bufs.take((void**)&s_key, m * sizeof(uint64_t)), "S keys");
+    HIP_TRY(bufs.take((void**)&s_count, m * sizeof(uint32_t)), "S counts");
+    HIP_TRY(bufs.take((void**)&parent, m * sizeof(uint32_t)), "parent");
+    HIP_TRY(bufs.take((void**)&size, m * sizeof(uint32_t)), "sizes");
+
+    raster_result* r = new raster_result();
+    r->pool = bufs.pool;
+    auto drop = [&](raster_status s) {
+        raster_result_free(r);
+        return s;
+    };
+    const size_t row_bytes = 2 * sizeof(int32_t) + sizeof(uint32_t) + sizeof(uint64_t);
+    hipError_t e = r->pool->alloc(&r->block, m * row_bytes + 256);
+    if (e != hipSuccess) return drop(hip_fail(e, "result arrays"));
+    char* b = (char*)r->block;
+    r->label = (uint64_t*)b;
+    r->kx = (int32_t*)(b + m * sizeof(uint64_t));
+    r->ky = r->kx + m;
+    r->count = (uint32_t*)(r->ky + m);
+
+    e = launch_zero_u64((uint64_t*)ctr + C_DISTINCT, C_COUNT_ - C_DISTINCT, stream);
+    if (e == hipSuccess) e = launch_threshold(tab, cap, tau, s_key, s_count, parent, size, partials, ctr, stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[2], stream);
+    if (e == hipSuccess) e = launch_agglomerate(tab, cap, s_key, parent, size, m, ctr, stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[3], stream);
+    if (e == hipSuccess)
+        e = launch_filter(s_key, s_count, parent, size, mu, m, r->kx, r->ky, r->count, r->label, partials, ctr,
+                          stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[4], stream);
+    if (e != hipSuccess) return drop(hip_fail(e, "agglomeration launch"));
+    raster_status ps = pull_counters();
+    if (ps != RASTER_OK) return drop(ps);
+
+    raster_stats& S = r->stats;
+    std::memset(&S, 0, sizeof S);
+    S.n_points = n_points;
+    S.distinct_tiles = (int64_t)h_ctr[C_DISTINCT];
+    S.significant_tiles = (int64_t)h_ctr[C_SIGNIFICANT];
+    S.components = (int64_t)h_ctr[C_COMPONENTS];
+    S.clusters = (int64_t)h_ctr[C_CLUSTERS];
+    S.tiles = (int64_t)h_ctr[C_TILES];
+    S.table_capacity = (int64_t)cap;
+    S.grow_events = grow_events;
+    (void)hipEventElapsedTime(&S.us_contract, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&S.us_threshold, ev[1], ev[2]);
+    (void)hipEventElapsedTime(&S.us_agglomerate, ev[2], ev[3]);
+    (void)hipEventElapsedTime(&S.us_filter, ev[3], ev[4]);
+    S.us_contract *= 1000.0f;
+    S.us_threshold *= 1000.0f;
+    S.us_agglomerate *= 1000.0f;
+    S.us_filter *= 1000.0f;
+    S.count_launches = count_launches;
+    S.us_count_kernel = (float)us_count_kernel;
+    r->tiles = S.tiles;
+    r->clusters = S.clusters;
+    if (h_ctr[C_ERROR] & kErrInternal) return drop(fail(RASTER_E_DEVICE, "agglomeration state inconsistent"));
+    if (h_ctr[C_SUM] != (unsigned long long)n_points || h_ctr[C_DISTINCT] != h_ctr[C_INSERTED])
+        return drop(fail(RASTER_E_DEVICE, "table inconsistent: sum %llu vs n %lld, occupied %llu vs inserted %llu",
+                         h_ctr[C_SUM], (long long)n_points, h_ctr[C_DISTINCT], h_ctr[C_INSERTED]));
+    bufs.give_back(s_key);
+    bufs.give_back(s_count);
+    bufs.give_back(parent);
+    bufs.give_back(size);
+    *out = r;
+    return RASTER_OK;
+}
+
+raster_status TableRun::export_tiles(uint64_t* keys, uint32_t* counts, int64_t cap_rows, int64_t* m) {
+    raster_status st = settle();
+    if (st != RASTER_OK) return st;
+    HIP_TRY(launch_zero_u64((uint64_t*)ctr + C_DISTINCT, 1, stream), "zero counter");
+    HIP_TRY(launch_export_tiles(tab, cap, keys, counts, (uint64_t)std::max<int64_t>(cap_rows, 0), partials, ctr,
+                                stream),
+            "export tiles");
+    raster_status ps = pull_counters();
+    if (ps != RASTER_OK) return ps;
+    *m = (int64_t)h_ctr[C_DISTINCT];
+    return RASTER_OK;
+}
+
+}  // namespace rst
+
+// ============================================================== C ABI ======
+
+struct raster_stream {
+    rst::TableRun run;
+    enum State { OPEN, FINISHED, FAILED } state = OPEN;
+};
+
+extern "C" {
+
+raster_status raster_cluster_scaled(const void* d_points, int64_t n, raster_dtype dt, double scale, uint32_t tau,
+                                    uint32_t mu, hipStream_t stream, raster_result** out) {
+    if (!out) return fail(RASTER_E_INVAL, "out is NULL");
+    *out = nullptr;
+    raster_status st = check_params(scale, tau, mu);
+    if (st != RASTER_OK) return st;
+    st = check_points(d_points, n, dt);
+    if (st != RASTER_OK) return st;
+    TableRun run;
+    const raster_tuning t = current_tuning();
+    (void)t;
+    st = run.init(scale, tau, mu, std::max<int64_t>(n / 8, 1024), stream);
+    if (st != RASTER_OK) return st;
+    st = run.feed(d_points, n, dt);
+    if (st != RASTER_OK) return st;
+    return run.finish(out);
+}
+
+raster_status raster_cluster(const void* d_points, int64_t n, raster_dtype dt, int32_t precision, uint32_t tau,
+                             uint32_t mu, hipStream_t stream, raster_result** out) {
+    double s;
+    if (out) *out = nullptr;
+    if (!scale_for_precision(precision, &s)) return fail(RASTER_E_INVAL, "precision %d outside [0, 15]", precision);
+    return raster_cluster_scaled(d_points, n, dt, s, tau, mu, stream, out);
+}
+
+int64_t raster_result_num_tiles(const raster_result* r) { return r ? r->tiles : -1; }
+int64_t raster_result_num_clusters(const raster_result* r) { return r ? r->clusters : -1; }
+
+raster_status raster_result_arrays(const raster_result* r, const int32_t** d_kx, const int32_t** d_ky,
+                                   const uint32_t** d_count, const uint64_t** d_label) {
+    if (!r) return fail(RASTER_E_INVAL, "result is NULL");
+    if (d_kx) *d_kx = r->kx;
+    if (d_ky) *d_ky = r->ky;
+    if (d_count) *d_count = r->count;
+    if (d_label) *d_label = r->label;
+    return RASTER_OK;
+}
+
+raster_status raster_result_copy(const raster_result* r, int32_t* d_kx, int32_t* d_ky, uint32_t* d_count,
+                                 uint64_t* d_label, hipStream_t stream) {
+    if (!r) return fail(RASTER_E_INVAL, "result is NULL");
+    const size_t t = (size_t)r->tiles;
+    if (t == 0) return RASTER_OK;
+    if (d_kx) HIP_TRY(hipMemcpyAsync(d_kx, r->kx, t * 4, hipMemcpyDeviceToDevice, stream), "copy kx");
+    if (d_ky) HIP_TRY(hipMemcpyAsync(d_ky, r->ky, t * 4, hipMemcpyDeviceToDevice, stream), "copy ky");
+    if (d_count) HIP_TRY(hipMemcpyAsync(d_count, r->count, t * 4, hipMemcpyDeviceToDevice, stream), "copy count");
+    if (d_label) HIP_TRY(hipMemcpyAsync(d_label, r->label, t * 8, hipMemcpyDeviceToDevice, stream), "copy label");
+    return RASTER_OK;
+}
+
+raster_status raster_result_stats(const raster_result* r, raster_stats* out) {
+    if (!r || !out) return fail(RASTER_E_INVAL, "NULL argument");
+    *out = r->stats;
+    return RASTER_OK;
+}
+
+void raster_result_free(raster_result* r) {
+    if (!r) return;
+    if (r->pool && r->block) r->pool->release(r->block);
+    delete r;
+}
+
+raster_status raster_begin_scaled(double scale, uint32_t tau, uint32_t mu, int64_t tile_hint, hipStream_t stream,
+                                  raster_stream** st) {
+    if (!st) return fail(RASTER_E_INVAL, "st is NULL");
+    *st = nullptr;
+    raster_status s = check_params(scale, tau, mu);
+    if (s != RASTER_OK) return s;
+    if (tile_hint < 0) return fail(RASTER_E_INVAL, "negative tile_hint");
+    raster_stream* h = new raster_stream();
+    s = h->run.init(scale, tau, mu, tile_hint > 0 ? tile_hint : (1 << 20), stream);
+    if (s != RASTER_OK) {
+        delete h;
+        return s;
+    }
+    *st = h;
+    return RASTER_OK;
+}
+
+raster_status raster_begin(int32_t precision, uint32_t tau, uint32_t mu, int64_t tile_hint, hipStream_t stream,
+                           raster_stream** st) {
+    double s;
+    if (st) *st = nullptr;
+    if (!scale_for_precision(precision, &s)) return fail(RASTER_E_INVAL, "precision %d outside [0, 15]", precision);
+    return raster_begin_scaled(s, tau, mu, tile_hint, stream, st);
+}
+
+raster_status raster_feed_chunk(raster_stream* st, const void* d_points, int64_t n, raster_dtype dt) {
+    if (!st) return fail(RASTER_E_INVAL, "stream is NULL");
+    if (st->state != raster_stream::OPEN) {
+        if (st->state == raster_stream::FAILED && st->run.failed != RASTER_OK)
+            return fail(st->run.failed, "stream failed earlier: %s", raster_status_string(st->run.failed));
+        return fail(RASTER_E_STATE, "stream is not open");
+    }
+    raster_status s = check_points(d_points, n, dt);
+    if (s != RASTER_OK) return s;
+    s = st->run.feed(d_points, n, dt);
+    if (s != RASTER_OK && st->run.failed != RASTER_OK) st->state = raster_stream::FAILED;
+    return s;
+}
+
+raster_status raster_finish(raster_stream* st, raster_result** out) {
+    if (!out) return fail(RASTER_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!st) return fail(RASTER_E_INVAL, "stream is NULL");
+    if (st->state != raster_stream::OPEN) {
+        if (st->state == raster_stream::FAILED && st->run.failed != RASTER_OK)
+            return fail(st->run.failed, "stream failed earlier: %s", raster_status_string(st->run.failed));
+        return fail(RASTER_E_STATE, "stream is not open");
+    }
+    raster_status s = st->run.finish(out);
+    st->state = (s == RASTER_OK) ? raster_stream::FINISHED : raster_stream::FAILED;
+    if (s != RASTER_OK && st->run.failed == RASTER_OK) st->run.failed = s;
+    return s;
+}
+
+raster_status raster_stream_tiles(raster_stream* st, uint64_t* d_keys, uint32_t* d_counts, int64_t cap,
+                                  int64_t* m) {
+    if (!st || !m) return fail(RASTER_E_INVAL, "NULL argument");
+    if (cap > 0 && (!d_keys || !d_counts)) return fail(RASTER_E_INVAL, "NULL output buffers");
+    if (st->state != raster_stream::OPEN) return fail(RASTER_E_STATE, "stream is not open");
+    raster_status s = st->run.export_tiles(d_keys, d_counts, cap, m);
+    if (s != RASTER_OK && st->run.failed != RASTER_OK) st->state = raster_stream::FAILED;
+    return s;
+}
+
+void raster_stream_destroy(raster_stream* st) {
+    if (!st) return;
+    (void)hipStreamSynchronize(st->run.stream);
+    delete st;
+}
+
+raster_status raster_set_tuning(const raster_tuning* t) {
+    raster_tuning v = {256, 4, 0, 0.5f};
+    if (t) {
+        v = *t;
+        if (v.block < 64 || v.block > 1024 || v.block % 64) return fail(RASTER_E_INVAL, "block must be 64..1024, x64");
+        if (!(v.items == 1 || v.items == 2 || v.items == 4 || v.items == 8 || v.items == 16))
+            return fail(RASTER_E_INVAL, "items must be 1, 2, 4, 8 or 16");
+        if (v.preagg_slots != 0 &&
+            (v.preagg_slots < 256 || v.preagg_slots > 4096 || (v.preagg_slots & (v.preagg_slots - 1))))
+            return fail(RASTER_E_INVAL, "preagg_slots must be 0 or a power of two in [256, 4096]");
+        if (!(v.load_factor > 0.05f && v.load_factor <= 0.9f)) return fail(RASTER_E_INVAL, "load_factor in (0.05, 0.9]");
+    }
+    std::lock_guard<std::mutex> g(g_tuning_mu);
+    g_tuning = v;
+    return RASTER_OK;
+}
+
+raster_status raster_get_tuning(raster_tuning* t) {
+    if (!t) return fail(RASTER_E_INVAL, "NULL argument");
+    *t = current_tuning();
+    return RASTER_OK;
+}
+
+const char* raster_status_string(raster_status s) {
+    switch (s) {
+        case RASTER_OK: return "RASTER_OK";
+        case RASTER_E_INVAL: return "RASTER_E_INVAL";
+        case RASTER_E_RANGE: return "RASTER_E_RANGE";
+        case RASTER_E_NOMEM: return "RASTER_E_NOMEM";
+        case RASTER_E_DEVICE: return "RASTER_E_DEVICE";
+        case RASTER_E_STATE: return "RASTER_E_STATE";
+        case RASTER_E_BUDGET: return "RASTER_E_BUDGET";
+    }
+    return "RASTER_E_UNKNOWN";
+}
+
+const char* raster_last_error(void) { return g_last_error.c_str(); }
+
+const char* raster_version(void) { return "raster-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// Internal interface between the host runtime (raster_host.cpp) and the
+// gfx950 kernels (raster_kernels.hip).  Not installed; not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace rst {
+
+// Empty marker of a table slot.  A valid biased key has a high word of at
+// most 2^32 - 2, so it never equals this value.
+constexpr uint64_t kEmptyKey = ~0ull;
+// aux of a slot whose tile is not significant.
+constexpr uint32_t kNotSignificant = 0xFFFFFFFFu;
+// Longest probe window of the open-addressing table.  A key lives within this
+// many slots of its home slot; an insert that finds the window full of other
+// keys spills the key instead, and the table is grown afterwards.
+constexpr uint32_t kMaxProbe = 128;
+
+// One table slot: 16 bytes, so a probe and the count update touch one line.
+struct alignas(16) Slot {
+    uint64_t key;    // biased tile key or kEmptyKey
+    uint32_t count;  // points on the tile
+    uint32_t aux;    // after the significance scan: compact index or kNotSignificant
+};
+static_assert(sizeof(Slot) == 16, "slot must be 16 bytes");
+
+// Device counter words (unsigned 64-bit), one block per table / job.
+enum CounterIndex : int {
+    C_INSERTED = 0,  // new keys inserted by counting kernels
+    C_SPILLED,       // spill records written (points or rehash entries)
+    C_ERROR,         // kErr* bits
+    C_DISTINCT,      // occupied slots (m), from the significance scan
+    C_SIGNIFICANT,   // s
+    C_SUM,           // sum of all counts (equals the points counted)
+    C_COMPONENTS,    // roots of the union-find forest
+    C_CLUSTERS,      // roots with at least mu tiles
+    C_TILES,         // output rows t
+    C_COUNT_
+};
+constexpr int kCounterWords = 16;  // padded to 128 bytes
+
+constexpr uint64_t kErrRange = 1;
+constexpr uint64_t kErrSpillOverflow = 2;
+constexpr uint64_t kErrInternal = 4;  // union-find walk hit its bound or an index out of range
+
+// Overflow records of the counting kernels.
+struct SpillBuf {
+    uint64_t* keys;
+    uint32_t* counts;
+    uint64_t cap;
+};
+
+struct KernelTuning {
+    int block;         // threads per workgroup of the counting kernel
+    int items;         // points per thread per sweep
+    int preagg_slots;  // LDS pre-aggregation slots (0 = off)
+    int preagg_tiles;  // sweeps a workgroup aggregates before flushing its LDS table
+};
+
+// Fixed number of workgroups of the scan passes; the partial-sum array of a
+// scan holds this many entries.
+constexpr int kScanBlocks = 2048;
+
+// ---- launchers (all enqueue on `stream`, none synchronises) ------------------
+
+hipError_t launch_fill_table(Slot* tab, uint64_t cap, hipStream_t stream);
+hipError_t launch_zero_u64(uint64_t* p, uint64_t n, hipStream_t stream);
+
+// Projection + counting of n points into the table (dtype 1 = f32, 2 = f64).
+hipError_t launch_project_count(const void* pts, int64_t n, int dtype, double scale, Slot* tab,
+                                 uint64_t cap, SpillBuf spill, unsigned long long* ctr,
+                                 const KernelTuning& tu, hipStream_t stream);
+
+// Insert n (key, count) records (spilled keys, or a rehash source).
+hipError_t launch_insert_records(const uint64_t* keys, const uint32_t* counts, uint64_t n,
+                                 Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr,
+                                 hipStream_t stream);
+
+// Move every occupied slot of `from` into `to` (a larger table).
+hipError_t launch_rehash(const Slot* from, uint64_t from_cap, Slot* to, uint64_t to_cap,
+                         SpillBuf spill, unsigned long long* ctr, hipStream_t stream);
+
+// Export every occupied (key, count) pair, compacted; writes at most cap rows,
+// and the number of occupied slots to ctr[C_DISTINCT].
+hipError_t launch_export_tiles(const Slot* tab, uint64_t tcap, uint64_t* keys, uint32_t* counts,
+                               uint64_t cap, uint32_t* partials, unsigned long long* ctr,
+                               hipStream_t stream);
+
+// Significance scan: flags count >= tau, writes the compact arrays S_key,
+// S_count, sets slot.aux, initialises parent[i] = i and size[i] = 0, and fills
+// ctr[C_DISTINCT], ctr[C_SIGNIFICANT], ctr[C_SUM].
+hipError_t launch_threshold(Slot* tab, uint64_t cap, uint32_t tau, uint64_t* s_key,
+                            uint32_t* s_count, uint32_t* parent, uint32_t* size,
+                            uint32_t* partials, unsigned long long* ctr, hipStream_t stream);
+
+// Union-find over the forward neighbours of every significant tile, then full
+// path compression, component sizes and the component count.
+hipError_t launch_agglomerate(const Slot* tab, uint64_t cap, const uint64_t* s_key,
+                              uint32_t* parent, uint32_t* size, uint64_t s_max,
+                              unsigned long long* ctr, hipStream_t stream);
+
+// mu filter and output compaction: rows of kept components in compact order.
+hipError_t launch_filter(const uint64_t* s_key, const uint32_t* s_count, const uint32_t* parent,
+                         const uint32_t* size, uint32_t mu, uint64_t s_max, int32_t* out_kx,
+                         int32_t* out_ky, uint32_t* out_count, uint64_t* out_label,
+                         uint32_t* partials, unsigned long long* ctr, hipStream_t stream);
+
+}  // namespace rst

@@ -1,0 +1,878 @@
+// gfx950 kernels of the RASTER hot path (Algorithm 1 of the RASTER paper):
+//   contraction   -- projection (Section 3.2) fused with per-tile counting in
+//                    an open-addressing device table, then a prefix-scan
+//                    compaction of the tiles holding at least tau points;
+//   agglomeration -- union-find connected components over the eight-neighbour
+//                    adjacency of significant tiles (Section 3.2, Chebyshev
+//                    distance 1), then the mu filter and the min-key label.
+//
+// Everything is integer work except one binary64 product per coordinate.  The
+// file is compiled with -ffp-contract=off and without fast-math so that the
+// product is the correctly rounded IEEE one.
+//
+// Wavefront size is 64.  Counters that many lanes bump are aggregated per
+// wave with a ballot before the single global atomic.
+
+#include "raster_internal.h"
+
+namespace rst {
+namespace {
+
+// ---------------------------------------------------------------- helpers ---
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    // SplitMix64 output finaliser (Steele, Lea and Flood, OOPSLA 2014): an
+    // invertible 64-bit mixer.  Only the slot a key probes from depends on it.
+    z ^= z >> 30;
+    z *= 0xbf58476d1ce4e5b9ull;
+    z ^= z >> 27;
+    z *= 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    return z;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    return (1ull << lane_id()) - 1ull;
+}
+
+__device__ __forceinline__ uint64_t ld_relaxed(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint32_t ld_relaxed(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
+    uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Adds the number of lanes with `pred` to *ctr with one atomic per wave.
+// Must be reached by every active lane of the wave.
+__device__ __forceinline__ void wave_count(unsigned long long* ctr, bool pred) {
+    const uint64_t b = __ballot(pred);
+    if (b != 0 && lane_id() == __ffsll((long long)b) - 1) atomicAdd(ctr, (unsigned long long)__popcll(b));
+}
+
+// Projection of Section 3.2: one binary64 product per coordinate, truncated
+// toward zero.  Returns false (range error) unless both tiles satisfy
+// |k| <= 2^31 - 2, which also rejects NaN and infinities.  The key is the
+// biased pair (kx + 2^31, ky + 2^31) packed high/low.
+__device__ __forceinline__ bool tile_key(double x, double y, double s, uint64_t& key) {
+    const double px = x * s;
+    const double py = y * s;
+    if (!(fabs(px) < 2147483647.0) || !(fabs(py) < 2147483647.0)) return false;
+    const uint32_t bx = (uint32_t)(int32_t)px + 0x80000000u;
+    const uint32_t by = (uint32_t)(int32_t)py + 0x80000000u;
+    key = ((uint64_t)bx << 32) | by;
+    return true;
+}
+
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+template <typename T> struct Pair;
+template <> struct Pair<double> {
+    using V = f64x2;
+};
+template <> struct Pair<float> {
+    using V = f32x2;
+};
+
+template <typename T>
+__device__ __forceinline__ void load_point(const T* pts, int64_t i, double& x, double& y) {
+    using V = typename Pair<T>::V;
+    const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(pts) + i);
+    x = (double)v.x;  // FP32 widens exactly
+    y = (double)v.y;
+}
+
+enum AddResult : int { ADD_FOUND = 0, ADD_NEW = 1, ADD_FULL = 2 };
+
+// Adds `inc` to the count of `key`, inserting the key into an empty slot of
+// its probe window if it is not there yet.  Keys are only ever written once
+// (empty -> key), so a stale read can only show a slot as empty; the
+// compare-and-swap then returns the true occupant.
+__device__ __forceinline__ int table_add(Slot* tab, uint64_t mask, uint64_t key, uint32_t inc) {
+    uint64_t pos = mix64(key) & mask;
+    for (uint32_t p = 0; p < kMaxProbe; ++p) {
+        Slot* sl = tab + pos;
+        uint64_t cur = ld_relaxed(&sl->key);
+        if (cur == kEmptyKey) {
+            cur = atomicCAS(reinterpret_cast<unsigned long long*>(&sl->key), (unsigned long long)kEmptyKey,
+                            (unsigned long long)key);
+            if (cur == kEmptyKey) {
+                atomicAdd(&sl->count, inc);
+                return ADD_NEW;
+            }
+        }
+        if (cur == key) {
+            atomicAdd(&sl->count, inc);
+            return ADD_FOUND;
+        }
+        pos = (pos + 1) & mask;
+    }
+    return ADD_FULL;
+}
+
+// Read-only lookup; returns the slot index or ~0 when the key is absent.
+__device__ __forceinline__ uint64_t table_find(const Slot* tab, uint64_t mask, uint64_t key) {
+    uint64_t pos = mix64(key) & mask;
+    for (uint32_t p = 0; p < kMaxProbe; ++p) {
+        const uint64_t cur = tab[pos].key;
+        if (cur == key) return pos;
+        if (cur == kEmptyKey) return ~0ull;
+        pos = (pos + 1) & mask;
+    }
+    return ~0ull;
+}
+
+// Appends (key, count) records of the lanes with `pred` to the spill buffer;
+// one atomic per wave reserves the positions.  Reached by the whole wave.
+__device__ __forceinline__ void spill_push(const SpillBuf& sp, unsigned long long* ctr, bool pred,
+                                           uint64_t key, uint32_t count) {
+    const uint64_t b = __ballot(pred);
+    if (b == 0) return;
+    const int leader = __ffsll((long long)b) - 1;
+    uint64_t base = 0;
+    if (lane_id() == leader) base = atomicAdd(&ctr[C_SPILLED], (unsigned long long)__popcll(b));
+    base = readlane64(base, leader);
+    if (pred) {
+        const uint64_t idx = base + __popcll(b & lanemask_lt());
+        if (idx < sp.cap) {
+            sp.keys[idx] = key;
+            sp.counts[idx] = count;
+        } else {
+            atomicOr(&ctr[C_ERROR], (unsigned long long)kErrSpillOverflow);
+        }
+    }
+}
+
+// ------------------------------------------------------------ contraction ---
+
+__global__ void k_fill_table(Slot* tab, uint64_t cap) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        Slot s;
+        s.key = kEmptyKey;
+        s.count = 0;
+        s.aux = kNotSignificant;
+        tab[i] = s;
+    }
+}
+
+__global__ void k_zero_u64(uint64_t* p, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// Direct counting: every point goes straight to the device table.  A
+// workgroup covers blockDim * ITEMS consecutive points; lane t of the group
+// takes points base + t + j * blockDim so each load instruction is coalesced.
+template <typename T, int ITEMS>
+__global__ void k_count_direct(const T* __restrict__ pts, int64_t n, double scale, Slot* tab,
+                               uint64_t mask, SpillBuf sp, unsigned long long* ctr) {
+    const int64_t base = (int64_t)blockIdx.x * blockDim.x * ITEMS + threadIdx.x;
+    uint64_t key[ITEMS];
+    uint32_t valid = 0;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int64_t i = base + (int64_t)j * blockDim.x;
+        key[j] = 0;
+        if (i < n) {
+            double x, y;
+            load_point(pts, i, x, y);
+            if (tile_key(x, y, scale, key[j])) valid |= 1u << j;
+            else bad = true;
+        }
+    }
+    if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrRange);
+    uint32_t fresh = 0;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        int r = ADD_FOUND;
+        if (valid & (1u << j)) {
+            r = table_add(tab, mask, key[j], 1u);
+            fresh += (r == ADD_NEW);
+        }
+        spill_push(sp, ctr, r == ADD_FULL, key[j], 1u);
+    }
+    // one atomic per wave for the inserted-key counter
+    uint32_t tot = fresh;
+    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+    if (lane_id() == 0 && tot) atomicAdd(&ctr[C_INSERTED], (unsigned long long)tot);
+}
+
+// Counting with LDS pre-aggregation: a workgroup first combines equal tiles
+// of `sweeps` consecutive tiles of points in a small LDS hash table, then adds
+// each distinct tile once to the device table.  Points whose tile finds no
+// room in LDS go straight to the device table.  Pays off when a few hot tiles
+// take a large share of the points.
+template <typename T, int ITEMS>
+__global__ void k_count_preagg(const T* __restrict__ pts, int64_t n, double scale, Slot* tab,
+                               uint64_t mask, SpillBuf sp, unsigned long long* ctr, int lds_log2,
+                               int sweeps) {
+    extern __shared__ unsigned char smem[];
+    const uint32_t L = 1u << lds_log2;
+    uint64_t* lkey = reinterpret_cast<uint64_t*>(smem);
+    uint32_t* lcnt = reinterpret_cast<uint32_t*>(lkey + L);
+    for (uint32_t s = threadIdx.x; s < L; s += blockDim.x) {
+        lkey[s] = kEmptyKey;
+        lcnt[s] = 0;
+    }
+    __syncthreads();
+    bool bad = false;
+    uint32_t fresh = 0;
+    const int64_t span = (int64_t)blockDim.x * ITEMS;
+    for (int sw = 0; sw < sweeps; ++sw) {
+        const int64_t base = ((int64_t)blockIdx.x * sweeps + sw) * span + threadIdx.x;
+        if (base - threadIdx.x >= n) break;  // uniform across the workgroup
+        uint64_t key[ITEMS];
+        uint32_t valid = 0;
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int64_t i = base + (int64_t)j * blockDim.x;
+            key[j] = 0;
+            if (i < n) {
+                double x, y;
+                load_point(pts, i, x, y);
+                if (tile_key(x, y, scale, key[j])) valid |= 1u << j;
+                else bad = true;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            int r = ADD_FOUND;
+            if (valid & (1u << j)) {
+                const uint64_t k = key[j];
+                uint32_t pos = (uint32_t)(mix64(k) >> 40) & (L - 1);
+                bool done = false;
+                for (int p = 0; p < 8 && !done; ++p) {
+                    uint64_t cur = *(volatile uint64_t*)&lkey[pos];
+                    if (cur == kEmptyKey) cur = atomicCAS(reinterpret_cast<unsigned long long*>(&lkey[pos]),
+                                                          (unsigned long long)kEmptyKey, (unsigned long long)k);
+                    if (cur == kEmptyKey || cur == k) {
+                        atomicAdd(&lcnt[pos], 1u);
+                        done = true;
+                    }
+                    pos = (pos + 1) & (L - 1);
+                }
+                if (!done) {
+                    r = table_add(tab, mask, k, 1u);
+                    fresh += (r == ADD_NEW);
+                }
+            }
+            spill_push(sp, ctr, r == ADD_FULL, key[j], 1u);
+        }
+    }
+    if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrRange);
+    __syncthreads();
+    for (uint32_t s0 = 0; s0 < L; s0 += blockDim.x) {
+        const uint32_t s = s0 + threadIdx.x;
+        int r = ADD_FOUND;
+        uint64_t k = kEmptyKey;
+        uint32_t c = 0;
+        if (s < L) {
+            k = lkey[s];
+            c = lcnt[s];
+            if (k != kEmptyKey) {
+                r = table_add(tab, mask, k, c);
+                fresh += (r == ADD_NEW);
+            }
+        }
+        spill_push(sp, ctr, r == ADD_FULL, k, c);
+    }
+    uint32_t tot = fresh;
+    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+    if (lane_id() == 0 && tot) atomicAdd(&ctr[C_INSERTED], (unsigned long long)tot);
+}
+
+__global__ void k_insert_records(const uint64_t* keys, const uint32_t* counts, uint64_t n, Slot* tab,
+                                 uint64_t mask, SpillBuf sp, unsigned long long* ctr) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t n_round = (n + 63) / 64 * 64;  // whole waves iterate together
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_round; i += stride) {
+        int r = ADD_FOUND;
+        uint64_t k = 0;
+        uint32_t c = 0;
+        if (i < n) {
+            k = keys[i];
+            c = counts[i];
+            r = table_add(tab, mask, k, c);
+        }
+        wave_count(&ctr[C_INSERTED], r == ADD_NEW);
+        spill_push(sp, ctr, r == ADD_FULL, k, c);
+    }
+}
+
+__global__ void k_rehash(const Slot* from, uint64_t from_cap, Slot* to, uint64_t to_mask, SpillBuf sp,
+                         unsigned long long* ctr) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t n_round = (from_cap + 63) / 64 * 64;  // whole waves iterate together
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_round; i += stride) {
+        int r = ADD_FOUND;
+        uint64_t k = kEmptyKey;
+        uint32_t c = 0;
+        if (i < from_cap) {
+            const Slot s = from[i];
+            k = s.key;
+            c = s.count;
+            if (k != kEmptyKey) r = table_add(to, to_mask, k, c);
+        }
+        wave_count(&ctr[C_INSERTED], r == ADD_NEW);
+        spill_push(sp, ctr, r == ADD_FULL, k, c);
+    }
+}
+
+// ---------------------------------------------------------------- scans ----
+//
+// Stream compaction in three passes over a fixed grid of kScanBlocks
+// workgroups.  Workgroup b owns a contiguous range of indices, cut into tiles
+// of SCAN_TILE = 256 threads x 16 items (thread t takes tile offsets
+// t + 256 j).  Pass 1 counts flagged indices per range, pass 2 scans the
+// kScanBlocks partial counts, pass 3 recomputes the flags and writes every
+// flagged index to its position.  Positions follow index order, so the
+// compaction is stable.
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+constexpr int SCAN_WAVES = SCAN_THREADS / 64;
+
+__device__ __forceinline__ void block_range(uint64_t N, uint64_t& lo, uint64_t& hi) {
+    uint64_t per = (N + gridDim.x - 1) / gridDim.x;
+    per = (per + SCAN_TILE - 1) / SCAN_TILE * SCAN_TILE;
+    lo = (uint64_t)blockIdx.x * per;
+    hi = lo + per;
+    if (lo > N) lo = N;
+    if (hi > N) hi = N;
+}
+
+// Sum of a per-thread value over the workgroup (SCAN_THREADS threads).
+template <typename V>
+__device__ __forceinline__ V block_sum(V v, V* red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane_id() == 0) red[w] = v;
+    __syncthreads();
+    V t = 0;
+    for (int i = 0; i < SCAN_WAVES; ++i) t += red[i];
+    return t;
+}
+
+// Positions of the flagged items of one tile.  `bits` holds this lane's flags
+// (bit j for item j).  Returns the tile's flagged count; pos_j gives item j's
+// exclusive position within the tile (only meaningful when bit j is set).
+struct TileScratch {
+    uint32_t cnt[SCAN_ITEMS][SCAN_WAVES];
+    uint32_t total;
+};
+
+__device__ __forceinline__ uint32_t tile_positions(uint32_t bits, uint32_t (&pos)[SCAN_ITEMS],
+                                                   TileScratch& ts) {
+    const int w = threadIdx.x >> 6;
+    const uint64_t lt = lanemask_lt();
+    uint32_t within[SCAN_ITEMS];
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        const uint64_t b = __ballot((bits >> j) & 1u);
+        within[j] = __popcll(b & lt);
+        if (lane_id() == 0) ts.cnt[j][w] = __popcll(b);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int j = 0; j < SCAN_ITEMS; ++j)
+            for (int q = 0; q < SCAN_WAVES; ++q) {
+                const uint32_t c = ts.cnt[j][q];
+                ts.cnt[j][q] = run;
+                run += c;
+            }
+        ts.total = run;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) pos[j] = ts.cnt[j][w] + within[j];
+    const uint32_t total = ts.total;
+    __syncthreads();  // scratch is reused by the next tile
+    return total;
+}
+
+// Exclusive scan of kScanBlocks partial counts by one workgroup of 1024
+// threads; the total goes to *total_out.
+__global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* partials, unsigned long long* total_out) {
+    constexpr int PER = kScanBlocks / 1024;
+    __shared__ uint32_t wsum[16];
+    uint32_t v[PER];
+    uint32_t local = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        v[k] = partials[threadIdx.x * PER + k];
+        local += v[k];
+    }
+    // inclusive scan of `local` across the workgroup
+    uint32_t inc = local;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(inc, off);
+        if (lane_id() >= off) inc += o;
+    }
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 63) wsum[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int i = 0; i < 16; ++i) {
+            const uint32_t c = wsum[i];
+            wsum[i] = run;
+            run += c;
+        }
+        *total_out = run;
+    }
+    __syncthreads();
+    uint32_t ex = wsum[w] + inc - local;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        partials[threadIdx.x * PER + k] = ex;
+        ex += v[k];
+    }
+}
+
+// ---- significance scan (Algorithm 1: drop tiles with fewer than tau points) --
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_threshold_count(const Slot* tab, uint64_t cap, uint32_t tau,
+                                                                  uint32_t* partials, unsigned long long* ctr) {
+    __shared__ unsigned long long red[SCAN_WAVES];
+    uint64_t lo, hi;
+    block_range(cap, lo, hi);
+    unsigned long long sig = 0, occ = 0, sum = 0;
+    for (uint64_t t0 = lo; t0 < hi; t0 += SCAN_TILE) {
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
+            const uint64_t i = t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x;
+            if (i < hi) {
+                const Slot s = tab[i];
+                if (s.key != kEmptyKey) {
+                    occ += 1;
+                    sum += s.count;
+                    sig += (s.count >= tau);
+                }
+            }
+        }
+    }
+    sig = block_sum(sig, red);
+    occ = block_sum(occ, red);
+    sum = block_sum(sum, red);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = (uint32_t)sig;
+        if (occ) atomicAdd(&ctr[C_DISTINCT], occ);
+        if (sum) atomicAdd(&ctr[C_SUM], sum);
+    }
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_threshold_scatter(Slot* tab, uint64_t cap, uint32_t tau,
+                                                                    const uint32_t* offsets, uint64_t* s_key,
+                                                                    uint32_t* s_count, uint32_t* parent,
+                                                                    uint32_t* size) {
+    __shared__ TileScratch ts;
+    uint64_t lo, hi;
+    block_range(cap, lo, hi);
+    uint64_t run = offsets[blockIdx.x];
+    for (uint64_t t0 = lo; t0 < hi; t0 += SCAN_TILE) {
+        uint32_t bits = 0;
+        uint64_t key[SCAN_ITEMS];
+        uint32_t cnt[SCAN_ITEMS];
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
+            const uint64_t i = t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x;
+            key[j] = kEmptyKey;
+            cnt[j] = 0;
+            if (i < hi) {
+                const Slot s = tab[i];
+                key[j] = s.key;
+                cnt[j] = s.count;
+                if (s.key != kEmptyKey && s.count >= tau) bits |= 1u << j;
+            }
+        }
+        uint32_t pos[SCAN_ITEMS];
+        const uint32_t total = tile_positions(bits, pos, ts);
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
+            const uint64_t i = t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x;
+            if (key[j] == kEmptyKey) continue;
+            if (bits & (1u << j)) {
+                const uint64_t p = run + pos[j];
+                s_key[p] = key[j];
+                s_count[p] = cnt[j];
+                parent[p] = (uint32_t)p;
+                size[p] = 0;
+                tab[i].aux = (uint32_t)p;
+            } else {
+                tab[i].aux = kNotSignificant;
+            }
+        }
+        run += total;
+    }
+}
+
+// ---- export of all (key, count) pairs, for checking the contraction ---------
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_export_count(const Slot* tab, uint64_t cap, uint32_t* partials,
+                                                               unsigned long long* ctr) {
+    __shared__ unsigned long long red[SCAN_WAVES];
+    uint64_t lo, hi;
+    block_range(cap, lo, hi);
+    unsigned long long occ = 0;
+    for (uint64_t t0 = lo; t0 < hi; t0 += SCAN_TILE)
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
+            const uint64_t i = t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x;
+            if (i < hi && tab[i].key != kEmptyKey) occ += 1;
+        }
+    occ = block_sum(occ, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = (uint32_t)occ;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_export_scatter(const Slot* tab, uint64_t cap,
+                                                                 const uint32_t* offsets, uint64_t* keys,
+                                                                 uint32_t* counts, uint64_t out_cap) {
+    __shared__ TileScratch ts;
+    uint64_t lo, hi;
+    block_range(cap, lo, hi);
+    uint64_t run = offsets[blockIdx.x];
+    for (uint64_t t0 = lo; t0 < hi; t0 += SCAN_TILE) {
+        uint32_t bits = 0;
+        uint64_t key[SCAN_ITEMS];
+        uint32_t cnt[SCAN_ITEMS];
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
+            const uint64_t i = t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x;
+            key[j] = kEmptyKey;
+            cnt[j] = 0;
+            if (i < hi) {
+                const Slot s = tab[i];
+                key[j] = s.key;
+                cnt[j] = s.count;
+                if (s.key != kEmptyKey) bits |= 1u << j;
+            }
+        }
+        uint32_t pos[SCAN_ITEMS];
+        const uint32_t total = tile_positions(bits, pos, ts);
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
+            if (!(bits & (1u << j))) continue;
+            const uint64_t p = run + pos[j];
+            if (p < out_cap) {
+                keys[p] = key[j];
+                counts[p] = cnt[j];
+            }
+        }
+        run += total;
+    }
+}
+
+// ---------------------------------------------------------- agglomeration ---
+//
+// Union-find over compact indices.  A root is hooked under the root with the
+// smaller tile key, so parent chains strictly decrease in key and every final
+// root is its component's smallest tile: the label comes for free.
+
+// Walk bound: every chain is far shorter (hooks strictly decrease the key and
+// path halving shortens chains), so hitting it means corrupt state; the walk
+// then stops and raises kErrInternal instead of spinning.
+constexpr uint32_t kUfMaxSteps = 1u << 24;
+
+__device__ __forceinline__ uint32_t uf_find(uint32_t* parent, uint32_t x, uint32_t s, bool& bad) {
+    for (uint32_t it = 0; it < kUfMaxSteps; ++it) {
+        const uint32_t p = ld_relaxed(parent + x);
+        if (p >= s) break;
+        if (p == x) return x;
+        const uint32_t gp = ld_relaxed(parent + p);
+        if (gp >= s) break;
+        if (gp == p) return p;
+        st_relaxed(parent + x, gp);  // path halving; x is not a root, no hook races this
+        x = gp;
+    }
+    bad = true;
+    return x;
+}
+
+__device__ __forceinline__ void uf_unite(uint32_t* parent, const uint64_t* key, uint32_t a, uint32_t b, uint32_t s,
+                                         bool& bad) {
+    for (uint32_t it = 0; it < kUfMaxSteps; ++it) {
+        a = uf_find(parent, a, s, bad);
+        b = uf_find(parent, b, s, bad);
+        if (bad || a == b) return;
+        if (key[a] < key[b]) {
+            const uint32_t t = a;
+            a = b;
+            b = t;
+        }
+        // a has the larger key: hook it under b if it is still a root
+        if (atomicCAS(parent + a, a, b) == a) return;
+    }
+    bad = true;
+}
+
+__device__ __forceinline__ void link_neighbour(const Slot* tab, uint64_t mask, uint32_t* parent,
+                                               const uint64_t* s_key, uint32_t i, uint32_t bx, uint32_t by, uint32_t s,
+                                               bool& bad) {
+    const uint64_t nk = ((uint64_t)bx << 32) | by;
+    const uint64_t slot = table_find(tab, mask, nk);
+    if (slot == ~0ull) return;
+    const uint32_t j = tab[slot].aux;
+    if (j == kNotSignificant) return;
+    if (j >= s) {
+        bad = true;
+        return;
+    }
+    uf_unite(parent, s_key, i, j, s, bad);
+}
+
+// Each significant tile looks up its four forward neighbours (x, y+1),
+// (x+1, y-1), (x+1, y), (x+1, y+1); with the symmetric backward lookups done
+// by those neighbours this covers all eight directions.  Biased coordinates
+// of valid tiles lie in [2, 2^32 - 2]; neighbours outside are skipped.
+__global__ void k_hook(const Slot* tab, uint64_t mask, const uint64_t* s_key, uint32_t* parent,
+                       unsigned long long* ctr) {
+    const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
+    bool bad = false;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < s;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = s_key[i];
+        const uint32_t bx = (uint32_t)(key >> 32);
+        const uint32_t by = (uint32_t)key;
+        const bool up = by < 0xFFFFFFFEu;
+        const bool down = by > 2u;
+        const bool right = bx < 0xFFFFFFFEu;
+        if (up) link_neighbour(tab, mask, parent, s_key, (uint32_t)i, bx, by + 1, s, bad);
+        if (right) {
+            if (down) link_neighbour(tab, mask, parent, s_key, (uint32_t)i, bx + 1, by - 1, s, bad);
+            link_neighbour(tab, mask, parent, s_key, (uint32_t)i, bx + 1, by, s, bad);
+            if (up) link_neighbour(tab, mask, parent, s_key, (uint32_t)i, bx + 1, by + 1, s, bad);
+        }
+    }
+    if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
+}
+
+// Full compression (parent[i] = root), component sizes and the root count.
+__global__ void k_compress(uint32_t* parent, uint32_t* size, unsigned long long* ctr) {
+    const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t s_round = ((uint64_t)s + 63) / 64 * 64;
+    bool bad = false;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < s_round; i += stride) {
+        bool root = false;
+        if (i < s) {
+            const uint32_t r = uf_find(parent, (uint32_t)i, s, bad);
+            st_relaxed(parent + i, r);
+            atomicAdd(size + r, 1u);
+            root = (r == (uint32_t)i);
+        }
+        wave_count(&ctr[C_COMPONENTS], root);
+    }
+    if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
+}
+
+// ---- mu filter (Algorithm 1: keep clusters of at least mu tiles) -----------
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_filter_count(const uint32_t* parent, const uint32_t* size,
+                                                               uint32_t mu, uint32_t* partials,
+                                                               unsigned long long* ctr) {
+    __shared__ unsigned long long red[SCAN_WAVES];
+    const uint64_t s = ctr[C_SIGNIFICANT];
+    uint64_t lo, hi;
+    block_range(s, lo, hi);
+    unsigned long long keep = 0, kept_roots = 0;
+    for (uint64_t t0 = lo; t0 < hi; t0 += SCAN_TILE)
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
+            const uint64_t i = t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x;
+            if (i < hi) {
+                const uint32_t r = parent[i];
+                const bool k = r < s && size[r] >= mu;
+                keep += k;
+                kept_roots += (k && r == (uint32_t)i);
+            }
+        }
+    keep = block_sum(keep, red);
+    kept_roots = block_sum(kept_roots, red);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = (uint32_t)keep;
+        if (kept_roots) atomicAdd(&ctr[C_CLUSTERS], kept_roots);
+    }
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_filter_scatter(const uint64_t* s_key, const uint32_t* s_count,
+                                                                 const uint32_t* parent, const uint32_t* size,
+                                                                 uint32_t mu, const uint32_t* offsets,
+                                                                 const unsigned long long* ctr, int32_t* out_kx,
+                                                                 int32_t* out_ky, uint32_t* out_count,
+                                                                 uint64_t* out_label) {
+    __shared__ TileScratch ts;
+    const uint64_t s = ctr[C_SIGNIFICANT];
+    uint64_t lo, hi;
+    block_range(s, lo, hi);
+    uint64_t run = offsets[blockIdx.x];
+    for (uint64_t t0 = lo; t0 < hi; t0 += SCAN_TILE) {
+        uint32_t bits = 0;
+        uint32_t root[SCAN_ITEMS];
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
+            const uint64_t i = t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x;
+            root[j] = 0;
+            if (i < hi) {
+                root[j] = parent[i];
+                if (root[j] < s && size[root[j]] >= mu) bits |= 1u << j;
+            }
+        }
+        uint32_t pos[SCAN_ITEMS];
+        const uint32_t total = tile_positions(bits, pos, ts);
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
+            if (!(bits & (1u << j))) continue;
+            const uint64_t i = t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x;
+            const uint64_t p = run + pos[j];
+            const uint64_t key = s_key[i];
+            out_kx[p] = (int32_t)((uint32_t)(key >> 32) - 0x80000000u);
+            out_ky[p] = (int32_t)((uint32_t)key - 0x80000000u);
+            out_count[p] = s_count[i];
+            out_label[p] = s_key[root[j]];
+        }
+        run += total;
+    }
+}
+
+int grid_for(uint64_t work, int block, int max_blocks) {
+    uint64_t g = (work + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > (uint64_t)max_blocks) g = max_blocks;
+    return (int)g;
+}
+
+// Persistent grids for the data-dependent passes: enough waves to fill 256
+// CUs several times over.
+constexpr int kPersistBlocks = 256 * 8;
+
+template <typename T, int ITEMS>
+hipError_t launch_count_t(const T* pts, int64_t n, double scale, Slot* tab, uint64_t mask, SpillBuf sp,
+                          unsigned long long* ctr, const KernelTuning& tu, hipStream_t stream) {
+    const int block = tu.block;
+    if (tu.preagg_slots > 0) {
+        int lds_log2 = 0;
+        while ((1 << lds_log2) < tu.preagg_slots) ++lds_log2;
+        const int sweeps = tu.preagg_tiles > 0 ? tu.preagg_tiles : 1;
+        const int64_t per_block = (int64_t)block * ITEMS * sweeps;
+        const int64_t grid = (n + per_block - 1) / per_block;
+        const size_t lds = (size_t)(1u << lds_log2) * (sizeof(uint64_t) + sizeof(uint32_t));
+        hipLaunchKernelGGL((k_count_preagg<T, ITEMS>), dim3((unsigned)grid), dim3(block), lds, stream, pts, n,
+                           scale, tab, mask, sp, ctr, lds_log2, sweeps);
+    } else {
+        const int64_t per_block = (int64_t)block * ITEMS;
+        const int64_t grid = (n + per_block - 1) / per_block;
+        hipLaunchKernelGGL((k_count_direct<T, ITEMS>), dim3((unsigned)grid), dim3(block), 0, stream, pts, n, scale,
+                           tab, mask, sp, ctr);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_count_items(const T* pts, int64_t n, double scale, Slot* tab, uint64_t mask, SpillBuf sp,
+                              unsigned long long* ctr, const KernelTuning& tu, hipStream_t stream) {
+    switch (tu.items) {
+        case 1: return launch_count_t<T, 1>(pts, n, scale, tab, mask, sp, ctr, tu, stream);
+        case 2: return launch_count_t<T, 2>(pts, n, scale, tab, mask, sp, ctr, tu, stream);
+        case 4: return launch_count_t<T, 4>(pts, n, scale, tab, mask, sp, ctr, tu, stream);
+        case 8: return launch_count_t<T, 8>(pts, n, scale, tab, mask, sp, ctr, tu, stream);
+        default: return launch_count_t<T, 16>(pts, n, scale, tab, mask, sp, ctr, tu, stream);
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers ---
+
+hipError_t launch_fill_table(Slot* tab, uint64_t cap, hipStream_t stream) {
+    hipLaunchKernelGGL(k_fill_table, dim3(grid_for(cap, 256, 65536)), dim3(256), 0, stream, tab, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(uint64_t* p, uint64_t n, hipStream_t stream) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(n, 256, 65536)), dim3(256), 0, stream, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_count(const void* pts, int64_t n, int dtype, double scale, Slot* tab, uint64_t cap,
+                                 SpillBuf spill, unsigned long long* ctr, const KernelTuning& tu,
+                                 hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const uint64_t mask = cap - 1;
+    if (dtype == 1)
+        return launch_count_items(static_cast<const float*>(pts), n, scale, tab, mask, spill, ctr, tu, stream);
+    return launch_count_items(static_cast<const double*>(pts), n, scale, tab, mask, spill, ctr, tu, stream);
+}
+
+hipError_t launch_insert_records(const uint64_t* keys, const uint32_t* counts, uint64_t n, Slot* tab,
+                                 uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_insert_records, dim3(grid_for(n, 256, kPersistBlocks)), dim3(256), 0, stream, keys,
+                       counts, n, tab, cap - 1, spill, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_rehash(const Slot* from, uint64_t from_cap, Slot* to, uint64_t to_cap, SpillBuf spill,
+                         unsigned long long* ctr, hipStream_t stream) {
+    hipLaunchKernelGGL(k_rehash, dim3(grid_for(from_cap, 256, kPersistBlocks)), dim3(256), 0, stream, from,
+                       from_cap, to, to_cap - 1, spill, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_export_tiles(const Slot* tab, uint64_t tcap, uint64_t* keys, uint32_t* counts, uint64_t cap,
+                               uint32_t* partials, unsigned long long* ctr, hipStream_t stream) {
+    hipLaunchKernelGGL(k_export_count, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, tab, tcap, partials, ctr);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, stream, partials, ctr + C_DISTINCT);
+    hipLaunchKernelGGL(k_export_scatter, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, tab, tcap, partials,
+                       keys, counts, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_threshold(Slot* tab, uint64_t cap, uint32_t tau, uint64_t* s_key, uint32_t* s_count,
+                            uint32_t* parent, uint32_t* size, uint32_t* partials, unsigned long long* ctr,
+                            hipStream_t stream) {
+    hipLaunchKernelGGL(k_threshold_count, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, tab, cap, tau,
+                       partials, ctr);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, stream, partials, ctr + C_SIGNIFICANT);
+    hipLaunchKernelGGL(k_threshold_scatter, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, tab, cap, tau,
+                       partials, s_key, s_count, parent, size);
+    return hipGetLastError();
+}
+
+hipError_t launch_agglomerate(const Slot* tab, uint64_t cap, const uint64_t* s_key, uint32_t* parent,
+                              uint32_t* size, uint64_t s_max, unsigned long long* ctr, hipStream_t stream) {
+    const int grid = grid_for(s_max, 256, kPersistBlocks);
+    hipLaunchKernelGGL(k_hook, dim3(grid), dim3(256), 0, stream, tab, cap - 1, s_key, parent, ctr);
+    hipLaunchKernelGGL(k_compress, dim3(grid), dim3(256), 0, stream, parent, size, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter(const uint64_t* s_key, const uint32_t* s_count, const uint32_t* parent,
+                         const uint32_t* size, uint32_t mu, uint64_t s_max, int32_t* out_kx, int32_t* out_ky,
+                         uint32_t* out_count, uint64_t* out_label, uint32_t* partials, unsigned long long* ctr,
+                         hipStream_t stream) {
+    (void)s_max;
+    hipLaunchKernelGGL(k_filter_count, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, parent, size, mu,
+                       partials, ctr);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, stream, partials, ctr + C_TILES);
+    hipLaunchKernelGGL(k_filter_scatter, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, s_key, s_count, parent,
+                       size, mu, partials, ctr, out_kx, out_ky, out_count, out_label);
+    return hipGetLastError();
+}
+
+}  // namespace rst

@@ -1,0 +1,112 @@
+// Host-side runtime pieces shared by the plain, streaming, batched and served
+// forms: error reporting, the device memory pool, the table life cycle and the
+// result object.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "raster.h"
+#include "raster_internal.h"
+
+namespace rst {
+class DevicePool;
+}
+
+struct raster_result {
+    rst::DevicePool* pool = nullptr;  // owner of `block`
+    void* block = nullptr;            // one device allocation holding the arrays
+    uint64_t* label = nullptr;
+    int32_t* kx = nullptr;
+    int32_t* ky = nullptr;
+    uint32_t* count = nullptr;
+    int64_t tiles = 0;
+    int64_t clusters = 0;
+    raster_stats stats{};
+};
+
+namespace rst {
+
+extern thread_local std::string g_last_error;
+raster_status fail(raster_status s, const char* fmt, ...);
+raster_status hip_fail(hipError_t e, const char* what);
+
+raster_tuning current_tuning();
+KernelTuning kernel_tuning(const raster_tuning& t);
+bool scale_for_precision(int32_t p, double* s);
+uint64_t next_pow2(uint64_t v);
+raster_status check_points(const void* p, int64_t n, raster_dtype dt);
+raster_status check_params(double scale, uint32_t tau, uint32_t mu);
+
+class DevicePool {
+  public:
+    static DevicePool& get(int device);
+    hipError_t alloc(void** out, size_t bytes);
+    void release(void* p);
+    void trim();
+    size_t used_bytes();
+
+  private:
+    std::mutex mu_;
+    std::multimap<size_t, void*> free_;
+    std::unordered_map<void*, size_t> sizes_;
+    size_t cached_ = 0, used_ = 0;
+    int device_ = 0;
+};
+
+struct Buffers {
+    DevicePool* pool = nullptr;
+    std::vector<void*> blocks;
+    ~Buffers();
+    hipError_t take(void** out, size_t bytes);
+    void give_back(void* p);
+    void release_all();
+};
+
+// One device tile table and everything needed to fill it and cluster it.
+struct TableRun {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    double scale = 1.0;
+    uint32_t tau = 1, mu = 1;
+    raster_tuning tuning{};
+    Buffers bufs;
+    Slot* tab = nullptr;
+    uint64_t cap = 0;
+    unsigned long long* ctr = nullptr;    // device counters
+    unsigned long long* h_ctr = nullptr;  // pinned host mirror
+    uint32_t* partials = nullptr;
+    uint64_t* spill_keys[2] = {nullptr, nullptr};
+    uint32_t* spill_counts[2] = {nullptr, nullptr};
+    uint64_t spill_cap = 0;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev_chunk = nullptr;
+    hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;  // around the last counting launch
+    int64_t count_launches = 0;
+    double us_count_kernel = 0.0;
+    bool chunk_pending = false;
+    bool timing_started = false;
+    int64_t n_points = 0;
+    int64_t grow_events = 0;
+    raster_status failed = RASTER_OK;
+
+    ~TableRun();
+    raster_status init(double scale, uint32_t tau, uint32_t mu, int64_t tile_hint, hipStream_t stream);
+    raster_status feed(const void* pts, int64_t n, raster_dtype dt);
+    raster_status finish(raster_result** out);
+    raster_status export_tiles(uint64_t* keys, uint32_t* counts, int64_t cap_rows, int64_t* m);
+
+    raster_status alloc_table(uint64_t c, Slot** t, uint64_t* c_out);
+    raster_status ensure_spill(uint64_t need);
+    raster_status pull_counters();
+    raster_status grow(uint64_t new_cap, uint64_t pending, int src);
+    raster_status settle();
+};
+
+}  // namespace rst

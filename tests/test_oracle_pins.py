@@ -224,3 +224,19 @@ def test_non_integer_scale(oracle_mod):
     kx, ky = oracle_mod.project(pts, s)
     assert kx.tolist() == [int(math.trunc(1.0 * s)), int(math.trunc(1.0001 * s))]
     assert ky.tolist() == [int(math.trunc(2.0 * s)), int(math.trunc(2.0001 * s))]
+
+
+def test_count_tiles_matches_accumulator(oracle_mod):
+    # the single-tile query agrees with the full accumulator on every tile,
+    # and reports zero for tiles no point falls on
+    rng = np.random.default_rng(21)
+    pts = rng.normal(0.0, 0.3, size=(5000, 2))
+    s = oracle_mod.scale_for_precision(1)
+    st = oracle_mod.OracleStream(s, 1, 1)
+    st.feed(pts)
+    kx, ky, c = st.tile_counts()
+    qx = np.concatenate([kx, [999, -999]])
+    qy = np.concatenate([ky, [0, 5]])
+    got = oracle_mod.count_tiles(pts[:2500], s, qx, qy)
+    got = oracle_mod.count_tiles(pts[2500:], s, qx, qy, out=got)
+    assert got[:-2].tolist() == c.tolist() and got[-2:].tolist() == [0, 0]
