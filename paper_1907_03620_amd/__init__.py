@@ -344,7 +344,7 @@ class Tuning:
     block: int = 256
     items: int = 4
     preagg_slots: int = 0
-    load_factor: float = 0.5
+    load_factor: float = 0.6
 
 
 def set_tuning(t: Tuning | None = None, **kw) -> None:

@@ -48,7 +48,7 @@ raster_status hip_fail(hipError_t e, const char* what) {
 // ========================================================= tuning ==========
 
 static std::mutex g_tuning_mu;
-static raster_tuning g_tuning = {256, 4, 0, 0.5f};
+static raster_tuning g_tuning = {256, 4, 0, 0.6f};
 
 raster_tuning current_tuning() {
     std::lock_guard<std::mutex> g(g_tuning_mu);
@@ -242,6 +242,7 @@ raster_status TableRun::init(double scale_, uint32_t tau_, uint32_t mu_, int64_t
     HIP_TRY(bufs.take((void**)&ctr, kCounterWords * sizeof(unsigned long long)), "counters");
     HIP_TRY(bufs.take((void**)&partials, kScanBlocks * sizeof(uint32_t)), "scan partials");
     HIP_TRY(launch_zero_u64((uint64_t*)ctr, kCounterWords, stream), "zero counters");
+    hinted = tile_hint > 0;
     const double lf = tuning.load_factor;
     const uint64_t want = (uint64_t)std::max<double>(4096.0, (double)std::max<int64_t>(tile_hint, 1) / lf);
     return alloc_table(next_pow2(want), &tab, &cap);
@@ -255,18 +256,19 @@ raster_status TableRun::alloc_table(uint64_t c, Slot** t, uint64_t* c_out) {
     return RASTER_OK;
 }
 
-raster_status TableRun::ensure_spill(uint64_t need) {
-    if (spill_cap >= need) return RASTER_OK;
+// Makes spill buffer b hold at least `need` records.  Only that buffer is
+// replaced, so records still waiting in the other one survive.
+raster_status TableRun::ensure_spill(int b, uint64_t need) {
+    if (spill_cap[b] >= need) return RASTER_OK;
     const uint64_t c = std::max<uint64_t>(need, 1 << 16);
-    for (int b = 0; b < 2; ++b) {
-        if (spill_keys[b]) bufs.give_back(spill_keys[b]);
-        if (spill_counts[b]) bufs.give_back(spill_counts[b]);
-        spill_keys[b] = nullptr;
-        spill_counts[b] = nullptr;
-        HIP_TRY(bufs.take((void**)&spill_keys[b], c * sizeof(uint64_t)), "spill keys");
-        HIP_TRY(bufs.take((void**)&spill_counts[b], c * sizeof(uint32_t)), "spill counts");
-    }
-    spill_cap = c;
+    if (spill_keys[b]) bufs.give_back(spill_keys[b]);
+    if (spill_counts[b]) bufs.give_back(spill_counts[b]);
+    spill_keys[b] = nullptr;
+    spill_counts[b] = nullptr;
+    spill_cap[b] = 0;
+    HIP_TRY(bufs.take((void**)&spill_keys[b], c * sizeof(uint64_t)), "spill keys");
+    HIP_TRY(bufs.take((void**)&spill_counts[b], c * sizeof(uint32_t)), "spill counts");
+    spill_cap[b] = c;
     return RASTER_OK;
 }
 
@@ -287,10 +289,11 @@ raster_status TableRun::grow(uint64_t new_cap, uint64_t pending, int src) {
         raster_status st = alloc_table(new_cap, &nt, &nc);
         if (st != RASTER_OK) return st;
         const int dst = src ^ 1;
-        st = ensure_spill(std::max<uint64_t>(cap + pending, spill_cap));
+        // the rehash spills at most `cap` records and the re-insert `pending`
+        st = ensure_spill(dst, cap + pending);
         if (st != RASTER_OK) return st;
         HIP_TRY(launch_zero_u64((uint64_t*)ctr + C_INSERTED, 2, stream), "reset counters");
-        SpillBuf sp{spill_keys[dst], spill_counts[dst], spill_cap};
+        SpillBuf sp{spill_keys[dst], spill_counts[dst], spill_cap[dst]};
         HIP_TRY(launch_rehash(tab, cap, nt, nc, sp, ctr, stream), "rehash");
         HIP_TRY(launch_insert_records(spill_keys[src], spill_counts[src], pending, nt, nc, sp, ctr, stream),
                 "reinsert");
@@ -343,23 +346,31 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
     if (n == 0) return RASTER_OK;
     if ((uint64_t)n_points + (uint64_t)n > 0xFFFFFFFFull)
         return fail(RASTER_E_RANGE, "more than 2^32 - 1 points in one table");
-    // keep the table under its target load: grow before the chunk if the
-    // previous chunks already filled it past the target
     const double lf = tuning.load_factor;
-    if ((double)h_ctr[C_INSERTED] > lf * (double)cap) {
-        st = grow(next_pow2((uint64_t)(2.0 * (double)h_ctr[C_INSERTED] / lf)), 0, 0);
+    uint64_t want = 0;
+    if (n_points == 0 && !hinted) {
+        // no hint and nothing seen yet: size for half the first chunk's points
+        // being distinct tiles
+        want = next_pow2((uint64_t)((double)n / 2.0 / lf) + 1);
+    } else if ((double)h_ctr[C_INSERTED] > lf * (double)cap) {
+        // keep the table under its target load: grow before the chunk if the
+        // previous chunks already filled it past the target
+        want = next_pow2((uint64_t)(2.0 * (double)h_ctr[C_INSERTED] / lf));
+    }
+    if (want > cap) {
+        st = grow(want, 0, 0);
         if (st != RASTER_OK) {
             failed = st;
             return st;
         }
     }
-    st = ensure_spill((uint64_t)n);
+    st = ensure_spill(0, (uint64_t)n);
     if (st != RASTER_OK) return st;
     if (!timing_started) {
         HIP_TRY(hipEventRecord(ev[0], stream), "hipEventRecord");
         timing_started = true;
     }
-    SpillBuf sp{spill_keys[0], spill_counts[0], spill_cap};
+    SpillBuf sp{spill_keys[0], spill_counts[0], spill_cap[0]};
     HIP_TRY(hipEventRecord(ev_k0, stream), "hipEventRecord");
     HIP_TRY(launch_project_count(pts, n, (int)dt, scale, tab, cap, sp, ctr, kernel_tuning(tuning), stream),
             "project_count");
@@ -545,7 +556,7 @@ raster_status raster_begin_scaled(double scale, uint32_t tau, uint32_t mu, int64
     if (s != RASTER_OK) return s;
     if (tile_hint < 0) return fail(RASTER_E_INVAL, "negative tile_hint");
     raster_stream* h = new raster_stream();
-    s = h->run.init(scale, tau, mu, tile_hint > 0 ? tile_hint : (1 << 20), stream);
+    s = h->run.init(scale, tau, mu, tile_hint, stream);
     if (s != RASTER_OK) {
         delete h;
         return s;
@@ -608,7 +619,7 @@ void raster_stream_destroy(raster_stream* st) {
 }
 
 raster_status raster_set_tuning(const raster_tuning* t) {
-    raster_tuning v = {256, 4, 0, 0.5f};
+    raster_tuning v = {256, 4, 0, 0.6f};
     if (t) {
         v = *t;
         if (v.block < 64 || v.block > 1024 || v.block % 64) return fail(RASTER_E_INVAL, "block must be 64..1024, x64");

@@ -84,7 +84,7 @@ struct TableRun {
     uint32_t* partials = nullptr;
     uint64_t* spill_keys[2] = {nullptr, nullptr};
     uint32_t* spill_counts[2] = {nullptr, nullptr};
-    uint64_t spill_cap = 0;
+    uint64_t spill_cap[2] = {0, 0};
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     hipEvent_t ev_chunk = nullptr;
     hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;  // around the last counting launch
@@ -92,6 +92,7 @@ struct TableRun {
     double us_count_kernel = 0.0;
     bool chunk_pending = false;
     bool timing_started = false;
+    bool hinted = false;  // tile_hint given: the first chunk does not resize the table
     int64_t n_points = 0;
     int64_t grow_events = 0;
     raster_status failed = RASTER_OK;
@@ -103,7 +104,7 @@ struct TableRun {
     raster_status export_tiles(uint64_t* keys, uint32_t* counts, int64_t cap_rows, int64_t* m);
 
     raster_status alloc_table(uint64_t c, Slot** t, uint64_t* c_out);
-    raster_status ensure_spill(uint64_t need);
+    raster_status ensure_spill(int b, uint64_t need);
     raster_status pull_counters();
     raster_status grow(uint64_t new_cap, uint64_t pending, int src);
     raster_status settle();
