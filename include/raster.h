@@ -82,9 +82,11 @@ typedef struct raster_stats {
     float us_threshold;        /* significance scan and compaction                */
     float us_agglomerate;      /* neighbour union-find                            */
     float us_filter;           /* mu filter, labels and output compaction         */
-    int64_t count_launches;    /* launches of the projection + counting kernel    */
+    int64_t count_launches;    /* launches of the kernel that streams the points   */
     float us_count_kernel;     /* their summed device time, microseconds          */
-    float reserved;
+    float us_bin_keys;         /* binned path: second-level binning, summed       */
+    float us_aggregate;        /* binned path: LDS partition updates, summed      */
+    int32_t flushes;           /* binned path: groups of keys applied to the table */
 } raster_stats;
 
 /* Launch knobs of the contraction kernels.  Any value gives the same result;
@@ -96,6 +98,12 @@ typedef struct raster_tuning {
                              in [256, 4096]): duplicate tiles within a workgroup's points are
                              combined in LDS before touching the device table               */
     float load_factor;    /* target occupancy of the device table in (0.05, 0.9]               */
+    int32_t mode;         /* counting path: 0 auto, 1 direct (one device atomic per point),
+                             2 binned (keys binned by table partition, then each partition
+                             updated in LDS by one workgroup; used when the table has
+                             128..65536 partitions of 4096 slots, else direct)            */
+    int32_t group_mpoints; /* binned path: millions of points binned before the table is
+                              updated (1..4096); bounds the binning and spill buffers      */
 } raster_tuning;
 
 /* ---- plain form (Algorithm 1 on one resident point set) -------------------- */

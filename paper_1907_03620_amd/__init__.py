@@ -49,12 +49,14 @@ class _Stats(ctypes.Structure):
                 ("us_contract", ctypes.c_float), ("us_threshold", ctypes.c_float),
                 ("us_agglomerate", ctypes.c_float), ("us_filter", ctypes.c_float),
                 ("count_launches", ctypes.c_int64), ("us_count_kernel", ctypes.c_float),
-                ("reserved", ctypes.c_float)]
+                ("us_bin_keys", ctypes.c_float), ("us_aggregate", ctypes.c_float),
+                ("flushes", ctypes.c_int32)]
 
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("items", ctypes.c_int32),
-                ("preagg_slots", ctypes.c_int32), ("load_factor", ctypes.c_float)]
+                ("preagg_slots", ctypes.c_int32), ("load_factor", ctypes.c_float),
+                ("mode", ctypes.c_int32), ("group_mpoints", ctypes.c_int32)]
 
 
 class _Job(ctypes.Structure):
@@ -345,6 +347,8 @@ class Tuning:
     items: int = 4
     preagg_slots: int = 0
     load_factor: float = 0.6
+    mode: int = 0
+    group_mpoints: int = 256
 
 
 def set_tuning(t: Tuning | None = None, **kw) -> None:
@@ -355,11 +359,12 @@ def set_tuning(t: Tuning | None = None, **kw) -> None:
     t = t or Tuning()
     for k, v in kw.items():
         setattr(t, k, v)
-    c = _Tuning(int(t.block), int(t.items), int(t.preagg_slots), float(t.load_factor))
+    c = _Tuning(int(t.block), int(t.items), int(t.preagg_slots), float(t.load_factor), int(t.mode),
+                int(t.group_mpoints))
     _check(lib.raster_set_tuning(ctypes.byref(c)), "raster_set_tuning")
 
 
 def get_tuning() -> Tuning:
     c = _Tuning()
     _check(load().raster_get_tuning(ctypes.byref(c)), "raster_get_tuning")
-    return Tuning(c.block, c.items, c.preagg_slots, c.load_factor)
+    return Tuning(c.block, c.items, c.preagg_slots, c.load_factor, c.mode, c.group_mpoints)

@@ -48,7 +48,8 @@ raster_status hip_fail(hipError_t e, const char* what) {
 // ========================================================= tuning ==========
 
 static std::mutex g_tuning_mu;
-static raster_tuning g_tuning = {256, 4, 0, 0.6f};
+static const raster_tuning kDefaultTuning = {256, 4, 0, 0.6f, 0, 256};
+static raster_tuning g_tuning = kDefaultTuning;
 
 raster_tuning current_tuning() {
     std::lock_guard<std::mutex> g(g_tuning_mu);
@@ -218,8 +219,11 @@ raster_status check_params(double scale, uint32_t tau, uint32_t mu) {
 TableRun::~TableRun() {
     for (hipEvent_t& e : ev) if (e) (void)hipEventDestroy(e);
     if (ev_chunk) (void)hipEventDestroy(ev_chunk);
-    if (ev_k0) (void)hipEventDestroy(ev_k0);
-    if (ev_k1) (void)hipEventDestroy(ev_k1);
+    for (const Span& sp : spans) {
+        (void)hipEventDestroy(sp.a);
+        (void)hipEventDestroy(sp.b);
+    }
+    for (hipEvent_t e : ev_free) (void)hipEventDestroy(e);
     if (h_ctr) (void)hipHostFree(h_ctr);
 }
 
@@ -232,13 +236,12 @@ raster_status TableRun::init(double scale_, uint32_t tau_, uint32_t mu_, int64_t
     HIP_TRY(hipGetDevice(&device), "hipGetDevice");
     bufs.pool = &DevicePool::get(device);
     tuning = current_tuning();
+    group_budget = (uint64_t)tuning.group_mpoints * 1000000ull;
     HIP_TRY(hipHostMalloc((void**)&h_ctr, kCounterWords * sizeof(unsigned long long), hipHostMallocDefault),
             "hipHostMalloc");
     std::memset(h_ctr, 0, kCounterWords * sizeof(unsigned long long));
     for (hipEvent_t& e : ev) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
     HIP_TRY(hipEventCreateWithFlags(&ev_chunk, hipEventDisableTiming), "hipEventCreate");
-    HIP_TRY(hipEventCreate(&ev_k0), "hipEventCreate");
-    HIP_TRY(hipEventCreate(&ev_k1), "hipEventCreate");
     HIP_TRY(bufs.take((void**)&ctr, kCounterWords * sizeof(unsigned long long)), "counters");
     HIP_TRY(bufs.take((void**)&partials, kScanBlocks * sizeof(uint32_t)), "scan partials");
     HIP_TRY(launch_zero_u64((uint64_t*)ctr, kCounterWords, stream), "zero counters");
@@ -276,12 +279,54 @@ raster_status TableRun::pull_counters() {
     HIP_TRY(hipMemcpyAsync(h_ctr, ctr, kCounterWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream),
             "counter copy");
     HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    resolve_spans();
     return RASTER_OK;
+}
+
+// ---- per-kernel device timing: events around launches, read after a sync ----
+
+raster_status TableRun::span_begin(int kind, hipEvent_t* a) {
+    (void)kind;
+    if (!ev_free.empty()) {
+        *a = ev_free.back();
+        ev_free.pop_back();
+    } else {
+        HIP_TRY(hipEventCreate(a), "hipEventCreate");
+    }
+    HIP_TRY(hipEventRecord(*a, stream), "hipEventRecord");
+    return RASTER_OK;
+}
+
+raster_status TableRun::span_end(int kind, hipEvent_t a) {
+    hipEvent_t b;
+    if (!ev_free.empty()) {
+        b = ev_free.back();
+        ev_free.pop_back();
+    } else {
+        HIP_TRY(hipEventCreate(&b), "hipEventCreate");
+    }
+    HIP_TRY(hipEventRecord(b, stream), "hipEventRecord");
+    spans.push_back(Span{kind, a, b});
+    return RASTER_OK;
+}
+
+void TableRun::resolve_spans() {
+    for (const Span& sp : spans) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, sp.a, sp.b) == hipSuccess) {
+            span_us[sp.kind] += 1000.0 * ms;
+            span_n[sp.kind] += 1;
+        }
+        ev_free.push_back(sp.a);
+        ev_free.push_back(sp.b);
+    }
+    spans.clear();
 }
 
 // Moves everything into a table of new_cap slots, then re-adds the `pending`
 // spilled records held in spill buffer `src`.  Repeats with a larger table
-// in the (unlikely) case the new table spills again.
+// in the (unlikely) case the new table spills again.  Keys waiting in the
+// coarse buckets stay valid: their bucket depends on the key alone.
 raster_status TableRun::grow(uint64_t new_cap, uint64_t pending, int src) {
     while (true) {
         Slot* nt = nullptr;
@@ -311,14 +356,13 @@ raster_status TableRun::grow(uint64_t new_cap, uint64_t pending, int src) {
     }
 }
 
-// Reads the previous chunk's counters and repairs the table if it spilled.
+// Waits for the work enqueued by the last feed or flush, then checks its
+// counters: range errors fail the run, spilled records make the table grow.
 raster_status TableRun::settle() {
     if (!chunk_pending) return RASTER_OK;
     chunk_pending = false;
     HIP_TRY(hipEventSynchronize(ev_chunk), "hipEventSynchronize");
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, ev_k0, ev_k1) == hipSuccess) us_count_kernel += 1000.0 * ms;
-    count_launches += 1;
+    resolve_spans();
     if (h_ctr[C_ERROR] & kErrRange) {
         failed = RASTER_E_RANGE;
         return fail(RASTER_E_RANGE, "a coordinate is not finite or its tile is outside +-(2^31 - 2)");
@@ -338,6 +382,66 @@ raster_status TableRun::settle() {
         }
     }
     return RASTER_OK;
+}
+
+raster_status TableRun::mark_pending() {
+    HIP_TRY(hipMemcpyAsync(h_ctr, ctr, kCounterWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream),
+            "counter copy");
+    HIP_TRY(hipEventRecord(ev_chunk, stream), "hipEventRecord");
+    chunk_pending = true;
+    return RASTER_OK;
+}
+
+raster_status TableRun::ensure_bins() {
+    if (bin1) return RASTER_OK;
+    // a coarse bucket receives about group_budget / 128 keys; the slack is
+    // far beyond the binomial spread, and overflow only costs direct inserts
+    cap1 = (group_budget / kCoarse) + (group_budget / kCoarse) / 50 + 8192;
+    cap1 = (cap1 + 255) / 256 * 256;
+    HIP_TRY(bufs.take((void**)&bin1, kCoarse * cap1 * sizeof(uint64_t)), "coarse buckets");
+    HIP_TRY(bufs.take((void**)&cursor1, kCoarse * sizeof(uint32_t)), "coarse cursors");
+    HIP_TRY(launch_zero_u64((uint64_t*)cursor1, kCoarse / 2, stream), "zero cursors");
+    return RASTER_OK;
+}
+
+// Applies the keys waiting in the coarse buckets to the table.
+raster_status TableRun::flush() {
+    if (group_points == 0) return RASTER_OK;
+    raster_status st = settle();
+    if (st != RASTER_OK) return st;
+    const Geo g = make_geo(cap);
+    SpillBuf sp{spill_keys[0], spill_counts[0], spill_cap[0]};
+    if (!binned_geometry(g)) {
+        HIP_TRY(launch_drain_bins(bin1, cap1, cursor1, tab, cap, sp, ctr, stream), "drain bins");
+    } else {
+        const uint64_t parts = 1ull << g.p_log2;
+        uint64_t c2 = group_points / parts;
+        c2 = c2 + c2 / 8 + 4 * (uint64_t)std::sqrt((double)c2 + 1.0) + 256;
+        c2 = (c2 + 63) / 64 * 64;
+        if (parts * c2 > bin2_slots || parts > cursor2_n) {
+            if (bin2) bufs.give_back(bin2);
+            if (cursor2) bufs.give_back(cursor2);
+            bin2 = nullptr;
+            cursor2 = nullptr;
+            bin2_slots = parts * c2 + parts * c2 / 4;  // headroom for later groups
+            cursor2_n = parts;
+            HIP_TRY(bufs.take((void**)&bin2, bin2_slots * sizeof(uint64_t)), "partition buckets");
+            HIP_TRY(bufs.take((void**)&cursor2, cursor2_n * sizeof(uint32_t)), "partition cursors");
+        }
+        c2 = bin2_slots / parts;
+        hipEvent_t a = nullptr;
+        if ((st = span_begin(1, &a)) != RASTER_OK) return st;
+        HIP_TRY(launch_bin_keys(bin1, cap1, cursor1, bin2, c2, cursor2, tab, cap, sp, ctr, stream), "bin keys");
+        if ((st = span_end(1, a)) != RASTER_OK) return st;
+        if ((st = span_begin(2, &a)) != RASTER_OK) return st;
+        HIP_TRY(launch_aggregate(bin2, c2, cursor2, cursor1, tab, cap, sp, ctr, stream), "aggregate");
+        if ((st = span_end(2, a)) != RASTER_OK) return st;
+    }
+    flushes += 1;
+    group_points = 0;
+    st = mark_pending();
+    if (st != RASTER_OK) return st;
+    return settle();
 }
 
 raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
@@ -364,27 +468,53 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
             return st;
         }
     }
-    st = ensure_spill(0, (uint64_t)n);
-    if (st != RASTER_OK) return st;
     if (!timing_started) {
         HIP_TRY(hipEventRecord(ev[0], stream), "hipEventRecord");
         timing_started = true;
     }
-    SpillBuf sp{spill_keys[0], spill_counts[0], spill_cap[0]};
-    HIP_TRY(hipEventRecord(ev_k0, stream), "hipEventRecord");
-    HIP_TRY(launch_project_count(pts, n, (int)dt, scale, tab, cap, sp, ctr, kernel_tuning(tuning), stream),
-            "project_count");
-    HIP_TRY(hipEventRecord(ev_k1, stream), "hipEventRecord");
-    HIP_TRY(hipMemcpyAsync(h_ctr, ctr, kCounterWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream),
-            "counter copy");
-    HIP_TRY(hipEventRecord(ev_chunk, stream), "hipEventRecord");
-    chunk_pending = true;
-    n_points += n;
+    const size_t point_bytes = dt == RASTER_F64 ? 16 : 8;
+    // pieces of at most group_budget points; between pieces the work is
+    // settled, so the spill buffer never needs more than one piece or group
+    st = ensure_spill(0, group_budget);
+    if (st != RASTER_OK) return st;
+    for (int64_t off = 0; off < n;) {
+        const int64_t piece = std::min<int64_t>(n - off, (int64_t)group_budget);
+        const void* p = (const char*)pts + (size_t)off * point_bytes;
+        const Geo g = make_geo(cap);
+        const bool binned = (tuning.mode == 2 || (tuning.mode == 0 && (uint64_t)piece >= cap / 8)) &&
+                            binned_geometry(g);
+        SpillBuf sp{spill_keys[0], spill_counts[0], spill_cap[0]};
+        hipEvent_t a = nullptr;
+        if (binned) {
+            if (group_points + (uint64_t)piece > group_budget) {
+                st = flush();
+                if (st != RASTER_OK) return st;
+            }
+            st = ensure_bins();
+            if (st != RASTER_OK) return st;
+            if ((st = span_begin(0, &a)) != RASTER_OK) return st;
+            HIP_TRY(launch_bin_points(p, piece, (int)dt, scale, bin1, cap1, cursor1, tab, cap, sp, ctr, stream),
+                    "bin points");
+            if ((st = span_end(0, a)) != RASTER_OK) return st;
+            group_points += (uint64_t)piece;
+        } else {
+            if ((st = span_begin(0, &a)) != RASTER_OK) return st;
+            HIP_TRY(launch_project_count(p, piece, (int)dt, scale, tab, cap, sp, ctr, kernel_tuning(tuning), stream),
+                    "project_count");
+            if ((st = span_end(0, a)) != RASTER_OK) return st;
+        }
+        n_points += piece;
+        off += piece;
+        if ((st = mark_pending()) != RASTER_OK) return st;
+        if (off < n && (st = settle()) != RASTER_OK) return st;
+    }
     return RASTER_OK;
 }
 
 raster_status TableRun::finish(raster_result** out) {
     raster_status st = settle();
+    if (st != RASTER_OK) return st;
+    st = flush();
     if (st != RASTER_OK) return st;
     if (!timing_started) {
         HIP_TRY(hipEventRecord(ev[0], stream), "hipEventRecord");
@@ -445,8 +575,11 @@ raster_status TableRun::finish(raster_result** out) {
     S.us_threshold *= 1000.0f;
     S.us_agglomerate *= 1000.0f;
     S.us_filter *= 1000.0f;
-    S.count_launches = count_launches;
-    S.us_count_kernel = (float)us_count_kernel;
+    S.count_launches = span_n[0];
+    S.us_count_kernel = (float)span_us[0];
+    S.us_bin_keys = (float)span_us[1];
+    S.us_aggregate = (float)span_us[2];
+    S.flushes = flushes;
     r->tiles = S.tiles;
     r->clusters = S.clusters;
     if (h_ctr[C_ERROR] & kErrInternal) return drop(fail(RASTER_E_DEVICE, "agglomeration state inconsistent"));
@@ -463,6 +596,8 @@ raster_status TableRun::finish(raster_result** out) {
 
 raster_status TableRun::export_tiles(uint64_t* keys, uint32_t* counts, int64_t cap_rows, int64_t* m) {
     raster_status st = settle();
+    if (st != RASTER_OK) return st;
+    st = flush();
     if (st != RASTER_OK) return st;
     HIP_TRY(launch_zero_u64((uint64_t*)ctr + C_DISTINCT, 1, stream), "zero counter");
     HIP_TRY(launch_export_tiles(tab, cap, keys, counts, (uint64_t)std::max<int64_t>(cap_rows, 0), partials, ctr,
@@ -619,7 +754,7 @@ void raster_stream_destroy(raster_stream* st) {
 }
 
 raster_status raster_set_tuning(const raster_tuning* t) {
-    raster_tuning v = {256, 4, 0, 0.6f};
+    raster_tuning v = kDefaultTuning;
     if (t) {
         v = *t;
         if (v.block < 64 || v.block > 1024 || v.block % 64) return fail(RASTER_E_INVAL, "block must be 64..1024, x64");
@@ -629,6 +764,8 @@ raster_status raster_set_tuning(const raster_tuning* t) {
             (v.preagg_slots < 256 || v.preagg_slots > 4096 || (v.preagg_slots & (v.preagg_slots - 1))))
             return fail(RASTER_E_INVAL, "preagg_slots must be 0 or a power of two in [256, 4096]");
         if (!(v.load_factor > 0.05f && v.load_factor <= 0.9f)) return fail(RASTER_E_INVAL, "load_factor in (0.05, 0.9]");
+        if (v.mode < 0 || v.mode > 2) return fail(RASTER_E_INVAL, "mode must be 0, 1 or 2");
+        if (v.group_mpoints < 1 || v.group_mpoints > 4096) return fail(RASTER_E_INVAL, "group_mpoints in [1, 4096]");
     }
     std::lock_guard<std::mutex> g(g_tuning_mu);
     g_tuning = v;

@@ -18,6 +18,39 @@ constexpr uint32_t kNotSignificant = 0xFFFFFFFFu;
 // keys spills the key instead, and the table is grown afterwards.
 constexpr uint32_t kMaxProbe = 128;
 
+// Table geometry.  The table is cut into partitions of 2^cp_log2 slots
+// (4096 once the table is that large); a key's partition is the top p_log2
+// bits of its hash, its home slot inside the partition the low cp_log2 bits,
+// and probing wraps inside the partition.  A partition is then exactly the
+// slice one workgroup can hold in LDS, and the top hash bits name a key's
+// partition whatever the table size.
+constexpr uint32_t kPartLog2 = 12;
+struct Geo {
+    uint64_t cap;      // slots, a power of two
+    uint32_t cp_log2;  // log2 slots per partition
+    uint32_t p_log2;   // log2 partitions
+};
+inline Geo make_geo(uint64_t cap) {
+    uint32_t l = 0;
+    while ((1ull << l) < cap) ++l;
+    Geo g;
+    g.cap = cap;
+    g.cp_log2 = l < kPartLog2 ? l : kPartLog2;
+    g.p_log2 = l - g.cp_log2;
+    return g;
+}
+
+// Binned contraction: keys are first binned into 2^kCoarseLog2 buckets by the
+// top bits of their hash, then each bucket into its partitions, then every
+// partition is updated in LDS by one workgroup.  It needs at least one
+// partition per coarse bucket and at most kMaxFine partitions per bucket.
+constexpr uint32_t kCoarseLog2 = 7;
+constexpr uint32_t kCoarse = 1u << kCoarseLog2;
+constexpr uint32_t kMaxFine = 512;
+inline bool binned_geometry(const Geo& g) {
+    return g.cp_log2 == kPartLog2 && g.p_log2 >= kCoarseLog2 && (1ull << (g.p_log2 - kCoarseLog2)) <= kMaxFine;
+}
+
 // One table slot: 16 bytes, so a probe and the count update touch one line.
 struct alignas(16) Slot {
     uint64_t key;    // biased tile key or kEmptyKey
@@ -63,6 +96,9 @@ struct KernelTuning {
 // scan holds this many entries.
 constexpr int kScanBlocks = 2048;
 
+// Keys per binning tile (one workgroup pass).
+constexpr uint32_t kBinTile = 4096;
+
 // ---- launchers (all enqueue on `stream`, none synchronises) ------------------
 
 hipError_t launch_fill_table(Slot* tab, uint64_t cap, hipStream_t stream);
@@ -72,6 +108,26 @@ hipError_t launch_zero_u64(uint64_t* p, uint64_t n, hipStream_t stream);
 hipError_t launch_project_count(const void* pts, int64_t n, int dtype, double scale, Slot* tab,
                                  uint64_t cap, SpillBuf spill, unsigned long long* ctr,
                                  const KernelTuning& tu, hipStream_t stream);
+
+// Binned contraction, level 1: project n points and append each key to its
+// coarse bucket: bucket b holds keys at bin1[b * cap1 + i], i < cursor1[b].
+// Keys past a bucket's capacity go straight into the table.
+hipError_t launch_bin_points(const void* pts, int64_t n, int dtype, double scale, uint64_t* bin1, uint64_t cap1,
+                             uint32_t* cursor1, Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr,
+                             hipStream_t stream);
+// Binned contraction, level 2: split every coarse bucket into its partitions
+// (bin2, cap2 keys per partition, counts in cursor2, which this clears first).
+hipError_t launch_bin_keys(const uint64_t* bin1, uint64_t cap1, const uint32_t* cursor1, uint64_t* bin2,
+                           uint64_t cap2, uint32_t* cursor2, Slot* tab, uint64_t cap, SpillBuf spill,
+                           unsigned long long* ctr, hipStream_t stream);
+// Binned contraction, update: one workgroup per partition adds that
+// partition's keys to the table in LDS; then clears cursor1 for the next group.
+hipError_t launch_aggregate(const uint64_t* bin2, uint64_t cap2, const uint32_t* cursor2, uint32_t* cursor1,
+                            Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream);
+// Direct insertion of everything held in the coarse buckets (used when the
+// table is outside the binned geometry).  Clears cursor1.
+hipError_t launch_drain_bins(uint64_t* bin1, uint64_t cap1, uint32_t* cursor1, Slot* tab, uint64_t cap,
+                             SpillBuf spill, unsigned long long* ctr, hipStream_t stream);
 
 // Insert n (key, count) records (spilled keys, or a rehash source).
 hipError_t launch_insert_records(const uint64_t* keys, const uint32_t* counts, uint64_t n,

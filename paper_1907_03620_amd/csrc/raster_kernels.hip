@@ -98,8 +98,19 @@ enum AddResult : int { ADD_FOUND = 0, ADD_NEW = 1, ADD_FULL = 2 };
 // its probe window if it is not there yet.  Keys are only ever written once
 // (empty -> key), so a stale read can only show a slot as empty; the
 // compare-and-swap then returns the true occupant.
-__device__ __forceinline__ int table_add(Slot* tab, uint64_t mask, uint64_t key, uint32_t inc) {
-    uint64_t pos = mix64(key) & mask;
+__device__ __forceinline__ uint64_t home_slot(uint64_t h, const Geo& g) {
+    const uint64_t part = g.p_log2 ? (h >> (64 - g.p_log2)) : 0;
+    return (part << g.cp_log2) | (h & ((1ull << g.cp_log2) - 1));
+}
+
+// Next probe position: linear, wrapping inside the partition.
+__device__ __forceinline__ uint64_t next_slot(uint64_t s, const Geo& g) {
+    const uint64_t m = (1ull << g.cp_log2) - 1;
+    return (s & ~m) | ((s + 1) & m);
+}
+
+__device__ __forceinline__ int table_add(Slot* tab, const Geo& g, uint64_t key, uint32_t inc) {
+    uint64_t pos = home_slot(mix64(key), g);
     for (uint32_t p = 0; p < kMaxProbe; ++p) {
         Slot* sl = tab + pos;
         uint64_t cur = ld_relaxed(&sl->key);
@@ -115,19 +126,19 @@ __device__ __forceinline__ int table_add(Slot* tab, uint64_t mask, uint64_t key,
             atomicAdd(&sl->count, inc);
             return ADD_FOUND;
         }
-        pos = (pos + 1) & mask;
+        pos = next_slot(pos, g);
     }
     return ADD_FULL;
 }
 
 // Read-only lookup; returns the slot index or ~0 when the key is absent.
-__device__ __forceinline__ uint64_t table_find(const Slot* tab, uint64_t mask, uint64_t key) {
-    uint64_t pos = mix64(key) & mask;
+__device__ __forceinline__ uint64_t table_find(const Slot* tab, const Geo& g, uint64_t key) {
+    uint64_t pos = home_slot(mix64(key), g);
     for (uint32_t p = 0; p < kMaxProbe; ++p) {
         const uint64_t cur = tab[pos].key;
         if (cur == key) return pos;
         if (cur == kEmptyKey) return ~0ull;
-        pos = (pos + 1) & mask;
+        pos = next_slot(pos, g);
     }
     return ~0ull;
 }
@@ -177,7 +188,7 @@ __global__ void k_zero_u64(uint64_t* p, uint64_t n) {
 // takes points base + t + j * blockDim so each load instruction is coalesced.
 template <typename T, int ITEMS>
 __global__ void k_count_direct(const T* __restrict__ pts, int64_t n, double scale, Slot* tab,
-                               uint64_t mask, SpillBuf sp, unsigned long long* ctr) {
+                               const Geo g, SpillBuf sp, unsigned long long* ctr) {
     const int64_t base = (int64_t)blockIdx.x * blockDim.x * ITEMS + threadIdx.x;
     uint64_t key[ITEMS];
     uint32_t valid = 0;
@@ -199,7 +210,7 @@ __global__ void k_count_direct(const T* __restrict__ pts, int64_t n, double scal
     for (int j = 0; j < ITEMS; ++j) {
         int r = ADD_FOUND;
         if (valid & (1u << j)) {
-            r = table_add(tab, mask, key[j], 1u);
+            r = table_add(tab, g, key[j], 1u);
             fresh += (r == ADD_NEW);
         }
         spill_push(sp, ctr, r == ADD_FULL, key[j], 1u);
@@ -217,7 +228,7 @@ __global__ void k_count_direct(const T* __restrict__ pts, int64_t n, double scal
 // take a large share of the points.
 template <typename T, int ITEMS>
 __global__ void k_count_preagg(const T* __restrict__ pts, int64_t n, double scale, Slot* tab,
-                               uint64_t mask, SpillBuf sp, unsigned long long* ctr, int lds_log2,
+                               const Geo g, SpillBuf sp, unsigned long long* ctr, int lds_log2,
                                int sweeps) {
     extern __shared__ unsigned char smem[];
     const uint32_t L = 1u << lds_log2;
@@ -265,7 +276,7 @@ __global__ void k_count_preagg(const T* __restrict__ pts, int64_t n, double scal
                     pos = (pos + 1) & (L - 1);
                 }
                 if (!done) {
-                    r = table_add(tab, mask, k, 1u);
+                    r = table_add(tab, g, k, 1u);
                     fresh += (r == ADD_NEW);
                 }
             }
@@ -283,7 +294,7 @@ __global__ void k_count_preagg(const T* __restrict__ pts, int64_t n, double scal
             k = lkey[s];
             c = lcnt[s];
             if (k != kEmptyKey) {
-                r = table_add(tab, mask, k, c);
+                r = table_add(tab, g, k, c);
                 fresh += (r == ADD_NEW);
             }
         }
@@ -295,7 +306,7 @@ __global__ void k_count_preagg(const T* __restrict__ pts, int64_t n, double scal
 }
 
 __global__ void k_insert_records(const uint64_t* keys, const uint32_t* counts, uint64_t n, Slot* tab,
-                                 uint64_t mask, SpillBuf sp, unsigned long long* ctr) {
+                                 const Geo g, SpillBuf sp, unsigned long long* ctr) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t n_round = (n + 63) / 64 * 64;  // whole waves iterate together
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_round; i += stride) {
@@ -305,14 +316,14 @@ __global__ void k_insert_records(const uint64_t* keys, const uint32_t* counts, u
         if (i < n) {
             k = keys[i];
             c = counts[i];
-            r = table_add(tab, mask, k, c);
+            r = table_add(tab, g, k, c);
         }
         wave_count(&ctr[C_INSERTED], r == ADD_NEW);
         spill_push(sp, ctr, r == ADD_FULL, k, c);
     }
 }
 
-__global__ void k_rehash(const Slot* from, uint64_t from_cap, Slot* to, uint64_t to_mask, SpillBuf sp,
+__global__ void k_rehash(const Slot* from, uint64_t from_cap, Slot* to, const Geo to_g, SpillBuf sp,
                          unsigned long long* ctr) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t n_round = (from_cap + 63) / 64 * 64;  // whole waves iterate together
@@ -324,11 +335,278 @@ __global__ void k_rehash(const Slot* from, uint64_t from_cap, Slot* to, uint64_t
             const Slot s = from[i];
             k = s.key;
             c = s.count;
-            if (k != kEmptyKey) r = table_add(to, to_mask, k, c);
+            if (k != kEmptyKey) r = table_add(to, to_g, k, c);
         }
         wave_count(&ctr[C_INSERTED], r == ADD_NEW);
         spill_push(sp, ctr, r == ADD_FULL, k, c);
     }
+}
+
+// ------------------------------------------------------ binned contraction ---
+//
+// The per-point count update is the hot loop of the method.  Done directly it
+// costs one device-scope atomic per point, and those are executed at a single
+// memory-side point at a few tens of billions per second.  The binned path
+// instead routes every key to the workgroup that owns its table partition:
+//   level 1: project the points and append each key to one of 128 coarse
+//            buckets (top 7 hash bits), in runs written by one workgroup;
+//   level 2: split each coarse bucket into its partitions;
+//   update : one workgroup per partition loads the 4096-slot slice into LDS,
+//            adds every key with LDS atomics and writes the slice back.
+// All traffic is then sequential HBM streams plus one table read and write
+// per group of chunks.
+
+constexpr int BIN_THREADS = 256;
+constexpr int BIN_ITEMS = (int)kBinTile / BIN_THREADS;  // 16
+
+struct BinScratch {
+    uint64_t key[kBinTile];
+    uint16_t bin[kBinTile];
+    uint32_t hist[kMaxFine];
+    uint32_t off[kMaxFine];
+    uint32_t base[kMaxFine];
+    uint32_t total;
+};
+
+// Scatters this tile's valid keys into nb buckets: bucket b's keys are
+// appended at out[b * stride + cursor[b] ...].  A key past its bucket's
+// capacity (stride) goes straight into the table instead.  S.hist must be
+// zero on entry (and a barrier passed); every thread of the workgroup calls.
+__device__ void bin_tile(BinScratch& S, const uint64_t (&key)[BIN_ITEMS], const uint16_t (&bucket)[BIN_ITEMS],
+                         uint32_t valid, uint32_t nb, uint64_t* out, uint64_t stride, uint32_t* cursor, Slot* tab,
+                         const Geo& g, const SpillBuf& sp, unsigned long long* ctr, uint32_t& fresh) {
+    uint32_t rank[BIN_ITEMS];
+#pragma unroll
+    for (int j = 0; j < BIN_ITEMS; ++j) {
+        rank[j] = 0;
+        if (valid & (1u << j)) rank[j] = atomicAdd(&S.hist[bucket[j]], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const uint32_t per = (nb + 63) / 64;
+        const uint32_t lo = threadIdx.x * per;
+        uint32_t sum = 0;
+        for (uint32_t q = 0; q < per; ++q)
+            if (lo + q < nb) sum += S.hist[lo + q];
+        uint32_t inc = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t v = __shfl_up(inc, o);
+            if (lane_id() >= o) inc += v;
+        }
+        uint32_t ex = inc - sum;
+        for (uint32_t q = 0; q < per; ++q)
+            if (lo + q < nb) {
+                S.off[lo + q] = ex;
+                ex += S.hist[lo + q];
+            }
+        if (threadIdx.x == 63) S.total = inc;
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < nb; b += BIN_THREADS)
+        S.base[b] = S.hist[b] ? atomicAdd(&cursor[b], S.hist[b]) : 0u;
+#pragma unroll
+    for (int j = 0; j < BIN_ITEMS; ++j) {
+        if (valid & (1u << j)) {
+            const uint32_t p = S.off[bucket[j]] + rank[j];
+            S.key[p] = key[j];
+            S.bin[p] = bucket[j];
+        }
+    }
+    __syncthreads();
+    const uint32_t total = S.total;
+    for (uint32_t q0 = 0; q0 < total; q0 += BIN_THREADS) {
+        const uint32_t q = q0 + threadIdx.x;
+        int r = ADD_FOUND;
+        uint64_t k = 0;
+        if (q < total) {
+            const uint32_t b = S.bin[q];
+            const uint64_t dst = (uint64_t)S.base[b] + (q - S.off[b]);
+            k = S.key[q];
+            if (dst < stride) {
+                out[(uint64_t)b * stride + dst] = k;
+            } else {
+                r = table_add(tab, g, k, 1u);
+                fresh += (r == ADD_NEW);
+            }
+        }
+        spill_push(sp, ctr, r == ADD_FULL, k, 1u);
+    }
+}
+
+__device__ __forceinline__ void add_fresh(unsigned long long* ctr, uint32_t fresh) {
+    for (int off = 32; off > 0; off >>= 1) fresh += __shfl_xor(fresh, off);
+    if (lane_id() == 0 && fresh) atomicAdd(&ctr[C_INSERTED], (unsigned long long)fresh);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BIN_THREADS) void k_bin_points(const T* __restrict__ pts, int64_t n, double scale,
+                                                            uint64_t* bin1, uint64_t cap1, uint32_t* cursor1,
+                                                            Slot* tab, const Geo g, SpillBuf sp,
+                                                            unsigned long long* ctr) {
+    __shared__ BinScratch S;
+    for (uint32_t b = threadIdx.x; b < kCoarse; b += BIN_THREADS) S.hist[b] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kBinTile + threadIdx.x;
+    uint64_t key[BIN_ITEMS];
+    uint16_t bucket[BIN_ITEMS];
+    uint32_t valid = 0;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < BIN_ITEMS; ++j) {
+        const int64_t i = base + (int64_t)j * BIN_THREADS;
+        key[j] = 0;
+        bucket[j] = 0;
+        if (i < n) {
+            double x, y;
+            load_point(pts, i, x, y);
+            if (tile_key(x, y, scale, key[j])) {
+                valid |= 1u << j;
+                bucket[j] = (uint16_t)(mix64(key[j]) >> (64 - kCoarseLog2));
+            } else {
+                bad = true;
+            }
+        }
+    }
+    if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrRange);
+    uint32_t fresh = 0;
+    bin_tile(S, key, bucket, valid, kCoarse, bin1, cap1, cursor1, tab, g, sp, ctr, fresh);
+    add_fresh(ctr, fresh);
+}
+
+// Level 2: workgroup (b1, seg) splits keys [seg * kBinTile, ...) of coarse
+// bucket b1 into that bucket's partitions.
+__global__ __launch_bounds__(BIN_THREADS) void k_bin_keys(const uint64_t* __restrict__ bin1, uint64_t cap1,
+                                                          const uint32_t* cursor1, uint32_t segs, uint64_t* bin2,
+                                                          uint64_t cap2, uint32_t* cursor2, Slot* tab, const Geo g,
+                                                          SpillBuf sp, unsigned long long* ctr) {
+    __shared__ BinScratch S;
+    const uint32_t b1 = blockIdx.x / segs;
+    const uint32_t seg = blockIdx.x % segs;
+    const uint64_t cnt = min((uint64_t)cursor1[b1], cap1);
+    const uint64_t start = (uint64_t)seg * kBinTile;
+    if (start >= cnt) return;  // uniform across the workgroup
+    const uint32_t fine_log2 = g.p_log2 - kCoarseLog2;
+    const uint32_t nb = 1u << fine_log2;
+    for (uint32_t b = threadIdx.x; b < nb; b += BIN_THREADS) S.hist[b] = 0;
+    __syncthreads();
+    uint64_t key[BIN_ITEMS];
+    uint16_t bucket[BIN_ITEMS];
+    uint32_t valid = 0;
+    const uint64_t* src = bin1 + (uint64_t)b1 * cap1;
+#pragma unroll
+    for (int j = 0; j < BIN_ITEMS; ++j) {
+        const uint64_t i = start + (uint64_t)j * BIN_THREADS + threadIdx.x;
+        key[j] = 0;
+        bucket[j] = 0;
+        if (i < cnt) {
+            key[j] = __builtin_nontemporal_load(src + i);
+            const uint64_t part = mix64(key[j]) >> (64 - g.p_log2);
+            bucket[j] = (uint16_t)(part & (nb - 1));
+            valid |= 1u << j;
+        }
+    }
+    uint32_t fresh = 0;
+    const uint64_t first = (uint64_t)b1 << fine_log2;
+    bin_tile(S, key, bucket, valid, nb, bin2 + first * cap2, cap2, cursor2 + first, tab, g, sp, ctr, fresh);
+    add_fresh(ctr, fresh);
+}
+
+constexpr int AGG_THREADS = 256;
+constexpr uint32_t kPartSlots = 1u << kPartLog2;
+
+// LDS version of table_add over one partition slice (same probe sequence as
+// the device table, so slots stay where a device-table probe looks for them).
+__device__ __forceinline__ int lds_add(uint64_t* lkey, uint32_t* lcnt, uint64_t key) {
+    uint32_t pos = (uint32_t)mix64(key) & (kPartSlots - 1);
+    for (uint32_t p = 0; p < kMaxProbe; ++p) {
+        uint64_t cur = *(volatile uint64_t*)&lkey[pos];
+        if (cur == kEmptyKey) {
+            cur = atomicCAS(reinterpret_cast<unsigned long long*>(&lkey[pos]), (unsigned long long)kEmptyKey,
+                            (unsigned long long)key);
+            if (cur == kEmptyKey) {
+                atomicAdd(&lcnt[pos], 1u);
+                return ADD_NEW;
+            }
+        }
+        if (cur == key) {
+            atomicAdd(&lcnt[pos], 1u);
+            return ADD_FOUND;
+        }
+        pos = (pos + 1) & (kPartSlots - 1);
+    }
+    return ADD_FULL;
+}
+
+// One workgroup per partition: load the slice, add its keys, store it back.
+__global__ __launch_bounds__(AGG_THREADS) void k_aggregate(const uint64_t* __restrict__ bin2, uint64_t cap2,
+                                                           const uint32_t* cursor2, Slot* tab, SpillBuf sp,
+                                                           unsigned long long* ctr) {
+    __shared__ uint64_t lkey[kPartSlots];
+    __shared__ uint32_t lcnt[kPartSlots];
+    const uint64_t p = blockIdx.x;
+    const uint64_t cnt = min((uint64_t)cursor2[p], cap2);
+    if (cnt == 0) return;  // uniform across the workgroup
+    Slot* part = tab + (p << kPartLog2);
+    for (uint32_t s = threadIdx.x; s < kPartSlots; s += AGG_THREADS) {
+        const Slot v = part[s];
+        lkey[s] = v.key;
+        lcnt[s] = v.count;
+    }
+    __syncthreads();
+    uint32_t fresh = 0;
+    const uint64_t* src = bin2 + p * cap2;
+    for (uint64_t q0 = 0; q0 < cnt; q0 += AGG_THREADS) {
+        const uint64_t q = q0 + threadIdx.x;
+        int r = ADD_FOUND;
+        uint64_t k = 0;
+        if (q < cnt) {
+            k = __builtin_nontemporal_load(src + q);
+            r = lds_add(lkey, lcnt, k);
+            fresh += (r == ADD_NEW);
+        }
+        spill_push(sp, ctr, r == ADD_FULL, k, 1u);
+    }
+    __syncthreads();
+    for (uint32_t s = threadIdx.x; s < kPartSlots; s += AGG_THREADS) {
+        const uint64_t k = lkey[s];
+        if (k != kEmptyKey) {
+            Slot v;
+            v.key = k;
+            v.count = lcnt[s];
+            v.aux = kNotSignificant;
+            part[s] = v;
+        }
+    }
+    add_fresh(ctr, fresh);
+}
+
+// Fallback: every key held in the coarse buckets goes straight to the table.
+__global__ void k_drain_bins(const uint64_t* bin1, uint64_t cap1, const uint32_t* cursor1, Slot* tab, const Geo g,
+                             SpillBuf sp, unsigned long long* ctr) {
+    const uint64_t total = (uint64_t)kCoarse * cap1;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t n_round = (total + 63) / 64 * 64;
+    uint32_t fresh = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_round; i += stride) {
+        int r = ADD_FOUND;
+        uint64_t k = 0;
+        if (i < total) {
+            const uint64_t b = i / cap1, q = i % cap1;
+            if (q < min((uint64_t)cursor1[b], cap1)) {
+                k = bin1[i];
+                r = table_add(tab, g, k, 1u);
+                fresh += (r == ADD_NEW);
+            }
+        }
+        spill_push(sp, ctr, r == ADD_FULL, k, 1u);
+    }
+    add_fresh(ctr, fresh);
+}
+
+__global__ void k_zero_u32(uint32_t* p, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
 }
 
 // ---------------------------------------------------------------- scans ----
@@ -621,11 +899,11 @@ __device__ __forceinline__ void uf_unite(uint32_t* parent, const uint64_t* key, 
     bad = true;
 }
 
-__device__ __forceinline__ void link_neighbour(const Slot* tab, uint64_t mask, uint32_t* parent,
+__device__ __forceinline__ void link_neighbour(const Slot* tab, const Geo& g, uint32_t* parent,
                                                const uint64_t* s_key, uint32_t i, uint32_t bx, uint32_t by, uint32_t s,
                                                bool& bad) {
     const uint64_t nk = ((uint64_t)bx << 32) | by;
-    const uint64_t slot = table_find(tab, mask, nk);
+    const uint64_t slot = table_find(tab, g, nk);
     if (slot == ~0ull) return;
     const uint32_t j = tab[slot].aux;
     if (j == kNotSignificant) return;
@@ -640,7 +918,7 @@ __device__ __forceinline__ void link_neighbour(const Slot* tab, uint64_t mask, u
 // (x+1, y-1), (x+1, y), (x+1, y+1); with the symmetric backward lookups done
 // by those neighbours this covers all eight directions.  Biased coordinates
 // of valid tiles lie in [2, 2^32 - 2]; neighbours outside are skipped.
-__global__ void k_hook(const Slot* tab, uint64_t mask, const uint64_t* s_key, uint32_t* parent,
+__global__ void k_hook(const Slot* tab, const Geo g, const uint64_t* s_key, uint32_t* parent,
                        unsigned long long* ctr) {
     const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
     bool bad = false;
@@ -652,11 +930,11 @@ __global__ void k_hook(const Slot* tab, uint64_t mask, const uint64_t* s_key, ui
         const bool up = by < 0xFFFFFFFEu;
         const bool down = by > 2u;
         const bool right = bx < 0xFFFFFFFEu;
-        if (up) link_neighbour(tab, mask, parent, s_key, (uint32_t)i, bx, by + 1, s, bad);
+        if (up) link_neighbour(tab, g, parent, s_key, (uint32_t)i, bx, by + 1, s, bad);
         if (right) {
-            if (down) link_neighbour(tab, mask, parent, s_key, (uint32_t)i, bx + 1, by - 1, s, bad);
-            link_neighbour(tab, mask, parent, s_key, (uint32_t)i, bx + 1, by, s, bad);
-            if (up) link_neighbour(tab, mask, parent, s_key, (uint32_t)i, bx + 1, by + 1, s, bad);
+            if (down) link_neighbour(tab, g, parent, s_key, (uint32_t)i, bx + 1, by - 1, s, bad);
+            link_neighbour(tab, g, parent, s_key, (uint32_t)i, bx + 1, by, s, bad);
+            if (up) link_neighbour(tab, g, parent, s_key, (uint32_t)i, bx + 1, by + 1, s, bad);
         }
     }
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
@@ -762,7 +1040,7 @@ int grid_for(uint64_t work, int block, int max_blocks) {
 constexpr int kPersistBlocks = 256 * 8;
 
 template <typename T, int ITEMS>
-hipError_t launch_count_t(const T* pts, int64_t n, double scale, Slot* tab, uint64_t mask, SpillBuf sp,
+hipError_t launch_count_t(const T* pts, int64_t n, double scale, Slot* tab, const Geo g, SpillBuf sp,
                           unsigned long long* ctr, const KernelTuning& tu, hipStream_t stream) {
     const int block = tu.block;
     if (tu.preagg_slots > 0) {
@@ -773,25 +1051,25 @@ hipError_t launch_count_t(const T* pts, int64_t n, double scale, Slot* tab, uint
         const int64_t grid = (n + per_block - 1) / per_block;
         const size_t lds = (size_t)(1u << lds_log2) * (sizeof(uint64_t) + sizeof(uint32_t));
         hipLaunchKernelGGL((k_count_preagg<T, ITEMS>), dim3((unsigned)grid), dim3(block), lds, stream, pts, n,
-                           scale, tab, mask, sp, ctr, lds_log2, sweeps);
+                           scale, tab, g, sp, ctr, lds_log2, sweeps);
     } else {
         const int64_t per_block = (int64_t)block * ITEMS;
         const int64_t grid = (n + per_block - 1) / per_block;
         hipLaunchKernelGGL((k_count_direct<T, ITEMS>), dim3((unsigned)grid), dim3(block), 0, stream, pts, n, scale,
-                           tab, mask, sp, ctr);
+                           tab, g, sp, ctr);
     }
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_count_items(const T* pts, int64_t n, double scale, Slot* tab, uint64_t mask, SpillBuf sp,
+hipError_t launch_count_items(const T* pts, int64_t n, double scale, Slot* tab, const Geo g, SpillBuf sp,
                               unsigned long long* ctr, const KernelTuning& tu, hipStream_t stream) {
     switch (tu.items) {
-        case 1: return launch_count_t<T, 1>(pts, n, scale, tab, mask, sp, ctr, tu, stream);
-        case 2: return launch_count_t<T, 2>(pts, n, scale, tab, mask, sp, ctr, tu, stream);
-        case 4: return launch_count_t<T, 4>(pts, n, scale, tab, mask, sp, ctr, tu, stream);
-        case 8: return launch_count_t<T, 8>(pts, n, scale, tab, mask, sp, ctr, tu, stream);
-        default: return launch_count_t<T, 16>(pts, n, scale, tab, mask, sp, ctr, tu, stream);
+        case 1: return launch_count_t<T, 1>(pts, n, scale, tab, g, sp, ctr, tu, stream);
+        case 2: return launch_count_t<T, 2>(pts, n, scale, tab, g, sp, ctr, tu, stream);
+        case 4: return launch_count_t<T, 4>(pts, n, scale, tab, g, sp, ctr, tu, stream);
+        case 8: return launch_count_t<T, 8>(pts, n, scale, tab, g, sp, ctr, tu, stream);
+        default: return launch_count_t<T, 16>(pts, n, scale, tab, g, sp, ctr, tu, stream);
     }
 }
 
@@ -813,24 +1091,71 @@ hipError_t launch_project_count(const void* pts, int64_t n, int dtype, double sc
                                  SpillBuf spill, unsigned long long* ctr, const KernelTuning& tu,
                                  hipStream_t stream) {
     if (n <= 0) return hipSuccess;
-    const uint64_t mask = cap - 1;
+    const Geo g = make_geo(cap);
     if (dtype == 1)
-        return launch_count_items(static_cast<const float*>(pts), n, scale, tab, mask, spill, ctr, tu, stream);
-    return launch_count_items(static_cast<const double*>(pts), n, scale, tab, mask, spill, ctr, tu, stream);
+        return launch_count_items(static_cast<const float*>(pts), n, scale, tab, g, spill, ctr, tu, stream);
+    return launch_count_items(static_cast<const double*>(pts), n, scale, tab, g, spill, ctr, tu, stream);
+}
+
+hipError_t launch_bin_points(const void* pts, int64_t n, int dtype, double scale, uint64_t* bin1, uint64_t cap1,
+                             uint32_t* cursor1, Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr,
+                             hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const Geo g = make_geo(cap);
+    const unsigned grid = (unsigned)((n + kBinTile - 1) / kBinTile);
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_bin_points<float>, dim3(grid), dim3(BIN_THREADS), 0, stream,
+                           static_cast<const float*>(pts), n, scale, bin1, cap1, cursor1, tab, g, spill, ctr);
+    else
+        hipLaunchKernelGGL(k_bin_points<double>, dim3(grid), dim3(BIN_THREADS), 0, stream,
+                           static_cast<const double*>(pts), n, scale, bin1, cap1, cursor1, tab, g, spill, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_keys(const uint64_t* bin1, uint64_t cap1, const uint32_t* cursor1, uint64_t* bin2,
+                           uint64_t cap2, uint32_t* cursor2, Slot* tab, uint64_t cap, SpillBuf spill,
+                           unsigned long long* ctr, hipStream_t stream) {
+    const Geo g = make_geo(cap);
+    if (!binned_geometry(g)) return hipErrorInvalidValue;
+    const uint64_t parts = 1ull << g.p_log2;
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(parts, 256, 4096)), dim3(256), 0, stream, cursor2, parts);
+    const uint32_t segs = (uint32_t)((cap1 + kBinTile - 1) / kBinTile);
+    hipLaunchKernelGGL(k_bin_keys, dim3(kCoarse * segs), dim3(BIN_THREADS), 0, stream, bin1, cap1, cursor1, segs,
+                       bin2, cap2, cursor2, tab, g, spill, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_aggregate(const uint64_t* bin2, uint64_t cap2, const uint32_t* cursor2, uint32_t* cursor1,
+                            Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream) {
+    const Geo g = make_geo(cap);
+    if (!binned_geometry(g)) return hipErrorInvalidValue;
+    const uint64_t parts = 1ull << g.p_log2;
+    hipLaunchKernelGGL(k_aggregate, dim3((unsigned)parts), dim3(AGG_THREADS), 0, stream, bin2, cap2, cursor2, tab,
+                       spill, ctr);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, stream, cursor1, (uint64_t)kCoarse);
+    return hipGetLastError();
+}
+
+hipError_t launch_drain_bins(uint64_t* bin1, uint64_t cap1, uint32_t* cursor1, Slot* tab, uint64_t cap,
+                             SpillBuf spill, unsigned long long* ctr, hipStream_t stream) {
+    hipLaunchKernelGGL(k_drain_bins, dim3(grid_for((uint64_t)kCoarse * cap1, 256, kPersistBlocks)), dim3(256), 0,
+                       stream, bin1, cap1, cursor1, tab, make_geo(cap), spill, ctr);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, stream, cursor1, (uint64_t)kCoarse);
+    return hipGetLastError();
 }
 
 hipError_t launch_insert_records(const uint64_t* keys, const uint32_t* counts, uint64_t n, Slot* tab,
                                  uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_insert_records, dim3(grid_for(n, 256, kPersistBlocks)), dim3(256), 0, stream, keys,
-                       counts, n, tab, cap - 1, spill, ctr);
+                       counts, n, tab, make_geo(cap), spill, ctr);
     return hipGetLastError();
 }
 
 hipError_t launch_rehash(const Slot* from, uint64_t from_cap, Slot* to, uint64_t to_cap, SpillBuf spill,
                          unsigned long long* ctr, hipStream_t stream) {
     hipLaunchKernelGGL(k_rehash, dim3(grid_for(from_cap, 256, kPersistBlocks)), dim3(256), 0, stream, from,
-                       from_cap, to, to_cap - 1, spill, ctr);
+                       from_cap, to, make_geo(to_cap), spill, ctr);
     return hipGetLastError();
 }
 
@@ -857,7 +1182,7 @@ hipError_t launch_threshold(Slot* tab, uint64_t cap, uint32_t tau, uint64_t* s_k
 hipError_t launch_agglomerate(const Slot* tab, uint64_t cap, const uint64_t* s_key, uint32_t* parent,
                               uint32_t* size, uint64_t s_max, unsigned long long* ctr, hipStream_t stream) {
     const int grid = grid_for(s_max, 256, kPersistBlocks);
-    hipLaunchKernelGGL(k_hook, dim3(grid), dim3(256), 0, stream, tab, cap - 1, s_key, parent, ctr);
+    hipLaunchKernelGGL(k_hook, dim3(grid), dim3(256), 0, stream, tab, make_geo(cap), s_key, parent, ctr);
     hipLaunchKernelGGL(k_compress, dim3(grid), dim3(256), 0, stream, parent, size, ctr);
     return hipGetLastError();
 }

@@ -87,9 +87,27 @@ struct TableRun {
     uint64_t spill_cap[2] = {0, 0};
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     hipEvent_t ev_chunk = nullptr;
-    hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;  // around the last counting launch
-    int64_t count_launches = 0;
-    double us_count_kernel = 0.0;
+    // device time per kernel kind: 0 = the point-streaming kernel (direct
+    // count or level-1 binning), 1 = level-2 binning, 2 = partition update
+    struct Span {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Span> spans;
+    std::vector<hipEvent_t> ev_free;
+    double span_us[3] = {0, 0, 0};
+    int64_t span_n[3] = {0, 0, 0};
+    // binned contraction
+    uint64_t* bin1 = nullptr;
+    uint64_t cap1 = 0;
+    uint32_t* cursor1 = nullptr;
+    uint64_t* bin2 = nullptr;
+    uint64_t bin2_slots = 0;
+    uint32_t* cursor2 = nullptr;
+    uint64_t cursor2_n = 0;
+    uint64_t group_points = 0;  // points binned since the last flush
+    uint64_t group_budget = 0;
+    int32_t flushes = 0;
     bool chunk_pending = false;
     bool timing_started = false;
     bool hinted = false;  // tile_hint given: the first chunk does not resize the table
@@ -108,6 +126,12 @@ struct TableRun {
     raster_status pull_counters();
     raster_status grow(uint64_t new_cap, uint64_t pending, int src);
     raster_status settle();
+    raster_status flush();
+    raster_status ensure_bins();
+    raster_status mark_pending();
+    raster_status span_begin(int kind, hipEvent_t* a);
+    raster_status span_end(int kind, hipEvent_t a);
+    void resolve_spans();
 };
 
 }  // namespace rst

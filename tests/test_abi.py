@@ -87,19 +87,22 @@ def test_argument_errors_without_gpu(lib):
 def test_tuning_validation(lib):
     class T(ctypes.Structure):
         _fields_ = [("block", ctypes.c_int32), ("items", ctypes.c_int32),
-                    ("preagg_slots", ctypes.c_int32), ("load_factor", ctypes.c_float)]
+                    ("preagg_slots", ctypes.c_int32), ("load_factor", ctypes.c_float),
+                    ("mode", ctypes.c_int32), ("group_mpoints", ctypes.c_int32)]
     lib.raster_set_tuning.argtypes = [ctypes.POINTER(T)]
     lib.raster_get_tuning.argtypes = [ctypes.POINTER(T)]
-    for bad in [T(100, 4, 0, 0.5), T(256, 3, 0, 0.5), T(256, 4, 300, 0.5), T(256, 4, 0, 0.95), T(2048, 4, 0, 0.5)]:
+    for bad in [T(100, 4, 0, 0.5, 0, 256), T(256, 3, 0, 0.5, 0, 256), T(256, 4, 300, 0.5, 0, 256),
+                T(256, 4, 0, 0.95, 0, 256), T(2048, 4, 0, 0.5, 0, 256), T(256, 4, 0, 0.5, 3, 256),
+                T(256, 4, 0, 0.5, 0, 0), T(256, 4, 0, 0.5, 0, 5000)]:
         assert lib.raster_set_tuning(ctypes.byref(bad)) == -1
-    good = T(512, 8, 2048, 0.4)
+    good = T(512, 8, 2048, 0.4, 2, 64)
     assert lib.raster_set_tuning(ctypes.byref(good)) == 0
     got = T()
     assert lib.raster_get_tuning(ctypes.byref(got)) == 0
-    assert (got.block, got.items, got.preagg_slots) == (512, 8, 2048)
+    assert (got.block, got.items, got.preagg_slots, got.mode, got.group_mpoints) == (512, 8, 2048, 2, 64)
     assert lib.raster_set_tuning(None) == 0
     assert lib.raster_get_tuning(ctypes.byref(got)) == 0
-    assert (got.block, got.items, got.preagg_slots) == (256, 4, 0)
+    assert (got.block, got.items, got.preagg_slots, got.mode, got.group_mpoints) == (256, 4, 0, 0, 256)
 
 
 def test_binding_refuses_cpu_tensors():

@@ -255,3 +255,69 @@ def test_non_integer_scale(raster, torch, small):
     o = oracle.cluster(small, tau=5, mu=2, scale=s)
     g = raster.cluster(dev(small, torch), scale=s, tau=5, mu=2)
     assert_same(g, o, "scale 10^0.5")
+
+
+@pytest.fixture(scope="module")
+def mid():
+    # 3M points with hot tiles and noise: large enough for the binned path
+    return synth.zipf_hot(2, n=3_000_000, block=1_000_000)
+
+
+@pytest.fixture(scope="module")
+def mid_oracle(mid):
+    return oracle.cluster(mid, tau=5, mu=4, precision=2)
+
+
+@pytest.mark.parametrize("mode,group,hint,chunks", [
+    (2, 1, 2_000_000, 1),    # binned, three flushes of one million points
+    (2, 1, 2_000_000, 7),    # binned, uneven chunks straddling flushes
+    (2, 1, 300_000, 3),      # binned into a table that must grow with keys in flight
+    (2, 2, 0, 5),            # binned, table sized from the first chunk
+    (1, 256, 0, 3),          # direct
+    (0, 256, 0, 1),          # automatic choice
+])
+def test_counting_paths_agree(raster, torch, mid, mid_oracle, mode, group, hint, chunks):
+    raster.set_tuning(mode=mode, group_mpoints=group)
+    try:
+        st = raster.Stream(tau=5, mu=4, precision=2, tile_hint=hint)
+        for c in np.array_split(mid, chunks):
+            st.feed(dev(c, torch))
+        g = st.finish()
+        st.close()
+    finally:
+        raster.set_tuning(None)
+    assert_same(g, mid_oracle, f"mode {mode} group {group} hint {hint} chunks {chunks}")
+    if mode == 2 and hint >= 2_000_000:
+        assert g.stats["flushes"] >= 3
+    if mode == 1:
+        assert g.stats["flushes"] == 0
+
+
+def test_plain_binned_auto(raster, torch, mid, mid_oracle):
+    g = raster.cluster(dev(mid, torch), precision=2, tau=5, mu=4)
+    assert g.stats["flushes"] >= 1
+    assert_same(g, mid_oracle, "plain 3M auto")
+
+
+def test_binned_f32(raster, torch, mid):
+    pts = mid.astype(np.float32)
+    o = oracle.cluster(pts, tau=5, mu=4, precision=2)
+    raster.set_tuning(mode=2)
+    try:
+        g = raster.cluster(dev(pts, torch), precision=2, tau=5, mu=4)
+    finally:
+        raster.set_tuning(None)
+    assert g.stats["flushes"] >= 1
+    assert_same(g, o, "binned f32")
+
+
+def test_binned_range_error(raster, torch, mid):
+    bad = mid[:1_000_000].copy()
+    bad[777_777, 1] = np.nan
+    raster.set_tuning(mode=2)
+    try:
+        with pytest.raises(raster.RasterError) as e:
+            raster.cluster(dev(bad, torch), precision=2, tau=5, mu=4)
+    finally:
+        raster.set_tuning(None)
+    assert e.value.code == raster.E_RANGE
