@@ -99,7 +99,7 @@ def main():
     ap.add_argument("--tile-hint", type=int, default=0,
                     help="expected distinct tiles passed to raster_begin (0: let the table grow)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-strip", type=float, default=400.0)
+    ap.add_argument("--cpu-strip", type=float, default=2000.0)
     ap.add_argument("--tuning", default="", help="JSON object of raster_tuning fields")
     args = ap.parse_args()
 

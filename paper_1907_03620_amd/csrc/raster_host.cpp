@@ -392,15 +392,23 @@ raster_status TableRun::mark_pending() {
     return RASTER_OK;
 }
 
-raster_status TableRun::ensure_bins() {
-    if (bin1) return RASTER_OK;
-    // a coarse bucket receives about group_budget / 128 keys; the slack is
-    // far beyond the binomial spread, and overflow only costs direct inserts
-    cap1 = (group_budget / kCoarse) + (group_budget / kCoarse) / 50 + 8192;
-    cap1 = (cap1 + 255) / 256 * 256;
+// Coarse buckets for `want_points` keys per group (at most group_budget).
+// They are only re-sized while empty.
+raster_status TableRun::ensure_bins(uint64_t want_points) {
+    want_points = std::min<uint64_t>(std::max<uint64_t>(want_points, 1u << 20), group_budget);
+    if (bin1 && (bin_points >= want_points || group_points > 0)) return RASTER_OK;
+    if (bin1) bufs.give_back(bin1);
+    bin1 = nullptr;
+    // a coarse bucket receives about want_points / 128 keys; the slack is far
+    // beyond the binomial spread, and overflow only costs direct inserts
+    const uint64_t per = want_points / kCoarse;
+    cap1 = (per + per / 50 + 8192 + 255) / 256 * 256;
     HIP_TRY(bufs.take((void**)&bin1, kCoarse * cap1 * sizeof(uint64_t)), "coarse buckets");
-    HIP_TRY(bufs.take((void**)&cursor1, kCoarse * sizeof(uint32_t)), "coarse cursors");
-    HIP_TRY(launch_zero_u64((uint64_t*)cursor1, kCoarse / 2, stream), "zero cursors");
+    if (!cursor1) {
+        HIP_TRY(bufs.take((void**)&cursor1, kCoarse * sizeof(uint32_t)), "coarse cursors");
+        HIP_TRY(launch_zero_u64((uint64_t*)cursor1, kCoarse / 2, stream), "zero cursors");
+    }
+    bin_points = want_points;
     return RASTER_OK;
 }
 
@@ -473,9 +481,10 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
         timing_started = true;
     }
     const size_t point_bytes = dt == RASTER_F64 ? 16 : 8;
-    // pieces of at most group_budget points; between pieces the work is
-    // settled, so the spill buffer never needs more than one piece or group
-    st = ensure_spill(0, group_budget);
+    // Pieces of at most group_budget points, settled in between.  Spill
+    // records between two settles come from one piece or one group, so the
+    // buffer never needs more than what is binned plus this chunk.
+    st = ensure_spill(0, std::min<uint64_t>(group_budget, group_points + (uint64_t)n));
     if (st != RASTER_OK) return st;
     for (int64_t off = 0; off < n;) {
         const int64_t piece = std::min<int64_t>(n - off, (int64_t)group_budget);
@@ -486,12 +495,16 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
         SpillBuf sp{spill_keys[0], spill_counts[0], spill_cap[0]};
         hipEvent_t a = nullptr;
         if (binned) {
-            if (group_points + (uint64_t)piece > group_budget) {
+            // a one-shot call bins exactly its points; a stream expects more
+            // chunks like this one and bins several before updating the table
+            st = ensure_bins(single_shot ? (uint64_t)piece : 8 * (uint64_t)piece);
+            if (st != RASTER_OK) return st;
+            if (group_points + (uint64_t)piece > bin_points) {
                 st = flush();
                 if (st != RASTER_OK) return st;
+                st = ensure_bins(single_shot ? (uint64_t)piece : 8 * (uint64_t)piece);
+                if (st != RASTER_OK) return st;
             }
-            st = ensure_bins();
-            if (st != RASTER_OK) return st;
             if ((st = span_begin(0, &a)) != RASTER_OK) return st;
             HIP_TRY(launch_bin_points(p, piece, (int)dt, scale, bin1, cap1, cursor1, tab, cap, sp, ctr, stream),
                     "bin points");
@@ -629,8 +642,7 @@ raster_status raster_cluster_scaled(const void* d_points, int64_t n, raster_dtyp
     st = check_points(d_points, n, dt);
     if (st != RASTER_OK) return st;
     TableRun run;
-    const raster_tuning t = current_tuning();
-    (void)t;
+    run.single_shot = true;
     st = run.init(scale, tau, mu, std::max<int64_t>(n / 8, 1024), stream);
     if (st != RASTER_OK) return st;
     st = run.feed(d_points, n, dt);

@@ -107,6 +107,8 @@ struct TableRun {
     uint64_t cursor2_n = 0;
     uint64_t group_points = 0;  // points binned since the last flush
     uint64_t group_budget = 0;
+    uint64_t bin_points = 0;   // keys the coarse buckets are sized for
+    bool single_shot = false;  // plain call: all points come in one feed
     int32_t flushes = 0;
     bool chunk_pending = false;
     bool timing_started = false;
@@ -127,7 +129,7 @@ struct TableRun {
     raster_status grow(uint64_t new_cap, uint64_t pending, int src);
     raster_status settle();
     raster_status flush();
-    raster_status ensure_bins();
+    raster_status ensure_bins(uint64_t want_points);
     raster_status mark_pending();
     raster_status span_begin(int kind, hipEvent_t* a);
     raster_status span_end(int kind, hipEvent_t a);
