@@ -560,7 +560,7 @@ raster_status TableRun::finish(raster_result** out) {
     e = launch_zero_u64((uint64_t*)ctr + C_DISTINCT, C_COUNT_ - C_DISTINCT, stream);
     if (e == hipSuccess) e = launch_threshold(tab, cap, tau, s_key, s_count, parent, size, partials, ctr, stream);
     if (e == hipSuccess) e = hipEventRecord(ev[2], stream);
-    if (e == hipSuccess) e = launch_agglomerate(tab, cap, s_key, parent, size, m, ctr, stream);
+    if (e == hipSuccess) e = launch_agglomerate(tab, cap, s_key, parent, size, mu, m, ctr, stream);
     if (e == hipSuccess) e = hipEventRecord(ev[3], stream);
     if (e == hipSuccess)
         e = launch_filter(s_key, s_count, parent, size, mu, m, r->kx, r->ky, r->count, r->label, partials, ctr,

@@ -40,11 +40,13 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 __device__ __forceinline__ uint64_t ld_relaxed(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+// Relaxed atomic accesses at workgroup scope: ordinary cached loads and stores
+// in the ISA, but well-defined when other threads write the same word.
 __device__ __forceinline__ uint32_t ld_relaxed(const uint32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ void st_relaxed(uint32_t* p, uint32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
@@ -361,20 +363,26 @@ constexpr int BIN_ITEMS = (int)kBinTile / BIN_THREADS;  // 16
 
 struct BinScratch {
     uint64_t key[kBinTile];
-    uint16_t bin[kBinTile];
     uint32_t hist[kMaxFine];
     uint32_t off[kMaxFine];
     uint32_t base[kMaxFine];
     uint32_t total;
 };
 
+// Bucket of a key: bits [shift, shift + log2 nb) of its hash, counted from the top.
+__device__ __forceinline__ uint32_t bucket_of(uint64_t key, uint32_t top_bits, uint32_t nb) {
+    return (uint32_t)(mix64(key) >> (64 - top_bits)) & (nb - 1);
+}
+
 // Scatters this tile's valid keys into nb buckets: bucket b's keys are
 // appended at out[b * stride + cursor[b] ...].  A key past its bucket's
-// capacity (stride) goes straight into the table instead.  S.hist must be
-// zero on entry (and a barrier passed); every thread of the workgroup calls.
+// capacity (stride) goes straight into the table instead.  The bucket of a
+// key is bucket_of(key, top_bits, nb).  S.hist must be zero on entry (and a
+// barrier passed); every thread of the workgroup calls.
 __device__ void bin_tile(BinScratch& S, const uint64_t (&key)[BIN_ITEMS], const uint16_t (&bucket)[BIN_ITEMS],
-                         uint32_t valid, uint32_t nb, uint64_t* out, uint64_t stride, uint32_t* cursor, Slot* tab,
-                         const Geo& g, const SpillBuf& sp, unsigned long long* ctr, uint32_t& fresh) {
+                         uint32_t valid, uint32_t nb, uint32_t top_bits, uint64_t* out, uint64_t stride,
+                         uint32_t* cursor, Slot* tab, const Geo& g, const SpillBuf& sp, unsigned long long* ctr,
+                         uint32_t& fresh) {
     uint32_t rank[BIN_ITEMS];
 #pragma unroll
     for (int j = 0; j < BIN_ITEMS; ++j) {
@@ -409,7 +417,6 @@ __device__ void bin_tile(BinScratch& S, const uint64_t (&key)[BIN_ITEMS], const 
         if (valid & (1u << j)) {
             const uint32_t p = S.off[bucket[j]] + rank[j];
             S.key[p] = key[j];
-            S.bin[p] = bucket[j];
         }
     }
     __syncthreads();
@@ -419,9 +426,9 @@ __device__ void bin_tile(BinScratch& S, const uint64_t (&key)[BIN_ITEMS], const 
         int r = ADD_FOUND;
         uint64_t k = 0;
         if (q < total) {
-            const uint32_t b = S.bin[q];
-            const uint64_t dst = (uint64_t)S.base[b] + (q - S.off[b]);
             k = S.key[q];
+            const uint32_t b = bucket_of(k, top_bits, nb);
+            const uint64_t dst = (uint64_t)S.base[b] + (q - S.off[b]);
             if (dst < stride) {
                 out[(uint64_t)b * stride + dst] = k;
             } else {
@@ -461,7 +468,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_points(const T* __restrict_
             load_point(pts, i, x, y);
             if (tile_key(x, y, scale, key[j])) {
                 valid |= 1u << j;
-                bucket[j] = (uint16_t)(mix64(key[j]) >> (64 - kCoarseLog2));
+                bucket[j] = (uint16_t)bucket_of(key[j], kCoarseLog2, kCoarse);
             } else {
                 bad = true;
             }
@@ -469,7 +476,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_points(const T* __restrict_
     }
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrRange);
     uint32_t fresh = 0;
-    bin_tile(S, key, bucket, valid, kCoarse, bin1, cap1, cursor1, tab, g, sp, ctr, fresh);
+    bin_tile(S, key, bucket, valid, kCoarse, kCoarseLog2, bin1, cap1, cursor1, tab, g, sp, ctr, fresh);
     add_fresh(ctr, fresh);
 }
 
@@ -500,18 +507,18 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_keys(const uint64_t* __rest
         bucket[j] = 0;
         if (i < cnt) {
             key[j] = __builtin_nontemporal_load(src + i);
-            const uint64_t part = mix64(key[j]) >> (64 - g.p_log2);
-            bucket[j] = (uint16_t)(part & (nb - 1));
+            bucket[j] = (uint16_t)bucket_of(key[j], g.p_log2, nb);
             valid |= 1u << j;
         }
     }
     uint32_t fresh = 0;
     const uint64_t first = (uint64_t)b1 << fine_log2;
-    bin_tile(S, key, bucket, valid, nb, bin2 + first * cap2, cap2, cursor2 + first, tab, g, sp, ctr, fresh);
+    bin_tile(S, key, bucket, valid, nb, g.p_log2, bin2 + first * cap2, cap2, cursor2 + first, tab, g, sp, ctr,
+             fresh);
     add_fresh(ctr, fresh);
 }
 
-constexpr int AGG_THREADS = 256;
+constexpr int AGG_THREADS = 512;
 constexpr uint32_t kPartSlots = 1u << kPartLog2;
 
 // LDS version of table_add over one partition slice (same probe sequence as
@@ -538,6 +545,10 @@ __device__ __forceinline__ int lds_add(uint64_t* lkey, uint32_t* lcnt, uint64_t 
 }
 
 // One workgroup per partition: load the slice, add its keys, store it back.
+// Keys are fetched AGG_BATCH per thread at a time so that many loads are in
+// flight before the LDS work that depends on them.
+constexpr int AGG_BATCH = 8;
+
 __global__ __launch_bounds__(AGG_THREADS) void k_aggregate(const uint64_t* __restrict__ bin2, uint64_t cap2,
                                                            const uint32_t* cursor2, Slot* tab, SpillBuf sp,
                                                            unsigned long long* ctr) {
@@ -547,27 +558,41 @@ __global__ __launch_bounds__(AGG_THREADS) void k_aggregate(const uint64_t* __res
     const uint64_t cnt = min((uint64_t)cursor2[p], cap2);
     if (cnt == 0) return;  // uniform across the workgroup
     Slot* part = tab + (p << kPartLog2);
-    for (uint32_t s = threadIdx.x; s < kPartSlots; s += AGG_THREADS) {
-        const Slot v = part[s];
-        lkey[s] = v.key;
-        lcnt[s] = v.count;
+    constexpr int PER = (int)kPartSlots / AGG_THREADS;
+    {
+        Slot v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) v[u] = part[u * AGG_THREADS + threadIdx.x];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            lkey[u * AGG_THREADS + threadIdx.x] = v[u].key;
+            lcnt[u * AGG_THREADS + threadIdx.x] = v[u].count;
+        }
     }
     __syncthreads();
     uint32_t fresh = 0;
     const uint64_t* src = bin2 + p * cap2;
-    for (uint64_t q0 = 0; q0 < cnt; q0 += AGG_THREADS) {
-        const uint64_t q = q0 + threadIdx.x;
-        int r = ADD_FOUND;
-        uint64_t k = 0;
-        if (q < cnt) {
-            k = __builtin_nontemporal_load(src + q);
-            r = lds_add(lkey, lcnt, k);
-            fresh += (r == ADD_NEW);
+    for (uint64_t q0 = 0; q0 < cnt; q0 += (uint64_t)AGG_THREADS * AGG_BATCH) {
+        uint64_t k[AGG_BATCH];
+#pragma unroll
+        for (int u = 0; u < AGG_BATCH; ++u) {
+            const uint64_t q = q0 + (uint64_t)u * AGG_THREADS + threadIdx.x;
+            k[u] = q < cnt ? __builtin_nontemporal_load(src + q) : kEmptyKey;
         }
-        spill_push(sp, ctr, r == ADD_FULL, k, 1u);
+#pragma unroll
+        for (int u = 0; u < AGG_BATCH; ++u) {
+            int r = ADD_FOUND;
+            if (k[u] != kEmptyKey) {
+                r = lds_add(lkey, lcnt, k[u]);
+                fresh += (r == ADD_NEW);
+            }
+            spill_push(sp, ctr, r == ADD_FULL, k[u], 1u);
+        }
     }
     __syncthreads();
-    for (uint32_t s = threadIdx.x; s < kPartSlots; s += AGG_THREADS) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const uint32_t s = u * AGG_THREADS + threadIdx.x;
         const uint64_t k = lkey[s];
         if (k != kEmptyKey) {
             Slot v;
@@ -861,10 +886,18 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_export_scatter(const Slot* tab
 // Union-find over compact indices.  A root is hooked under the root with the
 // smaller tile key, so parent chains strictly decrease in key and every final
 // root is its component's smallest tile: the label comes for free.
+//
+// Parent words are read with ordinary (cached) loads.  A cached value may be
+// stale, but every value a parent word ever holds is an ancestor of that node,
+// so a walk still only moves down in key.  Hooks are device-scope
+// compare-and-swaps; when one fails, the walk continues from the parent value
+// the CAS returned, which has a strictly smaller key, so every retry makes
+// progress.  Because a root always has the smallest key of its tree, a CAS that
+// succeeds can never close a cycle, even when the other side's root was read
+// stale.
 
-// Walk bound: every chain is far shorter (hooks strictly decrease the key and
-// path halving shortens chains), so hitting it means corrupt state; the walk
-// then stops and raises kErrInternal instead of spinning.
+// Walk bound: every chain is far shorter, so hitting it means corrupt state;
+// the walk then stops and raises kErrInternal instead of spinning.
 constexpr uint32_t kUfMaxSteps = 1u << 24;
 
 __device__ __forceinline__ uint32_t uf_find(uint32_t* parent, uint32_t x, uint32_t s, bool& bad) {
@@ -875,7 +908,7 @@ __device__ __forceinline__ uint32_t uf_find(uint32_t* parent, uint32_t x, uint32
         const uint32_t gp = ld_relaxed(parent + p);
         if (gp >= s) break;
         if (gp == p) return p;
-        st_relaxed(parent + x, gp);  // path halving; x is not a root, no hook races this
+        st_relaxed(parent + x, gp);  // path halving; x is not a root, so no hook targets this word
         x = gp;
     }
     bad = true;
@@ -884,9 +917,9 @@ __device__ __forceinline__ uint32_t uf_find(uint32_t* parent, uint32_t x, uint32
 
 __device__ __forceinline__ void uf_unite(uint32_t* parent, const uint64_t* key, uint32_t a, uint32_t b, uint32_t s,
                                          bool& bad) {
+    a = uf_find(parent, a, s, bad);
+    b = uf_find(parent, b, s, bad);
     for (uint32_t it = 0; it < kUfMaxSteps; ++it) {
-        a = uf_find(parent, a, s, bad);
-        b = uf_find(parent, b, s, bad);
         if (bad || a == b) return;
         if (key[a] < key[b]) {
             const uint32_t t = a;
@@ -894,30 +927,23 @@ __device__ __forceinline__ void uf_unite(uint32_t* parent, const uint64_t* key, 
             b = t;
         }
         // a has the larger key: hook it under b if it is still a root
-        if (atomicCAS(parent + a, a, b) == a) return;
+        const uint32_t old = atomicCAS(parent + a, a, b);
+        if (old == a) return;
+        if (old >= s) {
+            bad = true;
+            return;
+        }
+        a = uf_find(parent, old, s, bad);
+        b = uf_find(parent, b, s, bad);
     }
     bad = true;
-}
-
-__device__ __forceinline__ void link_neighbour(const Slot* tab, const Geo& g, uint32_t* parent,
-                                               const uint64_t* s_key, uint32_t i, uint32_t bx, uint32_t by, uint32_t s,
-                                               bool& bad) {
-    const uint64_t nk = ((uint64_t)bx << 32) | by;
-    const uint64_t slot = table_find(tab, g, nk);
-    if (slot == ~0ull) return;
-    const uint32_t j = tab[slot].aux;
-    if (j == kNotSignificant) return;
-    if (j >= s) {
-        bad = true;
-        return;
-    }
-    uf_unite(parent, s_key, i, j, s, bad);
 }
 
 // Each significant tile looks up its four forward neighbours (x, y+1),
 // (x+1, y-1), (x+1, y), (x+1, y+1); with the symmetric backward lookups done
 // by those neighbours this covers all eight directions.  Biased coordinates
-// of valid tiles lie in [2, 2^32 - 2]; neighbours outside are skipped.
+// of valid tiles lie in [2, 2^32 - 2]; neighbours outside are skipped.  The
+// four home slots are loaded together, then any longer probes finish.
 __global__ void k_hook(const Slot* tab, const Geo g, const uint64_t* s_key, uint32_t* parent,
                        unsigned long long* ctr) {
     const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
@@ -930,18 +956,54 @@ __global__ void k_hook(const Slot* tab, const Geo g, const uint64_t* s_key, uint
         const bool up = by < 0xFFFFFFFEu;
         const bool down = by > 2u;
         const bool right = bx < 0xFFFFFFFEu;
-        if (up) link_neighbour(tab, g, parent, s_key, (uint32_t)i, bx, by + 1, s, bad);
-        if (right) {
-            if (down) link_neighbour(tab, g, parent, s_key, (uint32_t)i, bx + 1, by - 1, s, bad);
-            link_neighbour(tab, g, parent, s_key, (uint32_t)i, bx + 1, by, s, bad);
-            if (up) link_neighbour(tab, g, parent, s_key, (uint32_t)i, bx + 1, by + 1, s, bad);
+        uint64_t nk[4];
+        bool want[4];
+        nk[0] = ((uint64_t)bx << 32) | (uint32_t)(by + 1);
+        want[0] = up;
+        nk[1] = ((uint64_t)(bx + 1) << 32) | (uint32_t)(by - 1);
+        want[1] = right && down;
+        nk[2] = ((uint64_t)(bx + 1) << 32) | by;
+        want[2] = right;
+        nk[3] = ((uint64_t)(bx + 1) << 32) | (uint32_t)(by + 1);
+        want[3] = right && up;
+        uint64_t pos[4];
+        Slot v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            pos[q] = home_slot(mix64(nk[q]), g);
+            if (want[q]) v[q] = tab[pos[q]];
+        }
+        uint32_t j[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            j[q] = kNotSignificant;
+            if (!want[q]) continue;
+            uint32_t steps = 1;
+            while (v[q].key != nk[q] && v[q].key != kEmptyKey && steps < kMaxProbe) {
+                pos[q] = next_slot(pos[q], g);
+                v[q] = tab[pos[q]];
+                ++steps;
+            }
+            if (v[q].key == nk[q]) j[q] = v[q].aux;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (j[q] == kNotSignificant) continue;
+            if (j[q] >= s) {
+                bad = true;
+                continue;
+            }
+            uf_unite(parent, s_key, (uint32_t)i, j[q], s, bad);
         }
     }
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
 }
 
-// Full compression (parent[i] = root), component sizes and the root count.
-__global__ void k_compress(uint32_t* parent, uint32_t* size, unsigned long long* ctr) {
+// Full compression (parent[i] = root), the root count, and component sizes
+// counted up to mu: a member adds itself only while the size it reads is
+// below mu.  Reads only ever under-state the size, so the final value is
+// below mu exactly when the component has fewer than mu tiles.
+__global__ void k_compress(uint32_t* parent, uint32_t* size, uint32_t mu, unsigned long long* ctr) {
     const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t s_round = ((uint64_t)s + 63) / 64 * 64;
@@ -951,7 +1013,7 @@ __global__ void k_compress(uint32_t* parent, uint32_t* size, unsigned long long*
         if (i < s) {
             const uint32_t r = uf_find(parent, (uint32_t)i, s, bad);
             st_relaxed(parent + i, r);
-            atomicAdd(size + r, 1u);
+            if (ld_relaxed(size + r) < mu) atomicAdd(size + r, 1u);
             root = (r == (uint32_t)i);
         }
         wave_count(&ctr[C_COMPONENTS], root);
@@ -1180,10 +1242,11 @@ hipError_t launch_threshold(Slot* tab, uint64_t cap, uint32_t tau, uint64_t* s_k
 }
 
 hipError_t launch_agglomerate(const Slot* tab, uint64_t cap, const uint64_t* s_key, uint32_t* parent,
-                              uint32_t* size, uint64_t s_max, unsigned long long* ctr, hipStream_t stream) {
+                              uint32_t* size, uint32_t mu, uint64_t s_max, unsigned long long* ctr,
+                              hipStream_t stream) {
     const int grid = grid_for(s_max, 256, kPersistBlocks);
     hipLaunchKernelGGL(k_hook, dim3(grid), dim3(256), 0, stream, tab, make_geo(cap), s_key, parent, ctr);
-    hipLaunchKernelGGL(k_compress, dim3(grid), dim3(256), 0, stream, parent, size, ctr);
+    hipLaunchKernelGGL(k_compress, dim3(grid), dim3(256), 0, stream, parent, size, mu, ctr);
     return hipGetLastError();
 }
 
