@@ -541,6 +541,8 @@ raster_status TableRun::finish(raster_result** out) {
     HIP_TRY(bufs.take((void**)&s_count, m * sizeof(uint32_t)), "S counts");
     HIP_TRY(bufs.take((void**)&parent, m * sizeof(uint32_t)), "parent");
     HIP_TRY(bufs.take((void**)&size, m * sizeof(uint32_t)), "sizes");
+    uint32_t* nbr = nullptr;
+    HIP_TRY(bufs.take((void**)&nbr, m * 4 * sizeof(uint32_t)), "neighbour lists");
 
     raster_result* r = new raster_result();
     r->pool = bufs.pool;
@@ -560,7 +562,7 @@ raster_status TableRun::finish(raster_result** out) {
     e = launch_zero_u64((uint64_t*)ctr + C_DISTINCT, C_COUNT_ - C_DISTINCT, stream);
     if (e == hipSuccess) e = launch_threshold(tab, cap, tau, s_key, s_count, parent, size, partials, ctr, stream);
     if (e == hipSuccess) e = hipEventRecord(ev[2], stream);
-    if (e == hipSuccess) e = launch_agglomerate(tab, cap, s_key, parent, size, mu, m, ctr, stream);
+    if (e == hipSuccess) e = launch_agglomerate(tab, cap, s_key, parent, nbr, size, mu, m, ctr, stream);
     if (e == hipSuccess) e = hipEventRecord(ev[3], stream);
     if (e == hipSuccess)
         e = launch_filter(s_key, s_count, parent, size, mu, m, r->kx, r->ky, r->count, r->label, partials, ctr,
@@ -603,6 +605,7 @@ raster_status TableRun::finish(raster_result** out) {
     bufs.give_back(s_count);
     bufs.give_back(parent);
     bufs.give_back(size);
+    bufs.give_back(nbr);
     *out = r;
     return RASTER_OK;
 }

@@ -40,13 +40,14 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 __device__ __forceinline__ uint64_t ld_relaxed(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-// Relaxed atomic accesses at workgroup scope: ordinary cached loads and stores
-// in the ISA, but well-defined when other threads write the same word.
+// Device-scope relaxed accesses for words other workgroups modify during the
+// same kernel (union-find parents and sizes).  They bypass the per-XCD L2, so
+// every read sees the device-coherent value.
 __device__ __forceinline__ uint32_t ld_relaxed(const uint32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_relaxed(uint32_t* p, uint32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
@@ -883,42 +884,66 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_export_scatter(const Slot* tab
 
 // ---------------------------------------------------------- agglomeration ---
 //
-// Union-find over compact indices.  A root is hooked under the root with the
-// smaller tile key, so parent chains strictly decrease in key and every final
-// root is its component's smallest tile: the label comes for free.
-//
-// Parent words are read with ordinary (cached) loads.  A cached value may be
-// stale, but every value a parent word ever holds is an ancestor of that node,
-// so a walk still only moves down in key.  Hooks are device-scope
-// compare-and-swaps; when one fails, the walk continues from the parent value
-// the CAS returned, which has a strictly smaller key, so every retry makes
-// progress.  Because a root always has the smallest key of its tree, a CAS that
-// succeeds can never close a cycle, even when the other side's root was read
-// stale.
+// Connected components of the significant tiles under 8-adjacency, as a
+// union-find forest over compact indices in which every parent has a smaller
+// tile key than its child.  The root of a component is then its smallest
+// tile, so the label comes for free.  Four passes:
+//   link  : each tile looks up its four backward neighbours (x-1, y-1),
+//           (x-1, y), (x-1, y+1), (x, y-1) -- the ones with smaller keys -- and
+//           points at the smallest significant one; it also records them.
+//           Forward neighbours are covered because each forward edge is a
+//           backward edge of the other tile.
+//   jump  : every tile replaces its parent by its root.
+//   merge : for every recorded neighbour in a different tree, the two trees
+//           are united with a device-scope compare-and-swap hook.
+//   finish: every tile takes its final root; component sizes and roots are
+//           counted.
+// Link, jump and finish write only words no other thread hooks in the same
+// kernel, so they use ordinary cached accesses; merge, where concurrent hooks
+// happen, reads parents at device scope.
+
+constexpr uint32_t kNoNeighbour = 0xFFFFFFFFu;
 
 // Walk bound: every chain is far shorter, so hitting it means corrupt state;
 // the walk then stops and raises kErrInternal instead of spinning.
 constexpr uint32_t kUfMaxSteps = 1u << 24;
 
-__device__ __forceinline__ uint32_t uf_find(uint32_t* parent, uint32_t x, uint32_t s, bool& bad) {
+// Root walk with path halving, ordinary loads and stores.  Only for kernels
+// in which no thread hooks (parents only move to ancestors).
+__device__ __forceinline__ uint32_t uf_root_cached(uint32_t* parent, uint32_t x, uint32_t s, bool& bad) {
     for (uint32_t it = 0; it < kUfMaxSteps; ++it) {
-        const uint32_t p = ld_relaxed(parent + x);
+        const uint32_t p = parent[x];
         if (p >= s) break;
         if (p == x) return x;
-        const uint32_t gp = ld_relaxed(parent + p);
+        const uint32_t gp = parent[p];
         if (gp >= s) break;
         if (gp == p) return p;
-        st_relaxed(parent + x, gp);  // path halving; x is not a root, so no hook targets this word
+        parent[x] = gp;
         x = gp;
     }
     bad = true;
     return x;
 }
 
+// Root walk at device scope, for the merge kernel where hooks run concurrently.
+__device__ __forceinline__ uint32_t uf_root(uint32_t* parent, uint32_t x, uint32_t s, bool& bad) {
+    for (uint32_t it = 0; it < kUfMaxSteps; ++it) {
+        const uint32_t p = ld_relaxed(parent + x);
+        if (p >= s) break;
+        if (p == x) return x;
+        x = p;
+    }
+    bad = true;
+    return x;
+}
+
+// Hooks the trees of a and b together: the root with the larger key goes
+// under the other root.  A failed compare-and-swap continues from the parent
+// value it returned, which has a strictly smaller key.
 __device__ __forceinline__ void uf_unite(uint32_t* parent, const uint64_t* key, uint32_t a, uint32_t b, uint32_t s,
                                          bool& bad) {
-    a = uf_find(parent, a, s, bad);
-    b = uf_find(parent, b, s, bad);
+    a = uf_root(parent, a, s, bad);
+    b = uf_root(parent, b, s, bad);
     for (uint32_t it = 0; it < kUfMaxSteps; ++it) {
         if (bad || a == b) return;
         if (key[a] < key[b]) {
@@ -926,25 +951,19 @@ __device__ __forceinline__ void uf_unite(uint32_t* parent, const uint64_t* key, 
             a = b;
             b = t;
         }
-        // a has the larger key: hook it under b if it is still a root
         const uint32_t old = atomicCAS(parent + a, a, b);
         if (old == a) return;
         if (old >= s) {
             bad = true;
             return;
         }
-        a = uf_find(parent, old, s, bad);
-        b = uf_find(parent, b, s, bad);
+        a = uf_root(parent, old, s, bad);
+        b = uf_root(parent, b, s, bad);
     }
     bad = true;
 }
 
-// Each significant tile looks up its four forward neighbours (x, y+1),
-// (x+1, y-1), (x+1, y), (x+1, y+1); with the symmetric backward lookups done
-// by those neighbours this covers all eight directions.  Biased coordinates
-// of valid tiles lie in [2, 2^32 - 2]; neighbours outside are skipped.  The
-// four home slots are loaded together, then any longer probes finish.
-__global__ void k_hook(const Slot* tab, const Geo g, const uint64_t* s_key, uint32_t* parent,
+__global__ void k_link(const Slot* tab, const Geo g, const uint64_t* s_key, uint32_t* parent, uint32_t* nbr,
                        unsigned long long* ctr) {
     const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
     bool bad = false;
@@ -953,19 +972,20 @@ __global__ void k_hook(const Slot* tab, const Geo g, const uint64_t* s_key, uint
         const uint64_t key = s_key[i];
         const uint32_t bx = (uint32_t)(key >> 32);
         const uint32_t by = (uint32_t)key;
-        const bool up = by < 0xFFFFFFFEu;
+        // valid biased coordinates lie in [2, 2^32 - 2]
+        const bool left = bx > 2u;
         const bool down = by > 2u;
-        const bool right = bx < 0xFFFFFFFEu;
+        const bool up = by < 0xFFFFFFFEu;
         uint64_t nk[4];
         bool want[4];
-        nk[0] = ((uint64_t)bx << 32) | (uint32_t)(by + 1);
-        want[0] = up;
-        nk[1] = ((uint64_t)(bx + 1) << 32) | (uint32_t)(by - 1);
-        want[1] = right && down;
-        nk[2] = ((uint64_t)(bx + 1) << 32) | by;
-        want[2] = right;
-        nk[3] = ((uint64_t)(bx + 1) << 32) | (uint32_t)(by + 1);
-        want[3] = right && up;
+        nk[0] = ((uint64_t)(bx - 1) << 32) | (uint32_t)(by - 1);
+        want[0] = left && down;
+        nk[1] = ((uint64_t)(bx - 1) << 32) | by;
+        want[1] = left;
+        nk[2] = ((uint64_t)(bx - 1) << 32) | (uint32_t)(by + 1);
+        want[2] = left && up;
+        nk[3] = ((uint64_t)bx << 32) | (uint32_t)(by - 1);
+        want[3] = down;
         uint64_t pos[4];
         Slot v[4];
 #pragma unroll
@@ -973,10 +993,12 @@ __global__ void k_hook(const Slot* tab, const Geo g, const uint64_t* s_key, uint
             pos[q] = home_slot(mix64(nk[q]), g);
             if (want[q]) v[q] = tab[pos[q]];
         }
+        uint32_t best = (uint32_t)i;
+        uint64_t best_key = key;
         uint32_t j[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            j[q] = kNotSignificant;
+            j[q] = kNoNeighbour;
             if (!want[q]) continue;
             uint32_t steps = 1;
             while (v[q].key != nk[q] && v[q].key != kEmptyKey && steps < kMaxProbe) {
@@ -984,25 +1006,63 @@ __global__ void k_hook(const Slot* tab, const Geo g, const uint64_t* s_key, uint
                 v[q] = tab[pos[q]];
                 ++steps;
             }
-            if (v[q].key == nk[q]) j[q] = v[q].aux;
+            if (v[q].key == nk[q] && v[q].aux != kNotSignificant) {
+                j[q] = v[q].aux;
+                if (j[q] >= s) {
+                    bad = true;
+                    j[q] = kNoNeighbour;
+                } else if (nk[q] < best_key) {
+                    best_key = nk[q];
+                    best = j[q];
+                }
+            }
         }
+        parent[i] = best;
+        uint4 rec;
+        rec.x = j[0];
+        rec.y = j[1];
+        rec.z = j[2];
+        rec.w = j[3];
+        reinterpret_cast<uint4*>(nbr)[i] = rec;
+    }
+    if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
+}
+
+__global__ void k_jump(uint32_t* parent, unsigned long long* ctr) {
+    const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
+    bool bad = false;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < s;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        parent[i] = uf_root_cached(parent, (uint32_t)i, s, bad);
+    if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
+}
+
+__global__ void k_merge(const uint32_t* nbr, const uint64_t* s_key, uint32_t* parent, unsigned long long* ctr) {
+    const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
+    bool bad = false;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < s;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint4 rec = reinterpret_cast<const uint4*>(nbr)[i];
+        const uint32_t j[4] = {rec.x, rec.y, rec.z, rec.w};
+        // After the jump pass parents are roots; a tile whose recorded
+        // neighbours share its root needs no hook.  These first reads may be
+        // stale within this kernel: an equal value still proves the two tiles
+        // are connected, and a differing one only costs a redundant unite.
+        const uint32_t ri = __hip_atomic_load(parent + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            if (j[q] == kNotSignificant) continue;
-            if (j[q] >= s) {
-                bad = true;
-                continue;
-            }
+            if (j[q] == kNoNeighbour) continue;
+            if (__hip_atomic_load(parent + j[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == ri) continue;
             uf_unite(parent, s_key, (uint32_t)i, j[q], s, bad);
         }
     }
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
 }
 
-// Full compression (parent[i] = root), the root count, and component sizes
-// counted up to mu: a member adds itself only while the size it reads is
-// below mu.  Reads only ever under-state the size, so the final value is
-// below mu exactly when the component has fewer than mu tiles.
+// Final roots, the root count, and component sizes counted up to mu: a member
+// adds itself only while the size it reads is below mu.  Reads only ever
+// under-state the size, so the final value is below mu exactly when the
+// component has fewer than mu tiles.
 __global__ void k_compress(uint32_t* parent, uint32_t* size, uint32_t mu, unsigned long long* ctr) {
     const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -1011,8 +1071,8 @@ __global__ void k_compress(uint32_t* parent, uint32_t* size, uint32_t mu, unsign
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < s_round; i += stride) {
         bool root = false;
         if (i < s) {
-            const uint32_t r = uf_find(parent, (uint32_t)i, s, bad);
-            st_relaxed(parent + i, r);
+            const uint32_t r = uf_root_cached(parent, (uint32_t)i, s, bad);
+            parent[i] = r;
             if (ld_relaxed(size + r) < mu) atomicAdd(size + r, 1u);
             root = (r == (uint32_t)i);
         }
@@ -1242,10 +1302,12 @@ hipError_t launch_threshold(Slot* tab, uint64_t cap, uint32_t tau, uint64_t* s_k
 }
 
 hipError_t launch_agglomerate(const Slot* tab, uint64_t cap, const uint64_t* s_key, uint32_t* parent,
-                              uint32_t* size, uint32_t mu, uint64_t s_max, unsigned long long* ctr,
+                              uint32_t* nbr, uint32_t* size, uint32_t mu, uint64_t s_max, unsigned long long* ctr,
                               hipStream_t stream) {
     const int grid = grid_for(s_max, 256, kPersistBlocks);
-    hipLaunchKernelGGL(k_hook, dim3(grid), dim3(256), 0, stream, tab, make_geo(cap), s_key, parent, ctr);
+    hipLaunchKernelGGL(k_link, dim3(grid), dim3(256), 0, stream, tab, make_geo(cap), s_key, parent, nbr, ctr);
+    hipLaunchKernelGGL(k_jump, dim3(grid), dim3(256), 0, stream, parent, ctr);
+    hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, stream, nbr, s_key, parent, ctr);
     hipLaunchKernelGGL(k_compress, dim3(grid), dim3(256), 0, stream, parent, size, mu, ctr);
     return hipGetLastError();
 }
