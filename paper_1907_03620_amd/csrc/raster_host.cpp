@@ -565,7 +565,7 @@ raster_status TableRun::finish(raster_result** out) {
     if (e == hipSuccess) e = launch_agglomerate(tab, cap, s_key, parent, nbr, size, mu, m, ctr, stream);
     if (e == hipSuccess) e = hipEventRecord(ev[3], stream);
     if (e == hipSuccess)
-        e = launch_filter(s_key, s_count, parent, size, mu, m, r->kx, r->ky, r->count, r->label, partials, ctr,
+        e = launch_filter(s_key, s_count, nbr, size, mu, m, r->kx, r->ky, r->count, r->label, partials, ctr,
                           stream);
     if (e == hipSuccess) e = hipEventRecord(ev[4], stream);
     if (e != hipSuccess) return drop(hip_fail(e, "agglomeration launch"));

@@ -151,11 +151,12 @@ hipError_t launch_threshold(Slot* tab, uint64_t cap, uint32_t tau, uint64_t* s_k
                             uint32_t* s_count, uint32_t* parent, uint32_t* size,
                             uint32_t* partials, unsigned long long* ctr, hipStream_t stream);
 
-// Connected components of the significant tiles (8-adjacency): parent[i]
-// ends as the compact index of the component's smallest tile; the component
-// count goes to ctr[C_COMPONENTS] and size[root] counts members up to mu
-// (size[root] >= mu exactly when the component has at least mu tiles).
-// nbr is scratch of 4 words per significant tile, 16-byte aligned.
+// Connected components of the significant tiles (8-adjacency).  On return
+// nbr[i] (its first s words) holds the compact index of the smallest tile of
+// tile i's component; the component count goes to ctr[C_COMPONENTS] and
+// size[root] counts members up to mu (size[root] >= mu exactly when the
+// component has at least mu tiles).  parent is scratch; nbr is scratch of 4
+// words per significant tile, 16-byte aligned.
 hipError_t launch_agglomerate(const Slot* tab, uint64_t cap, const uint64_t* s_key,
                               uint32_t* parent, uint32_t* nbr, uint32_t* size, uint32_t mu, uint64_t s_max,
                               unsigned long long* ctr, hipStream_t stream);

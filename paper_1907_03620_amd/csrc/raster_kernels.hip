@@ -1028,6 +1028,9 @@ __global__ void k_link(const Slot* tab, const Geo g, const uint64_t* s_key, uint
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
 }
 
+// Parents after this pass are roots or, where a concurrent path-halving write
+// lands after the root is stored, ancestors; merge and compress only need
+// ancestors.
 __global__ void k_jump(uint32_t* parent, unsigned long long* ctr) {
     const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
     bool bad = false;
@@ -1059,24 +1062,26 @@ __global__ void k_merge(const uint32_t* nbr, const uint64_t* s_key, uint32_t* pa
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
 }
 
-// Final roots, the root count, and component sizes counted up to mu: a member
-// adds itself only while the size it reads is below mu.  Reads only ever
-// under-state the size, so the final value is below mu exactly when the
-// component has fewer than mu tiles.
-__global__ void k_compress(uint32_t* parent, uint32_t* size, uint32_t mu, unsigned long long* ctr) {
+// Final roots into root[] (a separate array: path halving by other threads
+// keeps rewriting parent words with ancestors that need not be roots), the
+// root count, and component sizes counted up to mu: a member adds itself only
+// while the size it reads is below mu.  Reads only ever under-state the size,
+// so the final value is below mu exactly when the component has fewer than mu
+// tiles.
+__global__ void k_compress(uint32_t* parent, uint32_t* root, uint32_t* size, uint32_t mu, unsigned long long* ctr) {
     const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t s_round = ((uint64_t)s + 63) / 64 * 64;
     bool bad = false;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < s_round; i += stride) {
-        bool root = false;
+        bool is_root = false;
         if (i < s) {
             const uint32_t r = uf_root_cached(parent, (uint32_t)i, s, bad);
-            parent[i] = r;
+            root[i] = r;
             if (ld_relaxed(size + r) < mu) atomicAdd(size + r, 1u);
-            root = (r == (uint32_t)i);
+            is_root = (r == (uint32_t)i);
         }
-        wave_count(&ctr[C_COMPONENTS], root);
+        wave_count(&ctr[C_COMPONENTS], is_root);
     }
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
 }
@@ -1308,7 +1313,9 @@ hipError_t launch_agglomerate(const Slot* tab, uint64_t cap, const uint64_t* s_k
     hipLaunchKernelGGL(k_link, dim3(grid), dim3(256), 0, stream, tab, make_geo(cap), s_key, parent, nbr, ctr);
     hipLaunchKernelGGL(k_jump, dim3(grid), dim3(256), 0, stream, parent, ctr);
     hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, stream, nbr, s_key, parent, ctr);
-    hipLaunchKernelGGL(k_compress, dim3(grid), dim3(256), 0, stream, parent, size, mu, ctr);
+    // the neighbour lists are dead after the merge pass; their first s words
+    // take the final roots
+    hipLaunchKernelGGL(k_compress, dim3(grid), dim3(256), 0, stream, parent, nbr, size, mu, ctr);
     return hipGetLastError();
 }
 

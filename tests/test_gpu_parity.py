@@ -321,3 +321,11 @@ def test_binned_range_error(raster, torch, mid):
     finally:
         raster.set_tuning(None)
     assert e.value.code == raster.E_RANGE
+
+
+def test_repeated_runs_identical(raster, torch, mid, mid_oracle):
+    # races in the union-find passes show up as run-to-run differences
+    d = dev(mid, torch)
+    for rep in range(6):
+        g = raster.cluster(d, precision=2, tau=5, mu=4)
+        assert_same(g, mid_oracle, f"repeat {rep}")
