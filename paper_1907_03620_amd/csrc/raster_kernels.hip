@@ -56,11 +56,22 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Adds the number of lanes with `pred` to *ctr with one atomic per wave.
-// Must be reached by every active lane of the wave.
-__device__ __forceinline__ void wave_count(unsigned long long* ctr, bool pred) {
-    const uint64_t b = __ballot(pred);
-    if (b != 0 && lane_id() == __ffsll((long long)b) - 1) atomicAdd(ctr, (unsigned long long)__popcll(b));
+// Adds every thread's `v` to *ctr with one atomic per workgroup (a single
+// counter word hit once per wave would serialise hundreds of thousands of
+// same-address atomics).  Every thread of the workgroup must call it, once,
+// at a point all of them reach.
+__device__ __forceinline__ void block_count_add(unsigned long long* ctr, uint32_t v) {
+    __shared__ uint32_t part[16];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane_id() == 0) part[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int i = 0; i < (int)((blockDim.x + 63) >> 6); ++i) t += part[i];
+        if (t) atomicAdd(ctr, t);
+    }
 }
 
 // Projection of Section 3.2: one binary64 product per coordinate, truncated
@@ -218,10 +229,7 @@ __global__ void k_count_direct(const T* __restrict__ pts, int64_t n, double scal
         }
         spill_push(sp, ctr, r == ADD_FULL, key[j], 1u);
     }
-    // one atomic per wave for the inserted-key counter
-    uint32_t tot = fresh;
-    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
-    if (lane_id() == 0 && tot) atomicAdd(&ctr[C_INSERTED], (unsigned long long)tot);
+    block_count_add(&ctr[C_INSERTED], fresh);
 }
 
 // Counting with LDS pre-aggregation: a workgroup first combines equal tiles
@@ -303,15 +311,14 @@ __global__ void k_count_preagg(const T* __restrict__ pts, int64_t n, double scal
         }
         spill_push(sp, ctr, r == ADD_FULL, k, c);
     }
-    uint32_t tot = fresh;
-    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
-    if (lane_id() == 0 && tot) atomicAdd(&ctr[C_INSERTED], (unsigned long long)tot);
+    block_count_add(&ctr[C_INSERTED], fresh);
 }
 
 __global__ void k_insert_records(const uint64_t* keys, const uint32_t* counts, uint64_t n, Slot* tab,
                                  const Geo g, SpillBuf sp, unsigned long long* ctr) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t n_round = (n + 63) / 64 * 64;  // whole waves iterate together
+    uint32_t fresh = 0;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_round; i += stride) {
         int r = ADD_FOUND;
         uint64_t k = 0;
@@ -321,15 +328,17 @@ __global__ void k_insert_records(const uint64_t* keys, const uint32_t* counts, u
             c = counts[i];
             r = table_add(tab, g, k, c);
         }
-        wave_count(&ctr[C_INSERTED], r == ADD_NEW);
+        fresh += (r == ADD_NEW);
         spill_push(sp, ctr, r == ADD_FULL, k, c);
     }
+    block_count_add(&ctr[C_INSERTED], fresh);
 }
 
 __global__ void k_rehash(const Slot* from, uint64_t from_cap, Slot* to, const Geo to_g, SpillBuf sp,
                          unsigned long long* ctr) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t n_round = (from_cap + 63) / 64 * 64;  // whole waves iterate together
+    uint32_t fresh = 0;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_round; i += stride) {
         int r = ADD_FOUND;
         uint64_t k = kEmptyKey;
@@ -340,9 +349,10 @@ __global__ void k_rehash(const Slot* from, uint64_t from_cap, Slot* to, const Ge
             c = s.count;
             if (k != kEmptyKey) r = table_add(to, to_g, k, c);
         }
-        wave_count(&ctr[C_INSERTED], r == ADD_NEW);
+        fresh += (r == ADD_NEW);
         spill_push(sp, ctr, r == ADD_FULL, k, c);
     }
+    block_count_add(&ctr[C_INSERTED], fresh);
 }
 
 // ------------------------------------------------------ binned contraction ---
@@ -442,8 +452,7 @@ __device__ void bin_tile(BinScratch& S, const uint64_t (&key)[BIN_ITEMS], const 
 }
 
 __device__ __forceinline__ void add_fresh(unsigned long long* ctr, uint32_t fresh) {
-    for (int off = 32; off > 0; off >>= 1) fresh += __shfl_xor(fresh, off);
-    if (lane_id() == 0 && fresh) atomicAdd(&ctr[C_INSERTED], (unsigned long long)fresh);
+    block_count_add(&ctr[C_INSERTED], fresh);
 }
 
 template <typename T>
@@ -1073,16 +1082,16 @@ __global__ void k_compress(uint32_t* parent, uint32_t* root, uint32_t* size, uin
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t s_round = ((uint64_t)s + 63) / 64 * 64;
     bool bad = false;
+    uint32_t roots = 0;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < s_round; i += stride) {
-        bool is_root = false;
         if (i < s) {
             const uint32_t r = uf_root_cached(parent, (uint32_t)i, s, bad);
             root[i] = r;
             if (ld_relaxed(size + r) < mu) atomicAdd(size + r, 1u);
-            is_root = (r == (uint32_t)i);
+            roots += (r == (uint32_t)i);
         }
-        wave_count(&ctr[C_COMPONENTS], is_root);
     }
+    block_count_add(&ctr[C_COMPONENTS], roots);
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
 }
 
