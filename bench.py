@@ -101,7 +101,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-strip", type=float, default=2000.0)
     ap.add_argument("--tuning", default="", help="JSON object of raster_tuning fields")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (3 times), to scale HBM counters")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "copies": 3}), flush=True)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -145,16 +158,19 @@ def main():
     value = n_total * args.steps / elapsed
 
     st = results[-1].stats
+    binned = st["flushes"] > 0
     launches = sum(r.stats["count_launches"] for r in results)
     us_kernel = sum(r.stats["us_count_kernel"] for r in results)
     avg_us = us_kernel / max(1, launches)
-    bytes_per_launch = 16.0 * args.chunk
+    points_per_launch = n_total * args.steps / max(1, launches)
+    bytes_per_launch = 16.0 * points_per_launch
     achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9
-    traffic = measured_traffic(args.chunk)
+    traffic = measured_traffic(int(points_per_launch))
     m, s, t = st["distinct_tiles"], st["significant_tiles"], st["tiles"]
     alg_bytes = 16.0 * n_total + 2 * 12.0 * m + 20.0 * s + 20.0 * t
     phases = {k: round(float(np.mean([r.stats[k] for r in results])), 1)
-              for k in ("us_contract", "us_threshold", "us_agglomerate", "us_filter")}
+              for k in ("us_contract", "us_threshold", "us_agglomerate", "us_filter",
+                        "us_count_kernel", "us_bin_keys", "us_aggregate")}
 
     line = {
         "metric": METRIC,
@@ -178,8 +194,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "project_count (k_count_direct)" if raster.get_tuning().preagg_slots == 0
-                      else "project_count (k_count_preagg)",
+            "kernel": "k_bin_points (projection + level-1 binning)" if binned
+                      else "k_count_direct (projection + device-table count)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
@@ -187,6 +203,7 @@ def main():
             "traffic": traffic,
             "avg_launch_us": avg_us,
             "bytes_per_launch": bytes_per_launch,
+            "algorithmic_bytes": "16 B of FP64 coordinates per point, read once",
         },
         "hbm_gbps_algorithmic_step": alg_bytes / (ms_per_step * 1e-3) / 1e9,
         "phases_us": phases,
