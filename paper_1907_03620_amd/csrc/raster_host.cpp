@@ -559,13 +559,31 @@ raster_status TableRun::finish(raster_result** out) {
     r->ky = r->kx + m;
     r->count = (uint32_t*)(r->ky + m);
 
+    // one job: the whole table
+    single.job.pts = nullptr;
+    single.job.n = n_points;
+    single.job.scale = scale;
+    single.job.slot_base = 0;
+    single.job.cap = cap;
+    single.job.tau = tau;
+    single.job.mu = mu;
+    single.job.dtype = 0;
+    single.job.first_tile = 0;
+    single.dims.slots = cap;
+    single.dims.njobs = 1;
+    single.dims.tiles = 0;
+    SingleJob* sj_dev = nullptr;
+    HIP_TRY(bufs.take((void**)&sj_dev, sizeof(SingleJob)), "job descriptor");
+    HIP_TRY(hipMemcpyAsync(sj_dev, &single, sizeof(SingleJob), hipMemcpyHostToDevice, stream), "job descriptor");
+    JobView jv{&sj_dev->dims, &sj_dev->job, nullptr, nullptr, nullptr};
+
     e = launch_zero_u64((uint64_t*)ctr + C_DISTINCT, C_COUNT_ - C_DISTINCT, stream);
-    if (e == hipSuccess) e = launch_threshold(tab, cap, tau, s_key, s_count, parent, size, partials, ctr, stream);
+    if (e == hipSuccess) e = launch_threshold(tab, jv, s_key, s_count, size, partials, ctr, stream);
     if (e == hipSuccess) e = hipEventRecord(ev[2], stream);
-    if (e == hipSuccess) e = launch_agglomerate(tab, cap, s_key, parent, nbr, size, mu, m, ctr, stream);
+    if (e == hipSuccess) e = launch_agglomerate(tab, jv, s_key, parent, nbr, size, m, ctr, stream);
     if (e == hipSuccess) e = hipEventRecord(ev[3], stream);
     if (e == hipSuccess)
-        e = launch_filter(s_key, s_count, nbr, size, mu, m, r->kx, r->ky, r->count, r->label, partials, ctr,
+        e = launch_filter(jv, s_key, s_count, nbr, size, r->kx, r->ky, r->count, r->label, nullptr, partials, ctr,
                           stream);
     if (e == hipSuccess) e = hipEventRecord(ev[4], stream);
     if (e != hipSuccess) return drop(hip_fail(e, "agglomeration launch"));
@@ -606,6 +624,7 @@ raster_status TableRun::finish(raster_result** out) {
     bufs.give_back(parent);
     bufs.give_back(size);
     bufs.give_back(nbr);
+    bufs.give_back(sj_dev);
     *out = r;
     return RASTER_OK;
 }
@@ -695,7 +714,7 @@ raster_status raster_result_stats(const raster_result* r, raster_stats* out) {
 void raster_result_free(raster_result* r) {
     if (!r) return;
     if (r->pool && r->block) r->pool->release(r->block);
-    delete r;
+    delete r;  // a shared block goes back to the pool with its last result
 }
 
 raster_status raster_begin_scaled(double scale, uint32_t tau, uint32_t mu, int64_t tile_hint, hipStream_t stream,

@@ -30,9 +30,8 @@ struct Geo {
     uint32_t cp_log2;  // log2 slots per partition
     uint32_t p_log2;   // log2 partitions
 };
-inline Geo make_geo(uint64_t cap) {
-    uint32_t l = 0;
-    while ((1ull << l) < cap) ++l;
+__host__ __device__ inline Geo make_geo(uint64_t cap) {
+    const uint32_t l = (uint32_t)__builtin_ctzll(cap);  // cap is a power of two
     Geo g;
     g.cap = cap;
     g.cp_log2 = l < kPartLog2 ? l : kPartLog2;
@@ -77,6 +76,39 @@ constexpr int kCounterWords = 16;  // padded to 128 bytes
 constexpr uint64_t kErrRange = 1;
 constexpr uint64_t kErrSpillOverflow = 2;
 constexpr uint64_t kErrInternal = 4;  // union-find walk hit its bound or an index out of range
+
+// Per-job parameters read by the kernels.  A single table is one job with
+// slot_base 0; a batch lays its jobs' tables one after another in one arena,
+// each a whole number of 4096-slot partitions.
+struct JobInfo {
+    const void* pts;      // batched counting: the job's points
+    int64_t n;            // batched counting: its point count
+    double scale;
+    uint64_t slot_base;   // first slot of the job's table
+    uint64_t cap;         // slots of the job's table (power of two)
+    uint32_t tau, mu;
+    int32_t dtype;        // 1 = FP32, 2 = FP64
+    uint32_t first_tile;  // batched counting: first point tile of the job
+};
+
+// Sizes read from device memory, so that a captured graph can be replayed
+// for any batch that fits its buffers.
+struct Dims {
+    uint64_t slots;   // table slots in use (all jobs)
+    uint32_t njobs;
+    uint32_t tiles;   // point tiles of the batched counting launch
+};
+
+// Job-aware views passed to the post-contraction kernels.  part_job maps a
+// 4096-slot partition to its job and s_job a compact tile to its job; both
+// are null for a single table, and non-null for a batch (even of one job).
+struct JobView {
+    const Dims* dims;
+    const JobInfo* jobs;
+    const uint32_t* part_job;
+    uint32_t* s_job;
+    unsigned long long* job_ctr;  // kCounterWords per job (multi-job only)
+};
 
 // Overflow records of the counting kernels.
 struct SpillBuf {
@@ -144,27 +176,48 @@ hipError_t launch_export_tiles(const Slot* tab, uint64_t tcap, uint64_t* keys, u
                                uint64_t cap, uint32_t* partials, unsigned long long* ctr,
                                hipStream_t stream);
 
-// Significance scan: flags count >= tau, writes the compact arrays S_key,
-// S_count, sets slot.aux, initialises parent[i] = i and size[i] = 0, and fills
-// ctr[C_DISTINCT], ctr[C_SIGNIFICANT], ctr[C_SUM].
-hipError_t launch_threshold(Slot* tab, uint64_t cap, uint32_t tau, uint64_t* s_key,
-                            uint32_t* s_count, uint32_t* parent, uint32_t* size,
+// Significance scan: flags count >= tau (per job), writes the compact arrays
+// S_key, S_count (and S_job for several jobs), sets slot.aux, zeroes size[i],
+// and fills ctr[C_DISTINCT], ctr[C_SIGNIFICANT], ctr[C_SUM] (per job too).
+hipError_t launch_threshold(Slot* tab, const JobView& jv, uint64_t* s_key, uint32_t* s_count, uint32_t* size,
                             uint32_t* partials, unsigned long long* ctr, hipStream_t stream);
 
 // Connected components of the significant tiles (8-adjacency).  On return
 // nbr[i] (its first s words) holds the compact index of the smallest tile of
 // tile i's component; the component count goes to ctr[C_COMPONENTS] and
-// size[root] counts members up to mu (size[root] >= mu exactly when the
-// component has at least mu tiles).  parent is scratch; nbr is scratch of 4
-// words per significant tile, 16-byte aligned.
-hipError_t launch_agglomerate(const Slot* tab, uint64_t cap, const uint64_t* s_key,
-                              uint32_t* parent, uint32_t* nbr, uint32_t* size, uint32_t mu, uint64_t s_max,
-                              unsigned long long* ctr, hipStream_t stream);
+// size[root] counts members up to the job's mu (size[root] >= mu exactly when
+// the component has at least mu tiles).  parent is scratch; nbr is scratch of
+// 4 words per significant tile, 16-byte aligned.
+hipError_t launch_agglomerate(const Slot* tab, const JobView& jv, const uint64_t* s_key, uint32_t* parent,
+                              uint32_t* nbr, uint32_t* size, uint64_t s_max, unsigned long long* ctr,
+                              hipStream_t stream);
 
-// mu filter and output compaction: rows of kept components in compact order.
-hipError_t launch_filter(const uint64_t* s_key, const uint32_t* s_count, const uint32_t* parent,
-                         const uint32_t* size, uint32_t mu, uint64_t s_max, int32_t* out_kx,
-                         int32_t* out_ky, uint32_t* out_count, uint64_t* out_label,
-                         uint32_t* partials, unsigned long long* ctr, hipStream_t stream);
+// mu filter and output compaction: rows of kept components in compact order
+// (out_job gets each row's job for several jobs).
+hipError_t launch_filter(const JobView& jv, const uint64_t* s_key, const uint32_t* s_count, const uint32_t* root,
+                         const uint32_t* size, int32_t* out_kx, int32_t* out_ky, uint32_t* out_count,
+                         uint64_t* out_label, uint32_t* out_job, uint32_t* partials, unsigned long long* ctr,
+                         hipStream_t stream);
+
+// Batched counting: one launch over the point tiles of every job, each point
+// added to its job's table with device atomics (LDS pre-aggregation per tile
+// when tu.preagg_slots > 0).  A key that finds no room raises its job's
+// C_SPILLED count; such a job is redone alone.
+hipError_t launch_batch_count(const JobView& jv, const uint32_t* tile_prefix, Slot* tab, const KernelTuning& tu,
+                              int max_tiles_grid, hipStream_t stream);
+
+// Fills table slots [0, dims->slots) with empty slots.
+hipError_t launch_fill_dims(Slot* tab, const Dims* dims, hipStream_t stream);
+
+// Per-job boundaries of a job-sorted array seg_job[0, *n): start[j], end[j]
+// (both must be zero for jobs without entries beforehand).
+hipError_t launch_bounds(const uint32_t* seg_job, const unsigned long long* n, uint32_t* start, uint32_t* end,
+                         uint64_t n_max, hipStream_t stream);
+
+// Per-job components, clusters, significant tiles and rows, from the compact
+// ranges [s_start, s_end) and row ranges [o_start, o_end).
+hipError_t launch_job_stats(const JobView& jv, const uint32_t* root, const uint32_t* size, const uint32_t* s_start,
+                            const uint32_t* s_end, const uint32_t* o_start, const uint32_t* o_end,
+                            uint32_t max_jobs, hipStream_t stream);
 
 }  // namespace rst

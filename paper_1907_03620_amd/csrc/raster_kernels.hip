@@ -759,24 +759,46 @@ __global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* partials, unsi
 }
 
 // ---- significance scan (Algorithm 1: drop tiles with fewer than tau points) --
+//
+// Scan tiles are 4096 slots, the size of a table partition, so with several
+// jobs every scan tile belongs to exactly one job (its tau, its counters).
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_threshold_count(const Slot* tab, uint64_t cap, uint32_t tau,
-                                                                  uint32_t* partials, unsigned long long* ctr) {
+__device__ __forceinline__ uint32_t job_of_slot(const JobView& jv, bool multi, uint64_t slot) {
+    return multi ? jv.part_job[slot >> kPartLog2] : 0u;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_threshold_count(const Slot* tab, JobView jv, uint32_t* partials,
+                                                                  unsigned long long* ctr) {
     __shared__ unsigned long long red[SCAN_WAVES];
+    const uint64_t N = jv.dims->slots;
+    const bool multi = jv.part_job != nullptr;
     uint64_t lo, hi;
-    block_range(cap, lo, hi);
+    block_range(N, lo, hi);
     unsigned long long sig = 0, occ = 0, sum = 0;
     for (uint64_t t0 = lo; t0 < hi; t0 += SCAN_TILE) {
+        const uint32_t job = job_of_slot(jv, multi, t0);
+        const uint32_t tau = jv.jobs[job].tau;
+        unsigned long long occ_t = 0, sum_t = 0;
 #pragma unroll
         for (int j = 0; j < SCAN_ITEMS; ++j) {
             const uint64_t i = t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x;
             if (i < hi) {
-                const Slot s = tab[i];
-                if (s.key != kEmptyKey) {
-                    occ += 1;
-                    sum += s.count;
-                    sig += (s.count >= tau);
+                const Slot v = tab[i];
+                if (v.key != kEmptyKey) {
+                    occ_t += 1;
+                    sum_t += v.count;
+                    sig += (v.count >= tau);
                 }
+            }
+        }
+        occ += occ_t;
+        sum += sum_t;
+        if (multi) {
+            occ_t = block_sum(occ_t, red);
+            sum_t = block_sum(sum_t, red);
+            if (threadIdx.x == 0) {
+                if (occ_t) atomicAdd(&jv.job_ctr[(uint64_t)job * kCounterWords + C_DISTINCT], occ_t);
+                if (sum_t) atomicAdd(&jv.job_ctr[(uint64_t)job * kCounterWords + C_SUM], sum_t);
             }
         }
     }
@@ -790,15 +812,18 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_threshold_count(const Slot* ta
     }
 }
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_threshold_scatter(Slot* tab, uint64_t cap, uint32_t tau,
-                                                                    const uint32_t* offsets, uint64_t* s_key,
-                                                                    uint32_t* s_count, uint32_t* parent,
+__global__ __launch_bounds__(SCAN_THREADS) void k_threshold_scatter(Slot* tab, JobView jv, const uint32_t* offsets,
+                                                                    uint64_t* s_key, uint32_t* s_count,
                                                                     uint32_t* size) {
     __shared__ TileScratch ts;
+    const uint64_t N = jv.dims->slots;
+    const bool multi = jv.part_job != nullptr;
     uint64_t lo, hi;
-    block_range(cap, lo, hi);
+    block_range(N, lo, hi);
     uint64_t run = offsets[blockIdx.x];
     for (uint64_t t0 = lo; t0 < hi; t0 += SCAN_TILE) {
+        const uint32_t job = job_of_slot(jv, multi, t0);
+        const uint32_t tau = jv.jobs[job].tau;
         uint32_t bits = 0;
         uint64_t key[SCAN_ITEMS];
         uint32_t cnt[SCAN_ITEMS];
@@ -808,10 +833,10 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_threshold_scatter(Slot* tab, u
             key[j] = kEmptyKey;
             cnt[j] = 0;
             if (i < hi) {
-                const Slot s = tab[i];
-                key[j] = s.key;
-                cnt[j] = s.count;
-                if (s.key != kEmptyKey && s.count >= tau) bits |= 1u << j;
+                const Slot v = tab[i];
+                key[j] = v.key;
+                cnt[j] = v.count;
+                if (v.key != kEmptyKey && v.count >= tau) bits |= 1u << j;
             }
         }
         uint32_t pos[SCAN_ITEMS];
@@ -824,8 +849,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_threshold_scatter(Slot* tab, u
                 const uint64_t p = run + pos[j];
                 s_key[p] = key[j];
                 s_count[p] = cnt[j];
-                parent[p] = (uint32_t)p;
                 size[p] = 0;
+                if (multi) jv.s_job[p] = job;
                 tab[i].aux = (uint32_t)p;
             } else {
                 tab[i].aux = kNotSignificant;
@@ -972,12 +997,16 @@ __device__ __forceinline__ void uf_unite(uint32_t* parent, const uint64_t* key, 
     bad = true;
 }
 
-__global__ void k_link(const Slot* tab, const Geo g, const uint64_t* s_key, uint32_t* parent, uint32_t* nbr,
+__global__ void k_link(const Slot* tab, JobView jv, const uint64_t* s_key, uint32_t* parent, uint32_t* nbr,
                        unsigned long long* ctr) {
     const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
+    const bool multi = jv.part_job != nullptr;
     bool bad = false;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < s;
          i += (uint64_t)gridDim.x * blockDim.x) {
+        const JobInfo& J = jv.jobs[multi ? jv.s_job[i] : 0u];
+        const Slot* jt = tab + J.slot_base;
+        const Geo g = make_geo(J.cap);
         const uint64_t key = s_key[i];
         const uint32_t bx = (uint32_t)(key >> 32);
         const uint32_t by = (uint32_t)key;
@@ -1000,7 +1029,7 @@ __global__ void k_link(const Slot* tab, const Geo g, const uint64_t* s_key, uint
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             pos[q] = home_slot(mix64(nk[q]), g);
-            if (want[q]) v[q] = tab[pos[q]];
+            if (want[q]) v[q] = jt[pos[q]];
         }
         uint32_t best = (uint32_t)i;
         uint64_t best_key = key;
@@ -1012,7 +1041,7 @@ __global__ void k_link(const Slot* tab, const Geo g, const uint64_t* s_key, uint
             uint32_t steps = 1;
             while (v[q].key != nk[q] && v[q].key != kEmptyKey && steps < kMaxProbe) {
                 pos[q] = next_slot(pos[q], g);
-                v[q] = tab[pos[q]];
+                v[q] = jt[pos[q]];
                 ++steps;
             }
             if (v[q].key == nk[q] && v[q].aux != kNotSignificant) {
@@ -1077,8 +1106,9 @@ __global__ void k_merge(const uint32_t* nbr, const uint64_t* s_key, uint32_t* pa
 // while the size it reads is below mu.  Reads only ever under-state the size,
 // so the final value is below mu exactly when the component has fewer than mu
 // tiles.
-__global__ void k_compress(uint32_t* parent, uint32_t* root, uint32_t* size, uint32_t mu, unsigned long long* ctr) {
+__global__ void k_compress(JobView jv, uint32_t* parent, uint32_t* root, uint32_t* size, unsigned long long* ctr) {
     const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
+    const bool multi = jv.part_job != nullptr;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t s_round = ((uint64_t)s + 63) / 64 * 64;
     bool bad = false;
@@ -1087,6 +1117,7 @@ __global__ void k_compress(uint32_t* parent, uint32_t* root, uint32_t* size, uin
         if (i < s) {
             const uint32_t r = uf_root_cached(parent, (uint32_t)i, s, bad);
             root[i] = r;
+            const uint32_t mu = jv.jobs[multi ? jv.s_job[i] : 0u].mu;
             if (ld_relaxed(size + r) < mu) atomicAdd(size + r, 1u);
             roots += (r == (uint32_t)i);
         }
@@ -1097,11 +1128,12 @@ __global__ void k_compress(uint32_t* parent, uint32_t* root, uint32_t* size, uin
 
 // ---- mu filter (Algorithm 1: keep clusters of at least mu tiles) -----------
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_filter_count(const uint32_t* parent, const uint32_t* size,
-                                                               uint32_t mu, uint32_t* partials,
-                                                               unsigned long long* ctr) {
+__global__ __launch_bounds__(SCAN_THREADS) void k_filter_count(JobView jv, const uint32_t* root, const uint32_t* size,
+                                                               uint32_t* partials, unsigned long long* ctr) {
     __shared__ unsigned long long red[SCAN_WAVES];
     const uint64_t s = ctr[C_SIGNIFICANT];
+    const bool multi = jv.part_job != nullptr;
+    const uint32_t mu0 = jv.jobs[0].mu;
     uint64_t lo, hi;
     block_range(s, lo, hi);
     unsigned long long keep = 0, kept_roots = 0;
@@ -1110,7 +1142,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_filter_count(const uint32_t* p
         for (int j = 0; j < SCAN_ITEMS; ++j) {
             const uint64_t i = t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x;
             if (i < hi) {
-                const uint32_t r = parent[i];
+                const uint32_t r = root[i];
+                const uint32_t mu = multi ? jv.jobs[jv.s_job[i]].mu : mu0;
                 const bool k = r < s && size[r] >= mu;
                 keep += k;
                 kept_roots += (k && r == (uint32_t)i);
@@ -1124,27 +1157,30 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_filter_count(const uint32_t* p
     }
 }
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_filter_scatter(const uint64_t* s_key, const uint32_t* s_count,
-                                                                 const uint32_t* parent, const uint32_t* size,
-                                                                 uint32_t mu, const uint32_t* offsets,
+__global__ __launch_bounds__(SCAN_THREADS) void k_filter_scatter(JobView jv, const uint64_t* s_key,
+                                                                 const uint32_t* s_count, const uint32_t* root,
+                                                                 const uint32_t* size, const uint32_t* offsets,
                                                                  const unsigned long long* ctr, int32_t* out_kx,
                                                                  int32_t* out_ky, uint32_t* out_count,
-                                                                 uint64_t* out_label) {
+                                                                 uint64_t* out_label, uint32_t* out_job) {
     __shared__ TileScratch ts;
     const uint64_t s = ctr[C_SIGNIFICANT];
+    const bool multi = jv.part_job != nullptr;
+    const uint32_t mu0 = jv.jobs[0].mu;
     uint64_t lo, hi;
     block_range(s, lo, hi);
     uint64_t run = offsets[blockIdx.x];
     for (uint64_t t0 = lo; t0 < hi; t0 += SCAN_TILE) {
         uint32_t bits = 0;
-        uint32_t root[SCAN_ITEMS];
+        uint32_t rt[SCAN_ITEMS];
 #pragma unroll
         for (int j = 0; j < SCAN_ITEMS; ++j) {
             const uint64_t i = t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x;
-            root[j] = 0;
+            rt[j] = 0;
             if (i < hi) {
-                root[j] = parent[i];
-                if (root[j] < s && size[root[j]] >= mu) bits |= 1u << j;
+                rt[j] = root[i];
+                const uint32_t mu = multi ? jv.jobs[jv.s_job[i]].mu : mu0;
+                if (rt[j] < s && size[rt[j]] >= mu) bits |= 1u << j;
             }
         }
         uint32_t pos[SCAN_ITEMS];
@@ -1158,9 +1194,145 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_filter_scatter(const uint64_t*
             out_kx[p] = (int32_t)((uint32_t)(key >> 32) - 0x80000000u);
             out_ky[p] = (int32_t)((uint32_t)key - 0x80000000u);
             out_count[p] = s_count[i];
-            out_label[p] = s_key[root[j]];
+            out_label[p] = s_key[rt[j]];
+            if (multi) out_job[p] = jv.s_job[i];
         }
         run += total;
+    }
+}
+
+// ---- per-job ranges and statistics (batches) ----------------------------------
+
+__global__ void k_bounds(const uint32_t* seg_job, const unsigned long long* n_dev, uint32_t* start, uint32_t* end) {
+    const uint64_t n = *n_dev;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t j = seg_job[i];
+        if (i == 0 || seg_job[i - 1] != j) start[j] = (uint32_t)i;
+        if (i + 1 == n || seg_job[i + 1] != j) end[j] = (uint32_t)(i + 1);
+    }
+}
+
+// One workgroup per job: roots and kept roots among the job's compact tiles.
+__global__ __launch_bounds__(SCAN_THREADS) void k_job_stats(JobView jv, const uint32_t* root, const uint32_t* size,
+                                                            const uint32_t* s_start, const uint32_t* s_end,
+                                                            const uint32_t* o_start, const uint32_t* o_end) {
+    __shared__ unsigned long long red[SCAN_WAVES];
+    const uint32_t job = blockIdx.x;
+    if (job >= jv.dims->njobs) return;  // uniform
+    const uint32_t mu = jv.jobs[job].mu;
+    const uint32_t a = s_start[job], b = s_end[job];
+    unsigned long long comps = 0, kept = 0;
+    for (uint32_t i = a + threadIdx.x; i < b; i += SCAN_THREADS) {
+        if (root[i] == i) {
+            comps += 1;
+            kept += (size[i] >= mu);
+        }
+    }
+    comps = block_sum(comps, red);
+    kept = block_sum(kept, red);
+    if (threadIdx.x == 0) {
+        unsigned long long* c = jv.job_ctr + (uint64_t)job * kCounterWords;
+        c[C_COMPONENTS] = comps;
+        c[C_CLUSTERS] = kept;
+        c[C_SIGNIFICANT] = b - a;
+        c[C_TILES] = o_end[job] - o_start[job];
+    }
+}
+
+// ---- batched counting: every job's points in one launch -----------------------
+
+__global__ void k_fill_dims(Slot* tab, const Dims* dims) {
+    const uint64_t cap = dims->slots;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        Slot v;
+        v.key = kEmptyKey;
+        v.count = 0;
+        v.aux = kNotSignificant;
+        tab[i] = v;
+    }
+}
+
+__device__ __forceinline__ uint32_t job_of_tile(const uint32_t* tile_prefix, uint32_t njobs, uint32_t t) {
+    uint32_t lo = 0, hi = njobs;  // find the last j with tile_prefix[j] <= t
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (tile_prefix[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool job_point_key(const JobInfo& J, int64_t i, uint64_t& key) {
+    double x, y;
+    if (J.dtype == 1) load_point(static_cast<const float*>(J.pts), i, x, y);
+    else load_point(static_cast<const double*>(J.pts), i, x, y);
+    return tile_key(x, y, J.scale, key);
+}
+
+// Work tile t holds blockDim * ITEMS consecutive points of one job.  With
+// lds_log2 > 0 the tile's keys are first combined in an LDS hash table and
+// each distinct tile of the work tile is added once.
+template <int ITEMS>
+__global__ void k_batch_count(JobView jv, const uint32_t* tile_prefix, Slot* tab, int lds_log2) {
+    extern __shared__ unsigned char smem[];
+    const uint32_t tiles = jv.dims->tiles, njobs = jv.dims->njobs;
+    const uint32_t L = lds_log2 > 0 ? (1u << lds_log2) : 0u;
+    uint64_t* lkey = reinterpret_cast<uint64_t*>(smem);
+    uint32_t* lcnt = reinterpret_cast<uint32_t*>(lkey + L);
+    for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const uint32_t job = job_of_tile(tile_prefix, njobs, t);
+        const JobInfo& J = jv.jobs[job];
+        Slot* jt = tab + J.slot_base;
+        const Geo g = make_geo(J.cap);
+        unsigned long long* jc = jv.job_ctr + (uint64_t)job * kCounterWords;
+        const int64_t base = (int64_t)(t - J.first_tile) * blockDim.x * ITEMS;
+        if (L) {
+            for (uint32_t q = threadIdx.x; q < L; q += blockDim.x) {
+                lkey[q] = kEmptyKey;
+                lcnt[q] = 0;
+            }
+            __syncthreads();
+        }
+        bool bad = false;
+        uint32_t full = 0;
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int64_t i = base + (int64_t)j * blockDim.x + threadIdx.x;
+            if (i >= J.n) continue;
+            uint64_t k;
+            if (!job_point_key(J, i, k)) {
+                bad = true;
+                continue;
+            }
+            bool done = false;
+            if (L) {
+                uint32_t pos = (uint32_t)(mix64(k) >> 40) & (L - 1);
+                for (int p = 0; p < 8 && !done; ++p) {
+                    uint64_t cur = *(volatile uint64_t*)&lkey[pos];
+                    if (cur == kEmptyKey)
+                        cur = atomicCAS(reinterpret_cast<unsigned long long*>(&lkey[pos]),
+                                        (unsigned long long)kEmptyKey, (unsigned long long)k);
+                    if (cur == kEmptyKey || cur == k) {
+                        atomicAdd(&lcnt[pos], 1u);
+                        done = true;
+                    }
+                    pos = (pos + 1) & (L - 1);
+                }
+            }
+            if (!done) full += (table_add(jt, g, k, 1u) == ADD_FULL);
+        }
+        if (L) {
+            __syncthreads();
+            for (uint32_t q = threadIdx.x; q < L; q += blockDim.x) {
+                const uint64_t k = lkey[q];
+                if (k != kEmptyKey) full += (table_add(jt, g, k, lcnt[q]) == ADD_FULL);
+            }
+            __syncthreads();
+        }
+        if (bad) atomicOr(&jc[C_ERROR], (unsigned long long)kErrRange);
+        if (full) atomicAdd(&jc[C_SPILLED], (unsigned long long)full);
     }
 }
 
@@ -1304,40 +1476,74 @@ hipError_t launch_export_tiles(const Slot* tab, uint64_t tcap, uint64_t* keys, u
     return hipGetLastError();
 }
 
-hipError_t launch_threshold(Slot* tab, uint64_t cap, uint32_t tau, uint64_t* s_key, uint32_t* s_count,
-                            uint32_t* parent, uint32_t* size, uint32_t* partials, unsigned long long* ctr,
-                            hipStream_t stream) {
-    hipLaunchKernelGGL(k_threshold_count, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, tab, cap, tau,
-                       partials, ctr);
+hipError_t launch_threshold(Slot* tab, const JobView& jv, uint64_t* s_key, uint32_t* s_count, uint32_t* size,
+                            uint32_t* partials, unsigned long long* ctr, hipStream_t stream) {
+    hipLaunchKernelGGL(k_threshold_count, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, tab, jv, partials, ctr);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, stream, partials, ctr + C_SIGNIFICANT);
-    hipLaunchKernelGGL(k_threshold_scatter, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, tab, cap, tau,
-                       partials, s_key, s_count, parent, size);
+    hipLaunchKernelGGL(k_threshold_scatter, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, tab, jv, partials,
+                       s_key, s_count, size);
     return hipGetLastError();
 }
 
-hipError_t launch_agglomerate(const Slot* tab, uint64_t cap, const uint64_t* s_key, uint32_t* parent,
-                              uint32_t* nbr, uint32_t* size, uint32_t mu, uint64_t s_max, unsigned long long* ctr,
+hipError_t launch_agglomerate(const Slot* tab, const JobView& jv, const uint64_t* s_key, uint32_t* parent,
+                              uint32_t* nbr, uint32_t* size, uint64_t s_max, unsigned long long* ctr,
                               hipStream_t stream) {
     const int grid = grid_for(s_max, 256, kPersistBlocks);
-    hipLaunchKernelGGL(k_link, dim3(grid), dim3(256), 0, stream, tab, make_geo(cap), s_key, parent, nbr, ctr);
+    hipLaunchKernelGGL(k_link, dim3(grid), dim3(256), 0, stream, tab, jv, s_key, parent, nbr, ctr);
     hipLaunchKernelGGL(k_jump, dim3(grid), dim3(256), 0, stream, parent, ctr);
     hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, stream, nbr, s_key, parent, ctr);
     // the neighbour lists are dead after the merge pass; their first s words
     // take the final roots
-    hipLaunchKernelGGL(k_compress, dim3(grid), dim3(256), 0, stream, parent, nbr, size, mu, ctr);
+    hipLaunchKernelGGL(k_compress, dim3(grid), dim3(256), 0, stream, jv, parent, nbr, size, ctr);
     return hipGetLastError();
 }
 
-hipError_t launch_filter(const uint64_t* s_key, const uint32_t* s_count, const uint32_t* parent,
-                         const uint32_t* size, uint32_t mu, uint64_t s_max, int32_t* out_kx, int32_t* out_ky,
-                         uint32_t* out_count, uint64_t* out_label, uint32_t* partials, unsigned long long* ctr,
+hipError_t launch_filter(const JobView& jv, const uint64_t* s_key, const uint32_t* s_count, const uint32_t* root,
+                         const uint32_t* size, int32_t* out_kx, int32_t* out_ky, uint32_t* out_count,
+                         uint64_t* out_label, uint32_t* out_job, uint32_t* partials, unsigned long long* ctr,
                          hipStream_t stream) {
-    (void)s_max;
-    hipLaunchKernelGGL(k_filter_count, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, parent, size, mu,
-                       partials, ctr);
+    hipLaunchKernelGGL(k_filter_count, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, jv, root, size, partials,
+                       ctr);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, stream, partials, ctr + C_TILES);
-    hipLaunchKernelGGL(k_filter_scatter, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, s_key, s_count, parent,
-                       size, mu, partials, ctr, out_kx, out_ky, out_count, out_label);
+    hipLaunchKernelGGL(k_filter_scatter, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, jv, s_key, s_count, root,
+                       size, partials, ctr, out_kx, out_ky, out_count, out_label, out_job);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_count(const JobView& jv, const uint32_t* tile_prefix, Slot* tab, const KernelTuning& tu,
+                              int max_tiles_grid, hipStream_t stream) {
+    int lds_log2 = 0;
+    if (tu.preagg_slots > 0)
+        while ((1 << lds_log2) < tu.preagg_slots) ++lds_log2;
+    const size_t lds = lds_log2 ? (size_t)(1u << lds_log2) * (sizeof(uint64_t) + sizeof(uint32_t)) : 0;
+    const dim3 grid((unsigned)max_tiles_grid), block((unsigned)tu.block);
+    switch (tu.items) {
+        case 1: hipLaunchKernelGGL(k_batch_count<1>, grid, block, lds, stream, jv, tile_prefix, tab, lds_log2); break;
+        case 2: hipLaunchKernelGGL(k_batch_count<2>, grid, block, lds, stream, jv, tile_prefix, tab, lds_log2); break;
+        case 4: hipLaunchKernelGGL(k_batch_count<4>, grid, block, lds, stream, jv, tile_prefix, tab, lds_log2); break;
+        case 8: hipLaunchKernelGGL(k_batch_count<8>, grid, block, lds, stream, jv, tile_prefix, tab, lds_log2); break;
+        default: hipLaunchKernelGGL(k_batch_count<16>, grid, block, lds, stream, jv, tile_prefix, tab, lds_log2); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_dims(Slot* tab, const Dims* dims, hipStream_t stream) {
+    hipLaunchKernelGGL(k_fill_dims, dim3(8192), dim3(256), 0, stream, tab, dims);
+    return hipGetLastError();
+}
+
+hipError_t launch_bounds(const uint32_t* seg_job, const unsigned long long* n, uint32_t* start, uint32_t* end,
+                         uint64_t n_max, hipStream_t stream) {
+    hipLaunchKernelGGL(k_bounds, dim3(grid_for(n_max, 256, kPersistBlocks)), dim3(256), 0, stream, seg_job, n, start,
+                       end);
+    return hipGetLastError();
+}
+
+hipError_t launch_job_stats(const JobView& jv, const uint32_t* root, const uint32_t* size, const uint32_t* s_start,
+                            const uint32_t* s_end, const uint32_t* o_start, const uint32_t* o_end,
+                            uint32_t max_jobs, hipStream_t stream) {
+    hipLaunchKernelGGL(k_job_stats, dim3(max_jobs), dim3(SCAN_THREADS), 0, stream, jv, root, size, s_start, s_end,
+                       o_start, o_end);
     return hipGetLastError();
 }
 

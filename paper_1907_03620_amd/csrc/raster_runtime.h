@@ -7,6 +7,7 @@
 
 #include <cstdint>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -22,6 +23,7 @@ class DevicePool;
 struct raster_result {
     rst::DevicePool* pool = nullptr;  // owner of `block`
     void* block = nullptr;            // one device allocation holding the arrays
+    std::shared_ptr<void> shared;     // or: a block shared with other results of one batch
     uint64_t* label = nullptr;
     int32_t* kx = nullptr;
     int32_t* ky = nullptr;
@@ -69,8 +71,15 @@ struct Buffers {
     void release_all();
 };
 
+// Device image of a one-job view.
+struct SingleJob {
+    Dims dims;
+    JobInfo job;
+};
+
 // One device tile table and everything needed to fill it and cluster it.
 struct TableRun {
+    SingleJob single{};
     int device = 0;
     hipStream_t stream = nullptr;
     double scale = 1.0;

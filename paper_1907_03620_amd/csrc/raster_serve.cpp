@@ -3,135 +3,573 @@
 
 #include <chrono>
 #include <condition_variable>
+#include <cstring>
 #include <deque>
+#include <map>
+#include <mutex>
+#include <vector>
+#include <string>
 #include <thread>
+#include <unordered_map>
 
 #include "raster.h"
 #include "raster_runtime.h"
 
 using namespace rst;
 
-static raster_status job_scale(const raster_job& j, double* s) {
-    if (j.scale > 0.0) {
-        *s = j.scale;
+// ----------------------------------------------------------------- batch ---
+//
+// A batch is clustered by one pipeline over all its jobs: one fused counting
+// launch over every job's point tiles, then the job-aware significance scan,
+// agglomeration and mu filter over one arena holding every job's table.  All
+// sizes the kernels need are read from device memory, so the pipeline is
+// captured once into a HIP graph and replayed for every batch that fits the
+// engine's buffers; a batch that does not fit grows the buffers and
+// re-captures.  A job whose table turns out too small (a key found its probe
+// window full) is redone alone with the growable single-table path.
+
+namespace rst {
+
+struct BatchEngine {
+    int device = 0;
+    hipStream_t bs = nullptr;  // capture and replay stream
+    hipEvent_t ev_in = nullptr;
+    Buffers bufs;
+    uint64_t arena_cap = 0, parts_cap = 0, s_cap = 0;
+    uint32_t jobs_cap = 0;
+    Slot* arena = nullptr;
+    JobInfo* jobs_dev = nullptr;
+    Dims* dims_dev = nullptr;
+    uint32_t* tile_prefix = nullptr;
+    uint32_t* part_job = nullptr;
+    unsigned long long* ctr = nullptr;
+    unsigned long long* job_ctr = nullptr;
+    uint64_t* s_key = nullptr;
+    uint32_t *s_count = nullptr, *s_job = nullptr, *parent = nullptr, *nbr = nullptr, *size = nullptr;
+    int32_t *o_kx = nullptr, *o_ky = nullptr;
+    uint32_t *o_count = nullptr, *o_job = nullptr;
+    uint64_t* o_label = nullptr;
+    uint32_t* bounds = nullptr;  // s_start, s_end, o_start, o_end: jobs_cap each
+    uint32_t* partials = nullptr;
+    // pinned host mirrors
+    JobInfo* h_jobs = nullptr;
+    Dims* h_dims = nullptr;
+    uint32_t* h_tile_prefix = nullptr;
+    uint32_t* h_part_job = nullptr;
+    unsigned long long* h_job_ctr = nullptr;
+    unsigned long long* h_ctr = nullptr;
+    uint32_t* h_bounds = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    raster_tuning graph_tuning{};
+    bool graph_valid = false;
+    std::mutex mu;
+    float last_us = 0.f;  // device time of the last replay
+
+    ~BatchEngine() { release(); }
+    void release_host() {
+        if (h_jobs) (void)hipHostFree(h_jobs);
+        if (h_dims) (void)hipHostFree(h_dims);
+        if (h_tile_prefix) (void)hipHostFree(h_tile_prefix);
+        if (h_part_job) (void)hipHostFree(h_part_job);
+        if (h_job_ctr) (void)hipHostFree(h_job_ctr);
+        if (h_ctr) (void)hipHostFree(h_ctr);
+        if (h_bounds) (void)hipHostFree(h_bounds);
+        h_jobs = nullptr;
+        h_dims = nullptr;
+        h_tile_prefix = nullptr;
+        h_part_job = nullptr;
+        h_job_ctr = nullptr;
+        h_ctr = nullptr;
+        h_bounds = nullptr;
+    }
+    void drop_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        graph_valid = false;
+    }
+    void release() {
+        if (bs) (void)hipStreamSynchronize(bs);
+        drop_graph();
+        bufs.release_all();
+        release_host();
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (bs) (void)hipStreamDestroy(bs);
+        ev_in = nullptr;
+        bs = nullptr;
+        arena_cap = parts_cap = s_cap = 0;
+        jobs_cap = 0;
+    }
+
+    raster_status init() {
+        if (bs) return RASTER_OK;
+        hipError_t e = hipGetDevice(&device);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&bs, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_in, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "batch engine");
+        bufs.pool = &DevicePool::get(device);
         return RASTER_OK;
     }
-    if (!scale_for_precision(j.precision, s)) return fail(RASTER_E_INVAL, "precision %d outside [0, 15]", j.precision);
+
+    // Grows every buffer to hold the given totals (with headroom), dropping
+    // the captured graph when anything moves.
+    raster_status reserve(uint64_t slots, uint64_t s_need, uint32_t njobs) {
+        const bool ok = slots <= arena_cap && s_need <= s_cap && njobs <= jobs_cap;
+        if (ok) return RASTER_OK;
+        (void)hipStreamSynchronize(bs);
+        drop_graph();
+        bufs.release_all();
+        release_host();
+        arena_cap = std::max<uint64_t>(slots + slots / 4, arena_cap);
+        arena_cap = (arena_cap + kPartSlotsHost - 1) / kPartSlotsHost * kPartSlotsHost;
+        parts_cap = arena_cap / kPartSlotsHost;
+        s_cap = std::max<uint64_t>(s_need + s_need / 4 + 1024, s_cap);
+        jobs_cap = std::max<uint32_t>(njobs + njobs / 4 + 8, jobs_cap);
+        auto take = [&](void** p, size_t bytes, const char* what) -> raster_status {
+            hipError_t e = bufs.take(p, bytes);
+            return e == hipSuccess ? RASTER_OK : hip_fail(e, what);
+        };
+        raster_status st;
+#define TAKE(ptr, bytes, what) \
+    if ((st = take((void**)&(ptr), (bytes), (what))) != RASTER_OK) return st
+        TAKE(arena, arena_cap * sizeof(Slot), "batch arena");
+        TAKE(jobs_dev, jobs_cap * sizeof(JobInfo), "job table");
+        TAKE(dims_dev, sizeof(Dims), "dims");
+        TAKE(tile_prefix, (jobs_cap + 1) * sizeof(uint32_t), "tile prefix");
+        TAKE(part_job, parts_cap * sizeof(uint32_t), "partition map");
+        TAKE(ctr, kCounterWords * sizeof(unsigned long long), "counters");
+        TAKE(job_ctr, (size_t)jobs_cap * kCounterWords * sizeof(unsigned long long), "job counters");
+        TAKE(s_key, s_cap * sizeof(uint64_t), "S keys");
+        TAKE(s_count, s_cap * sizeof(uint32_t), "S counts");
+        TAKE(s_job, s_cap * sizeof(uint32_t), "S jobs");
+        TAKE(parent, s_cap * sizeof(uint32_t), "parents");
+        TAKE(nbr, s_cap * 4 * sizeof(uint32_t), "neighbour lists");
+        TAKE(size, s_cap * sizeof(uint32_t), "sizes");
+        TAKE(o_kx, s_cap * sizeof(int32_t), "rows");
+        TAKE(o_ky, s_cap * sizeof(int32_t), "rows");
+        TAKE(o_count, s_cap * sizeof(uint32_t), "rows");
+        TAKE(o_label, s_cap * sizeof(uint64_t), "rows");
+        TAKE(o_job, s_cap * sizeof(uint32_t), "rows");
+        TAKE(bounds, (size_t)4 * jobs_cap * sizeof(uint32_t), "job bounds");
+        TAKE(partials, kScanBlocks * sizeof(uint32_t), "scan partials");
+#undef TAKE
+        hipError_t e = hipHostMalloc((void**)&h_jobs, jobs_cap * sizeof(JobInfo), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&h_dims, sizeof(Dims), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&h_tile_prefix, (jobs_cap + 1) * sizeof(uint32_t), 0);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&h_part_job, parts_cap * sizeof(uint32_t), 0);
+        if (e == hipSuccess)
+            e = hipHostMalloc((void**)&h_job_ctr, (size_t)jobs_cap * kCounterWords * sizeof(unsigned long long), 0);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&h_ctr, kCounterWords * sizeof(unsigned long long), 0);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&h_bounds, (size_t)4 * jobs_cap * sizeof(uint32_t), 0);
+        if (e != hipSuccess) return hip_fail(e, "pinned batch mirrors");
+        return RASTER_OK;
+    }
+
+    JobView view() const {
+        return JobView{dims_dev, jobs_dev, part_job, s_job, job_ctr};
+    }
+
+    // The pipeline; enqueued on bs, directly or under capture.
+    hipError_t enqueue(const raster_tuning& tu) {
+        const JobView jv = view();
+        hipError_t e = launch_zero_u64((uint64_t*)ctr, kCounterWords, bs);
+        if (e == hipSuccess) e = launch_zero_u64((uint64_t*)job_ctr, (uint64_t)jobs_cap * kCounterWords, bs);
+        if (e == hipSuccess) e = launch_zero_u64((uint64_t*)bounds, (uint64_t)2 * jobs_cap, bs);
+        if (e == hipSuccess) e = launch_fill_dims(arena, dims_dev, bs);
+        if (e == hipSuccess) e = launch_batch_count(jv, tile_prefix, arena, kernel_tuning(tu), 4096, bs);
+        if (e == hipSuccess) e = launch_threshold(arena, jv, s_key, s_count, size, partials, ctr, bs);
+        if (e == hipSuccess) e = launch_agglomerate(arena, jv, s_key, parent, nbr, size, s_cap, ctr, bs);
+        if (e == hipSuccess)
+            e = launch_filter(jv, s_key, s_count, nbr, size, o_kx, o_ky, o_count, o_label, o_job, partials, ctr, bs);
+        uint32_t* s_start = bounds;
+        uint32_t* s_end = bounds + jobs_cap;
+        uint32_t* o_start = bounds + 2 * jobs_cap;
+        uint32_t* o_end = bounds + 3 * jobs_cap;
+        if (e == hipSuccess) e = launch_bounds(s_job, ctr + C_SIGNIFICANT, s_start, s_end, s_cap, bs);
+        if (e == hipSuccess) e = launch_bounds(o_job, ctr + C_TILES, o_start, o_end, s_cap, bs);
+        if (e == hipSuccess) e = launch_job_stats(jv, nbr, size, s_start, s_end, o_start, o_end, jobs_cap, bs);
+        return e;
+    }
+
+    raster_status run(const raster_job* jobs, int32_t n_jobs, hipStream_t user, raster_result** outs,
+                      std::vector<int32_t>* redo);
+
+    static constexpr uint64_t kPartSlotsHost = 4096;
+};
+
+raster_status BatchEngine::run(const raster_job* jobs, int32_t n_jobs, hipStream_t user, raster_result** outs,
+                               std::vector<int32_t>* redo) {
+    raster_status st = init();
+    if (st != RASTER_OK) return st;
+    const raster_tuning tu = current_tuning();
+    const uint64_t tile = (uint64_t)tu.block * (uint64_t)tu.items;
+    // sizes of every job's table and work tiles
+    std::vector<uint64_t> caps(n_jobs), bases(n_jobs);
+    std::vector<uint32_t> tiles(n_jobs);
+    uint64_t slots = 0, pts_total = 0, tiles_total = 0;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        const double est = std::max<double>((double)jobs[i].n / 8.0, 1.0) / tu.load_factor;
+        caps[i] = next_pow2(std::max<uint64_t>(kPartSlotsHost, (uint64_t)est));
+        bases[i] = slots;
+        slots += caps[i];
+        pts_total += (uint64_t)jobs[i].n;
+        tiles[i] = (uint32_t)(((uint64_t)jobs[i].n + tile - 1) / tile);
+        tiles_total += tiles[i];
+    }
+    if (tiles_total > 0xFFFFFFF0ull || slots > (1ull << 33))
+        return fail(RASTER_E_NOMEM, "batch too large for one launch");
+    const uint64_t s_need = std::max<uint64_t>(1, std::min<uint64_t>(slots, pts_total));
+    st = reserve(slots, s_need, (uint32_t)n_jobs);
+    if (st != RASTER_OK) return st;
+    // host mirrors
+    uint32_t tp = 0;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        double sc = jobs[i].scale;
+        if (!(sc > 0.0)) scale_for_precision(jobs[i].precision, &sc);
+        JobInfo& J = h_jobs[i];
+        J.pts = jobs[i].d_points;
+        J.n = jobs[i].n;
+        J.scale = sc;
+        J.slot_base = bases[i];
+        J.cap = caps[i];
+        J.tau = jobs[i].tau;
+        J.mu = jobs[i].mu;
+        J.dtype = (int32_t)jobs[i].dt;
+        J.first_tile = tp;
+        h_tile_prefix[i] = tp;
+        tp += tiles[i];
+        for (uint64_t p = bases[i] / kPartSlotsHost; p < (bases[i] + caps[i]) / kPartSlotsHost; ++p)
+            h_part_job[p] = (uint32_t)i;
+    }
+    h_tile_prefix[n_jobs] = tp;
+    h_dims->slots = slots;
+    h_dims->njobs = (uint32_t)n_jobs;
+    h_dims->tiles = tp;
+    hipError_t e = hipEventRecord(ev_in, user);
+    if (e == hipSuccess) e = hipStreamWaitEvent(bs, ev_in, 0);
+    if (e == hipSuccess) e = hipMemcpyAsync(jobs_dev, h_jobs, n_jobs * sizeof(JobInfo), hipMemcpyHostToDevice, bs);
+    if (e == hipSuccess) e = hipMemcpyAsync(dims_dev, h_dims, sizeof(Dims), hipMemcpyHostToDevice, bs);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(tile_prefix, h_tile_prefix, (n_jobs + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, bs);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(part_job, h_part_job, (slots / kPartSlotsHost) * sizeof(uint32_t), hipMemcpyHostToDevice,
+                           bs);
+    if (e != hipSuccess) return hip_fail(e, "batch upload");
+    const bool same_tuning = graph_tuning.block == tu.block && graph_tuning.items == tu.items &&
+                             graph_tuning.preagg_slots == tu.preagg_slots;
+    if (!graph_valid || !same_tuning) {
+        drop_graph();
+        e = hipStreamBeginCapture(bs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t le = enqueue(tu);
+            e = hipStreamEndCapture(bs, &graph);
+            if (le != hipSuccess) e = le;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graph();
+            (void)hipGetLastError();
+            return hip_fail(e, "batch graph capture");
+        }
+        graph_valid = true;
+        graph_tuning = tu;
+    }
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    (void)hipEventCreate(&t0);
+    (void)hipEventCreate(&t1);
+    (void)hipEventRecord(t0, bs);
+    e = hipGraphLaunch(exec, bs);
+    (void)hipEventRecord(t1, bs);
+    if (e == hipSuccess) e = hipMemcpyAsync(h_ctr, ctr, kCounterWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, bs);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h_job_ctr, job_ctr, (size_t)n_jobs * kCounterWords * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, bs);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h_bounds, bounds, (size_t)4 * jobs_cap * sizeof(uint32_t), hipMemcpyDeviceToHost, bs);
+    if (e == hipSuccess) e = hipStreamSynchronize(bs);
+    if (e == hipSuccess) (void)hipEventElapsedTime(&last_us, t0, t1);
+    last_us *= 1000.f;
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (e != hipSuccess) return hip_fail(e, "batch run");
+    if (h_ctr[C_ERROR] & kErrInternal) return fail(RASTER_E_DEVICE, "agglomeration state inconsistent");
+    for (int32_t i = 0; i < n_jobs; ++i)
+        if (h_job_ctr[(size_t)i * kCounterWords + C_ERROR] & kErrRange)
+            return fail(RASTER_E_RANGE, "job %d: a coordinate is not finite or its tile is out of range", i);
+    // copy the rows out of the reusable buffers into one block the results share
+    const uint64_t t = h_ctr[C_TILES];
+    const size_t row_bytes = 2 * sizeof(int32_t) + sizeof(uint32_t) + sizeof(uint64_t);
+    void* block = nullptr;
+    e = bufs.pool->alloc(&block, t * row_bytes + 256);
+    if (e != hipSuccess) return hip_fail(e, "batch result block");
+    DevicePool* pool = bufs.pool;
+    std::shared_ptr<void> owner(block, [pool](void* p) { pool->release(p); });
+    char* b = (char*)block;
+    uint64_t* lab = (uint64_t*)b;
+    int32_t* kx = (int32_t*)(b + t * sizeof(uint64_t));
+    int32_t* ky = kx + t;
+    uint32_t* cnt = (uint32_t*)(ky + t);
+    if (t) {
+        e = hipMemcpyAsync(lab, o_label, t * 8, hipMemcpyDeviceToDevice, bs);
+        if (e == hipSuccess) e = hipMemcpyAsync(kx, o_kx, t * 4, hipMemcpyDeviceToDevice, bs);
+        if (e == hipSuccess) e = hipMemcpyAsync(ky, o_ky, t * 4, hipMemcpyDeviceToDevice, bs);
+        if (e == hipSuccess) e = hipMemcpyAsync(cnt, o_count, t * 4, hipMemcpyDeviceToDevice, bs);
+        if (e == hipSuccess) e = hipStreamSynchronize(bs);
+        if (e != hipSuccess) return hip_fail(e, "batch result copy");
+    }
+    const uint32_t* o_start = h_bounds + 2 * jobs_cap;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        const unsigned long long* c = h_job_ctr + (size_t)i * kCounterWords;
+        if (c[C_SPILLED] > 0) {
+            redo->push_back(i);
+            continue;
+        }
+        if (c[C_SUM] != (unsigned long long)jobs[i].n)
+            return fail(RASTER_E_DEVICE, "job %d: counts sum to %llu, not %lld", i, c[C_SUM], (long long)jobs[i].n);
+        raster_result* r = new raster_result();
+        r->shared = owner;
+        const uint64_t off = c[C_TILES] ? o_start[i] : 0;
+        r->label = lab + off;
+        r->kx = kx + off;
+        r->ky = ky + off;
+        r->count = cnt + off;
+        raster_stats& S = r->stats;
+        std::memset(&S, 0, sizeof S);
+        S.n_points = jobs[i].n;
+        S.distinct_tiles = (int64_t)c[C_DISTINCT];
+        S.significant_tiles = (int64_t)c[C_SIGNIFICANT];
+        S.components = (int64_t)c[C_COMPONENTS];
+        S.clusters = (int64_t)c[C_CLUSTERS];
+        S.tiles = (int64_t)c[C_TILES];
+        S.table_capacity = (int64_t)caps[i];
+        S.us_contract = last_us;  // the whole batch's device time
+        r->tiles = S.tiles;
+        r->clusters = S.clusters;
+        outs[i] = r;
+    }
     return RASTER_OK;
 }
+
+static std::mutex g_engines_mu;
+static std::map<int, BatchEngine*> g_engines;
+
+BatchEngine& default_engine() {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> g(g_engines_mu);
+    auto it = g_engines.find(dev);
+    if (it != g_engines.end()) return *it->second;
+    BatchEngine* e = new BatchEngine();  // lives until process exit
+    g_engines[dev] = e;
+    return *e;
+}
+
+raster_status validate_job(const raster_job& j, int32_t i) {
+    raster_status st = check_points(j.d_points, j.n, j.dt);
+    double sc = j.scale;
+    if (st == RASTER_OK && !(sc > 0.0) && !scale_for_precision(j.precision, &sc))
+        st = fail(RASTER_E_INVAL, "job %d: precision %d outside [0, 15]", i, j.precision);
+    if (st == RASTER_OK) st = check_params(sc, j.tau, j.mu);
+    if (st == RASTER_OK && (uint64_t)j.n > 0xFFFFFFFFull) st = fail(RASTER_E_RANGE, "job %d: too many points", i);
+    return st;
+}
+
+raster_status run_batch(BatchEngine& eng, const raster_job* jobs, int32_t n_jobs, hipStream_t stream,
+                        raster_result** outs) {
+    for (int32_t i = 0; i < n_jobs; ++i) outs[i] = nullptr;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        raster_status st = validate_job(jobs[i], i);
+        if (st != RASTER_OK) return st;
+    }
+    if (n_jobs == 0) return RASTER_OK;
+    std::vector<int32_t> redo;
+    raster_status st;
+    {
+        std::lock_guard<std::mutex> g(eng.mu);
+        st = eng.run(jobs, n_jobs, stream, outs, &redo);
+    }
+    for (size_t k = 0; st == RASTER_OK && k < redo.size(); ++k) {
+        const raster_job& j = jobs[redo[k]];
+        double sc = j.scale;
+        if (!(sc > 0.0)) scale_for_precision(j.precision, &sc);
+        st = raster_cluster_scaled(j.d_points, j.n, j.dt, sc, j.tau, j.mu, stream, &outs[redo[k]]);
+    }
+    if (st != RASTER_OK) {
+        for (int32_t k = 0; k < n_jobs; ++k) {
+            raster_result_free(outs[k]);
+            outs[k] = nullptr;
+        }
+    }
+    return st;
+}
+
+}  // namespace rst
 
 extern "C" raster_status raster_cluster_batch(const raster_job* jobs, int32_t n_jobs, hipStream_t stream,
                                               raster_result** outs) {
     if (n_jobs < 0 || (n_jobs > 0 && (!jobs || !outs))) return fail(RASTER_E_INVAL, "bad batch arguments");
-    for (int32_t i = 0; i < n_jobs; ++i) outs[i] = nullptr;
-    for (int32_t i = 0; i < n_jobs; ++i) {
-        double s;
-        raster_status st = job_scale(jobs[i], &s);
-        if (st == RASTER_OK) st = raster_cluster_scaled(jobs[i].d_points, jobs[i].n, jobs[i].dt, s, jobs[i].tau,
-                                                         jobs[i].mu, stream, &outs[i]);
-        if (st != RASTER_OK) {
-            for (int32_t k = 0; k < n_jobs; ++k) {
-                raster_result_free(outs[k]);
-                outs[k] = nullptr;
-            }
-            return st;
-        }
-    }
-    return RASTER_OK;
+    return run_batch(default_engine(), jobs, n_jobs, stream, outs);
 }
 
 // ---------------------------------------------------------------- server ---
+//
+// Continuous batching: max_slots worker threads, each owning a batch engine
+// (its own HIP stream and resident device buffers).  A free worker takes the
+// queued jobs, in arrival order, that fit the memory budget left by the
+// batches already running, runs them as one batch, and hands out the results.
+// Jobs arriving while batches are on the GPU are picked up by the next free
+// worker, so their work overlaps the running batches.
 
 struct ServerJob {
-    uint64_t ticket;
-    raster_job job;
+    uint64_t ticket = 0;
+    raster_job job{};
+    size_t bytes = 0;
     std::chrono::steady_clock::time_point submitted;
     bool done = false;
     raster_status status = RASTER_OK;
     raster_result* result = nullptr;
     double latency = 0.0;
+    std::string error;
 };
 
 struct raster_server {
     size_t budget = 0;
     int slots = 1;
+    int device = 0;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<ServerJob*> queue;
     std::unordered_map<uint64_t, ServerJob*> jobs;
     uint64_t next_ticket = 1;
+    size_t in_flight = 0;  // bytes held by running batches
     bool stop = false;
-    std::thread worker;
-    hipStream_t stream = nullptr;
-    int device = 0;
+    std::vector<std::thread> workers;
+    std::vector<BatchEngine*> engines;
 };
 
+// Device working set of one job in a batch: its table (16 B per slot), the
+// compact arrays and rows (sized by its points or table, whichever is
+// smaller, about 60 B each), and its share of the job tables.
 static size_t job_bytes(const raster_job& j) {
-    // table (16 B/slot at load 0.5 for up to n/8 tiles) + spill + outputs
-    const uint64_t n = (uint64_t)std::max<int64_t>(j.n, 1);
-    return (size_t)(n / 8 * 32 + n * 12 + n / 8 * 40 + (1 << 20));
+    const raster_tuning tu = current_tuning();
+    const double est = std::max<double>((double)j.n / 8.0, 1.0) / tu.load_factor;
+    const uint64_t cap = next_pow2(std::max<uint64_t>(4096, (uint64_t)est));
+    const uint64_t s = std::min<uint64_t>(cap, (uint64_t)std::max<int64_t>(j.n, 1));
+    return (size_t)(cap * 16 * 5 / 4 + s * 60 * 5 / 4 + 4096);
 }
 
-static void server_loop(raster_server* s) {
+static constexpr size_t kMaxBatchJobs = 128;
+static constexpr uint64_t kMaxBatchPoints = 256ull * 1000 * 1000;
+
+static void server_worker(raster_server* s, int slot) {
     (void)hipSetDevice(s->device);
+    BatchEngine& eng = *s->engines[slot];
     while (true) {
-        ServerJob* j = nullptr;
+        std::vector<ServerJob*> batch;
+        size_t bytes = 0;
         {
             std::unique_lock<std::mutex> g(s->mu);
-            s->cv_work.wait(g, [&] { return s->stop || !s->queue.empty(); });
-            if (s->queue.empty()) return;
-            j = s->queue.front();
-            s->queue.pop_front();
+            s->cv_work.wait(g, [&] {
+                return (!s->queue.empty() && s->queue.front()->bytes <= s->budget - s->in_flight) ||
+                       (s->stop && s->queue.empty());
+            });
+            if (s->queue.empty()) return;  // stopping and drained
+            uint64_t pts = 0;
+            while (!s->queue.empty() && batch.size() < kMaxBatchJobs) {
+                ServerJob* j = s->queue.front();
+                if (j->bytes > s->budget - s->in_flight - bytes) break;
+                if (!batch.empty() && pts + (uint64_t)j->job.n > kMaxBatchPoints) break;
+                batch.push_back(j);
+                bytes += j->bytes;
+                pts += (uint64_t)j->job.n;
+                s->queue.pop_front();
+            }
+            s->in_flight += bytes;
         }
-        double sc = 0;
-        raster_status st = job_scale(j->job, &sc);
-        raster_result* r = nullptr;
-        if (st == RASTER_OK)
-            st = raster_cluster_scaled(j->job.d_points, j->job.n, j->job.dt, sc, j->job.tau, j->job.mu, s->stream, &r);
+        s->cv_work.notify_all();  // another worker may take what is left
+        std::vector<raster_job> jv(batch.size());
+        std::vector<raster_result*> outs(batch.size(), nullptr);
+        for (size_t i = 0; i < batch.size(); ++i) jv[i] = batch[i]->job;
+        raster_status st = RASTER_OK;
+        (void)eng.init();
+        st = run_batch(eng, jv.data(), (int32_t)jv.size(), eng.bs, outs.data());
+        std::string err = st == RASTER_OK ? std::string() : g_last_error;
+        if (st != RASTER_OK && batch.size() > 1) {
+            // isolate the failing job(s): redo each job alone
+            st = RASTER_OK;
+            for (size_t i = 0; i < batch.size(); ++i) {
+                raster_status si = run_batch(eng, &jv[i], 1, eng.bs, &outs[i]);
+                if (si != RASTER_OK) batch[i]->error = g_last_error;
+                batch[i]->status = si;
+            }
+        } else {
+            for (size_t i = 0; i < batch.size(); ++i) {
+                batch[i]->status = st;
+                batch[i]->error = err;
+            }
+        }
         const auto t1 = std::chrono::steady_clock::now();
         {
             std::lock_guard<std::mutex> g(s->mu);
-            j->status = st;
-            j->result = r;
-            j->latency = std::chrono::duration<double>(t1 - j->submitted).count();
-            j->done = true;
+            for (size_t i = 0; i < batch.size(); ++i) {
+                batch[i]->result = outs[i];
+                batch[i]->latency = std::chrono::duration<double>(t1 - batch[i]->submitted).count();
+                batch[i]->done = true;
+            }
+            s->in_flight -= bytes;
         }
         s->cv_done.notify_all();
+        s->cv_work.notify_all();
     }
 }
 
 extern "C" raster_status raster_server_create(size_t budget_bytes, int32_t max_slots, raster_server** srv) {
     if (!srv) return fail(RASTER_E_INVAL, "srv is NULL");
     *srv = nullptr;
-    if (budget_bytes == 0 || max_slots < 1) return fail(RASTER_E_INVAL, "budget and slots must be positive");
+    if (budget_bytes == 0 || max_slots < 1 || max_slots > 16)
+        return fail(RASTER_E_INVAL, "budget must be positive and slots in [1, 16]");
     raster_server* s = new raster_server();
     s->budget = budget_bytes;
     s->slots = max_slots;
     hipError_t e = hipGetDevice(&s->device);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete s;
-        return hip_fail(e, "server stream");
+        return hip_fail(e, "hipGetDevice");
     }
-    s->worker = std::thread(server_loop, s);
+    for (int i = 0; i < max_slots; ++i) {
+        s->engines.push_back(new BatchEngine());
+        raster_status st = s->engines.back()->init();
+        if (st != RASTER_OK) {
+            for (BatchEngine* b : s->engines) delete b;
+            delete s;
+            return st;
+        }
+    }
+    for (int i = 0; i < max_slots; ++i) s->workers.emplace_back(server_worker, s, i);
     *srv = s;
     return RASTER_OK;
 }
 
 extern "C" raster_status raster_server_submit(raster_server* s, const raster_job* job, uint64_t* ticket) {
     if (!s || !job || !ticket) return fail(RASTER_E_INVAL, "NULL argument");
-    raster_status st = check_points(job->d_points, job->n, job->dt);
+    raster_status st = validate_job(*job, 0);
     if (st != RASTER_OK) return st;
-    double sc;
-    st = job_scale(*job, &sc);
-    if (st == RASTER_OK) st = check_params(sc, job->tau, job->mu);
-    if (st != RASTER_OK) return st;
-    if (job_bytes(*job) > s->budget) return fail(RASTER_E_BUDGET, "job needs more device memory than the budget");
+    const size_t bytes = job_bytes(*job);
+    if (bytes > s->budget)
+        return fail(RASTER_E_BUDGET, "job needs about %zu bytes of device memory, more than the budget %zu", bytes,
+                    s->budget);
     ServerJob* j = new ServerJob();
     j->job = *job;
+    j->bytes = bytes;
     j->submitted = std::chrono::steady_clock::now();
     {
         std::lock_guard<std::mutex> g(s->mu);
+        if (s->stop) {
+            delete j;
+            return fail(RASTER_E_STATE, "server is stopping");
+        }
         j->ticket = s->next_ticket++;
         s->jobs[j->ticket] = j;
         s->queue.push_back(j);
@@ -152,13 +590,14 @@ extern "C" raster_status raster_server_wait(raster_server* s, uint64_t ticket, r
         if (it == s->jobs.end()) return fail(RASTER_E_INVAL, "unknown ticket %llu", (unsigned long long)ticket);
         j = it->second;
         s->cv_done.wait(g, [&] { return j->done; });
-        s->jobs.erase(it);
+        s->jobs.erase(ticket);
     }
     raster_status st = j->status;
     *out = j->result;
     if (latency_s) *latency_s = j->latency;
+    std::string err = j->error;
     delete j;
-    if (st != RASTER_OK) return fail(st, "job failed: %s", raster_status_string(st));
+    if (st != RASTER_OK) return fail(st, "job failed: %s", err.c_str());
     return RASTER_OK;
 }
 
@@ -169,11 +608,12 @@ extern "C" void raster_server_destroy(raster_server* s) {
         s->stop = true;
     }
     s->cv_work.notify_all();
-    if (s->worker.joinable()) s->worker.join();
+    for (std::thread& t : s->workers)
+        if (t.joinable()) t.join();
     for (auto& kv : s->jobs) {
         raster_result_free(kv.second->result);
         delete kv.second;
     }
-    (void)hipStreamDestroy(s->stream);
+    for (BatchEngine* b : s->engines) delete b;
     delete s;
 }
