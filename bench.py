@@ -89,6 +89,161 @@ def cpu_baseline(host_chunks, strip: float, precision: int, tau: int, mu: int):
                 seconds=dt, points=int(sample.shape[0]))
 
 
+def pct(values, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(values), q)) if len(values) else None
+
+
+def bench_batched(raster, torch, n_jobs: int, reps: int):
+    """256 jobs (sizes log-uniform in [1e4, 5e6], parameters drawn per job),
+    each generated from its own seed; plain per-job calls against one batch."""
+    import synth
+    from paper_1907_03620_amd import autotune
+    specs = synth.batch_jobs(seed=4, n_jobs=n_jobs)
+    log(f"batched: generating {len(specs)} jobs, {sum(s.n for s in specs)} points")
+    with ThreadPoolExecutor(16) as ex:
+        host = list(ex.map(synth.job_points, specs))
+    dev = [torch.from_numpy(h).to("cuda") for h in host]
+    del host
+    args = [dict(points=d, precision=sp.precision, tau=sp.tau, mu=sp.mu) for sp, d in zip(specs, dev)]
+    total = sum(sp.n for sp in specs)
+    saved = raster.get_tuning()
+    best = autotune.tune("batch", lambda: raster.cluster_batch(args), points=total, reps=2, log=log)
+    raster.set_tuning(best)
+
+    def plain():
+        return [raster.cluster(**a) for a in args]
+
+    def batched():
+        return raster.cluster_batch(args)
+
+    out = {}
+    for name, fn in (("plain_per_job", plain), ("batched", batched)):
+        fn()
+        best_t = float("inf")
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = fn()
+            torch.cuda.synchronize()
+            best_t = min(best_t, time.perf_counter() - t0)
+            del res
+        out[name] = {"seconds": best_t, "points_per_s": total / best_t}
+    raster.set_tuning(saved)
+    del dev, args
+    torch.cuda.empty_cache()
+    return {"workload": f"{len(specs)} jobs, n log-uniform in [1e4, 5e6], {total} FP64 points, "
+                        "p/tau/mu drawn per job, each job generated from its own seed",
+            "jobs": len(specs), "points": total, "tuning": best.__dict__,
+            "plain_per_job": out["plain_per_job"], "batched": out["batched"],
+            "speedup": out["plain_per_job"]["seconds"] / out["batched"]["seconds"]}
+
+
+def bench_served(raster, torch, duration_s: float, rate: float, slots: int):
+    """Poisson arrivals replayed in real time: the continuous-batching server
+    against a plain FIFO worker issuing one call per job."""
+    import threading
+    import numpy as np
+    import synth
+    trace = synth.served_trace(seed=5, rate=rate, duration_s=duration_s)
+    pool_n = 20_000_000
+    log(f"served: {len(trace)} jobs over {duration_s:g} s; pool of {pool_n} points")
+    pool_h = synth.job_points(synth.JobSpec(seed=5, n=pool_n, precision=1, tau=5, mu=4))
+    pool64 = torch.from_numpy(pool_h).to("cuda")
+    pool32 = pool64.to(torch.float32)
+    del pool_h
+
+    def points(j, sp):
+        off = (j * 7919) % max(1, pool_n - sp.n + 1)
+        src = pool32 if sp.dtype == "f32" else pool64
+        return src[off:off + sp.n]
+
+    views = [points(j, sp) for j, sp in enumerate(trace)]
+    total = sum(sp.n for sp in trace)
+    torch.cuda.synchronize()
+
+    def run_server():
+        srv = raster.Server(budget_bytes=64 << 30, max_slots=slots)
+        lat, tickets = [], []
+        done_at = [0.0]
+        lock = threading.Lock()
+
+        def waiter():
+            i = 0
+            while True:
+                with lock:
+                    if i >= len(trace):
+                        return
+                    ready = i < len(tickets)
+                    t = tickets[i] if ready else None
+                if not ready:
+                    time.sleep(0.0005)
+                    continue
+                r, l = srv.wait(t)
+                lat.append(l)
+                r.free()
+                done_at[0] = time.perf_counter()
+                i += 1
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        t0 = time.perf_counter()
+        for j, sp in enumerate(trace):
+            d = t0 + sp.arrival_s - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            tk = srv.submit(views[j], tau=sp.tau, mu=sp.mu, precision=sp.precision)
+            with lock:
+                tickets.append(tk)
+        th.join()
+        srv.close()
+        return lat, done_at[0] - t0
+
+    def run_fifo():
+        import queue
+        q = queue.Queue()
+        lat = []
+        done_at = [0.0]
+
+        def worker():
+            while True:
+                item = q.get()
+                if item is None:
+                    return
+                j, arrived = item
+                sp = trace[j]
+                r = raster.cluster(views[j], precision=sp.precision, tau=sp.tau, mu=sp.mu)
+                r.free()
+                now = time.perf_counter()
+                lat.append(now - arrived)
+                done_at[0] = now
+
+        th = threading.Thread(target=worker)
+        th.start()
+        t0 = time.perf_counter()
+        for j, sp in enumerate(trace):
+            d = t0 + sp.arrival_s - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            q.put((j, time.perf_counter()))
+        q.put(None)
+        th.join()
+        return lat, done_at[0] - t0
+
+    out = {}
+    for name, fn in (("server", run_server), ("plain_fifo", run_fifo)):
+        lat, span = fn()
+        out[name] = {"p50_ms": 1e3 * pct(lat, 50), "p99_ms": 1e3 * pct(lat, 99), "mean_ms": 1e3 * float(np.mean(lat)),
+                     "points_per_s": total / span, "makespan_s": span}
+    del views, pool64, pool32
+    torch.cuda.empty_cache()
+    return {"workload": f"Poisson {rate:g} jobs/s for {duration_s:g} s ({len(trace)} jobs), n log-uniform in "
+                        "[1e3, 2e7] (windows of one 20M-point set shaped like workload 1), FP32/FP64 per job, "
+                        "p/tau/mu drawn per job, budget 64 GiB",
+            "jobs": len(trace), "points": total, "offered_points_per_s": total / duration_s, "slots": slots,
+            "server": out["server"], "plain_fifo": out["plain_fifo"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +256,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-strip", type=float, default=2000.0)
     ap.add_argument("--tuning", default="", help="JSON object of raster_tuning fields")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched (256-job) comparison")
+    ap.add_argument("--no-served", action="store_true", help="skip the served (Poisson trace) comparison")
+    ap.add_argument("--served-seconds", type=float, default=10.0)
+    ap.add_argument("--served-rate", type=float, default=200.0)
+    ap.add_argument("--served-slots", type=int, default=4)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (3 times), to scale HBM counters")
     args = ap.parse_args()
@@ -213,6 +373,9 @@ def main():
     }
     del dev
     torch.cuda.empty_cache()
+    line["batched"] = None if args.no_batched else bench_batched(raster, torch, 256, 3)
+    line["served"] = None if args.no_served else bench_served(raster, torch, args.served_seconds, args.served_rate,
+                                                              args.served_slots)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one core)")
         line["cpu_baseline"] = cpu_baseline(host, args.cpu_strip, precision, tau, mu)

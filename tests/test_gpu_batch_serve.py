@@ -160,3 +160,21 @@ def test_server_tight_budget_queues(raster, torch, batch24):
             same_result(r, raster.cluster(d, precision=sp.precision, tau=sp.tau, mu=sp.mu), f"queued job {k}")
     finally:
         srv.close()
+
+
+def test_autotuner_choice_gives_same_results(raster, torch, batch24, tmp_path, monkeypatch):
+    monkeypatch.setenv("RASTER_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    from paper_1907_03620_amd import autotune
+    args = _batch_args(batch24)
+    points = sum(sp.n for sp, _, _ in batch24)
+    base = raster.cluster_batch(args)
+    best = autotune.tune("batch", lambda: raster.cluster_batch(args), points=points, reps=1, use_cache=False,
+                         sweeps={"block": [128, 512], "preagg_slots": [0, 1024], "load_factor": [0.4, 0.8]})
+    assert autotune.cached("batch", points) == best
+    raster.set_tuning(best)
+    try:
+        res = raster.cluster_batch(args)
+    finally:
+        raster.set_tuning(None)
+    for k in range(len(batch24)):
+        same_result(base[k], res[k], f"autotuned job {k}")
