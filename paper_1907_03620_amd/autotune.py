@@ -22,6 +22,7 @@ from dataclasses import asdict
 from . import Tuning, get_tuning, set_tuning
 
 SWEEPS = {
+    "mode": [0, 1],
     "block": [128, 256, 512],
     "items": [2, 4, 8],
     "preagg_slots": [0, 1024, 4096],

@@ -89,14 +89,22 @@ struct JobInfo {
     uint32_t tau, mu;
     int32_t dtype;        // 1 = FP32, 2 = FP64
     uint32_t first_tile;  // batched counting: first point tile of the job
+    uint32_t part_base;   // slot_base / 4096: first partition of the job
+    uint32_t cbase;       // binned batches: first coarse bucket of the job
+    uint32_t cshift;      // binned batches: log2 partitions per coarse bucket
+    uint32_t pad;
 };
 
 // Sizes read from device memory, so that a captured graph can be replayed
 // for any batch that fits its buffers.
 struct Dims {
-    uint64_t slots;   // table slots in use (all jobs)
+    uint64_t slots;    // table slots in use (all jobs)
     uint32_t njobs;
-    uint32_t tiles;   // point tiles of the batched counting launch
+    uint32_t tiles;    // point tiles of the batched counting launch
+    uint64_t cap1;     // binned batches: keys per coarse bucket
+    uint64_t cap2;     // binned batches: keys per partition bucket
+    uint32_t ncoarse;  // binned batches: coarse buckets in use
+    uint32_t segs;     // binned batches: kBinTile segments per coarse bucket
 };
 
 // Job-aware views passed to the post-contraction kernels.  part_job maps a
@@ -205,6 +213,13 @@ hipError_t launch_filter(const JobView& jv, const uint64_t* s_key, const uint32_
 // C_SPILLED count; such a job is redone alone.
 hipError_t launch_batch_count(const JobView& jv, const uint32_t* tile_prefix, Slot* tab, const KernelTuning& tu,
                               int max_tiles_grid, hipStream_t stream);
+
+// Binned batched counting: level 1 over job-homogeneous tiles of kBinTile
+// points into each job's coarse buckets (cjob maps a coarse bucket to its
+// job), level 2 into partition buckets, then the LDS update of every
+// partition.  cursor1 (ncoarse) and cursor2 (partitions) must be zero.
+hipError_t launch_batch_binned(const JobView& jv, const uint32_t* tile_prefix, const uint32_t* cjob, uint64_t* bin1,
+                               uint32_t* cursor1, uint64_t* bin2, uint32_t* cursor2, Slot* tab, hipStream_t stream);
 
 // Fills table slots [0, dims->slots) with empty slots.
 hipError_t launch_fill_dims(Slot* tab, const Dims* dims, hipStream_t stream);

@@ -106,6 +106,23 @@ __device__ __forceinline__ void load_point(const T* pts, int64_t i, double& x, d
     y = (double)v.y;
 }
 
+__device__ __forceinline__ uint32_t job_of_tile(const uint32_t* tile_prefix, uint32_t njobs, uint32_t t) {
+    uint32_t lo = 0, hi = njobs;  // find the last j with tile_prefix[j] <= t
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (tile_prefix[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool job_point_key(const JobInfo& J, int64_t i, uint64_t& key) {
+    double x, y;
+    if (J.dtype == 1) load_point(static_cast<const float*>(J.pts), i, x, y);
+    else load_point(static_cast<const double*>(J.pts), i, x, y);
+    return tile_key(x, y, J.scale, key);
+}
+
 enum AddResult : int { ADD_FOUND = 0, ADD_NEW = 1, ADD_FULL = 2 };
 
 // Adds `inc` to the count of `key`, inserting the key into an empty slot of
@@ -382,7 +399,7 @@ struct BinScratch {
 
 // Bucket of a key: bits [shift, shift + log2 nb) of its hash, counted from the top.
 __device__ __forceinline__ uint32_t bucket_of(uint64_t key, uint32_t top_bits, uint32_t nb) {
-    return (uint32_t)(mix64(key) >> (64 - top_bits)) & (nb - 1);
+    return top_bits ? (uint32_t)(mix64(key) >> (64 - top_bits)) & (nb - 1) : 0u;
 }
 
 // Scatters this tile's valid keys into nb buckets: bucket b's keys are
@@ -559,15 +576,10 @@ __device__ __forceinline__ int lds_add(uint64_t* lkey, uint32_t* lcnt, uint64_t 
 // flight before the LDS work that depends on them.
 constexpr int AGG_BATCH = 8;
 
-__global__ __launch_bounds__(AGG_THREADS) void k_aggregate(const uint64_t* __restrict__ bin2, uint64_t cap2,
-                                                           const uint32_t* cursor2, Slot* tab, SpillBuf sp,
-                                                           unsigned long long* ctr) {
-    __shared__ uint64_t lkey[kPartSlots];
-    __shared__ uint32_t lcnt[kPartSlots];
-    const uint64_t p = blockIdx.x;
-    const uint64_t cnt = min((uint64_t)cursor2[p], cap2);
-    if (cnt == 0) return;  // uniform across the workgroup
-    Slot* part = tab + (p << kPartLog2);
+// Adds the cnt keys at src to one 4096-slot partition through LDS.
+__device__ __forceinline__ void aggregate_partition(const uint64_t* __restrict__ src, uint64_t cnt, Slot* part,
+                                                    uint64_t* lkey, uint32_t* lcnt, const SpillBuf& sp,
+                                                    unsigned long long* spill_ctr, uint32_t& fresh) {
     constexpr int PER = (int)kPartSlots / AGG_THREADS;
     {
         Slot v[PER];
@@ -580,8 +592,6 @@ __global__ __launch_bounds__(AGG_THREADS) void k_aggregate(const uint64_t* __res
         }
     }
     __syncthreads();
-    uint32_t fresh = 0;
-    const uint64_t* src = bin2 + p * cap2;
     for (uint64_t q0 = 0; q0 < cnt; q0 += (uint64_t)AGG_THREADS * AGG_BATCH) {
         uint64_t k[AGG_BATCH];
 #pragma unroll
@@ -596,7 +606,7 @@ __global__ __launch_bounds__(AGG_THREADS) void k_aggregate(const uint64_t* __res
                 r = lds_add(lkey, lcnt, k[u]);
                 fresh += (r == ADD_NEW);
             }
-            spill_push(sp, ctr, r == ADD_FULL, k[u], 1u);
+            spill_push(sp, spill_ctr, r == ADD_FULL, k[u], 1u);
         }
     }
     __syncthreads();
@@ -612,7 +622,128 @@ __global__ __launch_bounds__(AGG_THREADS) void k_aggregate(const uint64_t* __res
             part[s] = v;
         }
     }
+}
+
+__global__ __launch_bounds__(AGG_THREADS) void k_aggregate(const uint64_t* __restrict__ bin2, uint64_t cap2,
+                                                           const uint32_t* cursor2, Slot* tab, SpillBuf sp,
+                                                           unsigned long long* ctr) {
+    __shared__ uint64_t lkey[kPartSlots];
+    __shared__ uint32_t lcnt[kPartSlots];
+    const uint64_t p = blockIdx.x;
+    const uint64_t cnt = min((uint64_t)cursor2[p], cap2);
+    if (cnt == 0) return;  // uniform across the workgroup
+    uint32_t fresh = 0;
+    aggregate_partition(bin2 + p * cap2, cnt, tab + (p << kPartLog2), lkey, lcnt, sp, ctr, fresh);
     add_fresh(ctr, fresh);
+}
+
+// ---- binned counting for batches ----------------------------------------------
+//
+// The same two binning levels and LDS update, over every job of a batch at
+// once.  Each job owns 2^(p_log2 - cshift) coarse buckets (a coarse bucket
+// names its job) and its partitions in the arena; a work tile of level 1 holds
+// kBinTile points of one job.  Persistent grids read every size from Dims.
+
+__global__ __launch_bounds__(BIN_THREADS) void k_bbin_points(JobView jv, const uint32_t* tile_prefix, uint64_t* bin1,
+                                                             uint32_t* cursor1, Slot* tab) {
+    __shared__ BinScratch S;
+    const uint32_t tiles = jv.dims->tiles, njobs = jv.dims->njobs;
+    const uint64_t cap1 = jv.dims->cap1;
+    const SpillBuf none{nullptr, nullptr, 0};
+    for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const uint32_t job = job_of_tile(tile_prefix, njobs, t);
+        const JobInfo& J = jv.jobs[job];
+        const Geo g = make_geo(J.cap);
+        const uint32_t top = g.p_log2 - J.cshift;  // coarse bits of the hash
+        const uint32_t nb = 1u << top;
+        for (uint32_t b = threadIdx.x; b < nb; b += BIN_THREADS) S.hist[b] = 0;
+        __syncthreads();
+        const int64_t base = (int64_t)(t - J.first_tile) * kBinTile + threadIdx.x;
+        uint64_t key[BIN_ITEMS];
+        uint16_t bucket[BIN_ITEMS];
+        uint32_t valid = 0;
+        bool bad = false;
+#pragma unroll
+        for (int j = 0; j < BIN_ITEMS; ++j) {
+            const int64_t i = base + (int64_t)j * BIN_THREADS;
+            key[j] = 0;
+            bucket[j] = 0;
+            if (i < J.n) {
+                if (job_point_key(J, i, key[j])) {
+                    valid |= 1u << j;
+                    bucket[j] = (uint16_t)bucket_of(key[j], top, nb);
+                } else {
+                    bad = true;
+                }
+            }
+        }
+        unsigned long long* jc = jv.job_ctr + (uint64_t)job * kCounterWords;
+        if (bad) atomicOr(&jc[C_ERROR], (unsigned long long)kErrRange);
+        uint32_t fresh = 0;
+        bin_tile(S, key, bucket, valid, nb, top, bin1 + (uint64_t)J.cbase * cap1, cap1, cursor1 + J.cbase,
+                 tab + J.slot_base, g, none, jc, fresh);
+        __syncthreads();  // S is reused by the next tile
+    }
+}
+
+__global__ __launch_bounds__(BIN_THREADS) void k_bbin_keys(JobView jv, const uint32_t* cjob, const uint64_t* bin1,
+                                                           const uint32_t* cursor1, uint64_t* bin2,
+                                                           uint32_t* cursor2, Slot* tab) {
+    __shared__ BinScratch S;
+    const uint64_t cap1 = jv.dims->cap1, cap2 = jv.dims->cap2;
+    const uint32_t segs = jv.dims->segs;
+    const uint64_t work = (uint64_t)jv.dims->ncoarse * segs;
+    const SpillBuf none{nullptr, nullptr, 0};
+    for (uint64_t w = blockIdx.x; w < work; w += gridDim.x) {
+        const uint32_t c = (uint32_t)(w / segs);
+        const uint32_t seg = (uint32_t)(w % segs);
+        const uint64_t cnt = min((uint64_t)cursor1[c], cap1);
+        const uint64_t start = (uint64_t)seg * kBinTile;
+        if (start >= cnt) continue;  // uniform across the workgroup
+        const uint32_t job = cjob[c];
+        const JobInfo& J = jv.jobs[job];
+        const Geo g = make_geo(J.cap);
+        const uint32_t nb = 1u << J.cshift;
+        for (uint32_t b = threadIdx.x; b < nb; b += BIN_THREADS) S.hist[b] = 0;
+        __syncthreads();
+        uint64_t key[BIN_ITEMS];
+        uint16_t bucket[BIN_ITEMS];
+        uint32_t valid = 0;
+        const uint64_t* src = bin1 + (uint64_t)c * cap1;
+#pragma unroll
+        for (int j = 0; j < BIN_ITEMS; ++j) {
+            const uint64_t i = start + (uint64_t)j * BIN_THREADS + threadIdx.x;
+            key[j] = 0;
+            bucket[j] = 0;
+            if (i < cnt) {
+                key[j] = __builtin_nontemporal_load(src + i);
+                bucket[j] = (uint16_t)bucket_of(key[j], g.p_log2, nb);
+                valid |= 1u << j;
+            }
+        }
+        uint32_t fresh = 0;
+        const uint64_t first = (uint64_t)J.part_base + ((uint64_t)(c - J.cbase) << J.cshift);
+        bin_tile(S, key, bucket, valid, nb, g.p_log2, bin2 + first * cap2, cap2, cursor2 + first,
+                 tab + J.slot_base, g, none, jv.job_ctr + (uint64_t)job * kCounterWords, fresh);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(AGG_THREADS) void k_bagg(JobView jv, const uint64_t* __restrict__ bin2,
+                                                      const uint32_t* cursor2, Slot* tab) {
+    __shared__ uint64_t lkey[kPartSlots];
+    __shared__ uint32_t lcnt[kPartSlots];
+    const uint64_t parts = jv.dims->slots >> kPartLog2;
+    const uint64_t cap2 = jv.dims->cap2;
+    const SpillBuf none{nullptr, nullptr, 0};
+    for (uint64_t p = blockIdx.x; p < parts; p += gridDim.x) {
+        const uint64_t cnt = min((uint64_t)cursor2[p], cap2);
+        if (cnt == 0) continue;  // uniform across the workgroup
+        uint32_t fresh = 0;
+        aggregate_partition(bin2 + p * cap2, cnt, tab + (p << kPartLog2), lkey, lcnt, none,
+                            jv.job_ctr + (uint64_t)jv.part_job[p] * kCounterWords, fresh);
+        __syncthreads();
+    }
 }
 
 // Fallback: every key held in the coarse buckets goes straight to the table.
@@ -1254,23 +1385,6 @@ __global__ void k_fill_dims(Slot* tab, const Dims* dims) {
     }
 }
 
-__device__ __forceinline__ uint32_t job_of_tile(const uint32_t* tile_prefix, uint32_t njobs, uint32_t t) {
-    uint32_t lo = 0, hi = njobs;  // find the last j with tile_prefix[j] <= t
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (tile_prefix[mid] <= t) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ bool job_point_key(const JobInfo& J, int64_t i, uint64_t& key) {
-    double x, y;
-    if (J.dtype == 1) load_point(static_cast<const float*>(J.pts), i, x, y);
-    else load_point(static_cast<const double*>(J.pts), i, x, y);
-    return tile_key(x, y, J.scale, key);
-}
-
 // Work tile t holds blockDim * ITEMS consecutive points of one job.  With
 // lds_log2 > 0 the tile's keys are first combined in an LDS hash table and
 // each distinct tile of the work tile is added once.
@@ -1524,6 +1638,15 @@ hipError_t launch_batch_count(const JobView& jv, const uint32_t* tile_prefix, Sl
         case 8: hipLaunchKernelGGL(k_batch_count<8>, grid, block, lds, stream, jv, tile_prefix, tab, lds_log2); break;
         default: hipLaunchKernelGGL(k_batch_count<16>, grid, block, lds, stream, jv, tile_prefix, tab, lds_log2); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_binned(const JobView& jv, const uint32_t* tile_prefix, const uint32_t* cjob, uint64_t* bin1,
+                               uint32_t* cursor1, uint64_t* bin2, uint32_t* cursor2, Slot* tab, hipStream_t stream) {
+    hipLaunchKernelGGL(k_bbin_points, dim3(4096), dim3(BIN_THREADS), 0, stream, jv, tile_prefix, bin1, cursor1, tab);
+    hipLaunchKernelGGL(k_bbin_keys, dim3(8192), dim3(BIN_THREADS), 0, stream, jv, cjob, bin1, cursor1, bin2, cursor2,
+                       tab);
+    hipLaunchKernelGGL(k_bagg, dim3(4096), dim3(AGG_THREADS), 0, stream, jv, bin2, cursor2, tab);
     return hipGetLastError();
 }
 

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -51,6 +52,15 @@ struct BatchEngine {
     uint64_t* o_label = nullptr;
     uint32_t* bounds = nullptr;  // s_start, s_end, o_start, o_end: jobs_cap each
     uint32_t* partials = nullptr;
+    // binned counting
+    uint64_t coarse_cap = 0, bin1_cap = 0, bin2_cap = 0;  // coarse buckets, keys
+    uint32_t* cjob = nullptr;
+    uint32_t* cursor1 = nullptr;
+    uint32_t* cursor2 = nullptr;
+    uint64_t* bin1 = nullptr;
+    uint64_t* bin2 = nullptr;
+    uint32_t* h_cjob = nullptr;
+    bool graph_binned = false;
     // pinned host mirrors
     JobInfo* h_jobs = nullptr;
     Dims* h_dims = nullptr;
@@ -75,6 +85,8 @@ struct BatchEngine {
         if (h_job_ctr) (void)hipHostFree(h_job_ctr);
         if (h_ctr) (void)hipHostFree(h_ctr);
         if (h_bounds) (void)hipHostFree(h_bounds);
+        if (h_cjob) (void)hipHostFree(h_cjob);
+        h_cjob = nullptr;
         h_jobs = nullptr;
         h_dims = nullptr;
         h_tile_prefix = nullptr;
@@ -100,6 +112,7 @@ struct BatchEngine {
         ev_in = nullptr;
         bs = nullptr;
         arena_cap = parts_cap = s_cap = 0;
+        coarse_cap = bin1_cap = bin2_cap = 0;
         jobs_cap = 0;
     }
 
@@ -115,18 +128,22 @@ struct BatchEngine {
 
     // Grows every buffer to hold the given totals (with headroom), dropping
     // the captured graph when anything moves.
-    raster_status reserve(uint64_t slots, uint64_t s_need, uint32_t njobs) {
-        const bool ok = slots <= arena_cap && s_need <= s_cap && njobs <= jobs_cap;
+    raster_status reserve(uint64_t slots, uint64_t s_need, uint32_t njobs, uint64_t ncoarse, uint64_t b1, uint64_t b2) {
+        const bool ok = slots <= arena_cap && s_need <= s_cap && njobs <= jobs_cap && ncoarse <= coarse_cap &&
+                        b1 <= bin1_cap && b2 <= bin2_cap;
         if (ok) return RASTER_OK;
         (void)hipStreamSynchronize(bs);
         drop_graph();
         bufs.release_all();
         release_host();
         arena_cap = std::max<uint64_t>(slots + slots / 4, arena_cap);
-        arena_cap = (arena_cap + kPartSlotsHost - 1) / kPartSlotsHost * kPartSlotsHost;
+        arena_cap = (arena_cap + 2 * kPartSlotsHost - 1) / (2 * kPartSlotsHost) * (2 * kPartSlotsHost);
         parts_cap = arena_cap / kPartSlotsHost;
         s_cap = std::max<uint64_t>(s_need + s_need / 4 + 1024, s_cap);
         jobs_cap = std::max<uint32_t>(njobs + njobs / 4 + 8, jobs_cap);
+        coarse_cap = std::max<uint64_t>((ncoarse + ncoarse / 4 + 9) & ~1ull, coarse_cap);
+        bin1_cap = std::max<uint64_t>(b1 + b1 / 4, bin1_cap);
+        bin2_cap = std::max<uint64_t>(b2 + b2 / 4, bin2_cap);
         auto take = [&](void** p, size_t bytes, const char* what) -> raster_status {
             hipError_t e = bufs.take(p, bytes);
             return e == hipSuccess ? RASTER_OK : hip_fail(e, what);
@@ -154,6 +171,11 @@ struct BatchEngine {
         TAKE(o_job, s_cap * sizeof(uint32_t), "rows");
         TAKE(bounds, (size_t)4 * jobs_cap * sizeof(uint32_t), "job bounds");
         TAKE(partials, kScanBlocks * sizeof(uint32_t), "scan partials");
+        TAKE(cjob, coarse_cap * sizeof(uint32_t), "coarse map");
+        TAKE(cursor1, coarse_cap * sizeof(uint32_t), "coarse cursors");
+        TAKE(cursor2, parts_cap * sizeof(uint32_t), "partition cursors");
+        if (bin1_cap) TAKE(bin1, bin1_cap * sizeof(uint64_t), "coarse buckets");
+        if (bin2_cap) TAKE(bin2, bin2_cap * sizeof(uint64_t), "partition buckets");
 #undef TAKE
         hipError_t e = hipHostMalloc((void**)&h_jobs, jobs_cap * sizeof(JobInfo), hipHostMallocDefault);
         if (e == hipSuccess) e = hipHostMalloc((void**)&h_dims, sizeof(Dims), hipHostMallocDefault);
@@ -163,6 +185,7 @@ struct BatchEngine {
             e = hipHostMalloc((void**)&h_job_ctr, (size_t)jobs_cap * kCounterWords * sizeof(unsigned long long), 0);
         if (e == hipSuccess) e = hipHostMalloc((void**)&h_ctr, kCounterWords * sizeof(unsigned long long), 0);
         if (e == hipSuccess) e = hipHostMalloc((void**)&h_bounds, (size_t)4 * jobs_cap * sizeof(uint32_t), 0);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&h_cjob, coarse_cap * sizeof(uint32_t), 0);
         if (e != hipSuccess) return hip_fail(e, "pinned batch mirrors");
         return RASTER_OK;
     }
@@ -172,13 +195,20 @@ struct BatchEngine {
     }
 
     // The pipeline; enqueued on bs, directly or under capture.
-    hipError_t enqueue(const raster_tuning& tu) {
+    hipError_t enqueue(const raster_tuning& tu, bool binned) {
         const JobView jv = view();
         hipError_t e = launch_zero_u64((uint64_t*)ctr, kCounterWords, bs);
         if (e == hipSuccess) e = launch_zero_u64((uint64_t*)job_ctr, (uint64_t)jobs_cap * kCounterWords, bs);
         if (e == hipSuccess) e = launch_zero_u64((uint64_t*)bounds, (uint64_t)2 * jobs_cap, bs);
         if (e == hipSuccess) e = launch_fill_dims(arena, dims_dev, bs);
-        if (e == hipSuccess) e = launch_batch_count(jv, tile_prefix, arena, kernel_tuning(tu), 4096, bs);
+        if (binned) {
+            if (e == hipSuccess) e = launch_zero_u64((uint64_t*)cursor1, coarse_cap / 2, bs);
+            if (e == hipSuccess) e = launch_zero_u64((uint64_t*)cursor2, parts_cap / 2, bs);
+            if (e == hipSuccess)
+                e = launch_batch_binned(jv, tile_prefix, cjob, bin1, cursor1, bin2, cursor2, arena, bs);
+        } else {
+            if (e == hipSuccess) e = launch_batch_count(jv, tile_prefix, arena, kernel_tuning(tu), 4096, bs);
+        }
         if (e == hipSuccess) e = launch_threshold(arena, jv, s_key, s_count, size, partials, ctr, bs);
         if (e == hipSuccess) e = launch_agglomerate(arena, jv, s_key, parent, nbr, size, s_cap, ctr, bs);
         if (e == hipSuccess)
@@ -204,24 +234,50 @@ raster_status BatchEngine::run(const raster_job* jobs, int32_t n_jobs, hipStream
     raster_status st = init();
     if (st != RASTER_OK) return st;
     const raster_tuning tu = current_tuning();
-    const uint64_t tile = (uint64_t)tu.block * (uint64_t)tu.items;
-    // sizes of every job's table and work tiles
-    std::vector<uint64_t> caps(n_jobs), bases(n_jobs);
-    std::vector<uint32_t> tiles(n_jobs);
-    uint64_t slots = 0, pts_total = 0, tiles_total = 0;
-    for (int32_t i = 0; i < n_jobs; ++i) {
+    bool binned = tu.mode != 1;
+    for (int32_t i = 0; i < n_jobs && binned; ++i) {
+        // level 2 splits a coarse bucket into at most kMaxFine partitions
         const double est = std::max<double>((double)jobs[i].n / 8.0, 1.0) / tu.load_factor;
+        const uint64_t parts = next_pow2(std::max<uint64_t>(kPartSlotsHost, (uint64_t)est)) / kPartSlotsHost;
+        if (parts > 128ull * kMaxFine) binned = false;
+    }
+    const uint64_t tile = binned ? (uint64_t)kBinTile : (uint64_t)tu.block * (uint64_t)tu.items;
+    // sizes of every job's table, coarse buckets and work tiles
+    std::vector<uint64_t> caps(n_jobs), bases(n_jobs);
+    std::vector<uint32_t> tiles(n_jobs), ncs(n_jobs), shifts(n_jobs), cbases(n_jobs);
+    uint64_t slots = 0, pts_total = 0, tiles_total = 0, ncoarse = 0, per1 = 1, per2 = 1;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        const uint64_t n = (uint64_t)jobs[i].n;
+        const double est = std::max<double>((double)n / 8.0, 1.0) / tu.load_factor;
         caps[i] = next_pow2(std::max<uint64_t>(kPartSlotsHost, (uint64_t)est));
         bases[i] = slots;
         slots += caps[i];
-        pts_total += (uint64_t)jobs[i].n;
-        tiles[i] = (uint32_t)(((uint64_t)jobs[i].n + tile - 1) / tile);
+        pts_total += n;
+        tiles[i] = (uint32_t)((n + tile - 1) / tile);
         tiles_total += tiles[i];
+        // about 32K keys per coarse bucket, at most 128 buckets per job
+        const uint64_t parts = caps[i] / kPartSlotsHost;
+        uint64_t nc = next_pow2(std::max<uint64_t>(1, (n + 32767) / 32768));
+        nc = std::min<uint64_t>(nc, std::min<uint64_t>(parts, 128));
+        ncs[i] = (uint32_t)nc;
+        shifts[i] = (uint32_t)(__builtin_ctzll(parts) - __builtin_ctzll(nc));
+        cbases[i] = (uint32_t)ncoarse;
+        ncoarse += nc;
+        per1 = std::max<uint64_t>(per1, (n + nc - 1) / nc);
+        per2 = std::max<uint64_t>(per2, (n + parts - 1) / parts);
     }
     if (tiles_total > 0xFFFFFFF0ull || slots > (1ull << 33))
         return fail(RASTER_E_NOMEM, "batch too large for one launch");
+    // bucket capacities: the expected share plus slack far beyond the binomial
+    // spread; a key past its bucket's capacity is added directly instead
+    uint64_t cap1 = per1 + per1 / 16 + 4 * (uint64_t)std::sqrt((double)per1) + 1024;
+    cap1 = (cap1 + 255) / 256 * 256;
+    uint64_t cap2 = per2 + per2 / 8 + 4 * (uint64_t)std::sqrt((double)per2) + 256;
+    cap2 = (cap2 + 63) / 64 * 64;
+    const uint64_t parts_total = slots / kPartSlotsHost;
     const uint64_t s_need = std::max<uint64_t>(1, std::min<uint64_t>(slots, pts_total));
-    st = reserve(slots, s_need, (uint32_t)n_jobs);
+    st = reserve(slots, s_need, (uint32_t)n_jobs, binned ? ncoarse : 0, binned ? ncoarse * cap1 : 0,
+                 binned ? parts_total * cap2 : 0);
     if (st != RASTER_OK) return st;
     // host mirrors
     uint32_t tp = 0;
@@ -238,15 +294,25 @@ raster_status BatchEngine::run(const raster_job* jobs, int32_t n_jobs, hipStream
         J.mu = jobs[i].mu;
         J.dtype = (int32_t)jobs[i].dt;
         J.first_tile = tp;
+        J.part_base = (uint32_t)(bases[i] / kPartSlotsHost);
+        J.cbase = cbases[i];
+        J.cshift = shifts[i];
+        J.pad = 0;
         h_tile_prefix[i] = tp;
         tp += tiles[i];
         for (uint64_t p = bases[i] / kPartSlotsHost; p < (bases[i] + caps[i]) / kPartSlotsHost; ++p)
             h_part_job[p] = (uint32_t)i;
+        if (binned)
+            for (uint32_t c = 0; c < ncs[i]; ++c) h_cjob[cbases[i] + c] = (uint32_t)i;
     }
     h_tile_prefix[n_jobs] = tp;
     h_dims->slots = slots;
     h_dims->njobs = (uint32_t)n_jobs;
     h_dims->tiles = tp;
+    h_dims->cap1 = cap1;
+    h_dims->cap2 = cap2;
+    h_dims->ncoarse = binned ? (uint32_t)ncoarse : 0;
+    h_dims->segs = (uint32_t)((cap1 + kBinTile - 1) / kBinTile);
     hipError_t e = hipEventRecord(ev_in, user);
     if (e == hipSuccess) e = hipStreamWaitEvent(bs, ev_in, 0);
     if (e == hipSuccess) e = hipMemcpyAsync(jobs_dev, h_jobs, n_jobs * sizeof(JobInfo), hipMemcpyHostToDevice, bs);
@@ -256,14 +322,16 @@ raster_status BatchEngine::run(const raster_job* jobs, int32_t n_jobs, hipStream
     if (e == hipSuccess)
         e = hipMemcpyAsync(part_job, h_part_job, (slots / kPartSlotsHost) * sizeof(uint32_t), hipMemcpyHostToDevice,
                            bs);
+    if (e == hipSuccess && binned)
+        e = hipMemcpyAsync(cjob, h_cjob, ncoarse * sizeof(uint32_t), hipMemcpyHostToDevice, bs);
     if (e != hipSuccess) return hip_fail(e, "batch upload");
     const bool same_tuning = graph_tuning.block == tu.block && graph_tuning.items == tu.items &&
-                             graph_tuning.preagg_slots == tu.preagg_slots;
+                             graph_tuning.preagg_slots == tu.preagg_slots && graph_binned == binned;
     if (!graph_valid || !same_tuning) {
         drop_graph();
         e = hipStreamBeginCapture(bs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipError_t le = enqueue(tu);
+            hipError_t le = enqueue(tu, binned);
             e = hipStreamEndCapture(bs, &graph);
             if (le != hipSuccess) e = le;
         }
@@ -275,6 +343,7 @@ raster_status BatchEngine::run(const raster_job* jobs, int32_t n_jobs, hipStream
         }
         graph_valid = true;
         graph_tuning = tu;
+        graph_binned = binned;
     }
     hipEvent_t t0 = nullptr, t1 = nullptr;
     (void)hipEventCreate(&t0);

@@ -59,9 +59,14 @@ def _batch_args(batch):
     return [dict(points=d, precision=sp.precision, tau=sp.tau, mu=sp.mu) for sp, _, d in batch]
 
 
-def test_batch_matches_alone_and_oracle(raster, torch, batch24):
-    _say(f"batch of {len(batch24)} jobs, {sum(sp.n for sp, _, _ in batch24)} points")
-    res = raster.cluster_batch(_batch_args(batch24))
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_matches_alone_and_oracle(raster, torch, batch24, mode):
+    _say(f"batch of {len(batch24)} jobs, {sum(sp.n for sp, _, _ in batch24)} points, mode {mode}")
+    raster.set_tuning(mode=mode)
+    try:
+        res = raster.cluster_batch(_batch_args(batch24))
+    finally:
+        raster.set_tuning(None)
     assert len(res) == len(batch24)
     for k, ((sp, pts, d), r) in enumerate(zip(batch24, res)):
         alone = raster.cluster(d, precision=sp.precision, tau=sp.tau, mu=sp.mu)
@@ -78,7 +83,8 @@ def test_batch_graph_replay_and_recapture(raster, torch, batch24):
         same_result(first[k], again[k], f"replay job {k}")
     for k in range(8):
         same_result(first[k + 3], smaller[k], f"sub-batch job {k}")
-    for tuning in (dict(block=512, items=2), dict(preagg_slots=2048), dict(block=128, items=16, load_factor=0.3)):
+    for tuning in (dict(block=512, items=2, mode=1), dict(preagg_slots=2048, mode=1),
+                   dict(block=128, items=16, load_factor=0.3), dict(mode=1, load_factor=0.8)):
         raster.set_tuning(**tuning)
         try:
             other = raster.cluster_batch(_batch_args(batch24))
@@ -95,10 +101,15 @@ def test_batch_spilled_job_is_redone(raster, torch):
     noise = rng.uniform(0.0, 1000.0, size=(400_000, 2))
     small = synth.plain_small(1)[:50_000]
     d1, d2 = dev(noise, torch), dev(small, torch)
-    res = raster.cluster_batch([dict(points=d1, precision=2, tau=1, mu=1),
-                                dict(points=d2, precision=1, tau=5, mu=4)])
-    assert_same(res[0], oracle.cluster(noise, tau=1, mu=1, precision=2), "spilled job")
-    assert_same(res[1], oracle.cluster(small, tau=5, mu=4, precision=1), "neighbour of spilled job")
+    for mode in (0, 1):
+        raster.set_tuning(mode=mode)
+        try:
+            res = raster.cluster_batch([dict(points=d1, precision=2, tau=1, mu=1),
+                                        dict(points=d2, precision=1, tau=5, mu=4)])
+        finally:
+            raster.set_tuning(None)
+        assert_same(res[0], oracle.cluster(noise, tau=1, mu=1, precision=2), f"spilled job, mode {mode}")
+        assert_same(res[1], oracle.cluster(small, tau=5, mu=4, precision=1), f"neighbour of spilled job, mode {mode}")
 
 
 def test_batch_range_error_fails_whole_batch(raster, torch, batch24):
