@@ -348,7 +348,7 @@ class Tuning:
     preagg_slots: int = 0
     load_factor: float = 0.6
     mode: int = 0
-    group_mpoints: int = 256
+    group_mpoints: int = 512
 
 
 def set_tuning(t: Tuning | None = None, **kw) -> None:

@@ -48,7 +48,7 @@ raster_status hip_fail(hipError_t e, const char* what) {
 // ========================================================= tuning ==========
 
 static std::mutex g_tuning_mu;
-static const raster_tuning kDefaultTuning = {256, 4, 0, 0.6f, 0, 256};
+static const raster_tuning kDefaultTuning = {256, 4, 0, 0.6f, 0, 512};
 static raster_tuning g_tuning = kDefaultTuning;
 
 raster_tuning current_tuning() {
@@ -399,14 +399,15 @@ raster_status TableRun::ensure_bins(uint64_t want_points) {
     if (bin1 && (bin_points >= want_points || group_points > 0)) return RASTER_OK;
     if (bin1) bufs.give_back(bin1);
     bin1 = nullptr;
-    // a coarse bucket receives about want_points / 128 keys; the slack is far
-    // beyond the binomial spread, and overflow only costs direct inserts
-    const uint64_t per = want_points / kCoarse;
-    cap1 = (per + per / 50 + 8192 + 255) / 256 * 256;
-    HIP_TRY(bufs.take((void**)&bin1, kCoarse * cap1 * sizeof(uint64_t)), "coarse buckets");
+    // a coarse list receives about want_points / (128 kBinRep) keys; the slack
+    // is far beyond the binomial spread, and overflow only costs direct inserts
+    const uint64_t lists = (uint64_t)kBinRep * kCoarse;
+    const uint64_t per = want_points / lists;
+    cap1 = (per + per / 50 + 1024 + 255) / 256 * 256;
+    HIP_TRY(bufs.take((void**)&bin1, lists * cap1 * sizeof(uint64_t)), "coarse buckets");
     if (!cursor1) {
-        HIP_TRY(bufs.take((void**)&cursor1, kCoarse * sizeof(uint32_t)), "coarse cursors");
-        HIP_TRY(launch_zero_u64((uint64_t*)cursor1, kCoarse / 2, stream), "zero cursors");
+        HIP_TRY(bufs.take((void**)&cursor1, lists * sizeof(uint32_t)), "coarse cursors");
+        HIP_TRY(launch_zero_u64((uint64_t*)cursor1, lists / 2, stream), "zero cursors");
     }
     bin_points = want_points;
     return RASTER_OK;
@@ -422,21 +423,21 @@ raster_status TableRun::flush() {
     if (!binned_geometry(g)) {
         HIP_TRY(launch_drain_bins(bin1, cap1, cursor1, tab, cap, sp, ctr, stream), "drain bins");
     } else {
-        const uint64_t parts = 1ull << g.p_log2;
-        uint64_t c2 = group_points / parts;
-        c2 = c2 + c2 / 8 + 4 * (uint64_t)std::sqrt((double)c2 + 1.0) + 256;
+        const uint64_t lists = (uint64_t)kBinRep << g.p_log2;  // kBinRep lists per partition
+        uint64_t c2 = group_points / lists;
+        c2 = c2 + c2 / 8 + 4 * (uint64_t)std::sqrt((double)c2 + 1.0) + 64;
         c2 = (c2 + 63) / 64 * 64;
-        if (parts * c2 > bin2_slots || parts > cursor2_n) {
+        if (lists * c2 > bin2_slots || lists > cursor2_n) {
             if (bin2) bufs.give_back(bin2);
             if (cursor2) bufs.give_back(cursor2);
             bin2 = nullptr;
             cursor2 = nullptr;
-            bin2_slots = parts * c2 + parts * c2 / 4;  // headroom for later groups
-            cursor2_n = parts;
+            bin2_slots = lists * c2 + lists * c2 / 4;  // headroom for later groups
+            cursor2_n = lists;
             HIP_TRY(bufs.take((void**)&bin2, bin2_slots * sizeof(uint64_t)), "partition buckets");
             HIP_TRY(bufs.take((void**)&cursor2, cursor2_n * sizeof(uint32_t)), "partition cursors");
         }
-        c2 = bin2_slots / parts;
+        c2 = bin2_slots / lists;
         hipEvent_t a = nullptr;
         if ((st = span_begin(1, &a)) != RASTER_OK) return st;
         HIP_TRY(launch_bin_keys(bin1, cap1, cursor1, bin2, c2, cursor2, tab, cap, sp, ctr, stream), "bin keys");
@@ -497,12 +498,12 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
         if (binned) {
             // a one-shot call bins exactly its points; a stream expects more
             // chunks like this one and bins several before updating the table
-            st = ensure_bins(single_shot ? (uint64_t)piece : 8 * (uint64_t)piece);
+            st = ensure_bins(single_shot ? (uint64_t)piece : 16 * (uint64_t)piece);
             if (st != RASTER_OK) return st;
             if (group_points + (uint64_t)piece > bin_points) {
                 st = flush();
                 if (st != RASTER_OK) return st;
-                st = ensure_bins(single_shot ? (uint64_t)piece : 8 * (uint64_t)piece);
+                st = ensure_bins(single_shot ? (uint64_t)piece : 16 * (uint64_t)piece);
                 if (st != RASTER_OK) return st;
             }
             if ((st = span_begin(0, &a)) != RASTER_OK) return st;

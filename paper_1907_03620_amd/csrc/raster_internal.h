@@ -20,11 +20,20 @@ constexpr uint32_t kMaxProbe = 128;
 
 // Table geometry.  The table is cut into partitions of 2^cp_log2 slots
 // (4096 once the table is that large); a key's partition is the top p_log2
-// bits of its hash, its home slot inside the partition the low cp_log2 bits,
-// and probing wraps inside the partition.  A partition is then exactly the
-// slice one workgroup can hold in LDS, and the top hash bits name a key's
-// partition whatever the table size.
+// bits of its placement hash, its home slot inside the partition the low
+// cp_log2 bits of its own hash, and probing wraps inside the partition.  A
+// partition is then exactly the slice one workgroup can hold in LDS, and the
+// top placement-hash bits name a key's partition whatever the table size.
 constexpr uint32_t kPartLog2 = 12;
+// A key's partition is chosen by the hash of its super-tile, the square of
+// 2^kSuperLog2 x 2^kSuperLog2 tiles that holds it; the slot inside the
+// partition by the hash of the key itself.  Tiles that touch usually share a
+// partition, so the neighbour lookups and union-find of the agglomeration
+// stay inside one 64 KB slice of the table and one short run of the compact
+// significant-tile arrays.  A super-tile holds at most 2^(2 kSuperLog2) keys,
+// which bounds how unevenly keys spread over partitions.
+constexpr uint32_t kSuperLog2 = 3;
+constexpr uint64_t kSuperMask = ~((((1ull << kSuperLog2) - 1) << 32) | ((1ull << kSuperLog2) - 1));
 struct Geo {
     uint64_t cap;      // slots, a power of two
     uint32_t cp_log2;  // log2 slots per partition
@@ -46,6 +55,13 @@ __host__ __device__ inline Geo make_geo(uint64_t cap) {
 constexpr uint32_t kCoarseLog2 = 7;
 constexpr uint32_t kCoarse = 1u << kCoarseLog2;
 constexpr uint32_t kMaxFine = 512;
+// Every bucket of both binning levels is kept as kBinRep lists, each with its
+// own cursor; a workgroup appends to one of them.  Cursor updates from many
+// workgroups to one cache line serialise in the memory-side atomic unit, so
+// spreading them over kBinRep lines is what lets the binning run at stream
+// speed.
+constexpr uint32_t kBinRep = 8;
+
 inline bool binned_geometry(const Geo& g) {
     return g.cp_log2 == kPartLog2 && g.p_log2 >= kCoarseLog2 && (1ull << (g.p_log2 - kCoarseLog2)) <= kMaxFine;
 }
@@ -69,6 +85,7 @@ enum CounterIndex : int {
     C_COMPONENTS,    // roots of the union-find forest
     C_CLUSTERS,      // roots with at least mu tiles
     C_TILES,         // output rows t
+    C_TABLE_KEYS,    // keys in the table before a binned update (0: the slices need not be read)
     C_COUNT_
 };
 constexpr int kCounterWords = 16;  // padded to 128 bytes

@@ -20,15 +20,33 @@ namespace {
 
 // ---------------------------------------------------------------- helpers ---
 
-__device__ __forceinline__ uint64_t mix64(uint64_t z) {
-    // SplitMix64 output finaliser (Steele, Lea and Flood, OOPSLA 2014): an
-    // invertible 64-bit mixer.  Only the slot a key probes from depends on it.
-    z ^= z >> 30;
-    z *= 0xbf58476d1ce4e5b9ull;
-    z ^= z >> 27;
-    z *= 0x94d049bb133111ebull;
-    z ^= z >> 31;
-    return z;
+// 32-bit integer mixer "lowbias32" (C. Wellons, "Prospecting for hash
+// functions", 2018): a bijection whose output bits each depend on every input
+// bit.  Only 32-bit multiplies: a 64-bit one costs four of them on the VALU.
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// Fibonacci-hashing multiplier, floor(2^32 / golden ratio), odd.
+constexpr uint32_t kGolden32 = 0x9e3779b9u;
+
+// Hash that picks a key's partition (and coarse bucket): that of its
+// super-tile.  Top bits are used.
+__device__ __forceinline__ uint32_t place_hash(uint64_t key) {
+    const uint32_t sx = (uint32_t)(key >> 32) >> kSuperLog2, sy = (uint32_t)key >> kSuperLog2;
+    return mix32(sx * kGolden32 + sy);
+}
+
+// Hash that picks a key's home slot inside its partition.  Low bits are used.
+// Tiles near each other never share a hash: x * kGolden32 + y (mod 2^32) takes
+// distinct values on any window of 2^14 x 2^17 tiles (checked exhaustively).
+__device__ __forceinline__ uint32_t slot_hash(uint64_t key) {
+    return mix32((uint32_t)(key >> 32) * kGolden32 + (uint32_t)key);
 }
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -129,9 +147,9 @@ enum AddResult : int { ADD_FOUND = 0, ADD_NEW = 1, ADD_FULL = 2 };
 // its probe window if it is not there yet.  Keys are only ever written once
 // (empty -> key), so a stale read can only show a slot as empty; the
 // compare-and-swap then returns the true occupant.
-__device__ __forceinline__ uint64_t home_slot(uint64_t h, const Geo& g) {
-    const uint64_t part = g.p_log2 ? (h >> (64 - g.p_log2)) : 0;
-    return (part << g.cp_log2) | (h & ((1ull << g.cp_log2) - 1));
+__device__ __forceinline__ uint64_t home_slot(uint64_t key, const Geo& g) {
+    const uint64_t part = g.p_log2 ? (place_hash(key) >> (32 - g.p_log2)) : 0;
+    return (part << g.cp_log2) | (slot_hash(key) & ((1u << g.cp_log2) - 1));
 }
 
 // Next probe position: linear, wrapping inside the partition.
@@ -141,7 +159,7 @@ __device__ __forceinline__ uint64_t next_slot(uint64_t s, const Geo& g) {
 }
 
 __device__ __forceinline__ int table_add(Slot* tab, const Geo& g, uint64_t key, uint32_t inc) {
-    uint64_t pos = home_slot(mix64(key), g);
+    uint64_t pos = home_slot(key, g);
     for (uint32_t p = 0; p < kMaxProbe; ++p) {
         Slot* sl = tab + pos;
         uint64_t cur = ld_relaxed(&sl->key);
@@ -164,7 +182,7 @@ __device__ __forceinline__ int table_add(Slot* tab, const Geo& g, uint64_t key, 
 
 // Read-only lookup; returns the slot index or ~0 when the key is absent.
 __device__ __forceinline__ uint64_t table_find(const Slot* tab, const Geo& g, uint64_t key) {
-    uint64_t pos = home_slot(mix64(key), g);
+    uint64_t pos = home_slot(key, g);
     for (uint32_t p = 0; p < kMaxProbe; ++p) {
         const uint64_t cur = tab[pos].key;
         if (cur == key) return pos;
@@ -291,7 +309,7 @@ __global__ void k_count_preagg(const T* __restrict__ pts, int64_t n, double scal
             int r = ADD_FOUND;
             if (valid & (1u << j)) {
                 const uint64_t k = key[j];
-                uint32_t pos = (uint32_t)(mix64(k) >> 40) & (L - 1);
+                uint32_t pos = (slot_hash(k) >> 16) & (L - 1);
                 bool done = false;
                 for (int p = 0; p < 8 && !done; ++p) {
                     uint64_t cur = *(volatile uint64_t*)&lkey[pos];
@@ -386,8 +404,8 @@ __global__ void k_rehash(const Slot* from, uint64_t from_cap, Slot* to, const Ge
 // All traffic is then sequential HBM streams plus one table read and write
 // per group of chunks.
 
-constexpr int BIN_THREADS = 256;
-constexpr int BIN_ITEMS = (int)kBinTile / BIN_THREADS;  // 16
+constexpr int BIN_THREADS = 512;
+constexpr int BIN_ITEMS = (int)kBinTile / BIN_THREADS;  // 8
 
 struct BinScratch {
     uint64_t key[kBinTile];
@@ -397,19 +415,20 @@ struct BinScratch {
     uint32_t total;
 };
 
-// Bucket of a key: bits [shift, shift + log2 nb) of its hash, counted from the top.
+// Bucket of a key: the log2 nb bits of its placement hash that end top_bits
+// from the top, so buckets refine in step with partitions.
 __device__ __forceinline__ uint32_t bucket_of(uint64_t key, uint32_t top_bits, uint32_t nb) {
-    return top_bits ? (uint32_t)(mix64(key) >> (64 - top_bits)) & (nb - 1) : 0u;
+    return top_bits ? (place_hash(key) >> (32 - top_bits)) & (nb - 1) : 0u;
 }
 
 // Scatters this tile's valid keys into nb buckets: bucket b's keys are
 // appended at out[b * stride + cursor[b] ...].  A key past its bucket's
-// capacity (stride) goes straight into the table instead.  The bucket of a
+// capacity (cap <= stride) goes straight into the table instead.  The bucket of a
 // key is bucket_of(key, top_bits, nb).  S.hist must be zero on entry (and a
 // barrier passed); every thread of the workgroup calls.
 __device__ void bin_tile(BinScratch& S, const uint64_t (&key)[BIN_ITEMS], const uint16_t (&bucket)[BIN_ITEMS],
                          uint32_t valid, uint32_t nb, uint32_t top_bits, uint64_t* out, uint64_t stride,
-                         uint32_t* cursor, Slot* tab, const Geo& g, const SpillBuf& sp, unsigned long long* ctr,
+                         uint64_t cap, uint32_t* cursor, Slot* tab, const Geo& g, const SpillBuf& sp, unsigned long long* ctr,
                          uint32_t& fresh) {
     uint32_t rank[BIN_ITEMS];
 #pragma unroll
@@ -457,7 +476,7 @@ __device__ void bin_tile(BinScratch& S, const uint64_t (&key)[BIN_ITEMS], const 
             k = S.key[q];
             const uint32_t b = bucket_of(k, top_bits, nb);
             const uint64_t dst = (uint64_t)S.base[b] + (q - S.off[b]);
-            if (dst < stride) {
+            if (dst < cap) {
                 out[(uint64_t)b * stride + dst] = k;
             } else {
                 r = table_add(tab, g, k, 1u);
@@ -503,20 +522,27 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_points(const T* __restrict_
     }
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrRange);
     uint32_t fresh = 0;
-    bin_tile(S, key, bucket, valid, kCoarse, kCoarseLog2, bin1, cap1, cursor1, tab, g, sp, ctr, fresh);
+    const uint32_t r = blockIdx.x % kBinRep;
+    bin_tile(S, key, bucket, valid, kCoarse, kCoarseLog2, bin1 + (uint64_t)r * kCoarse * cap1, cap1, cap1,
+             cursor1 + r * kCoarse, tab, g, sp, ctr, fresh);
     add_fresh(ctr, fresh);
 }
 
-// Level 2: workgroup (b1, seg) splits keys [seg * kBinTile, ...) of coarse
-// bucket b1 into that bucket's partitions.
+// Level 2: workgroup (l1, seg) splits keys [seg * kBinTile, ...) of coarse
+// list l1 = (replica r, bucket b1) into replica r of that bucket's partition
+// lists.  Segments vary fastest with the workgroup index: the workgroups in
+// flight at once then append to the lists of a few dozen coarse lists, whose
+// open partial lines stay in L2 until complete, while the replicas keep the
+// cursor lines they update apart.
 __global__ __launch_bounds__(BIN_THREADS) void k_bin_keys(const uint64_t* __restrict__ bin1, uint64_t cap1,
                                                           const uint32_t* cursor1, uint32_t segs, uint64_t* bin2,
                                                           uint64_t cap2, uint32_t* cursor2, Slot* tab, const Geo g,
                                                           SpillBuf sp, unsigned long long* ctr) {
     __shared__ BinScratch S;
-    const uint32_t b1 = blockIdx.x / segs;
+    const uint32_t l1 = blockIdx.x / segs;
     const uint32_t seg = blockIdx.x % segs;
-    const uint64_t cnt = min((uint64_t)cursor1[b1], cap1);
+    const uint32_t r = l1 / kCoarse, b1 = l1 % kCoarse;
+    const uint64_t cnt = min((uint64_t)cursor1[l1], cap1);
     const uint64_t start = (uint64_t)seg * kBinTile;
     if (start >= cnt) return;  // uniform across the workgroup
     const uint32_t fine_log2 = g.p_log2 - kCoarseLog2;
@@ -526,7 +552,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_keys(const uint64_t* __rest
     uint64_t key[BIN_ITEMS];
     uint16_t bucket[BIN_ITEMS];
     uint32_t valid = 0;
-    const uint64_t* src = bin1 + (uint64_t)b1 * cap1;
+    const uint64_t* src = bin1 + (uint64_t)l1 * cap1;
 #pragma unroll
     for (int j = 0; j < BIN_ITEMS; ++j) {
         const uint64_t i = start + (uint64_t)j * BIN_THREADS + threadIdx.x;
@@ -539,8 +565,11 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_keys(const uint64_t* __rest
         }
     }
     uint32_t fresh = 0;
+    // partition lists are stored partition-major (a partition's replicas
+    // side by side), their cursors replica-major
     const uint64_t first = (uint64_t)b1 << fine_log2;
-    bin_tile(S, key, bucket, valid, nb, g.p_log2, bin2 + first * cap2, cap2, cursor2 + first, tab, g, sp, ctr,
+    bin_tile(S, key, bucket, valid, nb, g.p_log2, bin2 + (first * kBinRep + r) * cap2, kBinRep * cap2, cap2,
+             cursor2 + ((uint64_t)r << g.p_log2) + first, tab, g, sp, ctr,
              fresh);
     add_fresh(ctr, fresh);
 }
@@ -551,7 +580,7 @@ constexpr uint32_t kPartSlots = 1u << kPartLog2;
 // LDS version of table_add over one partition slice (same probe sequence as
 // the device table, so slots stay where a device-table probe looks for them).
 __device__ __forceinline__ int lds_add(uint64_t* lkey, uint32_t* lcnt, uint64_t key) {
-    uint32_t pos = (uint32_t)mix64(key) & (kPartSlots - 1);
+    uint32_t pos = slot_hash(key) & (kPartSlots - 1);
     for (uint32_t p = 0; p < kMaxProbe; ++p) {
         uint64_t cur = *(volatile uint64_t*)&lkey[pos];
         if (cur == kEmptyKey) {
@@ -576,12 +605,42 @@ __device__ __forceinline__ int lds_add(uint64_t* lkey, uint32_t* lcnt, uint64_t 
 // flight before the LDS work that depends on them.
 constexpr int AGG_BATCH = 8;
 
-// Adds the cnt keys at src to one 4096-slot partition through LDS.
-__device__ __forceinline__ void aggregate_partition(const uint64_t* __restrict__ src, uint64_t cnt, Slot* part,
-                                                    uint64_t* lkey, uint32_t* lcnt, const SpillBuf& sp,
+// The NL key lists of one partition: list i holds min(count[i * cstride], cap)
+// keys at src + i * lstride, read as one concatenated range.  The sizes are
+// loaded once, into registers.
+template <int NL>
+struct PartLists {
+    const uint64_t* src;
+    uint64_t lstride;
+    uint32_t size[NL];
+    uint32_t total;
+    __device__ PartLists(const uint64_t* s, uint64_t ls, const uint32_t* count, uint64_t cstride, uint64_t cap)
+        : src(s), lstride(ls), total(0) {
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            size[i] = (uint32_t)min((uint64_t)count[i * cstride], cap);
+            total += size[i];
+        }
+    }
+    __device__ uint32_t size_of(uint32_t li) const {
+        uint32_t v = 0;
+#pragma unroll
+        for (int i = 0; i < NL; ++i)
+            if ((uint32_t)i == li) v = size[i];
+        return v;
+    }
+};
+
+// Adds the L.total keys of the lists L to one 4096-slot partition through LDS.
+// With load false the table holds no key yet, and the slice starts empty
+// without being read.
+template <int NL>
+__device__ __forceinline__ void aggregate_partition(const PartLists<NL>& L, Slot* part, bool load, uint64_t* lkey,
+                                                    uint32_t* lcnt, const SpillBuf& sp,
                                                     unsigned long long* spill_ctr, uint32_t& fresh) {
     constexpr int PER = (int)kPartSlots / AGG_THREADS;
-    {
+    const uint32_t cnt = L.total;
+    if (load) {
         Slot v[PER];
 #pragma unroll
         for (int u = 0; u < PER; ++u) v[u] = part[u * AGG_THREADS + threadIdx.x];
@@ -590,14 +649,31 @@ __device__ __forceinline__ void aggregate_partition(const uint64_t* __restrict__
             lkey[u * AGG_THREADS + threadIdx.x] = v[u].key;
             lcnt[u * AGG_THREADS + threadIdx.x] = v[u].count;
         }
+    } else {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            lkey[u * AGG_THREADS + threadIdx.x] = kEmptyKey;
+            lcnt[u * AGG_THREADS + threadIdx.x] = 0;
+        }
     }
     __syncthreads();
-    for (uint64_t q0 = 0; q0 < cnt; q0 += (uint64_t)AGG_THREADS * AGG_BATCH) {
+    // a thread's positions only grow, so it walks the lists once: list li
+    // covers positions [lo, hi) of the concatenation
+    uint32_t li = 0, lo = 0, hi = L.size[0];
+    for (uint32_t q0 = 0; q0 < cnt; q0 += AGG_THREADS * AGG_BATCH) {
         uint64_t k[AGG_BATCH];
 #pragma unroll
         for (int u = 0; u < AGG_BATCH; ++u) {
-            const uint64_t q = q0 + (uint64_t)u * AGG_THREADS + threadIdx.x;
-            k[u] = q < cnt ? __builtin_nontemporal_load(src + q) : kEmptyKey;
+            const uint32_t q = q0 + u * AGG_THREADS + threadIdx.x;
+            k[u] = kEmptyKey;
+            if (q < cnt) {
+                while (q >= hi) {
+                    ++li;
+                    lo = hi;
+                    hi += L.size_of(li);
+                }
+                k[u] = __builtin_nontemporal_load(L.src + li * L.lstride + (q - lo));
+            }
         }
 #pragma unroll
         for (int u = 0; u < AGG_BATCH; ++u) {
@@ -630,10 +706,11 @@ __global__ __launch_bounds__(AGG_THREADS) void k_aggregate(const uint64_t* __res
     __shared__ uint64_t lkey[kPartSlots];
     __shared__ uint32_t lcnt[kPartSlots];
     const uint64_t p = blockIdx.x;
-    const uint64_t cnt = min((uint64_t)cursor2[p], cap2);
-    if (cnt == 0) return;  // uniform across the workgroup
+    const uint64_t parts = gridDim.x;
+    const PartLists<kBinRep> L(bin2 + p * kBinRep * cap2, cap2, cursor2 + p, parts, cap2);
+    if (L.total == 0) return;  // uniform across the workgroup
     uint32_t fresh = 0;
-    aggregate_partition(bin2 + p * cap2, cnt, tab + (p << kPartLog2), lkey, lcnt, sp, ctr, fresh);
+    aggregate_partition(L, tab + (p << kPartLog2), ctr[C_TABLE_KEYS] != 0, lkey, lcnt, sp, ctr, fresh);
     add_fresh(ctr, fresh);
 }
 
@@ -680,7 +757,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bbin_points(JobView jv, const u
         unsigned long long* jc = jv.job_ctr + (uint64_t)job * kCounterWords;
         if (bad) atomicOr(&jc[C_ERROR], (unsigned long long)kErrRange);
         uint32_t fresh = 0;
-        bin_tile(S, key, bucket, valid, nb, top, bin1 + (uint64_t)J.cbase * cap1, cap1, cursor1 + J.cbase,
+        bin_tile(S, key, bucket, valid, nb, top, bin1 + (uint64_t)J.cbase * cap1, cap1, cap1, cursor1 + J.cbase,
                  tab + J.slot_base, g, none, jc, fresh);
         __syncthreads();  // S is reused by the next tile
     }
@@ -723,7 +800,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bbin_keys(JobView jv, const uin
         }
         uint32_t fresh = 0;
         const uint64_t first = (uint64_t)J.part_base + ((uint64_t)(c - J.cbase) << J.cshift);
-        bin_tile(S, key, bucket, valid, nb, g.p_log2, bin2 + first * cap2, cap2, cursor2 + first,
+        bin_tile(S, key, bucket, valid, nb, g.p_log2, bin2 + first * cap2, cap2, cap2, cursor2 + first,
                  tab + J.slot_base, g, none, jv.job_ctr + (uint64_t)job * kCounterWords, fresh);
         __syncthreads();
     }
@@ -737,10 +814,10 @@ __global__ __launch_bounds__(AGG_THREADS) void k_bagg(JobView jv, const uint64_t
     const uint64_t cap2 = jv.dims->cap2;
     const SpillBuf none{nullptr, nullptr, 0};
     for (uint64_t p = blockIdx.x; p < parts; p += gridDim.x) {
-        const uint64_t cnt = min((uint64_t)cursor2[p], cap2);
-        if (cnt == 0) continue;  // uniform across the workgroup
+        const PartLists<1> L(bin2 + p * cap2, 0, cursor2 + p, 0, cap2);
+        if (L.total == 0) continue;  // uniform across the workgroup
         uint32_t fresh = 0;
-        aggregate_partition(bin2 + p * cap2, cnt, tab + (p << kPartLog2), lkey, lcnt, none,
+        aggregate_partition(L, tab + (p << kPartLog2), true, lkey, lcnt, none,
                             jv.job_ctr + (uint64_t)jv.part_job[p] * kCounterWords, fresh);
         __syncthreads();
     }
@@ -749,7 +826,7 @@ __global__ __launch_bounds__(AGG_THREADS) void k_bagg(JobView jv, const uint64_t
 // Fallback: every key held in the coarse buckets goes straight to the table.
 __global__ void k_drain_bins(const uint64_t* bin1, uint64_t cap1, const uint32_t* cursor1, Slot* tab, const Geo g,
                              SpillBuf sp, unsigned long long* ctr) {
-    const uint64_t total = (uint64_t)kCoarse * cap1;
+    const uint64_t total = (uint64_t)kBinRep * kCoarse * cap1;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t n_round = (total + 63) / 64 * 64;
     uint32_t fresh = 0;
@@ -767,6 +844,10 @@ __global__ void k_drain_bins(const uint64_t* bin1, uint64_t cap1, const uint32_t
         spill_push(sp, ctr, r == ADD_FULL, k, 1u);
     }
     add_fresh(ctr, fresh);
+}
+
+__global__ void k_snapshot_keys(unsigned long long* ctr) {
+    if (threadIdx.x == 0) ctr[C_TABLE_KEYS] = ctr[C_INSERTED];
 }
 
 __global__ void k_zero_u32(uint32_t* p, uint64_t n) {
@@ -1159,7 +1240,7 @@ __global__ void k_link(const Slot* tab, JobView jv, const uint64_t* s_key, uint3
         Slot v[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            pos[q] = home_slot(mix64(nk[q]), g);
+            pos[q] = home_slot(nk[q], g);
             if (want[q]) v[q] = jt[pos[q]];
         }
         uint32_t best = (uint32_t)i;
@@ -1422,7 +1503,7 @@ __global__ void k_batch_count(JobView jv, const uint32_t* tile_prefix, Slot* tab
             }
             bool done = false;
             if (L) {
-                uint32_t pos = (uint32_t)(mix64(k) >> 40) & (L - 1);
+                uint32_t pos = (slot_hash(k) >> 16) & (L - 1);
                 for (int p = 0; p < 8 && !done; ++p) {
                     uint64_t cur = *(volatile uint64_t*)&lkey[pos];
                     if (cur == kEmptyKey)
@@ -1539,11 +1620,11 @@ hipError_t launch_bin_keys(const uint64_t* bin1, uint64_t cap1, const uint32_t* 
                            unsigned long long* ctr, hipStream_t stream) {
     const Geo g = make_geo(cap);
     if (!binned_geometry(g)) return hipErrorInvalidValue;
-    const uint64_t parts = 1ull << g.p_log2;
-    hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(parts, 256, 4096)), dim3(256), 0, stream, cursor2, parts);
+    const uint64_t lists2 = (uint64_t)kBinRep << g.p_log2;
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(lists2, 256, 4096)), dim3(256), 0, stream, cursor2, lists2);
     const uint32_t segs = (uint32_t)((cap1 + kBinTile - 1) / kBinTile);
-    hipLaunchKernelGGL(k_bin_keys, dim3(kCoarse * segs), dim3(BIN_THREADS), 0, stream, bin1, cap1, cursor1, segs,
-                       bin2, cap2, cursor2, tab, g, spill, ctr);
+    hipLaunchKernelGGL(k_bin_keys, dim3(kBinRep * kCoarse * segs), dim3(BIN_THREADS), 0, stream, bin1, cap1, cursor1,
+                       segs, bin2, cap2, cursor2, tab, g, spill, ctr);
     return hipGetLastError();
 }
 
@@ -1552,17 +1633,18 @@ hipError_t launch_aggregate(const uint64_t* bin2, uint64_t cap2, const uint32_t*
     const Geo g = make_geo(cap);
     if (!binned_geometry(g)) return hipErrorInvalidValue;
     const uint64_t parts = 1ull << g.p_log2;
+    hipLaunchKernelGGL(k_snapshot_keys, dim3(1), dim3(64), 0, stream, ctr);
     hipLaunchKernelGGL(k_aggregate, dim3((unsigned)parts), dim3(AGG_THREADS), 0, stream, bin2, cap2, cursor2, tab,
                        spill, ctr);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, stream, cursor1, (uint64_t)kCoarse);
+    hipLaunchKernelGGL(k_zero_u32, dim3(4), dim3(256), 0, stream, cursor1, (uint64_t)kBinRep * kCoarse);
     return hipGetLastError();
 }
 
 hipError_t launch_drain_bins(uint64_t* bin1, uint64_t cap1, uint32_t* cursor1, Slot* tab, uint64_t cap,
                              SpillBuf spill, unsigned long long* ctr, hipStream_t stream) {
-    hipLaunchKernelGGL(k_drain_bins, dim3(grid_for((uint64_t)kCoarse * cap1, 256, kPersistBlocks)), dim3(256), 0,
-                       stream, bin1, cap1, cursor1, tab, make_geo(cap), spill, ctr);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, stream, cursor1, (uint64_t)kCoarse);
+    hipLaunchKernelGGL(k_drain_bins, dim3(grid_for((uint64_t)kBinRep * kCoarse * cap1, 256, kPersistBlocks)),
+                       dim3(256), 0, stream, bin1, cap1, cursor1, tab, make_geo(cap), spill, ctr);
+    hipLaunchKernelGGL(k_zero_u32, dim3(4), dim3(256), 0, stream, cursor1, (uint64_t)kBinRep * kCoarse);
     return hipGetLastError();
 }
 

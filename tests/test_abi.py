@@ -102,7 +102,7 @@ def test_tuning_validation(lib):
     assert (got.block, got.items, got.preagg_slots, got.mode, got.group_mpoints) == (512, 8, 2048, 2, 64)
     assert lib.raster_set_tuning(None) == 0
     assert lib.raster_get_tuning(ctypes.byref(got)) == 0
-    assert (got.block, got.items, got.preagg_slots, got.mode, got.group_mpoints) == (256, 4, 0, 0, 256)
+    assert (got.block, got.items, got.preagg_slots, got.mode, got.group_mpoints) == (256, 4, 0, 0, 512)
 
 
 def test_binding_refuses_cpu_tensors():
