@@ -55,6 +55,13 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return (1ull << lane_id()) - 1ull;
 }
 
+// Relaxed read of an LDS word that other lanes may be updating; unlike a
+// volatile read it compiles to an LDS load, not a generic one that also waits
+// for outstanding global loads.
+__device__ __forceinline__ uint64_t lds_load_relaxed(uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 __device__ __forceinline__ uint64_t ld_relaxed(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -119,7 +126,10 @@ template <> struct Pair<float> {
 template <typename T>
 __device__ __forceinline__ void load_point(const T* pts, int64_t i, double& x, double& y) {
     using V = typename Pair<T>::V;
-    const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(pts) + i);
+    // points are in device (global) memory: saying so lets the compiler use
+    // global loads, not generic ones, when the pointer came from memory
+    const __attribute__((address_space(1))) V* g = (const __attribute__((address_space(1))) V*)(pts);
+    const V v = __builtin_nontemporal_load(g + i);
     x = (double)v.x;  // FP32 widens exactly
     y = (double)v.y;
 }
@@ -312,7 +322,7 @@ __global__ void k_count_preagg(const T* __restrict__ pts, int64_t n, double scal
                 uint32_t pos = (slot_hash(k) >> 16) & (L - 1);
                 bool done = false;
                 for (int p = 0; p < 8 && !done; ++p) {
-                    uint64_t cur = *(volatile uint64_t*)&lkey[pos];
+                    uint64_t cur = lds_load_relaxed(&lkey[pos]);
                     if (cur == kEmptyKey) cur = atomicCAS(reinterpret_cast<unsigned long long*>(&lkey[pos]),
                                                           (unsigned long long)kEmptyKey, (unsigned long long)k);
                     if (cur == kEmptyKey || cur == k) {
@@ -582,7 +592,7 @@ constexpr uint32_t kPartSlots = 1u << kPartLog2;
 __device__ __forceinline__ int lds_add(uint64_t* lkey, uint32_t* lcnt, uint64_t key) {
     uint32_t pos = slot_hash(key) & (kPartSlots - 1);
     for (uint32_t p = 0; p < kMaxProbe; ++p) {
-        uint64_t cur = *(volatile uint64_t*)&lkey[pos];
+        uint64_t cur = lds_load_relaxed(&lkey[pos]);
         if (cur == kEmptyKey) {
             cur = atomicCAS(reinterpret_cast<unsigned long long*>(&lkey[pos]), (unsigned long long)kEmptyKey,
                             (unsigned long long)key);
@@ -1505,7 +1515,7 @@ __global__ void k_batch_count(JobView jv, const uint32_t* tile_prefix, Slot* tab
             if (L) {
                 uint32_t pos = (slot_hash(k) >> 16) & (L - 1);
                 for (int p = 0; p < 8 && !done; ++p) {
-                    uint64_t cur = *(volatile uint64_t*)&lkey[pos];
+                    uint64_t cur = lds_load_relaxed(&lkey[pos]);
                     if (cur == kEmptyKey)
                         cur = atomicCAS(reinterpret_cast<unsigned long long*>(&lkey[pos]),
                                         (unsigned long long)kEmptyKey, (unsigned long long)k);
