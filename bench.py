@@ -139,19 +139,33 @@ def bench_batched(raster, torch, n_jobs: int, reps: int):
             "speedup": out["plain_per_job"]["seconds"] / out["batched"]["seconds"]}
 
 
-def bench_served(raster, torch, duration_s: float, rate: float, slots: int):
+def bench_served(raster, torch, duration_s: float, rate: float, slots: int, stress_rate: float = 0.0,
+                 stress_s: float = 4.0):
     """Poisson arrivals replayed in real time: the continuous-batching server
-    against a plain FIFO worker issuing one call per job."""
-    import threading
-    import numpy as np
+    against a plain FIFO worker issuing one call per job; at the workload's
+    rate and, if stress_rate > 0, at a rate that queues jobs."""
     import synth
-    trace = synth.served_trace(seed=5, rate=rate, duration_s=duration_s)
     pool_n = 20_000_000
-    log(f"served: {len(trace)} jobs over {duration_s:g} s; pool of {pool_n} points")
+    log(f"served: pool of {pool_n} points")
     pool_h = synth.job_points(synth.JobSpec(seed=5, n=pool_n, precision=1, tau=5, mu=4))
     pool64 = torch.from_numpy(pool_h).to("cuda")
     pool32 = pool64.to(torch.float32)
     del pool_h
+    out = served_run(raster, torch, pool64, pool32, duration_s, rate, slots)
+    if stress_rate > 0:
+        out["stress"] = served_run(raster, torch, pool64, pool32, stress_s, stress_rate, slots)
+    del pool64, pool32
+    torch.cuda.empty_cache()
+    return out
+
+
+def served_run(raster, torch, pool64, pool32, duration_s: float, rate: float, slots: int):
+    import threading
+    import numpy as np
+    import synth
+    trace = synth.served_trace(seed=5, rate=rate, duration_s=duration_s)
+    pool_n = pool64.shape[0]
+    log(f"served: {len(trace)} jobs over {duration_s:g} s at {rate:g} jobs/s")
 
     def points(j, sp):
         off = (j * 7919) % max(1, pool_n - sp.n + 1)
@@ -235,8 +249,7 @@ def bench_served(raster, torch, duration_s: float, rate: float, slots: int):
         lat, span = fn()
         out[name] = {"p50_ms": 1e3 * pct(lat, 50), "p99_ms": 1e3 * pct(lat, 99), "mean_ms": 1e3 * float(np.mean(lat)),
                      "points_per_s": total / span, "makespan_s": span}
-    del views, pool64, pool32
-    torch.cuda.empty_cache()
+    del views
     return {"workload": f"Poisson {rate:g} jobs/s for {duration_s:g} s ({len(trace)} jobs), n log-uniform in "
                         "[1e3, 2e7] (windows of one 20M-point set shaped like workload 1), FP32/FP64 per job, "
                         "p/tau/mu drawn per job, budget 64 GiB",
@@ -261,6 +274,8 @@ def main():
     ap.add_argument("--served-seconds", type=float, default=10.0)
     ap.add_argument("--served-rate", type=float, default=200.0)
     ap.add_argument("--served-slots", type=int, default=4)
+    ap.add_argument("--served-stress-rate", type=float, default=2000.0,
+                    help="second served run at this rate (jobs/s, 4 s), where jobs queue; 0 skips it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (3 times), to scale HBM counters")
     args = ap.parse_args()
@@ -375,7 +390,7 @@ def main():
     torch.cuda.empty_cache()
     line["batched"] = None if args.no_batched else bench_batched(raster, torch, 256, 3)
     line["served"] = None if args.no_served else bench_served(raster, torch, args.served_seconds, args.served_rate,
-                                                              args.served_slots)
+                                                              args.served_slots, args.served_stress_rate)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one core)")
         line["cpu_baseline"] = cpu_baseline(host, args.cpu_strip, precision, tau, mu)

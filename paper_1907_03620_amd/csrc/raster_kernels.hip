@@ -62,6 +62,26 @@ __device__ __forceinline__ uint64_t lds_load_relaxed(uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin by index, and each XCD
+// has its own L2.  For a pass over n items whose random accesses stay near
+// the item (table slices and union-find words of neighbouring tiles), each
+// XCD takes one contiguous eighth of [0, n) and its workgroups stride over
+// it, so every slice is fetched into one L2 only.  Covers [0, n) exactly once
+// for any grid; a grid that is not a multiple of 8 falls back to a plain
+// grid stride.
+constexpr uint32_t kXcds = 8;
+struct XcdSpan {
+    uint64_t lo, hi;      // this XCD's items
+    uint64_t first, step; // this thread's first item and stride
+};
+__device__ __forceinline__ XcdSpan xcd_span(uint64_t n) {
+    if (gridDim.x % kXcds != 0)
+        return {0, n, blockIdx.x * (uint64_t)blockDim.x + threadIdx.x, (uint64_t)gridDim.x * blockDim.x};
+    const uint32_t x = blockIdx.x % kXcds, w = blockIdx.x / kXcds;
+    const uint64_t lo = n * x / kXcds, hi = n * (x + 1) / kXcds;
+    return {lo, hi, lo + (uint64_t)w * blockDim.x + threadIdx.x, (uint64_t)(gridDim.x / kXcds) * blockDim.x};
+}
+
 __device__ __forceinline__ uint64_t ld_relaxed(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -1224,8 +1244,8 @@ __global__ void k_link(const Slot* tab, JobView jv, const uint64_t* s_key, uint3
     const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
     const bool multi = jv.part_job != nullptr;
     bool bad = false;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < s;
-         i += (uint64_t)gridDim.x * blockDim.x) {
+    const XcdSpan span = xcd_span(s);
+    for (uint64_t i = span.first; i < span.hi; i += span.step) {
         const JobInfo& J = jv.jobs[multi ? jv.s_job[i] : 0u];
         const Slot* jt = tab + J.slot_base;
         const Geo g = make_geo(J.cap);
@@ -1294,8 +1314,8 @@ __global__ void k_link(const Slot* tab, JobView jv, const uint64_t* s_key, uint3
 __global__ void k_jump(uint32_t* parent, unsigned long long* ctr) {
     const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
     bool bad = false;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < s;
-         i += (uint64_t)gridDim.x * blockDim.x)
+    const XcdSpan span = xcd_span(s);
+    for (uint64_t i = span.first; i < span.hi; i += span.step)
         parent[i] = uf_root_cached(parent, (uint32_t)i, s, bad);
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
 }
@@ -1303,8 +1323,8 @@ __global__ void k_jump(uint32_t* parent, unsigned long long* ctr) {
 __global__ void k_merge(const uint32_t* nbr, const uint64_t* s_key, uint32_t* parent, unsigned long long* ctr) {
     const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
     bool bad = false;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < s;
-         i += (uint64_t)gridDim.x * blockDim.x) {
+    const XcdSpan span = xcd_span(s);
+    for (uint64_t i = span.first; i < span.hi; i += span.step) {
         const uint4 rec = reinterpret_cast<const uint4*>(nbr)[i];
         const uint32_t j[4] = {rec.x, rec.y, rec.z, rec.w};
         // After the jump pass parents are roots; a tile whose recorded
@@ -1331,8 +1351,10 @@ __global__ void k_merge(const uint32_t* nbr, const uint64_t* s_key, uint32_t* pa
 __global__ void k_compress(JobView jv, uint32_t* parent, uint32_t* root, uint32_t* size, unsigned long long* ctr) {
     const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
     const bool multi = jv.part_job != nullptr;
+    // a plain grid stride: the size counters take memory-side atomics, which
+    // run faster spread over all of [0, s) than gathered per XCD
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t s_round = ((uint64_t)s + 63) / 64 * 64;
+    const uint64_t s_round = ((uint64_t)s + 63) / 64 * 64;  // whole waves run the same trip count
     bool bad = false;
     uint32_t roots = 0;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < s_round; i += stride) {
@@ -1694,7 +1716,7 @@ hipError_t launch_threshold(Slot* tab, const JobView& jv, uint64_t* s_key, uint3
 hipError_t launch_agglomerate(const Slot* tab, const JobView& jv, const uint64_t* s_key, uint32_t* parent,
                               uint32_t* nbr, uint32_t* size, uint64_t s_max, unsigned long long* ctr,
                               hipStream_t stream) {
-    const int grid = grid_for(s_max, 256, kPersistBlocks);
+    const int grid = (grid_for(s_max, 256, kPersistBlocks) + kXcds - 1) / kXcds * kXcds;
     hipLaunchKernelGGL(k_link, dim3(grid), dim3(256), 0, stream, tab, jv, s_key, parent, nbr, ctr);
     hipLaunchKernelGGL(k_jump, dim3(grid), dim3(256), 0, stream, parent, ctr);
     hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, stream, nbr, s_key, parent, ctr);

@@ -531,6 +531,9 @@ static size_t job_bytes(const raster_job& j) {
 
 static constexpr size_t kMaxBatchJobs = 128;
 static constexpr uint64_t kMaxBatchPoints = 256ull * 1000 * 1000;
+// Jobs of at least this many points run alone: their passes already fill the
+// GPU, and fusing them would hold small jobs queued behind them.
+static constexpr uint64_t kSoloPoints = 2ull * 1000 * 1000;
 
 static void server_worker(raster_server* s, int slot) {
     (void)hipSetDevice(s->device);
@@ -545,15 +548,19 @@ static void server_worker(raster_server* s, int slot) {
                        (s->stop && s->queue.empty());
             });
             if (s->queue.empty()) return;  // stopping and drained
+            // a large job runs alone; small jobs waiting together share one
+            // fused batch
             uint64_t pts = 0;
             while (!s->queue.empty() && batch.size() < kMaxBatchJobs) {
                 ServerJob* j = s->queue.front();
                 if (j->bytes > s->budget - s->in_flight - bytes) break;
-                if (!batch.empty() && pts + (uint64_t)j->job.n > kMaxBatchPoints) break;
+                const bool large = (uint64_t)j->job.n >= kSoloPoints;
+                if (!batch.empty() && (large || pts + (uint64_t)j->job.n > kMaxBatchPoints)) break;
                 batch.push_back(j);
                 bytes += j->bytes;
                 pts += (uint64_t)j->job.n;
                 s->queue.pop_front();
+                if (large) break;
             }
             s->in_flight += bytes;
         }
@@ -563,7 +570,15 @@ static void server_worker(raster_server* s, int slot) {
         for (size_t i = 0; i < batch.size(); ++i) jv[i] = batch[i]->job;
         raster_status st = RASTER_OK;
         (void)eng.init();
-        st = run_batch(eng, jv.data(), (int32_t)jv.size(), eng.bs, outs.data());
+        if (batch.size() == 1) {
+            // nothing to fuse with: the plain path has the least fixed cost
+            const raster_job& j = jv[0];
+            double sc = j.scale;
+            if (!(sc > 0.0)) scale_for_precision(j.precision, &sc);
+            st = raster_cluster_scaled(j.d_points, j.n, j.dt, sc, j.tau, j.mu, eng.bs, &outs[0]);
+        } else {
+            st = run_batch(eng, jv.data(), (int32_t)jv.size(), eng.bs, outs.data());
+        }
         std::string err = st == RASTER_OK ? std::string() : g_last_error;
         if (st != RASTER_OK && batch.size() > 1) {
             // isolate the failing job(s): redo each job alone
