@@ -581,7 +581,7 @@ raster_status TableRun::finish(raster_result** out) {
     e = launch_zero_u64((uint64_t*)ctr + C_DISTINCT, C_COUNT_ - C_DISTINCT, stream);
     if (e == hipSuccess) e = launch_threshold(tab, jv, s_key, s_count, size, partials, ctr, stream);
     if (e == hipSuccess) e = hipEventRecord(ev[2], stream);
-    if (e == hipSuccess) e = launch_agglomerate(tab, jv, s_key, parent, nbr, size, m, ctr, stream);
+    if (e == hipSuccess) e = launch_agglomerate(tab, cap, jv, s_key, parent, nbr, size, m, ctr, stream);
     if (e == hipSuccess) e = hipEventRecord(ev[3], stream);
     if (e == hipSuccess)
         e = launch_filter(jv, s_key, s_count, nbr, size, r->kx, r->ky, r->count, r->label, nullptr, partials, ctr,

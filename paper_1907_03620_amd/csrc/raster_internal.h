@@ -213,9 +213,9 @@ hipError_t launch_threshold(Slot* tab, const JobView& jv, uint64_t* s_key, uint3
 // size[root] counts members up to the job's mu (size[root] >= mu exactly when
 // the component has at least mu tiles).  parent is scratch; nbr is scratch of
 // 4 words per significant tile, 16-byte aligned.
-hipError_t launch_agglomerate(const Slot* tab, const JobView& jv, const uint64_t* s_key, uint32_t* parent,
-                              uint32_t* nbr, uint32_t* size, uint64_t s_max, unsigned long long* ctr,
-                              hipStream_t stream);
+hipError_t launch_agglomerate(const Slot* tab, uint64_t slots_max, const JobView& jv, const uint64_t* s_key,
+                              uint32_t* parent, uint32_t* nbr, uint32_t* size, uint64_t s_max,
+                              unsigned long long* ctr, hipStream_t stream);
 
 // mu filter and output compaction: rows of kept components in compact order
 // (out_job gets each row's job for several jobs).

@@ -1239,71 +1239,146 @@ __device__ __forceinline__ void uf_unite(uint32_t* parent, const uint64_t* key, 
     bad = true;
 }
 
-__global__ void k_link(const Slot* tab, JobView jv, const uint64_t* s_key, uint32_t* parent, uint32_t* nbr,
-                       unsigned long long* ctr) {
+// Link pass: parent = the significant backward neighbour with the smallest
+// key (or the tile itself), nbr = the compact indices of all significant
+// backward neighbours ((x-1, y-1), (x-1, y), (x-1, y+1), (x, y-1); with the
+// forward ones seen from the other side they cover all eight).  One
+// workgroup per table partition: the slice is read into LDS once, and with
+// super-tile placement most neighbours share the tile's partition and are
+// probed there; only the others are probed in the device table.
+constexpr int LINK_THREADS = 512;
+
+__global__ __launch_bounds__(LINK_THREADS) void k_link_part(const Slot* tab, JobView jv, uint32_t* parent,
+                                                            uint32_t* nbr, unsigned long long* ctr) {
+    __shared__ uint64_t lkey[kPartSlots];
+    __shared__ uint32_t laux[kPartSlots];
+    __shared__ uint16_t list[kPartSlots];
+    __shared__ uint32_t nlist;
     const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
     const bool multi = jv.part_job != nullptr;
+    const uint64_t parts = (jv.dims->slots + kPartSlots - 1) >> kPartLog2;
     bool bad = false;
-    const XcdSpan span = xcd_span(s);
-    for (uint64_t i = span.first; i < span.hi; i += span.step) {
-        const JobInfo& J = jv.jobs[multi ? jv.s_job[i] : 0u];
-        const Slot* jt = tab + J.slot_base;
+    for (uint64_t p = blockIdx.x; p < parts; p += gridDim.x) {
+        const JobInfo& J = jv.jobs[multi ? jv.part_job[p] : 0u];
         const Geo g = make_geo(J.cap);
-        const uint64_t key = s_key[i];
-        const uint32_t bx = (uint32_t)(key >> 32);
-        const uint32_t by = (uint32_t)key;
-        // valid biased coordinates lie in [2, 2^32 - 2]
-        const bool left = bx > 2u;
-        const bool down = by > 2u;
-        const bool up = by < 0xFFFFFFFEu;
-        uint64_t nk[4];
-        bool want[4];
-        nk[0] = ((uint64_t)(bx - 1) << 32) | (uint32_t)(by - 1);
-        want[0] = left && down;
-        nk[1] = ((uint64_t)(bx - 1) << 32) | by;
-        want[1] = left;
-        nk[2] = ((uint64_t)(bx - 1) << 32) | (uint32_t)(by + 1);
-        want[2] = left && up;
-        nk[3] = ((uint64_t)bx << 32) | (uint32_t)(by - 1);
-        want[3] = down;
-        uint64_t pos[4];
-        Slot v[4];
+        const uint32_t psize = (uint32_t)min<uint64_t>(J.cap, kPartSlots);  // a power of two
+        const uint64_t base = p << kPartLog2;
+        if (threadIdx.x == 0) nlist = 0;
+        __syncthreads();  // also orders the previous partition's LDS reads before the overwrite
+        // slice into LDS, all loads in flight at once
+        constexpr int PER = (int)kPartSlots / LINK_THREADS;
+        {
+            Slot v[PER];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            pos[q] = home_slot(nk[q], g);
-            if (want[q]) v[q] = jt[pos[q]];
-        }
-        uint32_t best = (uint32_t)i;
-        uint64_t best_key = key;
-        uint32_t j[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            j[q] = kNoNeighbour;
-            if (!want[q]) continue;
-            uint32_t steps = 1;
-            while (v[q].key != nk[q] && v[q].key != kEmptyKey && steps < kMaxProbe) {
-                pos[q] = next_slot(pos[q], g);
-                v[q] = jt[pos[q]];
-                ++steps;
+            for (int k = 0; k < PER; ++k) {
+                const uint32_t u = k * LINK_THREADS + threadIdx.x;
+                if (u < psize) v[k] = tab[base + u];
             }
-            if (v[q].key == nk[q] && v[q].aux != kNotSignificant) {
-                j[q] = v[q].aux;
-                if (j[q] >= s) {
-                    bad = true;
-                    j[q] = kNoNeighbour;
-                } else if (nk[q] < best_key) {
-                    best_key = nk[q];
-                    best = j[q];
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const uint32_t u = k * LINK_THREADS + threadIdx.x;
+                if (u < psize) {
+                    lkey[u] = v[k].key;
+                    laux[u] = v[k].aux;
                 }
             }
         }
-        parent[i] = best;
-        uint4 rec;
-        rec.x = j[0];
-        rec.y = j[1];
-        rec.z = j[2];
-        rec.w = j[3];
-        reinterpret_cast<uint4*>(nbr)[i] = rec;
+        // local indices of the significant slots into list
+        for (uint32_t u0 = 0; u0 < psize; u0 += LINK_THREADS) {
+            const uint32_t u = u0 + threadIdx.x;
+            const bool sig = u < psize && lkey[u] != kEmptyKey && laux[u] != kNotSignificant;
+            const uint64_t b = __ballot(sig);
+            uint32_t wbase = 0;
+            if (lane_id() == 0 && b) wbase = atomicAdd(&nlist, (uint32_t)__popcll(b));
+            wbase = __shfl(wbase, 0);
+            if (sig) list[wbase + __popcll(b & lanemask_lt())] = (uint16_t)u;
+        }
+        __syncthreads();
+        const uint32_t nl = nlist;
+        const Slot* jt = tab + J.slot_base;
+        for (uint32_t t = threadIdx.x; t < nl; t += LINK_THREADS) {
+            const uint32_t u = list[t];
+            const uint64_t key = lkey[u];
+            const uint32_t i = laux[u];
+            if (i >= s) {
+                bad = true;
+                continue;
+            }
+            const uint32_t bx = (uint32_t)(key >> 32);
+            const uint32_t by = (uint32_t)key;
+            // valid biased coordinates lie in [2, 2^32 - 2]
+            const bool left = bx > 2u;
+            const bool down = by > 2u;
+            const bool up = by < 0xFFFFFFFEu;
+            uint64_t nk[4];
+            bool want[4];
+            nk[0] = ((uint64_t)(bx - 1) << 32) | (uint32_t)(by - 1);
+            want[0] = left && down;
+            nk[1] = ((uint64_t)(bx - 1) << 32) | by;
+            want[1] = left;
+            nk[2] = ((uint64_t)(bx - 1) << 32) | (uint32_t)(by + 1);
+            want[2] = left && up;
+            nk[3] = ((uint64_t)bx << 32) | (uint32_t)(by - 1);
+            want[3] = down;
+            // first probes: device-table loads for the other partitions are
+            // issued together, LDS probes need no wait
+            uint64_t pos[4];
+            bool local[4];
+            Slot v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                pos[q] = home_slot(nk[q], g);
+                local[q] = ((J.slot_base + pos[q]) >> kPartLog2) == p;
+                if (want[q] && !local[q]) v[q] = jt[pos[q]];
+            }
+            uint32_t best = i;
+            uint64_t best_key = key;
+            uint32_t j[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                j[q] = kNoNeighbour;
+                if (!want[q]) continue;
+                uint32_t aux = kNotSignificant;
+                if (local[q]) {
+                    uint32_t lp = (uint32_t)(J.slot_base + pos[q] - base);
+                    for (uint32_t step = 0; step < kMaxProbe; ++step) {
+                        const uint64_t cur = lkey[lp];
+                        if (cur == nk[q]) {
+                            aux = laux[lp];
+                            break;
+                        }
+                        if (cur == kEmptyKey) break;
+                        lp = (lp + 1) & (psize - 1);
+                    }
+                } else {
+                    uint32_t steps = 1;
+                    while (v[q].key != nk[q] && v[q].key != kEmptyKey && steps < kMaxProbe) {
+                        pos[q] = next_slot(pos[q], g);
+                        v[q] = jt[pos[q]];
+                        ++steps;
+                    }
+                    if (v[q].key == nk[q]) aux = v[q].aux;
+                }
+                if (aux != kNotSignificant) {
+                    if (aux >= s) {
+                        bad = true;
+                    } else {
+                        j[q] = aux;
+                        if (nk[q] < best_key) {
+                            best_key = nk[q];
+                            best = aux;
+                        }
+                    }
+                }
+            }
+            parent[i] = best;
+            uint4 rec;
+            rec.x = j[0];
+            rec.y = j[1];
+            rec.z = j[2];
+            rec.w = j[3];
+            reinterpret_cast<uint4*>(nbr)[i] = rec;
+        }
     }
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
 }
@@ -1713,11 +1788,12 @@ hipError_t launch_threshold(Slot* tab, const JobView& jv, uint64_t* s_key, uint3
     return hipGetLastError();
 }
 
-hipError_t launch_agglomerate(const Slot* tab, const JobView& jv, const uint64_t* s_key, uint32_t* parent,
-                              uint32_t* nbr, uint32_t* size, uint64_t s_max, unsigned long long* ctr,
-                              hipStream_t stream) {
+hipError_t launch_agglomerate(const Slot* tab, uint64_t slots_max, const JobView& jv, const uint64_t* s_key,
+                              uint32_t* parent, uint32_t* nbr, uint32_t* size, uint64_t s_max,
+                              unsigned long long* ctr, hipStream_t stream) {
     const int grid = (grid_for(s_max, 256, kPersistBlocks) + kXcds - 1) / kXcds * kXcds;
-    hipLaunchKernelGGL(k_link, dim3(grid), dim3(256), 0, stream, tab, jv, s_key, parent, nbr, ctr);
+    const int link_grid = grid_for((slots_max + kPartSlots - 1) >> kPartLog2, 1, 8192);
+    hipLaunchKernelGGL(k_link_part, dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, jv, parent, nbr, ctr);
     hipLaunchKernelGGL(k_jump, dim3(grid), dim3(256), 0, stream, parent, ctr);
     hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, stream, nbr, s_key, parent, ctr);
     // the neighbour lists are dead after the merge pass; their first s words

@@ -210,7 +210,7 @@ struct BatchEngine {
             if (e == hipSuccess) e = launch_batch_count(jv, tile_prefix, arena, kernel_tuning(tu), 4096, bs);
         }
         if (e == hipSuccess) e = launch_threshold(arena, jv, s_key, s_count, size, partials, ctr, bs);
-        if (e == hipSuccess) e = launch_agglomerate(arena, jv, s_key, parent, nbr, size, s_cap, ctr, bs);
+        if (e == hipSuccess) e = launch_agglomerate(arena, arena_cap, jv, s_key, parent, nbr, size, s_cap, ctr, bs);
         if (e == hipSuccess)
             e = launch_filter(jv, s_key, s_count, nbr, size, o_kx, o_ky, o_count, o_label, o_job, partials, ctr, bs);
         uint32_t* s_start = bounds;
