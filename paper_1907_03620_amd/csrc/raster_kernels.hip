@@ -534,15 +534,22 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_points(const T* __restrict_
     uint16_t bucket[BIN_ITEMS];
     uint32_t valid = 0;
     bool bad = false;
+    // all loads first, so that they are in flight together
+    double x[BIN_ITEMS], y[BIN_ITEMS];
+#pragma unroll
+    for (int j = 0; j < BIN_ITEMS; ++j) {
+        const int64_t i = base + (int64_t)j * BIN_THREADS;
+        x[j] = 0.0;
+        y[j] = 0.0;
+        if (i < n) load_point(pts, i, x[j], y[j]);
+    }
 #pragma unroll
     for (int j = 0; j < BIN_ITEMS; ++j) {
         const int64_t i = base + (int64_t)j * BIN_THREADS;
         key[j] = 0;
         bucket[j] = 0;
         if (i < n) {
-            double x, y;
-            load_point(pts, i, x, y);
-            if (tile_key(x, y, scale, key[j])) {
+            if (tile_key(x[j], y[j], scale, key[j])) {
                 valid |= 1u << j;
                 bucket[j] = (uint16_t)bucket_of(key[j], kCoarseLog2, kCoarse);
             } else {
@@ -583,13 +590,18 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_keys(const uint64_t* __rest
     uint16_t bucket[BIN_ITEMS];
     uint32_t valid = 0;
     const uint64_t* src = bin1 + (uint64_t)l1 * cap1;
+    // all loads first, so that they are in flight together
 #pragma unroll
     for (int j = 0; j < BIN_ITEMS; ++j) {
         const uint64_t i = start + (uint64_t)j * BIN_THREADS + threadIdx.x;
         key[j] = 0;
+        if (i < cnt) key[j] = __builtin_nontemporal_load(src + i);
+    }
+#pragma unroll
+    for (int j = 0; j < BIN_ITEMS; ++j) {
+        const uint64_t i = start + (uint64_t)j * BIN_THREADS + threadIdx.x;
         bucket[j] = 0;
         if (i < cnt) {
-            key[j] = __builtin_nontemporal_load(src + i);
             bucket[j] = (uint16_t)bucket_of(key[j], g.p_log2, nb);
             valid |= 1u << j;
         }
@@ -609,10 +621,12 @@ constexpr uint32_t kPartSlots = 1u << kPartLog2;
 
 // LDS version of table_add over one partition slice (same probe sequence as
 // the device table, so slots stay where a device-table probe looks for them).
-__device__ __forceinline__ int lds_add(uint64_t* lkey, uint32_t* lcnt, uint64_t key) {
-    uint32_t pos = slot_hash(key) & (kPartSlots - 1);
+// Continues from position pos, whose word was read as cur (possibly stale:
+// a stale empty only sends the key through the compare-and-swap).
+__device__ __forceinline__ int lds_add_from(uint64_t* lkey, uint32_t* lcnt, uint64_t key, uint32_t pos,
+                                            uint64_t cur) {
     for (uint32_t p = 0; p < kMaxProbe; ++p) {
-        uint64_t cur = lds_load_relaxed(&lkey[pos]);
+        if (p) cur = lds_load_relaxed(&lkey[pos]);
         if (cur == kEmptyKey) {
             cur = atomicCAS(reinterpret_cast<unsigned long long*>(&lkey[pos]), (unsigned long long)kEmptyKey,
                             (unsigned long long)key);
@@ -705,12 +719,25 @@ __device__ __forceinline__ void aggregate_partition(const PartLists<NL>& L, Slot
                 k[u] = __builtin_nontemporal_load(L.src + li * L.lstride + (q - lo));
             }
         }
+        // home-slot reads of all keys together; most keys find themselves
+        // there, and only the others walk the probe sequence
+        uint32_t pos[AGG_BATCH];
+        uint64_t cur[AGG_BATCH];
+#pragma unroll
+        for (int u = 0; u < AGG_BATCH; ++u) {
+            pos[u] = slot_hash(k[u]) & (kPartSlots - 1);
+            cur[u] = k[u] != kEmptyKey ? lds_load_relaxed(&lkey[pos[u]]) : kEmptyKey;
+        }
 #pragma unroll
         for (int u = 0; u < AGG_BATCH; ++u) {
             int r = ADD_FOUND;
             if (k[u] != kEmptyKey) {
-                r = lds_add(lkey, lcnt, k[u]);
-                fresh += (r == ADD_NEW);
+                if (cur[u] == k[u]) {
+                    atomicAdd(&lcnt[pos[u]], 1u);
+                } else {
+                    r = lds_add_from(lkey, lcnt, k[u], pos[u], cur[u]);
+                    fresh += (r == ADD_NEW);
+                }
             }
             spill_push(sp, spill_ctr, r == ADD_FULL, k[u], 1u);
         }
