@@ -1036,6 +1036,22 @@ __device__ __forceinline__ uint32_t job_of_slot(const JobView& jv, bool multi, u
     return multi ? jv.part_job[slot >> kPartLog2] : 0u;
 }
 
+// Key and count of the slots of one scan tile (t0 < hi).  The loads are
+// unconditional -- items past hi re-read slot hi - 1 and are then marked
+// empty -- so that all of them are in flight together.
+__device__ __forceinline__ void load_slots(const Slot* tab, uint64_t t0, uint64_t hi, uint64_t (&key)[SCAN_ITEMS],
+                                           uint32_t (&cnt)[SCAN_ITEMS]) {
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        const uint64_t i = min(t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x, hi - 1);
+        key[j] = tab[i].key;
+        cnt[j] = tab[i].count;
+    }
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j)
+        if (t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x >= hi) key[j] = kEmptyKey;
+}
+
 __global__ __launch_bounds__(SCAN_THREADS) void k_threshold_count(const Slot* tab, JobView jv, uint32_t* partials,
                                                                   unsigned long long* ctr) {
     __shared__ unsigned long long red[SCAN_WAVES];
@@ -1048,16 +1064,15 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_threshold_count(const Slot* ta
         const uint32_t job = job_of_slot(jv, multi, t0);
         const uint32_t tau = jv.jobs[job].tau;
         unsigned long long occ_t = 0, sum_t = 0;
+        uint64_t key[SCAN_ITEMS];
+        uint32_t cnt[SCAN_ITEMS];
+        load_slots(tab, t0, hi, key, cnt);
 #pragma unroll
         for (int j = 0; j < SCAN_ITEMS; ++j) {
-            const uint64_t i = t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x;
-            if (i < hi) {
-                const Slot v = tab[i];
-                if (v.key != kEmptyKey) {
-                    occ_t += 1;
-                    sum_t += v.count;
-                    sig += (v.count >= tau);
-                }
+            if (key[j] != kEmptyKey) {
+                occ_t += 1;
+                sum_t += cnt[j];
+                sig += (cnt[j] >= tau);
             }
         }
         occ += occ_t;
@@ -1096,18 +1111,10 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_threshold_scatter(Slot* tab, J
         uint32_t bits = 0;
         uint64_t key[SCAN_ITEMS];
         uint32_t cnt[SCAN_ITEMS];
+        load_slots(tab, t0, hi, key, cnt);
 #pragma unroll
-        for (int j = 0; j < SCAN_ITEMS; ++j) {
-            const uint64_t i = t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x;
-            key[j] = kEmptyKey;
-            cnt[j] = 0;
-            if (i < hi) {
-                const Slot v = tab[i];
-                key[j] = v.key;
-                cnt[j] = v.count;
-                if (v.key != kEmptyKey && v.count >= tau) bits |= 1u << j;
-            }
-        }
+        for (int j = 0; j < SCAN_ITEMS; ++j)
+            if (key[j] != kEmptyKey && cnt[j] >= tau) bits |= 1u << j;
         uint32_t pos[SCAN_ITEMS];
         const uint32_t total = tile_positions(bits, pos, ts);
 #pragma unroll
@@ -1474,6 +1481,27 @@ __global__ void k_compress(JobView jv, uint32_t* parent, uint32_t* root, uint32_
 
 // ---- mu filter (Algorithm 1: keep clusters of at least mu tiles) -----------
 
+// Root, mu and root size of the items of one scan tile (t0 < hi <= s).  Each
+// round of loads is unconditional (indices clamped, results masked) so that
+// it is in flight for all items at once.  Items past hi read as root s.
+__device__ __forceinline__ void filter_items(const JobView& jv, bool multi, uint32_t mu0, const uint32_t* root,
+                                             const uint32_t* size, uint64_t s, uint64_t t0, uint64_t hi,
+                                             uint32_t (&rt)[SCAN_ITEMS], uint32_t (&mu)[SCAN_ITEMS],
+                                             uint32_t (&sz)[SCAN_ITEMS]) {
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        const uint64_t i = min(t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x, hi - 1);
+        rt[j] = root[i];
+        mu[j] = multi ? jv.s_job[i] : mu0;  // the job id, for now
+    }
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        if (t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x >= hi) rt[j] = (uint32_t)s;
+        sz[j] = size[min((uint64_t)rt[j], s - 1)];
+        if (multi) mu[j] = jv.jobs[mu[j]].mu;
+    }
+}
+
 __global__ __launch_bounds__(SCAN_THREADS) void k_filter_count(JobView jv, const uint32_t* root, const uint32_t* size,
                                                                uint32_t* partials, unsigned long long* ctr) {
     __shared__ unsigned long long red[SCAN_WAVES];
@@ -1483,18 +1511,17 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_filter_count(JobView jv, const
     uint64_t lo, hi;
     block_range(s, lo, hi);
     unsigned long long keep = 0, kept_roots = 0;
-    for (uint64_t t0 = lo; t0 < hi; t0 += SCAN_TILE)
+    for (uint64_t t0 = lo; t0 < hi; t0 += SCAN_TILE) {
+        uint32_t rt[SCAN_ITEMS], mu[SCAN_ITEMS], sz[SCAN_ITEMS];
+        filter_items(jv, multi, mu0, root, size, s, t0, hi, rt, mu, sz);
 #pragma unroll
         for (int j = 0; j < SCAN_ITEMS; ++j) {
             const uint64_t i = t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x;
-            if (i < hi) {
-                const uint32_t r = root[i];
-                const uint32_t mu = multi ? jv.jobs[jv.s_job[i]].mu : mu0;
-                const bool k = r < s && size[r] >= mu;
-                keep += k;
-                kept_roots += (k && r == (uint32_t)i);
-            }
+            const bool k = i < hi && rt[j] < s && sz[j] >= mu[j];
+            keep += k;
+            kept_roots += (k && rt[j] == (uint32_t)i);
         }
+    }
     keep = block_sum(keep, red);
     kept_roots = block_sum(kept_roots, red);
     if (threadIdx.x == 0) {
@@ -1518,29 +1545,35 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_filter_scatter(JobView jv, con
     uint64_t run = offsets[blockIdx.x];
     for (uint64_t t0 = lo; t0 < hi; t0 += SCAN_TILE) {
         uint32_t bits = 0;
-        uint32_t rt[SCAN_ITEMS];
+        uint32_t rt[SCAN_ITEMS], mu[SCAN_ITEMS], sz[SCAN_ITEMS];
+        filter_items(jv, multi, mu0, root, size, s, t0, hi, rt, mu, sz);
 #pragma unroll
         for (int j = 0; j < SCAN_ITEMS; ++j) {
             const uint64_t i = t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x;
-            rt[j] = 0;
-            if (i < hi) {
-                rt[j] = root[i];
-                const uint32_t mu = multi ? jv.jobs[jv.s_job[i]].mu : mu0;
-                if (rt[j] < s && size[rt[j]] >= mu) bits |= 1u << j;
-            }
+            if (i < hi && rt[j] < s && sz[j] >= mu[j]) bits |= 1u << j;
         }
         uint32_t pos[SCAN_ITEMS];
         const uint32_t total = tile_positions(bits, pos, ts);
+        // row data of all items loaded together (indices clamped), then
+        // the kept rows written
+        uint64_t key[SCAN_ITEMS], label[SCAN_ITEMS];
+        uint32_t cnt[SCAN_ITEMS];
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
+            const uint64_t i = min(t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x, hi - 1);
+            key[j] = s_key[i];
+            cnt[j] = s_count[i];
+            label[j] = s_key[min((uint64_t)rt[j], s - 1)];
+        }
 #pragma unroll
         for (int j = 0; j < SCAN_ITEMS; ++j) {
             if (!(bits & (1u << j))) continue;
             const uint64_t i = t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x;
             const uint64_t p = run + pos[j];
-            const uint64_t key = s_key[i];
-            out_kx[p] = (int32_t)((uint32_t)(key >> 32) - 0x80000000u);
-            out_ky[p] = (int32_t)((uint32_t)key - 0x80000000u);
-            out_count[p] = s_count[i];
-            out_label[p] = s_key[rt[j]];
+            out_kx[p] = (int32_t)((uint32_t)(key[j] >> 32) - 0x80000000u);
+            out_ky[p] = (int32_t)((uint32_t)key[j] - 0x80000000u);
+            out_count[p] = cnt[j];
+            out_label[p] = label[j];
             if (multi) out_job[p] = jv.s_job[i];
         }
         run += total;
