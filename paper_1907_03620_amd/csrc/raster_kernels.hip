@@ -1356,14 +1356,18 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_part(const Slot* tab, Job
             want[3] = down;
             // first probes: device-table loads for the other partitions are
             // issued together, LDS probes need no wait
+            // (home slot and the next one: a probe walk mostly ends there)
             uint64_t pos[4];
             bool local[4];
-            Slot v[4];
+            Slot v[4], w[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 pos[q] = home_slot(nk[q], g);
                 local[q] = ((J.slot_base + pos[q]) >> kPartLog2) == p;
-                if (want[q] && !local[q]) v[q] = jt[pos[q]];
+                if (want[q] && !local[q]) {
+                    v[q] = jt[pos[q]];
+                    w[q] = jt[next_slot(pos[q], g)];
+                }
             }
             uint32_t best = i;
             uint64_t best_key = key;
@@ -1385,11 +1389,16 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_part(const Slot* tab, Job
                         lp = (lp + 1) & (psize - 1);
                     }
                 } else {
-                    uint32_t steps = 1;
-                    while (v[q].key != nk[q] && v[q].key != kEmptyKey && steps < kMaxProbe) {
+                    if (v[q].key != nk[q] && v[q].key != kEmptyKey) {
+                        // second probe already loaded
                         pos[q] = next_slot(pos[q], g);
-                        v[q] = jt[pos[q]];
-                        ++steps;
+                        v[q] = w[q];
+                        uint32_t steps = 2;
+                        while (v[q].key != nk[q] && v[q].key != kEmptyKey && steps < kMaxProbe) {
+                            pos[q] = next_slot(pos[q], g);
+                            v[q] = jt[pos[q]];
+                            ++steps;
+                        }
                     }
                     if (v[q].key == nk[q]) aux = v[q].aux;
                 }
