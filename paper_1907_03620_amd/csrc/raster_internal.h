@@ -109,7 +109,8 @@ struct JobInfo {
     uint32_t part_base;   // slot_base / 4096: first partition of the job
     uint32_t cbase;       // binned batches: first coarse bucket of the job
     uint32_t cshift;      // binned batches: log2 partitions per coarse bucket
-    uint32_t pad;
+    uint32_t cap2;        // binned batches: keys per partition list of the job
+    uint64_t bin2_base;   // binned batches: first key of the job's partition lists
 };
 
 // Sizes read from device memory, so that a captured graph can be replayed
@@ -119,7 +120,7 @@ struct Dims {
     uint32_t njobs;
     uint32_t tiles;    // point tiles of the batched counting launch
     uint64_t cap1;     // binned batches: keys per coarse bucket
-    uint64_t cap2;     // binned batches: keys per partition bucket
+    uint64_t cap2;     // unused (partition-list capacities are per job)
     uint32_t ncoarse;  // binned batches: coarse buckets in use
     uint32_t segs;     // binned batches: kBinTile segments per coarse bucket
 };
@@ -235,6 +236,12 @@ hipError_t launch_batch_count(const JobView& jv, const uint32_t* tile_prefix, Sl
 // points into each job's coarse buckets (cjob maps a coarse bucket to its
 // job), level 2 into partition buckets, then the LDS update of every
 // partition.  cursor1 (ncoarse) and cursor2 (partitions) must be zero.
+// Distinct-tile sketch per job: HyperLogLog registers (2^kHllLog2 per job,
+// job-major, zeroed here) over a fixed 1/64 hash sample of each job's tiles.
+constexpr uint32_t kHllLog2 = 8;
+hipError_t launch_batch_hll(const JobView& jv, const uint32_t* tile_prefix, uint32_t tile, uint32_t* hll,
+                            uint32_t njobs, uint32_t tiles, hipStream_t stream);
+
 hipError_t launch_batch_binned(const JobView& jv, const uint32_t* tile_prefix, const uint32_t* cjob, uint64_t* bin1,
                                uint32_t* cursor1, uint64_t* bin2, uint32_t* cursor2, Slot* tab, hipStream_t stream);
 

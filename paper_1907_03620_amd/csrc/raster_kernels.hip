@@ -824,7 +824,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bbin_keys(JobView jv, const uin
                                                            const uint32_t* cursor1, uint64_t* bin2,
                                                            uint32_t* cursor2, Slot* tab) {
     __shared__ BinScratch S;
-    const uint64_t cap1 = jv.dims->cap1, cap2 = jv.dims->cap2;
+    const uint64_t cap1 = jv.dims->cap1;
     const uint32_t segs = jv.dims->segs;
     const uint64_t work = (uint64_t)jv.dims->ncoarse * segs;
     const SpillBuf none{nullptr, nullptr, 0};
@@ -856,9 +856,10 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bbin_keys(JobView jv, const uin
             }
         }
         uint32_t fresh = 0;
-        const uint64_t first = (uint64_t)J.part_base + ((uint64_t)(c - J.cbase) << J.cshift);
-        bin_tile(S, key, bucket, valid, nb, g.p_log2, bin2 + first * cap2, cap2, cap2, cursor2 + first,
-                 tab + J.slot_base, g, none, jv.job_ctr + (uint64_t)job * kCounterWords, fresh);
+        const uint64_t first = (uint64_t)(c - J.cbase) << J.cshift;  // job-local partition
+        bin_tile(S, key, bucket, valid, nb, g.p_log2, bin2 + J.bin2_base + first * J.cap2, J.cap2, J.cap2,
+                 cursor2 + J.part_base + first, tab + J.slot_base, g, none,
+                 jv.job_ctr + (uint64_t)job * kCounterWords, fresh);
         __syncthreads();
     }
 }
@@ -868,10 +869,10 @@ __global__ __launch_bounds__(AGG_THREADS) void k_bagg(JobView jv, const uint64_t
     __shared__ uint64_t lkey[kPartSlots];
     __shared__ uint32_t lcnt[kPartSlots];
     const uint64_t parts = jv.dims->slots >> kPartLog2;
-    const uint64_t cap2 = jv.dims->cap2;
     const SpillBuf none{nullptr, nullptr, 0};
     for (uint64_t p = blockIdx.x; p < parts; p += gridDim.x) {
-        const PartLists<1> L(bin2 + p * cap2, 0, cursor2 + p, 0, cap2);
+        const JobInfo& J = jv.jobs[jv.part_job[p]];
+        const PartLists<1> L(bin2 + J.bin2_base + (p - J.part_base) * J.cap2, 0, cursor2 + p, 0, J.cap2);
         if (L.total == 0) continue;  // uniform across the workgroup
         uint32_t fresh = 0;
         aggregate_partition(L, tab + (p << kPartLog2), true, lkey, lcnt, none,
@@ -1589,6 +1590,50 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_filter_scatter(JobView jv, con
     }
 }
 
+// ---- distinct-tile estimate per job (batches) ---------------------------------
+//
+// HyperLogLog (Flajolet, Fusy, Gandouet and Meunier, AofA 2007) over the
+// tiles of each job, so that its table can be sized before counting.  Only
+// keys whose slot hash has its low 6 bits zero are registered (a fixed 1/64
+// of the distinct tiles, so the estimate is scaled by 64): register = top
+// kHllLog2 bits of the hash, rank = 1 + leading zeros of hash bits
+// [6, 32 - kHllLog2).  Reads every point once; range errors are left to the
+// counting pass.
+
+__global__ __launch_bounds__(256) void k_batch_hll(JobView jv, const uint32_t* tile_prefix, uint32_t tile,
+                                                   uint32_t* hll) {
+    constexpr int U = 8;
+    constexpr uint32_t rank_bits = 26 - kHllLog2;
+    const uint32_t tiles = jv.dims->tiles, njobs = jv.dims->njobs;
+    for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const uint32_t job = job_of_tile(tile_prefix, njobs, t);
+        const JobInfo& J = jv.jobs[job];
+        const int64_t base = (int64_t)(t - J.first_tile) * tile;
+        const int64_t end = min(base + (int64_t)tile, J.n);
+        uint32_t* reg = hll + ((uint64_t)job << kHllLog2);
+        for (int64_t i0 = base; i0 < end; i0 += (int64_t)U * blockDim.x) {
+            // loads of all items first (indices clamped, results masked)
+            double x[U], y[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t i = min(i0 + (int64_t)u * blockDim.x + threadIdx.x, end - 1);
+                if (J.dtype == 1) load_point(static_cast<const float*>(J.pts), i, x[u], y[u]);
+                else load_point(static_cast<const double*>(J.pts), i, x[u], y[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                uint64_t key;
+                if (i0 + (int64_t)u * blockDim.x + threadIdx.x >= end || !tile_key(x[u], y[u], J.scale, key)) continue;
+                const uint32_t h = slot_hash(key);
+                if (h & 63u) continue;
+                const uint32_t rest = (h >> 6) & ((1u << rank_bits) - 1);
+                const uint32_t rank = rest ? (uint32_t)__clz(rest) - (32 - rank_bits) + 1 : rank_bits + 1;
+                atomicMax(reg + (h >> (32 - kHllLog2)), rank);
+            }
+        }
+    }
+}
+
 // ---- per-job ranges and statistics (batches) ----------------------------------
 
 __global__ void k_bounds(const uint32_t* seg_job, const unsigned long long* n_dev, uint32_t* start, uint32_t* end) {
@@ -1906,6 +1951,16 @@ hipError_t launch_batch_binned(const JobView& jv, const uint32_t* tile_prefix, c
     hipLaunchKernelGGL(k_bbin_keys, dim3(8192), dim3(BIN_THREADS), 0, stream, jv, cjob, bin1, cursor1, bin2, cursor2,
                        tab);
     hipLaunchKernelGGL(k_bagg, dim3(4096), dim3(AGG_THREADS), 0, stream, jv, bin2, cursor2, tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_hll(const JobView& jv, const uint32_t* tile_prefix, uint32_t tile, uint32_t* hll,
+                            uint32_t njobs, uint32_t tiles, hipStream_t stream) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid_for((uint64_t)njobs << kHllLog2, 256, 256)), dim3(256), 0, stream, hll,
+                       (uint64_t)njobs << kHllLog2);
+    if (tiles)
+        hipLaunchKernelGGL(k_batch_hll, dim3(grid_for(tiles, 1, 8192)), dim3(256), 0, stream, jv, tile_prefix, tile,
+                           hll);
     return hipGetLastError();
 }
 

@@ -69,6 +69,17 @@ struct BatchEngine {
     unsigned long long* h_job_ctr = nullptr;
     unsigned long long* h_ctr = nullptr;
     uint32_t* h_bounds = nullptr;
+    // distinct-tile sketch pass (before the tables are sized)
+    uint32_t sk_cap = 0;
+    JobInfo* sk_jobs = nullptr;
+    Dims* sk_dims = nullptr;
+    uint32_t* sk_prefix = nullptr;
+    uint32_t* sk_hll = nullptr;
+    JobInfo* h_sk_jobs = nullptr;
+    Dims* h_sk_dims = nullptr;
+    uint32_t* h_sk_prefix = nullptr;
+    uint32_t* h_sk_hll = nullptr;
+    Buffers sk_bufs;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     raster_tuning graph_tuning{};
@@ -102,11 +113,28 @@ struct BatchEngine {
         graph = nullptr;
         graph_valid = false;
     }
+    void release_sketch() {
+        sk_bufs.release_all();
+        if (h_sk_jobs) (void)hipHostFree(h_sk_jobs);
+        if (h_sk_dims) (void)hipHostFree(h_sk_dims);
+        if (h_sk_prefix) (void)hipHostFree(h_sk_prefix);
+        if (h_sk_hll) (void)hipHostFree(h_sk_hll);
+        h_sk_jobs = nullptr;
+        h_sk_dims = nullptr;
+        h_sk_prefix = nullptr;
+        h_sk_hll = nullptr;
+        sk_jobs = nullptr;
+        sk_dims = nullptr;
+        sk_prefix = nullptr;
+        sk_hll = nullptr;
+        sk_cap = 0;
+    }
     void release() {
         if (bs) (void)hipStreamSynchronize(bs);
         drop_graph();
         bufs.release_all();
         release_host();
+        release_sketch();
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (bs) (void)hipStreamDestroy(bs);
         ev_in = nullptr;
@@ -123,6 +151,76 @@ struct BatchEngine {
         if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_in, hipEventDisableTiming);
         if (e != hipSuccess) return hip_fail(e, "batch engine");
         bufs.pool = &DevicePool::get(device);
+        sk_bufs.pool = bufs.pool;
+        return RASTER_OK;
+    }
+
+    // Distinct tiles per job, estimated from one pass over the points (see
+    // k_batch_hll); tile_prefix and tile as for the counting launch.
+    raster_status estimate_distinct(const raster_job* jobs, int32_t n_jobs, const std::vector<uint32_t>& prefix,
+                                    uint32_t tile, std::vector<double>* est) {
+        if ((uint32_t)n_jobs > sk_cap) {
+            (void)hipStreamSynchronize(bs);
+            release_sketch();
+            sk_cap = (uint32_t)n_jobs + (uint32_t)n_jobs / 4 + 8;
+            hipError_t e = sk_bufs.take((void**)&sk_jobs, sk_cap * sizeof(JobInfo));
+            if (e == hipSuccess) e = sk_bufs.take((void**)&sk_dims, sizeof(Dims));
+            if (e == hipSuccess) e = sk_bufs.take((void**)&sk_prefix, (sk_cap + 1) * sizeof(uint32_t));
+            if (e == hipSuccess) e = sk_bufs.take((void**)&sk_hll, ((size_t)sk_cap << kHllLog2) * sizeof(uint32_t));
+            if (e == hipSuccess) e = hipHostMalloc((void**)&h_sk_jobs, sk_cap * sizeof(JobInfo), 0);
+            if (e == hipSuccess) e = hipHostMalloc((void**)&h_sk_dims, sizeof(Dims), 0);
+            if (e == hipSuccess) e = hipHostMalloc((void**)&h_sk_prefix, (sk_cap + 1) * sizeof(uint32_t), 0);
+            if (e == hipSuccess)
+                e = hipHostMalloc((void**)&h_sk_hll, ((size_t)sk_cap << kHllLog2) * sizeof(uint32_t), 0);
+            if (e != hipSuccess) {
+                release_sketch();
+                return hip_fail(e, "distinct-tile sketch buffers");
+            }
+        }
+        std::memset(h_sk_jobs, 0, n_jobs * sizeof(JobInfo));
+        for (int32_t i = 0; i < n_jobs; ++i) {
+            double sc = jobs[i].scale;
+            if (!(sc > 0.0)) scale_for_precision(jobs[i].precision, &sc);
+            JobInfo& J = h_sk_jobs[i];
+            J.pts = jobs[i].d_points;
+            J.n = jobs[i].n;
+            J.scale = sc;
+            J.dtype = (int32_t)jobs[i].dt;
+            J.first_tile = prefix[i];
+            h_sk_prefix[i] = prefix[i];
+        }
+        h_sk_prefix[n_jobs] = prefix[n_jobs];
+        std::memset(h_sk_dims, 0, sizeof(Dims));
+        h_sk_dims->njobs = (uint32_t)n_jobs;
+        h_sk_dims->tiles = prefix[n_jobs];
+        hipError_t e = hipMemcpyAsync(sk_jobs, h_sk_jobs, n_jobs * sizeof(JobInfo), hipMemcpyHostToDevice, bs);
+        if (e == hipSuccess) e = hipMemcpyAsync(sk_dims, h_sk_dims, sizeof(Dims), hipMemcpyHostToDevice, bs);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(sk_prefix, h_sk_prefix, (n_jobs + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, bs);
+        const JobView jv{sk_dims, sk_jobs, nullptr, nullptr, nullptr};
+        if (e == hipSuccess)
+            e = launch_batch_hll(jv, sk_prefix, tile, sk_hll, (uint32_t)n_jobs, prefix[n_jobs], bs);
+        const size_t regs = (size_t)n_jobs << kHllLog2;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h_sk_hll, sk_hll, regs * sizeof(uint32_t), hipMemcpyDeviceToHost, bs);
+        if (e == hipSuccess) e = hipStreamSynchronize(bs);
+        if (e != hipSuccess) return hip_fail(e, "distinct-tile sketch");
+        // HyperLogLog estimate with the small-range (linear counting) form
+        constexpr double m = (double)(1u << kHllLog2);
+        const double alpha = 0.7213 / (1.0 + 1.079 / m);
+        est->assign(n_jobs, 0.0);
+        for (int32_t i = 0; i < n_jobs; ++i) {
+            const uint32_t* M = h_sk_hll + ((size_t)i << kHllLog2);
+            double z = 0.0;
+            int zeros = 0;
+            for (uint32_t j = 0; j < (1u << kHllLog2); ++j) {
+                z += std::ldexp(1.0, -(int)M[j]);
+                zeros += M[j] == 0;
+            }
+            double e_hll = alpha * m * m / z;
+            if (e_hll <= 2.5 * m && zeros > 0) e_hll = m * std::log(m / zeros);
+            (*est)[i] = 64.0 * e_hll;  // the sketch registers 1/64 of the tiles
+        }
         return RASTER_OK;
     }
 
@@ -234,27 +332,54 @@ raster_status BatchEngine::run(const raster_job* jobs, int32_t n_jobs, hipStream
     raster_status st = init();
     if (st != RASTER_OK) return st;
     const raster_tuning tu = current_tuning();
-    bool binned = tu.mode != 1;
-    for (int32_t i = 0; i < n_jobs && binned; ++i) {
-        // level 2 splits a coarse bucket into at most kMaxFine partitions
-        const double est = std::max<double>((double)jobs[i].n / 8.0, 1.0) / tu.load_factor;
-        const uint64_t parts = next_pow2(std::max<uint64_t>(kPartSlotsHost, (uint64_t)est)) / kPartSlotsHost;
-        if (parts > 128ull * kMaxFine) binned = false;
+    // every job's table sized from its estimated distinct tiles (a job that
+    // still overflows is redone alone); the sketch reads the points in tiles
+    // of its own size
+    constexpr uint64_t sk_tile = 4096;
+    std::vector<uint32_t> sk_prefix(n_jobs + 1);
+    uint64_t sk_tiles = 0;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        sk_prefix[i] = (uint32_t)sk_tiles;
+        sk_tiles += ((uint64_t)jobs[i].n + sk_tile - 1) / sk_tile;
+        if (sk_tiles > 0xFFFFFFF0ull) return fail(RASTER_E_NOMEM, "batch too large for one launch");
     }
-    const uint64_t tile = binned ? (uint64_t)kBinTile : (uint64_t)tu.block * (uint64_t)tu.items;
-    // sizes of every job's table, coarse buckets and work tiles
-    std::vector<uint64_t> caps(n_jobs), bases(n_jobs);
-    std::vector<uint32_t> tiles(n_jobs), ncs(n_jobs), shifts(n_jobs), cbases(n_jobs);
-    uint64_t slots = 0, pts_total = 0, tiles_total = 0, ncoarse = 0, per1 = 1, per2 = 1;
+    sk_prefix[n_jobs] = (uint32_t)sk_tiles;
+    hipError_t e = hipEventRecord(ev_in, user);
+    if (e == hipSuccess) e = hipStreamWaitEvent(bs, ev_in, 0);
+    if (e != hipSuccess) return hip_fail(e, "batch stream order");
+    std::vector<double> distinct;
+    st = estimate_distinct(jobs, n_jobs, sk_prefix, (uint32_t)sk_tile, &distinct);
+    if (st != RASTER_OK) return st;
+    std::vector<uint64_t> caps(n_jobs);
+    bool binned = tu.mode != 1;
     for (int32_t i = 0; i < n_jobs; ++i) {
         const uint64_t n = (uint64_t)jobs[i].n;
-        const double est = std::max<double>((double)n / 8.0, 1.0) / tu.load_factor;
-        caps[i] = next_pow2(std::max<uint64_t>(kPartSlotsHost, (uint64_t)est));
+        const double d = std::min<double>(1.25 * distinct[i], (double)n);
+        // at least one partition per coarse bucket of about 32K keys (at most
+        // 128), which bounds the coarse-bucket capacity
+        const uint64_t nc = std::min<uint64_t>(next_pow2(std::max<uint64_t>(1, (n + 32767) / 32768)), 128);
+        caps[i] = next_pow2(std::max<uint64_t>(nc * kPartSlotsHost, (uint64_t)(d / tu.load_factor) + 1));
+        // level 2 splits a coarse bucket into at most kMaxFine partitions
+        if (caps[i] / kPartSlotsHost > 128ull * kMaxFine) binned = false;
+    }
+    const uint64_t tile = binned ? (uint64_t)kBinTile : (uint64_t)tu.block * (uint64_t)tu.items;
+    // work tiles of every job
+    std::vector<uint32_t> tiles(n_jobs);
+    uint64_t tiles_total = 0;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        tiles[i] = (uint32_t)(((uint64_t)jobs[i].n + tile - 1) / tile);
+        tiles_total += tiles[i];
+        if (tiles_total > 0xFFFFFFF0ull) return fail(RASTER_E_NOMEM, "batch too large for one launch");
+    }
+    // layout of the tables and coarse buckets
+    std::vector<uint64_t> bases(n_jobs), b2base(n_jobs);
+    std::vector<uint32_t> ncs(n_jobs), shifts(n_jobs), cbases(n_jobs), cap2s(n_jobs);
+    uint64_t slots = 0, pts_total = 0, ncoarse = 0, per1 = 1, b2_total = 0;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        const uint64_t n = (uint64_t)jobs[i].n;
         bases[i] = slots;
         slots += caps[i];
         pts_total += n;
-        tiles[i] = (uint32_t)((n + tile - 1) / tile);
-        tiles_total += tiles[i];
         // about 32K keys per coarse bucket, at most 128 buckets per job
         const uint64_t parts = caps[i] / kPartSlotsHost;
         uint64_t nc = next_pow2(std::max<uint64_t>(1, (n + 32767) / 32768));
@@ -264,20 +389,23 @@ raster_status BatchEngine::run(const raster_job* jobs, int32_t n_jobs, hipStream
         cbases[i] = (uint32_t)ncoarse;
         ncoarse += nc;
         per1 = std::max<uint64_t>(per1, (n + nc - 1) / nc);
-        per2 = std::max<uint64_t>(per2, (n + parts - 1) / parts);
+        // partition-list capacity: the expected share plus slack far beyond
+        // the binomial spread; a key past it is added directly instead
+        const uint64_t per2 = (n + parts - 1) / parts;
+        uint64_t c2 = per2 + per2 / 8 + 4 * (uint64_t)std::sqrt((double)per2) + 256;
+        c2 = (c2 + 63) / 64 * 64;
+        cap2s[i] = (uint32_t)c2;
+        b2base[i] = b2_total;
+        b2_total += parts * c2;
     }
-    if (tiles_total > 0xFFFFFFF0ull || slots > (1ull << 33))
-        return fail(RASTER_E_NOMEM, "batch too large for one launch");
-    // bucket capacities: the expected share plus slack far beyond the binomial
-    // spread; a key past its bucket's capacity is added directly instead
+    if (slots > (1ull << 33)) return fail(RASTER_E_NOMEM, "batch too large for one launch");
+    // coarse-bucket capacity: the expected share plus slack far beyond the
+    // binomial spread; a key past it is added directly instead
     uint64_t cap1 = per1 + per1 / 16 + 4 * (uint64_t)std::sqrt((double)per1) + 1024;
     cap1 = (cap1 + 255) / 256 * 256;
-    uint64_t cap2 = per2 + per2 / 8 + 4 * (uint64_t)std::sqrt((double)per2) + 256;
-    cap2 = (cap2 + 63) / 64 * 64;
-    const uint64_t parts_total = slots / kPartSlotsHost;
     const uint64_t s_need = std::max<uint64_t>(1, std::min<uint64_t>(slots, pts_total));
     st = reserve(slots, s_need, (uint32_t)n_jobs, binned ? ncoarse : 0, binned ? ncoarse * cap1 : 0,
-                 binned ? parts_total * cap2 : 0);
+                 binned ? b2_total : 0);
     if (st != RASTER_OK) return st;
     // host mirrors
     uint32_t tp = 0;
@@ -297,7 +425,8 @@ raster_status BatchEngine::run(const raster_job* jobs, int32_t n_jobs, hipStream
         J.part_base = (uint32_t)(bases[i] / kPartSlotsHost);
         J.cbase = cbases[i];
         J.cshift = shifts[i];
-        J.pad = 0;
+        J.cap2 = cap2s[i];
+        J.bin2_base = b2base[i];
         h_tile_prefix[i] = tp;
         tp += tiles[i];
         for (uint64_t p = bases[i] / kPartSlotsHost; p < (bases[i] + caps[i]) / kPartSlotsHost; ++p)
@@ -310,12 +439,10 @@ raster_status BatchEngine::run(const raster_job* jobs, int32_t n_jobs, hipStream
     h_dims->njobs = (uint32_t)n_jobs;
     h_dims->tiles = tp;
     h_dims->cap1 = cap1;
-    h_dims->cap2 = cap2;
+    h_dims->cap2 = 0;
     h_dims->ncoarse = binned ? (uint32_t)ncoarse : 0;
     h_dims->segs = (uint32_t)((cap1 + kBinTile - 1) / kBinTile);
-    hipError_t e = hipEventRecord(ev_in, user);
-    if (e == hipSuccess) e = hipStreamWaitEvent(bs, ev_in, 0);
-    if (e == hipSuccess) e = hipMemcpyAsync(jobs_dev, h_jobs, n_jobs * sizeof(JobInfo), hipMemcpyHostToDevice, bs);
+    e = hipMemcpyAsync(jobs_dev, h_jobs, n_jobs * sizeof(JobInfo), hipMemcpyHostToDevice, bs);
     if (e == hipSuccess) e = hipMemcpyAsync(dims_dev, h_dims, sizeof(Dims), hipMemcpyHostToDevice, bs);
     if (e == hipSuccess)
         e = hipMemcpyAsync(tile_prefix, h_tile_prefix, (n_jobs + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, bs);
