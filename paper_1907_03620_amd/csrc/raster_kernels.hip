@@ -873,6 +873,8 @@ __global__ __launch_bounds__(AGG_THREADS) void k_bagg(JobView jv, const uint64_t
     for (uint64_t p = blockIdx.x; p < parts; p += gridDim.x) {
         const JobInfo& J = jv.jobs[jv.part_job[p]];
         const PartLists<1> L(bin2 + J.bin2_base + (p - J.part_base) * J.cap2, 0, cursor2 + p, 0, J.cap2);
+        // keys past a bucket's capacity were added to the table directly, so
+        // the slice is read
         if (L.total == 0) continue;  // uniform across the workgroup
         uint32_t fresh = 0;
         aggregate_partition(L, tab + (p << kPartLog2), true, lkey, lcnt, none,
@@ -1129,9 +1131,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_threshold_scatter(Slot* tab, J
                 size[p] = 0;
                 if (multi) jv.s_job[p] = job;
                 tab[i].aux = (uint32_t)p;
-            } else {
-                tab[i].aux = kNotSignificant;
-            }
+            }  // other slots already hold kNotSignificant (fill and update passes write it)
         }
         run += total;
     }
@@ -1602,7 +1602,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_filter_scatter(JobView jv, con
 
 __global__ __launch_bounds__(256) void k_batch_hll(JobView jv, const uint32_t* tile_prefix, uint32_t tile,
                                                    uint32_t* hll) {
-    constexpr int U = 8;
+    constexpr int U = 16;
     constexpr uint32_t rank_bits = 26 - kHllLog2;
     const uint32_t tiles = jv.dims->tiles, njobs = jv.dims->njobs;
     for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
@@ -1647,16 +1647,20 @@ __global__ void k_bounds(const uint32_t* seg_job, const unsigned long long* n_de
 }
 
 // One workgroup per job: roots and kept roots among the job's compact tiles.
+// Workgroups per job of the statistics pass; the job's range is shared
+// between them round-robin.
+constexpr uint32_t kJobStatSplit = 8;
+
 __global__ __launch_bounds__(SCAN_THREADS) void k_job_stats(JobView jv, const uint32_t* root, const uint32_t* size,
                                                             const uint32_t* s_start, const uint32_t* s_end,
                                                             const uint32_t* o_start, const uint32_t* o_end) {
     __shared__ unsigned long long red[SCAN_WAVES];
-    const uint32_t job = blockIdx.x;
+    const uint32_t job = blockIdx.x / kJobStatSplit, part = blockIdx.x % kJobStatSplit;
     if (job >= jv.dims->njobs) return;  // uniform
     const uint32_t mu = jv.jobs[job].mu;
     const uint32_t a = s_start[job], b = s_end[job];
     unsigned long long comps = 0, kept = 0;
-    for (uint32_t i = a + threadIdx.x; i < b; i += SCAN_THREADS) {
+    for (uint32_t i = a + part * SCAN_THREADS + threadIdx.x; i < b; i += kJobStatSplit * SCAN_THREADS) {
         if (root[i] == i) {
             comps += 1;
             kept += (size[i] >= mu);
@@ -1666,10 +1670,12 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_job_stats(JobView jv, const ui
     kept = block_sum(kept, red);
     if (threadIdx.x == 0) {
         unsigned long long* c = jv.job_ctr + (uint64_t)job * kCounterWords;
-        c[C_COMPONENTS] = comps;
-        c[C_CLUSTERS] = kept;
-        c[C_SIGNIFICANT] = b - a;
-        c[C_TILES] = o_end[job] - o_start[job];
+        if (comps) atomicAdd(&c[C_COMPONENTS], comps);
+        if (kept) atomicAdd(&c[C_CLUSTERS], kept);
+        if (part == 0) {
+            c[C_SIGNIFICANT] = b - a;
+            c[C_TILES] = o_end[job] - o_start[job];
+        }
     }
 }
 
@@ -1979,7 +1985,8 @@ hipError_t launch_bounds(const uint32_t* seg_job, const unsigned long long* n, u
 hipError_t launch_job_stats(const JobView& jv, const uint32_t* root, const uint32_t* size, const uint32_t* s_start,
                             const uint32_t* s_end, const uint32_t* o_start, const uint32_t* o_end,
                             uint32_t max_jobs, hipStream_t stream) {
-    hipLaunchKernelGGL(k_job_stats, dim3(max_jobs), dim3(SCAN_THREADS), 0, stream, jv, root, size, s_start, s_end,
+    hipLaunchKernelGGL(k_job_stats, dim3(max_jobs * kJobStatSplit), dim3(SCAN_THREADS), 0, stream, jv, root, size,
+                       s_start, s_end,
                        o_start, o_end);
     return hipGetLastError();
 }
