@@ -329,3 +329,20 @@ def test_repeated_runs_identical(raster, torch, mid, mid_oracle):
     for rep in range(6):
         g = raster.cluster(d, precision=2, tau=5, mu=4)
         assert_same(g, mid_oracle, f"repeat {rep}")
+
+
+def test_dense_uniform_grid(raster, torch):
+    """Mostly-singleton tiles: 3M uniform points over 1000 x 1000 tiles (p = 1).
+    The table-size guess (n/8 distinct) is far too small, so the binned path
+    spills, grows and re-inserts; results must not change."""
+    rng = synth.rng_for(11)
+    pts = rng.uniform(0.0, 100.0, size=(3_000_000, 2))
+    _say(f"dense uniform grid: {pts.shape[0]} points")
+    for mode in (0, 2):
+        raster.set_tuning(mode=mode)
+        try:
+            r = raster.cluster(dev(pts, torch), precision=1, tau=3, mu=4)
+        finally:
+            raster.set_tuning(None)
+        assert r.stats["distinct_tiles"] > 900_000
+        assert_same(r, oracle.cluster(pts, tau=3, mu=4, precision=1), f"dense uniform grid, mode {mode}")
