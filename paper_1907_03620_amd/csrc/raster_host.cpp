@@ -227,6 +227,61 @@ TableRun::~TableRun() {
     if (h_ctr) (void)hipHostFree(h_ctr);
 }
 
+double hll_estimate(const uint32_t* M) {
+    constexpr double m = (double)(1u << kHllLog2);
+    const double alpha = 0.7213 / (1.0 + 1.079 / m);
+    double z = 0.0;
+    int zeros = 0;
+    for (uint32_t j = 0; j < (1u << kHllLog2); ++j) {
+        z += std::ldexp(1.0, -(int)M[j]);
+        zeros += M[j] == 0;
+    }
+    double e = alpha * m * m / z;
+    if (e <= 2.5 * m && zeros > 0) e = m * std::log(m / zeros);
+    return 64.0 * e;  // the sketch registers 1/64 of the tiles
+}
+
+// One-shot calls counted directly take a sketch pass first from this size on;
+// below it a wrong guess only costs a cheap table growth.
+static constexpr uint64_t kSketchMinPoints = 1u << 16;
+
+// One-shot calls: the table was sized by a guess (n/8 distinct tiles) before
+// any key was seen; before the keys are split into partitions, the sketch
+// taken while binning sizes it properly.  The table is still empty apart from
+// keys that overflowed a bucket, so growing it is cheap.
+raster_status TableRun::ensure_sketch() {
+    if (sketch) return RASTER_OK;
+    const size_t regs = (size_t)kHllReps << kHllLog2;
+    HIP_TRY(bufs.take((void**)&sketch, regs * sizeof(uint32_t)), "sketch");
+    HIP_TRY(launch_zero_u64((uint64_t*)sketch, regs / 2, stream), "zero sketch");
+    return RASTER_OK;
+}
+
+raster_status TableRun::size_from_sketch(uint64_t points) {
+    const size_t regs = (size_t)kHllReps << kHllLog2;
+    std::vector<uint32_t> h(regs);
+    HIP_TRY(hipMemcpyAsync(h.data(), sketch, regs * sizeof(uint32_t), hipMemcpyDeviceToHost, stream), "sketch copy");
+    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    std::vector<uint32_t> M(1u << kHllLog2, 0);
+    for (uint32_t r = 0; r < kHllReps; ++r)
+        for (uint32_t j = 0; j < (1u << kHllLog2); ++j) M[j] = std::max(M[j], h[((size_t)r << kHllLog2) + j]);
+    const double d = std::min<double>(1.25 * hll_estimate(M.data()) + (double)h_ctr[C_INSERTED], (double)points);
+    const uint64_t want = next_pow2((uint64_t)(d / tuning.load_factor) + 1);
+    if (want <= cap) return RASTER_OK;
+    if (h_ctr[C_INSERTED] == 0 && h_ctr[C_SPILLED] == 0) {
+        // nothing inserted yet: a fresh table, no rehash
+        Slot* nt = nullptr;
+        uint64_t nc = 0;
+        raster_status st = alloc_table(want, &nt, &nc);
+        if (st != RASTER_OK) return st;
+        bufs.give_back(tab);
+        tab = nt;
+        cap = nc;
+        return RASTER_OK;
+    }
+    return grow(want, 0, 0);
+}
+
 raster_status TableRun::init(double scale_, uint32_t tau_, uint32_t mu_, int64_t tile_hint,
                              hipStream_t stream_) {
     scale = scale_;
@@ -418,6 +473,7 @@ raster_status TableRun::flush() {
     if (group_points == 0) return RASTER_OK;
     raster_status st = settle();
     if (st != RASTER_OK) return st;
+    if (sketch && (st = size_from_sketch(group_points)) != RASTER_OK) return st;
     const Geo g = make_geo(cap);
     SpillBuf sp{spill_keys[0], spill_counts[0], spill_cap[0]};
     if (!binned_geometry(g)) {
@@ -507,11 +563,19 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
                 if (st != RASTER_OK) return st;
             }
             if ((st = span_begin(0, &a)) != RASTER_OK) return st;
-            HIP_TRY(launch_bin_points(p, piece, (int)dt, scale, bin1, cap1, cursor1, tab, cap, sp, ctr, stream),
+            if (single_shot && (st = ensure_sketch()) != RASTER_OK) return st;
+            HIP_TRY(launch_bin_points(p, piece, (int)dt, scale, bin1, cap1, cursor1, tab, cap, sp, ctr, sketch, stream),
                     "bin points");
             if ((st = span_end(0, a)) != RASTER_OK) return st;
             group_points += (uint64_t)piece;
         } else {
+            if (single_shot && piece >= (int64_t)kSketchMinPoints && n_points == 0) {
+                // one read of the points sizes the table before any insert
+                if ((st = ensure_sketch()) != RASTER_OK) return st;
+                HIP_TRY(launch_points_hll(p, piece, (int)dt, scale, sketch, stream), "sketch");
+                if ((st = size_from_sketch((uint64_t)piece)) != RASTER_OK) return st;
+                sp = SpillBuf{spill_keys[0], spill_counts[0], spill_cap[0]};
+            }
             if ((st = span_begin(0, &a)) != RASTER_OK) return st;
             HIP_TRY(launch_project_count(p, piece, (int)dt, scale, tab, cap, sp, ctr, kernel_tuning(tuning), stream),
                     "project_count");

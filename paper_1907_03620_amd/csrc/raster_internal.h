@@ -62,6 +62,11 @@ constexpr uint32_t kMaxFine = 512;
 // speed.
 constexpr uint32_t kBinRep = 8;
 
+// Distinct-tile sketches: 2^kHllLog2 HyperLogLog registers over a fixed 1/64
+// hash sample of the tiles; kHllReps replicas where many workgroups merge.
+constexpr uint32_t kHllLog2 = 8;
+constexpr uint32_t kHllReps = 64;
+
 inline bool binned_geometry(const Geo& g) {
     return g.cp_log2 == kPartLog2 && g.p_log2 >= kCoarseLog2 && (1ull << (g.p_log2 - kCoarseLog2)) <= kMaxFine;
 }
@@ -170,9 +175,11 @@ hipError_t launch_project_count(const void* pts, int64_t n, int dtype, double sc
 // Binned contraction, level 1: project n points and append each key to its
 // coarse bucket: bucket b holds keys at bin1[b * cap1 + i], i < cursor1[b].
 // Keys past a bucket's capacity go straight into the table.
+// hll, if not null, gets the distinct-tile sketch of the keys (kHllReps
+// replicas of 2^kHllLog2 registers; merge them by maximum).
 hipError_t launch_bin_points(const void* pts, int64_t n, int dtype, double scale, uint64_t* bin1, uint64_t cap1,
                              uint32_t* cursor1, Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr,
-                             hipStream_t stream);
+                             uint32_t* hll, hipStream_t stream);
 // Binned contraction, level 2: split every coarse bucket into its partitions
 // (bin2, cap2 keys per partition, counts in cursor2, which this clears first).
 hipError_t launch_bin_keys(const uint64_t* bin1, uint64_t cap1, const uint32_t* cursor1, uint64_t* bin2,
@@ -238,7 +245,10 @@ hipError_t launch_batch_count(const JobView& jv, const uint32_t* tile_prefix, Sl
 // partition.  cursor1 (ncoarse) and cursor2 (partitions) must be zero.
 // Distinct-tile sketch per job: HyperLogLog registers (2^kHllLog2 per job,
 // job-major, zeroed here) over a fixed 1/64 hash sample of each job's tiles.
-constexpr uint32_t kHllLog2 = 8;
+// Distinct-tile sketch of one point set into hll (kHllReps replicas, not
+// zeroed here).
+hipError_t launch_points_hll(const void* pts, int64_t n, int dtype, double scale, uint32_t* hll,
+                             hipStream_t stream);
 hipError_t launch_batch_hll(const JobView& jv, const uint32_t* tile_prefix, uint32_t tile, uint32_t* hll,
                             uint32_t njobs, uint32_t tiles, hipStream_t stream);
 

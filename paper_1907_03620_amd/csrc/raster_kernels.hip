@@ -49,6 +49,21 @@ __device__ __forceinline__ uint32_t slot_hash(uint64_t key) {
     return mix32((uint32_t)(key >> 32) * kGolden32 + (uint32_t)key);
 }
 
+// Distinct-tile sketch (HyperLogLog, Flajolet, Fusy, Gandouet and Meunier,
+// AofA 2007) over a fixed 1/64 of the tiles: those whose slot hash has its
+// low 6 bits zero.  Register = the top kHllLog2 hash bits, rank = 1 + the
+// leading zeros of hash bits [6, 32 - kHllLog2).  Returns false for a tile
+// outside the sample.
+__device__ __forceinline__ bool hll_sample(uint64_t key, uint32_t& reg, uint32_t& rank) {
+    constexpr uint32_t rank_bits = 26 - kHllLog2;
+    const uint32_t h = slot_hash(key);
+    if (h & 63u) return false;
+    const uint32_t rest = (h >> 6) & ((1u << rank_bits) - 1);
+    rank = rest ? (uint32_t)__clz(rest) - (32 - rank_bits) + 1 : rank_bits + 1;
+    reg = h >> (32 - kHllLog2);
+    return true;
+}
+
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
@@ -521,13 +536,19 @@ __device__ __forceinline__ void add_fresh(unsigned long long* ctr, uint32_t fres
     block_count_add(&ctr[C_INSERTED], fresh);
 }
 
+// hll, if not null, receives the hll_sample sketch of the keys: kHllReps
+// replicas of the registers (one per workgroup index modulo kHllReps, so
+// that the merges of many workgroups do not meet on a few cache lines).
 template <typename T>
 __global__ __launch_bounds__(BIN_THREADS) void k_bin_points(const T* __restrict__ pts, int64_t n, double scale,
                                                             uint64_t* bin1, uint64_t cap1, uint32_t* cursor1,
                                                             Slot* tab, const Geo g, SpillBuf sp,
-                                                            unsigned long long* ctr) {
+                                                            unsigned long long* ctr, uint32_t* hll) {
     __shared__ BinScratch S;
+    __shared__ uint32_t sk[1u << kHllLog2];
     for (uint32_t b = threadIdx.x; b < kCoarse; b += BIN_THREADS) S.hist[b] = 0;
+    if (hll)
+        for (uint32_t b = threadIdx.x; b < (1u << kHllLog2); b += BIN_THREADS) sk[b] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kBinTile + threadIdx.x;
     uint64_t key[BIN_ITEMS];
@@ -558,11 +579,24 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_points(const T* __restrict_
         }
     }
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrRange);
+    if (hll) {
+#pragma unroll
+        for (int j = 0; j < BIN_ITEMS; ++j) {
+            uint32_t reg, rank;
+            if ((valid & (1u << j)) && hll_sample(key[j], reg, rank)) atomicMax(&sk[reg], rank);
+        }
+    }
     uint32_t fresh = 0;
     const uint32_t r = blockIdx.x % kBinRep;
     bin_tile(S, key, bucket, valid, kCoarse, kCoarseLog2, bin1 + (uint64_t)r * kCoarse * cap1, cap1, cap1,
              cursor1 + r * kCoarse, tab, g, sp, ctr, fresh);
     add_fresh(ctr, fresh);
+    if (hll) {
+        __syncthreads();  // every sampled key is registered
+        uint32_t* rep = hll + ((uint64_t)(blockIdx.x % kHllReps) << kHllLog2);
+        for (uint32_t b = threadIdx.x; b < (1u << kHllLog2); b += BIN_THREADS)
+            if (sk[b]) atomicMax(rep + b, sk[b]);
+    }
 }
 
 // Level 2: workgroup (l1, seg) splits keys [seg * kBinTile, ...) of coarse
@@ -1590,20 +1624,41 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_filter_scatter(JobView jv, con
     }
 }
 
+// ---- distinct-tile sketch of one point set -------------------------------------
+//
+// The hll_sample sketch of n points into kHllReps register replicas (one per
+// workgroup index modulo kHllReps).  Range errors are left to the counting
+// pass.
+template <typename T>
+__global__ __launch_bounds__(256) void k_points_hll(const T* __restrict__ pts, int64_t n, double scale,
+                                                    uint32_t* hll) {
+    constexpr int U = 16;
+    uint32_t* rep = hll + ((uint64_t)(blockIdx.x % kHllReps) << kHllLog2);
+    for (int64_t i0 = (int64_t)blockIdx.x * U * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * U * blockDim.x) {
+        // loads of all items first (indices clamped, results masked)
+        double x[U], y[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) load_point(pts, min(i0 + (int64_t)u * blockDim.x + threadIdx.x, n - 1), x[u], y[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            uint64_t key;
+            uint32_t r, rank;
+            if (i0 + (int64_t)u * blockDim.x + threadIdx.x < n && tile_key(x[u], y[u], scale, key) &&
+                hll_sample(key, r, rank))
+                atomicMax(rep + r, rank);
+        }
+    }
+}
+
 // ---- distinct-tile estimate per job (batches) ---------------------------------
 //
-// HyperLogLog (Flajolet, Fusy, Gandouet and Meunier, AofA 2007) over the
-// tiles of each job, so that its table can be sized before counting.  Only
-// keys whose slot hash has its low 6 bits zero are registered (a fixed 1/64
-// of the distinct tiles, so the estimate is scaled by 64): register = top
-// kHllLog2 bits of the hash, rank = 1 + leading zeros of hash bits
-// [6, 32 - kHllLog2).  Reads every point once; range errors are left to the
+// The hll_sample sketch of each job's tiles, so that its table can be sized
+// before counting.  Reads every point once; range errors are left to the
 // counting pass.
 
 __global__ __launch_bounds__(256) void k_batch_hll(JobView jv, const uint32_t* tile_prefix, uint32_t tile,
                                                    uint32_t* hll) {
     constexpr int U = 16;
-    constexpr uint32_t rank_bits = 26 - kHllLog2;
     const uint32_t tiles = jv.dims->tiles, njobs = jv.dims->njobs;
     for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         const uint32_t job = job_of_tile(tile_prefix, njobs, t);
@@ -1624,11 +1679,8 @@ __global__ __launch_bounds__(256) void k_batch_hll(JobView jv, const uint32_t* t
             for (int u = 0; u < U; ++u) {
                 uint64_t key;
                 if (i0 + (int64_t)u * blockDim.x + threadIdx.x >= end || !tile_key(x[u], y[u], J.scale, key)) continue;
-                const uint32_t h = slot_hash(key);
-                if (h & 63u) continue;
-                const uint32_t rest = (h >> 6) & ((1u << rank_bits) - 1);
-                const uint32_t rank = rest ? (uint32_t)__clz(rest) - (32 - rank_bits) + 1 : rank_bits + 1;
-                atomicMax(reg + (h >> (32 - kHllLog2)), rank);
+                uint32_t r, rank;
+                if (hll_sample(key, r, rank)) atomicMax(reg + r, rank);
             }
         }
     }
@@ -1829,16 +1881,16 @@ hipError_t launch_project_count(const void* pts, int64_t n, int dtype, double sc
 
 hipError_t launch_bin_points(const void* pts, int64_t n, int dtype, double scale, uint64_t* bin1, uint64_t cap1,
                              uint32_t* cursor1, Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr,
-                             hipStream_t stream) {
+                             uint32_t* hll, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
     const Geo g = make_geo(cap);
     const unsigned grid = (unsigned)((n + kBinTile - 1) / kBinTile);
     if (dtype == 1)
         hipLaunchKernelGGL(k_bin_points<float>, dim3(grid), dim3(BIN_THREADS), 0, stream,
-                           static_cast<const float*>(pts), n, scale, bin1, cap1, cursor1, tab, g, spill, ctr);
+                           static_cast<const float*>(pts), n, scale, bin1, cap1, cursor1, tab, g, spill, ctr, hll);
     else
         hipLaunchKernelGGL(k_bin_points<double>, dim3(grid), dim3(BIN_THREADS), 0, stream,
-                           static_cast<const double*>(pts), n, scale, bin1, cap1, cursor1, tab, g, spill, ctr);
+                           static_cast<const double*>(pts), n, scale, bin1, cap1, cursor1, tab, g, spill, ctr, hll);
     return hipGetLastError();
 }
 
@@ -1957,6 +2009,19 @@ hipError_t launch_batch_binned(const JobView& jv, const uint32_t* tile_prefix, c
     hipLaunchKernelGGL(k_bbin_keys, dim3(8192), dim3(BIN_THREADS), 0, stream, jv, cjob, bin1, cursor1, bin2, cursor2,
                        tab);
     hipLaunchKernelGGL(k_bagg, dim3(4096), dim3(AGG_THREADS), 0, stream, jv, bin2, cursor2, tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_points_hll(const void* pts, int64_t n, int dtype, double scale, uint32_t* hll,
+                             hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)grid_for((uint64_t)n, 256 * 16, 4096);
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_points_hll<float>, dim3(grid), dim3(256), 0, stream, static_cast<const float*>(pts), n,
+                           scale, hll);
+    else
+        hipLaunchKernelGGL(k_points_hll<double>, dim3(grid), dim3(256), 0, stream, static_cast<const double*>(pts), n,
+                           scale, hll);
     return hipGetLastError();
 }
 

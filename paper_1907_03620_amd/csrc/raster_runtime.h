@@ -114,6 +114,7 @@ struct TableRun {
     uint64_t bin2_slots = 0;
     uint32_t* cursor2 = nullptr;
     uint64_t cursor2_n = 0;
+    uint32_t* sketch = nullptr;  // one-shot calls: distinct-tile sketch of the binned keys
     uint64_t group_points = 0;  // points binned since the last flush
     uint64_t group_budget = 0;
     uint64_t bin_points = 0;   // keys the coarse buckets are sized for
@@ -133,6 +134,8 @@ struct TableRun {
     raster_status export_tiles(uint64_t* keys, uint32_t* counts, int64_t cap_rows, int64_t* m);
 
     raster_status alloc_table(uint64_t c, Slot** t, uint64_t* c_out);
+    raster_status size_from_sketch(uint64_t points);
+    raster_status ensure_sketch();
     raster_status ensure_spill(int b, uint64_t need);
     raster_status pull_counters();
     raster_status grow(uint64_t new_cap, uint64_t pending, int src);
@@ -144,5 +147,9 @@ struct TableRun {
     raster_status span_end(int kind, hipEvent_t a);
     void resolve_spans();
 };
+
+// Distinct tiles estimated from 2^kHllLog2 sketch registers (HyperLogLog
+// with its small-range correction; the sketch holds 1/64 of the tiles).
+double hll_estimate(const uint32_t* regs);
 
 }  // namespace rst

@@ -205,22 +205,8 @@ struct BatchEngine {
             e = hipMemcpyAsync(h_sk_hll, sk_hll, regs * sizeof(uint32_t), hipMemcpyDeviceToHost, bs);
         if (e == hipSuccess) e = hipStreamSynchronize(bs);
         if (e != hipSuccess) return hip_fail(e, "distinct-tile sketch");
-        // HyperLogLog estimate with the small-range (linear counting) form
-        constexpr double m = (double)(1u << kHllLog2);
-        const double alpha = 0.7213 / (1.0 + 1.079 / m);
         est->assign(n_jobs, 0.0);
-        for (int32_t i = 0; i < n_jobs; ++i) {
-            const uint32_t* M = h_sk_hll + ((size_t)i << kHllLog2);
-            double z = 0.0;
-            int zeros = 0;
-            for (uint32_t j = 0; j < (1u << kHllLog2); ++j) {
-                z += std::ldexp(1.0, -(int)M[j]);
-                zeros += M[j] == 0;
-            }
-            double e_hll = alpha * m * m / z;
-            if (e_hll <= 2.5 * m && zeros > 0) e_hll = m * std::log(m / zeros);
-            (*est)[i] = 64.0 * e_hll;  // the sketch registers 1/64 of the tiles
-        }
+        for (int32_t i = 0; i < n_jobs; ++i) (*est)[i] = hll_estimate(h_sk_hll + ((size_t)i << kHllLog2));
         return RASTER_OK;
     }
 
