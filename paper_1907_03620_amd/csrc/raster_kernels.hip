@@ -539,15 +539,17 @@ __device__ __forceinline__ void add_fresh(unsigned long long* ctr, uint32_t fres
 // hll, if not null, receives the hll_sample sketch of the keys: kHllReps
 // replicas of the registers (one per workgroup index modulo kHllReps, so
 // that the merges of many workgroups do not meet on a few cache lines).
-template <typename T>
+// (SKETCH is a template parameter so that the sketch's LDS does not cost the
+// other calls occupancy.)
+template <typename T, bool SKETCH>
 __global__ __launch_bounds__(BIN_THREADS) void k_bin_points(const T* __restrict__ pts, int64_t n, double scale,
                                                             uint64_t* bin1, uint64_t cap1, uint32_t* cursor1,
                                                             Slot* tab, const Geo g, SpillBuf sp,
                                                             unsigned long long* ctr, uint32_t* hll) {
     __shared__ BinScratch S;
-    __shared__ uint32_t sk[1u << kHllLog2];
+    __shared__ uint32_t sk[SKETCH ? (1u << kHllLog2) : 1u];
     for (uint32_t b = threadIdx.x; b < kCoarse; b += BIN_THREADS) S.hist[b] = 0;
-    if (hll)
+    if (SKETCH)
         for (uint32_t b = threadIdx.x; b < (1u << kHllLog2); b += BIN_THREADS) sk[b] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kBinTile + threadIdx.x;
@@ -573,25 +575,20 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_points(const T* __restrict_
             if (tile_key(x[j], y[j], scale, key[j])) {
                 valid |= 1u << j;
                 bucket[j] = (uint16_t)bucket_of(key[j], kCoarseLog2, kCoarse);
+                uint32_t reg, rank;
+                if (SKETCH && hll_sample(key[j], reg, rank)) atomicMax(&sk[reg], rank);
             } else {
                 bad = true;
             }
         }
     }
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrRange);
-    if (hll) {
-#pragma unroll
-        for (int j = 0; j < BIN_ITEMS; ++j) {
-            uint32_t reg, rank;
-            if ((valid & (1u << j)) && hll_sample(key[j], reg, rank)) atomicMax(&sk[reg], rank);
-        }
-    }
     uint32_t fresh = 0;
     const uint32_t r = blockIdx.x % kBinRep;
     bin_tile(S, key, bucket, valid, kCoarse, kCoarseLog2, bin1 + (uint64_t)r * kCoarse * cap1, cap1, cap1,
              cursor1 + r * kCoarse, tab, g, sp, ctr, fresh);
     add_fresh(ctr, fresh);
-    if (hll) {
+    if (SKETCH) {
         __syncthreads();  // every sampled key is registered
         uint32_t* rep = hll + ((uint64_t)(blockIdx.x % kHllReps) << kHllLog2);
         for (uint32_t b = threadIdx.x; b < (1u << kHllLog2); b += BIN_THREADS)
@@ -1885,12 +1882,19 @@ hipError_t launch_bin_points(const void* pts, int64_t n, int dtype, double scale
     if (n <= 0) return hipSuccess;
     const Geo g = make_geo(cap);
     const unsigned grid = (unsigned)((n + kBinTile - 1) / kBinTile);
-    if (dtype == 1)
-        hipLaunchKernelGGL(k_bin_points<float>, dim3(grid), dim3(BIN_THREADS), 0, stream,
-                           static_cast<const float*>(pts), n, scale, bin1, cap1, cursor1, tab, g, spill, ctr, hll);
-    else
-        hipLaunchKernelGGL(k_bin_points<double>, dim3(grid), dim3(BIN_THREADS), 0, stream,
-                           static_cast<const double*>(pts), n, scale, bin1, cap1, cursor1, tab, g, spill, ctr, hll);
+    auto go = [&](auto kernel, const auto* p) {
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(BIN_THREADS), 0, stream, p, n, scale, bin1, cap1, cursor1, tab, g,
+                           spill, ctr, hll);
+    };
+    const float* pf = static_cast<const float*>(pts);
+    const double* pd = static_cast<const double*>(pts);
+    if (dtype == 1) {
+        if (hll) go(k_bin_points<float, true>, pf);
+        else go(k_bin_points<float, false>, pf);
+    } else {
+        if (hll) go(k_bin_points<double, true>, pd);
+        else go(k_bin_points<double, false>, pd);
+    }
     return hipGetLastError();
 }
 
