@@ -136,6 +136,23 @@ raster_status raster_result_copy(const raster_result* r, int32_t* d_kx, int32_t*
 raster_status raster_result_stats(const raster_result* r, raster_stats* out);
 void raster_result_free(raster_result* r);
 
+/* Per-point labels: the label of every input point, obtained as in the
+ * paper's comparison experiment (Section 4, its RASTER-star variant) by
+ * projecting the points a second time.  Each of the n points of d_points
+ * ((n, 2) row-major, dt as for clustering, borrowed for the call) is projected
+ * with the scale the result was computed with; d_labels[i] (caller-owned
+ * device array of n uint64, 8-byte aligned) receives the label of the kept
+ * cluster its tile belongs to (the biased key of that cluster's smallest
+ * tile, as in the rows), or 0xFFFFFFFFFFFFFFFF (-1 as int64) when its tile is
+ * in no kept cluster.  The points need not be the ones that were clustered.
+ * The first call builds a device lookup table of the result's tiles, kept
+ * with the result until raster_result_free.  Synchronises `stream`.  Errors:
+ * E_INVAL for bad arguments; E_RANGE if a point is not finite or its tile is
+ * outside +-(2^31 - 2) (that point's label is then -1; the others are
+ * written).  Calls on one result are serialised. */
+raster_status raster_result_point_labels(raster_result* r, const void* d_points, int64_t n, raster_dtype dt,
+                                         uint64_t* d_labels, hipStream_t stream);
+
 /* ---- streaming form (chunked input, Section 3.6) ---------------------------- */
 
 /* Start a stream.  tile_hint: expected number of distinct tiles (0 = unknown);

@@ -232,6 +232,33 @@ def cluster(points, tau: int, mu: int, precision: int | None = None,
         st.close()
 
 
+def point_labels(points, result: OracleResult, precision: int | None = None,
+                 scale: float | None = None):
+    """Per-point labels as in the paper's comparison experiment (Section 4):
+    the points are projected a second time (Section 3.2), and a point on a
+    tile of a kept cluster gets that cluster's label; the others get -1.  A
+    label is the cluster's smallest tile (label_x, label_y) written as
+    ((label_x + 2^31) << 32) | (label_y + 2^31), returned as int64 (two's
+    complement), so that -1 is never a label.  A tile (kx, ky) is looked up
+    among the result's tiles through the bijection kx * 2^32 + ky, which keeps
+    the lexicographic order for |k| <= 2^31 - 2."""
+    kx, ky = project(points, _scale(precision, scale))
+    out = np.full(kx.shape[0], -1, dtype=np.int64)
+    if result.num_tiles == 0 or kx.shape[0] == 0:
+        return out
+    tiles = result.kx.astype(np.int64) * (1 << 32) + result.ky.astype(np.int64)
+    order = np.argsort(tiles, kind="stable")
+    tiles = tiles[order]
+    lab = (((result.label_x[order].astype(np.int64) + (1 << 31)).astype(np.uint64) << np.uint64(32))
+           | (result.label_y[order].astype(np.int64) + (1 << 31)).astype(np.uint64)).view(np.int64)
+    q = kx * (1 << 32) + ky
+    pos = np.searchsorted(tiles, q)
+    hit = pos < tiles.shape[0]
+    hit[hit] = tiles[pos[hit]] == q[hit]
+    out[hit] = lab[pos[hit]]
+    return out
+
+
 def cluster_chunks(chunks, tau: int, mu: int, precision: int | None = None,
                    scale: float | None = None) -> OracleResult:
     """RASTER over an iterable of point chunks (Section 3.6)."""

@@ -92,6 +92,7 @@ def load():
         "raster_result_copy": (st, [vp, vp, vp, vp, vp, vp]),
         "raster_result_stats": (st, [vp, ctypes.POINTER(_Stats)]),
         "raster_result_free": (None, [vp]),
+        "raster_result_point_labels": (st, [vp, vp, i64, ctypes.c_int, vp, vp]),
         "raster_begin": (st, [i32, u32, u32, i64, vp, pp]),
         "raster_begin_scaled": (st, [dbl, u32, u32, i64, vp, pp]),
         "raster_feed_chunk": (st, [vp, vp, i64, ctypes.c_int]),
@@ -205,6 +206,18 @@ class Result:
             order = np.lexsort((ky, kx))
             kx, ky, cnt, lab = kx[order], ky[order], cnt[order], lab[order]
         return kx, ky, cnt, lab
+
+    def point_labels(self, points, stream=None):
+        """Label of every point (Section 4): the cluster label of its tile as
+        int64 (the biased key of the cluster's smallest tile, read as
+        two's complement), or -1 for a point on no kept tile."""
+        torch = _torch()
+        p, n, dt = _points(points)
+        out = torch.empty(n, dtype=torch.int64, device=points.device)
+        st = _stream_handle(stream if stream is not None else self._stream)
+        _check(load().raster_result_point_labels(self._h, p, n, dt, ctypes.c_void_p(out.data_ptr()), st),
+               "raster_result_point_labels")
+        return out
 
     def free(self):
         if self._h:

@@ -611,6 +611,7 @@ raster_status TableRun::finish(raster_result** out) {
 
     raster_result* r = new raster_result();
     r->pool = bufs.pool;
+    r->scale = scale;
     auto drop = [&](raster_status s) {
         raster_result_free(r);
         return s;
@@ -779,7 +780,60 @@ raster_status raster_result_stats(const raster_result* r, raster_stats* out) {
 void raster_result_free(raster_result* r) {
     if (!r) return;
     if (r->pool && r->block) r->pool->release(r->block);
+    if (r->lt) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        DevicePool& pool = DevicePool::get(dev);
+        pool.release(r->lt);
+        pool.release(r->lt_err);
+    }
     delete r;  // a shared block goes back to the pool with its last result
+}
+
+raster_status raster_result_point_labels(raster_result* r, const void* d_points, int64_t n, raster_dtype dt,
+                                         uint64_t* d_labels, hipStream_t stream) {
+    if (!r) return fail(RASTER_E_INVAL, "result is NULL");
+    raster_status st = check_points(d_points, n, dt);
+    if (st != RASTER_OK) return st;
+    if (n > 0 && !d_labels) return fail(RASTER_E_INVAL, "labels is NULL with n = %lld", (long long)n);
+    if (((uintptr_t)d_labels % 8) != 0) return fail(RASTER_E_INVAL, "labels must be 8-byte aligned");
+    if (n == 0) return RASTER_OK;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    DevicePool& pool = DevicePool::get(dev);
+    unsigned long long err = 0;
+    {
+        std::lock_guard<std::mutex> g(r->lt_mu);
+        if (!r->lt) {
+            // at most half full, so every lookup ends at an empty slot
+            const uint64_t cap = next_pow2(std::max<uint64_t>(64, 2 * (uint64_t)r->tiles));
+            void* tab = nullptr;
+            void* e = nullptr;
+            HIP_TRY(pool.alloc(&tab, 2 * cap * sizeof(uint64_t)), "label table");
+            if (pool.alloc(&e, sizeof(unsigned long long)) != hipSuccess) {
+                pool.release(tab);
+                return fail(RASTER_E_NOMEM, "label table: out of device memory");
+            }
+            const hipError_t le = launch_label_table(r->kx, r->ky, r->label, (uint64_t)r->tiles, (uint64_t*)tab, cap,
+                                                     stream);
+            if (le != hipSuccess) {
+                pool.release(tab);
+                pool.release(e);
+                return hip_fail(le, "label table");
+            }
+            r->lt = (uint64_t*)tab;
+            r->lt_err = (unsigned long long*)e;
+            r->lt_cap = cap;
+        }
+        HIP_TRY(launch_zero_u64((uint64_t*)r->lt_err, 1, stream), "zero flag");
+        HIP_TRY(launch_point_labels(d_points, n, (int)dt, r->scale, r->lt, r->lt_cap, d_labels, r->lt_err, stream),
+                "point labels");
+        HIP_TRY(hipMemcpyAsync(&err, r->lt_err, sizeof err, hipMemcpyDeviceToHost, stream), "flag copy");
+        HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    }
+    if (err & kErrRange)
+        return fail(RASTER_E_RANGE, "a coordinate is not finite or its tile is outside +-(2^31 - 2)");
+    return RASTER_OK;
 }
 
 raster_status raster_begin_scaled(double scale, uint32_t tau, uint32_t mu, int64_t tile_hint, hipStream_t stream,

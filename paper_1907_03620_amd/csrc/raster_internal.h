@@ -245,6 +245,14 @@ hipError_t launch_batch_count(const JobView& jv, const uint32_t* tile_prefix, Sl
 // partition.  cursor1 (ncoarse) and cursor2 (partitions) must be zero.
 // Distinct-tile sketch per job: HyperLogLog registers (2^kHllLog2 per job,
 // job-major, zeroed here) over a fixed 1/64 hash sample of each job's tiles.
+// Per-point labels: a lookup table {key, label} of t result rows (cap slots,
+// a power of two >= 2t; filled here), then the label of every point's tile
+// (UINT64_MAX for none; range errors set kErrRange in *err).
+hipError_t launch_label_table(const int32_t* kx, const int32_t* ky, const uint64_t* label, uint64_t t,
+                              uint64_t* tab, uint64_t cap, hipStream_t stream);
+hipError_t launch_point_labels(const void* pts, int64_t n, int dtype, double scale, const uint64_t* tab,
+                               uint64_t cap, uint64_t* out, unsigned long long* err, hipStream_t stream);
+
 // Distinct-tile sketch of one point set into hll (kHllReps replicas, not
 // zeroed here).
 hipError_t launch_points_hll(const void* pts, int64_t n, int dtype, double scale, uint32_t* hll,

@@ -937,6 +937,12 @@ __global__ void k_drain_bins(const uint64_t* bin1, uint64_t cap1, const uint32_t
     add_fresh(ctr, fresh);
 }
 
+__global__ void k_fill_words(uint64_t* p, uint64_t n, uint64_t v) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
 __global__ void k_snapshot_keys(unsigned long long* ctr) {
     if (threadIdx.x == 0) ctr[C_TABLE_KEYS] = ctr[C_INSERTED];
 }
@@ -1683,6 +1689,67 @@ __global__ __launch_bounds__(256) void k_batch_hll(JobView jv, const uint32_t* t
     }
 }
 
+// ---- per-point labels (the second projection pass of Section 4) -----------------
+//
+// A lookup table of a result's tiles: cap (a power of two) slots of two words
+// {biased key, cluster label}, empty key UINT64_MAX, home slot from the slot
+// hash, linear probing over the whole table.  Every point is then projected
+// again and its tile looked up.
+
+__global__ void k_label_table(const int32_t* kx, const int32_t* ky, const uint64_t* label, uint64_t t,
+                              uint64_t* tab, uint64_t cap) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < t;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = ((uint64_t)((uint32_t)kx[i] + 0x80000000u) << 32) | ((uint32_t)ky[i] + 0x80000000u);
+        uint64_t pos = slot_hash(key) & (cap - 1);
+        // the keys are distinct and the table is at most half full: a free
+        // slot is always found
+        while (atomicCAS(reinterpret_cast<unsigned long long*>(tab + 2 * pos), (unsigned long long)kEmptyKey,
+                         (unsigned long long)key) != kEmptyKey)
+            pos = (pos + 1) & (cap - 1);
+        tab[2 * pos + 1] = label[i];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_point_labels(const T* __restrict__ pts, int64_t n, double scale,
+                                                      const uint64_t* __restrict__ tab, uint64_t cap,
+                                                      uint64_t* __restrict__ out, unsigned long long* err) {
+    constexpr int U = 8;
+    bool bad = false;
+    for (int64_t i0 = (int64_t)blockIdx.x * U * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * U * blockDim.x) {
+        // loads of all items first (indices clamped, results masked)
+        double x[U], y[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) load_point(pts, min(i0 + (int64_t)u * blockDim.x + threadIdx.x, n - 1), x[u], y[u]);
+        uint64_t key[U], pos[U], cur[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            ok[u] = tile_key(x[u], y[u], scale, key[u]);
+            pos[u] = slot_hash(key[u]) & (cap - 1);
+            cur[u] = ok[u] ? tab[2 * pos[u]] : kEmptyKey;  // first probes together
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + (int64_t)u * blockDim.x + threadIdx.x;
+            if (i >= n) continue;
+            uint64_t lab = kEmptyKey;  // -1: the point is on no kept tile
+            if (!ok[u]) {
+                bad = true;
+            } else {
+                while (cur[u] != key[u] && cur[u] != kEmptyKey) {
+                    pos[u] = (pos[u] + 1) & (cap - 1);
+                    cur[u] = tab[2 * pos[u]];
+                }
+                if (cur[u] == key[u]) lab = tab[2 * pos[u] + 1];
+            }
+            out[i] = lab;
+        }
+    }
+    if (bad) atomicOr(err, (unsigned long long)kErrRange);
+}
+
 // ---- per-job ranges and statistics (batches) ----------------------------------
 
 __global__ void k_bounds(const uint32_t* seg_job, const unsigned long long* n_dev, uint32_t* start, uint32_t* end) {
@@ -2013,6 +2080,29 @@ hipError_t launch_batch_binned(const JobView& jv, const uint32_t* tile_prefix, c
     hipLaunchKernelGGL(k_bbin_keys, dim3(8192), dim3(BIN_THREADS), 0, stream, jv, cjob, bin1, cursor1, bin2, cursor2,
                        tab);
     hipLaunchKernelGGL(k_bagg, dim3(4096), dim3(AGG_THREADS), 0, stream, jv, bin2, cursor2, tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_label_table(const int32_t* kx, const int32_t* ky, const uint64_t* label, uint64_t t,
+                              uint64_t* tab, uint64_t cap, hipStream_t stream) {
+    hipLaunchKernelGGL(k_fill_words, dim3(grid_for(2 * cap, 256, kPersistBlocks)), dim3(256), 0, stream, tab,
+                       2 * cap, kEmptyKey);
+    if (t)
+        hipLaunchKernelGGL(k_label_table, dim3(grid_for(t, 256, kPersistBlocks)), dim3(256), 0, stream, kx, ky, label,
+                           t, tab, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_point_labels(const void* pts, int64_t n, int dtype, double scale, const uint64_t* tab,
+                               uint64_t cap, uint64_t* out, unsigned long long* err, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)grid_for((uint64_t)n, 256 * 8, 8192);
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_point_labels<float>, dim3(grid), dim3(256), 0, stream, static_cast<const float*>(pts), n,
+                           scale, tab, cap, out, err);
+    else
+        hipLaunchKernelGGL(k_point_labels<double>, dim3(grid), dim3(256), 0, stream,
+                           static_cast<const double*>(pts), n, scale, tab, cap, out, err);
     return hipGetLastError();
 }
 

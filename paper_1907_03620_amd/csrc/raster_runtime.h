@@ -31,6 +31,12 @@ struct raster_result {
     int64_t tiles = 0;
     int64_t clusters = 0;
     raster_stats stats{};
+    double scale = 0.0;  // the projection the result was computed with
+    // per-point labels: a lookup table of the rows, built on first use
+    std::mutex lt_mu;
+    uint64_t* lt = nullptr;
+    uint64_t lt_cap = 0;
+    unsigned long long* lt_err = nullptr;
 };
 
 namespace rst {

@@ -512,6 +512,7 @@ raster_status BatchEngine::run(const raster_job* jobs, int32_t n_jobs, hipStream
             return fail(RASTER_E_DEVICE, "job %d: counts sum to %llu, not %lld", i, c[C_SUM], (long long)jobs[i].n);
         raster_result* r = new raster_result();
         r->shared = owner;
+        r->scale = h_jobs[i].scale;
         const uint64_t off = c[C_TILES] ? o_start[i] : 0;
         r->label = lab + off;
         r->kx = kx + off;

@@ -151,3 +151,32 @@ def test_paper_stream_full_size_sampled(raster, torch):
         assert all(exact[t] < tau for t in ring), label
         assert len(_components(tiles)) == 1, label
         assert int(raster.biased_key([min(tiles)[0]], [min(tiles)[1]])[0]) == label
+    # per-point labels over all 500M points: each cluster holds exactly the
+    # points its tiles counted, the rest are noise, and sampled points carry
+    # the label of their tile as the oracle projects and looks it up
+    _say("paper-500M: per-point labels")
+    lab_i = lab.astype(np.uint64).view(np.int64)
+    labs_u, inv = np.unique(lab_i, return_inverse=True)
+    want_pts = np.bincount(inv, weights=cnt.astype(np.float64)).astype(np.int64)
+    lab_u = lab.astype(np.uint64)
+    rows = oracle.OracleResult(kx, ky, cnt.astype(np.uint64),
+                               (lab_u >> np.uint64(32)).astype(np.int64) - (1 << 31),
+                               (lab_u & np.uint64(0xFFFFFFFF)).astype(np.int64) - (1 << 31))
+    got_pts = np.zeros(labs_u.shape[0], np.int64)
+    noise = 0
+    for c, h in enumerate(host):
+        d = dev(h, torch)
+        pl = g.point_labels(d)
+        u, n_u = torch.unique(pl, return_counts=True)
+        u, n_u = u.cpu().numpy(), n_u.cpu().numpy()
+        noise += int(n_u[u == -1].sum())
+        keep = u != -1
+        pos = np.searchsorted(labs_u, u[keep])
+        assert (pos < labs_u.shape[0]).all() and np.array_equal(labs_u[pos], u[keep]), c
+        got_pts[pos] += n_u[keep]
+        sample = rng.choice(h.shape[0], size=20_000, replace=False)
+        want = oracle.point_labels(h[sample], rows, precision=2)
+        assert np.array_equal(pl[torch.from_numpy(sample).to(pl.device)].cpu().numpy(), want), c
+        del d, pl
+    assert np.array_equal(got_pts, want_pts)
+    assert noise == n_chunks * chunk - int(want_pts.sum())

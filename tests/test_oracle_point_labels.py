@@ -1,0 +1,150 @@
+"""Pins of the oracle's per-point labels (Section 4's per-point variant).
+
+A point on a tile of a kept cluster carries the cluster's label, packed as
+((label_x + 2^31) << 32) | (label_y + 2^31) and read as int64; every other
+point carries -1.  The expected values come from the paper's worked examples
+(tests/golden/), from packing written out with Python integers, and from the
+brute force of tests/brute.py; the last test plants mistakes in a copy of the
+oracle's function and checks that these pins catch each one.
+"""
+import json
+import os
+import sys
+import types
+
+import numpy as np
+import pytest
+
+from brute import brute_cluster
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _pack(lx, ly):
+    """The label word of tile (lx, ly) as a signed 64-bit Python integer."""
+    v = ((lx + (1 << 31)) << 32) | (ly + (1 << 31))
+    return v - (1 << 64) if v >= (1 << 63) else v
+
+
+def _labels(oracle_mod, pts, tau, mu, precision=None, scale=None):
+    r = oracle_mod.cluster(pts, tau=tau, mu=mu, precision=precision, scale=scale)
+    return oracle_mod.point_labels(pts, r, precision=precision, scale=scale).tolist()
+
+
+def pin_worked_example(oracle_mod):
+    g = _golden("worked_example.json")
+    pts = np.array(g["points"])
+    lab = _pack(*g["tile"])
+    assert lab == 0x8000006480000064 - (1 << 64)
+    for tau in range(1, g["significant_for_tau_at_most"] + 2):
+        want = [lab] * len(pts) if tau <= g["significant_for_tau_at_most"] else [-1] * len(pts)
+        assert _labels(oracle_mod, pts, tau, 1, precision=g["precision"]) == want
+
+
+def pin_fig4_corner(oracle_mod):
+    g = _golden("fig4_grid_corner.json")
+    pts = np.array(g["points"])
+    assert _labels(oracle_mod, pts, 1, 4, precision=g["precision"]) == [_pack(*g["tau1_mu4_label"])] * 4
+    assert _labels(oracle_mod, pts, 1, 5, precision=g["precision"]) == [-1] * 4
+    assert _labels(oracle_mod, pts, 4, 1, precision=g["precision"]) == [-1] * 4
+
+
+def pin_negative_tiles_and_order(oracle_mod):
+    # two clusters on the negative side; points given in an order unlike the tiles'
+    pts = np.array([[-0.15, -0.15], [0.55, 0.05], [-0.15, -0.05], [0.55, 0.15], [3.0, 3.0], [-0.15, -0.15]])
+    got = _labels(oracle_mod, pts, 1, 2, precision=1)
+    a, b = _pack(-1, -1), _pack(5, 0)
+    assert a == 0x7FFFFFFF7FFFFFFF
+    assert got == [a, b, a, b, -1, a]
+
+
+def pin_lookup_needs_both_axes(oracle_mod):
+    # tiles (1, 2) and (2, 1) are far apart; a query on (2, 1) must not find (1, 2)
+    pts = np.array([[1.5, 2.5]] * 3 + [[2.5, 1.5]])
+    assert _labels(oracle_mod, pts, 3, 1, precision=0) == [_pack(1, 2)] * 3 + [-1]
+
+
+def pin_counts_per_label(oracle_mod):
+    rng = np.random.default_rng(3)
+    pts = np.concatenate([rng.normal(c, 0.25, size=(400, 2)) for c in ((0, 0), (3, 1), (-2, 4))]
+                         + [rng.uniform(-5, 5, size=(300, 2))])
+    r = oracle_mod.cluster(pts, tau=3, mu=3, precision=1)
+    got = oracle_mod.point_labels(pts, r, precision=1)
+    packed = [_pack(int(x), int(y)) for x, y in zip(r.label_x, r.label_y)]
+    want = {}
+    for lab, c in zip(packed, r.count):
+        want[lab] = want.get(lab, 0) + int(c)
+    labs, cnt = np.unique(got[got != -1], return_counts=True)
+    assert dict(zip(labs.tolist(), cnt.tolist())) == want
+    assert int((got == -1).sum()) == pts.shape[0] - sum(want.values())
+
+
+def pin_brute_force(oracle_mod):
+    for seed in range(120):
+        rng = np.random.default_rng(500 + seed)
+        n = int(rng.integers(0, 200))
+        pts = rng.uniform(-1.0, 1.0, size=2) + rng.normal(0.0, 0.4, size=(n, 2))
+        if seed % 4 == 0:
+            pts = pts.astype(np.float32)
+        p, tau, mu = int(rng.integers(0, 3)), int(rng.integers(1, 5)), int(rng.integers(1, 5))
+        s = oracle_mod.scale_for_precision(p)
+        rows, _ = brute_cluster(pts, s, tau, mu)
+        tile_label = {(kx, ky): _pack(lx, ly) for kx, ky, _, lx, ly in rows}
+        a = np.asarray(pts).astype(np.float64)
+        k = np.trunc(a * s).astype(np.int64)
+        want = [tile_label.get((int(x), int(y)), -1) for x, y in k]
+        assert _labels(oracle_mod, pts, tau, mu, scale=s) == want, seed
+
+
+PINS = [pin_worked_example, pin_fig4_corner, pin_negative_tiles_and_order, pin_lookup_needs_both_axes,
+        pin_counts_per_label, pin_brute_force]
+
+
+@pytest.mark.parametrize("pin", PINS, ids=[f.__name__ for f in PINS])
+def test_point_label_pin(oracle_mod, pin):
+    pin(oracle_mod)
+
+
+def test_point_labels_of_empty_input(oracle_mod):
+    r = oracle_mod.cluster(np.zeros((0, 2)), tau=1, mu=1, precision=0)
+    assert oracle_mod.point_labels(np.zeros((0, 2)), r, precision=0).shape == (0,)
+    r = oracle_mod.cluster(np.array([[0.5, 0.5]]), tau=1, mu=1, precision=0)
+    assert oracle_mod.point_labels(np.zeros((0, 2)), r, precision=0).shape == (0,)
+
+
+MUTANTS = {
+    "halves_swapped": ("(((result.label_x[order]", "(((result.label_y[order]"),
+    "no_bias_on_y": ("| (result.label_y[order].astype(np.int64) + (1 << 31))",
+                     "| (result.label_y[order].astype(np.int64))"),
+    "query_axes_swapped": ("q = kx * (1 << 32) + ky", "q = ky * (1 << 32) + kx"),
+    "noise_is_zero": ("out = np.full(kx.shape[0], -1, dtype=np.int64)",
+                      "out = np.full(kx.shape[0], 0, dtype=np.int64)"),
+    "nearest_not_equal": ("hit[hit] = tiles[pos[hit]] == q[hit]", "pass"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_label_mistake(oracle_mod, name):
+    old, new = MUTANTS[name]
+    src = open(os.path.join(ROOT, "oracle", "__init__.py")).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not found"
+    mod = types.ModuleType("oracle_mutant")
+    mod.__file__ = os.path.join(ROOT, "oracle", "__init__.py")
+    sys.modules[mod.__name__] = mod     # dataclasses look their module up there
+    try:
+        exec(compile(src.replace(old, new), mod.__file__, "exec"), mod.__dict__)
+    finally:
+        sys.modules.pop(mod.__name__, None)
+    caught = []
+    for pin in PINS:
+        try:
+            pin(mod)
+        except AssertionError:
+            caught.append(pin.__name__)
+    assert caught, f"mutant {name} passed every point-label pin"
