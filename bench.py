@@ -9,7 +9,9 @@ chunks, finish (significance scan, union-find agglomeration, mu filter).
 Prints one JSON line with points/s, the counting kernel's roofline (HIP-event
 duration per launch against the 8 TB/s HBM peak, algorithmic bytes = 16 bytes
 of FP64 coordinates per point) and the CPU oracle timed on a bounded sample
-of the same workload on this host.
+of the same workload on this host.  After the timed steps it also times the
+per-point label pass over all 500M resident points (Section 4.1), the 256-job
+batch against plain calls, and the server on a Poisson trace.
 """
 from __future__ import annotations
 
@@ -35,13 +37,23 @@ def log(msg):
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the kernel source's code: comments and blank lines are dropped,
+    so that editing a comment does not void the recorded counters."""
+    import re
+    with open(KERNEL_SRC) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    code = "\n".join(l.rstrip() for l in src.splitlines() if l.strip())
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
-def measured_traffic(per_launch_points: int):
-    """HBM bytes per counting launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
+def measured_traffic(per_launch_points: int, key: str = "hbm_bytes_per_launch"):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source with launches of
+    the same size; else None.  ``key`` picks the kernel: the counting kernel
+    (hbm_bytes_per_launch) or the per-point label kernel
+    (labels_hbm_bytes_per_launch)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -51,9 +63,9 @@ def measured_traffic(per_launch_points: int):
             kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    if int(kv.get("points_per_launch", -1)) != per_launch_points:
+    if int(kv.get("points_per_launch", -1)) != per_launch_points or key not in kv:
         return None
-    return float(kv["hbm_bytes_per_launch"])
+    return float(kv[key])
 
 
 def gen_paper_scale(n_chunks: int, chunk: int):
@@ -83,10 +95,52 @@ def cpu_baseline(host_chunks, strip: float, precision: int, tau: int, mu: int):
         os.sched_setaffinity(0, set(range(os.cpu_count() or 1)))
     except (AttributeError, OSError):
         pass
-    return dict(value=sample.shape[0] / dt, unit="points/s", cores=1, kind="oracle",
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
+    return dict(value=sample.shape[0] / dt, unit="points/s", cores=1, kind="oracle", cpu=model,
                 sample=(f"x in [0, {strip:g}) strip of all chunks: {sample.shape[0]} points "
                         f"({res.stats['clusters']} clusters), full Algorithm 1, {dt:.1f} s"),
                 seconds=dt, points=int(sample.shape[0]))
+
+
+def bench_point_labels(raster, torch, res, dev, reps: int = 3):
+    """Per-point labels (Section 4.1) of every resident point from one step's
+    result: one call per chunk on the current stream, each bracketed by HIP
+    events on that stream.  The first call builds the result's lookup table
+    and is not timed.  Algorithmic bytes per point: 16 of FP64 coordinates
+    read, one 16-byte table slot read, 8 bytes of label written."""
+    import numpy as np
+    s = torch.cuda.current_stream()
+    res.point_labels(dev[0], stream=s)
+    torch.cuda.synchronize()
+    per_call, passes, noise = [], [], 0
+    for r in range(reps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * len(dev))]
+        for k, d in enumerate(dev):
+            ev[2 * k].record(s)
+            lab = res.point_labels(d, stream=s)
+            ev[2 * k + 1].record(s)
+            if r == 0:
+                noise += int((lab == -1).sum().item())
+        torch.cuda.synchronize()
+        calls = [ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(len(dev))]
+        per_call += calls
+        passes.append(sum(calls))
+    n = sum(int(d.shape[0]) for d in dev)
+    ms = float(np.median(passes))
+    avg_call_us = 1000.0 * float(np.mean(per_call))
+    per_launch = n / len(dev)
+    gbps = 40.0 * per_launch / (avg_call_us * 1e-6) / 1e9
+    return {"points": n, "ms_per_pass": ms, "points_per_s": n / (ms * 1e-3),
+            "avg_launch_us": avg_call_us, "launches_per_pass": len(dev),
+            "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
+            "algorithmic_bytes": "40 B per point: 16 of coordinates in, one 16-byte slot, 8 of label out",
+            "traffic": measured_traffic(int(per_launch), "labels_hbm_bytes_per_launch"),
+            "noise_points": noise}
 
 
 def pct(values, q):
@@ -272,6 +326,7 @@ def main():
     ap.add_argument("--cpu-strip", type=float, default=2000.0)
     ap.add_argument("--tuning", default="", help="JSON object of raster_tuning fields")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (256-job) comparison")
+    ap.add_argument("--no-point-labels", action="store_true", help="skip the per-point label pass")
     ap.add_argument("--no-served", action="store_true", help="skip the served (Poisson trace) comparison")
     ap.add_argument("--served-seconds", type=float, default=10.0)
     ap.add_argument("--served-rate", type=float, default=200.0)
@@ -324,7 +379,7 @@ def main():
 
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
-        res = step()
+        step()
     log(f"timing {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -388,7 +443,8 @@ def main():
                    "table_capacity": st["table_capacity"], "grow_events": st["grow_events"]},
         "cpu_baseline": None,
     }
-    del dev
+    line["point_labels"] = None if args.no_point_labels else bench_point_labels(raster, torch, results[-1], dev)
+    del dev, results
     torch.cuda.empty_cache()
     line["batched"] = None if args.no_batched else bench_batched(raster, torch, 256, 3)
     line["served"] = None if args.no_served else bench_served(raster, torch, args.served_seconds, args.served_rate,

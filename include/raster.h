@@ -137,7 +137,7 @@ raster_status raster_result_stats(const raster_result* r, raster_stats* out);
 void raster_result_free(raster_result* r);
 
 /* Per-point labels: the label of every input point, obtained as in the
- * paper's comparison experiment (Section 4, its RASTER-star variant) by
+ * paper's comparison experiment (Section 4.1, its RASTER-star variant) by
  * projecting the points a second time.  Each of the n points of d_points
  * ((n, 2) row-major, dt as for clustering, borrowed for the call) is projected
  * with the scale the result was computed with; d_labels[i] (caller-owned

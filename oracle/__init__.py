@@ -234,7 +234,7 @@ def cluster(points, tau: int, mu: int, precision: int | None = None,
 
 def point_labels(points, result: OracleResult, precision: int | None = None,
                  scale: float | None = None):
-    """Per-point labels as in the paper's comparison experiment (Section 4):
+    """Per-point labels as in the paper's comparison experiment (Section 4.1, RASTER-star):
     the points are projected a second time (Section 3.2), and a point on a
     tile of a kept cluster gets that cluster's label; the others get -1.  A
     label is the cluster's smallest tile (label_x, label_y) written as

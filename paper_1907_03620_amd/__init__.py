@@ -208,7 +208,7 @@ class Result:
         return kx, ky, cnt, lab
 
     def point_labels(self, points, stream=None):
-        """Label of every point (Section 4): the cluster label of its tile as
+        """Label of every point (Section 4.1, RASTER-star): the cluster label of its tile as
         int64 (the biased key of the cluster's smallest tile, read as
         two's complement), or -1 for a point on no kept tile."""
         torch = _torch()

@@ -1689,7 +1689,7 @@ __global__ __launch_bounds__(256) void k_batch_hll(JobView jv, const uint32_t* t
     }
 }
 
-// ---- per-point labels (the second projection pass of Section 4) -----------------
+// ---- per-point labels (the second projection pass of Section 4.1) ---------------
 //
 // A lookup table of a result's tiles: cap (a power of two) slots of two words
 // {biased key, cluster label}, empty key UINT64_MAX, home slot from the slot
@@ -1715,6 +1715,10 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_point_labels(const T* __restrict__ pts, int64_t n, double scale,
                                                       const uint64_t* __restrict__ tab, uint64_t cap,
                                                       uint64_t* __restrict__ out, unsigned long long* err) {
+    // One slot is {key, label}, 16-byte aligned, read by a single 16-byte load:
+    // the label arrives with the key compare instead of a second round trip.
+    typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+    const u64x2* __restrict__ slots = reinterpret_cast<const u64x2*>(tab);
     constexpr int U = 8;
     bool bad = false;
     for (int64_t i0 = (int64_t)blockIdx.x * U * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * U * blockDim.x) {
@@ -1722,13 +1726,15 @@ __global__ __launch_bounds__(256) void k_point_labels(const T* __restrict__ pts,
         double x[U], y[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) load_point(pts, min(i0 + (int64_t)u * blockDim.x + threadIdx.x, n - 1), x[u], y[u]);
-        uint64_t key[U], pos[U], cur[U];
+        uint64_t key[U], pos[U];
+        u64x2 cur[U];
         bool ok[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
+            key[u] = 0;
             ok[u] = tile_key(x[u], y[u], scale, key[u]);
             pos[u] = slot_hash(key[u]) & (cap - 1);
-            cur[u] = ok[u] ? tab[2 * pos[u]] : kEmptyKey;  // first probes together
+            cur[u] = slots[pos[u]];  // first probes together; a bad key's probe is discarded
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1738,11 +1744,12 @@ __global__ __launch_bounds__(256) void k_point_labels(const T* __restrict__ pts,
             if (!ok[u]) {
                 bad = true;
             } else {
-                while (cur[u] != key[u] && cur[u] != kEmptyKey) {
+                // the table is at most half full: the walk ends at the key or an empty slot
+                while (cur[u].x != key[u] && cur[u].x != kEmptyKey) {
                     pos[u] = (pos[u] + 1) & (cap - 1);
-                    cur[u] = tab[2 * pos[u]];
+                    cur[u] = slots[pos[u]];
                 }
-                if (cur[u] == key[u]) lab = tab[2 * pos[u] + 1];
+                if (cur[u].x == key[u]) lab = cur[u].y;
             }
             out[i] = lab;
         }

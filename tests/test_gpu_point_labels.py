@@ -1,6 +1,6 @@
 """Per-point labels on the GPU against the oracle, element by element.
 
-Every point gets the label of its tile's cluster (Section 4's per-point
+Every point gets the label of its tile's cluster (Section 4.1's per-point
 variant) or -1.  The lookup table the library builds from a result is reused
 by later calls; points that were not part of the clustering, empty inputs,
 results without tiles and range errors are covered as well as plain, chunked

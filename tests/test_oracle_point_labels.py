@@ -1,4 +1,4 @@
-"""Pins of the oracle's per-point labels (Section 4's per-point variant).
+"""Pins of the oracle's per-point labels (Section 4.1's RASTER-star).
 
 A point on a tile of a kept cluster carries the cluster's label, packed as
 ((label_x + 2^31) << 32) | (label_y + 2^31) and read as int64; every other
