@@ -102,6 +102,7 @@ def cpu_baseline(host_chunks, strip: float, precision: int, tau: int, mu: int):
     except OSError:
         pass
     return dict(value=sample.shape[0] / dt, unit="points/s", cores=1, kind="oracle", cpu=model,
+                host_cpus=os.cpu_count(),
                 sample=(f"x in [0, {strip:g}) strip of all chunks: {sample.shape[0]} points "
                         f"({res.stats['clusters']} clusters), full Algorithm 1, {dt:.1f} s"),
                 seconds=dt, points=int(sample.shape[0]))
@@ -141,6 +142,58 @@ def bench_point_labels(raster, torch, res, dev, reps: int = 3):
             "algorithmic_bytes": "40 B per point: 16 of coordinates in, one 16-byte slot, 8 of label out",
             "traffic": measured_traffic(int(per_launch), "labels_hbm_bytes_per_launch"),
             "noise_points": noise}
+
+
+def bench_h2d_stream(raster, torch, host, precision: int, tau: int, mu: int, reps: int = 2):
+    """Context only, never `value`: the same stream with the chunks in pinned
+    host memory.  Each chunk is copied on a copy stream into one of two device
+    buffers while the previous chunk is counted; the compute stream waits for
+    the copy, and a copy waits until the chunk that used its buffer two steps
+    earlier has been fed.  Bound by the host link."""
+    import numpy as np
+    pinned = [torch.from_numpy(h).pin_memory() for h in host]
+    rows = max(p.shape[0] for p in pinned)
+    bufs = [torch.empty((rows, 2), dtype=pinned[0].dtype, device="cuda") for _ in range(2)]
+    comp = torch.cuda.current_stream()
+    copy = torch.cuda.Stream()
+
+    def run():
+        free = [None, None]
+        st = raster.Stream(tau=tau, mu=mu, precision=precision, stream=comp)
+        for k, p in enumerate(pinned):
+            b = k % 2
+            buf = bufs[b][: p.shape[0]]
+            with torch.cuda.stream(copy):
+                if free[b] is not None:
+                    copy.wait_event(free[b])
+                buf.copy_(p, non_blocking=True)
+                done = torch.cuda.Event()
+                done.record(copy)
+            comp.wait_event(done)
+            st.feed(buf)
+            free[b] = torch.cuda.Event()
+            free[b].record(comp)
+        res = st.finish()
+        st.close()
+        return res
+
+    first = run()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        res = run()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    n = sum(int(p.shape[0]) for p in pinned)
+    nbytes = sum(p.numel() * p.element_size() for p in pinned)
+    sec = float(np.median(times))
+    same = all(res.stats[k] == first.stats[k] for k in ("tiles", "clusters", "distinct_tiles"))
+    del pinned, bufs
+    return {"ms_per_step": 1000.0 * sec, "points_per_s": n / sec, "host_to_device_gb_per_s": nbytes / sec / 1e9,
+            "clusters": int(res.stats["clusters"]), "same_result_as_first_run": bool(same),
+            "how": "chunks in pinned host memory, copied on a second stream into two device buffers, "
+                   "overlapped with counting; median of %d runs after one warm-up" % reps}
 
 
 def pct(values, q):
@@ -316,7 +369,7 @@ def served_run(raster, torch, pool64, pool32, duration_s: float, rate: float, sl
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--chunks", type=int, default=10)
     ap.add_argument("--chunk", type=int, default=50_000_000)
@@ -326,6 +379,7 @@ def main():
     ap.add_argument("--cpu-strip", type=float, default=2000.0)
     ap.add_argument("--tuning", default="", help="JSON object of raster_tuning fields")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (256-job) comparison")
+    ap.add_argument("--no-h2d", action="store_true", help="skip the host-to-device streaming run")
     ap.add_argument("--no-point-labels", action="store_true", help="skip the per-point label pass")
     ap.add_argument("--no-served", action="store_true", help="skip the served (Poisson trace) comparison")
     ap.add_argument("--served-seconds", type=float, default=10.0)
@@ -446,6 +500,12 @@ def main():
     line["point_labels"] = None if args.no_point_labels else bench_point_labels(raster, torch, results[-1], dev)
     del dev, results
     torch.cuda.empty_cache()
+    line["h2d_stream"] = None
+    if not args.no_h2d:
+        log("host-to-device stream (pinned chunks, two buffers)")
+        line["h2d_stream"] = bench_h2d_stream(raster, torch, host, precision, tau, mu)
+        line["h2d_stream"]["resident_clusters"] = st["clusters"]
+        torch.cuda.empty_cache()
     line["batched"] = None if args.no_batched else bench_batched(raster, torch, 256, 3)
     line["served"] = None if args.no_served else bench_served(raster, torch, args.served_seconds, args.served_rate,
                                                               args.served_slots, args.served_stress_rate)
