@@ -76,13 +76,17 @@ def gen_paper_scale(n_chunks: int, chunk: int):
                                                              n_chunks=n_chunks), range(n_chunks)))
 
 
-def cpu_baseline(host_chunks, strip: float, precision: int, tau: int, mu: int):
-    """Times the oracle, single-threaded and pinned to one core, on the points
-    of every chunk whose x lies in [0, strip): a strip of the canvas with the
-    full workload's density."""
+def strip_sample(host_chunks, strip: float):
+    """The points of every chunk whose x lies in [0, strip): a strip of the
+    canvas with the full workload's density."""
     import numpy as np
+    return np.concatenate([h[h[:, 0] < strip] for h in host_chunks])
+
+
+def cpu_baseline(sample, strip: float, precision: int, tau: int, mu: int):
+    """Times the oracle, single-threaded and pinned to one core, on the strip
+    sample."""
     import oracle
-    sample = np.concatenate([h[h[:, 0] < strip] for h in host_chunks])
     try:
         cpu = sorted(os.sched_getaffinity(0))[0]
         os.sched_setaffinity(0, {cpu})
@@ -105,7 +109,28 @@ def cpu_baseline(host_chunks, strip: float, precision: int, tau: int, mu: int):
                 host_cpus=os.cpu_count(),
                 sample=(f"x in [0, {strip:g}) strip of all chunks: {sample.shape[0]} points "
                         f"({res.stats['clusters']} clusters), full Algorithm 1, {dt:.1f} s"),
-                seconds=dt, points=int(sample.shape[0]))
+                seconds=dt, points=int(sample.shape[0]), clusters=int(res.stats["clusters"]))
+
+
+def cpu_p_raster(sample, precision: int, tau: int, mu: int):
+    """Times the multi-core P-RASTER baseline (Section 3.5) on the same strip
+    sample, on up to 16 host threads, after one untimed run."""
+    import cpu_baseline as cb
+    threads = cb.default_threads()
+    scale = float(10 ** precision)
+    cb.cluster(sample[: min(len(sample), 1_000_000)], tau=tau, mu=mu, scale=scale, threads=threads)
+    t0 = time.perf_counter()
+    res = cb.cluster(sample, tau=tau, mu=mu, scale=scale, threads=threads)
+    dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    one = cb.cluster(sample, tau=tau, mu=mu, scale=scale, threads=1)
+    dt1 = time.perf_counter() - t1
+    return dict(value=sample.shape[0] / dt, unit="points/s", cores=threads, kind="P-RASTER (Algorithms 2 and 3)",
+                seconds=dt, phases_s=res.stats["seconds"], clusters=res.stats["clusters"],
+                one_thread_seconds=dt1, speedup_over_one_thread=dt1 / dt,
+                same_clusters_one_thread=bool(one.stats["clusters"] == res.stats["clusters"]
+                                              and one.num_tiles == res.num_tiles),
+                sample="the same strip as cpu_baseline")
 
 
 def bench_point_labels(raster, torch, res, dev, reps: int = 3):
@@ -509,9 +534,15 @@ def main():
     line["batched"] = None if args.no_batched else bench_batched(raster, torch, 256, 3)
     line["served"] = None if args.no_served else bench_served(raster, torch, args.served_seconds, args.served_rate,
                                                               args.served_slots, args.served_stress_rate)
+    line["cpu_p_raster"] = None
     if not args.no_cpu_baseline:
+        sample = strip_sample(host, args.cpu_strip)
         log("cpu baseline (oracle, one core)")
-        line["cpu_baseline"] = cpu_baseline(host, args.cpu_strip, precision, tau, mu)
+        line["cpu_baseline"] = cpu_baseline(sample, args.cpu_strip, precision, tau, mu)
+        log("cpu P-RASTER (host threads)")
+        line["cpu_p_raster"] = cpu_p_raster(sample, precision, tau, mu)
+        line["cpu_p_raster"]["same_clusters_as_oracle"] = (line["cpu_p_raster"]["clusters"]
+                                                           == line["cpu_baseline"]["clusters"])
     print(json.dumps(line), flush=True)
 
 
