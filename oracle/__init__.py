@@ -62,6 +62,8 @@ def _load():
     lib.oracle_project.restype = ctypes.c_int
     lib.oracle_begin.argtypes = [dbl, u64, u64]
     lib.oracle_begin.restype = vp
+    lib.oracle_begin_ex.argtypes = [dbl, u64, u64, i32, i64]
+    lib.oracle_begin_ex.restype = vp
     lib.oracle_feed.argtypes = [vp, vp, i64, i32]
     lib.oracle_feed.restype = ctypes.c_int
     lib.oracle_num_tiles.argtypes = [vp]
@@ -148,12 +150,17 @@ class OracleResult:
         return int(self.stats.get("clusters", 0))
 
 
-class OracleStream:
-    """Chunked contraction (Section 3.6) followed by one agglomeration."""
+METRICS = {"chebyshev": 0, "manhattan": 1}
 
-    def __init__(self, scale: float, tau: int, mu: int):
+
+class OracleStream:
+    """Chunked contraction (Section 3.6) followed by one agglomeration.
+    Clusters join significant tiles within ``delta`` steps of each other in
+    the given metric (Section 3.2); the default is the eight adjacent tiles."""
+
+    def __init__(self, scale: float, tau: int, mu: int, metric: str = "chebyshev", delta: int = 1):
         self._lib = _load()
-        self._h = self._lib.oracle_begin(float(scale), int(tau), int(mu))
+        self._h = self._lib.oracle_begin_ex(float(scale), int(tau), int(mu), METRICS[metric], int(delta))
         if not self._h:
             raise OracleError(E_INVAL, "begin")
 
@@ -222,9 +229,9 @@ def _scale(precision, scale):
 
 
 def cluster(points, tau: int, mu: int, precision: int | None = None,
-            scale: float | None = None) -> OracleResult:
+            scale: float | None = None, metric: str = "chebyshev", delta: int = 1) -> OracleResult:
     """RASTER on one in-memory point set."""
-    st = OracleStream(_scale(precision, scale), tau, mu)
+    st = OracleStream(_scale(precision, scale), tau, mu, metric, delta)
     try:
         st.feed(points)
         return st.finish()
@@ -260,9 +267,9 @@ def point_labels(points, result: OracleResult, precision: int | None = None,
 
 
 def cluster_chunks(chunks, tau: int, mu: int, precision: int | None = None,
-                   scale: float | None = None) -> OracleResult:
+                   scale: float | None = None, metric: str = "chebyshev", delta: int = 1) -> OracleResult:
     """RASTER over an iterable of point chunks (Section 3.6)."""
-    st = OracleStream(_scale(precision, scale), tau, mu)
+    st = OracleStream(_scale(precision, scale), tau, mu, metric, delta)
     try:
         for c in chunks:
             st.feed(c)

@@ -21,8 +21,11 @@
 //     the whole chunk is then rejected and the stream fails.
 //   * Significant means count >= tau (Algorithm 1 removes tiles whose count is
 //     below tau).  tau = 0 and mu = 0 are invalid arguments.
-//   * neighbors(u, delta) is the Chebyshev-1 neighbourhood (Section 3.2: all
-//     eight adjacent tiles); only significant tiles are taken into a cluster.
+//   * neighbors(u, delta) holds the tiles at Chebyshev distance 1 to delta
+//     (metric 0) or Manhattan distance 1 to delta (metric 1) from u
+//     (Section 3.2 names both metrics and a distance delta; the paper's own
+//     code uses Chebyshev 1, the eight adjacent tiles, which is the default
+//     here).  Only significant tiles are taken into a cluster.
 //   * A cluster is kept when it holds at least mu tiles.
 //   * Each kept tile is reported with its count and the lexicographically
 //     smallest (kx, ky) of its cluster as the cluster's label; output is sorted
@@ -72,6 +75,8 @@ int project_coord(double v, double scale, int64_t* k) {
 struct OracleStream {
     double scale;
     uint64_t tau, mu;
+    int32_t metric = 0;  // 0: Chebyshev, 1: Manhattan
+    int64_t delta = 1;
     bool failed = false;
     bool finished = false;
     uint64_t n_points = 0;
@@ -113,14 +118,20 @@ int oracle_project(const void* pts, int64_t n, int32_t dtype, double scale,
     return kOK;
 }
 
-void* oracle_begin(double scale, uint64_t tau, uint64_t mu) {
+// metric: 0 = Chebyshev, 1 = Manhattan; 1 <= delta <= 64.
+void* oracle_begin_ex(double scale, uint64_t tau, uint64_t mu, int32_t metric, int64_t delta) {
     if (!(scale > 0.0) || !std::isfinite(scale) || tau == 0 || mu == 0) return nullptr;
+    if ((metric != 0 && metric != 1) || delta < 1 || delta > 64) return nullptr;
     OracleStream* s = new OracleStream();
     s->scale = scale;
     s->tau = tau;
     s->mu = mu;
+    s->metric = metric;
+    s->delta = delta;
     return s;
 }
+
+void* oracle_begin(double scale, uint64_t tau, uint64_t mu) { return oracle_begin_ex(scale, tau, mu, 0, 1); }
 
 // Contraction over one chunk of points (Algorithm 1, first loop).  Chunks may
 // come in any number and order (Section 3.6).  The chunk is checked first, so a
@@ -207,9 +218,11 @@ int oracle_finish(void* h) {
             cluster.push_back(u);
             // ns = neighbours of u that are still in sigma; drop them from
             // sigma and queue them for the visit.
-            for (int64_t dx = -1; dx <= 1; ++dx) {
-                for (int64_t dy = -1; dy <= 1; ++dy) {
+            const int64_t d = s->delta;
+            for (int64_t dx = -d; dx <= d; ++dx) {
+                for (int64_t dy = -d; dy <= d; ++dy) {
                     if (dx == 0 && dy == 0) continue;
+                    if (s->metric == 1 && std::llabs(dx) + std::llabs(dy) > d) continue;
                     Tile v{u.x + dx, u.y + dy};
                     auto it = sigma.find(v);
                     if (it != sigma.end()) {

@@ -5,9 +5,9 @@ run-length encoding (numpy ``unique``) instead of a hash map, and clusters are
 found from an explicit O(T^2) adjacency matrix with breadth-first search
 instead of a depth-first walk over hash lookups.  Each step is a direct
 reading of the paper: projection by scaling and truncation (Section 3.2),
-significance as count >= tau, adjacency as Chebyshev distance 1 (all eight
-neighbours, Section 3.2), clusters kept when they hold at least mu tiles
-(Algorithm 1).
+significance as count >= tau, adjacency as a Chebyshev or Manhattan
+distance between 1 and delta (Section 3.2; by default Chebyshev 1, all eight
+neighbours), clusters kept when they hold at least mu tiles (Algorithm 1).
 """
 from __future__ import annotations
 
@@ -31,17 +31,20 @@ def brute_tile_counts(points, scale: float):
     return tiles, counts
 
 
-def brute_cluster(points, scale: float, tau: int, mu: int):
+def brute_cluster(points, scale: float, tau: int, mu: int, metric: str = "chebyshev", delta: int = 1):
     """Returns rows (kx, ky, count, label_x, label_y) sorted by tile, plus the
-    number of kept clusters."""
+    number of kept clusters.  Two significant tiles are adjacent when their
+    distance in ``metric`` is between 1 and ``delta`` (Section 3.2)."""
     tiles, counts = brute_tile_counts(points, scale)
     sig = counts >= tau
     st, sc = tiles[sig], counts[sig]
     t = st.shape[0]
     if t == 0:
         return [], 0
-    d = np.maximum(np.abs(st[:, None, 0] - st[None, :, 0]), np.abs(st[:, None, 1] - st[None, :, 1]))
-    adj = d == 1
+    ax = np.abs(st[:, None, 0] - st[None, :, 0])
+    ay = np.abs(st[:, None, 1] - st[None, :, 1])
+    d = np.maximum(ax, ay) if metric == "chebyshev" else ax + ay
+    adj = (d >= 1) & (d <= delta)
     comp = -np.ones(t, np.int64)
     ncomp = 0
     for s in range(t):

@@ -55,3 +55,17 @@ def test_tile_counts_match_sort_and_run_length(oracle_mod, seed):
     assert ky.tolist() == tiles[:, 1].tolist() if len(tiles) else ky.size == 0
     assert c.tolist() == counts.tolist()
     assert int(c.sum()) == pts.shape[0]
+
+
+@pytest.mark.parametrize("metric,delta", [("chebyshev", 2), ("chebyshev", 3), ("manhattan", 1),
+                                          ("manhattan", 2), ("manhattan", 4)])
+def test_oracle_matches_brute_force_delta(oracle_mod, metric, delta):
+    for seed in range(2000, 2080):
+        pts, p, tau, mu = _case(seed)
+        s = oracle_mod.scale_for_precision(p)
+        rows, kept = brute_cluster(pts, s, tau, mu, metric, delta)
+        r = oracle_mod.cluster(pts, tau=tau, mu=mu, scale=s, metric=metric, delta=delta)
+        got = [(int(a), int(b), int(c), int(d), int(e)) for a, b, c, d, e in
+               zip(r.kx, r.ky, r.count, r.label_x, r.label_y)]
+        assert got == rows, (seed, metric, delta)
+        assert r.stats["clusters"] == kept, seed

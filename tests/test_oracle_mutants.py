@@ -19,7 +19,11 @@ MUTANTS = {
     "round_not_trunc": ("*k = (int64_t)std::trunc(p);", "*k = (int64_t)std::llround(p);"),
     "fp32_product": ("double p = v * scale;", "double p = (double)((float)v * (float)scale);"),
     "four_neighbours": ("if (dx == 0 && dy == 0) continue;", "if (dx == dy || dx == -dy) continue;"),
-    "one_sided_neighbours": ("for (int64_t dx = -1; dx <= 1; ++dx) {", "for (int64_t dx = -1; dx <= 0; ++dx) {"),
+    "one_sided_neighbours": ("for (int64_t dx = -d; dx <= d; ++dx) {", "for (int64_t dx = -d; dx <= 0; ++dx) {"),
+    "delta_ignored": ("const int64_t d = s->delta;", "const int64_t d = 1;"),
+    "manhattan_as_chebyshev": ("if (s->metric == 1 && std::llabs(dx) + std::llabs(dy) > d) continue;", ""),
+    "manhattan_strict": ("std::llabs(dx) + std::llabs(dy) > d) continue;", "std::llabs(dx) + std::llabs(dy) >= d) continue;"),
+    "chebyshev_square_too_small": ("for (int64_t dy = -d; dy <= d; ++dy) {", "for (int64_t dy = -d; dy < d; ++dy) {"),
     "tau_strict": ("if (it->second < s->tau) it", "if (it->second <= s->tau) it"),
     "mu_strict": ("if (cluster.size() >= s->mu)", "if (cluster.size() > s->mu)"),
     "label_is_max": ("if (t < lab) lab = t;", "if (lab < t) lab = t;"),

@@ -240,3 +240,73 @@ def test_count_tiles_matches_accumulator(oracle_mod):
     got = oracle_mod.count_tiles(pts[:2500], s, qx, qy)
     got = oracle_mod.count_tiles(pts[2500:], s, qx, qy, out=got)
     assert got[:-2].tolist() == c.tolist() and got[-2:].tolist() == [0, 0]
+
+
+# ---- neighbourhood: Chebyshev or Manhattan distance delta (Section 3.2) ----
+
+def _sig_tiles(oracle_mod, tiles, metric, delta, mu=1):
+    r = oracle_mod.cluster(_tile_points(tiles, 1, scale=10.0), tau=1, mu=mu, precision=1,
+                           metric=metric, delta=delta)
+    return r
+
+
+def test_neighbour_counts_match_section_3_6(oracle_mod):
+    # Section 3.6 (higher dimensions): at Manhattan distance 1 a tile has 2d
+    # neighbours, and 3^d - 1 when all adjacent tiles count; for d = 2, 4 and 8.
+    # Count the adjacent offsets whose tile joins (100, 100).
+    units = [(dx, dy) for dx in (-1, 0, 1) for dy in (-1, 0, 1) if (dx, dy) != (0, 0)]
+    for metric, want in (("chebyshev", 8), ("manhattan", 4)):
+        joined = sum(_sig_tiles(oracle_mod, [(100, 100), (100 + dx, 100 + dy)], metric, 1).stats["clusters"] == 1
+                     for dx, dy in units)
+        assert joined == want, metric
+
+
+def test_delta_two_joins_a_one_tile_gap(oracle_mod):
+    # tiles two columns apart: separate at distance 1, one cluster at 2 in both
+    # metrics; the joined cluster has tiles without direct neighbours, which
+    # Section 3.2 notes for Manhattan distances above 1
+    tiles = [(0, 0), (2, 0)]
+    for metric in ("chebyshev", "manhattan"):
+        assert _sig_tiles(oracle_mod, tiles, metric, 1).stats["clusters"] == 2
+        r = _sig_tiles(oracle_mod, tiles, metric, 2)
+        assert r.stats["clusters"] == 1
+        assert set(zip(r.label_x.tolist(), r.label_y.tolist())) == {(0, 0)}
+
+
+def test_diagonal_needs_chebyshev_or_manhattan_two(oracle_mod):
+    tiles = [(5, 5), (6, 6)]
+    assert _sig_tiles(oracle_mod, tiles, "chebyshev", 1).stats["clusters"] == 1
+    assert _sig_tiles(oracle_mod, tiles, "manhattan", 1).stats["clusters"] == 2
+    assert _sig_tiles(oracle_mod, tiles, "manhattan", 2).stats["clusters"] == 1
+
+
+def test_knight_move_and_ring_radius(oracle_mod):
+    # (0, 0)-(1, 2): Chebyshev 2 and Manhattan 3 apart
+    tiles = [(0, 0), (1, 2)]
+    assert _sig_tiles(oracle_mod, tiles, "chebyshev", 1).stats["clusters"] == 2
+    assert _sig_tiles(oracle_mod, tiles, "chebyshev", 2).stats["clusters"] == 1
+    assert _sig_tiles(oracle_mod, tiles, "manhattan", 2).stats["clusters"] == 2
+    assert _sig_tiles(oracle_mod, tiles, "manhattan", 3).stats["clusters"] == 1
+    # all tiles at Chebyshev distance exactly 3 from a centre: (2*3+1)^2 - (2*3-1)^2 = 24
+    ring3 = [(dx, dy) for dx in range(-3, 4) for dy in range(-3, 4) if max(abs(dx), abs(dy)) == 3]
+    assert len(ring3) == 24
+    for metric, delta, want in (("chebyshev", 3, 24), ("chebyshev", 2, 0), ("manhattan", 3, 4),
+                                ("manhattan", 6, 24), ("manhattan", 5, 20)):
+        joined = sum(_sig_tiles(oracle_mod, [(50, 50), (50 + dx, 50 + dy)], metric, delta).stats["clusters"] == 1
+                     for dx, dy in ring3)
+        assert joined == want, (metric, delta)
+
+
+def test_delta_chain_and_mu(oracle_mod):
+    # a chain of tiles 3 apart: one cluster of 5 at delta 3, five singletons at 2
+    tiles = [(3 * k, 0) for k in range(5)]
+    assert _sig_tiles(oracle_mod, tiles, "chebyshev", 3, mu=5).stats["clusters"] == 1
+    assert _sig_tiles(oracle_mod, tiles, "chebyshev", 3, mu=6).stats["clusters"] == 0
+    assert _sig_tiles(oracle_mod, tiles, "manhattan", 2, mu=1).stats["clusters"] == 5
+
+
+def test_invalid_neighbourhood(oracle_mod):
+    pts = np.array([[0.5, 0.5]])
+    for kw in (dict(delta=0), dict(delta=65), dict(metric="euclid")):
+        with pytest.raises((oracle_mod.OracleError, KeyError)):
+            oracle_mod.cluster(pts, tau=1, mu=1, precision=0, **kw)
