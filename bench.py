@@ -169,6 +169,32 @@ def bench_point_labels(raster, torch, res, dev, reps: int = 3):
             "noise_points": noise}
 
 
+def bench_neighbourhoods(raster, torch, dev, precision: int, tau: int, mu: int, steps: int = 3):
+    """The same 500M-point stream with other neighbourhoods of Section 3.2
+    (one pass of the link kernel per four backward offsets): ms per step and
+    the agglomeration phase, after one untimed step each."""
+    import numpy as np
+    out = []
+    for metric, delta in (("manhattan", 1), ("chebyshev", 2), ("chebyshev", 3)):
+        def step():
+            st = raster.Stream(tau=tau, mu=mu, precision=precision, metric=metric, delta=delta)
+            for d in dev:
+                st.feed(d)
+            r = st.finish()
+            st.close()
+            return r
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = [step() for _ in range(steps)]
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - t0) / steps
+        out.append({"metric": metric, "delta": delta, "ms_per_step": ms,
+                    "us_agglomerate": float(np.mean([r.stats["us_agglomerate"] for r in rs])),
+                    "clusters": int(rs[-1].stats["clusters"]), "tiles": int(rs[-1].stats["tiles"])})
+    return out
+
+
 def bench_h2d_stream(raster, torch, host, precision: int, tau: int, mu: int, reps: int = 2):
     """Context only, never `value`: the same stream with the chunks in pinned
     host memory.  Each chunk is copied on a copy stream into one of two device
@@ -404,6 +430,8 @@ def main():
     ap.add_argument("--cpu-strip", type=float, default=2000.0)
     ap.add_argument("--tuning", default="", help="JSON object of raster_tuning fields")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (256-job) comparison")
+    ap.add_argument("--no-neighbourhoods", action="store_true",
+                    help="skip the steps with Manhattan 1 and Chebyshev 2 and 3 neighbourhoods")
     ap.add_argument("--no-h2d", action="store_true", help="skip the host-to-device streaming run")
     ap.add_argument("--no-point-labels", action="store_true", help="skip the per-point label pass")
     ap.add_argument("--no-served", action="store_true", help="skip the served (Poisson trace) comparison")
@@ -523,6 +551,13 @@ def main():
         "cpu_baseline": None,
     }
     line["point_labels"] = None if args.no_point_labels else bench_point_labels(raster, torch, results[-1], dev)
+    line["neighbourhoods"] = None
+    if not args.no_neighbourhoods:
+        log("other neighbourhoods")
+        line["neighbourhoods"] = bench_neighbourhoods(raster, torch, dev, precision, tau, mu)
+        line["neighbourhoods"].insert(0, {"metric": "chebyshev", "delta": 1, "ms_per_step": ms_per_step,
+                                          "us_agglomerate": phases["us_agglomerate"], "clusters": st["clusters"],
+                                          "tiles": st["tiles"]})
     del dev, results
     torch.cuda.empty_cache()
     line["h2d_stream"] = None

@@ -51,6 +51,12 @@ extern "C" {
 
 typedef enum raster_dtype { RASTER_F32 = 1, RASTER_F64 = 2 } raster_dtype;
 
+/* Distance in the neighbourhood of a tile (Section 3.2 allows a Chebyshev or
+ * a Manhattan distance of delta steps; the paper's code, and every call
+ * without a _delta suffix, uses Chebyshev 1: the eight adjacent tiles). */
+typedef enum raster_metric { RASTER_CHEBYSHEV = 0, RASTER_MANHATTAN = 1 } raster_metric;
+#define RASTER_MAX_DELTA 8
+
 typedef enum raster_status {
     RASTER_OK = 0,
     RASTER_E_INVAL = -1,  /* bad argument: tau or mu 0, NULL pointer with n > 0,
@@ -119,6 +125,17 @@ raster_status raster_cluster_scaled(const void* d_points, int64_t n, raster_dtyp
                                     uint32_t tau, uint32_t mu, hipStream_t stream,
                                     raster_result** out);
 
+/* Same with a wider or Manhattan neighbourhood: two significant tiles belong
+ * to one cluster when a chain of significant tiles joins them in which each
+ * step is at most `delta` tiles in `metric` (Section 3.2, Algorithm 1's
+ * neighbors(u, delta)).  1 <= delta <= RASTER_MAX_DELTA, else E_INVAL.  The
+ * agglomeration makes one pass over the table per four backward offsets of
+ * the neighbourhood (Chebyshev delta has 2 delta (delta + 1) of them,
+ * Manhattan delta has delta (delta + 1)). */
+raster_status raster_cluster_delta(const void* d_points, int64_t n, raster_dtype dt, double scale,
+                                   uint32_t tau, uint32_t mu, raster_metric metric, uint32_t delta,
+                                   hipStream_t stream, raster_result** out);
+
 /* ---- results --------------------------------------------------------------- */
 
 int64_t raster_result_num_tiles(const raster_result* r);    /* rows t, or -1 if r is NULL */
@@ -162,6 +179,10 @@ raster_status raster_begin(int32_t precision, uint32_t tau, uint32_t mu, int64_t
                            hipStream_t stream, raster_stream** st);
 raster_status raster_begin_scaled(double scale, uint32_t tau, uint32_t mu, int64_t tile_hint,
                                   hipStream_t stream, raster_stream** st);
+/* A stream whose agglomeration uses the neighbourhood (metric, delta), as in
+ * raster_cluster_delta. */
+raster_status raster_begin_delta(double scale, uint32_t tau, uint32_t mu, raster_metric metric, uint32_t delta,
+                                 int64_t tile_hint, hipStream_t stream, raster_stream** st);
 /* Count one chunk.  d_points is borrowed until the stream has passed the
  * enqueued work (the next raster_* call on this stream object, or a
  * synchronisation of its HIP stream).  Returns without waiting for this chunk;

@@ -95,6 +95,8 @@ def load():
         "raster_result_point_labels": (st, [vp, vp, i64, ctypes.c_int, vp, vp]),
         "raster_begin": (st, [i32, u32, u32, i64, vp, pp]),
         "raster_begin_scaled": (st, [dbl, u32, u32, i64, vp, pp]),
+        "raster_begin_delta": (st, [dbl, u32, u32, ctypes.c_int, u32, i64, vp, pp]),
+        "raster_cluster_delta": (st, [vp, i64, ctypes.c_int, dbl, u32, u32, ctypes.c_int, u32, vp, pp]),
         "raster_feed_chunk": (st, [vp, vp, i64, ctypes.c_int]),
         "raster_finish": (st, [vp, pp]),
         "raster_stream_tiles": (st, [vp, vp, vp, i64, ctypes.POINTER(i64)]),
@@ -231,14 +233,32 @@ class Result:
             pass
 
 
+METRICS = {"chebyshev": 0, "manhattan": 1}
+
+
+def _scale_of(precision, scale) -> float:
+    if scale is not None:
+        return float(scale)
+    if precision is None:
+        raise ValueError("give precision or scale")
+    return float(10 ** int(precision))
+
+
 def cluster(points, tau: int, mu: int, precision: int | None = None, scale: float | None = None,
-            stream=None) -> Result:
-    """RASTER on one resident point tensor (Algorithm 1)."""
+            stream=None, metric: str = "chebyshev", delta: int = 1) -> Result:
+    """RASTER on one resident point tensor (Algorithm 1).  ``metric`` and
+    ``delta`` choose the neighbourhood of the agglomeration (Section 3.2); the
+    default is the eight adjacent tiles."""
     lib = load()
     p, n, dt = _points(points)
     out = ctypes.c_void_p()
     st = _stream_handle(stream)
-    if scale is not None:
+    if metric != "chebyshev" or delta != 1:
+        if scale is None and not (precision is not None and 0 <= int(precision) <= 15):
+            raise RasterError(E_INVAL, "raster_cluster_delta", f"precision {precision} outside [0, 15]")
+        rc = lib.raster_cluster_delta(p, n, dt, _scale_of(precision, scale), int(tau), int(mu), METRICS[metric],
+                                      int(delta), st, ctypes.byref(out))
+    elif scale is not None:
         rc = lib.raster_cluster_scaled(p, n, dt, float(scale), int(tau), int(mu), st, ctypes.byref(out))
     else:
         rc = lib.raster_cluster(p, n, dt, int(precision), int(tau), int(mu), st, ctypes.byref(out))
@@ -250,13 +270,18 @@ class Stream:
     """Chunked contraction with a device-resident table (Section 3.6)."""
 
     def __init__(self, tau: int, mu: int, precision: int | None = None, scale: float | None = None,
-                 tile_hint: int = 0, stream=None):
+                 tile_hint: int = 0, stream=None, metric: str = "chebyshev", delta: int = 1):
         self._lib = load()
         self._stream = stream
         self._h = ctypes.c_void_p()
         self._keep = []  # chunks stay referenced until the stream has consumed them
         st = _stream_handle(stream)
-        if scale is not None:
+        if metric != "chebyshev" or delta != 1:
+            if scale is None and not (precision is not None and 0 <= int(precision) <= 15):
+                raise RasterError(E_INVAL, "raster_begin_delta", f"precision {precision} outside [0, 15]")
+            rc = self._lib.raster_begin_delta(_scale_of(precision, scale), int(tau), int(mu), METRICS[metric],
+                                              int(delta), int(tile_hint), st, ctypes.byref(self._h))
+        elif scale is not None:
             rc = self._lib.raster_begin_scaled(float(scale), int(tau), int(mu), int(tile_hint), st,
                                                ctypes.byref(self._h))
         else:

@@ -208,6 +208,45 @@ raster_status check_params(double scale, uint32_t tau, uint32_t mu) {
     return RASTER_OK;
 }
 
+raster_status check_neighbourhood(int32_t metric, uint32_t delta) {
+    if (metric != RASTER_CHEBYSHEV && metric != RASTER_MANHATTAN) return fail(RASTER_E_INVAL, "unknown metric %d", metric);
+    if (delta < 1 || delta > kMaxDelta)
+        return fail(RASTER_E_INVAL, "delta %u outside [1, %u]", delta, (unsigned)kMaxDelta);
+    return RASTER_OK;
+}
+
+std::vector<NbrRound> neighbourhood_rounds(uint32_t metric, uint32_t delta) {
+    std::vector<NbrRound> rounds;
+    if (metric == RASTER_CHEBYSHEV && delta == 1) return rounds;
+    // backward offsets: each edge is looked up from its larger-key end
+    struct Off {
+        int32_t dx, dy;
+    };
+    std::vector<Off> offs;
+    const int32_t d = (int32_t)delta;
+    for (int32_t dx = -d; dx <= 0; ++dx)
+        for (int32_t dy = -d; dy <= d; ++dy) {
+            if (dx == 0 && dy >= 0) continue;
+            if (metric == RASTER_MANHATTAN && std::abs(dx) + std::abs(dy) > d) continue;
+            offs.push_back({dx, dy});
+        }
+    // nearest first, so that the first round's parent links cover most edges
+    std::stable_sort(offs.begin(), offs.end(), [](const Off& a, const Off& b) {
+        return std::abs(a.dx) + std::abs(a.dy) < std::abs(b.dx) + std::abs(b.dy);
+    });
+    for (size_t i = 0; i < offs.size(); i += 4) {
+        NbrRound r{};
+        r.count = (uint32_t)std::min<size_t>(4, offs.size() - i);
+        for (uint32_t q = 0; q < r.count; ++q) {
+            r.dx[q] = offs[i + q].dx;
+            r.dy[q] = offs[i + q].dy;
+        }
+        r.set_parent = rounds.empty() ? 1u : 0u;
+        rounds.push_back(r);
+    }
+    return rounds;
+}
+
 // ============================================================ table run ====
 
 #define HIP_TRY(expr, what)                          \
@@ -646,7 +685,10 @@ raster_status TableRun::finish(raster_result** out) {
     e = launch_zero_u64((uint64_t*)ctr + C_DISTINCT, C_COUNT_ - C_DISTINCT, stream);
     if (e == hipSuccess) e = launch_threshold(tab, jv, s_key, s_count, size, partials, ctr, stream);
     if (e == hipSuccess) e = hipEventRecord(ev[2], stream);
-    if (e == hipSuccess) e = launch_agglomerate(tab, cap, jv, s_key, parent, nbr, size, m, ctr, stream);
+    const std::vector<NbrRound> rounds = neighbourhood_rounds(metric, delta);
+    if (e == hipSuccess)
+        e = launch_agglomerate(tab, cap, jv, s_key, parent, nbr, size, m, ctr, stream, rounds.data(),
+                               (int)rounds.size());
     if (e == hipSuccess) e = hipEventRecord(ev[3], stream);
     if (e == hipSuccess)
         e = launch_filter(jv, s_key, s_count, nbr, size, r->kx, r->ky, r->count, r->label, nullptr, partials, ctr,
@@ -721,21 +763,31 @@ struct raster_stream {
 
 extern "C" {
 
-raster_status raster_cluster_scaled(const void* d_points, int64_t n, raster_dtype dt, double scale, uint32_t tau,
-                                    uint32_t mu, hipStream_t stream, raster_result** out) {
+raster_status raster_cluster_delta(const void* d_points, int64_t n, raster_dtype dt, double scale, uint32_t tau,
+                                   uint32_t mu, raster_metric metric, uint32_t delta, hipStream_t stream,
+                                   raster_result** out) {
     if (!out) return fail(RASTER_E_INVAL, "out is NULL");
     *out = nullptr;
     raster_status st = check_params(scale, tau, mu);
+    if (st != RASTER_OK) return st;
+    st = check_neighbourhood((int32_t)metric, delta);
     if (st != RASTER_OK) return st;
     st = check_points(d_points, n, dt);
     if (st != RASTER_OK) return st;
     TableRun run;
     run.single_shot = true;
+    run.metric = (uint32_t)metric;
+    run.delta = delta;
     st = run.init(scale, tau, mu, std::max<int64_t>(n / 8, 1024), stream);
     if (st != RASTER_OK) return st;
     st = run.feed(d_points, n, dt);
     if (st != RASTER_OK) return st;
     return run.finish(out);
+}
+
+raster_status raster_cluster_scaled(const void* d_points, int64_t n, raster_dtype dt, double scale, uint32_t tau,
+                                    uint32_t mu, hipStream_t stream, raster_result** out) {
+    return raster_cluster_delta(d_points, n, dt, scale, tau, mu, RASTER_CHEBYSHEV, 1, stream, out);
 }
 
 raster_status raster_cluster(const void* d_points, int64_t n, raster_dtype dt, int32_t precision, uint32_t tau,
@@ -836,14 +888,18 @@ raster_status raster_result_point_labels(raster_result* r, const void* d_points,
     return RASTER_OK;
 }
 
-raster_status raster_begin_scaled(double scale, uint32_t tau, uint32_t mu, int64_t tile_hint, hipStream_t stream,
-                                  raster_stream** st) {
+raster_status raster_begin_delta(double scale, uint32_t tau, uint32_t mu, raster_metric metric, uint32_t delta,
+                                 int64_t tile_hint, hipStream_t stream, raster_stream** st) {
     if (!st) return fail(RASTER_E_INVAL, "st is NULL");
     *st = nullptr;
     raster_status s = check_params(scale, tau, mu);
     if (s != RASTER_OK) return s;
+    s = check_neighbourhood((int32_t)metric, delta);
+    if (s != RASTER_OK) return s;
     if (tile_hint < 0) return fail(RASTER_E_INVAL, "negative tile_hint");
     raster_stream* h = new raster_stream();
+    h->run.metric = (uint32_t)metric;
+    h->run.delta = delta;
     s = h->run.init(scale, tau, mu, tile_hint, stream);
     if (s != RASTER_OK) {
         delete h;
@@ -851,6 +907,11 @@ raster_status raster_begin_scaled(double scale, uint32_t tau, uint32_t mu, int64
     }
     *st = h;
     return RASTER_OK;
+}
+
+raster_status raster_begin_scaled(double scale, uint32_t tau, uint32_t mu, int64_t tile_hint, hipStream_t stream,
+                                  raster_stream** st) {
+    return raster_begin_delta(scale, tau, mu, RASTER_CHEBYSHEV, 1, tile_hint, stream, st);
 }
 
 raster_status raster_begin(int32_t precision, uint32_t tau, uint32_t mu, int64_t tile_hint, hipStream_t stream,

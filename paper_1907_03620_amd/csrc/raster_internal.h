@@ -118,6 +118,18 @@ struct JobInfo {
     uint64_t bin2_base;   // binned batches: first key of the job's partition lists
 };
 
+// One round of the link pass for a neighbourhood other than the eight
+// adjacent tiles: up to four backward offsets (dx < 0, or dx == 0 and dy < 0;
+// each edge is then seen once, from its larger-key end).  The first round also
+// sets every tile's parent to its smallest-key neighbour among its offsets;
+// later rounds only record edges for the merge pass.
+struct NbrRound {
+    int32_t dx[4], dy[4];
+    uint32_t count;       // offsets in use, 1..4
+    uint32_t set_parent;  // 1 in the first round
+};
+constexpr uint32_t kMaxDelta = 8;
+
 // Sizes read from device memory, so that a captured graph can be replayed
 // for any batch that fits its buffers.
 struct Dims {
@@ -223,7 +235,8 @@ hipError_t launch_threshold(Slot* tab, const JobView& jv, uint64_t* s_key, uint3
 // 4 words per significant tile, 16-byte aligned.
 hipError_t launch_agglomerate(const Slot* tab, uint64_t slots_max, const JobView& jv, const uint64_t* s_key,
                               uint32_t* parent, uint32_t* nbr, uint32_t* size, uint64_t s_max,
-                              unsigned long long* ctr, hipStream_t stream);
+                              unsigned long long* ctr, hipStream_t stream,
+                              const NbrRound* rounds = nullptr, int nrounds = 0);
 
 // mu filter and output compaction: rows of kept components in compact order
 // (out_job gets each row's job for several jobs).

@@ -1318,10 +1318,15 @@ __device__ __forceinline__ void uf_unite(uint32_t* parent, const uint64_t* key, 
 // workgroup per table partition: the slice is read into LDS once, and with
 // super-tile placement most neighbours share the tile's partition and are
 // probed there; only the others are probed in the device table.
+//
+// GENERAL: the offsets come from `nr` (one round of a larger or Manhattan
+// neighbourhood) instead of the four fixed ones, and the parent is written in
+// the first round only.
 constexpr int LINK_THREADS = 512;
 
+template <bool GENERAL>
 __global__ __launch_bounds__(LINK_THREADS) void k_link_part(const Slot* tab, JobView jv, uint32_t* parent,
-                                                            uint32_t* nbr, unsigned long long* ctr) {
+                                                            uint32_t* nbr, unsigned long long* ctr, NbrRound nr) {
     __shared__ uint64_t lkey[kPartSlots];
     __shared__ uint32_t laux[kPartSlots];
     __shared__ uint16_t list[kPartSlots];
@@ -1378,20 +1383,30 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_part(const Slot* tab, Job
             }
             const uint32_t bx = (uint32_t)(key >> 32);
             const uint32_t by = (uint32_t)key;
-            // valid biased coordinates lie in [2, 2^32 - 2]
-            const bool left = bx > 2u;
-            const bool down = by > 2u;
-            const bool up = by < 0xFFFFFFFEu;
             uint64_t nk[4];
             bool want[4];
-            nk[0] = ((uint64_t)(bx - 1) << 32) | (uint32_t)(by - 1);
-            want[0] = left && down;
-            nk[1] = ((uint64_t)(bx - 1) << 32) | by;
-            want[1] = left;
-            nk[2] = ((uint64_t)(bx - 1) << 32) | (uint32_t)(by + 1);
-            want[2] = left && up;
-            nk[3] = ((uint64_t)bx << 32) | (uint32_t)(by - 1);
-            want[3] = down;
+            if (!GENERAL) {
+                // valid biased coordinates lie in [2, 2^32 - 2]
+                const bool left = bx > 2u;
+                const bool down = by > 2u;
+                const bool up = by < 0xFFFFFFFEu;
+                nk[0] = ((uint64_t)(bx - 1) << 32) | (uint32_t)(by - 1);
+                want[0] = left && down;
+                nk[1] = ((uint64_t)(bx - 1) << 32) | by;
+                want[1] = left;
+                nk[2] = ((uint64_t)(bx - 1) << 32) | (uint32_t)(by + 1);
+                want[2] = left && up;
+                nk[3] = ((uint64_t)bx << 32) | (uint32_t)(by - 1);
+                want[3] = down;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t x = (int64_t)bx + nr.dx[q];
+                    const int64_t y = (int64_t)by + nr.dy[q];
+                    want[q] = q < (int)nr.count && x >= 2 && x <= 0xFFFFFFFEll && y >= 2 && y <= 0xFFFFFFFEll;
+                    nk[q] = want[q] ? (((uint64_t)(uint32_t)x << 32) | (uint32_t)y) : key;
+                }
+            }
             // first probes: device-table loads for the other partitions are
             // issued together, LDS probes need no wait
             // (home slot and the next one: a probe walk mostly ends there)
@@ -1452,7 +1467,7 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_part(const Slot* tab, Job
                     }
                 }
             }
-            parent[i] = best;
+            if (!GENERAL || nr.set_parent) parent[i] = best;
             uint4 rec;
             rec.x = j[0];
             rec.y = j[1];
@@ -2040,12 +2055,24 @@ hipError_t launch_threshold(Slot* tab, const JobView& jv, uint64_t* s_key, uint3
 
 hipError_t launch_agglomerate(const Slot* tab, uint64_t slots_max, const JobView& jv, const uint64_t* s_key,
                               uint32_t* parent, uint32_t* nbr, uint32_t* size, uint64_t s_max,
-                              unsigned long long* ctr, hipStream_t stream) {
+                              unsigned long long* ctr, hipStream_t stream, const NbrRound* rounds, int nrounds) {
     const int grid = (grid_for(s_max, 256, kPersistBlocks) + kXcds - 1) / kXcds * kXcds;
     const int link_grid = grid_for((slots_max + kPartSlots - 1) >> kPartLog2, 1, 8192);
-    hipLaunchKernelGGL(k_link_part, dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, jv, parent, nbr, ctr);
-    hipLaunchKernelGGL(k_jump, dim3(grid), dim3(256), 0, stream, parent, ctr);
-    hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, stream, nbr, s_key, parent, ctr);
+    if (nrounds <= 0) {
+        hipLaunchKernelGGL(k_link_part<false>, dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, jv, parent, nbr,
+                           ctr, NbrRound{});
+        hipLaunchKernelGGL(k_jump, dim3(grid), dim3(256), 0, stream, parent, ctr);
+        hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, stream, nbr, s_key, parent, ctr);
+    } else {
+        // round 0 builds the forest from its offsets; each later round records
+        // the edges of four more offsets and unites along them
+        for (int r = 0; r < nrounds; ++r) {
+            hipLaunchKernelGGL(k_link_part<true>, dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, jv, parent,
+                               nbr, ctr, rounds[r]);
+            if (r == 0) hipLaunchKernelGGL(k_jump, dim3(grid), dim3(256), 0, stream, parent, ctr);
+            hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, stream, nbr, s_key, parent, ctr);
+        }
+    }
     // the neighbour lists are dead after the merge pass; their first s words
     // take the final roots
     hipLaunchKernelGGL(k_compress, dim3(grid), dim3(256), 0, stream, jv, parent, nbr, size, ctr);

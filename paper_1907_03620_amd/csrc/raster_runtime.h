@@ -51,6 +51,10 @@ bool scale_for_precision(int32_t p, double* s);
 uint64_t next_pow2(uint64_t v);
 raster_status check_points(const void* p, int64_t n, raster_dtype dt);
 raster_status check_params(double scale, uint32_t tau, uint32_t mu);
+raster_status check_neighbourhood(int32_t metric, uint32_t delta);
+// Link rounds of the neighbourhood; empty for Chebyshev 1, which has its own
+// fixed-offset pass.
+std::vector<NbrRound> neighbourhood_rounds(uint32_t metric, uint32_t delta);
 
 class DevicePool {
   public:
@@ -90,6 +94,7 @@ struct TableRun {
     hipStream_t stream = nullptr;
     double scale = 1.0;
     uint32_t tau = 1, mu = 1;
+    uint32_t metric = RASTER_CHEBYSHEV, delta = 1;  // neighbourhood of the agglomeration
     raster_tuning tuning{};
     Buffers bufs;
     Slot* tab = nullptr;

@@ -1,0 +1,139 @@
+"""Wider and Manhattan neighbourhoods on the GPU against the oracle.
+
+Section 3.2 lets clusters join significant tiles up to delta steps apart in
+Chebyshev or Manhattan distance.  The GPU path links over the backward half
+of that neighbourhood four offsets at a time; every case is compared row by
+row (tiles, counts, labels) and by statistics with the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import assert_same, dev
+
+pytestmark = pytest.mark.gpu
+
+NBHDS = [("manhattan", 1), ("chebyshev", 2), ("manhattan", 2), ("chebyshev", 3), ("manhattan", 4)]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU test run without a GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def raster(torch):
+    import paper_1907_03620_amd as r
+    r.load()
+    r.set_tuning(None)
+    yield r
+    r.set_tuning(None)
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _tiny(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(0, 400))
+    span = float(rng.choice([0.3, 0.6, 1.0, 2.0]))
+    centre = rng.uniform(-1.0, 1.0, size=2)
+    pts = centre + rng.normal(0.0, span / 3, size=(n, 2))
+    dtype = np.float32 if rng.random() < 0.25 else np.float64
+    return pts.astype(dtype), int(rng.integers(0, 3)), int(rng.integers(1, 5)), int(rng.integers(1, 6))
+
+
+@pytest.mark.parametrize("metric,delta", NBHDS)
+def test_tiny_corpus(raster, torch, metric, delta):
+    for seed in range(3000, 3060):
+        pts, p, tau, mu = _tiny(seed)
+        o = oracle.cluster(pts, tau=tau, mu=mu, precision=p, metric=metric, delta=delta)
+        g = raster.cluster(dev(pts, torch), precision=p, tau=tau, mu=mu, metric=metric, delta=delta)
+        assert_same(g, o, f"tiny seed {seed} {metric} {delta}")
+
+
+@pytest.fixture(scope="module")
+def small():
+    return synth.plain_small(1)
+
+
+@pytest.mark.parametrize("metric,delta", NBHDS + [("chebyshev", 8), ("manhattan", 8)])
+def test_plain_small(raster, torch, small, metric, delta):
+    _say(f"plain-200k {metric} {delta}")
+    o = oracle.cluster(small, tau=3, mu=4, precision=1, metric=metric, delta=delta)
+    g = raster.cluster(dev(small, torch), precision=1, tau=3, mu=4, metric=metric, delta=delta)
+    assert_same(g, o, f"plain-200k {metric} {delta}")
+
+
+@pytest.mark.parametrize("metric,delta,mode", [("chebyshev", 2, 2), ("manhattan", 2, 2), ("chebyshev", 3, 1)])
+def test_mid_counting_paths(raster, torch, metric, delta, mode):
+    pts = synth.zipf_hot(2, n=3_000_000, block=1_000_000)
+    o = oracle.cluster(pts, tau=5, mu=4, precision=2, metric=metric, delta=delta)
+    raster.set_tuning(mode=mode)
+    try:
+        g = raster.cluster(dev(pts, torch), precision=2, tau=5, mu=4, metric=metric, delta=delta)
+    finally:
+        raster.set_tuning(None)
+    assert_same(g, o, f"zipf 3M {metric} {delta} mode {mode}")
+
+
+def test_stream_chunks(raster, torch):
+    centres = synth.paper_scale_centres(3)
+    chunks = [synth.paper_scale_chunk(c, centres=centres, chunk=400_000) for c in range(5)]
+    st = raster.Stream(tau=2, mu=3, precision=2, metric="manhattan", delta=3)
+    for c in chunks:
+        st.feed(dev(c, torch))
+    g = st.finish()
+    st.close()
+    assert_same(g, oracle.cluster_chunks(chunks, tau=2, mu=3, precision=2, metric="manhattan", delta=3),
+                "stream manhattan 3")
+
+
+def test_gap_joins_and_default_unchanged(raster, torch):
+    # two tiles two apart: one cluster at delta 2, two at delta 1
+    pts = np.array([[0.55, 0.55], [0.75, 0.55]])
+    assert raster.cluster(dev(pts, torch), precision=1, tau=1, mu=1).num_clusters == 2
+    assert raster.cluster(dev(pts, torch), precision=1, tau=1, mu=1, delta=2).num_clusters == 1
+    assert raster.cluster(dev(pts, torch), precision=1, tau=1, mu=1, metric="manhattan", delta=2).num_clusters == 1
+    # diagonal: Chebyshev 1 joins, Manhattan 1 does not
+    pts = np.array([[0.55, 0.55], [0.65, 0.65]])
+    assert raster.cluster(dev(pts, torch), precision=1, tau=1, mu=1).num_clusters == 1
+    assert raster.cluster(dev(pts, torch), precision=1, tau=1, mu=1, metric="manhattan").num_clusters == 2
+
+
+def test_extreme_tiles(raster, torch):
+    # tiles at the edge of the coordinate range: offsets past it are skipped
+    lim = 2 ** 31 - 2
+    tiles = [(lim, lim), (lim - 2, lim), (lim, lim - 3), (-lim, -lim), (-lim + 1, -lim + 2), (0, 0), (3, 0)]
+    pts = np.array([[x + 0.5 if x >= 0 else x - 0.5, y + 0.5 if y >= 0 else y - 0.5] for x, y in tiles])
+    for metric, delta in (("chebyshev", 3), ("manhattan", 3), ("chebyshev", 2)):
+        o = oracle.cluster(pts, tau=1, mu=1, precision=0, metric=metric, delta=delta)
+        g = raster.cluster(dev(pts, torch), precision=0, tau=1, mu=1, metric=metric, delta=delta)
+        assert_same(g, o, f"extreme tiles {metric} {delta}")
+
+
+def test_point_labels_with_delta(raster, torch, small):
+    o = oracle.cluster(small, tau=3, mu=4, precision=1, metric="chebyshev", delta=2)
+    d = dev(small, torch)
+    g = raster.cluster(d, precision=1, tau=3, mu=4, metric="chebyshev", delta=2)
+    assert np.array_equal(g.point_labels(d).cpu().numpy(), oracle.point_labels(small, o, precision=1))
+
+
+def test_invalid_neighbourhoods(raster, torch):
+    pts = dev(np.array([[0.5, 0.5]]), torch)
+    for kw in (dict(delta=0), dict(delta=9), dict(metric="manhattan", delta=0)):
+        with pytest.raises(raster.RasterError) as e:
+            raster.cluster(pts, precision=1, tau=1, mu=1, **kw)
+        assert e.value.code == raster.E_INVAL
+        with pytest.raises(raster.RasterError) as e:
+            raster.Stream(tau=1, mu=1, precision=1, **kw)
+        assert e.value.code == raster.E_INVAL
+    lib = raster.load()
+    import ctypes
+    out = ctypes.c_void_p()
+    rc = lib.raster_cluster_delta(ctypes.c_void_p(pts.data_ptr()), 1, 2, 10.0, 1, 1, 2, 1, None, ctypes.byref(out))
+    assert rc == raster.E_INVAL and not out.value
