@@ -266,6 +266,31 @@ def point_labels(points, result: OracleResult, precision: int | None = None,
     return out
 
 
+def tile_points(points, result: OracleResult, precision: int | None = None,
+                scale: float | None = None):
+    """Points of every kept tile (RASTER', Section 3.4): the points are
+    projected a second time (Section 3.2) and each point on a row's tile is
+    listed under that row.  Returns (row_start, index) for the rows of
+    ``result`` in its order: the points on row j are
+    index[row_start[j]:row_start[j + 1]], ascending."""
+    kx, ky = project(points, _scale(precision, scale))
+    t = result.num_tiles
+    row_start = np.zeros(t + 1, dtype=np.int64)
+    if t == 0 or kx.shape[0] == 0:
+        return row_start, np.zeros(0, dtype=np.int64)
+    tiles = result.kx.astype(np.int64) * (1 << 32) + result.ky.astype(np.int64)
+    order = np.argsort(tiles, kind="stable")
+    q = kx * (1 << 32) + ky
+    pos = np.searchsorted(tiles[order], q)
+    hit = pos < t
+    hit[hit] = tiles[order][pos[hit]] == q[hit]
+    point = np.nonzero(hit)[0]
+    row = order[pos[hit]]
+    by_row = np.argsort(row, kind="stable")          # rows in order, points ascending within a row
+    row_start[1:] = np.cumsum(np.bincount(row, minlength=t))
+    return row_start, point[by_row].astype(np.int64)
+
+
 def cluster_chunks(chunks, tau: int, mu: int, precision: int | None = None,
                    scale: float | None = None, metric: str = "chebyshev", delta: int = 1) -> OracleResult:
     """RASTER over an iterable of point chunks (Section 3.6)."""
