@@ -169,6 +169,32 @@ def bench_point_labels(raster, torch, res, dev, reps: int = 3):
             "noise_points": noise}
 
 
+def bench_tile_points(raster, torch, res, dev, reps: int = 3):
+    """Per-tile point lists (RASTER', Section 3.4) of every resident point from
+    one step's result: one call per chunk (lookup, count per row, scan,
+    scatter; each call synchronises), timed with HIP events on the calling
+    stream.  The first call builds the row table and is not timed."""
+    import numpy as np
+    s = torch.cuda.current_stream()
+    res.tile_points(dev[0], stream=s)
+    torch.cuda.synchronize()
+    passes, kept = [], 0
+    for r in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for d in dev:
+            _, index = res.tile_points(d, stream=s)
+            if r == 0:
+                kept += int(index.shape[0])
+        e1.record(s)
+        torch.cuda.synchronize()
+        passes.append(e0.elapsed_time(e1))
+    n = sum(int(d.shape[0]) for d in dev)
+    ms = float(np.median(passes))
+    return {"points": n, "points_listed": kept, "ms_per_pass": ms, "points_per_s": n / (ms * 1e-3),
+            "calls_per_pass": len(dev)}
+
+
 def bench_neighbourhoods(raster, torch, dev, precision: int, tau: int, mu: int, steps: int = 3):
     """The same 500M-point stream with other neighbourhoods of Section 3.2
     (one pass of the link kernel per four backward offsets): ms per step and
@@ -433,7 +459,8 @@ def main():
     ap.add_argument("--no-neighbourhoods", action="store_true",
                     help="skip the steps with Manhattan 1 and Chebyshev 2 and 3 neighbourhoods")
     ap.add_argument("--no-h2d", action="store_true", help="skip the host-to-device streaming run")
-    ap.add_argument("--no-point-labels", action="store_true", help="skip the per-point label pass")
+    ap.add_argument("--no-point-labels", action="store_true",
+                    help="skip the per-point label pass and the per-tile point lists")
     ap.add_argument("--no-served", action="store_true", help="skip the served (Poisson trace) comparison")
     ap.add_argument("--served-seconds", type=float, default=10.0)
     ap.add_argument("--served-rate", type=float, default=200.0)
@@ -551,6 +578,7 @@ def main():
         "cpu_baseline": None,
     }
     line["point_labels"] = None if args.no_point_labels else bench_point_labels(raster, torch, results[-1], dev)
+    line["tile_points"] = None if args.no_point_labels else bench_tile_points(raster, torch, results[-1], dev)
     line["neighbourhoods"] = None
     if not args.no_neighbourhoods:
         log("other neighbourhoods")

@@ -170,6 +170,25 @@ void raster_result_free(raster_result* r);
 raster_status raster_result_point_labels(raster_result* r, const void* d_points, int64_t n, raster_dtype dt,
                                          uint64_t* d_labels, hipStream_t stream);
 
+/* Per-tile point lists (RASTER', Section 3.4): the points of every kept tile.
+ * The paper's RASTER' keeps each tile's points in the hash table during
+ * contraction; here they are gathered after clustering by projecting the
+ * points a second time, which gives the same sets.  For the n points of
+ * d_points (borrowed for the call; n < 2^32 - 1), the indices of the points
+ * on row j of the result (the row order of raster_result_arrays) are
+ * d_index[d_row_start[j] .. d_row_start[j + 1]), in no particular order within
+ * a row.  d_row_start: caller-owned device array of t + 1 uint64;
+ * d_index: caller-owned device array of `cap` uint64 (cap >= the number of
+ * points on kept tiles; n always suffices).  *n_kept (host) receives that
+ * number.  Points on no kept tile are not listed.  Synchronises `stream`.
+ * Errors: E_INVAL for bad arguments, or when cap is too small (then
+ * d_row_start and *n_kept are written, d_index is not); E_RANGE if a point is
+ * not finite or its tile is outside +-(2^31 - 2).  Calls on one result are
+ * serialised. */
+raster_status raster_result_tile_points(raster_result* r, const void* d_points, int64_t n, raster_dtype dt,
+                                        uint64_t* d_row_start, uint64_t* d_index, int64_t cap, int64_t* n_kept,
+                                        hipStream_t stream);
+
 /* ---- streaming form (chunked input, Section 3.6) ---------------------------- */
 
 /* Start a stream.  tile_hint: expected number of distinct tiles (0 = unknown);

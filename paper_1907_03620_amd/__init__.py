@@ -93,6 +93,7 @@ def load():
         "raster_result_stats": (st, [vp, ctypes.POINTER(_Stats)]),
         "raster_result_free": (None, [vp]),
         "raster_result_point_labels": (st, [vp, vp, i64, ctypes.c_int, vp, vp]),
+        "raster_result_tile_points": (st, [vp, vp, i64, ctypes.c_int, vp, vp, i64, ctypes.POINTER(i64), vp]),
         "raster_begin": (st, [i32, u32, u32, i64, vp, pp]),
         "raster_begin_scaled": (st, [dbl, u32, u32, i64, vp, pp]),
         "raster_begin_delta": (st, [dbl, u32, u32, ctypes.c_int, u32, i64, vp, pp]),
@@ -220,6 +221,22 @@ class Result:
         _check(load().raster_result_point_labels(self._h, p, n, dt, ctypes.c_void_p(out.data_ptr()), st),
                "raster_result_point_labels")
         return out
+
+    def tile_points(self, points, stream=None):
+        """Points of every kept tile (RASTER', Section 3.4): ``(row_start,
+        index)`` as int64 tensors, where the points on row j of
+        :meth:`tensors` are ``index[row_start[j]:row_start[j + 1]]`` (indices
+        into ``points``, unordered within a row)."""
+        torch = _torch()
+        p, n, dt = _points(points)
+        start = torch.empty(self.num_tiles + 1, dtype=torch.int64, device=points.device)
+        index = torch.empty(max(n, 1), dtype=torch.int64, device=points.device)
+        kept = ctypes.c_int64()
+        st = _stream_handle(stream if stream is not None else self._stream)
+        _check(load().raster_result_tile_points(self._h, p, n, dt, ctypes.c_void_p(start.data_ptr()),
+                                                ctypes.c_void_p(index.data_ptr()), n, ctypes.byref(kept), st),
+               "raster_result_tile_points")
+        return start, index[: kept.value]
 
     def free(self):
         if self._h:

@@ -832,14 +832,41 @@ raster_status raster_result_stats(const raster_result* r, raster_stats* out) {
 void raster_result_free(raster_result* r) {
     if (!r) return;
     if (r->pool && r->block) r->pool->release(r->block);
-    if (r->lt) {
+    if (r->lt || r->rt || r->lt_err) {
         int dev = 0;
         (void)hipGetDevice(&dev);
         DevicePool& pool = DevicePool::get(dev);
-        pool.release(r->lt);
-        pool.release(r->lt_err);
+        if (r->lt) pool.release(r->lt);
+        if (r->rt) pool.release(r->rt);
+        if (r->lt_err) pool.release(r->lt_err);
     }
     delete r;  // a shared block goes back to the pool with its last result
+}
+
+// The result's lookup table of one kind (rows = false: tile -> label, true:
+// tile -> row), built on first use; the caller holds r->lt_mu.
+static raster_status ensure_lookup(raster_result* r, bool rows, DevicePool& pool, hipStream_t stream) {
+    if (!r->lt_err) {
+        void* e = nullptr;
+        HIP_TRY(pool.alloc(&e, sizeof(unsigned long long)), "range flag");
+        r->lt_err = (unsigned long long*)e;
+    }
+    uint64_t*& tab = rows ? r->rt : r->lt;
+    uint64_t& tcap = rows ? r->rt_cap : r->lt_cap;
+    if (tab) return RASTER_OK;
+    // at most half full, so every lookup ends at an empty slot
+    const uint64_t cap = next_pow2(std::max<uint64_t>(64, 2 * (uint64_t)r->tiles));
+    void* t = nullptr;
+    HIP_TRY(pool.alloc(&t, 2 * cap * sizeof(uint64_t)), "lookup table");
+    const hipError_t le = launch_label_table(r->kx, r->ky, r->label, (uint64_t)r->tiles, (uint64_t*)t, cap, rows,
+                                             stream);
+    if (le != hipSuccess) {
+        pool.release(t);
+        return hip_fail(le, "lookup table");
+    }
+    tab = (uint64_t*)t;
+    tcap = cap;
+    return RASTER_OK;
 }
 
 raster_status raster_result_point_labels(raster_result* r, const void* d_points, int64_t n, raster_dtype dt,
@@ -856,27 +883,7 @@ raster_status raster_result_point_labels(raster_result* r, const void* d_points,
     unsigned long long err = 0;
     {
         std::lock_guard<std::mutex> g(r->lt_mu);
-        if (!r->lt) {
-            // at most half full, so every lookup ends at an empty slot
-            const uint64_t cap = next_pow2(std::max<uint64_t>(64, 2 * (uint64_t)r->tiles));
-            void* tab = nullptr;
-            void* e = nullptr;
-            HIP_TRY(pool.alloc(&tab, 2 * cap * sizeof(uint64_t)), "label table");
-            if (pool.alloc(&e, sizeof(unsigned long long)) != hipSuccess) {
-                pool.release(tab);
-                return fail(RASTER_E_NOMEM, "label table: out of device memory");
-            }
-            const hipError_t le = launch_label_table(r->kx, r->ky, r->label, (uint64_t)r->tiles, (uint64_t*)tab, cap,
-                                                     stream);
-            if (le != hipSuccess) {
-                pool.release(tab);
-                pool.release(e);
-                return hip_fail(le, "label table");
-            }
-            r->lt = (uint64_t*)tab;
-            r->lt_err = (unsigned long long*)e;
-            r->lt_cap = cap;
-        }
+        if ((st = ensure_lookup(r, false, pool, stream)) != RASTER_OK) return st;
         HIP_TRY(launch_zero_u64((uint64_t*)r->lt_err, 1, stream), "zero flag");
         HIP_TRY(launch_point_labels(d_points, n, (int)dt, r->scale, r->lt, r->lt_cap, d_labels, r->lt_err, stream),
                 "point labels");
@@ -885,6 +892,63 @@ raster_status raster_result_point_labels(raster_result* r, const void* d_points,
     }
     if (err & kErrRange)
         return fail(RASTER_E_RANGE, "a coordinate is not finite or its tile is outside +-(2^31 - 2)");
+    return RASTER_OK;
+}
+
+raster_status raster_result_tile_points(raster_result* r, const void* d_points, int64_t n, raster_dtype dt,
+                                        uint64_t* d_row_start, uint64_t* d_index, int64_t cap, int64_t* n_kept,
+                                        hipStream_t stream) {
+    if (n_kept) *n_kept = 0;
+    if (!r) return fail(RASTER_E_INVAL, "result is NULL");
+    if (!n_kept) return fail(RASTER_E_INVAL, "n_kept is NULL");
+    raster_status st = check_points(d_points, n, dt);
+    if (st != RASTER_OK) return st;
+    if (n >= (int64_t)0xFFFFFFFFll) return fail(RASTER_E_INVAL, "more than 2^32 - 2 points in one call");
+    if (!d_row_start || ((uintptr_t)d_row_start % 8) != 0)
+        return fail(RASTER_E_INVAL, "row_start must be an 8-byte aligned array of t + 1 words");
+    if (cap < 0 || (cap > 0 && (!d_index || ((uintptr_t)d_index % 8) != 0)))
+        return fail(RASTER_E_INVAL, "index must be an 8-byte aligned array of cap words");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    DevicePool& pool = DevicePool::get(dev);
+    const uint64_t t = (uint64_t)r->tiles;
+    // scratch: row and rank of every point, count per row, scan partials and total
+    const size_t b_rows = ((size_t)std::max<int64_t>(n, 1) * sizeof(uint32_t) + 255) / 256 * 256;
+    const size_t b_count = ((size_t)std::max<uint64_t>(t, 1) * sizeof(uint32_t) + 255) / 256 * 256;
+    const size_t b_part = (size_t)kScanBlocks * sizeof(uint32_t);
+    void* scratch = nullptr;
+    HIP_TRY(pool.alloc(&scratch, 2 * b_rows + b_count + b_part + 256), "tile-point scratch");
+    uint32_t* row_of = (uint32_t*)scratch;
+    uint32_t* rank = (uint32_t*)((char*)scratch + b_rows);
+    uint32_t* count = (uint32_t*)((char*)scratch + 2 * b_rows);
+    uint32_t* partials = (uint32_t*)((char*)scratch + 2 * b_rows + b_count);
+    unsigned long long* total = (unsigned long long*)((char*)scratch + 2 * b_rows + b_count + b_part);
+    struct Release {
+        DevicePool& p;
+        void* b;
+        ~Release() { p.release(b); }
+    } rel{pool, scratch};
+    unsigned long long h[2] = {0, 0};  // total, range flag
+    {
+        std::lock_guard<std::mutex> g(r->lt_mu);
+        if ((st = ensure_lookup(r, true, pool, stream)) != RASTER_OK) return st;
+        HIP_TRY(launch_zero_u64((uint64_t*)r->lt_err, 1, stream), "zero flag");
+        HIP_TRY(launch_zero_u32(count, std::max<uint64_t>(t, 1), stream), "zero counts");
+        HIP_TRY(launch_tile_points_count(d_points, n, (int)dt, r->scale, r->rt, r->rt_cap, row_of, rank, count, t,
+                                         partials, total, d_row_start, r->lt_err, stream),
+                "tile points");
+        HIP_TRY(hipMemcpyAsync(&h[0], total, sizeof h[0], hipMemcpyDeviceToHost, stream), "total copy");
+        HIP_TRY(hipMemcpyAsync(&h[1], r->lt_err, sizeof h[1], hipMemcpyDeviceToHost, stream), "flag copy");
+        HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+        if (h[1] & kErrRange)
+            return fail(RASTER_E_RANGE, "a coordinate is not finite or its tile is outside +-(2^31 - 2)");
+        *n_kept = (int64_t)h[0];
+        if ((int64_t)h[0] > cap)
+            return fail(RASTER_E_INVAL, "index holds %lld entries, %lld points lie on kept tiles", (long long)cap,
+                        (long long)h[0]);
+        HIP_TRY(launch_tile_points_scatter(row_of, rank, n, d_row_start, d_index, stream), "tile points scatter");
+        HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    }
     return RASTER_OK;
 }
 

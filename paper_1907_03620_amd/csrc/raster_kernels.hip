@@ -1707,10 +1707,12 @@ __global__ __launch_bounds__(256) void k_batch_hll(JobView jv, const uint32_t* t
 // ---- per-point labels (the second projection pass of Section 4.1) ---------------
 //
 // A lookup table of a result's tiles: cap (a power of two) slots of two words
-// {biased key, cluster label}, empty key UINT64_MAX, home slot from the slot
-// hash, linear probing over the whole table.  Every point is then projected
-// again and its tile looked up.
+// {biased key, value}, empty key UINT64_MAX, home slot from the slot hash,
+// linear probing over the whole table.  The value is the cluster label
+// (per-point labels) or, with ROWS, the tile's row in the result (per-tile
+// point lists).  Every point is then projected again and its tile looked up.
 
+template <bool ROWS>
 __global__ void k_label_table(const int32_t* kx, const int32_t* ky, const uint64_t* label, uint64_t t,
                               uint64_t* tab, uint64_t cap) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < t;
@@ -1722,7 +1724,7 @@ __global__ void k_label_table(const int32_t* kx, const int32_t* ky, const uint64
         while (atomicCAS(reinterpret_cast<unsigned long long*>(tab + 2 * pos), (unsigned long long)kEmptyKey,
                          (unsigned long long)key) != kEmptyKey)
             pos = (pos + 1) & (cap - 1);
-        tab[2 * pos + 1] = label[i];
+        tab[2 * pos + 1] = ROWS ? i : label[i];
     }
 }
 
@@ -1770,6 +1772,146 @@ __global__ __launch_bounds__(256) void k_point_labels(const T* __restrict__ pts,
         }
     }
     if (bad) atomicOr(err, (unsigned long long)kErrRange);
+}
+
+// ---- per-tile point lists (RASTER', Section 3.4) -----------------------------
+//
+// The points of every kept tile, gathered after clustering by a second pass
+// over the points: the row of each point's tile is looked up in a ROWS table
+// and counted; the count's old value is the point's rank within its row.  The
+// counts are scanned into row offsets and every point written to offset +
+// rank.  Within a row the order is that of the counting atomics (a tile's
+// points form a set).
+
+constexpr uint32_t kNoRow = 0xFFFFFFFFu;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_point_rows(const T* __restrict__ pts, int64_t n, double scale,
+                                                    const uint64_t* __restrict__ tab, uint64_t cap,
+                                                    uint32_t* __restrict__ row_of,
+                                                    uint32_t* __restrict__ rank, uint32_t* count,
+                                                    unsigned long long* err) {
+    typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+    const u64x2* __restrict__ slots = reinterpret_cast<const u64x2*>(tab);
+    constexpr int U = 8;
+    bool bad = false;
+    for (int64_t i0 = (int64_t)blockIdx.x * U * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * U * blockDim.x) {
+        double x[U], y[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) load_point(pts, min(i0 + (int64_t)u * blockDim.x + threadIdx.x, n - 1), x[u], y[u]);
+        uint64_t key[U], pos[U];
+        u64x2 cur[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            key[u] = 0;
+            ok[u] = tile_key(x[u], y[u], scale, key[u]);
+            pos[u] = slot_hash(key[u]) & (cap - 1);
+            cur[u] = slots[pos[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + (int64_t)u * blockDim.x + threadIdx.x;
+            if (i >= n) continue;
+            uint32_t row = kNoRow, k = 0;
+            if (!ok[u]) {
+                bad = true;
+            } else {
+                while (cur[u].x != key[u] && cur[u].x != kEmptyKey) {
+                    pos[u] = (pos[u] + 1) & (cap - 1);
+                    cur[u] = slots[pos[u]];
+                }
+                if (cur[u].x == key[u]) {
+                    row = (uint32_t)cur[u].y;
+                    k = atomicAdd(count + row, 1u);
+                }
+            }
+            row_of[i] = row;
+            rank[i] = k;
+        }
+    }
+    if (bad) atomicOr(err, (unsigned long long)kErrRange);
+}
+
+// pass 1 of the row-offset scan: the sum of each workgroup's range of counts
+__global__ __launch_bounds__(SCAN_THREADS) void k_rows_sum(const uint32_t* count, uint64_t t, uint32_t* partials) {
+    __shared__ uint32_t red[SCAN_WAVES];
+    uint64_t lo, hi;
+    block_range(t, lo, hi);
+    uint32_t sum = 0;
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += SCAN_THREADS) sum += count[i];
+    sum = block_sum(sum, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = sum;
+}
+
+// pass 3: start[i] = points on rows before i (start[t] = all of them).  Each
+// thread takes SCAN_ITEMS consecutive rows of a tile.
+__global__ __launch_bounds__(SCAN_THREADS) void k_rows_start(const uint32_t* count, uint64_t t,
+                                                             const uint32_t* partials,
+                                                             const unsigned long long* total, uint64_t* start) {
+    __shared__ uint32_t wsum[SCAN_WAVES];
+    uint64_t lo, hi;
+    block_range(t, lo, hi);
+    uint64_t run = partials[blockIdx.x];
+    for (uint64_t t0 = lo; t0 < hi; t0 += SCAN_TILE) {
+        const uint64_t first = t0 + (uint64_t)threadIdx.x * SCAN_ITEMS;
+        uint32_t v[SCAN_ITEMS];
+        uint32_t mine = 0;
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
+            v[j] = first + j < hi ? count[first + j] : 0u;
+            mine += v[j];
+        }
+        // exclusive scan of the per-thread sums over the workgroup
+        uint32_t inc = mine;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off);
+            if (lane_id() >= off) inc += o;
+        }
+        const int w = threadIdx.x >> 6;
+        if (lane_id() == 63) wsum[w] = inc;
+        __syncthreads();
+        uint32_t before = 0, tile_total = 0;
+        for (int q = 0; q < SCAN_WAVES; ++q) {
+            if (q < w) before += wsum[q];
+            tile_total += wsum[q];
+        }
+        __syncthreads();  // wsum is reused by the next tile
+        uint64_t at = run + before + inc - mine;
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
+            if (first + j < hi) start[first + j] = at;
+            at += v[j];
+        }
+        run += tile_total;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) start[t] = *total;
+}
+
+// Each point on a kept tile goes to its row's offset plus its rank.  Rows,
+// ranks and offsets of U items are loaded before the first store.
+__global__ __launch_bounds__(256) void k_scatter_rows(const uint32_t* __restrict__ row_of,
+                                                      const uint32_t* __restrict__ rank, int64_t n,
+                                                      const uint64_t* __restrict__ start,
+                                                      uint64_t* __restrict__ out) {
+    constexpr int U = 8;
+    for (int64_t i0 = (int64_t)blockIdx.x * U * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * U * blockDim.x) {
+        uint32_t r[U], k[U];
+        uint64_t at[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = min(i0 + (int64_t)u * blockDim.x + threadIdx.x, n - 1);
+            r[u] = row_of[i];
+            k[u] = rank[i];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) at[u] = r[u] != kNoRow ? start[r[u]] : 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + (int64_t)u * blockDim.x + threadIdx.x;
+            if (i < n && r[u] != kNoRow) out[at[u] + k[u]] = (uint64_t)i;
+        }
+    }
 }
 
 // ---- per-job ranges and statistics (batches) ----------------------------------
@@ -1955,6 +2097,11 @@ hipError_t launch_zero_u64(uint64_t* p, uint64_t n, hipStream_t stream) {
     return hipGetLastError();
 }
 
+hipError_t launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t stream) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(n, 256, 65536)), dim3(256), 0, stream, p, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_project_count(const void* pts, int64_t n, int dtype, double scale, Slot* tab, uint64_t cap,
                                  SpillBuf spill, unsigned long long* ctr, const KernelTuning& tu,
                                  hipStream_t stream) {
@@ -2118,12 +2265,18 @@ hipError_t launch_batch_binned(const JobView& jv, const uint32_t* tile_prefix, c
 }
 
 hipError_t launch_label_table(const int32_t* kx, const int32_t* ky, const uint64_t* label, uint64_t t,
-                              uint64_t* tab, uint64_t cap, hipStream_t stream) {
+                              uint64_t* tab, uint64_t cap, bool rows, hipStream_t stream) {
     hipLaunchKernelGGL(k_fill_words, dim3(grid_for(2 * cap, 256, kPersistBlocks)), dim3(256), 0, stream, tab,
                        2 * cap, kEmptyKey);
     if (t)
-        hipLaunchKernelGGL(k_label_table, dim3(grid_for(t, 256, kPersistBlocks)), dim3(256), 0, stream, kx, ky, label,
-                           t, tab, cap);
+    {
+        if (rows)
+            hipLaunchKernelGGL(k_label_table<true>, dim3(grid_for(t, 256, kPersistBlocks)), dim3(256), 0, stream, kx,
+                               ky, label, t, tab, cap);
+        else
+            hipLaunchKernelGGL(k_label_table<false>, dim3(grid_for(t, 256, kPersistBlocks)), dim3(256), 0, stream, kx,
+                               ky, label, t, tab, cap);
+    }
     return hipGetLastError();
 }
 
@@ -2137,6 +2290,34 @@ hipError_t launch_point_labels(const void* pts, int64_t n, int dtype, double sca
     else
         hipLaunchKernelGGL(k_point_labels<double>, dim3(grid), dim3(256), 0, stream,
                            static_cast<const double*>(pts), n, scale, tab, cap, out, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_points_count(const void* pts, int64_t n, int dtype, double scale, const uint64_t* tab,
+                                   uint64_t cap, uint32_t* row_of, uint32_t* rank, uint32_t* count, uint64_t t,
+                                   uint32_t* partials, unsigned long long* total, uint64_t* start,
+                                   unsigned long long* err, hipStream_t stream) {
+    if (n > 0) {
+        const unsigned grid = (unsigned)grid_for((uint64_t)n, 256 * 8, 8192);
+        if (dtype == 1)
+            hipLaunchKernelGGL(k_point_rows<float>, dim3(grid), dim3(256), 0, stream, static_cast<const float*>(pts), n,
+                               scale, tab, cap, row_of, rank, count, err);
+        else
+            hipLaunchKernelGGL(k_point_rows<double>, dim3(grid), dim3(256), 0, stream, static_cast<const double*>(pts),
+                               n, scale, tab, cap, row_of, rank, count, err);
+    }
+    hipLaunchKernelGGL(k_rows_sum, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, count, t, partials);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, stream, partials, total);
+    hipLaunchKernelGGL(k_rows_start, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, count, t, partials, total,
+                       start);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_points_scatter(const uint32_t* row_of, const uint32_t* rank, int64_t n,
+                                      const uint64_t* start, uint64_t* out, hipStream_t stream) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_scatter_rows, dim3(grid_for((uint64_t)n, 256 * 8, 8192)), dim3(256), 0, stream, row_of,
+                           rank, n, start, out);
     return hipGetLastError();
 }
 

@@ -32,10 +32,13 @@ struct raster_result {
     int64_t clusters = 0;
     raster_stats stats{};
     double scale = 0.0;  // the projection the result was computed with
-    // per-point labels: a lookup table of the rows, built on first use
+    // per-point labels and per-tile point lists: lookup tables of the rows
+    // (tile -> label, tile -> row), built on first use, and a range flag
     std::mutex lt_mu;
     uint64_t* lt = nullptr;
     uint64_t lt_cap = 0;
+    uint64_t* rt = nullptr;
+    uint64_t rt_cap = 0;
     unsigned long long* lt_err = nullptr;
 };
 

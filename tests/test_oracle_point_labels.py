@@ -122,7 +122,8 @@ MUTANTS = {
     "halves_swapped": ("(((result.label_x[order]", "(((result.label_y[order]"),
     "no_bias_on_y": ("| (result.label_y[order].astype(np.int64) + (1 << 31))",
                      "| (result.label_y[order].astype(np.int64))"),
-    "query_axes_swapped": ("q = kx * (1 << 32) + ky", "q = ky * (1 << 32) + kx"),
+    "query_axes_swapped": ("q = kx * (1 << 32) + ky\n    pos = np.searchsorted(tiles, q)",
+                           "q = ky * (1 << 32) + kx\n    pos = np.searchsorted(tiles, q)"),
     "noise_is_zero": ("out = np.full(kx.shape[0], -1, dtype=np.int64)",
                       "out = np.full(kx.shape[0], 0, dtype=np.int64)"),
     "nearest_not_equal": ("hit[hit] = tiles[pos[hit]] == q[hit]", "pass"),
