@@ -62,7 +62,7 @@ def _load():
     lib.oracle_project.restype = ctypes.c_int
     lib.oracle_begin.argtypes = [dbl, u64, u64]
     lib.oracle_begin.restype = vp
-    lib.oracle_begin_ex.argtypes = [dbl, u64, u64, i32, i64]
+    lib.oracle_begin_ex.argtypes = [dbl, u64, u64, i32, i64, i32]
     lib.oracle_begin_ex.restype = vp
     lib.oracle_feed.argtypes = [vp, vp, i64, i32]
     lib.oracle_feed.restype = ctypes.c_int
@@ -156,11 +156,14 @@ METRICS = {"chebyshev": 0, "manhattan": 1}
 class OracleStream:
     """Chunked contraction (Section 3.6) followed by one agglomeration.
     Clusters join significant tiles within ``delta`` steps of each other in
-    the given metric (Section 3.2); the default is the eight adjacent tiles."""
+    the given metric (Section 3.2); the default is the eight adjacent tiles.
+    ``window`` adds the 2x2 post-step of Section 3.6."""
 
-    def __init__(self, scale: float, tau: int, mu: int, metric: str = "chebyshev", delta: int = 1):
+    def __init__(self, scale: float, tau: int, mu: int, metric: str = "chebyshev", delta: int = 1,
+                 window: bool = False):
         self._lib = _load()
-        self._h = self._lib.oracle_begin_ex(float(scale), int(tau), int(mu), METRICS[metric], int(delta))
+        self._h = self._lib.oracle_begin_ex(float(scale), int(tau), int(mu), METRICS[metric], int(delta),
+                                            int(bool(window)))
         if not self._h:
             raise OracleError(E_INVAL, "begin")
 
@@ -229,9 +232,10 @@ def _scale(precision, scale):
 
 
 def cluster(points, tau: int, mu: int, precision: int | None = None,
-            scale: float | None = None, metric: str = "chebyshev", delta: int = 1) -> OracleResult:
+            scale: float | None = None, metric: str = "chebyshev", delta: int = 1,
+            window: bool = False) -> OracleResult:
     """RASTER on one in-memory point set."""
-    st = OracleStream(_scale(precision, scale), tau, mu, metric, delta)
+    st = OracleStream(_scale(precision, scale), tau, mu, metric, delta, window)
     try:
         st.feed(points)
         return st.finish()
@@ -292,9 +296,10 @@ def tile_points(points, result: OracleResult, precision: int | None = None,
 
 
 def cluster_chunks(chunks, tau: int, mu: int, precision: int | None = None,
-                   scale: float | None = None, metric: str = "chebyshev", delta: int = 1) -> OracleResult:
+                   scale: float | None = None, metric: str = "chebyshev", delta: int = 1,
+                   window: bool = False) -> OracleResult:
     """RASTER over an iterable of point chunks (Section 3.6)."""
-    st = OracleStream(_scale(precision, scale), tau, mu, metric, delta)
+    st = OracleStream(_scale(precision, scale), tau, mu, metric, delta, window)
     try:
         for c in chunks:
             st.feed(c)

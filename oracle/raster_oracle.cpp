@@ -26,6 +26,11 @@
 //     (Section 3.2 names both metrics and a distance delta; the paper's own
 //     code uses Chebyshev 1, the eight adjacent tiles, which is the default
 //     here).  Only significant tiles are taken into a cluster.
+//   * Optional 2x2 post-step (Section 3.6, Figure 4, for points spread over the
+//     tiles around a grid corner): a tile with fewer than tau points is also
+//     significant when the four tiles of some 2x2 square containing it hold at
+//     least tau points together.  Only tiles holding points are retained; the
+//     squares are summed over the counts before any tile is removed.
 //   * A cluster is kept when it holds at least mu tiles.
 //   * Each kept tile is reported with its count and the lexicographically
 //     smallest (kx, ky) of its cluster as the cluster's label; output is sorted
@@ -77,6 +82,7 @@ struct OracleStream {
     uint64_t tau, mu;
     int32_t metric = 0;  // 0: Chebyshev, 1: Manhattan
     int64_t delta = 1;
+    bool window = false;  // the 2x2 post-step
     bool failed = false;
     bool finished = false;
     uint64_t n_points = 0;
@@ -118,20 +124,22 @@ int oracle_project(const void* pts, int64_t n, int32_t dtype, double scale,
     return kOK;
 }
 
-// metric: 0 = Chebyshev, 1 = Manhattan; 1 <= delta <= 64.
-void* oracle_begin_ex(double scale, uint64_t tau, uint64_t mu, int32_t metric, int64_t delta) {
+// metric: 0 = Chebyshev, 1 = Manhattan; 1 <= delta <= 64; window: 0 or 1
+// (the 2x2 post-step).
+void* oracle_begin_ex(double scale, uint64_t tau, uint64_t mu, int32_t metric, int64_t delta, int32_t window) {
     if (!(scale > 0.0) || !std::isfinite(scale) || tau == 0 || mu == 0) return nullptr;
-    if ((metric != 0 && metric != 1) || delta < 1 || delta > 64) return nullptr;
+    if ((metric != 0 && metric != 1) || delta < 1 || delta > 64 || (window != 0 && window != 1)) return nullptr;
     OracleStream* s = new OracleStream();
     s->scale = scale;
     s->tau = tau;
     s->mu = mu;
     s->metric = metric;
     s->delta = delta;
+    s->window = window == 1;
     return s;
 }
 
-void* oracle_begin(double scale, uint64_t tau, uint64_t mu) { return oracle_begin_ex(scale, tau, mu, 0, 1); }
+void* oracle_begin(double scale, uint64_t tau, uint64_t mu) { return oracle_begin_ex(scale, tau, mu, 0, 1, 0); }
 
 // Contraction over one chunk of points (Algorithm 1, first loop).  Chunks may
 // come in any number and order (Section 3.6).  The chunk is checked first, so a
@@ -194,9 +202,35 @@ int oracle_finish(void* h) {
     s->finished = true;
     s->distinct = s->acc.size();
 
-    // Remove every tile whose count is below tau.
+    // With the 2x2 post-step: tiles below tau that lie in a 2x2 square of
+    // tiles holding at least tau points together, found on the full counts.
+    std::unordered_set<Tile, TileHash> by_square;
+    if (s->window) {
+        auto count_of = [&](int64_t x, int64_t y) -> uint64_t {
+            auto it = s->acc.find(Tile{x, y});
+            return it == s->acc.end() ? 0 : it->second;
+        };
+        for (const auto& kv : s->acc) {
+            if (kv.second >= s->tau) continue;
+            const Tile& t = kv.first;
+            // the four squares holding t have their lower-left corner at
+            // (t.x - a, t.y - b) for a, b in {0, 1}
+            for (int64_t a = 0; a <= 1 && !by_square.count(t); ++a)
+                for (int64_t b = 0; b <= 1; ++b) {
+                    const int64_t x0 = t.x - a, y0 = t.y - b;
+                    const uint64_t sum = count_of(x0, y0) + count_of(x0 + 1, y0) + count_of(x0, y0 + 1) +
+                                         count_of(x0 + 1, y0 + 1);
+                    if (sum >= s->tau) {
+                        by_square.insert(t);
+                        break;
+                    }
+                }
+        }
+    }
+
+    // Remove every tile whose count is below tau (unless a square keeps it).
     for (auto it = s->acc.begin(); it != s->acc.end();) {
-        if (it->second < s->tau) it = s->acc.erase(it);
+        if (it->second < s->tau && !by_square.count(it->first)) it = s->acc.erase(it);
         else ++it;
     }
     s->significant = s->acc.size();

@@ -31,12 +31,26 @@ def brute_tile_counts(points, scale: float):
     return tiles, counts
 
 
-def brute_cluster(points, scale: float, tau: int, mu: int, metric: str = "chebyshev", delta: int = 1):
+def brute_cluster(points, scale: float, tau: int, mu: int, metric: str = "chebyshev", delta: int = 1,
+                  window: bool = False):
     """Returns rows (kx, ky, count, label_x, label_y) sorted by tile, plus the
     number of kept clusters.  Two significant tiles are adjacent when their
-    distance in ``metric`` is between 1 and ``delta`` (Section 3.2)."""
+    distance in ``metric`` is between 1 and ``delta`` (Section 3.2).  With
+    ``window`` (Section 3.6's 2x2 post-step) a tile is also significant when
+    some 2x2 square of tiles containing it holds at least tau points."""
     tiles, counts = brute_tile_counts(points, scale)
     sig = counts >= tau
+    if window and tiles.shape[0]:
+        # every 2x2 square with at least one occupied tile, by its lower-left corner
+        total = {}
+        for (x, y), c in zip(tiles.tolist(), counts.tolist()):
+            for cx in (x - 1, x):
+                for cy in (y - 1, y):
+                    total[(cx, cy)] = total.get((cx, cy), 0) + c
+        heavy = {corner for corner, c in total.items() if c >= tau}
+        for i, (x, y) in enumerate(tiles.tolist()):
+            if any((cx, cy) in heavy for cx in (x - 1, x) for cy in (y - 1, y)):
+                sig[i] = True
     st, sc = tiles[sig], counts[sig]
     t = st.shape[0]
     if t == 0:

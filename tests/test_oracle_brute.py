@@ -69,3 +69,16 @@ def test_oracle_matches_brute_force_delta(oracle_mod, metric, delta):
                zip(r.kx, r.ky, r.count, r.label_x, r.label_y)]
         assert got == rows, (seed, metric, delta)
         assert r.stats["clusters"] == kept, seed
+
+
+@pytest.mark.parametrize("metric,delta", [("chebyshev", 1), ("manhattan", 2)])
+def test_oracle_matches_brute_force_2x2_step(oracle_mod, metric, delta):
+    for seed in range(4000, 4100):
+        pts, p, tau, mu = _case(seed)
+        s = oracle_mod.scale_for_precision(p)
+        rows, kept = brute_cluster(pts, s, tau, mu, metric, delta, window=True)
+        r = oracle_mod.cluster(pts, tau=tau, mu=mu, scale=s, metric=metric, delta=delta, window=True)
+        got = [(int(a), int(b), int(c), int(d), int(e)) for a, b, c, d, e in
+               zip(r.kx, r.ky, r.count, r.label_x, r.label_y)]
+        assert got == rows, (seed, metric, delta)
+        assert r.stats["clusters"] == kept, seed

@@ -23,8 +23,12 @@ MUTANTS = {
     "delta_ignored": ("const int64_t d = s->delta;", "const int64_t d = 1;"),
     "manhattan_as_chebyshev": ("if (s->metric == 1 && std::llabs(dx) + std::llabs(dy) > d) continue;", ""),
     "manhattan_strict": ("std::llabs(dx) + std::llabs(dy) > d) continue;", "std::llabs(dx) + std::llabs(dy) >= d) continue;"),
+    "square_one_corner_only": ("for (int64_t a = 0; a <= 1 && !by_square.count(t); ++a)",
+                               "for (int64_t a = 0; a <= 0 && !by_square.count(t); ++a)"),
+    "square_sum_strict": ("if (sum >= s->tau) {", "if (sum > s->tau) {"),
+    "square_step_ignored": ("if (s->window) {", "if (false) {"),
     "chebyshev_square_too_small": ("for (int64_t dy = -d; dy <= d; ++dy) {", "for (int64_t dy = -d; dy < d; ++dy) {"),
-    "tau_strict": ("if (it->second < s->tau) it", "if (it->second <= s->tau) it"),
+    "tau_strict": ("if (it->second < s->tau && !by_square", "if (it->second <= s->tau && !by_square"),
     "mu_strict": ("if (cluster.size() >= s->mu)", "if (cluster.size() > s->mu)"),
     "label_is_max": ("if (t < lab) lab = t;", "if (lab < t) lab = t;"),
     "axes_swapped": ("project_coord(point_coord(pts, dtype, i, 0), s->scale, &t.x)",

@@ -310,3 +310,51 @@ def test_invalid_neighbourhood(oracle_mod):
     for kw in (dict(delta=0), dict(delta=65), dict(metric="euclid")):
         with pytest.raises((oracle_mod.OracleError, KeyError)):
             oracle_mod.cluster(pts, tau=1, mu=1, precision=0, **kw)
+
+
+# ---- the 2x2 post-step for disadvantageous grid layouts (Section 3.6) -------
+
+def test_fig4_corner_with_2x2_step(oracle_mod):
+    g = _golden("fig4_grid_corner.json")
+    pts = np.array(g["points"])
+    r = oracle_mod.cluster(pts, tau=4, mu=1, precision=g["precision"], window=True)
+    assert r.stats["significant"] == g["tau4_with_2x2_step_significant"]
+    assert r.stats["clusters"] == 1
+    assert sorted(zip(r.kx.tolist(), r.ky.tolist())) == [tuple(t) for t in g["tiles"]]
+    assert set(zip(r.label_x.tolist(), r.label_y.tolist())) == {tuple(g["tau1_mu4_label"])}
+    assert r.count.tolist() == [1, 1, 1, 1]
+    # without the step nothing is significant
+    assert oracle_mod.cluster(pts, tau=4, mu=1, precision=g["precision"]).stats["significant"] == 0
+
+
+def _square_case(oracle_mod, counts, tau):
+    pts = _tile_points([t for t, c in counts.items() for _ in range(c)], 1, scale=10.0)
+    r = oracle_mod.cluster(pts, tau=tau, mu=1, precision=1, window=True)
+    return sorted(zip(r.kx.tolist(), r.ky.tolist()))
+
+
+def test_2x2_step_closed_forms(oracle_mod):
+    # three occupied tiles of one square: kept together at tau 3, not at 4;
+    # the empty fourth tile is never output
+    three = {(10, 10): 1, (11, 10): 1, (10, 11): 1}
+    assert _square_case(oracle_mod, three, 3) == [(10, 10), (10, 11), (11, 10)]
+    assert _square_case(oracle_mod, three, 4) == []
+    # a diagonal pair is one square: both corners are found
+    assert _square_case(oracle_mod, {(20, 20): 1, (21, 21): 2}, 3) == [(20, 20), (21, 21)]
+    assert _square_case(oracle_mod, {(20, 21): 1, (21, 20): 2}, 3) == [(20, 21), (21, 20)]
+    # two columns apart: no square holds both
+    assert _square_case(oracle_mod, {(30, 30): 2, (32, 30): 2}, 4) == []
+    # a significant tile does not make its light neighbours significant unless
+    # a square reaches tau: (40, 40) has 5 of tau 5, its neighbour 1 point;
+    # every square holding the neighbour also holds (40, 40), so it is kept
+    assert _square_case(oracle_mod, {(40, 40): 5, (41, 40): 1, (43, 40): 1}, 5) == [(40, 40), (41, 40)]
+
+
+def test_2x2_step_only_adds(oracle_mod):
+    rng = np.random.default_rng(31)
+    pts = rng.normal(0.0, 0.4, size=(3000, 2))
+    a = oracle_mod.cluster(pts, tau=6, mu=1, precision=1)
+    b = oracle_mod.cluster(pts, tau=6, mu=1, precision=1, window=True)
+    sa = set(zip(a.kx.tolist(), a.ky.tolist()))
+    sb = set(zip(b.kx.tolist(), b.ky.tolist()))
+    assert sa < sb and b.stats["distinct"] == a.stats["distinct"]
