@@ -196,14 +196,16 @@ def bench_tile_points(raster, torch, res, dev, reps: int = 3):
 
 
 def bench_neighbourhoods(raster, torch, dev, precision: int, tau: int, mu: int, steps: int = 3):
-    """The same 500M-point stream with other neighbourhoods of Section 3.2
-    (one pass of the link kernel per four backward offsets): ms per step and
-    the agglomeration phase, after one untimed step each."""
+    """The same 500M-point stream with the variants of the method: other
+    neighbourhoods of Section 3.2 (one pass of the link kernel per four
+    backward offsets) and the 2x2 post-step of Section 3.6.  ms per step, the
+    threshold and agglomeration phases, after one untimed step each."""
     import numpy as np
     out = []
-    for metric, delta in (("manhattan", 1), ("chebyshev", 2), ("chebyshev", 3)):
+    for metric, delta, square in (("manhattan", 1, False), ("chebyshev", 2, False), ("chebyshev", 3, False),
+                                  ("chebyshev", 1, True)):
         def step():
-            st = raster.Stream(tau=tau, mu=mu, precision=precision, metric=metric, delta=delta)
+            st = raster.Stream(tau=tau, mu=mu, precision=precision, metric=metric, delta=delta, square=square)
             for d in dev:
                 st.feed(d)
             r = st.finish()
@@ -215,7 +217,8 @@ def bench_neighbourhoods(raster, torch, dev, precision: int, tau: int, mu: int, 
         rs = [step() for _ in range(steps)]
         torch.cuda.synchronize()
         ms = 1000.0 * (time.perf_counter() - t0) / steps
-        out.append({"metric": metric, "delta": delta, "ms_per_step": ms,
+        out.append({"metric": metric, "delta": delta, "square_step": square, "ms_per_step": ms,
+                    "us_threshold": float(np.mean([r.stats["us_threshold"] for r in rs])),
                     "us_agglomerate": float(np.mean([r.stats["us_agglomerate"] for r in rs])),
                     "clusters": int(rs[-1].stats["clusters"]), "tiles": int(rs[-1].stats["tiles"])})
     return out
@@ -457,7 +460,7 @@ def main():
     ap.add_argument("--tuning", default="", help="JSON object of raster_tuning fields")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (256-job) comparison")
     ap.add_argument("--no-neighbourhoods", action="store_true",
-                    help="skip the steps with Manhattan 1 and Chebyshev 2 and 3 neighbourhoods")
+                    help="skip the steps with Manhattan 1 and Chebyshev 2 and 3 neighbourhoods and the 2x2 step")
     ap.add_argument("--no-h2d", action="store_true", help="skip the host-to-device streaming run")
     ap.add_argument("--no-point-labels", action="store_true",
                     help="skip the per-point label pass and the per-tile point lists")
@@ -583,7 +586,8 @@ def main():
     if not args.no_neighbourhoods:
         log("other neighbourhoods")
         line["neighbourhoods"] = bench_neighbourhoods(raster, torch, dev, precision, tau, mu)
-        line["neighbourhoods"].insert(0, {"metric": "chebyshev", "delta": 1, "ms_per_step": ms_per_step,
+        line["neighbourhoods"].insert(0, {"metric": "chebyshev", "delta": 1, "square_step": False,
+                                          "ms_per_step": ms_per_step, "us_threshold": phases["us_threshold"],
                                           "us_agglomerate": phases["us_agglomerate"], "clusters": st["clusters"],
                                           "tiles": st["tiles"]})
     del dev, results

@@ -57,6 +57,16 @@ typedef enum raster_dtype { RASTER_F32 = 1, RASTER_F64 = 2 } raster_dtype;
 typedef enum raster_metric { RASTER_CHEBYSHEV = 0, RASTER_MANHATTAN = 1 } raster_metric;
 #define RASTER_MAX_DELTA 8
 
+/* Variants of the method, for raster_cluster_opts and raster_begin_opts.
+ * NULL options mean {RASTER_CHEBYSHEV, 1, 0, 0}: Algorithm 1 as the paper's
+ * code runs it. */
+typedef struct raster_options {
+    raster_metric metric;  /* neighbourhood metric (Section 3.2)                      */
+    uint32_t delta;        /* neighbourhood distance, 1 .. RASTER_MAX_DELTA            */
+    uint32_t square_step;  /* 1: the 2x2 post-step of Section 3.6 (below), else 0      */
+    uint32_t reserved;     /* must be 0                                                 */
+} raster_options;
+
 typedef enum raster_status {
     RASTER_OK = 0,
     RASTER_E_INVAL = -1,  /* bad argument: tau or mu 0, NULL pointer with n > 0,
@@ -136,6 +146,19 @@ raster_status raster_cluster_delta(const void* d_points, int64_t n, raster_dtype
                                    uint32_t tau, uint32_t mu, raster_metric metric, uint32_t delta,
                                    hipStream_t stream, raster_result** out);
 
+/* Same with every variant in `opts` (NULL: the defaults).  square_step = 1
+ * adds the post-step that Section 3.6 proposes for points spread over the
+ * tiles around a grid corner (Figure 4): a tile with fewer than tau points is
+ * also significant when some 2x2 square of tiles containing it holds at least
+ * tau points together (counted before any tile is dropped).  Only tiles with
+ * points are retained.  It adds one pass over the table that probes the eight
+ * surrounding tiles of every tile below tau.  E_INVAL for an unknown metric,
+ * delta outside [1, RASTER_MAX_DELTA], square_step not 0 or 1, or reserved
+ * not 0. */
+raster_status raster_cluster_opts(const void* d_points, int64_t n, raster_dtype dt, double scale,
+                                  uint32_t tau, uint32_t mu, const raster_options* opts, hipStream_t stream,
+                                  raster_result** out);
+
 /* ---- results --------------------------------------------------------------- */
 
 int64_t raster_result_num_tiles(const raster_result* r);    /* rows t, or -1 if r is NULL */
@@ -202,6 +225,9 @@ raster_status raster_begin_scaled(double scale, uint32_t tau, uint32_t mu, int64
  * raster_cluster_delta. */
 raster_status raster_begin_delta(double scale, uint32_t tau, uint32_t mu, raster_metric metric, uint32_t delta,
                                  int64_t tile_hint, hipStream_t stream, raster_stream** st);
+/* A stream with every variant in `opts`, as in raster_cluster_opts. */
+raster_status raster_begin_opts(double scale, uint32_t tau, uint32_t mu, const raster_options* opts,
+                                int64_t tile_hint, hipStream_t stream, raster_stream** st);
 /* Count one chunk.  d_points is borrowed until the stream has passed the
  * enqueued work (the next raster_* call on this stream object, or a
  * synchronisation of its HIP stream).  Returns without waiting for this chunk;

@@ -41,6 +41,11 @@ class RasterError(RuntimeError):
         self.code = code
 
 
+class _Options(ctypes.Structure):
+    _fields_ = [("metric", ctypes.c_int), ("delta", ctypes.c_uint32), ("square_step", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
 class _Stats(ctypes.Structure):
     _fields_ = [("n_points", ctypes.c_int64), ("distinct_tiles", ctypes.c_int64),
                 ("significant_tiles", ctypes.c_int64), ("components", ctypes.c_int64),
@@ -98,6 +103,8 @@ def load():
         "raster_begin_scaled": (st, [dbl, u32, u32, i64, vp, pp]),
         "raster_begin_delta": (st, [dbl, u32, u32, ctypes.c_int, u32, i64, vp, pp]),
         "raster_cluster_delta": (st, [vp, i64, ctypes.c_int, dbl, u32, u32, ctypes.c_int, u32, vp, pp]),
+        "raster_cluster_opts": (st, [vp, i64, ctypes.c_int, dbl, u32, u32, ctypes.POINTER(_Options), vp, pp]),
+        "raster_begin_opts": (st, [dbl, u32, u32, ctypes.POINTER(_Options), i64, vp, pp]),
         "raster_feed_chunk": (st, [vp, vp, i64, ctypes.c_int]),
         "raster_finish": (st, [vp, pp]),
         "raster_stream_tiles": (st, [vp, vp, vp, i64, ctypes.POINTER(i64)]),
@@ -261,20 +268,35 @@ def _scale_of(precision, scale) -> float:
     return float(10 ** int(precision))
 
 
+def _options(metric: str, delta: int, square: bool):
+    """The options struct, or None for the defaults."""
+    if metric == "chebyshev" and delta == 1 and not square:
+        return None
+    if metric not in METRICS:
+        raise RasterError(E_INVAL, "options", f"unknown metric {metric!r}")
+    return _Options(METRICS[metric], int(delta), int(bool(square)), 0)
+
+
+def _variant_scale(precision, scale, what) -> float:
+    if scale is None and not (precision is not None and 0 <= int(precision) <= 15):
+        raise RasterError(E_INVAL, what, f"precision {precision} outside [0, 15]")
+    return _scale_of(precision, scale)
+
+
 def cluster(points, tau: int, mu: int, precision: int | None = None, scale: float | None = None,
-            stream=None, metric: str = "chebyshev", delta: int = 1) -> Result:
+            stream=None, metric: str = "chebyshev", delta: int = 1, square: bool = False) -> Result:
     """RASTER on one resident point tensor (Algorithm 1).  ``metric`` and
     ``delta`` choose the neighbourhood of the agglomeration (Section 3.2); the
-    default is the eight adjacent tiles."""
+    default is the eight adjacent tiles.  ``square`` adds the 2x2 post-step
+    of Section 3.6."""
     lib = load()
     p, n, dt = _points(points)
     out = ctypes.c_void_p()
     st = _stream_handle(stream)
-    if metric != "chebyshev" or delta != 1:
-        if scale is None and not (precision is not None and 0 <= int(precision) <= 15):
-            raise RasterError(E_INVAL, "raster_cluster_delta", f"precision {precision} outside [0, 15]")
-        rc = lib.raster_cluster_delta(p, n, dt, _scale_of(precision, scale), int(tau), int(mu), METRICS[metric],
-                                      int(delta), st, ctypes.byref(out))
+    opts = _options(metric, delta, square)
+    if opts is not None:
+        rc = lib.raster_cluster_opts(p, n, dt, _variant_scale(precision, scale, "raster_cluster_opts"), int(tau),
+                                     int(mu), ctypes.byref(opts), st, ctypes.byref(out))
     elif scale is not None:
         rc = lib.raster_cluster_scaled(p, n, dt, float(scale), int(tau), int(mu), st, ctypes.byref(out))
     else:
@@ -287,17 +309,16 @@ class Stream:
     """Chunked contraction with a device-resident table (Section 3.6)."""
 
     def __init__(self, tau: int, mu: int, precision: int | None = None, scale: float | None = None,
-                 tile_hint: int = 0, stream=None, metric: str = "chebyshev", delta: int = 1):
+                 tile_hint: int = 0, stream=None, metric: str = "chebyshev", delta: int = 1, square: bool = False):
         self._lib = load()
         self._stream = stream
         self._h = ctypes.c_void_p()
         self._keep = []  # chunks stay referenced until the stream has consumed them
         st = _stream_handle(stream)
-        if metric != "chebyshev" or delta != 1:
-            if scale is None and not (precision is not None and 0 <= int(precision) <= 15):
-                raise RasterError(E_INVAL, "raster_begin_delta", f"precision {precision} outside [0, 15]")
-            rc = self._lib.raster_begin_delta(_scale_of(precision, scale), int(tau), int(mu), METRICS[metric],
-                                              int(delta), int(tile_hint), st, ctypes.byref(self._h))
+        opts = _options(metric, delta, square)
+        if opts is not None:
+            rc = self._lib.raster_begin_opts(_variant_scale(precision, scale, "raster_begin_opts"), int(tau), int(mu),
+                                             ctypes.byref(opts), int(tile_hint), st, ctypes.byref(self._h))
         elif scale is not None:
             rc = self._lib.raster_begin_scaled(float(scale), int(tau), int(mu), int(tile_hint), st,
                                                ctypes.byref(self._h))

@@ -215,6 +215,15 @@ raster_status check_neighbourhood(int32_t metric, uint32_t delta) {
     return RASTER_OK;
 }
 
+raster_status check_options(const raster_options* o) {
+    if (!o) return RASTER_OK;
+    raster_status s = check_neighbourhood((int32_t)o->metric, o->delta);
+    if (s != RASTER_OK) return s;
+    if (o->square_step > 1) return fail(RASTER_E_INVAL, "square_step must be 0 or 1");
+    if (o->reserved != 0) return fail(RASTER_E_INVAL, "reserved must be 0");
+    return RASTER_OK;
+}
+
 std::vector<NbrRound> neighbourhood_rounds(uint32_t metric, uint32_t delta) {
     std::vector<NbrRound> rounds;
     if (metric == RASTER_CHEBYSHEV && delta == 1) return rounds;
@@ -683,7 +692,7 @@ raster_status TableRun::finish(raster_result** out) {
     JobView jv{&sj_dev->dims, &sj_dev->job, nullptr, nullptr, nullptr};
 
     e = launch_zero_u64((uint64_t*)ctr + C_DISTINCT, C_COUNT_ - C_DISTINCT, stream);
-    if (e == hipSuccess) e = launch_threshold(tab, jv, s_key, s_count, size, partials, ctr, stream);
+    if (e == hipSuccess) e = launch_threshold(tab, jv, s_key, s_count, size, partials, ctr, stream, square ? cap : 0);
     if (e == hipSuccess) e = hipEventRecord(ev[2], stream);
     const std::vector<NbrRound> rounds = neighbourhood_rounds(metric, delta);
     if (e == hipSuccess)
@@ -763,21 +772,23 @@ struct raster_stream {
 
 extern "C" {
 
-raster_status raster_cluster_delta(const void* d_points, int64_t n, raster_dtype dt, double scale, uint32_t tau,
-                                   uint32_t mu, raster_metric metric, uint32_t delta, hipStream_t stream,
-                                   raster_result** out) {
+raster_status raster_cluster_opts(const void* d_points, int64_t n, raster_dtype dt, double scale, uint32_t tau,
+                                  uint32_t mu, const raster_options* opts, hipStream_t stream, raster_result** out) {
     if (!out) return fail(RASTER_E_INVAL, "out is NULL");
     *out = nullptr;
     raster_status st = check_params(scale, tau, mu);
     if (st != RASTER_OK) return st;
-    st = check_neighbourhood((int32_t)metric, delta);
+    st = check_options(opts);
     if (st != RASTER_OK) return st;
     st = check_points(d_points, n, dt);
     if (st != RASTER_OK) return st;
     TableRun run;
     run.single_shot = true;
-    run.metric = (uint32_t)metric;
-    run.delta = delta;
+    if (opts) {
+        run.metric = (uint32_t)opts->metric;
+        run.delta = opts->delta;
+        run.square = opts->square_step == 1;
+    }
     st = run.init(scale, tau, mu, std::max<int64_t>(n / 8, 1024), stream);
     if (st != RASTER_OK) return st;
     st = run.feed(d_points, n, dt);
@@ -785,9 +796,16 @@ raster_status raster_cluster_delta(const void* d_points, int64_t n, raster_dtype
     return run.finish(out);
 }
 
+raster_status raster_cluster_delta(const void* d_points, int64_t n, raster_dtype dt, double scale, uint32_t tau,
+                                   uint32_t mu, raster_metric metric, uint32_t delta, hipStream_t stream,
+                                   raster_result** out) {
+    const raster_options o{metric, delta, 0, 0};
+    return raster_cluster_opts(d_points, n, dt, scale, tau, mu, &o, stream, out);
+}
+
 raster_status raster_cluster_scaled(const void* d_points, int64_t n, raster_dtype dt, double scale, uint32_t tau,
                                     uint32_t mu, hipStream_t stream, raster_result** out) {
-    return raster_cluster_delta(d_points, n, dt, scale, tau, mu, RASTER_CHEBYSHEV, 1, stream, out);
+    return raster_cluster_opts(d_points, n, dt, scale, tau, mu, nullptr, stream, out);
 }
 
 raster_status raster_cluster(const void* d_points, int64_t n, raster_dtype dt, int32_t precision, uint32_t tau,
@@ -952,18 +970,21 @@ raster_status raster_result_tile_points(raster_result* r, const void* d_points, 
     return RASTER_OK;
 }
 
-raster_status raster_begin_delta(double scale, uint32_t tau, uint32_t mu, raster_metric metric, uint32_t delta,
-                                 int64_t tile_hint, hipStream_t stream, raster_stream** st) {
+raster_status raster_begin_opts(double scale, uint32_t tau, uint32_t mu, const raster_options* opts,
+                                int64_t tile_hint, hipStream_t stream, raster_stream** st) {
     if (!st) return fail(RASTER_E_INVAL, "st is NULL");
     *st = nullptr;
     raster_status s = check_params(scale, tau, mu);
     if (s != RASTER_OK) return s;
-    s = check_neighbourhood((int32_t)metric, delta);
+    s = check_options(opts);
     if (s != RASTER_OK) return s;
     if (tile_hint < 0) return fail(RASTER_E_INVAL, "negative tile_hint");
     raster_stream* h = new raster_stream();
-    h->run.metric = (uint32_t)metric;
-    h->run.delta = delta;
+    if (opts) {
+        h->run.metric = (uint32_t)opts->metric;
+        h->run.delta = opts->delta;
+        h->run.square = opts->square_step == 1;
+    }
     s = h->run.init(scale, tau, mu, tile_hint, stream);
     if (s != RASTER_OK) {
         delete h;
@@ -973,9 +994,15 @@ raster_status raster_begin_delta(double scale, uint32_t tau, uint32_t mu, raster
     return RASTER_OK;
 }
 
+raster_status raster_begin_delta(double scale, uint32_t tau, uint32_t mu, raster_metric metric, uint32_t delta,
+                                 int64_t tile_hint, hipStream_t stream, raster_stream** st) {
+    const raster_options o{metric, delta, 0, 0};
+    return raster_begin_opts(scale, tau, mu, &o, tile_hint, stream, st);
+}
+
 raster_status raster_begin_scaled(double scale, uint32_t tau, uint32_t mu, int64_t tile_hint, hipStream_t stream,
                                   raster_stream** st) {
-    return raster_begin_delta(scale, tau, mu, RASTER_CHEBYSHEV, 1, tile_hint, stream, st);
+    return raster_begin_opts(scale, tau, mu, nullptr, tile_hint, stream, st);
 }
 
 raster_status raster_begin(int32_t precision, uint32_t tau, uint32_t mu, int64_t tile_hint, hipStream_t stream,

@@ -13,6 +13,7 @@ namespace rst {
 constexpr uint64_t kEmptyKey = ~0ull;
 // aux of a slot whose tile is not significant.
 constexpr uint32_t kNotSignificant = 0xFFFFFFFFu;
+constexpr uint32_t kSquareKeep = 0xFFFFFFFEu;  // aux of a slot kept by the 2x2 post-step
 // Longest probe window of the open-addressing table.  A key lives within this
 // many slots of its home slot; an insert that finds the window full of other
 // keys spills the key instead, and the table is grown afterwards.
@@ -226,7 +227,8 @@ hipError_t launch_export_tiles(const Slot* tab, uint64_t tcap, uint64_t* keys, u
 // S_key, S_count (and S_job for several jobs), sets slot.aux, zeroes size[i],
 // and fills ctr[C_DISTINCT], ctr[C_SIGNIFICANT], ctr[C_SUM] (per job too).
 hipError_t launch_threshold(Slot* tab, const JobView& jv, uint64_t* s_key, uint32_t* s_count, uint32_t* size,
-                            uint32_t* partials, unsigned long long* ctr, hipStream_t stream);
+                            uint32_t* partials, unsigned long long* ctr, hipStream_t stream,
+                            uint64_t square_cap = 0);
 
 // Connected components of the significant tiles (8-adjacency).  On return
 // nbr[i] (its first s words) holds the compact index of the smallest tile of

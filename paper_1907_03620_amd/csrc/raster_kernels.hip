@@ -1092,6 +1092,17 @@ __device__ __forceinline__ void load_slots(const Slot* tab, uint64_t t0, uint64_
         if (t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x >= hi) key[j] = kEmptyKey;
 }
 
+// Marks of the 2x2 post-step for the slots of one scan tile: aux ==
+// kSquareKeep (set by k_square_part) makes a slot significant whatever its
+// count.  Items past hi read slot hi - 1; the caller masks them by key.
+__device__ __forceinline__ void load_square_marks(const Slot* tab, uint64_t t0, uint64_t hi,
+                                                  bool (&mark)[SCAN_ITEMS]) {
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j)
+        mark[j] = tab[min(t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x, hi - 1)].aux == kSquareKeep;
+}
+
+template <bool SQUARE>
 __global__ __launch_bounds__(SCAN_THREADS) void k_threshold_count(const Slot* tab, JobView jv, uint32_t* partials,
                                                                   unsigned long long* ctr) {
     __shared__ unsigned long long red[SCAN_WAVES];
@@ -1106,13 +1117,15 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_threshold_count(const Slot* ta
         unsigned long long occ_t = 0, sum_t = 0;
         uint64_t key[SCAN_ITEMS];
         uint32_t cnt[SCAN_ITEMS];
+        bool mark[SCAN_ITEMS] = {};
         load_slots(tab, t0, hi, key, cnt);
+        if (SQUARE) load_square_marks(tab, t0, hi, mark);
 #pragma unroll
         for (int j = 0; j < SCAN_ITEMS; ++j) {
             if (key[j] != kEmptyKey) {
                 occ_t += 1;
                 sum_t += cnt[j];
-                sig += (cnt[j] >= tau);
+                sig += (cnt[j] >= tau || mark[j]);
             }
         }
         occ += occ_t;
@@ -1136,6 +1149,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_threshold_count(const Slot* ta
     }
 }
 
+template <bool SQUARE>
 __global__ __launch_bounds__(SCAN_THREADS) void k_threshold_scatter(Slot* tab, JobView jv, const uint32_t* offsets,
                                                                     uint64_t* s_key, uint32_t* s_count,
                                                                     uint32_t* size) {
@@ -1151,10 +1165,12 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_threshold_scatter(Slot* tab, J
         uint32_t bits = 0;
         uint64_t key[SCAN_ITEMS];
         uint32_t cnt[SCAN_ITEMS];
+        bool mark[SCAN_ITEMS] = {};
         load_slots(tab, t0, hi, key, cnt);
+        if (SQUARE) load_square_marks(tab, t0, hi, mark);
 #pragma unroll
         for (int j = 0; j < SCAN_ITEMS; ++j)
-            if (key[j] != kEmptyKey && cnt[j] >= tau) bits |= 1u << j;
+            if (key[j] != kEmptyKey && (cnt[j] >= tau || mark[j])) bits |= 1u << j;
         uint32_t pos[SCAN_ITEMS];
         const uint32_t total = tile_positions(bits, pos, ts);
 #pragma unroll
@@ -1168,7 +1184,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_threshold_scatter(Slot* tab, J
                 size[p] = 0;
                 if (multi) jv.s_job[p] = job;
                 tab[i].aux = (uint32_t)p;
-            }  // other slots already hold kNotSignificant (fill and update passes write it)
+            }  // other slots hold kNotSignificant (fill and update passes write it; the 2x2 pass marks only
+               // slots that become significant here)
         }
         run += total;
     }
@@ -1309,6 +1326,93 @@ __device__ __forceinline__ void uf_unite(uint32_t* parent, const uint64_t* key, 
         b = uf_root(parent, b, s, bad);
     }
     bad = true;
+}
+
+// 2x2 post-step (Section 3.6, for points spread over the tiles around a grid
+// corner): a slot below tau whose tile lies in a 2x2 square of tiles that hold
+// at least tau points together gets aux = kSquareKeep, which the threshold
+// scan then counts as significant.  One workgroup per table partition with the
+// slice's keys and counts in LDS; the counts of the eight surrounding tiles are
+// read there when they share the partition, else from the device table.  Only
+// counts are read, and only aux is written, so the order of the partitions
+// does not matter.  Single job.
+constexpr int SQUARE_THREADS = 512;
+
+__global__ __launch_bounds__(SQUARE_THREADS) void k_square_part(Slot* tab, JobView jv) {
+    __shared__ uint64_t lkey[kPartSlots];
+    __shared__ uint32_t lcnt[kPartSlots];
+    __shared__ uint16_t list[kPartSlots];
+    __shared__ uint32_t nlist;
+    const JobInfo& J = jv.jobs[0];
+    const uint32_t tau = J.tau;
+    const Geo g = make_geo(J.cap);
+    const uint32_t psize = (uint32_t)min<uint64_t>(J.cap, kPartSlots);
+    const uint64_t parts = (J.cap + kPartSlots - 1) >> kPartLog2;
+    for (uint64_t p = blockIdx.x; p < parts; p += gridDim.x) {
+        const uint64_t base = p << kPartLog2;
+        if (threadIdx.x == 0) nlist = 0;
+        __syncthreads();
+        for (uint32_t u = threadIdx.x; u < psize; u += SQUARE_THREADS) {
+            const Slot v = tab[base + u];
+            lkey[u] = v.key;
+            lcnt[u] = v.count;
+        }
+        __syncthreads();
+        for (uint32_t u0 = 0; u0 < psize; u0 += SQUARE_THREADS) {
+            const uint32_t u = u0 + threadIdx.x;
+            const bool light = u < psize && lkey[u] != kEmptyKey && lcnt[u] < tau;
+            const uint64_t b = __ballot(light);
+            uint32_t wbase = 0;
+            if (lane_id() == 0 && b) wbase = atomicAdd(&nlist, (uint32_t)__popcll(b));
+            wbase = __shfl(wbase, 0);
+            if (light) list[wbase + __popcll(b & lanemask_lt())] = (uint16_t)u;
+        }
+        __syncthreads();
+        const uint32_t nl = nlist;
+        for (uint32_t t = threadIdx.x; t < nl; t += SQUARE_THREADS) {
+            const uint32_t u = list[t];
+            const uint32_t bx = (uint32_t)(lkey[u] >> 32);
+            const uint32_t by = (uint32_t)lkey[u];
+            uint64_t c[3][3];  // counts of the tiles (bx + dx, by + dy), [dx + 1][dy + 1]
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx)
+#pragma unroll
+                for (int dy = -1; dy <= 1; ++dy) {
+                    uint64_t n_cnt = 0;
+                    const int64_t x = (int64_t)bx + dx, y = (int64_t)by + dy;
+                    if (dx == 0 && dy == 0) {
+                        n_cnt = lcnt[u];
+                    } else if (x >= 2 && x <= 0xFFFFFFFEll && y >= 2 && y <= 0xFFFFFFFEll) {
+                        const uint64_t nk = ((uint64_t)(uint32_t)x << 32) | (uint32_t)y;
+                        const uint64_t pos = home_slot(nk, g);
+                        if ((pos >> kPartLog2) == p) {
+                            uint32_t lp = (uint32_t)(pos - base);
+                            for (uint32_t step = 0; step < kMaxProbe; ++step) {
+                                const uint64_t cur = lkey[lp];
+                                if (cur == nk) {
+                                    n_cnt = lcnt[lp];
+                                    break;
+                                }
+                                if (cur == kEmptyKey) break;
+                                lp = (lp + 1) & (psize - 1);
+                            }
+                        } else {
+                            const uint64_t at = table_find(tab, g, nk);
+                            if (at != ~0ull) n_cnt = tab[at].count;
+                        }
+                    }
+                    c[dx + 1][dy + 1] = n_cnt;
+                }
+            bool keep = false;
+#pragma unroll
+            for (int a = 0; a <= 1; ++a)
+#pragma unroll
+                for (int b = 0; b <= 1; ++b)
+                    keep |= c[a][b] + c[a + 1][b] + c[a][b + 1] + c[a + 1][b + 1] >= (uint64_t)tau;
+            if (keep) tab[base + u].aux = kSquareKeep;
+        }
+        __syncthreads();  // the slice is overwritten by the next partition
+    }
 }
 
 // Link pass: parent = the significant backward neighbour with the smallest
@@ -2192,11 +2296,22 @@ hipError_t launch_export_tiles(const Slot* tab, uint64_t tcap, uint64_t* keys, u
 }
 
 hipError_t launch_threshold(Slot* tab, const JobView& jv, uint64_t* s_key, uint32_t* s_count, uint32_t* size,
-                            uint32_t* partials, unsigned long long* ctr, hipStream_t stream) {
-    hipLaunchKernelGGL(k_threshold_count, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, tab, jv, partials, ctr);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, stream, partials, ctr + C_SIGNIFICANT);
-    hipLaunchKernelGGL(k_threshold_scatter, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, tab, jv, partials,
-                       s_key, s_count, size);
+                            uint32_t* partials, unsigned long long* ctr, hipStream_t stream, uint64_t square_cap) {
+    if (square_cap) {
+        const int grid = grid_for((square_cap + kPartSlots - 1) >> kPartLog2, 1, 8192);
+        hipLaunchKernelGGL(k_square_part, dim3(grid), dim3(SQUARE_THREADS), 0, stream, tab, jv);
+        hipLaunchKernelGGL(k_threshold_count<true>, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, tab, jv,
+                           partials, ctr);
+        hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, stream, partials, ctr + C_SIGNIFICANT);
+        hipLaunchKernelGGL(k_threshold_scatter<true>, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, tab, jv,
+                           partials, s_key, s_count, size);
+    } else {
+        hipLaunchKernelGGL(k_threshold_count<false>, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, tab, jv,
+                           partials, ctr);
+        hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, stream, partials, ctr + C_SIGNIFICANT);
+        hipLaunchKernelGGL(k_threshold_scatter<false>, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, tab, jv,
+                           partials, s_key, s_count, size);
+    }
     return hipGetLastError();
 }
 

@@ -55,6 +55,7 @@ uint64_t next_pow2(uint64_t v);
 raster_status check_points(const void* p, int64_t n, raster_dtype dt);
 raster_status check_params(double scale, uint32_t tau, uint32_t mu);
 raster_status check_neighbourhood(int32_t metric, uint32_t delta);
+raster_status check_options(const raster_options* o);
 // Link rounds of the neighbourhood; empty for Chebyshev 1, which has its own
 // fixed-offset pass.
 std::vector<NbrRound> neighbourhood_rounds(uint32_t metric, uint32_t delta);
@@ -98,6 +99,7 @@ struct TableRun {
     double scale = 1.0;
     uint32_t tau = 1, mu = 1;
     uint32_t metric = RASTER_CHEBYSHEV, delta = 1;  // neighbourhood of the agglomeration
+    bool square = false;                            // the 2x2 post-step before the threshold
     raster_tuning tuning{};
     Buffers bufs;
     Slot* tab = nullptr;
