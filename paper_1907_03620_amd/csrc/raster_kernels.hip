@@ -179,6 +179,29 @@ __device__ __forceinline__ uint32_t job_of_tile(const uint32_t* tile_prefix, uin
     return lo;
 }
 
+// Contiguous range of work tiles of one persistent workgroup, and the job of
+// its first tile.  Consecutive tiles mostly belong to one job, so the job is
+// found once and then advanced at job boundaries (tile_prefix has njobs + 1
+// entries, the last one the tile total); and at any moment the workgroups
+// work on many jobs, not all on one job's buckets.
+struct TileRange {
+    uint32_t lo, hi, job;
+};
+
+__device__ __forceinline__ TileRange tile_range(const uint32_t* tile_prefix, uint32_t njobs, uint32_t tiles) {
+    const uint32_t per = (tiles + gridDim.x - 1) / gridDim.x;
+    TileRange r;
+    r.lo = min(blockIdx.x * per, tiles);
+    r.hi = min(r.lo + per, tiles);
+    r.job = r.lo < r.hi ? job_of_tile(tile_prefix, njobs, r.lo) : 0u;
+    return r;
+}
+
+__device__ __forceinline__ uint32_t advance_job(const uint32_t* tile_prefix, uint32_t job, uint32_t t) {
+    while (tile_prefix[job + 1] <= t) ++job;  // skips jobs without tiles
+    return job;
+}
+
 __device__ __forceinline__ bool job_point_key(const JobInfo& J, int64_t i, uint64_t& key) {
     double x, y;
     if (J.dtype == 1) load_point(static_cast<const float*>(J.pts), i, x, y);
@@ -815,8 +838,10 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bbin_points(JobView jv, const u
     const uint32_t tiles = jv.dims->tiles, njobs = jv.dims->njobs;
     const uint64_t cap1 = jv.dims->cap1;
     const SpillBuf none{nullptr, nullptr, 0};
-    for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
-        const uint32_t job = job_of_tile(tile_prefix, njobs, t);
+    const TileRange tr = tile_range(tile_prefix, njobs, tiles);
+    uint32_t job = tr.job;
+    for (uint32_t t = tr.lo; t < tr.hi; ++t) {
+        job = advance_job(tile_prefix, job, t);
         const JobInfo& J = jv.jobs[job];
         const Geo g = make_geo(J.cap);
         const uint32_t top = g.p_log2 - J.cshift;  // coarse bits of the hash
@@ -828,13 +853,26 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bbin_points(JobView jv, const u
         uint16_t bucket[BIN_ITEMS];
         uint32_t valid = 0;
         bool bad = false;
+        // all loads first, indices clamped (a tile holds at least one point of
+        // its job) and results masked, so that they are in flight together
+        double x[BIN_ITEMS], y[BIN_ITEMS];
+        if (J.dtype == 1) {
+#pragma unroll
+            for (int j = 0; j < BIN_ITEMS; ++j)
+                load_point(static_cast<const float*>(J.pts), min(base + (int64_t)j * BIN_THREADS, J.n - 1), x[j], y[j]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < BIN_ITEMS; ++j)
+                load_point(static_cast<const double*>(J.pts), min(base + (int64_t)j * BIN_THREADS, J.n - 1), x[j],
+                           y[j]);
+        }
 #pragma unroll
         for (int j = 0; j < BIN_ITEMS; ++j) {
             const int64_t i = base + (int64_t)j * BIN_THREADS;
             key[j] = 0;
             bucket[j] = 0;
             if (i < J.n) {
-                if (job_point_key(J, i, key[j])) {
+                if (tile_key(x[j], y[j], J.scale, key[j])) {
                     valid |= 1u << j;
                     bucket[j] = (uint16_t)bucket_of(key[j], top, nb);
                 } else {
@@ -857,11 +895,14 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bbin_keys(JobView jv, const uin
     __shared__ BinScratch S;
     const uint64_t cap1 = jv.dims->cap1;
     const uint32_t segs = jv.dims->segs;
-    const uint64_t work = (uint64_t)jv.dims->ncoarse * segs;
+    const uint32_t ncoarse = jv.dims->ncoarse;
+    const uint64_t work = (uint64_t)ncoarse * segs;
     const SpillBuf none{nullptr, nullptr, 0};
+    // segment-major: workgroups running together take different coarse
+    // buckets, so their cursor updates land on different partitions' lines
     for (uint64_t w = blockIdx.x; w < work; w += gridDim.x) {
-        const uint32_t c = (uint32_t)(w / segs);
-        const uint32_t seg = (uint32_t)(w % segs);
+        const uint32_t c = (uint32_t)(w % ncoarse);
+        const uint32_t seg = (uint32_t)(w / ncoarse);
         const uint64_t cnt = min((uint64_t)cursor1[c], cap1);
         const uint64_t start = (uint64_t)seg * kBinTile;
         if (start >= cnt) continue;  // uniform across the workgroup
@@ -875,15 +916,19 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bbin_keys(JobView jv, const uin
         uint16_t bucket[BIN_ITEMS];
         uint32_t valid = 0;
         const uint64_t* src = bin1 + (uint64_t)c * cap1;
+        // all loads first (indices clamped below cnt > start, results masked)
+#pragma unroll
+        for (int j = 0; j < BIN_ITEMS; ++j)
+            key[j] = __builtin_nontemporal_load(src + min(start + (uint64_t)j * BIN_THREADS + threadIdx.x, cnt - 1));
 #pragma unroll
         for (int j = 0; j < BIN_ITEMS; ++j) {
             const uint64_t i = start + (uint64_t)j * BIN_THREADS + threadIdx.x;
-            key[j] = 0;
             bucket[j] = 0;
             if (i < cnt) {
-                key[j] = __builtin_nontemporal_load(src + i);
                 bucket[j] = (uint16_t)bucket_of(key[j], g.p_log2, nb);
                 valid |= 1u << j;
+            } else {
+                key[j] = 0;
             }
         }
         uint32_t fresh = 0;
@@ -1778,33 +1823,38 @@ __global__ __launch_bounds__(256) void k_points_hll(const T* __restrict__ pts, i
 // before counting.  Reads every point once; range errors are left to the
 // counting pass.
 
+// One work tile of k_batch_hll in the job's point type: loads of all items
+// first (indices clamped, results masked), then the sampled keys.
+template <typename T>
+__device__ __forceinline__ void hll_tile(const T* pts, int64_t base, int64_t end, double scale, uint32_t* reg) {
+    constexpr int U = 16;
+    for (int64_t i0 = base; i0 < end; i0 += (int64_t)U * blockDim.x) {
+        double x[U], y[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) load_point(pts, min(i0 + (int64_t)u * blockDim.x + threadIdx.x, end - 1), x[u], y[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            uint64_t key;
+            if (i0 + (int64_t)u * blockDim.x + threadIdx.x >= end || !tile_key(x[u], y[u], scale, key)) continue;
+            uint32_t r, rank;
+            if (hll_sample(key, r, rank)) atomicMax(reg + r, rank);
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_batch_hll(JobView jv, const uint32_t* tile_prefix, uint32_t tile,
                                                    uint32_t* hll) {
-    constexpr int U = 16;
     const uint32_t tiles = jv.dims->tiles, njobs = jv.dims->njobs;
-    for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
-        const uint32_t job = job_of_tile(tile_prefix, njobs, t);
+    const TileRange tr = tile_range(tile_prefix, njobs, tiles);
+    uint32_t job = tr.job;
+    for (uint32_t t = tr.lo; t < tr.hi; ++t) {
+        job = advance_job(tile_prefix, job, t);
         const JobInfo& J = jv.jobs[job];
         const int64_t base = (int64_t)(t - J.first_tile) * tile;
         const int64_t end = min(base + (int64_t)tile, J.n);
         uint32_t* reg = hll + ((uint64_t)job << kHllLog2);
-        for (int64_t i0 = base; i0 < end; i0 += (int64_t)U * blockDim.x) {
-            // loads of all items first (indices clamped, results masked)
-            double x[U], y[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t i = min(i0 + (int64_t)u * blockDim.x + threadIdx.x, end - 1);
-                if (J.dtype == 1) load_point(static_cast<const float*>(J.pts), i, x[u], y[u]);
-                else load_point(static_cast<const double*>(J.pts), i, x[u], y[u]);
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                uint64_t key;
-                if (i0 + (int64_t)u * blockDim.x + threadIdx.x >= end || !tile_key(x[u], y[u], J.scale, key)) continue;
-                uint32_t r, rank;
-                if (hll_sample(key, r, rank)) atomicMax(reg + r, rank);
-            }
-        }
+        if (J.dtype == 1) hll_tile(static_cast<const float*>(J.pts), base, end, J.scale, reg);
+        else hll_tile(static_cast<const double*>(J.pts), base, end, J.scale, reg);
     }
 }
 
