@@ -759,20 +759,26 @@ __device__ __forceinline__ void aggregate_partition(const PartLists<NL>& L, Slot
     // covers positions [lo, hi) of the concatenation
     uint32_t li = 0, lo = 0, hi = L.size[0];
     for (uint32_t q0 = 0; q0 < cnt; q0 += AGG_THREADS * AGG_BATCH) {
-        uint64_t k[AGG_BATCH];
+        // addresses first (positions past the end clamped to the last key),
+        // then all loads unconditionally, then the masks: no load waits for
+        // another
+        const uint64_t* at[AGG_BATCH];
 #pragma unroll
         for (int u = 0; u < AGG_BATCH; ++u) {
-            const uint32_t q = q0 + u * AGG_THREADS + threadIdx.x;
-            k[u] = kEmptyKey;
-            if (q < cnt) {
-                while (q >= hi) {
-                    ++li;
-                    lo = hi;
-                    hi += L.size_of(li);
-                }
-                k[u] = __builtin_nontemporal_load(L.src + li * L.lstride + (q - lo));
+            const uint32_t q = min(q0 + u * AGG_THREADS + threadIdx.x, cnt - 1);
+            while (q >= hi) {
+                ++li;
+                lo = hi;
+                hi += L.size_of(li);
             }
+            at[u] = L.src + li * L.lstride + (q - lo);
         }
+        uint64_t k[AGG_BATCH];
+#pragma unroll
+        for (int u = 0; u < AGG_BATCH; ++u) k[u] = __builtin_nontemporal_load(at[u]);
+#pragma unroll
+        for (int u = 0; u < AGG_BATCH; ++u)
+            if (q0 + u * AGG_THREADS + threadIdx.x >= cnt) k[u] = kEmptyKey;
         // home-slot reads of all keys together; most keys find themselves
         // there, and only the others walk the probe sequence
         uint32_t pos[AGG_BATCH];
