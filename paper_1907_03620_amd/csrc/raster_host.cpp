@@ -557,15 +557,32 @@ raster_status TableRun::flush() {
     return settle();
 }
 
+// Whether a chunk of n points can be binned without first waiting for the
+// previous chunk's counters.  Binning writes the table only for keys past a
+// full bucket (spilled into a buffer that holds the whole group), so the
+// counters can only ask for a flush, a growth or a resize, none of which this
+// chunk needs when it fits the group, the bins and the spill buffer as they
+// are.  Errors of the earlier chunks are then reported by a later call.
+bool TableRun::can_bin_unsettled(int64_t n) const {
+    if (!chunk_pending || !last_binned || single_shot || n <= 0 || (uint64_t)n > group_budget) return false;
+    const Geo g = make_geo(cap);
+    const bool binned = (tuning.mode == 2 || (tuning.mode == 0 && (uint64_t)n >= cap / 8)) && binned_geometry(g);
+    if (!binned || !bin1 || group_points == 0 || group_points + (uint64_t)n > bin_points) return false;
+    return spill_cap[0] >= std::min<uint64_t>(group_budget, group_points + (uint64_t)n);
+}
+
 raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
-    raster_status st = settle();
+    const bool unsettled = can_bin_unsettled(n);
+    raster_status st = unsettled ? RASTER_OK : settle();
     if (st != RASTER_OK) return st;
     if (n == 0) return RASTER_OK;
     if ((uint64_t)n_points + (uint64_t)n > 0xFFFFFFFFull)
         return fail(RASTER_E_RANGE, "more than 2^32 - 1 points in one table");
     const double lf = tuning.load_factor;
     uint64_t want = 0;
-    if (n_points == 0 && !hinted) {
+    if (unsettled) {
+        // the counters are those of an earlier chunk: no growth decision
+    } else if (n_points == 0 && !hinted) {
         // no hint and nothing seen yet: size for half the first chunk's points
         // being distinct tiles
         want = next_pow2((uint64_t)((double)n / 2.0 / lf) + 1);
@@ -589,8 +606,13 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
     // Pieces of at most group_budget points, settled in between.  Spill
     // records between two settles come from one piece or one group, so the
     // buffer never needs more than what is binned plus this chunk.
-    st = ensure_spill(0, std::min<uint64_t>(group_budget, group_points + (uint64_t)n));
+    // A stream sizes the buffer for its whole bin group (which it reaches by
+    // the group's end anyway), so that later chunks need no resize and can go
+    // in without waiting (can_bin_unsettled).
+    const uint64_t spill_want = group_points + (uint64_t)n + (single_shot ? 0 : bin_points);
+    st = ensure_spill(0, std::min<uint64_t>(group_budget, spill_want));
     if (st != RASTER_OK) return st;
+    bool all_binned = true;
     for (int64_t off = 0; off < n;) {
         const int64_t piece = std::min<int64_t>(n - off, (int64_t)group_budget);
         const void* p = (const char*)pts + (size_t)off * point_bytes;
@@ -617,6 +639,7 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
             if ((st = span_end(0, a)) != RASTER_OK) return st;
             group_points += (uint64_t)piece;
         } else {
+            all_binned = false;
             if (single_shot && piece >= (int64_t)kSketchMinPoints && n_points == 0) {
                 // one read of the points sizes the table before any insert
                 if ((st = ensure_sketch()) != RASTER_OK) return st;
@@ -634,6 +657,7 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
         if ((st = mark_pending()) != RASTER_OK) return st;
         if (off < n && (st = settle()) != RASTER_OK) return st;
     }
+    last_binned = all_binned;
     return RASTER_OK;
 }
 

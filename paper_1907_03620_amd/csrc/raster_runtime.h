@@ -137,6 +137,7 @@ struct TableRun {
     bool single_shot = false;  // plain call: all points come in one feed
     int32_t flushes = 0;
     bool chunk_pending = false;
+    bool last_binned = false;  // the last chunk was binned whole (no table insert but overflow)
     bool timing_started = false;
     bool hinted = false;  // tile_hint given: the first chunk does not resize the table
     int64_t n_points = 0;
@@ -146,6 +147,7 @@ struct TableRun {
     ~TableRun();
     raster_status init(double scale, uint32_t tau, uint32_t mu, int64_t tile_hint, hipStream_t stream);
     raster_status feed(const void* pts, int64_t n, raster_dtype dt);
+    bool can_bin_unsettled(int64_t n) const;
     raster_status finish(raster_result** out);
     raster_status export_tiles(uint64_t* keys, uint32_t* counts, int64_t cap_rows, int64_t* m);
 

@@ -323,6 +323,27 @@ def test_binned_range_error(raster, torch, mid):
     assert e.value.code == raster.E_RANGE
 
 
+def test_stream_range_error_in_a_middle_chunk(raster, torch, mid):
+    # binned chunks go in without waiting for the previous chunk's counters;
+    # a bad coordinate in a middle chunk must still fail the stream, by
+    # finish at the latest, and every later call must report it
+    chunks = [c.copy() for c in np.array_split(mid[:1_200_000], 6)]
+    chunks[2][1234, 0] = np.nan
+    raster.set_tuning(mode=2)
+    try:
+        st = raster.Stream(tau=5, mu=4, precision=2, tile_hint=500_000)
+        with pytest.raises(raster.RasterError) as e:
+            for c in chunks:
+                st.feed(dev(c, torch))
+            st.finish()
+        assert e.value.code == raster.E_RANGE
+        with pytest.raises(raster.RasterError):
+            st.finish()
+        st.close()
+    finally:
+        raster.set_tuning(None)
+
+
 def test_repeated_runs_identical(raster, torch, mid, mid_oracle):
     # races in the union-find passes show up as run-to-run differences
     d = dev(mid, torch)
