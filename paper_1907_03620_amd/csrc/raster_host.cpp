@@ -264,15 +264,72 @@ std::vector<NbrRound> neighbourhood_rounds(uint32_t metric, uint32_t delta) {
         if (e_ != hipSuccess) return hip_fail(e_, what); \
     } while (0)
 
-TableRun::~TableRun() {
-    for (hipEvent_t& e : ev) if (e) (void)hipEventDestroy(e);
-    if (ev_chunk) (void)hipEventDestroy(ev_chunk);
-    for (const Span& sp : spans) {
-        (void)hipEventDestroy(sp.a);
-        (void)hipEventDestroy(sp.b);
+// ---- process-wide caches of pinned counter mirrors and events ---------------
+//
+// A stream's begin and end would otherwise pin and free host memory and
+// create and destroy events every time, which costs more than a small step's
+// kernels.  Events are kept per device (they belong to the device current at
+// creation).
+
+namespace {
+
+struct HostCache {
+    std::mutex mu;
+    std::vector<unsigned long long*> pinned;
+    std::map<std::pair<int, bool>, std::vector<hipEvent_t>> events;  // (device, timing) -> free events
+
+    static HostCache& get() {
+        static HostCache* c = new HostCache();  // never destroyed: lives past static teardown
+        return *c;
     }
-    for (hipEvent_t e : ev_free) (void)hipEventDestroy(e);
-    if (h_ctr) (void)hipHostFree(h_ctr);
+    hipError_t take_pinned(unsigned long long** p) {
+        {
+            std::lock_guard<std::mutex> g(mu);
+            if (!pinned.empty()) {
+                *p = pinned.back();
+                pinned.pop_back();
+                return hipSuccess;
+            }
+        }
+        return hipHostMalloc((void**)p, kCounterWords * sizeof(unsigned long long), hipHostMallocDefault);
+    }
+    void give_pinned(unsigned long long* p) {
+        std::lock_guard<std::mutex> g(mu);
+        pinned.push_back(p);
+    }
+    hipError_t take_event(int dev, bool timing, hipEvent_t* e) {
+        {
+            std::lock_guard<std::mutex> g(mu);
+            auto& v = events[{dev, timing}];
+            if (!v.empty()) {
+                *e = v.back();
+                v.pop_back();
+                return hipSuccess;
+            }
+        }
+        return timing ? hipEventCreate(e) : hipEventCreateWithFlags(e, hipEventDisableTiming);
+    }
+    void give_event(int dev, bool timing, hipEvent_t e) {
+        std::lock_guard<std::mutex> g(mu);
+        events[{dev, timing}].push_back(e);
+    }
+};
+
+}  // namespace
+
+TableRun::~TableRun() {
+    HostCache& hc = HostCache::get();
+    // a counter copy may still be in flight into h_ctr: wait before another
+    // stream can receive the mirror
+    if (chunk_pending && ev_chunk) (void)hipEventSynchronize(ev_chunk);
+    for (hipEvent_t& e : ev) if (e) hc.give_event(device, true, e);
+    if (ev_chunk) hc.give_event(device, false, ev_chunk);
+    for (const Span& sp : spans) {
+        hc.give_event(device, true, sp.a);
+        hc.give_event(device, true, sp.b);
+    }
+    for (hipEvent_t e : ev_free) hc.give_event(device, true, e);
+    if (h_ctr) hc.give_pinned(h_ctr);
 }
 
 double hll_estimate(const uint32_t* M) {
@@ -340,11 +397,11 @@ raster_status TableRun::init(double scale_, uint32_t tau_, uint32_t mu_, int64_t
     bufs.pool = &DevicePool::get(device);
     tuning = current_tuning();
     group_budget = (uint64_t)tuning.group_mpoints * 1000000ull;
-    HIP_TRY(hipHostMalloc((void**)&h_ctr, kCounterWords * sizeof(unsigned long long), hipHostMallocDefault),
-            "hipHostMalloc");
+    HostCache& hc = HostCache::get();
+    HIP_TRY(hc.take_pinned(&h_ctr), "hipHostMalloc");
     std::memset(h_ctr, 0, kCounterWords * sizeof(unsigned long long));
-    for (hipEvent_t& e : ev) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
-    HIP_TRY(hipEventCreateWithFlags(&ev_chunk, hipEventDisableTiming), "hipEventCreate");
+    for (hipEvent_t& e : ev) HIP_TRY(hc.take_event(device, true, &e), "hipEventCreate");
+    HIP_TRY(hc.take_event(device, false, &ev_chunk), "hipEventCreate");
     HIP_TRY(bufs.take((void**)&ctr, kCounterWords * sizeof(unsigned long long)), "counters");
     HIP_TRY(bufs.take((void**)&partials, kScanBlocks * sizeof(uint32_t)), "scan partials");
     HIP_TRY(launch_zero_u64((uint64_t*)ctr, kCounterWords, stream), "zero counters");
@@ -394,7 +451,7 @@ raster_status TableRun::span_begin(int kind, hipEvent_t* a) {
         *a = ev_free.back();
         ev_free.pop_back();
     } else {
-        HIP_TRY(hipEventCreate(a), "hipEventCreate");
+        HIP_TRY(HostCache::get().take_event(device, true, a), "hipEventCreate");
     }
     HIP_TRY(hipEventRecord(*a, stream), "hipEventRecord");
     return RASTER_OK;
@@ -406,7 +463,7 @@ raster_status TableRun::span_end(int kind, hipEvent_t a) {
         b = ev_free.back();
         ev_free.pop_back();
     } else {
-        HIP_TRY(hipEventCreate(&b), "hipEventCreate");
+        HIP_TRY(HostCache::get().take_event(device, true, &b), "hipEventCreate");
     }
     HIP_TRY(hipEventRecord(b, stream), "hipEventRecord");
     spans.push_back(Span{kind, a, b});
