@@ -62,19 +62,19 @@ def _load():
     lib.oracle_project.restype = ctypes.c_int
     lib.oracle_begin.argtypes = [dbl, u64, u64]
     lib.oracle_begin.restype = vp
-    lib.oracle_begin_ex.argtypes = [dbl, u64, u64, i32, i64, i32]
+    lib.oracle_begin_ex.argtypes = [dbl, u64, u64, i32, i64, i32, i32]
     lib.oracle_begin_ex.restype = vp
     lib.oracle_feed.argtypes = [vp, vp, i64, i32]
     lib.oracle_feed.restype = ctypes.c_int
     lib.oracle_num_tiles.argtypes = [vp]
     lib.oracle_num_tiles.restype = i64
-    lib.oracle_tile_counts.argtypes = [vp, vp, vp, vp]
+    lib.oracle_tile_counts.argtypes = [vp, vp, vp, vp, vp]
     lib.oracle_tile_counts.restype = ctypes.c_int
     lib.oracle_finish.argtypes = [vp]
     lib.oracle_finish.restype = ctypes.c_int
     lib.oracle_stats.argtypes = [vp, vp]
     lib.oracle_stats.restype = ctypes.c_int
-    lib.oracle_result.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.oracle_result.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.oracle_result.restype = ctypes.c_int
     lib.oracle_count_tiles.argtypes = [vp, i64, i32, dbl, vp, vp, i64, vp]
     lib.oracle_count_tiles.restype = ctypes.c_int
@@ -94,15 +94,21 @@ def scale_for_precision(p: int) -> float:
     return float(_load().oracle_scale_for_precision(int(p)))
 
 
-def _as_points(points):
+def _as_points(points, dims: int = 2):
     a = np.asarray(points)
     if a.dtype == np.float32:
         dt = F32
     else:
         a = a.astype(np.float64, copy=False)
         dt = F64
-    a = np.ascontiguousarray(a.reshape(-1, 2))
+    a = np.ascontiguousarray(a.reshape(-1, dims))
     return a, dt
+
+
+def _dims_of(points) -> int:
+    """3 for an (n, 3) array, else 2."""
+    a = np.asarray(points)
+    return 3 if a.ndim == 2 and a.shape[1] == 3 else 2
 
 
 def project(points, scale: float):
@@ -140,6 +146,8 @@ class OracleResult:
     label_x: np.ndarray
     label_y: np.ndarray
     stats: dict = field(default_factory=dict)
+    kz: np.ndarray | None = None       # 3-D only
+    label_z: np.ndarray | None = None  # 3-D only
 
     @property
     def num_tiles(self) -> int:
@@ -157,18 +165,20 @@ class OracleStream:
     """Chunked contraction (Section 3.6) followed by one agglomeration.
     Clusters join significant tiles within ``delta`` steps of each other in
     the given metric (Section 3.2); the default is the eight adjacent tiles.
-    ``window`` adds the 2x2 post-step of Section 3.6."""
+    ``window`` adds the 2x2 post-step of Section 3.6; ``dims`` = 3 takes
+    three-dimensional points (Section 3.6's generalisation)."""
 
     def __init__(self, scale: float, tau: int, mu: int, metric: str = "chebyshev", delta: int = 1,
-                 window: bool = False):
+                 window: bool = False, dims: int = 2):
         self._lib = _load()
+        self._dims = int(dims)
         self._h = self._lib.oracle_begin_ex(float(scale), int(tau), int(mu), METRICS[metric], int(delta),
-                                            int(bool(window)))
+                                            int(bool(window)), self._dims)
         if not self._h:
             raise OracleError(E_INVAL, "begin")
 
     def feed(self, points) -> None:
-        a, dt = _as_points(points)
+        a, dt = _as_points(points, self._dims)
         rc = self._lib.oracle_feed(self._h, a.ctypes.data, a.shape[0], dt)
         if rc != OK:
             raise OracleError(rc, "feed")
@@ -181,11 +191,13 @@ class OracleStream:
         m = self.num_tiles()
         kx = np.empty(m, np.int64)
         ky = np.empty(m, np.int64)
+        kz = np.empty(m, np.int64) if self._dims == 3 else None
         c = np.empty(m, np.uint64)
-        rc = self._lib.oracle_tile_counts(self._h, kx.ctypes.data, ky.ctypes.data, c.ctypes.data)
+        rc = self._lib.oracle_tile_counts(self._h, kx.ctypes.data, ky.ctypes.data,
+                                          kz.ctypes.data if kz is not None else None, c.ctypes.data)
         if rc != OK:
             raise OracleError(rc, "tile_counts")
-        return kx, ky, c
+        return (kx, ky, c) if kz is None else (kx, ky, kz, c)
 
     def stats(self) -> dict:
         st = np.zeros(7, np.int64)
@@ -205,11 +217,14 @@ class OracleStream:
         c = np.empty(t, np.uint64)
         lx = np.empty(t, np.int64)
         ly = np.empty(t, np.int64)
-        rc = self._lib.oracle_result(self._h, kx.ctypes.data, ky.ctypes.data, c.ctypes.data,
-                                     lx.ctypes.data, ly.ctypes.data)
+        kz = np.empty(t, np.int64) if self._dims == 3 else None
+        lz = np.empty(t, np.int64) if self._dims == 3 else None
+        rc = self._lib.oracle_result(self._h, kx.ctypes.data, ky.ctypes.data,
+                                     kz.ctypes.data if kz is not None else None, c.ctypes.data,
+                                     lx.ctypes.data, ly.ctypes.data, lz.ctypes.data if lz is not None else None)
         if rc != OK:
             raise OracleError(rc, "result")
-        return OracleResult(kx, ky, c, lx, ly, st)
+        return OracleResult(kx, ky, c, lx, ly, st, kz, lz)
 
     def close(self) -> None:
         if self._h:
@@ -233,9 +248,10 @@ def _scale(precision, scale):
 
 def cluster(points, tau: int, mu: int, precision: int | None = None,
             scale: float | None = None, metric: str = "chebyshev", delta: int = 1,
-            window: bool = False) -> OracleResult:
-    """RASTER on one in-memory point set."""
-    st = OracleStream(_scale(precision, scale), tau, mu, metric, delta, window)
+            window: bool = False, dims: int | None = None) -> OracleResult:
+    """RASTER on one in-memory point set ((n, 2), or (n, 3) for 3-D)."""
+    st = OracleStream(_scale(precision, scale), tau, mu, metric, delta, window,
+                      dims if dims is not None else _dims_of(points))
     try:
         st.feed(points)
         return st.finish()
@@ -297,9 +313,9 @@ def tile_points(points, result: OracleResult, precision: int | None = None,
 
 def cluster_chunks(chunks, tau: int, mu: int, precision: int | None = None,
                    scale: float | None = None, metric: str = "chebyshev", delta: int = 1,
-                   window: bool = False) -> OracleResult:
+                   window: bool = False, dims: int = 2) -> OracleResult:
     """RASTER over an iterable of point chunks (Section 3.6)."""
-    st = OracleStream(_scale(precision, scale), tau, mu, metric, delta, window)
+    st = OracleStream(_scale(precision, scale), tau, mu, metric, delta, window, dims)
     try:
         for c in chunks:
             st.feed(c)

@@ -19,6 +19,10 @@
 //   * A point whose product is not finite or whose magnitude is at least
 //     2^31 - 1 is a range error (tile coordinates must fit |k| <= 2^31 - 2);
 //     the whole chunk is then rejected and the stream fails.
+//   * Three-dimensional points (Section 3.6 generalises the method to d
+//     dimensions): the same projection per coordinate, |k| <= 2^20 - 2, and
+//     the neighbourhood taken over all three coordinates (26 tiles at
+//     Chebyshev 1, 6 at Manhattan 1: 3^d - 1 and 2d).
 //   * Significant means count >= tau (Algorithm 1 removes tiles whose count is
 //     below tau).  tau = 0 and mu = 0 are invalid arguments.
 //   * neighbors(u, delta) holds the tiles at Chebyshev distance 1 to delta
@@ -54,10 +58,14 @@ constexpr int kInval = -1;
 constexpr int kRange = -2;
 constexpr int kState = -5;
 
+// A tile of the 2-D grid (z = 0) or of the 3-D grid (Section 3.6 generalises
+// the method to d dimensions).  Order is lexicographic in (x, y, z).
 struct Tile {
-    int64_t x, y;
-    bool operator==(const Tile& o) const { return x == o.x && y == o.y; }
-    bool operator<(const Tile& o) const { return x < o.x || (x == o.x && y < o.y); }
+    int64_t x, y, z = 0;
+    bool operator==(const Tile& o) const { return x == o.x && y == o.y && z == o.z; }
+    bool operator<(const Tile& o) const {
+        return x < o.x || (x == o.x && (y < o.y || (y == o.y && z < o.z)));
+    }
 };
 
 struct TileHash {
@@ -65,14 +73,22 @@ struct TileHash {
         // std::hash of each coordinate, combined; any hash gives the same result.
         size_t a = std::hash<int64_t>()(t.x);
         size_t b = std::hash<int64_t>()(t.y);
-        return a ^ (b + 0x9e3779b97f4a7c15ULL + (a << 6) + (a >> 2));
+        size_t c = std::hash<int64_t>()(t.z);
+        a ^= b + 0x9e3779b97f4a7c15ULL + (a << 6) + (a >> 2);
+        return a ^ (c + 0x9e3779b97f4a7c15ULL + (a << 6) + (a >> 2));
     }
 };
 
+// Largest magnitude of a scaled coordinate, exclusive: tile coordinates must
+// fit |k| <= 2^31 - 2 in 2-D and |k| <= 2^20 - 2 in 3-D (three coordinates
+// share one 64-bit key on the GPU).
+constexpr double kBound2d = 2147483647.0;
+constexpr double kBound3d = 1048575.0;
+
 // Section 3.2: scale the coordinate and truncate it to an integer.
-int project_coord(double v, double scale, int64_t* k) {
+int project_coord(double v, double scale, double bound, int64_t* k) {
     double p = v * scale;
-    if (!(std::fabs(p) < 2147483647.0)) return kRange;  // also rejects NaN and Inf
+    if (!(std::fabs(p) < bound)) return kRange;  // also rejects NaN and Inf
     *k = (int64_t)std::trunc(p);
     return kOK;
 }
@@ -83,6 +99,8 @@ struct OracleStream {
     int32_t metric = 0;  // 0: Chebyshev, 1: Manhattan
     int64_t delta = 1;
     bool window = false;  // the 2x2 post-step
+    int32_t dims = 2;     // coordinates per point and per tile: 2 or 3
+    double bound = kBound2d;
     bool failed = false;
     bool finished = false;
     uint64_t n_points = 0;
@@ -95,9 +113,9 @@ struct OracleStream {
     std::vector<Tile> out_label;
 };
 
-double point_coord(const void* pts, int dtype, int64_t i, int c) {
-    if (dtype == 1) return (double)((const float*)pts)[2 * i + c];
-    return ((const double*)pts)[2 * i + c];
+double point_coord(const void* pts, int dtype, int dims, int64_t i, int c) {
+    if (dtype == 1) return (double)((const float*)pts)[dims * i + c];
+    return ((const double*)pts)[dims * i + c];
 }
 
 }  // namespace
@@ -118,17 +136,19 @@ int oracle_project(const void* pts, int64_t n, int32_t dtype, double scale,
                    int64_t* kx, int64_t* ky) {
     if (n < 0 || (dtype != 1 && dtype != 2) || (n > 0 && (!pts || !kx || !ky))) return kInval;
     for (int64_t i = 0; i < n; ++i) {
-        if (project_coord(point_coord(pts, dtype, i, 0), scale, &kx[i]) != kOK) return kRange;
-        if (project_coord(point_coord(pts, dtype, i, 1), scale, &ky[i]) != kOK) return kRange;
+        if (project_coord(point_coord(pts, dtype, 2, i, 0), scale, kBound2d, &kx[i]) != kOK) return kRange;
+        if (project_coord(point_coord(pts, dtype, 2, i, 1), scale, kBound2d, &ky[i]) != kOK) return kRange;
     }
     return kOK;
 }
 
 // metric: 0 = Chebyshev, 1 = Manhattan; 1 <= delta <= 64; window: 0 or 1
-// (the 2x2 post-step).
-void* oracle_begin_ex(double scale, uint64_t tau, uint64_t mu, int32_t metric, int64_t delta, int32_t window) {
+// (the 2x2 post-step, 2-D only); dims: 2 or 3.
+void* oracle_begin_ex(double scale, uint64_t tau, uint64_t mu, int32_t metric, int64_t delta, int32_t window,
+                      int32_t dims) {
     if (!(scale > 0.0) || !std::isfinite(scale) || tau == 0 || mu == 0) return nullptr;
     if ((metric != 0 && metric != 1) || delta < 1 || delta > 64 || (window != 0 && window != 1)) return nullptr;
+    if ((dims != 2 && dims != 3) || (dims == 3 && window == 1)) return nullptr;
     OracleStream* s = new OracleStream();
     s->scale = scale;
     s->tau = tau;
@@ -136,10 +156,12 @@ void* oracle_begin_ex(double scale, uint64_t tau, uint64_t mu, int32_t metric, i
     s->metric = metric;
     s->delta = delta;
     s->window = window == 1;
+    s->dims = dims;
+    s->bound = dims == 3 ? kBound3d : kBound2d;
     return s;
 }
 
-void* oracle_begin(double scale, uint64_t tau, uint64_t mu) { return oracle_begin_ex(scale, tau, mu, 0, 1, 0); }
+void* oracle_begin(double scale, uint64_t tau, uint64_t mu) { return oracle_begin_ex(scale, tau, mu, 0, 1, 0, 2); }
 
 // Contraction over one chunk of points (Algorithm 1, first loop).  Chunks may
 // come in any number and order (Section 3.6).  The chunk is checked first, so a
@@ -152,8 +174,10 @@ int oracle_feed(void* h, const void* pts, int64_t n, int32_t dtype) {
     std::vector<Tile> keys((size_t)n);
     for (int64_t i = 0; i < n; ++i) {
         Tile t;
-        if (project_coord(point_coord(pts, dtype, i, 0), s->scale, &t.x) != kOK ||
-            project_coord(point_coord(pts, dtype, i, 1), s->scale, &t.y) != kOK) {
+        if (project_coord(point_coord(pts, dtype, s->dims, i, 0), s->scale, s->bound, &t.x) != kOK ||
+            project_coord(point_coord(pts, dtype, s->dims, i, 1), s->scale, s->bound, &t.y) != kOK ||
+            (s->dims == 3 &&
+             project_coord(point_coord(pts, dtype, s->dims, i, 2), s->scale, s->bound, &t.z) != kOK)) {
             s->failed = true;
             return kRange;
         }
@@ -174,9 +198,9 @@ int64_t oracle_num_tiles(void* h) {
     return s ? (int64_t)s->acc.size() : -1;
 }
 
-// Every (kx, ky, count) of the accumulator, sorted by (kx, ky); call before
-// finish().  Arrays must hold oracle_num_tiles() entries.
-int oracle_tile_counts(void* h, int64_t* kx, int64_t* ky, uint64_t* count) {
+// Every (kx, ky[, kz], count) of the accumulator, sorted by tile; call before
+// finish().  Arrays must hold oracle_num_tiles() entries; kz may be NULL.
+int oracle_tile_counts(void* h, int64_t* kx, int64_t* ky, int64_t* kz, uint64_t* count) {
     OracleStream* s = (OracleStream*)h;
     if (!s) return kInval;
     if (s->finished) return kState;
@@ -188,6 +212,7 @@ int oracle_tile_counts(void* h, int64_t* kx, int64_t* ky, uint64_t* count) {
     for (size_t i = 0; i < all.size(); ++i) {
         kx[i] = all[i].first.x;
         ky[i] = all[i].first.y;
+        if (kz) kz[i] = all[i].first.z;
         count[i] = all[i].second;
     }
     return kOK;
@@ -253,15 +278,18 @@ int oracle_finish(void* h) {
             // ns = neighbours of u that are still in sigma; drop them from
             // sigma and queue them for the visit.
             const int64_t d = s->delta;
+            const int64_t dz_max = s->dims == 3 ? d : 0;
             for (int64_t dx = -d; dx <= d; ++dx) {
                 for (int64_t dy = -d; dy <= d; ++dy) {
-                    if (dx == 0 && dy == 0) continue;
-                    if (s->metric == 1 && std::llabs(dx) + std::llabs(dy) > d) continue;
-                    Tile v{u.x + dx, u.y + dy};
-                    auto it = sigma.find(v);
-                    if (it != sigma.end()) {
-                        sigma.erase(it);
-                        visit.push_back(v);
+                    for (int64_t dz = -dz_max; dz <= dz_max; ++dz) {
+                        if (dx == 0 && dy == 0 && dz == 0) continue;
+                        if (s->metric == 1 && std::llabs(dx) + std::llabs(dy) + std::llabs(dz) > d) continue;
+                        Tile v{u.x + dx, u.y + dy, u.z + dz};
+                        auto it = sigma.find(v);
+                        if (it != sigma.end()) {
+                            sigma.erase(it);
+                            visit.push_back(v);
+                        }
                     }
                 }
             }
@@ -308,9 +336,10 @@ int oracle_stats(void* h, int64_t* stats) {
     return kOK;
 }
 
-// Output rows after finish(): tile, count and label tile, sorted by tile.
-int oracle_result(void* h, int64_t* kx, int64_t* ky, uint64_t* count,
-                  int64_t* label_x, int64_t* label_y) {
+// Output rows after finish(): tile, count and label tile, sorted by tile;
+// kz and label_z (3-D) may be NULL.
+int oracle_result(void* h, int64_t* kx, int64_t* ky, int64_t* kz, uint64_t* count,
+                  int64_t* label_x, int64_t* label_y, int64_t* label_z) {
     OracleStream* s = (OracleStream*)h;
     if (!s) return kInval;
     if (!s->finished) return kState;
@@ -320,6 +349,8 @@ int oracle_result(void* h, int64_t* kx, int64_t* ky, uint64_t* count,
         count[i] = s->out_count[i];
         label_x[i] = s->out_label[i].x;
         label_y[i] = s->out_label[i].y;
+        if (kz) kz[i] = s->out_tile[i].z;
+        if (label_z) label_z[i] = s->out_label[i].z;
     }
     return kOK;
 }
@@ -336,8 +367,8 @@ int oracle_count_tiles(const void* pts, int64_t n, int32_t dtype, double scale, 
     for (int64_t q = 0; q < nq; ++q) where.emplace(Tile{qx[q], qy[q]}, q);
     for (int64_t i = 0; i < n; ++i) {
         Tile t;
-        if (project_coord(point_coord(pts, dtype, i, 0), scale, &t.x) != kOK ||
-            project_coord(point_coord(pts, dtype, i, 1), scale, &t.y) != kOK)
+        if (project_coord(point_coord(pts, dtype, 2, i, 0), scale, kBound2d, &t.x) != kOK ||
+            project_coord(point_coord(pts, dtype, 2, i, 1), scale, kBound2d, &t.y) != kOK)
             return kRange;
         auto it = where.find(t);
         if (it != where.end()) count[it->second] += 1;

@@ -17,16 +17,18 @@ import numpy as np
 
 
 def brute_tile_counts(points, scale: float):
-    """Sorted unique tiles and their counts via sort + run length."""
+    """Sorted unique tiles and their counts via sort + run length.  Points are
+    (n, 2), or (n, 3) in three dimensions (tiles then need |k| <= 2^20 - 2)."""
     a = np.asarray(points)
+    dims = 3 if a.ndim == 2 and a.shape[1] == 3 else 2
     a = a.astype(np.float64) if a.dtype == np.float32 else a.astype(np.float64, copy=False)
-    a = a.reshape(-1, 2)
+    a = a.reshape(-1, dims)
     prod = a * scale
-    if not np.all(np.abs(prod) < 2147483647.0):
+    if not np.all(np.abs(prod) < (2147483647.0 if dims == 2 else 1048575.0)):
         raise ValueError("coordinate out of range")
     k = np.trunc(prod).astype(np.int64)
     if k.shape[0] == 0:
-        return np.zeros((0, 2), np.int64), np.zeros(0, np.int64)
+        return np.zeros((0, dims), np.int64), np.zeros(0, np.int64)
     tiles, counts = np.unique(k, axis=0, return_counts=True)
     return tiles, counts
 
@@ -55,9 +57,8 @@ def brute_cluster(points, scale: float, tau: int, mu: int, metric: str = "chebys
     t = st.shape[0]
     if t == 0:
         return [], 0
-    ax = np.abs(st[:, None, 0] - st[None, :, 0])
-    ay = np.abs(st[:, None, 1] - st[None, :, 1])
-    d = np.maximum(ax, ay) if metric == "chebyshev" else ax + ay
+    diff = np.abs(st[:, None, :] - st[None, :, :])          # per coordinate
+    d = diff.max(axis=2) if metric == "chebyshev" else diff.sum(axis=2)
     adj = (d >= 1) & (d <= delta)
     comp = -np.ones(t, np.int64)
     ncomp = 0
@@ -79,8 +80,10 @@ def brute_cluster(points, scale: float, tau: int, mu: int, metric: str = "chebys
         if members.shape[0] < mu:
             continue
         kept += 1
-        lab = min((int(st[i, 0]), int(st[i, 1])) for i in members)
+        lab = min(tuple(int(v) for v in st[i]) for i in members)
         for i in members:
-            rows.append((int(st[i, 0]), int(st[i, 1]), int(sc[i]), lab[0], lab[1]))
+            tile = tuple(int(v) for v in st[i])
+            # 2-D rows: (kx, ky, count, lx, ly); 3-D rows: (kx, ky, kz, count, lx, ly, lz)
+            rows.append(tile + (int(sc[i]),) + lab)
     rows.sort()
     return rows, kept

@@ -82,3 +82,27 @@ def test_oracle_matches_brute_force_2x2_step(oracle_mod, metric, delta):
                zip(r.kx, r.ky, r.count, r.label_x, r.label_y)]
         assert got == rows, (seed, metric, delta)
         assert r.stats["clusters"] == kept, seed
+
+
+def _case3(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(0, 250))
+    centre = rng.uniform(-1.0, 1.0, size=3)
+    pts = centre + rng.normal(0.0, float(rng.choice([0.2, 0.4, 0.8])), size=(n, 3))
+    if rng.random() < 0.3:
+        pts = np.round(pts * 20) / 20
+    dtype = np.float32 if rng.random() < 0.25 else np.float64
+    return pts.astype(dtype), int(rng.integers(0, 2)), int(rng.integers(1, 4)), int(rng.integers(1, 5))
+
+
+@pytest.mark.parametrize("metric,delta", [("chebyshev", 1), ("manhattan", 1), ("chebyshev", 2), ("manhattan", 3)])
+def test_oracle_matches_brute_force_3d(oracle_mod, metric, delta):
+    for seed in range(6000, 6080):
+        pts, p, tau, mu = _case3(seed)
+        s = oracle_mod.scale_for_precision(p)
+        rows, kept = brute_cluster(pts, s, tau, mu, metric, delta)
+        r = oracle_mod.cluster(pts, tau=tau, mu=mu, scale=s, metric=metric, delta=delta, dims=3)
+        got = [tuple(int(v) for v in row) for row in
+               zip(r.kx, r.ky, r.kz, r.count, r.label_x, r.label_y, r.label_z)]
+        assert got == rows, (seed, metric, delta)
+        assert r.stats["clusters"] == kept, seed

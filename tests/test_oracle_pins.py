@@ -358,3 +358,58 @@ def test_2x2_step_only_adds(oracle_mod):
     sa = set(zip(a.kx.tolist(), a.ky.tolist()))
     sb = set(zip(b.kx.tolist(), b.ky.tolist()))
     assert sa < sb and b.stats["distinct"] == a.stats["distinct"]
+
+
+# ---- three dimensions (Section 3.6: RASTER in d dimensions) ----------------
+
+def _tiles3(tiles, per_tile=1, scale=10.0):
+    """per_tile points at the centre of each (x, y, z) tile (non-negative tiles)."""
+    return np.array([[(x + 0.5) / scale, (y + 0.5) / scale, (z + 0.5) / scale]
+                     for x, y, z in tiles for _ in range(per_tile)])
+
+
+def test_3d_neighbour_counts_match_section_3_6(oracle_mod):
+    # in d = 3 a tile has 3^d - 1 = 26 neighbours when all adjacent tiles
+    # count, and 2d = 6 at Manhattan distance 1
+    units = [(dx, dy, dz) for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1) if (dx, dy, dz) != (0, 0, 0)]
+    assert len(units) == 26
+    for metric, want in (("chebyshev", 26), ("manhattan", 6)):
+        joined = 0
+        for dx, dy, dz in units:
+            pts = _tiles3([(50, 50, 50), (50 + dx, 50 + dy, 50 + dz)])
+            joined += oracle_mod.cluster(pts, tau=1, mu=1, precision=1, metric=metric).stats["clusters"] == 1
+        assert joined == want, metric
+
+
+def test_3d_projection_and_range(oracle_mod):
+    # the same truncation per coordinate; |k| <= 2^20 - 2 in three dimensions
+    r = oracle_mod.cluster(np.array([[0.29, -0.57, 104857.4]]), tau=1, mu=1, precision=1)
+    assert (r.kx.tolist(), r.ky.tolist(), r.kz.tolist()) == ([2], [-5], [1048574])
+    r = oracle_mod.cluster(np.array([[0.29, 2.675, -0.001]]), tau=1, mu=1, precision=2)
+    assert (r.kx.tolist(), r.ky.tolist(), r.kz.tolist()) == ([28], [267], [0])
+    for bad in ([[0.5, 0.5, 104857.5]], [[-104857.5, 0.5, 0.5]], [[0.5, np.nan, 0.5]], [[2e5, 0.5, 0.5]]):
+        with pytest.raises(oracle_mod.OracleError) as e:
+            oracle_mod.cluster(np.array(bad), tau=1, mu=1, precision=1)
+        assert e.value.code == oracle_mod.E_RANGE
+    # the 2x2 post-step is two-dimensional
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.cluster(np.array([[0.5, 0.5, 0.5]]), tau=1, mu=1, precision=1, window=True)
+
+
+def test_3d_block_axes_and_z(oracle_mod):
+    block = [(x, y, z) for x in (3, 4) for y in (7, 8) for z in (1, 2)]
+    r = oracle_mod.cluster(_tiles3(block), tau=1, mu=8, precision=1)
+    assert r.stats["clusters"] == 1 and r.num_tiles == 8
+    assert set(zip(r.label_x.tolist(), r.label_y.tolist(), r.label_z.tolist())) == {(3, 7, 1)}
+    # an L in the x-z plane whose transposes are other tile sets
+    ell = [(3, 0, 7), (4, 0, 7), (5, 0, 7), (5, 0, 8)]
+    r = oracle_mod.cluster(_tiles3(ell), tau=1, mu=1, precision=1)
+    assert sorted(zip(r.kx.tolist(), r.ky.tolist(), r.kz.tolist())) == ell
+    # tiles apart only in z: two clusters at distance 1, one at 2
+    pair = [(9, 9, 0), (9, 9, 2)]
+    assert oracle_mod.cluster(_tiles3(pair), tau=1, mu=1, precision=1).stats["clusters"] == 2
+    assert oracle_mod.cluster(_tiles3(pair), tau=1, mu=1, precision=1, delta=2).stats["clusters"] == 1
+    # counts and tau in 3-D
+    r = oracle_mod.cluster(_tiles3([(1, 1, 1)], per_tile=4) , tau=4, mu=1, precision=1)
+    assert r.count.tolist() == [4]
+    assert oracle_mod.cluster(_tiles3([(1, 1, 1)], per_tile=3), tau=4, mu=1, precision=1).num_tiles == 0
