@@ -224,6 +224,47 @@ def bench_neighbourhoods(raster, torch, dev, precision: int, tau: int, mu: int, 
     return out
 
 
+def bench_3d(raster, torch, steps: int = 3, n_chunks: int = 10, chunk: int = 20_000_000):
+    """Section 3.6's generalisation to three dimensions: a stream of
+    n_chunks x chunk resident FP64 points; each chunk draws its own 100K
+    blobs (sigma 0.01, one tile) in [0, 1000]^3 with 2% noise, so the stream
+    holds 1M blobs of about 200 points; precision 2, tau 3, mu 4; ms per step
+    after one untimed step."""
+    import synth
+    with ThreadPoolExecutor(min(16, n_chunks)) as ex:
+        host = list(ex.map(lambda c: synth.blobs3d(9000 + c, n=chunk, n_centres=100_000, box=1000.0, sigma=0.01,
+                                                   noise_frac=0.02), range(n_chunks)))
+    dev = [torch.from_numpy(h).to("cuda") for h in host]
+    del host
+    torch.cuda.synchronize()
+
+    def step():
+        st = raster.Stream(tau=3, mu=4, precision=2, dims=3)
+        for d in dev:
+            st.feed(d)
+        r = st.finish()
+        st.close()
+        return r
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rs = [step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / steps
+    st = rs[-1].stats
+    n = n_chunks * chunk
+    out = {"workload": f"3-D stream: {n} FP64 points in {n_chunks} resident chunks, 100K blobs per chunk "
+                       "(1M in all, sigma 0.01) in [0,1000]^3, 2% noise, p=2, tau=3, mu=4",
+           "ms_per_step": ms, "points_per_s": n / (ms * 1e-3), "distinct_tiles": st["distinct_tiles"],
+           "significant_tiles": st["significant_tiles"], "clusters": st["clusters"],
+           "us_count_kernel_per_launch": st["us_count_kernel"] / max(1, st["count_launches"]),
+           "us_agglomerate": st["us_agglomerate"]}
+    del dev, rs
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_h2d_stream(raster, torch, host, precision: int, tau: int, mu: int, reps: int = 2):
     """Context only, never `value`: the same stream with the chunks in pinned
     host memory.  Each chunk is copied on a copy stream into one of two device
@@ -461,6 +502,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (256-job) comparison")
     ap.add_argument("--no-neighbourhoods", action="store_true",
                     help="skip the steps with Manhattan 1 and Chebyshev 2 and 3 neighbourhoods and the 2x2 step")
+    ap.add_argument("--no-3d", action="store_true", help="skip the three-dimensional stream")
     ap.add_argument("--no-h2d", action="store_true", help="skip the host-to-device streaming run")
     ap.add_argument("--no-point-labels", action="store_true",
                     help="skip the per-point label pass and the per-tile point lists")
@@ -592,6 +634,10 @@ def main():
                                           "tiles": st["tiles"]})
     del dev, results
     torch.cuda.empty_cache()
+    line["three_d"] = None
+    if not args.no_3d:
+        log("three-dimensional stream")
+        line["three_d"] = bench_3d(raster, torch)
     line["h2d_stream"] = None
     if not args.no_h2d:
         log("host-to-device stream (pinned chunks, two buffers)")

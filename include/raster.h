@@ -58,13 +58,14 @@ typedef enum raster_metric { RASTER_CHEBYSHEV = 0, RASTER_MANHATTAN = 1 } raster
 #define RASTER_MAX_DELTA 8
 
 /* Variants of the method, for raster_cluster_opts and raster_begin_opts.
- * NULL options mean {RASTER_CHEBYSHEV, 1, 0, 0}: Algorithm 1 as the paper's
+ * NULL options mean {RASTER_CHEBYSHEV, 1, 0, 2}: Algorithm 1 as the paper's
  * code runs it. */
 typedef struct raster_options {
     raster_metric metric;  /* neighbourhood metric (Section 3.2)                      */
     uint32_t delta;        /* neighbourhood distance, 1 .. RASTER_MAX_DELTA            */
     uint32_t square_step;  /* 1: the 2x2 post-step of Section 3.6 (below), else 0      */
-    uint32_t reserved;     /* must be 0                                                 */
+    uint32_t dims;         /* 2 (or 0): points (n, 2); 3: points (n, 3), Section 3.6's
+                              generalisation to three dimensions (below)              */
 } raster_options;
 
 typedef enum raster_status {
@@ -146,15 +147,23 @@ raster_status raster_cluster_delta(const void* d_points, int64_t n, raster_dtype
                                    uint32_t tau, uint32_t mu, raster_metric metric, uint32_t delta,
                                    hipStream_t stream, raster_result** out);
 
-/* Same with every variant in `opts` (NULL: the defaults).  square_step = 1
+/* Same with every variant in `opts` (NULL: the defaults).  dims = 3 takes
+ * three-dimensional points, row-major (n, 3) (8-byte aligned for FP64, 4 for
+ * FP32): each coordinate is projected as in two dimensions, tiles must satisfy
+ * |k| <= 2^20 - 2 (else E_RANGE), and the neighbourhood ranges over all three
+ * coordinates (Chebyshev 1: the 26 surrounding tiles; Manhattan 1: the 6 face
+ * neighbours).  The label is the biased key of the cluster's smallest tile in
+ * (x, y, z) order, ((kx + 2^20) << 42) | ((ky + 2^20) << 21) | (kz + 2^20);
+ * the third coordinate of each row comes from raster_result_kz.  Not with
+ * square_step, batches, per-point labels or per-tile point lists.  square_step = 1
  * adds the post-step that Section 3.6 proposes for points spread over the
  * tiles around a grid corner (Figure 4): a tile with fewer than tau points is
  * also significant when some 2x2 square of tiles containing it holds at least
  * tau points together (counted before any tile is dropped).  Only tiles with
  * points are retained.  It adds one pass over the table that probes the eight
  * surrounding tiles of every tile below tau.  E_INVAL for an unknown metric,
- * delta outside [1, RASTER_MAX_DELTA], square_step not 0 or 1, or reserved
- * not 0. */
+ * delta outside [1, RASTER_MAX_DELTA], square_step not 0 or 1, or dims not 0,
+ * 2 or 3. */
 raster_status raster_cluster_opts(const void* d_points, int64_t n, raster_dtype dt, double scale,
                                   uint32_t tau, uint32_t mu, const raster_options* opts, hipStream_t stream,
                                   raster_result** out);
@@ -174,6 +183,14 @@ raster_status raster_result_arrays(const raster_result* r, const int32_t** d_kx,
 raster_status raster_result_copy(const raster_result* r, int32_t* d_kx, int32_t* d_ky, uint32_t* d_count,
                                  uint64_t* d_label, hipStream_t stream);
 raster_status raster_result_stats(const raster_result* r, raster_stats* out);
+/* The third tile coordinate of every row of a three-dimensional result
+ * (borrowed device array of t int32, valid until raster_result_free); NULL for
+ * a two-dimensional result. */
+raster_status raster_result_kz(const raster_result* r, const int32_t** d_kz);
+/* Copy the t third coordinates of a three-dimensional result into a
+ * caller-owned device array of at least t int32, enqueued on `stream`; E_INVAL
+ * for a two-dimensional result. */
+raster_status raster_result_copy_kz(const raster_result* r, int32_t* d_kz, hipStream_t stream);
 void raster_result_free(raster_result* r);
 
 /* Per-point labels: the label of every input point, obtained as in the

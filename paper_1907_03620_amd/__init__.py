@@ -43,7 +43,7 @@ class RasterError(RuntimeError):
 
 class _Options(ctypes.Structure):
     _fields_ = [("metric", ctypes.c_int), ("delta", ctypes.c_uint32), ("square_step", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("dims", ctypes.c_uint32)]
 
 
 class _Stats(ctypes.Structure):
@@ -104,6 +104,8 @@ def load():
         "raster_begin_delta": (st, [dbl, u32, u32, ctypes.c_int, u32, i64, vp, pp]),
         "raster_cluster_delta": (st, [vp, i64, ctypes.c_int, dbl, u32, u32, ctypes.c_int, u32, vp, pp]),
         "raster_cluster_opts": (st, [vp, i64, ctypes.c_int, dbl, u32, u32, ctypes.POINTER(_Options), vp, pp]),
+        "raster_result_kz": (st, [vp, ctypes.POINTER(vp)]),
+        "raster_result_copy_kz": (st, [vp, vp, vp]),
         "raster_begin_opts": (st, [dbl, u32, u32, ctypes.POINTER(_Options), i64, vp, pp]),
         "raster_feed_chunk": (st, [vp, vp, i64, ctypes.c_int]),
         "raster_finish": (st, [vp, pp]),
@@ -146,17 +148,17 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def _points(points):
-    """(pointer, n, dtype) of a CUDA tensor of shape (n, 2)."""
+def _points(points, dims: int = 2):
+    """(pointer, n, dtype) of a CUDA tensor of shape (n, dims)."""
     torch = _torch()
     if not isinstance(points, torch.Tensor):
         raise TypeError("points must be a torch tensor on the GPU")
     if points.device.type != "cuda":
         raise ValueError("points must be on the GPU (device memory)")
-    if points.dim() != 2 or points.shape[1] != 2:
-        raise ValueError("points must have shape (n, 2)")
+    if points.dim() != 2 or points.shape[1] != dims:
+        raise ValueError(f"points must have shape (n, {dims})")
     if not points.is_contiguous():
-        raise ValueError("points must be contiguous (row-major (n, 2))")
+        raise ValueError(f"points must be contiguous (row-major (n, {dims}))")
     if points.dtype == torch.float64:
         dt = F64
     elif points.dtype == torch.float32:
@@ -209,13 +211,31 @@ class Result:
         return kx, ky, cnt, lab
 
     def numpy(self, sort: bool = True):
-        """Host copies (kx, ky, count, label) as numpy arrays, sorted by tile if ``sort``."""
+        """Host copies (kx, ky, count, label) as numpy arrays, sorted by tile if ``sort``
+        (three-dimensional results: (kx, ky, kz, count, label))."""
         import numpy as np
         kx, ky, cnt, lab = (a.cpu().numpy() for a in self.tensors())
+        kz = self.kz().cpu().numpy() if self.dims == 3 else None
         if sort and kx.shape[0]:
-            order = np.lexsort((ky, kx))
+            order = np.lexsort((ky, kx)) if kz is None else np.lexsort((kz, ky, kx))
             kx, ky, cnt, lab = kx[order], ky[order], cnt[order], lab[order]
-        return kx, ky, cnt, lab
+            kz = kz[order] if kz is not None else None
+        return (kx, ky, cnt, lab) if kz is None else (kx, ky, kz, cnt, lab)
+
+    @property
+    def dims(self) -> int:
+        p = ctypes.c_void_p()
+        _check(load().raster_result_kz(self._h, ctypes.byref(p)), "raster_result_kz")
+        return 3 if p.value else 2
+
+    def kz(self, device=None):
+        """The third tile coordinate of every row (three-dimensional results), int32."""
+        torch = _torch()
+        device = device or torch.device("cuda", torch.cuda.current_device())
+        kz = torch.empty(self.num_tiles, dtype=torch.int32, device=device)
+        _check(load().raster_result_copy_kz(self._h, ctypes.c_void_p(kz.data_ptr()), _stream_handle(self._stream)),
+               "raster_result_copy_kz")
+        return kz
 
     def point_labels(self, points, stream=None):
         """Label of every point (Section 4.1, RASTER-star): the cluster label of its tile as
@@ -268,13 +288,17 @@ def _scale_of(precision, scale) -> float:
     return float(10 ** int(precision))
 
 
-def _options(metric: str, delta: int, square: bool):
+def _options(metric: str, delta: int, square: bool, dims: int = 2):
     """The options struct, or None for the defaults."""
-    if metric == "chebyshev" and delta == 1 and not square:
+    if metric == "chebyshev" and delta == 1 and not square and dims == 2:
         return None
     if metric not in METRICS:
         raise RasterError(E_INVAL, "options", f"unknown metric {metric!r}")
-    return _Options(METRICS[metric], int(delta), int(bool(square)), 0)
+    return _Options(METRICS[metric], int(delta), int(bool(square)), int(dims))
+
+
+def _dims_of(points) -> int:
+    return 3 if points.dim() == 2 and points.shape[1] == 3 else 2
 
 
 def _variant_scale(precision, scale, what) -> float:
@@ -288,12 +312,14 @@ def cluster(points, tau: int, mu: int, precision: int | None = None, scale: floa
     """RASTER on one resident point tensor (Algorithm 1).  ``metric`` and
     ``delta`` choose the neighbourhood of the agglomeration (Section 3.2); the
     default is the eight adjacent tiles.  ``square`` adds the 2x2 post-step
-    of Section 3.6."""
+    of Section 3.6.  Points of shape (n, 3) are clustered in three dimensions
+    (Section 3.6's generalisation)."""
     lib = load()
-    p, n, dt = _points(points)
+    dims = _dims_of(points)
+    p, n, dt = _points(points, dims)
     out = ctypes.c_void_p()
     st = _stream_handle(stream)
-    opts = _options(metric, delta, square)
+    opts = _options(metric, delta, square, dims)
     if opts is not None:
         rc = lib.raster_cluster_opts(p, n, dt, _variant_scale(precision, scale, "raster_cluster_opts"), int(tau),
                                      int(mu), ctypes.byref(opts), st, ctypes.byref(out))
@@ -309,13 +335,15 @@ class Stream:
     """Chunked contraction with a device-resident table (Section 3.6)."""
 
     def __init__(self, tau: int, mu: int, precision: int | None = None, scale: float | None = None,
-                 tile_hint: int = 0, stream=None, metric: str = "chebyshev", delta: int = 1, square: bool = False):
+                 tile_hint: int = 0, stream=None, metric: str = "chebyshev", delta: int = 1, square: bool = False,
+                 dims: int = 2):
         self._lib = load()
         self._stream = stream
+        self._dims = int(dims)
         self._h = ctypes.c_void_p()
         self._keep = []  # chunks stay referenced until the stream has consumed them
         st = _stream_handle(stream)
-        opts = _options(metric, delta, square)
+        opts = _options(metric, delta, square, self._dims)
         if opts is not None:
             rc = self._lib.raster_begin_opts(_variant_scale(precision, scale, "raster_begin_opts"), int(tau), int(mu),
                                              ctypes.byref(opts), int(tile_hint), st, ctypes.byref(self._h))
@@ -327,7 +355,7 @@ class Stream:
         _check(rc, "raster_begin")
 
     def feed(self, points) -> None:
-        p, n, dt = _points(points)
+        p, n, dt = _points(points, self._dims)
         self._keep.append(points)
         _check(self._lib.raster_feed_chunk(self._h, p, n, dt), "raster_feed_chunk")
 

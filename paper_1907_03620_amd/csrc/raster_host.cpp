@@ -191,13 +191,14 @@ uint64_t next_pow2(uint64_t v) {
     return c;
 }
 
-raster_status check_points(const void* p, int64_t n, raster_dtype dt) {
+raster_status check_points(const void* p, int64_t n, raster_dtype dt, uint32_t dims) {
     if (dt != RASTER_F32 && dt != RASTER_F64) return fail(RASTER_E_INVAL, "unknown dtype %d", (int)dt);
     if (n < 0) return fail(RASTER_E_INVAL, "negative point count %lld", (long long)n);
     if (n > 0 && !p) return fail(RASTER_E_INVAL, "NULL points with n = %lld", (long long)n);
     const uintptr_t a = (uintptr_t)p;
-    if (n > 0 && (a % (dt == RASTER_F64 ? 16 : 8)) != 0)
-        return fail(RASTER_E_INVAL, "points must be %d-byte aligned", dt == RASTER_F64 ? 16 : 8);
+    // 2-D rows are read as one vector load, 3-D rows one coordinate at a time
+    const unsigned align = dims == 3 ? (dt == RASTER_F64 ? 8 : 4) : (dt == RASTER_F64 ? 16 : 8);
+    if (n > 0 && (a % align) != 0) return fail(RASTER_E_INVAL, "points must be %u-byte aligned", align);
     return RASTER_OK;
 }
 
@@ -220,28 +221,34 @@ raster_status check_options(const raster_options* o) {
     raster_status s = check_neighbourhood((int32_t)o->metric, o->delta);
     if (s != RASTER_OK) return s;
     if (o->square_step > 1) return fail(RASTER_E_INVAL, "square_step must be 0 or 1");
-    if (o->reserved != 0) return fail(RASTER_E_INVAL, "reserved must be 0");
+    if (o->dims != 0 && o->dims != 2 && o->dims != 3) return fail(RASTER_E_INVAL, "dims must be 0, 2 or 3");
+    if (o->dims == 3 && o->square_step) return fail(RASTER_E_INVAL, "the 2x2 post-step is two-dimensional");
     return RASTER_OK;
 }
 
-std::vector<NbrRound> neighbourhood_rounds(uint32_t metric, uint32_t delta) {
+uint32_t options_dims(const raster_options* o) { return o && o->dims == 3 ? 3u : 2u; }
+
+std::vector<NbrRound> neighbourhood_rounds(uint32_t metric, uint32_t delta, uint32_t dims) {
     std::vector<NbrRound> rounds;
-    if (metric == RASTER_CHEBYSHEV && delta == 1) return rounds;
-    // backward offsets: each edge is looked up from its larger-key end
+    if (metric == RASTER_CHEBYSHEV && delta == 1 && dims == 2) return rounds;
+    // backward offsets (smaller key): each edge is looked up from its
+    // larger-key end; keys order tiles lexicographically
     struct Off {
-        int32_t dx, dy;
+        int32_t dx, dy, dz;
     };
     std::vector<Off> offs;
     const int32_t d = (int32_t)delta;
+    const int32_t dzm = dims == 3 ? d : 0;
     for (int32_t dx = -d; dx <= 0; ++dx)
-        for (int32_t dy = -d; dy <= d; ++dy) {
-            if (dx == 0 && dy >= 0) continue;
-            if (metric == RASTER_MANHATTAN && std::abs(dx) + std::abs(dy) > d) continue;
-            offs.push_back({dx, dy});
-        }
+        for (int32_t dy = -d; dy <= d; ++dy)
+            for (int32_t dz = -dzm; dz <= dzm; ++dz) {
+                if (dx == 0 && (dy > 0 || (dy == 0 && dz >= 0))) continue;
+                if (metric == RASTER_MANHATTAN && std::abs(dx) + std::abs(dy) + std::abs(dz) > d) continue;
+                offs.push_back({dx, dy, dz});
+            }
     // nearest first, so that the first round's parent links cover most edges
     std::stable_sort(offs.begin(), offs.end(), [](const Off& a, const Off& b) {
-        return std::abs(a.dx) + std::abs(a.dy) < std::abs(b.dx) + std::abs(b.dy);
+        return std::abs(a.dx) + std::abs(a.dy) + std::abs(a.dz) < std::abs(b.dx) + std::abs(b.dy) + std::abs(b.dz);
     });
     for (size_t i = 0; i < offs.size(); i += 4) {
         NbrRound r{};
@@ -249,6 +256,7 @@ std::vector<NbrRound> neighbourhood_rounds(uint32_t metric, uint32_t delta) {
         for (uint32_t q = 0; q < r.count; ++q) {
             r.dx[q] = offs[i + q].dx;
             r.dy[q] = offs[i + q].dy;
+            r.dz[q] = offs[i + q].dz;
         }
         r.set_parent = rounds.empty() ? 1u : 0u;
         rounds.push_back(r);
@@ -659,7 +667,7 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
         HIP_TRY(hipEventRecord(ev[0], stream), "hipEventRecord");
         timing_started = true;
     }
-    const size_t point_bytes = dt == RASTER_F64 ? 16 : 8;
+    const size_t point_bytes = (dt == RASTER_F64 ? 8 : 4) * (size_t)dims;
     // Pieces of at most group_budget points, settled in between.  Spill
     // records between two settles come from one piece or one group, so the
     // buffer never needs more than what is binned plus this chunk.
@@ -691,7 +699,8 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
             }
             if ((st = span_begin(0, &a)) != RASTER_OK) return st;
             if (single_shot && (st = ensure_sketch()) != RASTER_OK) return st;
-            HIP_TRY(launch_bin_points(p, piece, (int)dt, scale, bin1, cap1, cursor1, tab, cap, sp, ctr, sketch, stream),
+            HIP_TRY(launch_bin_points(p, piece, (int)dt, scale, bin1, cap1, cursor1, tab, cap, sp, ctr, sketch, stream,
+                                      (int)dims),
                     "bin points");
             if ((st = span_end(0, a)) != RASTER_OK) return st;
             group_points += (uint64_t)piece;
@@ -700,12 +709,13 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
             if (single_shot && piece >= (int64_t)kSketchMinPoints && n_points == 0) {
                 // one read of the points sizes the table before any insert
                 if ((st = ensure_sketch()) != RASTER_OK) return st;
-                HIP_TRY(launch_points_hll(p, piece, (int)dt, scale, sketch, stream), "sketch");
+                HIP_TRY(launch_points_hll(p, piece, (int)dt, scale, sketch, stream, (int)dims), "sketch");
                 if ((st = size_from_sketch((uint64_t)piece)) != RASTER_OK) return st;
                 sp = SpillBuf{spill_keys[0], spill_counts[0], spill_cap[0]};
             }
             if ((st = span_begin(0, &a)) != RASTER_OK) return st;
-            HIP_TRY(launch_project_count(p, piece, (int)dt, scale, tab, cap, sp, ctr, kernel_tuning(tuning), stream),
+            HIP_TRY(launch_project_count(p, piece, (int)dt, scale, tab, cap, sp, ctr, kernel_tuning(tuning), stream,
+                                         (int)dims),
                     "project_count");
             if ((st = span_end(0, a)) != RASTER_OK) return st;
         }
@@ -745,7 +755,7 @@ raster_status TableRun::finish(raster_result** out) {
         raster_result_free(r);
         return s;
     };
-    const size_t row_bytes = 2 * sizeof(int32_t) + sizeof(uint32_t) + sizeof(uint64_t);
+    const size_t row_bytes = dims * sizeof(int32_t) + sizeof(uint32_t) + sizeof(uint64_t);
     hipError_t e = r->pool->alloc(&r->block, m * row_bytes + 256);
     if (e != hipSuccess) return drop(hip_fail(e, "result arrays"));
     char* b = (char*)r->block;
@@ -753,6 +763,8 @@ raster_status TableRun::finish(raster_result** out) {
     r->kx = (int32_t*)(b + m * sizeof(uint64_t));
     r->ky = r->kx + m;
     r->count = (uint32_t*)(r->ky + m);
+    r->dims = (int32_t)dims;
+    if (dims == 3) r->kz = (int32_t*)(r->count + m);
 
     // one job: the whole table
     single.job.pts = nullptr;
@@ -775,14 +787,14 @@ raster_status TableRun::finish(raster_result** out) {
     e = launch_zero_u64((uint64_t*)ctr + C_DISTINCT, C_COUNT_ - C_DISTINCT, stream);
     if (e == hipSuccess) e = launch_threshold(tab, jv, s_key, s_count, size, partials, ctr, stream, square ? cap : 0);
     if (e == hipSuccess) e = hipEventRecord(ev[2], stream);
-    const std::vector<NbrRound> rounds = neighbourhood_rounds(metric, delta);
+    const std::vector<NbrRound> rounds = neighbourhood_rounds(metric, delta, dims);
     if (e == hipSuccess)
         e = launch_agglomerate(tab, cap, jv, s_key, parent, nbr, size, m, ctr, stream, rounds.data(),
-                               (int)rounds.size());
+                               (int)rounds.size(), dims == 3);
     if (e == hipSuccess) e = hipEventRecord(ev[3], stream);
     if (e == hipSuccess)
         e = launch_filter(jv, s_key, s_count, nbr, size, r->kx, r->ky, r->count, r->label, nullptr, partials, ctr,
-                          stream);
+                          stream, r->kz);
     if (e == hipSuccess) e = hipEventRecord(ev[4], stream);
     if (e != hipSuccess) return drop(hip_fail(e, "agglomeration launch"));
     raster_status ps = pull_counters();
@@ -861,7 +873,7 @@ raster_status raster_cluster_opts(const void* d_points, int64_t n, raster_dtype 
     if (st != RASTER_OK) return st;
     st = check_options(opts);
     if (st != RASTER_OK) return st;
-    st = check_points(d_points, n, dt);
+    st = check_points(d_points, n, dt, options_dims(opts));
     if (st != RASTER_OK) return st;
     TableRun run;
     run.single_shot = true;
@@ -869,6 +881,7 @@ raster_status raster_cluster_opts(const void* d_points, int64_t n, raster_dtype 
         run.metric = (uint32_t)opts->metric;
         run.delta = opts->delta;
         run.square = opts->square_step == 1;
+        run.dims = options_dims(opts);
     }
     st = run.init(scale, tau, mu, std::max<int64_t>(n / 8, 1024), stream);
     if (st != RASTER_OK) return st;
@@ -899,6 +912,23 @@ raster_status raster_cluster(const void* d_points, int64_t n, raster_dtype dt, i
 
 int64_t raster_result_num_tiles(const raster_result* r) { return r ? r->tiles : -1; }
 int64_t raster_result_num_clusters(const raster_result* r) { return r ? r->clusters : -1; }
+
+raster_status raster_result_kz(const raster_result* r, const int32_t** d_kz) {
+    if (!r) return fail(RASTER_E_INVAL, "result is NULL");
+    if (!d_kz) return fail(RASTER_E_INVAL, "d_kz is NULL");
+    *d_kz = r->kz;
+    return RASTER_OK;
+}
+
+raster_status raster_result_copy_kz(const raster_result* r, int32_t* d_kz, hipStream_t stream) {
+    if (!r) return fail(RASTER_E_INVAL, "result is NULL");
+    if (!r->kz) return fail(RASTER_E_INVAL, "the result is two-dimensional");
+    if (r->tiles == 0) return RASTER_OK;
+    if (!d_kz) return fail(RASTER_E_INVAL, "d_kz is NULL");
+    HIP_TRY(hipMemcpyAsync(d_kz, r->kz, (size_t)r->tiles * sizeof(int32_t), hipMemcpyDeviceToDevice, stream),
+            "kz copy");
+    return RASTER_OK;
+}
 
 raster_status raster_result_arrays(const raster_result* r, const int32_t** d_kx, const int32_t** d_ky,
                                    const uint32_t** d_count, const uint64_t** d_label) {
@@ -971,6 +1001,7 @@ static raster_status ensure_lookup(raster_result* r, bool rows, DevicePool& pool
 raster_status raster_result_point_labels(raster_result* r, const void* d_points, int64_t n, raster_dtype dt,
                                          uint64_t* d_labels, hipStream_t stream) {
     if (!r) return fail(RASTER_E_INVAL, "result is NULL");
+    if (r->dims != 2) return fail(RASTER_E_INVAL, "per-point labels of a three-dimensional result");
     raster_status st = check_points(d_points, n, dt);
     if (st != RASTER_OK) return st;
     if (n > 0 && !d_labels) return fail(RASTER_E_INVAL, "labels is NULL with n = %lld", (long long)n);
@@ -999,6 +1030,7 @@ raster_status raster_result_tile_points(raster_result* r, const void* d_points, 
                                         hipStream_t stream) {
     if (n_kept) *n_kept = 0;
     if (!r) return fail(RASTER_E_INVAL, "result is NULL");
+    if (r->dims != 2) return fail(RASTER_E_INVAL, "per-tile point lists of a three-dimensional result");
     if (!n_kept) return fail(RASTER_E_INVAL, "n_kept is NULL");
     raster_status st = check_points(d_points, n, dt);
     if (st != RASTER_OK) return st;
@@ -1065,6 +1097,7 @@ raster_status raster_begin_opts(double scale, uint32_t tau, uint32_t mu, const r
         h->run.metric = (uint32_t)opts->metric;
         h->run.delta = opts->delta;
         h->run.square = opts->square_step == 1;
+        h->run.dims = options_dims(opts);
     }
     s = h->run.init(scale, tau, mu, tile_hint, stream);
     if (s != RASTER_OK) {
@@ -1101,7 +1134,7 @@ raster_status raster_feed_chunk(raster_stream* st, const void* d_points, int64_t
             return fail(st->run.failed, "stream failed earlier: %s", raster_status_string(st->run.failed));
         return fail(RASTER_E_STATE, "stream is not open");
     }
-    raster_status s = check_points(d_points, n, dt);
+    raster_status s = check_points(d_points, n, dt, st->run.dims);
     if (s != RASTER_OK) return s;
     s = st->run.feed(d_points, n, dt);
     if (s != RASTER_OK && st->run.failed != RASTER_OK) st->state = raster_stream::FAILED;

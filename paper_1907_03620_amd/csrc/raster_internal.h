@@ -125,7 +125,7 @@ struct JobInfo {
 // sets every tile's parent to its smallest-key neighbour among its offsets;
 // later rounds only record edges for the merge pass.
 struct NbrRound {
-    int32_t dx[4], dy[4];
+    int32_t dx[4], dy[4], dz[4];  // dz: 3-D keys only
     uint32_t count;       // offsets in use, 1..4
     uint32_t set_parent;  // 1 in the first round
 };
@@ -184,7 +184,7 @@ hipError_t launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t stream);
 // Projection + counting of n points into the table (dtype 1 = f32, 2 = f64).
 hipError_t launch_project_count(const void* pts, int64_t n, int dtype, double scale, Slot* tab,
                                  uint64_t cap, SpillBuf spill, unsigned long long* ctr,
-                                 const KernelTuning& tu, hipStream_t stream);
+                                 const KernelTuning& tu, hipStream_t stream, int dims = 2);
 
 // Binned contraction, level 1: project n points and append each key to its
 // coarse bucket: bucket b holds keys at bin1[b * cap1 + i], i < cursor1[b].
@@ -193,7 +193,7 @@ hipError_t launch_project_count(const void* pts, int64_t n, int dtype, double sc
 // replicas of 2^kHllLog2 registers; merge them by maximum).
 hipError_t launch_bin_points(const void* pts, int64_t n, int dtype, double scale, uint64_t* bin1, uint64_t cap1,
                              uint32_t* cursor1, Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr,
-                             uint32_t* hll, hipStream_t stream);
+                             uint32_t* hll, hipStream_t stream, int dims = 2);
 // Binned contraction, level 2: split every coarse bucket into its partitions
 // (bin2, cap2 keys per partition, counts in cursor2, which this clears first).
 hipError_t launch_bin_keys(const uint64_t* bin1, uint64_t cap1, const uint32_t* cursor1, uint64_t* bin2,
@@ -239,14 +239,15 @@ hipError_t launch_threshold(Slot* tab, const JobView& jv, uint64_t* s_key, uint3
 hipError_t launch_agglomerate(const Slot* tab, uint64_t slots_max, const JobView& jv, const uint64_t* s_key,
                               uint32_t* parent, uint32_t* nbr, uint32_t* size, uint64_t s_max,
                               unsigned long long* ctr, hipStream_t stream,
-                              const NbrRound* rounds = nullptr, int nrounds = 0);
+                              const NbrRound* rounds = nullptr, int nrounds = 0,
+                              bool d3 = false);
 
 // mu filter and output compaction: rows of kept components in compact order
 // (out_job gets each row's job for several jobs).
 hipError_t launch_filter(const JobView& jv, const uint64_t* s_key, const uint32_t* s_count, const uint32_t* root,
                          const uint32_t* size, int32_t* out_kx, int32_t* out_ky, uint32_t* out_count,
                          uint64_t* out_label, uint32_t* out_job, uint32_t* partials, unsigned long long* ctr,
-                         hipStream_t stream);
+                         hipStream_t stream, int32_t* out_kz = nullptr);
 
 // Batched counting: one launch over the point tiles of every job, each point
 // added to its job's table with device atomics (LDS pre-aggregation per tile
@@ -281,7 +282,7 @@ hipError_t launch_point_labels(const void* pts, int64_t n, int dtype, double sca
 // Distinct-tile sketch of one point set into hll (kHllReps replicas, not
 // zeroed here).
 hipError_t launch_points_hll(const void* pts, int64_t n, int dtype, double scale, uint32_t* hll,
-                             hipStream_t stream);
+                             hipStream_t stream, int dims = 2);
 hipError_t launch_batch_hll(const JobView& jv, const uint32_t* tile_prefix, uint32_t tile, uint32_t* hll,
                             uint32_t njobs, uint32_t tiles, hipStream_t stream);
 

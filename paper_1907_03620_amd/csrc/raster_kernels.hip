@@ -169,6 +169,58 @@ __device__ __forceinline__ void load_point(const T* pts, int64_t i, double& x, d
     y = (double)v.y;
 }
 
+// Three-dimensional rows (Section 3.6 generalises the method to d
+// dimensions) are a point type of their own, so that the counting kernels,
+// templated on the point type, take them as they are.  A 3-D key packs the
+// three biased coordinates k + 2^20 (21 bits each, |k| <= 2^20 - 2) as x:y:z
+// from the high bits: unsigned key order is the lexicographic tile order, and
+// no valid key reaches kEmptyKey.  The table, binning, scan and union-find
+// code treat keys as opaque, so they serve both.
+template <typename E> struct Pt3 {
+    E c[3];
+};
+template <typename P> struct PtDims {
+    static constexpr int value = 2;
+};
+template <typename E> struct PtDims<Pt3<E>> {
+    static constexpr int value = 3;
+};
+
+constexpr uint32_t kBias3 = 1u << 20;
+constexpr uint64_t kField3 = (1ull << 21) - 1;
+
+__device__ __forceinline__ bool tile_key3(double x, double y, double z, double s, uint64_t& key) {
+    const double px = x * s;
+    const double py = y * s;
+    const double pz = z * s;
+    if (!(fabs(px) < 1048575.0) || !(fabs(py) < 1048575.0) || !(fabs(pz) < 1048575.0)) return false;
+    const uint64_t bx = (uint32_t)((int32_t)px + (int32_t)kBias3);
+    const uint64_t by = (uint32_t)((int32_t)py + (int32_t)kBias3);
+    const uint64_t bz = (uint32_t)((int32_t)pz + (int32_t)kBias3);
+    key = (bx << 42) | (by << 21) | bz;
+    return true;
+}
+
+template <typename P>
+__device__ __forceinline__ void load_xyz(const P* pts, int64_t i, double& x, double& y, double& z) {
+    load_point(pts, i, x, y);
+    z = 0.0;
+}
+
+template <typename E>
+__device__ __forceinline__ void load_xyz(const Pt3<E>* pts, int64_t i, double& x, double& y, double& z) {
+    const __attribute__((address_space(1))) E* g = (const __attribute__((address_space(1))) E*)(pts);
+    x = (double)__builtin_nontemporal_load(g + 3 * i);
+    y = (double)__builtin_nontemporal_load(g + 3 * i + 1);
+    z = (double)__builtin_nontemporal_load(g + 3 * i + 2);
+}
+
+template <typename P>
+__device__ __forceinline__ bool point_key(double x, double y, double z, double s, uint64_t& key) {
+    if constexpr (PtDims<P>::value == 3) return tile_key3(x, y, z, s, key);
+    else return tile_key(x, y, s, key);
+}
+
 __device__ __forceinline__ uint32_t job_of_tile(const uint32_t* tile_prefix, uint32_t njobs, uint32_t t) {
     uint32_t lo = 0, hi = njobs;  // find the last j with tile_prefix[j] <= t
     while (hi - lo > 1) {
@@ -315,9 +367,9 @@ __global__ void k_count_direct(const T* __restrict__ pts, int64_t n, double scal
         const int64_t i = base + (int64_t)j * blockDim.x;
         key[j] = 0;
         if (i < n) {
-            double x, y;
-            load_point(pts, i, x, y);
-            if (tile_key(x, y, scale, key[j])) valid |= 1u << j;
+            double x, y, z;
+            load_xyz(pts, i, x, y, z);
+            if (point_key<T>(x, y, z, scale, key[j])) valid |= 1u << j;
             else bad = true;
         }
     }
@@ -366,9 +418,9 @@ __global__ void k_count_preagg(const T* __restrict__ pts, int64_t n, double scal
             const int64_t i = base + (int64_t)j * blockDim.x;
             key[j] = 0;
             if (i < n) {
-                double x, y;
-                load_point(pts, i, x, y);
-                if (tile_key(x, y, scale, key[j])) valid |= 1u << j;
+                double x, y, z;
+                load_xyz(pts, i, x, y, z);
+                if (point_key<T>(x, y, z, scale, key[j])) valid |= 1u << j;
                 else bad = true;
             }
         }
@@ -581,13 +633,14 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_points(const T* __restrict_
     uint32_t valid = 0;
     bool bad = false;
     // all loads first, so that they are in flight together
-    double x[BIN_ITEMS], y[BIN_ITEMS];
+    double x[BIN_ITEMS], y[BIN_ITEMS], z[BIN_ITEMS];
 #pragma unroll
     for (int j = 0; j < BIN_ITEMS; ++j) {
         const int64_t i = base + (int64_t)j * BIN_THREADS;
         x[j] = 0.0;
         y[j] = 0.0;
-        if (i < n) load_point(pts, i, x[j], y[j]);
+        z[j] = 0.0;
+        if (i < n) load_xyz(pts, i, x[j], y[j], z[j]);
     }
 #pragma unroll
     for (int j = 0; j < BIN_ITEMS; ++j) {
@@ -595,7 +648,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_points(const T* __restrict_
         key[j] = 0;
         bucket[j] = 0;
         if (i < n) {
-            if (tile_key(x[j], y[j], scale, key[j])) {
+            if (point_key<T>(x[j], y[j], z[j], scale, key[j])) {
                 valid |= 1u << j;
                 bucket[j] = (uint16_t)bucket_of(key[j], kCoarseLog2, kCoarse);
                 uint32_t reg, rank;
@@ -1475,11 +1528,11 @@ __global__ __launch_bounds__(SQUARE_THREADS) void k_square_part(Slot* tab, JobVi
 // probed there; only the others are probed in the device table.
 //
 // GENERAL: the offsets come from `nr` (one round of a larger or Manhattan
-// neighbourhood) instead of the four fixed ones, and the parent is written in
-// the first round only.
+// neighbourhood, or of the 3-D one with D3) instead of the four fixed ones,
+// and the parent is written in the first round only.
 constexpr int LINK_THREADS = 512;
 
-template <bool GENERAL>
+template <bool GENERAL, bool D3 = false>
 __global__ __launch_bounds__(LINK_THREADS) void k_link_part(const Slot* tab, JobView jv, uint32_t* parent,
                                                             uint32_t* nbr, unsigned long long* ctr, NbrRound nr) {
     __shared__ uint64_t lkey[kPartSlots];
@@ -1553,13 +1606,24 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_part(const Slot* tab, Job
                 want[2] = left && up;
                 nk[3] = ((uint64_t)bx << 32) | (uint32_t)(by - 1);
                 want[3] = down;
-            } else {
+            } else if (!D3) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int64_t x = (int64_t)bx + nr.dx[q];
                     const int64_t y = (int64_t)by + nr.dy[q];
                     want[q] = q < (int)nr.count && x >= 2 && x <= 0xFFFFFFFEll && y >= 2 && y <= 0xFFFFFFFEll;
                     nk[q] = want[q] ? (((uint64_t)(uint32_t)x << 32) | (uint32_t)y) : key;
+                }
+            } else {
+                // 3-D keys: biased fields of 21 bits, valid in [2, 2^21 - 2]
+                const int64_t x0 = (int64_t)(key >> 42), y0 = (int64_t)((key >> 21) & kField3);
+                const int64_t z0 = (int64_t)(key & kField3);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t x = x0 + nr.dx[q], y = y0 + nr.dy[q], z = z0 + nr.dz[q];
+                    const int64_t hi = (int64_t)kField3 - 1;
+                    want[q] = q < (int)nr.count && x >= 2 && x <= hi && y >= 2 && y <= hi && z >= 2 && z <= hi;
+                    nk[q] = want[q] ? (((uint64_t)x << 42) | ((uint64_t)y << 21) | (uint64_t)z) : key;
                 }
             }
             // first probes: device-table loads for the other partitions are
@@ -1751,8 +1815,9 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_filter_scatter(JobView jv, con
                                                                  const uint32_t* s_count, const uint32_t* root,
                                                                  const uint32_t* size, const uint32_t* offsets,
                                                                  const unsigned long long* ctr, int32_t* out_kx,
-                                                                 int32_t* out_ky, uint32_t* out_count,
-                                                                 uint64_t* out_label, uint32_t* out_job) {
+                                                                 int32_t* out_ky, int32_t* out_kz,
+                                                                 uint32_t* out_count, uint64_t* out_label,
+                                                                 uint32_t* out_job) {
     __shared__ TileScratch ts;
     const uint64_t s = ctr[C_SIGNIFICANT];
     const bool multi = jv.part_job != nullptr;
@@ -1787,8 +1852,14 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_filter_scatter(JobView jv, con
             if (!(bits & (1u << j))) continue;
             const uint64_t i = t0 + (uint64_t)j * SCAN_THREADS + threadIdx.x;
             const uint64_t p = run + pos[j];
-            out_kx[p] = (int32_t)((uint32_t)(key[j] >> 32) - 0x80000000u);
-            out_ky[p] = (int32_t)((uint32_t)key[j] - 0x80000000u);
+            if (out_kz) {  // 3-D keys (uniform across the grid)
+                out_kx[p] = (int32_t)(key[j] >> 42) - (int32_t)kBias3;
+                out_ky[p] = (int32_t)((key[j] >> 21) & kField3) - (int32_t)kBias3;
+                out_kz[p] = (int32_t)(key[j] & kField3) - (int32_t)kBias3;
+            } else {
+                out_kx[p] = (int32_t)((uint32_t)(key[j] >> 32) - 0x80000000u);
+                out_ky[p] = (int32_t)((uint32_t)key[j] - 0x80000000u);
+            }
             out_count[p] = cnt[j];
             out_label[p] = label[j];
             if (multi) out_job[p] = jv.s_job[i];
@@ -1809,14 +1880,15 @@ __global__ __launch_bounds__(256) void k_points_hll(const T* __restrict__ pts, i
     uint32_t* rep = hll + ((uint64_t)(blockIdx.x % kHllReps) << kHllLog2);
     for (int64_t i0 = (int64_t)blockIdx.x * U * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * U * blockDim.x) {
         // loads of all items first (indices clamped, results masked)
-        double x[U], y[U];
+        double x[U], y[U], z[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) load_point(pts, min(i0 + (int64_t)u * blockDim.x + threadIdx.x, n - 1), x[u], y[u]);
+        for (int u = 0; u < U; ++u)
+            load_xyz(pts, min(i0 + (int64_t)u * blockDim.x + threadIdx.x, n - 1), x[u], y[u], z[u]);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             uint64_t key;
             uint32_t r, rank;
-            if (i0 + (int64_t)u * blockDim.x + threadIdx.x < n && tile_key(x[u], y[u], scale, key) &&
+            if (i0 + (int64_t)u * blockDim.x + threadIdx.x < n && point_key<T>(x[u], y[u], z[u], scale, key) &&
                 hll_sample(key, r, rank))
                 atomicMax(rep + r, rank);
         }
@@ -2264,9 +2336,14 @@ hipError_t launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t stream) {
 
 hipError_t launch_project_count(const void* pts, int64_t n, int dtype, double scale, Slot* tab, uint64_t cap,
                                  SpillBuf spill, unsigned long long* ctr, const KernelTuning& tu,
-                                 hipStream_t stream) {
+                                 hipStream_t stream, int dims) {
     if (n <= 0) return hipSuccess;
     const Geo g = make_geo(cap);
+    if (dims == 3) {
+        if (dtype == 1)
+            return launch_count_items(static_cast<const Pt3<float>*>(pts), n, scale, tab, g, spill, ctr, tu, stream);
+        return launch_count_items(static_cast<const Pt3<double>*>(pts), n, scale, tab, g, spill, ctr, tu, stream);
+    }
     if (dtype == 1)
         return launch_count_items(static_cast<const float*>(pts), n, scale, tab, g, spill, ctr, tu, stream);
     return launch_count_items(static_cast<const double*>(pts), n, scale, tab, g, spill, ctr, tu, stream);
@@ -2274,7 +2351,7 @@ hipError_t launch_project_count(const void* pts, int64_t n, int dtype, double sc
 
 hipError_t launch_bin_points(const void* pts, int64_t n, int dtype, double scale, uint64_t* bin1, uint64_t cap1,
                              uint32_t* cursor1, Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr,
-                             uint32_t* hll, hipStream_t stream) {
+                             uint32_t* hll, hipStream_t stream, int dims) {
     if (n <= 0) return hipSuccess;
     const Geo g = make_geo(cap);
     const unsigned grid = (unsigned)((n + kBinTile - 1) / kBinTile);
@@ -2282,6 +2359,18 @@ hipError_t launch_bin_points(const void* pts, int64_t n, int dtype, double scale
         hipLaunchKernelGGL(kernel, dim3(grid), dim3(BIN_THREADS), 0, stream, p, n, scale, bin1, cap1, cursor1, tab, g,
                            spill, ctr, hll);
     };
+    if (dims == 3) {
+        const Pt3<float>* pf = static_cast<const Pt3<float>*>(pts);
+        const Pt3<double>* pd = static_cast<const Pt3<double>*>(pts);
+        if (dtype == 1) {
+            if (hll) go(k_bin_points<Pt3<float>, true>, pf);
+            else go(k_bin_points<Pt3<float>, false>, pf);
+        } else {
+            if (hll) go(k_bin_points<Pt3<double>, true>, pd);
+            else go(k_bin_points<Pt3<double>, false>, pd);
+        }
+        return hipGetLastError();
+    }
     const float* pf = static_cast<const float*>(pts);
     const double* pd = static_cast<const double*>(pts);
     if (dtype == 1) {
@@ -2373,20 +2462,25 @@ hipError_t launch_threshold(Slot* tab, const JobView& jv, uint64_t* s_key, uint3
 
 hipError_t launch_agglomerate(const Slot* tab, uint64_t slots_max, const JobView& jv, const uint64_t* s_key,
                               uint32_t* parent, uint32_t* nbr, uint32_t* size, uint64_t s_max,
-                              unsigned long long* ctr, hipStream_t stream, const NbrRound* rounds, int nrounds) {
+                              unsigned long long* ctr, hipStream_t stream, const NbrRound* rounds, int nrounds,
+                              bool d3) {
     const int grid = (grid_for(s_max, 256, kPersistBlocks) + kXcds - 1) / kXcds * kXcds;
     const int link_grid = grid_for((slots_max + kPartSlots - 1) >> kPartLog2, 1, 8192);
     if (nrounds <= 0) {
-        hipLaunchKernelGGL(k_link_part<false>, dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, jv, parent, nbr,
-                           ctr, NbrRound{});
+        hipLaunchKernelGGL((k_link_part<false, false>), dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, jv,
+                           parent, nbr, ctr, NbrRound{});
         hipLaunchKernelGGL(k_jump, dim3(grid), dim3(256), 0, stream, parent, ctr);
         hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, stream, nbr, s_key, parent, ctr);
     } else {
         // round 0 builds the forest from its offsets; each later round records
         // the edges of four more offsets and unites along them
         for (int r = 0; r < nrounds; ++r) {
-            hipLaunchKernelGGL(k_link_part<true>, dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, jv, parent,
-                               nbr, ctr, rounds[r]);
+            if (d3)
+                hipLaunchKernelGGL((k_link_part<true, true>), dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, jv,
+                                   parent, nbr, ctr, rounds[r]);
+            else
+                hipLaunchKernelGGL((k_link_part<true, false>), dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, jv,
+                                   parent, nbr, ctr, rounds[r]);
             if (r == 0) hipLaunchKernelGGL(k_jump, dim3(grid), dim3(256), 0, stream, parent, ctr);
             hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, stream, nbr, s_key, parent, ctr);
         }
@@ -2400,12 +2494,12 @@ hipError_t launch_agglomerate(const Slot* tab, uint64_t slots_max, const JobView
 hipError_t launch_filter(const JobView& jv, const uint64_t* s_key, const uint32_t* s_count, const uint32_t* root,
                          const uint32_t* size, int32_t* out_kx, int32_t* out_ky, uint32_t* out_count,
                          uint64_t* out_label, uint32_t* out_job, uint32_t* partials, unsigned long long* ctr,
-                         hipStream_t stream) {
+                         hipStream_t stream, int32_t* out_kz) {
     hipLaunchKernelGGL(k_filter_count, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, jv, root, size, partials,
                        ctr);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, stream, partials, ctr + C_TILES);
     hipLaunchKernelGGL(k_filter_scatter, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, jv, s_key, s_count, root,
-                       size, partials, ctr, out_kx, out_ky, out_count, out_label, out_job);
+                       size, partials, ctr, out_kx, out_ky, out_kz, out_count, out_label, out_job);
     return hipGetLastError();
 }
 
@@ -2493,15 +2587,23 @@ hipError_t launch_tile_points_scatter(const uint32_t* row_of, const uint32_t* ra
 }
 
 hipError_t launch_points_hll(const void* pts, int64_t n, int dtype, double scale, uint32_t* hll,
-                             hipStream_t stream) {
+                             hipStream_t stream, int dims) {
     if (n <= 0) return hipSuccess;
     const unsigned grid = (unsigned)grid_for((uint64_t)n, 256 * 16, 4096);
-    if (dtype == 1)
+    if (dims == 3) {
+        if (dtype == 1)
+            hipLaunchKernelGGL(k_points_hll<Pt3<float>>, dim3(grid), dim3(256), 0, stream,
+                               static_cast<const Pt3<float>*>(pts), n, scale, hll);
+        else
+            hipLaunchKernelGGL(k_points_hll<Pt3<double>>, dim3(grid), dim3(256), 0, stream,
+                               static_cast<const Pt3<double>*>(pts), n, scale, hll);
+    } else if (dtype == 1) {
         hipLaunchKernelGGL(k_points_hll<float>, dim3(grid), dim3(256), 0, stream, static_cast<const float*>(pts), n,
                            scale, hll);
-    else
+    } else {
         hipLaunchKernelGGL(k_points_hll<double>, dim3(grid), dim3(256), 0, stream, static_cast<const double*>(pts), n,
                            scale, hll);
+    }
     return hipGetLastError();
 }
 

@@ -27,6 +27,8 @@ struct raster_result {
     uint64_t* label = nullptr;
     int32_t* kx = nullptr;
     int32_t* ky = nullptr;
+    int32_t* kz = nullptr;  // three-dimensional results only
+    int32_t dims = 2;
     uint32_t* count = nullptr;
     int64_t tiles = 0;
     int64_t clusters = 0;
@@ -52,13 +54,14 @@ raster_tuning current_tuning();
 KernelTuning kernel_tuning(const raster_tuning& t);
 bool scale_for_precision(int32_t p, double* s);
 uint64_t next_pow2(uint64_t v);
-raster_status check_points(const void* p, int64_t n, raster_dtype dt);
+raster_status check_points(const void* p, int64_t n, raster_dtype dt, uint32_t dims = 2);
 raster_status check_params(double scale, uint32_t tau, uint32_t mu);
 raster_status check_neighbourhood(int32_t metric, uint32_t delta);
 raster_status check_options(const raster_options* o);
+uint32_t options_dims(const raster_options* o);  // 3 for three-dimensional points, else 2
 // Link rounds of the neighbourhood; empty for Chebyshev 1, which has its own
 // fixed-offset pass.
-std::vector<NbrRound> neighbourhood_rounds(uint32_t metric, uint32_t delta);
+std::vector<NbrRound> neighbourhood_rounds(uint32_t metric, uint32_t delta, uint32_t dims = 2);
 
 class DevicePool {
   public:
@@ -100,6 +103,7 @@ struct TableRun {
     uint32_t tau = 1, mu = 1;
     uint32_t metric = RASTER_CHEBYSHEV, delta = 1;  // neighbourhood of the agglomeration
     bool square = false;                            // the 2x2 post-step before the threshold
+    uint32_t dims = 2;                              // coordinates per point: 2 or 3
     raster_tuning tuning{};
     Buffers bufs;
     Slot* tab = nullptr;

@@ -22,7 +22,7 @@ from dataclasses import dataclass
 import numpy as np
 
 __all__ = [
-    "rng_for", "blobs", "plain_small", "zipf_hot", "paper_scale_chunk",
+    "rng_for", "blobs", "blobs3d", "plain_small", "zipf_hot", "paper_scale_chunk",
     "paper_scale_centres", "batch_jobs", "served_trace", "JobSpec",
     "PLAIN_SMALL", "ZIPF_HOT", "PAPER_SCALE",
 ]
@@ -53,6 +53,25 @@ def blobs(rng: np.random.Generator, n: int, n_centres: int, box: float,
     idx = rng.integers(0, n_centres, size=n - n_noise)
     out[~is_noise] = centres[idx] + rng.normal(0.0, sigma, size=(n - n_noise, 2))
     out[is_noise] = rng.uniform(0.0, box, size=(n_noise, 2))
+    return np.ascontiguousarray(out.astype(dtype, copy=False))
+
+
+def blobs3d(seed: int, n: int, n_centres: int, box: float, sigma: float, noise_frac: float,
+            dtype=np.float64) -> np.ndarray:
+    """Three-dimensional version of ``blobs`` for Section 3.6's
+    generalisation: n points of shape (n, 3) over [0, box]^3, a share
+    ``noise_frac`` uniform, the rest Gaussian (``sigma``) around centres drawn
+    uniformly.  There is no 3-D workload in the paper; this one keeps the 2-D
+    workloads' structure (dense blobs in sparse noise)."""
+    rng = rng_for(seed)
+    n = int(n)
+    centres = rng.uniform(0.0, box, size=(n_centres, 3))
+    is_noise = rng.random(n) < noise_frac
+    n_noise = int(is_noise.sum())
+    out = np.empty((n, 3), dtype=np.float64)
+    idx = rng.integers(0, n_centres, size=n - n_noise)
+    out[~is_noise] = centres[idx] + rng.normal(0.0, sigma, size=(n - n_noise, 3))
+    out[is_noise] = rng.uniform(0.0, box, size=(n_noise, 3))
     return np.ascontiguousarray(out.astype(dtype, copy=False))
 
 
