@@ -284,6 +284,7 @@ namespace {
 struct HostCache {
     std::mutex mu;
     std::vector<unsigned long long*> pinned;
+    std::vector<uint32_t*> pinned_sketch;  // kHllReps << kHllLog2 registers each
     std::map<std::pair<int, bool>, std::vector<hipEvent_t>> events;  // (device, timing) -> free events
 
     static HostCache& get() {
@@ -304,6 +305,21 @@ struct HostCache {
     void give_pinned(unsigned long long* p) {
         std::lock_guard<std::mutex> g(mu);
         pinned.push_back(p);
+    }
+    hipError_t take_pinned_sketch(uint32_t** p) {
+        {
+            std::lock_guard<std::mutex> g(mu);
+            if (!pinned_sketch.empty()) {
+                *p = pinned_sketch.back();
+                pinned_sketch.pop_back();
+                return hipSuccess;
+            }
+        }
+        return hipHostMalloc((void**)p, ((size_t)kHllReps << kHllLog2) * sizeof(uint32_t), hipHostMallocDefault);
+    }
+    void give_pinned_sketch(uint32_t* p) {
+        std::lock_guard<std::mutex> g(mu);
+        pinned_sketch.push_back(p);
     }
     hipError_t take_event(int dev, bool timing, hipEvent_t* e) {
         {
@@ -338,6 +354,7 @@ TableRun::~TableRun() {
     }
     for (hipEvent_t e : ev_free) hc.give_event(device, true, e);
     if (h_ctr) hc.give_pinned(h_ctr);
+    if (h_sketch) hc.give_pinned_sketch(h_sketch);
 }
 
 double hll_estimate(const uint32_t* M) {
@@ -365,21 +382,37 @@ static constexpr uint64_t kSketchMinPoints = 1u << 16;
 raster_status TableRun::ensure_sketch() {
     if (sketch) return RASTER_OK;
     const size_t regs = (size_t)kHllReps << kHllLog2;
+    HIP_TRY(HostCache::get().take_pinned_sketch(&h_sketch), "hipHostMalloc");
     HIP_TRY(bufs.take((void**)&sketch, regs * sizeof(uint32_t)), "sketch");
     HIP_TRY(launch_zero_u64((uint64_t*)sketch, regs / 2, stream), "zero sketch");
     return RASTER_OK;
 }
 
+// Reads the sketch registers (one copy and wait) and sizes the table from
+// them.  A single-shot call may replace an empty table by one of the
+// estimated size; a stream grows its table only when the estimate shows it
+// too full to work in.
 raster_status TableRun::size_from_sketch(uint64_t points) {
     const size_t regs = (size_t)kHllReps << kHllLog2;
-    std::vector<uint32_t> h(regs);
-    HIP_TRY(hipMemcpyAsync(h.data(), sketch, regs * sizeof(uint32_t), hipMemcpyDeviceToHost, stream), "sketch copy");
+    HIP_TRY(hipMemcpyAsync(h_sketch, sketch, regs * sizeof(uint32_t), hipMemcpyDeviceToHost, stream), "sketch copy");
     HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    const uint32_t* h = h_sketch;
     std::vector<uint32_t> M(1u << kHllLog2, 0);
     for (uint32_t r = 0; r < kHllReps; ++r)
         for (uint32_t j = 0; j < (1u << kHllLog2); ++j) M[j] = std::max(M[j], h[((size_t)r << kHllLog2) + j]);
-    const double d = std::min<double>(1.25 * hll_estimate(M.data()) + (double)h_ctr[C_INSERTED], (double)points);
-    const uint64_t want = next_pow2((uint64_t)(d / tuning.load_factor) + 1);
+    const double est = hll_estimate(M.data());
+    uint64_t want;
+    if (single_shot) {
+        const double d = std::min<double>(1.25 * est + (double)h_ctr[C_INSERTED], (double)points);
+        want = next_pow2((uint64_t)(d / tuning.load_factor) + 1);
+    } else {
+        // a stream's sketch covers every binned point so far, the keys
+        // already in the table included.  Its first guess (half a chunk) is
+        // kept unless the estimate shows the table too full to work in.
+        const double d = std::min<double>(std::max<double>(est, (double)h_ctr[C_INSERTED]), (double)n_points);
+        if (d <= 0.85 * (double)cap) return RASTER_OK;
+        want = next_pow2((uint64_t)(d / tuning.load_factor) + 1);
+    }
     if (want <= cap) return RASTER_OK;
     if (h_ctr[C_INSERTED] == 0 && h_ctr[C_SPILLED] == 0) {
         // nothing inserted yet: a fresh table, no rehash
@@ -555,6 +588,7 @@ raster_status TableRun::settle() {
 raster_status TableRun::mark_pending() {
     HIP_TRY(hipMemcpyAsync(h_ctr, ctr, kCounterWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream),
             "counter copy");
+
     HIP_TRY(hipEventRecord(ev_chunk, stream), "hipEventRecord");
     chunk_pending = true;
     return RASTER_OK;
@@ -698,7 +732,8 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
                 if (st != RASTER_OK) return st;
             }
             if ((st = span_begin(0, &a)) != RASTER_OK) return st;
-            if (single_shot && (st = ensure_sketch()) != RASTER_OK) return st;
+            // the sketch of the binned keys sizes the table before the flush
+            if ((st = ensure_sketch()) != RASTER_OK) return st;
             HIP_TRY(launch_bin_points(p, piece, (int)dt, scale, bin1, cap1, cursor1, tab, cap, sp, ctr, sketch, stream,
                                       (int)dims),
                     "bin points");

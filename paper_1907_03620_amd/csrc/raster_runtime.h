@@ -134,7 +134,8 @@ struct TableRun {
     uint64_t bin2_slots = 0;
     uint32_t* cursor2 = nullptr;
     uint64_t cursor2_n = 0;
-    uint32_t* sketch = nullptr;  // one-shot calls: distinct-tile sketch of the binned keys
+    uint32_t* sketch = nullptr;  // distinct-tile sketch of the binned keys
+    uint32_t* h_sketch = nullptr;  // pinned mirror of the registers, read when the table is sized
     uint64_t group_points = 0;  // points binned since the last flush
     uint64_t group_budget = 0;
     uint64_t bin_points = 0;   // keys the coarse buckets are sized for

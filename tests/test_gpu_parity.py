@@ -344,6 +344,32 @@ def test_stream_range_error_in_a_middle_chunk(raster, torch, mid):
         raster.set_tuning(None)
 
 
+def test_stream_whose_tiles_keep_growing(raster, torch):
+    # every chunk covers its own region, so the distinct tiles grow with each
+    # chunk far past the first chunk's guess; the sketch taken while binning
+    # sizes the table at the flush (no spill-and-grow), and the result is the
+    # oracle's
+    chunks = []
+    for c in range(8):
+        rng = synth.rng_for(300 + c)
+        centres = rng.uniform(0.0, 100.0, size=(2000, 2)) + np.array([200.0 * c, 0.0])
+        pts = centres[rng.integers(0, 2000, size=500_000)] + rng.normal(0.0, 0.05, size=(500_000, 2))
+        chunks.append(np.ascontiguousarray(pts))
+    raster.set_tuning(mode=2)
+    try:
+        st = raster.Stream(tau=3, mu=2, precision=2)
+        for c in chunks:
+            st.feed(dev(c, torch))
+        g = st.finish()
+        st.close()
+    finally:
+        raster.set_tuning(None)
+    o = oracle.cluster_chunks(chunks, tau=3, mu=2, precision=2)
+    assert g.stats["distinct_tiles"] > 4 * 250_000
+    assert g.stats["grow_events"] <= 1, g.stats
+    assert_same(g, o, "stream with growing tiles")
+
+
 def test_repeated_runs_identical(raster, torch, mid, mid_oracle):
     # races in the union-find passes show up as run-to-run differences
     d = dev(mid, torch)
