@@ -1089,11 +1089,17 @@ raster_status raster_result_tile_points(raster_result* r, const void* d_points, 
     uint32_t* count = (uint32_t*)((char*)scratch + 2 * b_rows);
     uint32_t* partials = (uint32_t*)((char*)scratch + 2 * b_rows + b_count);
     unsigned long long* total = (unsigned long long*)((char*)scratch + 2 * b_rows + b_count + b_part);
+    // the scratch goes back to the pool only once the stream has passed the
+    // work that uses it (every path below has waited, except a failed launch)
     struct Release {
         DevicePool& p;
         void* b;
-        ~Release() { p.release(b); }
-    } rel{pool, scratch};
+        hipStream_t s;
+        ~Release() {
+            (void)hipStreamSynchronize(s);
+            p.release(b);
+        }
+    } rel{pool, scratch, stream};
     unsigned long long h[2] = {0, 0};  // total, range flag
     {
         std::lock_guard<std::mutex> g(r->lt_mu);
