@@ -404,14 +404,14 @@ raster_status TableRun::size_from_sketch(uint64_t points) {
     uint64_t want;
     if (single_shot) {
         const double d = std::min<double>(1.25 * est + (double)h_ctr[C_INSERTED], (double)points);
-        want = next_pow2((uint64_t)(d / tuning.load_factor) + 1);
+        want = next_pow2((uint64_t)(d / target_load()) + 1);
     } else {
         // a stream's sketch covers every binned point so far, the keys
         // already in the table included.  Its first guess (half a chunk) is
         // kept unless the estimate shows the table too full to work in.
         const double d = std::min<double>(std::max<double>(est, (double)h_ctr[C_INSERTED]), (double)n_points);
         if (d <= 0.85 * (double)cap) return RASTER_OK;
-        want = next_pow2((uint64_t)(d / tuning.load_factor) + 1);
+        want = next_pow2((uint64_t)(d / target_load()) + 1);
     }
     if (want <= cap) return RASTER_OK;
     if (h_ctr[C_INSERTED] == 0 && h_ctr[C_SPILLED] == 0) {
@@ -447,7 +447,7 @@ raster_status TableRun::init(double scale_, uint32_t tau_, uint32_t mu_, int64_t
     HIP_TRY(bufs.take((void**)&partials, kScanBlocks * sizeof(uint32_t)), "scan partials");
     HIP_TRY(launch_zero_u64((uint64_t*)ctr, kCounterWords, stream), "zero counters");
     hinted = tile_hint > 0;
-    const double lf = tuning.load_factor;
+    const double lf = target_load();
     const uint64_t want = (uint64_t)std::max<double>(4096.0, (double)std::max<int64_t>(tile_hint, 1) / lf);
     return alloc_table(next_pow2(want), &tab, &cap);
 }
@@ -540,8 +540,8 @@ raster_status TableRun::grow(uint64_t new_cap, uint64_t pending, int src) {
         if (st != RASTER_OK) return st;
         HIP_TRY(launch_zero_u64((uint64_t*)ctr + C_INSERTED, 2, stream), "reset counters");
         SpillBuf sp{spill_keys[dst], spill_counts[dst], spill_cap[dst]};
-        HIP_TRY(launch_rehash(tab, cap, nt, nc, sp, ctr, stream), "rehash");
-        HIP_TRY(launch_insert_records(spill_keys[src], spill_counts[src], pending, nt, nc, sp, ctr, stream),
+        HIP_TRY(launch_rehash(tab, cap, nt, nc, sp, ctr, stream, dims == 3), "rehash");
+        HIP_TRY(launch_insert_records(spill_keys[src], spill_counts[src], pending, nt, nc, sp, ctr, stream, dims == 3),
                 "reinsert");
         raster_status ps = pull_counters();
         if (ps != RASTER_OK) return ps;
@@ -574,7 +574,7 @@ raster_status TableRun::settle() {
     }
     const uint64_t spilled = h_ctr[C_SPILLED];
     if (spilled > 0) {
-        const double lf = tuning.load_factor;
+        const double lf = target_load();
         const uint64_t want = next_pow2((uint64_t)((double)(h_ctr[C_INSERTED] + spilled) / lf) + 1);
         raster_status st = grow(std::max<uint64_t>(want, cap * 2), spilled, 0);
         if (st != RASTER_OK) {
@@ -621,10 +621,10 @@ raster_status TableRun::flush() {
     raster_status st = settle();
     if (st != RASTER_OK) return st;
     if (sketch && (st = size_from_sketch(group_points)) != RASTER_OK) return st;
-    const Geo g = make_geo(cap);
+    const Geo g = make_geo(cap, dims == 3);
     SpillBuf sp{spill_keys[0], spill_counts[0], spill_cap[0]};
     if (!binned_geometry(g)) {
-        HIP_TRY(launch_drain_bins(bin1, cap1, cursor1, tab, cap, sp, ctr, stream), "drain bins");
+        HIP_TRY(launch_drain_bins(bin1, cap1, cursor1, tab, cap, sp, ctr, stream, dims == 3), "drain bins");
     } else {
         const uint64_t lists = (uint64_t)kBinRep << g.p_log2;  // kBinRep lists per partition
         uint64_t c2 = group_points / lists;
@@ -643,10 +643,11 @@ raster_status TableRun::flush() {
         c2 = bin2_slots / lists;
         hipEvent_t a = nullptr;
         if ((st = span_begin(1, &a)) != RASTER_OK) return st;
-        HIP_TRY(launch_bin_keys(bin1, cap1, cursor1, bin2, c2, cursor2, tab, cap, sp, ctr, stream), "bin keys");
+        HIP_TRY(launch_bin_keys(bin1, cap1, cursor1, bin2, c2, cursor2, tab, cap, sp, ctr, stream, dims == 3),
+                "bin keys");
         if ((st = span_end(1, a)) != RASTER_OK) return st;
         if ((st = span_begin(2, &a)) != RASTER_OK) return st;
-        HIP_TRY(launch_aggregate(bin2, c2, cursor2, cursor1, tab, cap, sp, ctr, stream), "aggregate");
+        HIP_TRY(launch_aggregate(bin2, c2, cursor2, cursor1, tab, cap, sp, ctr, stream, dims == 3), "aggregate");
         if ((st = span_end(2, a)) != RASTER_OK) return st;
     }
     flushes += 1;
@@ -664,7 +665,7 @@ raster_status TableRun::flush() {
 // are.  Errors of the earlier chunks are then reported by a later call.
 bool TableRun::can_bin_unsettled(int64_t n) const {
     if (!chunk_pending || !last_binned || single_shot || n <= 0 || (uint64_t)n > group_budget) return false;
-    const Geo g = make_geo(cap);
+    const Geo g = make_geo(cap, dims == 3);
     const bool binned = (tuning.mode == 2 || (tuning.mode == 0 && (uint64_t)n >= cap / 8)) && binned_geometry(g);
     if (!binned || !bin1 || group_points == 0 || group_points + (uint64_t)n > bin_points) return false;
     return spill_cap[0] >= std::min<uint64_t>(group_budget, group_points + (uint64_t)n);
@@ -677,7 +678,7 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
     if (n == 0) return RASTER_OK;
     if ((uint64_t)n_points + (uint64_t)n > 0xFFFFFFFFull)
         return fail(RASTER_E_RANGE, "more than 2^32 - 1 points in one table");
-    const double lf = tuning.load_factor;
+    const double lf = target_load();
     uint64_t want = 0;
     if (unsettled) {
         // the counters are those of an earlier chunk: no growth decision
@@ -715,7 +716,7 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
     for (int64_t off = 0; off < n;) {
         const int64_t piece = std::min<int64_t>(n - off, (int64_t)group_budget);
         const void* p = (const char*)pts + (size_t)off * point_bytes;
-        const Geo g = make_geo(cap);
+        const Geo g = make_geo(cap, dims == 3);
         const bool binned = (tuning.mode == 2 || (tuning.mode == 0 && (uint64_t)piece >= cap / 8)) &&
                             binned_geometry(g);
         SpillBuf sp{spill_keys[0], spill_counts[0], spill_cap[0]};
@@ -811,6 +812,7 @@ raster_status TableRun::finish(raster_result** out) {
     single.job.mu = mu;
     single.job.dtype = 0;
     single.job.first_tile = 0;
+    single.job.d3 = dims == 3 ? 1u : 0u;
     single.dims.slots = cap;
     single.dims.njobs = 1;
     single.dims.tiles = 0;

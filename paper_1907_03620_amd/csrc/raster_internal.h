@@ -39,13 +39,15 @@ struct Geo {
     uint64_t cap;      // slots, a power of two
     uint32_t cp_log2;  // log2 slots per partition
     uint32_t p_log2;   // log2 partitions
+    uint32_t d3;       // 1: three-dimensional keys (placed by 4x4x4 super-cubes)
 };
-__host__ __device__ inline Geo make_geo(uint64_t cap) {
+__host__ __device__ inline Geo make_geo(uint64_t cap, bool d3 = false) {
     const uint32_t l = (uint32_t)__builtin_ctzll(cap);  // cap is a power of two
     Geo g;
     g.cap = cap;
     g.cp_log2 = l < kPartLog2 ? l : kPartLog2;
     g.p_log2 = l - g.cp_log2;
+    g.d3 = d3 ? 1u : 0u;
     return g;
 }
 
@@ -117,6 +119,7 @@ struct JobInfo {
     uint32_t cshift;      // binned batches: log2 partitions per coarse bucket
     uint32_t cap2;        // binned batches: keys per partition list of the job
     uint64_t bin2_base;   // binned batches: first key of the job's partition lists
+    uint32_t d3;          // 1: three-dimensional keys
 };
 
 // One round of the link pass for a neighbourhood other than the eight
@@ -198,24 +201,24 @@ hipError_t launch_bin_points(const void* pts, int64_t n, int dtype, double scale
 // (bin2, cap2 keys per partition, counts in cursor2, which this clears first).
 hipError_t launch_bin_keys(const uint64_t* bin1, uint64_t cap1, const uint32_t* cursor1, uint64_t* bin2,
                            uint64_t cap2, uint32_t* cursor2, Slot* tab, uint64_t cap, SpillBuf spill,
-                           unsigned long long* ctr, hipStream_t stream);
+                           unsigned long long* ctr, hipStream_t stream, bool d3 = false);
 // Binned contraction, update: one workgroup per partition adds that
 // partition's keys to the table in LDS; then clears cursor1 for the next group.
 hipError_t launch_aggregate(const uint64_t* bin2, uint64_t cap2, const uint32_t* cursor2, uint32_t* cursor1,
-                            Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream);
+                            Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream, bool d3 = false);
 // Direct insertion of everything held in the coarse buckets (used when the
 // table is outside the binned geometry).  Clears cursor1.
 hipError_t launch_drain_bins(uint64_t* bin1, uint64_t cap1, uint32_t* cursor1, Slot* tab, uint64_t cap,
-                             SpillBuf spill, unsigned long long* ctr, hipStream_t stream);
+                             SpillBuf spill, unsigned long long* ctr, hipStream_t stream, bool d3 = false);
 
 // Insert n (key, count) records (spilled keys, or a rehash source).
 hipError_t launch_insert_records(const uint64_t* keys, const uint32_t* counts, uint64_t n,
                                  Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr,
-                                 hipStream_t stream);
+                                 hipStream_t stream, bool d3 = false);
 
 // Move every occupied slot of `from` into `to` (a larger table).
 hipError_t launch_rehash(const Slot* from, uint64_t from_cap, Slot* to, uint64_t to_cap,
-                         SpillBuf spill, unsigned long long* ctr, hipStream_t stream);
+                         SpillBuf spill, unsigned long long* ctr, hipStream_t stream, bool d3 = false);
 
 // Export every occupied (key, count) pair, compacted; writes at most cap rows,
 // and the number of occupied slots to ctr[C_DISTINCT].

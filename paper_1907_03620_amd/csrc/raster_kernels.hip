@@ -42,6 +42,20 @@ __device__ __forceinline__ uint32_t place_hash(uint64_t key) {
     return mix32(sx * kGolden32 + sy);
 }
 
+// The same for three-dimensional keys (three biased 21-bit coordinates, x
+// highest): the super-tile is the 4x4x4 cube of tiles holding the key, 64
+// tiles as in two dimensions.
+__device__ __forceinline__ uint32_t place_hash3(uint64_t key) {
+    constexpr uint64_t f = (1ull << 21) - 1;
+    const uint32_t sx = (uint32_t)(key >> 42) >> 2, sy = (uint32_t)((key >> 21) & f) >> 2;
+    const uint32_t sz = (uint32_t)(key & f) >> 2;
+    return mix32((sx * kGolden32 + sy) * kGolden32 + sz);
+}
+
+__device__ __forceinline__ uint32_t place_of(uint64_t key, uint32_t d3) {
+    return d3 ? place_hash3(key) : place_hash(key);
+}
+
 // Hash that picks a key's home slot inside its partition.  Low bits are used.
 // Tiles near each other never share a hash: x * kGolden32 + y (mod 2^32) takes
 // distinct values on any window of 2^14 x 2^17 tiles (checked exhaustively).
@@ -268,7 +282,7 @@ enum AddResult : int { ADD_FOUND = 0, ADD_NEW = 1, ADD_FULL = 2 };
 // (empty -> key), so a stale read can only show a slot as empty; the
 // compare-and-swap then returns the true occupant.
 __device__ __forceinline__ uint64_t home_slot(uint64_t key, const Geo& g) {
-    const uint64_t part = g.p_log2 ? (place_hash(key) >> (32 - g.p_log2)) : 0;
+    const uint64_t part = g.p_log2 ? (place_of(key, g.d3) >> (32 - g.p_log2)) : 0;
     return (part << g.cp_log2) | (slot_hash(key) & ((1u << g.cp_log2) - 1));
 }
 
@@ -537,8 +551,8 @@ struct BinScratch {
 
 // Bucket of a key: the log2 nb bits of its placement hash that end top_bits
 // from the top, so buckets refine in step with partitions.
-__device__ __forceinline__ uint32_t bucket_of(uint64_t key, uint32_t top_bits, uint32_t nb) {
-    return top_bits ? (place_hash(key) >> (32 - top_bits)) & (nb - 1) : 0u;
+__device__ __forceinline__ uint32_t bucket_of(uint64_t key, uint32_t top_bits, uint32_t nb, uint32_t d3) {
+    return top_bits ? (place_of(key, d3) >> (32 - top_bits)) & (nb - 1) : 0u;
 }
 
 // Scatters this tile's valid keys into nb buckets: bucket b's keys are
@@ -594,7 +608,7 @@ __device__ void bin_tile(BinScratch& S, const uint64_t (&key)[BIN_ITEMS], const 
         uint64_t k = 0;
         if (q < total) {
             k = S.key[q];
-            const uint32_t b = bucket_of(k, top_bits, nb);
+            const uint32_t b = bucket_of(k, top_bits, nb, g.d3);
             const uint64_t dst = (uint64_t)S.base[b] + (q - S.off[b]);
             if (dst < cap) {
                 out[(uint64_t)b * stride + dst] = k;
@@ -650,7 +664,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_points(const T* __restrict_
         if (i < n) {
             if (point_key<T>(x[j], y[j], z[j], scale, key[j])) {
                 valid |= 1u << j;
-                bucket[j] = (uint16_t)bucket_of(key[j], kCoarseLog2, kCoarse);
+                bucket[j] = (uint16_t)bucket_of(key[j], kCoarseLog2, kCoarse, g.d3);
                 uint32_t reg, rank;
                 if (SKETCH && hll_sample(key[j], reg, rank)) atomicMax(&sk[reg], rank);
             } else {
@@ -709,7 +723,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_keys(const uint64_t* __rest
         const uint64_t i = start + (uint64_t)j * BIN_THREADS + threadIdx.x;
         bucket[j] = 0;
         if (i < cnt) {
-            bucket[j] = (uint16_t)bucket_of(key[j], g.p_log2, nb);
+            bucket[j] = (uint16_t)bucket_of(key[j], g.p_log2, nb, g.d3);
             valid |= 1u << j;
         }
     }
@@ -902,7 +916,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bbin_points(JobView jv, const u
     for (uint32_t t = tr.lo; t < tr.hi; ++t) {
         job = advance_job(tile_prefix, job, t);
         const JobInfo& J = jv.jobs[job];
-        const Geo g = make_geo(J.cap);
+        const Geo g = make_geo(J.cap, J.d3 != 0);
         const uint32_t top = g.p_log2 - J.cshift;  // coarse bits of the hash
         const uint32_t nb = 1u << top;
         for (uint32_t b = threadIdx.x; b < nb; b += BIN_THREADS) S.hist[b] = 0;
@@ -933,7 +947,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bbin_points(JobView jv, const u
             if (i < J.n) {
                 if (tile_key(x[j], y[j], J.scale, key[j])) {
                     valid |= 1u << j;
-                    bucket[j] = (uint16_t)bucket_of(key[j], top, nb);
+                    bucket[j] = (uint16_t)bucket_of(key[j], top, nb, g.d3);
                 } else {
                     bad = true;
                 }
@@ -967,7 +981,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bbin_keys(JobView jv, const uin
         if (start >= cnt) continue;  // uniform across the workgroup
         const uint32_t job = cjob[c];
         const JobInfo& J = jv.jobs[job];
-        const Geo g = make_geo(J.cap);
+        const Geo g = make_geo(J.cap, J.d3 != 0);
         const uint32_t nb = 1u << J.cshift;
         for (uint32_t b = threadIdx.x; b < nb; b += BIN_THREADS) S.hist[b] = 0;
         __syncthreads();
@@ -984,7 +998,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bbin_keys(JobView jv, const uin
             const uint64_t i = start + (uint64_t)j * BIN_THREADS + threadIdx.x;
             bucket[j] = 0;
             if (i < cnt) {
-                bucket[j] = (uint16_t)bucket_of(key[j], g.p_log2, nb);
+                bucket[j] = (uint16_t)bucket_of(key[j], g.p_log2, nb, g.d3);
                 valid |= 1u << j;
             } else {
                 key[j] = 0;
@@ -1449,7 +1463,7 @@ __global__ __launch_bounds__(SQUARE_THREADS) void k_square_part(Slot* tab, JobVi
     __shared__ uint32_t nlist;
     const JobInfo& J = jv.jobs[0];
     const uint32_t tau = J.tau;
-    const Geo g = make_geo(J.cap);
+    const Geo g = make_geo(J.cap, J.d3 != 0);
     const uint32_t psize = (uint32_t)min<uint64_t>(J.cap, kPartSlots);
     const uint64_t parts = (J.cap + kPartSlots - 1) >> kPartLog2;
     for (uint64_t p = blockIdx.x; p < parts; p += gridDim.x) {
@@ -1545,7 +1559,7 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_part(const Slot* tab, Job
     bool bad = false;
     for (uint64_t p = blockIdx.x; p < parts; p += gridDim.x) {
         const JobInfo& J = jv.jobs[multi ? jv.part_job[p] : 0u];
-        const Geo g = make_geo(J.cap);
+        const Geo g = make_geo(J.cap, J.d3 != 0);
         const uint32_t psize = (uint32_t)min<uint64_t>(J.cap, kPartSlots);  // a power of two
         const uint64_t base = p << kPartLog2;
         if (threadIdx.x == 0) nlist = 0;
@@ -2219,7 +2233,7 @@ __global__ void k_batch_count(JobView jv, const uint32_t* tile_prefix, Slot* tab
         const uint32_t job = job_of_tile(tile_prefix, njobs, t);
         const JobInfo& J = jv.jobs[job];
         Slot* jt = tab + J.slot_base;
-        const Geo g = make_geo(J.cap);
+        const Geo g = make_geo(J.cap, J.d3 != 0);
         unsigned long long* jc = jv.job_ctr + (uint64_t)job * kCounterWords;
         const int64_t base = (int64_t)(t - J.first_tile) * blockDim.x * ITEMS;
         if (L) {
@@ -2338,7 +2352,7 @@ hipError_t launch_project_count(const void* pts, int64_t n, int dtype, double sc
                                  SpillBuf spill, unsigned long long* ctr, const KernelTuning& tu,
                                  hipStream_t stream, int dims) {
     if (n <= 0) return hipSuccess;
-    const Geo g = make_geo(cap);
+    const Geo g = make_geo(cap, dims == 3);
     if (dims == 3) {
         if (dtype == 1)
             return launch_count_items(static_cast<const Pt3<float>*>(pts), n, scale, tab, g, spill, ctr, tu, stream);
@@ -2353,7 +2367,7 @@ hipError_t launch_bin_points(const void* pts, int64_t n, int dtype, double scale
                              uint32_t* cursor1, Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr,
                              uint32_t* hll, hipStream_t stream, int dims) {
     if (n <= 0) return hipSuccess;
-    const Geo g = make_geo(cap);
+    const Geo g = make_geo(cap, dims == 3);
     const unsigned grid = (unsigned)((n + kBinTile - 1) / kBinTile);
     auto go = [&](auto kernel, const auto* p) {
         hipLaunchKernelGGL(kernel, dim3(grid), dim3(BIN_THREADS), 0, stream, p, n, scale, bin1, cap1, cursor1, tab, g,
@@ -2385,8 +2399,8 @@ hipError_t launch_bin_points(const void* pts, int64_t n, int dtype, double scale
 
 hipError_t launch_bin_keys(const uint64_t* bin1, uint64_t cap1, const uint32_t* cursor1, uint64_t* bin2,
                            uint64_t cap2, uint32_t* cursor2, Slot* tab, uint64_t cap, SpillBuf spill,
-                           unsigned long long* ctr, hipStream_t stream) {
-    const Geo g = make_geo(cap);
+                           unsigned long long* ctr, hipStream_t stream, bool d3) {
+    const Geo g = make_geo(cap, d3);
     if (!binned_geometry(g)) return hipErrorInvalidValue;
     const uint64_t lists2 = (uint64_t)kBinRep << g.p_log2;
     hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(lists2, 256, 4096)), dim3(256), 0, stream, cursor2, lists2);
@@ -2397,8 +2411,8 @@ hipError_t launch_bin_keys(const uint64_t* bin1, uint64_t cap1, const uint32_t* 
 }
 
 hipError_t launch_aggregate(const uint64_t* bin2, uint64_t cap2, const uint32_t* cursor2, uint32_t* cursor1,
-                            Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream) {
-    const Geo g = make_geo(cap);
+                            Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream, bool d3) {
+    const Geo g = make_geo(cap, d3);
     if (!binned_geometry(g)) return hipErrorInvalidValue;
     const uint64_t parts = 1ull << g.p_log2;
     hipLaunchKernelGGL(k_snapshot_keys, dim3(1), dim3(64), 0, stream, ctr);
@@ -2409,25 +2423,25 @@ hipError_t launch_aggregate(const uint64_t* bin2, uint64_t cap2, const uint32_t*
 }
 
 hipError_t launch_drain_bins(uint64_t* bin1, uint64_t cap1, uint32_t* cursor1, Slot* tab, uint64_t cap,
-                             SpillBuf spill, unsigned long long* ctr, hipStream_t stream) {
+                             SpillBuf spill, unsigned long long* ctr, hipStream_t stream, bool d3) {
     hipLaunchKernelGGL(k_drain_bins, dim3(grid_for((uint64_t)kBinRep * kCoarse * cap1, 256, kPersistBlocks)),
-                       dim3(256), 0, stream, bin1, cap1, cursor1, tab, make_geo(cap), spill, ctr);
+                       dim3(256), 0, stream, bin1, cap1, cursor1, tab, make_geo(cap, d3), spill, ctr);
     hipLaunchKernelGGL(k_zero_u32, dim3(4), dim3(256), 0, stream, cursor1, (uint64_t)kBinRep * kCoarse);
     return hipGetLastError();
 }
 
 hipError_t launch_insert_records(const uint64_t* keys, const uint32_t* counts, uint64_t n, Slot* tab,
-                                 uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream) {
+                                 uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream, bool d3) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_insert_records, dim3(grid_for(n, 256, kPersistBlocks)), dim3(256), 0, stream, keys,
-                       counts, n, tab, make_geo(cap), spill, ctr);
+                       counts, n, tab, make_geo(cap, d3), spill, ctr);
     return hipGetLastError();
 }
 
 hipError_t launch_rehash(const Slot* from, uint64_t from_cap, Slot* to, uint64_t to_cap, SpillBuf spill,
-                         unsigned long long* ctr, hipStream_t stream) {
+                         unsigned long long* ctr, hipStream_t stream, bool d3) {
     hipLaunchKernelGGL(k_rehash, dim3(grid_for(from_cap, 256, kPersistBlocks)), dim3(256), 0, stream, from,
-                       from_cap, to, make_geo(to_cap), spill, ctr);
+                       from_cap, to, make_geo(to_cap, d3), spill, ctr);
     return hipGetLastError();
 }
 

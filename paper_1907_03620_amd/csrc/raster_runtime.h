@@ -104,6 +104,11 @@ struct TableRun {
     uint32_t metric = RASTER_CHEBYSHEV, delta = 1;  // neighbourhood of the agglomeration
     bool square = false;                            // the 2x2 post-step before the threshold
     uint32_t dims = 2;                              // coordinates per point: 2 or 3
+    // Occupancy the table is sized for.  Three-dimensional keys are placed
+    // in partitions by 4x4x4 blocks, which dense clusters fill completely, so
+    // partition loads spread wider than with 8x8 blocks of the plane and the
+    // table is kept emptier to avoid overflowing partitions.
+    double target_load() const { return dims == 3 ? 0.75 * tuning.load_factor : tuning.load_factor; }
     raster_tuning tuning{};
     Buffers bufs;
     Slot* tab = nullptr;
