@@ -258,7 +258,6 @@ std::vector<NbrRound> neighbourhood_rounds(uint32_t metric, uint32_t delta, uint
             r.dy[q] = offs[i + q].dy;
             r.dz[q] = offs[i + q].dz;
         }
-        r.set_parent = rounds.empty() ? 1u : 0u;
         rounds.push_back(r);
     }
     return rounds;
@@ -782,7 +781,8 @@ raster_status TableRun::finish(raster_result** out) {
     HIP_TRY(bufs.take((void**)&parent, m * sizeof(uint32_t)), "parent");
     HIP_TRY(bufs.take((void**)&size, m * sizeof(uint32_t)), "sizes");
     uint32_t* nbr = nullptr;
-    HIP_TRY(bufs.take((void**)&nbr, m * 4 * sizeof(uint32_t)), "neighbour lists");
+    const std::vector<NbrRound> rounds = neighbourhood_rounds(metric, delta, dims);
+    HIP_TRY(bufs.take((void**)&nbr, m * nbr_words((int)rounds.size()) * sizeof(uint32_t)), "neighbour lists");
 
     raster_result* r = new raster_result();
     r->pool = bufs.pool;
@@ -824,7 +824,6 @@ raster_status TableRun::finish(raster_result** out) {
     e = launch_zero_u64((uint64_t*)ctr + C_DISTINCT, C_COUNT_ - C_DISTINCT, stream);
     if (e == hipSuccess) e = launch_threshold(tab, jv, s_key, s_count, size, partials, ctr, stream, square ? cap : 0);
     if (e == hipSuccess) e = hipEventRecord(ev[2], stream);
-    const std::vector<NbrRound> rounds = neighbourhood_rounds(metric, delta, dims);
     if (e == hipSuccess)
         e = launch_agglomerate(tab, cap, jv, s_key, parent, nbr, size, m, ctr, stream, rounds.data(),
                                (int)rounds.size(), dims == 3);

@@ -123,16 +123,30 @@ struct JobInfo {
 };
 
 // One round of the link pass for a neighbourhood other than the eight
-// adjacent tiles: up to four backward offsets (dx < 0, or dx == 0 and dy < 0;
-// each edge is then seen once, from its larger-key end).  The first round also
-// sets every tile's parent to its smallest-key neighbour among its offsets;
-// later rounds only record edges for the merge pass.
+// adjacent tiles: up to four backward offsets (the neighbour's key is smaller,
+// so each edge is seen once, from its larger-key end).
 struct NbrRound {
     int32_t dx[4], dy[4], dz[4];  // dz: 3-D keys only
-    uint32_t count;       // offsets in use, 1..4
-    uint32_t set_parent;  // 1 in the first round
+    uint32_t count;               // offsets in use, 1..4
 };
 constexpr uint32_t kMaxDelta = 8;
+
+// The rounds one launch of the link pass covers: the partition slice is read
+// into LDS once for all of them, and one merge pass unites along all of their
+// edges.  The first group also sets every tile's parent to its smallest-key
+// neighbour among its offsets; later groups only record edges.
+constexpr int kLinkGroup = 4;
+struct NbrGroup {
+    NbrRound r[kLinkGroup];
+    uint32_t nrounds;     // rounds in use, 1..kLinkGroup
+    uint32_t set_parent;  // 1 in the first group
+};
+
+// Neighbour-list words per significant tile for a neighbourhood of `nrounds`
+// rounds (0: the eight adjacent tiles): four per round of one group.
+inline uint64_t nbr_words(int nrounds) {
+    return 4u * (uint64_t)(nrounds <= 1 ? 1 : nrounds < kLinkGroup ? nrounds : kLinkGroup);
+}
 
 // Sizes read from device memory, so that a captured graph can be replayed
 // for any batch that fits its buffers.
@@ -238,7 +252,7 @@ hipError_t launch_threshold(Slot* tab, const JobView& jv, uint64_t* s_key, uint3
 // tile i's component; the component count goes to ctr[C_COMPONENTS] and
 // size[root] counts members up to the job's mu (size[root] >= mu exactly when
 // the component has at least mu tiles).  parent is scratch; nbr is scratch of
-// 4 words per significant tile, 16-byte aligned.
+// nbr_words(nrounds) words per significant tile, 16-byte aligned.
 hipError_t launch_agglomerate(const Slot* tab, uint64_t slots_max, const JobView& jv, const uint64_t* s_key,
                               uint32_t* parent, uint32_t* nbr, uint32_t* size, uint64_t s_max,
                               unsigned long long* ctr, hipStream_t stream,

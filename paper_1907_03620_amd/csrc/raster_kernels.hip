@@ -1541,14 +1541,15 @@ __global__ __launch_bounds__(SQUARE_THREADS) void k_square_part(Slot* tab, JobVi
 // super-tile placement most neighbours share the tile's partition and are
 // probed there; only the others are probed in the device table.
 //
-// GENERAL: the offsets come from `nr` (one round of a larger or Manhattan
-// neighbourhood, or of the 3-D one with D3) instead of the four fixed ones,
-// and the parent is written in the first round only.
+// GENERAL: the offsets come from the rounds of `grp` (a larger or Manhattan
+// neighbourhood, or the 3-D one with D3) instead of the four fixed ones; each
+// round writes its own record of four words, and the parent (the smallest-key
+// neighbour over all the group's offsets) is written by the first group only.
 constexpr int LINK_THREADS = 512;
 
 template <bool GENERAL, bool D3 = false>
 __global__ __launch_bounds__(LINK_THREADS) void k_link_part(const Slot* tab, JobView jv, uint32_t* parent,
-                                                            uint32_t* nbr, unsigned long long* ctr, NbrRound nr) {
+                                                            uint32_t* nbr, unsigned long long* ctr, NbrGroup grp) {
     __shared__ uint64_t lkey[kPartSlots];
     __shared__ uint32_t laux[kPartSlots];
     __shared__ uint16_t list[kPartSlots];
@@ -1556,6 +1557,8 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_part(const Slot* tab, Job
     const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
     const bool multi = jv.part_job != nullptr;
     const uint64_t parts = (jv.dims->slots + kPartSlots - 1) >> kPartLog2;
+    // rounds of this launch: nbr holds one record of four words per round
+    const uint32_t rounds = GENERAL ? grp.nrounds : 1u;
     bool bad = false;
     for (uint64_t p = blockIdx.x; p < parts; p += gridDim.x) {
         const JobInfo& J = jv.jobs[multi ? jv.part_job[p] : 0u];
@@ -1605,108 +1608,112 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_part(const Slot* tab, Job
             }
             const uint32_t bx = (uint32_t)(key >> 32);
             const uint32_t by = (uint32_t)key;
-            uint64_t nk[4];
-            bool want[4];
-            if (!GENERAL) {
-                // valid biased coordinates lie in [2, 2^32 - 2]
-                const bool left = bx > 2u;
-                const bool down = by > 2u;
-                const bool up = by < 0xFFFFFFFEu;
-                nk[0] = ((uint64_t)(bx - 1) << 32) | (uint32_t)(by - 1);
-                want[0] = left && down;
-                nk[1] = ((uint64_t)(bx - 1) << 32) | by;
-                want[1] = left;
-                nk[2] = ((uint64_t)(bx - 1) << 32) | (uint32_t)(by + 1);
-                want[2] = left && up;
-                nk[3] = ((uint64_t)bx << 32) | (uint32_t)(by - 1);
-                want[3] = down;
-            } else if (!D3) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int64_t x = (int64_t)bx + nr.dx[q];
-                    const int64_t y = (int64_t)by + nr.dy[q];
-                    want[q] = q < (int)nr.count && x >= 2 && x <= 0xFFFFFFFEll && y >= 2 && y <= 0xFFFFFFFEll;
-                    nk[q] = want[q] ? (((uint64_t)(uint32_t)x << 32) | (uint32_t)y) : key;
-                }
-            } else {
-                // 3-D keys: biased fields of 21 bits, valid in [2, 2^21 - 2]
-                const int64_t x0 = (int64_t)(key >> 42), y0 = (int64_t)((key >> 21) & kField3);
-                const int64_t z0 = (int64_t)(key & kField3);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int64_t x = x0 + nr.dx[q], y = y0 + nr.dy[q], z = z0 + nr.dz[q];
-                    const int64_t hi = (int64_t)kField3 - 1;
-                    want[q] = q < (int)nr.count && x >= 2 && x <= hi && y >= 2 && y <= hi && z >= 2 && z <= hi;
-                    nk[q] = want[q] ? (((uint64_t)x << 42) | ((uint64_t)y << 21) | (uint64_t)z) : key;
-                }
-            }
-            // first probes: device-table loads for the other partitions are
-            // issued together, LDS probes need no wait
-            // (home slot and the next one: a probe walk mostly ends there)
-            uint64_t pos[4];
-            bool local[4];
-            Slot v[4], w[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                pos[q] = home_slot(nk[q], g);
-                local[q] = ((J.slot_base + pos[q]) >> kPartLog2) == p;
-                if (want[q] && !local[q]) {
-                    v[q] = jt[pos[q]];
-                    w[q] = jt[next_slot(pos[q], g)];
-                }
-            }
             uint32_t best = i;
             uint64_t best_key = key;
-            uint32_t j[4];
+#pragma unroll 1
+            for (uint32_t r = 0; r < rounds; ++r) {
+                const NbrRound& nr_ = grp.r[r];
+                uint64_t nk[4];
+                bool want[4];
+                if (!GENERAL) {
+                    // valid biased coordinates lie in [2, 2^32 - 2]
+                    const bool left = bx > 2u;
+                    const bool down = by > 2u;
+                    const bool up = by < 0xFFFFFFFEu;
+                    nk[0] = ((uint64_t)(bx - 1) << 32) | (uint32_t)(by - 1);
+                    want[0] = left && down;
+                    nk[1] = ((uint64_t)(bx - 1) << 32) | by;
+                    want[1] = left;
+                    nk[2] = ((uint64_t)(bx - 1) << 32) | (uint32_t)(by + 1);
+                    want[2] = left && up;
+                    nk[3] = ((uint64_t)bx << 32) | (uint32_t)(by - 1);
+                    want[3] = down;
+                } else if (!D3) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                j[q] = kNoNeighbour;
-                if (!want[q]) continue;
-                uint32_t aux = kNotSignificant;
-                if (local[q]) {
-                    uint32_t lp = (uint32_t)(J.slot_base + pos[q] - base);
-                    for (uint32_t step = 0; step < kMaxProbe; ++step) {
-                        const uint64_t cur = lkey[lp];
-                        if (cur == nk[q]) {
-                            aux = laux[lp];
-                            break;
-                        }
-                        if (cur == kEmptyKey) break;
-                        lp = (lp + 1) & (psize - 1);
+                    for (int q = 0; q < 4; ++q) {
+                        const int64_t x = (int64_t)bx + nr_.dx[q];
+                        const int64_t y = (int64_t)by + nr_.dy[q];
+                        want[q] = q < (int)nr_.count && x >= 2 && x <= 0xFFFFFFFEll && y >= 2 && y <= 0xFFFFFFFEll;
+                        nk[q] = want[q] ? (((uint64_t)(uint32_t)x << 32) | (uint32_t)y) : key;
                     }
                 } else {
-                    if (v[q].key != nk[q] && v[q].key != kEmptyKey) {
-                        // second probe already loaded
-                        pos[q] = next_slot(pos[q], g);
-                        v[q] = w[q];
-                        uint32_t steps = 2;
-                        while (v[q].key != nk[q] && v[q].key != kEmptyKey && steps < kMaxProbe) {
-                            pos[q] = next_slot(pos[q], g);
-                            v[q] = jt[pos[q]];
-                            ++steps;
-                        }
+                    // 3-D keys: biased fields of 21 bits, valid in [2, 2^21 - 2]
+                    const int64_t x0 = (int64_t)(key >> 42), y0 = (int64_t)((key >> 21) & kField3);
+                    const int64_t z0 = (int64_t)(key & kField3);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int64_t x = x0 + nr_.dx[q], y = y0 + nr_.dy[q], z = z0 + nr_.dz[q];
+                        const int64_t hi = (int64_t)kField3 - 1;
+                        want[q] = q < (int)nr_.count && x >= 2 && x <= hi && y >= 2 && y <= hi && z >= 2 && z <= hi;
+                        nk[q] = want[q] ? (((uint64_t)x << 42) | ((uint64_t)y << 21) | (uint64_t)z) : key;
                     }
-                    if (v[q].key == nk[q]) aux = v[q].aux;
                 }
-                if (aux != kNotSignificant) {
-                    if (aux >= s) {
-                        bad = true;
+                // first probes: device-table loads for the other partitions are
+                // issued together, LDS probes need no wait
+                // (home slot and the next one: a probe walk mostly ends there)
+                uint64_t pos[4];
+                bool local[4];
+                Slot v[4], w[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    pos[q] = home_slot(nk[q], g);
+                    local[q] = ((J.slot_base + pos[q]) >> kPartLog2) == p;
+                    if (want[q] && !local[q]) {
+                        v[q] = jt[pos[q]];
+                        w[q] = jt[next_slot(pos[q], g)];
+                    }
+                }
+                uint32_t j[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    j[q] = kNoNeighbour;
+                    if (!want[q]) continue;
+                    uint32_t aux = kNotSignificant;
+                    if (local[q]) {
+                        uint32_t lp = (uint32_t)(J.slot_base + pos[q] - base);
+                        for (uint32_t step = 0; step < kMaxProbe; ++step) {
+                            const uint64_t cur = lkey[lp];
+                            if (cur == nk[q]) {
+                                aux = laux[lp];
+                                break;
+                            }
+                            if (cur == kEmptyKey) break;
+                            lp = (lp + 1) & (psize - 1);
+                        }
                     } else {
-                        j[q] = aux;
-                        if (nk[q] < best_key) {
-                            best_key = nk[q];
-                            best = aux;
+                        if (v[q].key != nk[q] && v[q].key != kEmptyKey) {
+                            // second probe already loaded
+                            pos[q] = next_slot(pos[q], g);
+                            v[q] = w[q];
+                            uint32_t steps = 2;
+                            while (v[q].key != nk[q] && v[q].key != kEmptyKey && steps < kMaxProbe) {
+                                pos[q] = next_slot(pos[q], g);
+                                v[q] = jt[pos[q]];
+                                ++steps;
+                            }
+                        }
+                        if (v[q].key == nk[q]) aux = v[q].aux;
+                    }
+                    if (aux != kNotSignificant) {
+                        if (aux >= s) {
+                            bad = true;
+                        } else {
+                            j[q] = aux;
+                            if (nk[q] < best_key) {
+                                best_key = nk[q];
+                                best = aux;
+                            }
                         }
                     }
                 }
+                uint4 rec;
+                rec.x = j[0];
+                rec.y = j[1];
+                rec.z = j[2];
+                rec.w = j[3];
+                reinterpret_cast<uint4*>(nbr)[(uint64_t)i * rounds + r] = rec;
             }
-            if (!GENERAL || nr.set_parent) parent[i] = best;
-            uint4 rec;
-            rec.x = j[0];
-            rec.y = j[1];
-            rec.z = j[2];
-            rec.w = j[3];
-            reinterpret_cast<uint4*>(nbr)[i] = rec;
+            if (!GENERAL || grp.set_parent) parent[i] = best;
         }
     }
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
@@ -1724,23 +1731,29 @@ __global__ void k_jump(uint32_t* parent, unsigned long long* ctr) {
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
 }
 
-__global__ void k_merge(const uint32_t* nbr, const uint64_t* s_key, uint32_t* parent, unsigned long long* ctr) {
+// Unites every tile with the neighbours recorded by one link launch: `recs`
+// records of four words per tile.
+__global__ void k_merge(const uint32_t* nbr, uint32_t recs, const uint64_t* s_key, uint32_t* parent,
+                        unsigned long long* ctr) {
     const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
     bool bad = false;
     const XcdSpan span = xcd_span(s);
     for (uint64_t i = span.first; i < span.hi; i += span.step) {
-        const uint4 rec = reinterpret_cast<const uint4*>(nbr)[i];
-        const uint32_t j[4] = {rec.x, rec.y, rec.z, rec.w};
         // After the jump pass parents are roots; a tile whose recorded
         // neighbours share its root needs no hook.  These first reads may be
         // stale within this kernel: an equal value still proves the two tiles
         // are connected, and a differing one only costs a redundant unite.
         const uint32_t ri = __hip_atomic_load(parent + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll 1
+        for (uint32_t r = 0; r < recs; ++r) {
+            const uint4 rec = reinterpret_cast<const uint4*>(nbr)[i * recs + r];
+            const uint32_t j[4] = {rec.x, rec.y, rec.z, rec.w};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (j[q] == kNoNeighbour) continue;
-            if (__hip_atomic_load(parent + j[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == ri) continue;
-            uf_unite(parent, s_key, (uint32_t)i, j[q], s, bad);
+            for (int q = 0; q < 4; ++q) {
+                if (j[q] == kNoNeighbour) continue;
+                if (__hip_atomic_load(parent + j[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == ri) continue;
+                uf_unite(parent, s_key, (uint32_t)i, j[q], s, bad);
+            }
         }
     }
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
@@ -2482,21 +2495,26 @@ hipError_t launch_agglomerate(const Slot* tab, uint64_t slots_max, const JobView
     const int link_grid = grid_for((slots_max + kPartSlots - 1) >> kPartLog2, 1, 8192);
     if (nrounds <= 0) {
         hipLaunchKernelGGL((k_link_part<false, false>), dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, jv,
-                           parent, nbr, ctr, NbrRound{});
+                           parent, nbr, ctr, NbrGroup{});
         hipLaunchKernelGGL(k_jump, dim3(grid), dim3(256), 0, stream, parent, ctr);
-        hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, stream, nbr, s_key, parent, ctr);
+        hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, stream, nbr, 1u, s_key, parent, ctr);
     } else {
-        // round 0 builds the forest from its offsets; each later round records
-        // the edges of four more offsets and unites along them
-        for (int r = 0; r < nrounds; ++r) {
+        // the first group builds the forest from its offsets; each later group
+        // records the edges of up to kLinkGroup rounds more and unites along
+        // them
+        for (int r0 = 0; r0 < nrounds; r0 += kLinkGroup) {
+            NbrGroup grp{};
+            grp.nrounds = (uint32_t)std::min(kLinkGroup, nrounds - r0);
+            for (uint32_t r = 0; r < grp.nrounds; ++r) grp.r[r] = rounds[r0 + r];
+            grp.set_parent = r0 == 0 ? 1u : 0u;
             if (d3)
                 hipLaunchKernelGGL((k_link_part<true, true>), dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, jv,
-                                   parent, nbr, ctr, rounds[r]);
+                                   parent, nbr, ctr, grp);
             else
                 hipLaunchKernelGGL((k_link_part<true, false>), dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, jv,
-                                   parent, nbr, ctr, rounds[r]);
-            if (r == 0) hipLaunchKernelGGL(k_jump, dim3(grid), dim3(256), 0, stream, parent, ctr);
-            hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, stream, nbr, s_key, parent, ctr);
+                                   parent, nbr, ctr, grp);
+            if (r0 == 0) hipLaunchKernelGGL(k_jump, dim3(grid), dim3(256), 0, stream, parent, ctr);
+            hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, stream, nbr, grp.nrounds, s_key, parent, ctr);
         }
     }
     // the neighbour lists are dead after the merge pass; their first s words
