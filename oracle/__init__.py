@@ -60,6 +60,8 @@ def _load():
     lib.oracle_scale_for_precision.restype = dbl
     lib.oracle_project.argtypes = [vp, i64, i32, dbl, vp, vp]
     lib.oracle_project.restype = ctypes.c_int
+    lib.oracle_project3.argtypes = [vp, i64, i32, dbl, vp, vp, vp]
+    lib.oracle_project3.restype = ctypes.c_int
     lib.oracle_begin.argtypes = [dbl, u64, u64]
     lib.oracle_begin.restype = vp
     lib.oracle_begin_ex.argtypes = [dbl, u64, u64, i32, i64, i32, i32]
@@ -121,6 +123,18 @@ def project(points, scale: float):
     if rc != OK:
         raise OracleError(rc, "project")
     return kx, ky
+
+
+def project3(points, scale: float):
+    """Tile coordinates (kx, ky, kz) of every three-dimensional point
+    (Section 3.2's projection per coordinate, Section 3.6's d dimensions)."""
+    a, dt = _as_points(points, 3)
+    n = a.shape[0]
+    k = [np.empty(n, np.int64) for _ in range(3)]
+    rc = _load().oracle_project3(a.ctypes.data, n, dt, float(scale), *(c.ctypes.data for c in k))
+    if rc != OK:
+        raise OracleError(rc, "project3")
+    return tuple(k)
 
 
 def count_tiles(points, scale: float, qx, qy, out=None):
@@ -259,6 +273,33 @@ def cluster(points, tau: int, mu: int, precision: int | None = None,
         st.close()
 
 
+def _id_3d(kx, ky, kz):
+    """Three-dimensional tiles with |k| <= 2^20 - 2 as int64: the biased
+    coordinates k + 2^20 lie in [2, 2^21 - 2] and are written as the digits of
+    a number in base 2^21, most significant first, so the numbers order the
+    tiles lexicographically.  For a cluster's smallest tile this is its
+    label."""
+    base = 1 << 21
+    bias = 1 << 20
+    x, y, z = (np.asarray(c, dtype=np.int64) + bias for c in (kx, ky, kz))
+    return (x * base + y) * base + z
+
+
+def _rows_3d(points, result: OracleResult, s: float):
+    """Row of ``result`` holding each three-dimensional point's tile, or -1."""
+    kx, ky, kz = project3(points, s)
+    row = np.full(kx.shape[0], -1, dtype=np.int64)
+    if result.num_tiles == 0 or kx.shape[0] == 0:
+        return row
+    ids = _id_3d(result.kx, result.ky, result.kz)
+    by_id = np.argsort(ids)
+    want = _id_3d(kx, ky, kz)
+    at = np.minimum(np.searchsorted(ids[by_id], want), ids.shape[0] - 1)
+    found = ids[by_id][at] == want
+    row[found] = by_id[at[found]]
+    return row
+
+
 def point_labels(points, result: OracleResult, precision: int | None = None,
                  scale: float | None = None):
     """Per-point labels as in the paper's comparison experiment (Section 4.1, RASTER-star):
@@ -268,7 +309,15 @@ def point_labels(points, result: OracleResult, precision: int | None = None,
     ((label_x + 2^31) << 32) | (label_y + 2^31), returned as int64 (two's
     complement), so that -1 is never a label.  A tile (kx, ky) is looked up
     among the result's tiles through the bijection kx * 2^32 + ky, which keeps
-    the lexicographic order for |k| <= 2^31 - 2."""
+    the lexicographic order for |k| <= 2^31 - 2.  For a three-dimensional
+    result (Section 3.6) the points are (n, 3) and the label is _id_3d of the
+    cluster's smallest tile."""
+    if result.kz is not None:
+        row = _rows_3d(points, result, _scale(precision, scale))
+        out = np.full(row.shape[0], -1, dtype=np.int64)
+        on = row >= 0
+        out[on] = _id_3d(result.label_x, result.label_y, result.label_z)[row[on]]
+        return out
     kx, ky = project(points, _scale(precision, scale))
     out = np.full(kx.shape[0], -1, dtype=np.int64)
     if result.num_tiles == 0 or kx.shape[0] == 0:
@@ -292,9 +341,17 @@ def tile_points(points, result: OracleResult, precision: int | None = None,
     projected a second time (Section 3.2) and each point on a row's tile is
     listed under that row.  Returns (row_start, index) for the rows of
     ``result`` in its order: the points on row j are
-    index[row_start[j]:row_start[j + 1]], ascending."""
-    kx, ky = project(points, _scale(precision, scale))
+    index[row_start[j]:row_start[j + 1]], ascending.  Points are (n, 3) for a
+    three-dimensional result."""
     t = result.num_tiles
+    if result.kz is not None:
+        row = _rows_3d(points, result, _scale(precision, scale))
+        point = np.flatnonzero(row >= 0)
+        listed = point[np.lexsort((point, row[point]))]     # by row, then ascending point
+        starts = np.zeros(t + 1, dtype=np.int64)
+        starts[1:] = np.add.accumulate(np.bincount(row[point], minlength=t))
+        return starts, listed.astype(np.int64)
+    kx, ky = project(points, _scale(precision, scale))
     row_start = np.zeros(t + 1, dtype=np.int64)
     if t == 0 or kx.shape[0] == 0:
         return row_start, np.zeros(0, dtype=np.int64)

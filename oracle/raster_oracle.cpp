@@ -142,6 +142,18 @@ int oracle_project(const void* pts, int64_t n, int32_t dtype, double scale,
     return kOK;
 }
 
+// The same for three-dimensional points (row-major (n, 3)), each coordinate
+// projected alone; tiles must satisfy |k| <= 2^20 - 2.
+int oracle_project3(const void* pts, int64_t n, int32_t dtype, double scale,
+                    int64_t* kx, int64_t* ky, int64_t* kz) {
+    if (n < 0 || (dtype != 1 && dtype != 2) || (n > 0 && (!pts || !kx || !ky || !kz))) return kInval;
+    int64_t* out[3] = {kx, ky, kz};
+    for (int64_t i = 0; i < n; ++i)
+        for (int c = 0; c < 3; ++c)
+            if (project_coord(point_coord(pts, dtype, 3, i, c), scale, kBound3d, &out[c][i]) != kOK) return kRange;
+    return kOK;
+}
+
 // metric: 0 = Chebyshev, 1 = Manhattan; 1 <= delta <= 64; window: 0 or 1
 // (the 2x2 post-step, 2-D only); dims: 2 or 3.
 void* oracle_begin_ex(double scale, uint64_t tau, uint64_t mu, int32_t metric, int64_t delta, int32_t window,

@@ -102,8 +102,55 @@ def pin_brute_force(oracle_mod):
         assert _labels(oracle_mod, pts, tau, mu, scale=s) == want, seed
 
 
+def _pack3(lx, ly, lz):
+    """The label word of a 3-D tile: three biased 21-bit fields, x highest."""
+    return ((lx + (1 << 20)) << 42) | ((ly + (1 << 20)) << 21) | (lz + (1 << 20))
+
+
+def pin_brute_force_3d(oracle_mod):
+    # Section 3.6's three dimensions: every point carries the label of its
+    # tile's kept cluster, from the brute force's rows
+    for seed in range(60):
+        rng = np.random.default_rng(1500 + seed)
+        n = int(rng.integers(0, 250))
+        pts = rng.uniform(-1.0, 1.0, size=3) + rng.normal(0.0, 0.3, size=(n, 3))
+        if seed % 4 == 0:
+            pts = pts.astype(np.float32)
+        p, tau, mu = int(rng.integers(0, 3)), int(rng.integers(1, 4)), int(rng.integers(1, 4))
+        s = oracle_mod.scale_for_precision(p)
+        rows, _ = brute_cluster(pts, s, tau, mu)
+        tile_label = {(kx, ky, kz): _pack3(lx, ly, lz) for kx, ky, kz, _, lx, ly, lz in rows}
+        k = np.trunc(np.asarray(pts).astype(np.float64) * s).astype(np.int64)
+        want = [tile_label.get(tuple(int(v) for v in t), -1) for t in k]
+        assert _labels(oracle_mod, pts, tau, mu, scale=s) == want, seed
+
+
+def pin_3d_lookup_needs_every_axis(oracle_mod):
+    # tiles that are permutations of one another's coordinates: only the point
+    # on the kept tile (1, 2, 3) gets a label
+    pts = np.array([[1.5, 2.5, 3.5]] * 3 + [[3.5, 2.5, 1.5], [2.5, 1.5, 3.5], [1.5, 3.5, 2.5], [-1.5, -2.5, -3.5]])
+    assert _labels(oracle_mod, pts, 3, 1, precision=0) == [_pack3(1, 2, 3)] * 3 + [-1] * 4
+    pts = np.array([[-1.5, -2.5, -3.5]] * 2 + [[-1.5, -2.5, -2.5]])
+    assert _labels(oracle_mod, pts, 1, 2, precision=0) == [_pack3(-1, -2, -3)] * 3
+
+
+def pin_3d_rows_in_any_order(oracle_mod):
+    # a result's rows may come in any order (the GPU's come in compaction
+    # order): permuting them changes no label
+    rng = np.random.default_rng(21)
+    pts = rng.normal(0.0, 0.3, size=(3000, 3))
+    r = oracle_mod.cluster(pts, tau=2, mu=2, precision=1)
+    want = oracle_mod.point_labels(pts, r, precision=1).tolist()
+    assert r.num_tiles > 10 and sum(v != -1 for v in want) > 100
+    perm = rng.permutation(r.num_tiles)
+    rp = oracle_mod.OracleResult(r.kx[perm], r.ky[perm], r.count[perm], r.label_x[perm], r.label_y[perm], r.stats,
+                                 r.kz[perm], r.label_z[perm])
+    assert oracle_mod.point_labels(pts, rp, precision=1).tolist() == want
+
+
 PINS = [pin_worked_example, pin_fig4_corner, pin_negative_tiles_and_order, pin_lookup_needs_both_axes,
-        pin_counts_per_label, pin_brute_force]
+        pin_counts_per_label, pin_brute_force, pin_brute_force_3d, pin_3d_lookup_needs_every_axis,
+        pin_3d_rows_in_any_order]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=[f.__name__ for f in PINS])
@@ -127,6 +174,10 @@ MUTANTS = {
     "noise_is_zero": ("out = np.full(kx.shape[0], -1, dtype=np.int64)",
                       "out = np.full(kx.shape[0], 0, dtype=np.int64)"),
     "nearest_not_equal": ("hit[hit] = tiles[pos[hit]] == q[hit]", "pass"),
+    "3d_x_y_swapped": ("return (x * base + y) * base + z", "return (y * base + x) * base + z"),
+    "3d_no_bias": ("bias = 1 << 20", "bias = 0"),
+    "3d_nearest_not_equal": ("found = ids[by_id][at] == want", "found = at >= 0"),
+    "3d_sorted_row_not_result_row": ("row[found] = by_id[at[found]]", "row[found] = at[found]"),
 }
 
 

@@ -93,7 +93,27 @@ def pin_rows_in_result_order(mod):
         assert pi[ps[j]:ps[j + 1]].tolist() == index[start[q]:start[q + 1]].tolist()
 
 
-PINS = [pin_worked_example, pin_fig4_corner, pin_row_sizes_are_counts, pin_brute_force, pin_rows_in_result_order]
+def pin_brute_force_3d(mod):
+    # Section 3.6's three dimensions: the rows' lists from the brute force
+    for seed in range(50):
+        rng = np.random.default_rng(1900 + seed)
+        n = int(rng.integers(0, 250))
+        pts = rng.uniform(-1.0, 1.0, size=3) + rng.normal(0.0, 0.3, size=(n, 3))
+        p, tau, mu = int(rng.integers(0, 3)), int(rng.integers(1, 4)), int(rng.integers(1, 4))
+        s = mod.scale_for_precision(p)
+        rows, _ = brute_cluster(pts, s, tau, mu)
+        k = np.trunc(np.asarray(pts, dtype=np.float64) * s).astype(np.int64)
+        want = {row[:3]: [i for i in range(n) if tuple(int(v) for v in k[i]) == row[:3]] for row in rows}
+        r = mod.cluster(pts, tau=tau, mu=mu, scale=s)
+        start, index = mod.tile_points(pts, r, scale=s)
+        got = {(int(r.kx[j]), int(r.ky[j]), int(r.kz[j])): index[start[j]:start[j + 1]].tolist()
+               for j in range(r.num_tiles)}
+        assert got == want, seed
+        assert start.tolist() == [0] + np.cumsum(r.count.astype(np.int64)).tolist(), seed
+
+
+PINS = [pin_worked_example, pin_fig4_corner, pin_row_sizes_are_counts, pin_brute_force, pin_rows_in_result_order,
+        pin_brute_force_3d]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=[f.__name__ for f in PINS])
@@ -115,6 +135,8 @@ MUTANTS = {
     "offsets_shifted": ("row_start[1:] = np.cumsum(np.bincount(row, minlength=t))",
                         "row_start[:-1] = np.cumsum(np.bincount(row, minlength=t))"),
     "point_order_lost": ('by_row = np.argsort(row, kind="stable")', 'by_row = np.argsort(-row, kind="stable")[::-1]'),
+    "3d_points_before_rows": ("np.lexsort((point, row[point]))", "np.lexsort((row[point], point))"),
+    "3d_offsets_shifted": ("starts[1:] = np.add.accumulate(", "starts[:-1] = np.add.accumulate("),
 }
 
 
