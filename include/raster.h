@@ -155,7 +155,7 @@ raster_status raster_cluster_delta(const void* d_points, int64_t n, raster_dtype
  * neighbours).  The label is the biased key of the cluster's smallest tile in
  * (x, y, z) order, ((kx + 2^20) << 42) | ((ky + 2^20) << 21) | (kz + 2^20);
  * the third coordinate of each row comes from raster_result_kz.  Not with
- * square_step, batches, per-point labels or per-tile point lists.  square_step = 1
+ * square_step or in batches.  square_step = 1
  * adds the post-step that Section 3.6 proposes for points spread over the
  * tiles around a grid corner (Figure 4): a tile with fewer than tau points is
  * also significant when some 2x2 square of tiles containing it holds at least
@@ -196,7 +196,8 @@ void raster_result_free(raster_result* r);
 /* Per-point labels: the label of every input point, obtained as in the
  * paper's comparison experiment (Section 4.1, its RASTER-star variant) by
  * projecting the points a second time.  Each of the n points of d_points
- * ((n, 2) row-major, dt as for clustering, borrowed for the call) is projected
+ * ((n, 2) row-major, or (n, 3) for a three-dimensional result; dt as for
+ * clustering, borrowed for the call) is projected
  * with the scale the result was computed with; d_labels[i] (caller-owned
  * device array of n uint64, 8-byte aligned) receives the label of the kept
  * cluster its tile belongs to (the biased key of that cluster's smallest
@@ -205,8 +206,8 @@ void raster_result_free(raster_result* r);
  * The first call builds a device lookup table of the result's tiles, kept
  * with the result until raster_result_free.  Synchronises `stream`.  Errors:
  * E_INVAL for bad arguments; E_RANGE if a point is not finite or its tile is
- * outside +-(2^31 - 2) (that point's label is then -1; the others are
- * written).  Calls on one result are serialised. */
+ * outside +-(2^31 - 2) (+-(2^20 - 2) in three dimensions; that point's label
+ * is then -1; the others are written).  Calls on one result are serialised. */
 raster_status raster_result_point_labels(raster_result* r, const void* d_points, int64_t n, raster_dtype dt,
                                          uint64_t* d_labels, hipStream_t stream);
 
@@ -214,7 +215,8 @@ raster_status raster_result_point_labels(raster_result* r, const void* d_points,
  * The paper's RASTER' keeps each tile's points in the hash table during
  * contraction; here they are gathered after clustering by projecting the
  * points a second time, which gives the same sets.  For the n points of
- * d_points (borrowed for the call; n < 2^32 - 1), the indices of the points
+ * d_points ((n, 2), or (n, 3) for a three-dimensional result; borrowed for
+ * the call; n < 2^32 - 1), the indices of the points
  * on row j of the result (the row order of raster_result_arrays) are
  * d_index[d_row_start[j] .. d_row_start[j + 1]), in no particular order within
  * a row.  d_row_start: caller-owned device array of t + 1 uint64;
@@ -223,8 +225,8 @@ raster_status raster_result_point_labels(raster_result* r, const void* d_points,
  * number.  Points on no kept tile are not listed.  Synchronises `stream`.
  * Errors: E_INVAL for bad arguments, or when cap is too small (then
  * d_row_start and *n_kept are written, d_index is not); E_RANGE if a point is
- * not finite or its tile is outside +-(2^31 - 2).  Calls on one result are
- * serialised. */
+ * not finite or its tile is outside +-(2^31 - 2) (+-(2^20 - 2) in three
+ * dimensions).  Calls on one result are serialised. */
 raster_status raster_result_tile_points(raster_result* r, const void* d_points, int64_t n, raster_dtype dt,
                                         uint64_t* d_row_start, uint64_t* d_index, int64_t cap, int64_t* n_kept,
                                         hipStream_t stream);

@@ -240,9 +240,10 @@ class Result:
     def point_labels(self, points, stream=None):
         """Label of every point (Section 4.1, RASTER-star): the cluster label of its tile as
         int64 (the biased key of the cluster's smallest tile, read as
-        two's complement), or -1 for a point on no kept tile."""
+        two's complement), or -1 for a point on no kept tile.  Points are (n, 3)
+        for a three-dimensional result."""
         torch = _torch()
-        p, n, dt = _points(points)
+        p, n, dt = _points(points, self.dims)
         out = torch.empty(n, dtype=torch.int64, device=points.device)
         st = _stream_handle(stream if stream is not None else self._stream)
         _check(load().raster_result_point_labels(self._h, p, n, dt, ctypes.c_void_p(out.data_ptr()), st),
@@ -253,9 +254,10 @@ class Result:
         """Points of every kept tile (RASTER', Section 3.4): ``(row_start,
         index)`` as int64 tensors, where the points on row j of
         :meth:`tensors` are ``index[row_start[j]:row_start[j + 1]]`` (indices
-        into ``points``, unordered within a row)."""
+        into ``points``, unordered within a row).  Points are (n, 3) for a
+        three-dimensional result."""
         torch = _torch()
-        p, n, dt = _points(points)
+        p, n, dt = _points(points, self.dims)
         start = torch.empty(self.num_tiles + 1, dtype=torch.int64, device=points.device)
         index = torch.empty(max(n, 1), dtype=torch.int64, device=points.device)
         kept = ctypes.c_int64()

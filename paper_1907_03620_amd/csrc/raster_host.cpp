@@ -191,6 +191,11 @@ uint64_t next_pow2(uint64_t v) {
     return c;
 }
 
+const char* range_message(int dims) {
+    return dims == 3 ? "a coordinate is not finite or its tile is outside +-(2^20 - 2)"
+                     : "a coordinate is not finite or its tile is outside +-(2^31 - 2)";
+}
+
 raster_status check_points(const void* p, int64_t n, raster_dtype dt, uint32_t dims) {
     if (dt != RASTER_F32 && dt != RASTER_F64) return fail(RASTER_E_INVAL, "unknown dtype %d", (int)dt);
     if (n < 0) return fail(RASTER_E_INVAL, "negative point count %lld", (long long)n);
@@ -565,7 +570,7 @@ raster_status TableRun::settle() {
     resolve_spans();
     if (h_ctr[C_ERROR] & kErrRange) {
         failed = RASTER_E_RANGE;
-        return fail(RASTER_E_RANGE, "a coordinate is not finite or its tile is outside +-(2^31 - 2)");
+        return fail(RASTER_E_RANGE, "%s", range_message(dims));
     }
     if (h_ctr[C_ERROR] & kErrSpillOverflow) {
         failed = RASTER_E_DEVICE;
@@ -1024,7 +1029,7 @@ static raster_status ensure_lookup(raster_result* r, bool rows, DevicePool& pool
     void* t = nullptr;
     HIP_TRY(pool.alloc(&t, 2 * cap * sizeof(uint64_t)), "lookup table");
     const hipError_t le = launch_label_table(r->kx, r->ky, r->label, (uint64_t)r->tiles, (uint64_t*)t, cap, rows,
-                                             stream);
+                                             stream, r->kz);
     if (le != hipSuccess) {
         pool.release(t);
         return hip_fail(le, "lookup table");
@@ -1037,8 +1042,7 @@ static raster_status ensure_lookup(raster_result* r, bool rows, DevicePool& pool
 raster_status raster_result_point_labels(raster_result* r, const void* d_points, int64_t n, raster_dtype dt,
                                          uint64_t* d_labels, hipStream_t stream) {
     if (!r) return fail(RASTER_E_INVAL, "result is NULL");
-    if (r->dims != 2) return fail(RASTER_E_INVAL, "per-point labels of a three-dimensional result");
-    raster_status st = check_points(d_points, n, dt);
+    raster_status st = check_points(d_points, n, dt, (uint32_t)r->dims);
     if (st != RASTER_OK) return st;
     if (n > 0 && !d_labels) return fail(RASTER_E_INVAL, "labels is NULL with n = %lld", (long long)n);
     if (((uintptr_t)d_labels % 8) != 0) return fail(RASTER_E_INVAL, "labels must be 8-byte aligned");
@@ -1051,13 +1055,13 @@ raster_status raster_result_point_labels(raster_result* r, const void* d_points,
         std::lock_guard<std::mutex> g(r->lt_mu);
         if ((st = ensure_lookup(r, false, pool, stream)) != RASTER_OK) return st;
         HIP_TRY(launch_zero_u64((uint64_t*)r->lt_err, 1, stream), "zero flag");
-        HIP_TRY(launch_point_labels(d_points, n, (int)dt, r->scale, r->lt, r->lt_cap, d_labels, r->lt_err, stream),
+        HIP_TRY(launch_point_labels(d_points, n, (int)dt, r->scale, r->lt, r->lt_cap, d_labels, r->lt_err, stream,
+                                    r->dims),
                 "point labels");
         HIP_TRY(hipMemcpyAsync(&err, r->lt_err, sizeof err, hipMemcpyDeviceToHost, stream), "flag copy");
         HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
     }
-    if (err & kErrRange)
-        return fail(RASTER_E_RANGE, "a coordinate is not finite or its tile is outside +-(2^31 - 2)");
+    if (err & kErrRange) return fail(RASTER_E_RANGE, "%s", range_message(r->dims));
     return RASTER_OK;
 }
 
@@ -1066,9 +1070,8 @@ raster_status raster_result_tile_points(raster_result* r, const void* d_points, 
                                         hipStream_t stream) {
     if (n_kept) *n_kept = 0;
     if (!r) return fail(RASTER_E_INVAL, "result is NULL");
-    if (r->dims != 2) return fail(RASTER_E_INVAL, "per-tile point lists of a three-dimensional result");
     if (!n_kept) return fail(RASTER_E_INVAL, "n_kept is NULL");
-    raster_status st = check_points(d_points, n, dt);
+    raster_status st = check_points(d_points, n, dt, (uint32_t)r->dims);
     if (st != RASTER_OK) return st;
     if (n >= (int64_t)0xFFFFFFFFll) return fail(RASTER_E_INVAL, "more than 2^32 - 2 points in one call");
     if (!d_row_start || ((uintptr_t)d_row_start % 8) != 0)
@@ -1108,13 +1111,12 @@ raster_status raster_result_tile_points(raster_result* r, const void* d_points, 
         HIP_TRY(launch_zero_u64((uint64_t*)r->lt_err, 1, stream), "zero flag");
         HIP_TRY(launch_zero_u32(count, std::max<uint64_t>(t, 1), stream), "zero counts");
         HIP_TRY(launch_tile_points_count(d_points, n, (int)dt, r->scale, r->rt, r->rt_cap, row_of, rank, count, t,
-                                         partials, total, d_row_start, r->lt_err, stream),
+                                         partials, total, d_row_start, r->lt_err, stream, r->dims),
                 "tile points");
         HIP_TRY(hipMemcpyAsync(&h[0], total, sizeof h[0], hipMemcpyDeviceToHost, stream), "total copy");
         HIP_TRY(hipMemcpyAsync(&h[1], r->lt_err, sizeof h[1], hipMemcpyDeviceToHost, stream), "flag copy");
         HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
-        if (h[1] & kErrRange)
-            return fail(RASTER_E_RANGE, "a coordinate is not finite or its tile is outside +-(2^31 - 2)");
+        if (h[1] & kErrRange) return fail(RASTER_E_RANGE, "%s", range_message(r->dims));
         *n_kept = (int64_t)h[0];
         if ((int64_t)h[0] > cap)
             return fail(RASTER_E_INVAL, "index holds %lld entries, %lld points lie on kept tiles", (long long)cap,

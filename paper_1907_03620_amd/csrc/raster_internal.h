@@ -283,18 +283,20 @@ hipError_t launch_batch_count(const JobView& jv, const uint32_t* tile_prefix, Sl
 // a power of two >= 2t; filled here), then the label of every point's tile
 // (UINT64_MAX for none; range errors set kErrRange in *err).
 hipError_t launch_label_table(const int32_t* kx, const int32_t* ky, const uint64_t* label, uint64_t t,
-                              uint64_t* tab, uint64_t cap, bool rows, hipStream_t stream);
+                              uint64_t* tab, uint64_t cap, bool rows, hipStream_t stream,
+                              const int32_t* kz = nullptr);
 // Per-tile point lists: rows of the points and their ranks within the rows
 // (from the per-row counts), the row offsets (start[0..t]); then the scatter
 // of the point indices.
 hipError_t launch_tile_points_count(const void* pts, int64_t n, int dtype, double scale, const uint64_t* tab,
                                    uint64_t cap, uint32_t* row_of, uint32_t* rank, uint32_t* count, uint64_t t,
                                    uint32_t* partials, unsigned long long* total, uint64_t* start,
-                                   unsigned long long* err, hipStream_t stream);
+                                   unsigned long long* err, hipStream_t stream, int dims = 2);
 hipError_t launch_tile_points_scatter(const uint32_t* row_of, const uint32_t* rank, int64_t n,
                                       const uint64_t* start, uint64_t* out, hipStream_t stream);
 hipError_t launch_point_labels(const void* pts, int64_t n, int dtype, double scale, const uint64_t* tab,
-                               uint64_t cap, uint64_t* out, unsigned long long* err, hipStream_t stream);
+                               uint64_t cap, uint64_t* out, unsigned long long* err, hipStream_t stream,
+                               int dims = 2);
 
 // Distinct-tile sketch of one point set into hll (kHllReps replicas, not
 // zeroed here).

@@ -1972,11 +1972,15 @@ __global__ __launch_bounds__(256) void k_batch_hll(JobView jv, const uint32_t* t
 // point lists).  Every point is then projected again and its tile looked up.
 
 template <bool ROWS>
-__global__ void k_label_table(const int32_t* kx, const int32_t* ky, const uint64_t* label, uint64_t t,
-                              uint64_t* tab, uint64_t cap) {
+__global__ void k_label_table(const int32_t* kx, const int32_t* ky, const int32_t* kz, const uint64_t* label,
+                              uint64_t t, uint64_t* tab, uint64_t cap) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < t;
          i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t key = ((uint64_t)((uint32_t)kx[i] + 0x80000000u) << 32) | ((uint32_t)ky[i] + 0x80000000u);
+        // rows of a 3-D result (kz given) take the 3-D key
+        const uint64_t key =
+            kz ? ((uint64_t)(uint32_t)(kx[i] + (int32_t)kBias3) << 42) |
+                     ((uint64_t)(uint32_t)(ky[i] + (int32_t)kBias3) << 21) | (uint32_t)(kz[i] + (int32_t)kBias3)
+               : ((uint64_t)((uint32_t)kx[i] + 0x80000000u) << 32) | ((uint32_t)ky[i] + 0x80000000u);
         uint64_t pos = slot_hash(key) & (cap - 1);
         // the keys are distinct and the table is at most half full: a free
         // slot is always found
@@ -1987,8 +1991,8 @@ __global__ void k_label_table(const int32_t* kx, const int32_t* ky, const uint64
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_point_labels(const T* __restrict__ pts, int64_t n, double scale,
+template <typename P>
+__global__ __launch_bounds__(256) void k_point_labels(const P* __restrict__ pts, int64_t n, double scale,
                                                       const uint64_t* __restrict__ tab, uint64_t cap,
                                                       uint64_t* __restrict__ out, unsigned long long* err) {
     // One slot is {key, label}, 16-byte aligned, read by a single 16-byte load:
@@ -1999,16 +2003,17 @@ __global__ __launch_bounds__(256) void k_point_labels(const T* __restrict__ pts,
     bool bad = false;
     for (int64_t i0 = (int64_t)blockIdx.x * U * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * U * blockDim.x) {
         // loads of all items first (indices clamped, results masked)
-        double x[U], y[U];
+        double x[U], y[U], z[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) load_point(pts, min(i0 + (int64_t)u * blockDim.x + threadIdx.x, n - 1), x[u], y[u]);
+        for (int u = 0; u < U; ++u)
+            load_xyz(pts, min(i0 + (int64_t)u * blockDim.x + threadIdx.x, n - 1), x[u], y[u], z[u]);
         uint64_t key[U], pos[U];
         u64x2 cur[U];
         bool ok[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             key[u] = 0;
-            ok[u] = tile_key(x[u], y[u], scale, key[u]);
+            ok[u] = point_key<P>(x[u], y[u], z[u], scale, key[u]);
             pos[u] = slot_hash(key[u]) & (cap - 1);
             cur[u] = slots[pos[u]];  // first probes together; a bad key's probe is discarded
         }
@@ -2044,8 +2049,8 @@ __global__ __launch_bounds__(256) void k_point_labels(const T* __restrict__ pts,
 
 constexpr uint32_t kNoRow = 0xFFFFFFFFu;
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_point_rows(const T* __restrict__ pts, int64_t n, double scale,
+template <typename P>
+__global__ __launch_bounds__(256) void k_point_rows(const P* __restrict__ pts, int64_t n, double scale,
                                                     const uint64_t* __restrict__ tab, uint64_t cap,
                                                     uint32_t* __restrict__ row_of,
                                                     uint32_t* __restrict__ rank, uint32_t* count,
@@ -2055,16 +2060,17 @@ __global__ __launch_bounds__(256) void k_point_rows(const T* __restrict__ pts, i
     constexpr int U = 8;
     bool bad = false;
     for (int64_t i0 = (int64_t)blockIdx.x * U * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * U * blockDim.x) {
-        double x[U], y[U];
+        double x[U], y[U], z[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) load_point(pts, min(i0 + (int64_t)u * blockDim.x + threadIdx.x, n - 1), x[u], y[u]);
+        for (int u = 0; u < U; ++u)
+            load_xyz(pts, min(i0 + (int64_t)u * blockDim.x + threadIdx.x, n - 1), x[u], y[u], z[u]);
         uint64_t key[U], pos[U];
         u64x2 cur[U];
         bool ok[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             key[u] = 0;
-            ok[u] = tile_key(x[u], y[u], scale, key[u]);
+            ok[u] = point_key<P>(x[u], y[u], z[u], scale, key[u]);
             pos[u] = slot_hash(key[u]) & (cap - 1);
             cur[u] = slots[pos[u]];
         }
@@ -2562,26 +2568,32 @@ hipError_t launch_batch_binned(const JobView& jv, const uint32_t* tile_prefix, c
 }
 
 hipError_t launch_label_table(const int32_t* kx, const int32_t* ky, const uint64_t* label, uint64_t t,
-                              uint64_t* tab, uint64_t cap, bool rows, hipStream_t stream) {
+                              uint64_t* tab, uint64_t cap, bool rows, hipStream_t stream, const int32_t* kz) {
     hipLaunchKernelGGL(k_fill_words, dim3(grid_for(2 * cap, 256, kPersistBlocks)), dim3(256), 0, stream, tab,
                        2 * cap, kEmptyKey);
     if (t)
     {
         if (rows)
             hipLaunchKernelGGL(k_label_table<true>, dim3(grid_for(t, 256, kPersistBlocks)), dim3(256), 0, stream, kx,
-                               ky, label, t, tab, cap);
+                               ky, kz, label, t, tab, cap);
         else
             hipLaunchKernelGGL(k_label_table<false>, dim3(grid_for(t, 256, kPersistBlocks)), dim3(256), 0, stream, kx,
-                               ky, label, t, tab, cap);
+                               ky, kz, label, t, tab, cap);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_point_labels(const void* pts, int64_t n, int dtype, double scale, const uint64_t* tab,
-                               uint64_t cap, uint64_t* out, unsigned long long* err, hipStream_t stream) {
+                               uint64_t cap, uint64_t* out, unsigned long long* err, hipStream_t stream, int dims) {
     if (n <= 0) return hipSuccess;
     const unsigned grid = (unsigned)grid_for((uint64_t)n, 256 * 8, 8192);
-    if (dtype == 1)
+    if (dims == 3 && dtype == 1)
+        hipLaunchKernelGGL(k_point_labels<Pt3<float>>, dim3(grid), dim3(256), 0, stream,
+                           static_cast<const Pt3<float>*>(pts), n, scale, tab, cap, out, err);
+    else if (dims == 3)
+        hipLaunchKernelGGL(k_point_labels<Pt3<double>>, dim3(grid), dim3(256), 0, stream,
+                           static_cast<const Pt3<double>*>(pts), n, scale, tab, cap, out, err);
+    else if (dtype == 1)
         hipLaunchKernelGGL(k_point_labels<float>, dim3(grid), dim3(256), 0, stream, static_cast<const float*>(pts), n,
                            scale, tab, cap, out, err);
     else
@@ -2593,10 +2605,16 @@ hipError_t launch_point_labels(const void* pts, int64_t n, int dtype, double sca
 hipError_t launch_tile_points_count(const void* pts, int64_t n, int dtype, double scale, const uint64_t* tab,
                                    uint64_t cap, uint32_t* row_of, uint32_t* rank, uint32_t* count, uint64_t t,
                                    uint32_t* partials, unsigned long long* total, uint64_t* start,
-                                   unsigned long long* err, hipStream_t stream) {
+                                   unsigned long long* err, hipStream_t stream, int dims) {
     if (n > 0) {
         const unsigned grid = (unsigned)grid_for((uint64_t)n, 256 * 8, 8192);
-        if (dtype == 1)
+        if (dims == 3 && dtype == 1)
+            hipLaunchKernelGGL(k_point_rows<Pt3<float>>, dim3(grid), dim3(256), 0, stream,
+                               static_cast<const Pt3<float>*>(pts), n, scale, tab, cap, row_of, rank, count, err);
+        else if (dims == 3)
+            hipLaunchKernelGGL(k_point_rows<Pt3<double>>, dim3(grid), dim3(256), 0, stream,
+                               static_cast<const Pt3<double>*>(pts), n, scale, tab, cap, row_of, rank, count, err);
+        else if (dtype == 1)
             hipLaunchKernelGGL(k_point_rows<float>, dim3(grid), dim3(256), 0, stream, static_cast<const float*>(pts), n,
                                scale, tab, cap, row_of, rank, count, err);
         else

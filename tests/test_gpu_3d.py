@@ -144,6 +144,92 @@ def test_unsupported_combinations(raster, torch):
     assert e.value.code == raster.E_INVAL
     g = raster.cluster(pts, precision=1, tau=1, mu=1)
     assert g.dims == 3 and g.num_tiles == 1
-    with pytest.raises(raster.RasterError) as e:
+    # the points of a 3-D result's lookups have three coordinates
+    with pytest.raises(ValueError):
         g.point_labels(dev(np.array([[0.5, 0.5]]), torch))
-    assert e.value.code == raster.E_INVAL
+    with pytest.raises(ValueError):
+        g.tile_points(dev(np.array([[0.5, 0.5]]), torch))
+
+
+# ---- per-point labels (Section 4.1) and per-tile point lists (Section 3.4) in 3-D
+
+def _lists3(g, d):
+    start, index = g.tile_points(d)
+    start, index = start.cpu().numpy(), index.cpu().numpy()
+    kx, ky, cnt, _ = (a.cpu().numpy() for a in g.tensors())
+    kz = g.kz().cpu().numpy()
+    assert start.shape == (g.num_tiles + 1,) and start[0] == 0 and start[-1] == index.shape[0]
+    return {(int(kx[j]), int(ky[j]), int(kz[j])): np.sort(index[start[j]:start[j + 1]]) for j in range(g.num_tiles)}
+
+
+def _oracle_lists3(pts, o, **kw):
+    start, index = oracle.tile_points(pts, o, **kw)
+    return {(int(o.kx[j]), int(o.ky[j]), int(o.kz[j])): index[start[j]:start[j + 1]] for j in range(o.num_tiles)}
+
+
+def _check_lists(got, want, what):
+    assert got.keys() == want.keys(), what
+    bad = [t for t in want if not np.array_equal(got[t], want[t])]
+    assert not bad, f"{what}: {len(bad)} tiles differ, first {bad[:3]}"
+
+
+def test_point_labels_and_lists_tiny(raster, torch):
+    for seed in range(7100, 7140):
+        pts, p, tau, mu = _tiny3(seed)
+        o = oracle.cluster(pts, tau=tau, mu=mu, precision=p, dims=3)
+        d = dev(pts, torch)
+        g = raster.cluster(d, precision=p, tau=tau, mu=mu)
+        want = oracle.point_labels(pts, o, precision=p)
+        assert np.array_equal(g.point_labels(d).cpu().numpy(), want), seed
+        _check_lists(_lists3(g, d), _oracle_lists3(pts, o, precision=p), f"tiny 3-D seed {seed}")
+
+
+def test_point_labels_blobs_3M(raster, torch, mid3):
+    o = oracle.cluster(mid3, tau=4, mu=3, precision=1)
+    d = dev(mid3, torch)
+    g = raster.cluster(d, precision=1, tau=4, mu=3)
+    got = g.point_labels(d).cpu().numpy()
+    want = oracle.point_labels(mid3, o, precision=1)
+    _say(f"3-D labels 3M: {(want != -1).sum()} labelled")
+    assert (want != -1).sum() > 1_000_000 and (want == -1).sum() > 10_000
+    assert np.array_equal(got, want)
+    # labels agree with the rows' labels
+    _, _, _, _, lab = g.numpy()
+    assert set(np.unique(got[got != -1]).tolist()) == set(np.unique(lab.astype(np.int64)).tolist())
+    # points that were not clustered, in FP32: a prefix and shifted copies
+    other = (mid3[:400_000] + np.array([0.05, -0.05, 0.1])).astype(np.float32)
+    assert np.array_equal(g.point_labels(dev(other, torch)).cpu().numpy(),
+                          oracle.point_labels(other, o, precision=1))
+
+
+def test_tile_points_blobs_3M(raster, torch, mid3):
+    pts = mid3[:1_500_000]
+    o = oracle.cluster(pts, tau=4, mu=3, precision=1)
+    d = dev(pts, torch)
+    g = raster.cluster(d, precision=1, tau=4, mu=3)
+    _check_lists(_lists3(g, d), _oracle_lists3(pts, o, precision=1), "3-D tile points 1.5M")
+    start, _ = g.tile_points(d)
+    assert np.array_equal(np.diff(start.cpu().numpy()), g.tensors()[2].cpu().numpy().astype(np.int64))
+
+
+def test_stream_labels_and_range_errors(raster, torch, mid3):
+    chunks = [np.ascontiguousarray(c) for c in np.array_split(mid3[:900_000], 3)]
+    st = raster.Stream(tau=3, mu=3, precision=1, dims=3)
+    for c in chunks:
+        st.feed(dev(c, torch))
+    g = st.finish()
+    st.close()
+    o = oracle.cluster_chunks(chunks, tau=3, mu=3, precision=1, dims=3)
+    for k, c in enumerate(chunks):
+        assert np.array_equal(g.point_labels(dev(c, torch)).cpu().numpy(), oracle.point_labels(c, o, precision=1)), k
+    for bad in ([[0.5, 0.5, (B3 - 0.5) / 10]], [[np.nan, 0.5, 0.5]]):
+        pts = np.concatenate([chunks[0][:1000], np.array(bad)])
+        with pytest.raises(raster.RasterError) as e:
+            g.point_labels(dev(pts, torch))
+        assert e.value.code == raster.E_RANGE
+        with pytest.raises(raster.RasterError) as e:
+            g.tile_points(dev(pts, torch))
+        assert e.value.code == raster.E_RANGE
+    # a tile at the edge of the range is fine
+    edge = np.array([[0.05, 0.05, (B3 - 2.5) / 10]])
+    assert g.point_labels(dev(edge, torch)).cpu().numpy().tolist() == [-1]
