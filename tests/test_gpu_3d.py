@@ -122,6 +122,31 @@ def test_stream(raster, torch, mid3):
     _same3(g, oracle.cluster_chunks(chunks, tau=3, mu=3, precision=1, dims=3), "3-D stream")
 
 
+@pytest.mark.parametrize("mode,group,hint,chunks", [
+    (2, 1, 50_000, 3),     # binned, flushes of one million points into a table that must grow with keys in it
+    (2, 1, 0, 7),          # binned, uneven chunks straddling flushes
+    (1, 256, 20_000, 4),   # direct counting, growth by spills
+])
+def test_stream_growth_paths(raster, torch, mid3, mode, group, hint, chunks):
+    # growing a 3-D table rehashes its keys: home slots and partitions must
+    # follow the 3-D placement there too
+    pts = mid3[:2_500_000]
+    raster.set_tuning(mode=mode, group_mpoints=group)
+    try:
+        st = raster.Stream(tau=3, mu=3, precision=1, dims=3, tile_hint=hint)
+        for c in np.array_split(pts, chunks):
+            st.feed(dev(np.ascontiguousarray(c), torch))
+        g = st.finish()
+        st.close()
+    finally:
+        raster.set_tuning(None)
+    _say(f"3-D stream mode {mode} group {group} hint {hint}: {g.stats['grow_events']} growths, "
+         f"{g.stats['flushes']} flushes")
+    if hint:
+        assert g.stats["grow_events"] >= 1
+    _same3(g, oracle.cluster(pts, tau=3, mu=3, precision=1), f"3-D stream mode {mode} group {group} hint {hint}")
+
+
 def test_range_edges_and_errors(raster, torch):
     lim = B3 - 2
     tiles = [(lim, lim, lim), (lim - 1, lim, lim), (-lim, -lim, -lim), (-lim + 1, -lim + 1, -lim + 1),
