@@ -1612,7 +1612,7 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_part(const Slot* tab, Job
             uint64_t best_key = key;
 #pragma unroll 1
             for (uint32_t r = 0; r < rounds; ++r) {
-                const NbrRound& nr_ = grp.r[r];
+                const NbrRound& nr = grp.r[r];
                 uint64_t nk[4];
                 bool want[4];
                 if (!GENERAL) {
@@ -1631,9 +1631,9 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_part(const Slot* tab, Job
                 } else if (!D3) {
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const int64_t x = (int64_t)bx + nr_.dx[q];
-                        const int64_t y = (int64_t)by + nr_.dy[q];
-                        want[q] = q < (int)nr_.count && x >= 2 && x <= 0xFFFFFFFEll && y >= 2 && y <= 0xFFFFFFFEll;
+                        const int64_t x = (int64_t)bx + nr.dx[q];
+                        const int64_t y = (int64_t)by + nr.dy[q];
+                        want[q] = q < (int)nr.count && x >= 2 && x <= 0xFFFFFFFEll && y >= 2 && y <= 0xFFFFFFFEll;
                         nk[q] = want[q] ? (((uint64_t)(uint32_t)x << 32) | (uint32_t)y) : key;
                     }
                 } else {
@@ -1642,9 +1642,9 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_part(const Slot* tab, Job
                     const int64_t z0 = (int64_t)(key & kField3);
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const int64_t x = x0 + nr_.dx[q], y = y0 + nr_.dy[q], z = z0 + nr_.dz[q];
+                        const int64_t x = x0 + nr.dx[q], y = y0 + nr.dy[q], z = z0 + nr.dz[q];
                         const int64_t hi = (int64_t)kField3 - 1;
-                        want[q] = q < (int)nr_.count && x >= 2 && x <= hi && y >= 2 && y <= hi && z >= 2 && z <= hi;
+                        want[q] = q < (int)nr.count && x >= 2 && x <= hi && y >= 2 && y <= hi && z >= 2 && z <= hi;
                         nk[q] = want[q] ? (((uint64_t)x << 42) | ((uint64_t)y << 21) | (uint64_t)z) : key;
                     }
                 }
