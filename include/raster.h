@@ -75,7 +75,10 @@ typedef enum raster_status {
                              [0, 15], non-finite or non-positive scale        */
     RASTER_E_RANGE = -2,  /* a coordinate is NaN/Inf or its tile is out of range,
                              or more than 2^32 - 1 points went into one table */
-    RASTER_E_NOMEM = -3,  /* device allocation failed                          */
+    RASTER_E_NOMEM = -3,  /* device allocation failed, or a table would need
+                             more than 2^31 slots (about 1.29G distinct tiles
+                             at the default load factor; 0.97G in three
+                             dimensions, whose tables are kept emptier)       */
     RASTER_E_DEVICE = -4, /* a HIP call failed                                 */
     RASTER_E_STATE = -5,  /* streaming call in the wrong state                 */
     RASTER_E_BUDGET = -6  /* server: a single job exceeds the memory budget    */
