@@ -77,6 +77,16 @@ def test_tiny_corpus(raster, torch, metric, delta):
         _same3(g, o, f"tiny 3-D seed {seed} {metric} {delta}")
 
 
+@pytest.mark.parametrize("metric,delta", [("chebyshev", 4), ("manhattan", 8), ("chebyshev", 8)])
+def test_wide_neighbourhoods(raster, torch, metric, delta):
+    # many link groups (Chebyshev 8 in 3-D: 2456 backward offsets, 154 groups)
+    for seed in range(7200, 7206):
+        pts, p, tau, mu = _tiny3(seed)
+        o = oracle.cluster(pts, tau=tau, mu=mu, precision=p, metric=metric, delta=delta, dims=3)
+        g = raster.cluster(dev(pts, torch), precision=p, tau=tau, mu=mu, metric=metric, delta=delta)
+        _same3(g, o, f"tiny 3-D seed {seed} {metric} {delta}")
+
+
 def test_neighbour_counts_section_3_6(raster, torch):
     units = [(dx, dy, dz) for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1) if (dx, dy, dz) != (0, 0, 0)]
     for metric, want in (("chebyshev", 26), ("manhattan", 6)):
