@@ -817,7 +817,6 @@ raster_status TableRun::finish(raster_result** out) {
     single.job.mu = mu;
     single.job.dtype = 0;
     single.job.first_tile = 0;
-    single.job.d3 = dims == 3 ? 1u : 0u;
     single.dims.slots = cap;
     single.dims.njobs = 1;
     single.dims.tiles = 0;

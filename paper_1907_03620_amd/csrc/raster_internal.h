@@ -119,7 +119,6 @@ struct JobInfo {
     uint32_t cshift;      // binned batches: log2 partitions per coarse bucket
     uint32_t cap2;        // binned batches: keys per partition list of the job
     uint64_t bin2_base;   // binned batches: first key of the job's partition lists
-    uint32_t d3;          // 1: three-dimensional keys
 };
 
 // One round of the link pass for a neighbourhood other than the eight

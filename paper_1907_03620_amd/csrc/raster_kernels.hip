@@ -558,8 +558,9 @@ __device__ __forceinline__ uint32_t bucket_of(uint64_t key, uint32_t top_bits, u
 // Scatters this tile's valid keys into nb buckets: bucket b's keys are
 // appended at out[b * stride + cursor[b] ...].  A key past its bucket's
 // capacity (cap <= stride) goes straight into the table instead.  The bucket of a
-// key is bucket_of(key, top_bits, nb).  S.hist must be zero on entry (and a
+// key is bucket_of(key, top_bits, nb, D3).  S.hist must be zero on entry (and a
 // barrier passed); every thread of the workgroup calls.
+template <bool D3>
 __device__ void bin_tile(BinScratch& S, const uint64_t (&key)[BIN_ITEMS], const uint16_t (&bucket)[BIN_ITEMS],
                          uint32_t valid, uint32_t nb, uint32_t top_bits, uint64_t* out, uint64_t stride,
                          uint64_t cap, uint32_t* cursor, Slot* tab, const Geo& g, const SpillBuf& sp, unsigned long long* ctr,
@@ -608,7 +609,7 @@ __device__ void bin_tile(BinScratch& S, const uint64_t (&key)[BIN_ITEMS], const 
         uint64_t k = 0;
         if (q < total) {
             k = S.key[q];
-            const uint32_t b = bucket_of(k, top_bits, nb, g.d3);
+            const uint32_t b = bucket_of(k, top_bits, nb, D3);
             const uint64_t dst = (uint64_t)S.base[b] + (q - S.off[b]);
             if (dst < cap) {
                 out[(uint64_t)b * stride + dst] = k;
@@ -664,7 +665,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_points(const T* __restrict_
         if (i < n) {
             if (point_key<T>(x[j], y[j], z[j], scale, key[j])) {
                 valid |= 1u << j;
-                bucket[j] = (uint16_t)bucket_of(key[j], kCoarseLog2, kCoarse, g.d3);
+                bucket[j] = (uint16_t)bucket_of(key[j], kCoarseLog2, kCoarse, PtDims<T>::value == 3);
                 uint32_t reg, rank;
                 if (SKETCH && hll_sample(key[j], reg, rank)) atomicMax(&sk[reg], rank);
             } else {
@@ -675,7 +676,8 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_points(const T* __restrict_
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrRange);
     uint32_t fresh = 0;
     const uint32_t r = blockIdx.x % kBinRep;
-    bin_tile(S, key, bucket, valid, kCoarse, kCoarseLog2, bin1 + (uint64_t)r * kCoarse * cap1, cap1, cap1,
+    bin_tile<PtDims<T>::value == 3>(S, key, bucket, valid, kCoarse, kCoarseLog2, bin1 + (uint64_t)r * kCoarse * cap1,
+                                    cap1, cap1,
              cursor1 + r * kCoarse, tab, g, sp, ctr, fresh);
     add_fresh(ctr, fresh);
     if (SKETCH) {
@@ -692,6 +694,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_points(const T* __restrict_
 // flight at once then append to the lists of a few dozen coarse lists, whose
 // open partial lines stay in L2 until complete, while the replicas keep the
 // cursor lines they update apart.
+template <bool D3>
 __global__ __launch_bounds__(BIN_THREADS) void k_bin_keys(const uint64_t* __restrict__ bin1, uint64_t cap1,
                                                           const uint32_t* cursor1, uint32_t segs, uint64_t* bin2,
                                                           uint64_t cap2, uint32_t* cursor2, Slot* tab, const Geo g,
@@ -723,7 +726,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_keys(const uint64_t* __rest
         const uint64_t i = start + (uint64_t)j * BIN_THREADS + threadIdx.x;
         bucket[j] = 0;
         if (i < cnt) {
-            bucket[j] = (uint16_t)bucket_of(key[j], g.p_log2, nb, g.d3);
+            bucket[j] = (uint16_t)bucket_of(key[j], g.p_log2, nb, D3);
             valid |= 1u << j;
         }
     }
@@ -731,7 +734,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_keys(const uint64_t* __rest
     // partition lists are stored partition-major (a partition's replicas
     // side by side), their cursors replica-major
     const uint64_t first = (uint64_t)b1 << fine_log2;
-    bin_tile(S, key, bucket, valid, nb, g.p_log2, bin2 + (first * kBinRep + r) * cap2, kBinRep * cap2, cap2,
+    bin_tile<D3>(S, key, bucket, valid, nb, g.p_log2, bin2 + (first * kBinRep + r) * cap2, kBinRep * cap2, cap2,
              cursor2 + ((uint64_t)r << g.p_log2) + first, tab, g, sp, ctr,
              fresh);
     add_fresh(ctr, fresh);
@@ -825,10 +828,11 @@ __device__ __forceinline__ void aggregate_partition(const PartLists<NL>& L, Slot
     // a thread's positions only grow, so it walks the lists once: list li
     // covers positions [lo, hi) of the concatenation
     uint32_t li = 0, lo = 0, hi = L.size[0];
-    for (uint32_t q0 = 0; q0 < cnt; q0 += AGG_THREADS * AGG_BATCH) {
-        // addresses first (positions past the end clamped to the last key),
-        // then all loads unconditionally, then the masks: no load waits for
-        // another
+    constexpr uint32_t STEP = AGG_THREADS * AGG_BATCH;
+    // The keys of batch q0: addresses first (positions past the end clamped
+    // to the last key), then all loads unconditionally, so that no load waits
+    // for another.  Needs q0 < cnt.
+    auto fetch = [&](uint32_t q0, uint64_t (&k)[AGG_BATCH]) {
         const uint64_t* at[AGG_BATCH];
 #pragma unroll
         for (int u = 0; u < AGG_BATCH; ++u) {
@@ -840,9 +844,17 @@ __device__ __forceinline__ void aggregate_partition(const PartLists<NL>& L, Slot
             }
             at[u] = L.src + li * L.lstride + (q - lo);
         }
-        uint64_t k[AGG_BATCH];
 #pragma unroll
         for (int u = 0; u < AGG_BATCH; ++u) k[u] = __builtin_nontemporal_load(at[u]);
+    };
+    // software pipeline: the next batch's loads are in flight while this
+    // batch is added in LDS
+    uint64_t k[AGG_BATCH], next[AGG_BATCH];
+    if (cnt > 0) fetch(0, next);
+    for (uint32_t q0 = 0; q0 < cnt; q0 += STEP) {
+#pragma unroll
+        for (int u = 0; u < AGG_BATCH; ++u) k[u] = next[u];
+        if (q0 + STEP < cnt) fetch(q0 + STEP, next);  // uniform across the workgroup
 #pragma unroll
         for (int u = 0; u < AGG_BATCH; ++u)
             if (q0 + u * AGG_THREADS + threadIdx.x >= cnt) k[u] = kEmptyKey;
@@ -884,7 +896,7 @@ __device__ __forceinline__ void aggregate_partition(const PartLists<NL>& L, Slot
     }
 }
 
-__global__ __launch_bounds__(AGG_THREADS) void k_aggregate(const uint64_t* __restrict__ bin2, uint64_t cap2,
+__global__ __launch_bounds__(AGG_THREADS, 6) void k_aggregate(const uint64_t* __restrict__ bin2, uint64_t cap2,
                                                            const uint32_t* cursor2, Slot* tab, SpillBuf sp,
                                                            unsigned long long* ctr) {
     __shared__ uint64_t lkey[kPartSlots];
@@ -916,7 +928,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bbin_points(JobView jv, const u
     for (uint32_t t = tr.lo; t < tr.hi; ++t) {
         job = advance_job(tile_prefix, job, t);
         const JobInfo& J = jv.jobs[job];
-        const Geo g = make_geo(J.cap, J.d3 != 0);
+        const Geo g = make_geo(J.cap, false);  // batch jobs are two-dimensional
         const uint32_t top = g.p_log2 - J.cshift;  // coarse bits of the hash
         const uint32_t nb = 1u << top;
         for (uint32_t b = threadIdx.x; b < nb; b += BIN_THREADS) S.hist[b] = 0;
@@ -947,7 +959,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bbin_points(JobView jv, const u
             if (i < J.n) {
                 if (tile_key(x[j], y[j], J.scale, key[j])) {
                     valid |= 1u << j;
-                    bucket[j] = (uint16_t)bucket_of(key[j], top, nb, g.d3);
+                    bucket[j] = (uint16_t)bucket_of(key[j], top, nb, false);
                 } else {
                     bad = true;
                 }
@@ -956,7 +968,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bbin_points(JobView jv, const u
         unsigned long long* jc = jv.job_ctr + (uint64_t)job * kCounterWords;
         if (bad) atomicOr(&jc[C_ERROR], (unsigned long long)kErrRange);
         uint32_t fresh = 0;
-        bin_tile(S, key, bucket, valid, nb, top, bin1 + (uint64_t)J.cbase * cap1, cap1, cap1, cursor1 + J.cbase,
+        bin_tile<false>(S, key, bucket, valid, nb, top, bin1 + (uint64_t)J.cbase * cap1, cap1, cap1, cursor1 + J.cbase,
                  tab + J.slot_base, g, none, jc, fresh);
         __syncthreads();  // S is reused by the next tile
     }
@@ -981,7 +993,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bbin_keys(JobView jv, const uin
         if (start >= cnt) continue;  // uniform across the workgroup
         const uint32_t job = cjob[c];
         const JobInfo& J = jv.jobs[job];
-        const Geo g = make_geo(J.cap, J.d3 != 0);
+        const Geo g = make_geo(J.cap, false);  // batch jobs are two-dimensional
         const uint32_t nb = 1u << J.cshift;
         for (uint32_t b = threadIdx.x; b < nb; b += BIN_THREADS) S.hist[b] = 0;
         __syncthreads();
@@ -998,7 +1010,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bbin_keys(JobView jv, const uin
             const uint64_t i = start + (uint64_t)j * BIN_THREADS + threadIdx.x;
             bucket[j] = 0;
             if (i < cnt) {
-                bucket[j] = (uint16_t)bucket_of(key[j], g.p_log2, nb, g.d3);
+                bucket[j] = (uint16_t)bucket_of(key[j], g.p_log2, nb, false);
                 valid |= 1u << j;
             } else {
                 key[j] = 0;
@@ -1006,7 +1018,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bbin_keys(JobView jv, const uin
         }
         uint32_t fresh = 0;
         const uint64_t first = (uint64_t)(c - J.cbase) << J.cshift;  // job-local partition
-        bin_tile(S, key, bucket, valid, nb, g.p_log2, bin2 + J.bin2_base + first * J.cap2, J.cap2, J.cap2,
+        bin_tile<false>(S, key, bucket, valid, nb, g.p_log2, bin2 + J.bin2_base + first * J.cap2, J.cap2, J.cap2,
                  cursor2 + J.part_base + first, tab + J.slot_base, g, none,
                  jv.job_ctr + (uint64_t)job * kCounterWords, fresh);
         __syncthreads();
@@ -1463,7 +1475,7 @@ __global__ __launch_bounds__(SQUARE_THREADS) void k_square_part(Slot* tab, JobVi
     __shared__ uint32_t nlist;
     const JobInfo& J = jv.jobs[0];
     const uint32_t tau = J.tau;
-    const Geo g = make_geo(J.cap, J.d3 != 0);
+    const Geo g = make_geo(J.cap, false);  // the step is two-dimensional
     const uint32_t psize = (uint32_t)min<uint64_t>(J.cap, kPartSlots);
     const uint64_t parts = (J.cap + kPartSlots - 1) >> kPartLog2;
     for (uint64_t p = blockIdx.x; p < parts; p += gridDim.x) {
@@ -1562,7 +1574,7 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_part(const Slot* tab, Job
     bool bad = false;
     for (uint64_t p = blockIdx.x; p < parts; p += gridDim.x) {
         const JobInfo& J = jv.jobs[multi ? jv.part_job[p] : 0u];
-        const Geo g = make_geo(J.cap, J.d3 != 0);
+        const Geo g = make_geo(J.cap, D3);
         const uint32_t psize = (uint32_t)min<uint64_t>(J.cap, kPartSlots);  // a power of two
         const uint64_t base = p << kPartLog2;
         if (threadIdx.x == 0) nlist = 0;
@@ -2252,7 +2264,7 @@ __global__ void k_batch_count(JobView jv, const uint32_t* tile_prefix, Slot* tab
         const uint32_t job = job_of_tile(tile_prefix, njobs, t);
         const JobInfo& J = jv.jobs[job];
         Slot* jt = tab + J.slot_base;
-        const Geo g = make_geo(J.cap, J.d3 != 0);
+        const Geo g = make_geo(J.cap, false);  // batch jobs are two-dimensional
         unsigned long long* jc = jv.job_ctr + (uint64_t)job * kCounterWords;
         const int64_t base = (int64_t)(t - J.first_tile) * blockDim.x * ITEMS;
         if (L) {
@@ -2424,8 +2436,13 @@ hipError_t launch_bin_keys(const uint64_t* bin1, uint64_t cap1, const uint32_t* 
     const uint64_t lists2 = (uint64_t)kBinRep << g.p_log2;
     hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(lists2, 256, 4096)), dim3(256), 0, stream, cursor2, lists2);
     const uint32_t segs = (uint32_t)((cap1 + kBinTile - 1) / kBinTile);
-    hipLaunchKernelGGL(k_bin_keys, dim3(kBinRep * kCoarse * segs), dim3(BIN_THREADS), 0, stream, bin1, cap1, cursor1,
-                       segs, bin2, cap2, cursor2, tab, g, spill, ctr);
+    const dim3 grid(kBinRep * kCoarse * segs);
+    if (d3)
+        hipLaunchKernelGGL(k_bin_keys<true>, grid, dim3(BIN_THREADS), 0, stream, bin1, cap1, cursor1, segs, bin2, cap2,
+                           cursor2, tab, g, spill, ctr);
+    else
+        hipLaunchKernelGGL(k_bin_keys<false>, grid, dim3(BIN_THREADS), 0, stream, bin1, cap1, cursor1, segs, bin2, cap2,
+                           cursor2, tab, g, spill, ctr);
     return hipGetLastError();
 }
 

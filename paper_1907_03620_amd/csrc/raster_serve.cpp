@@ -413,7 +413,6 @@ raster_status BatchEngine::run(const raster_job* jobs, int32_t n_jobs, hipStream
         J.cshift = shifts[i];
         J.cap2 = cap2s[i];
         J.bin2_base = b2base[i];
-        J.d3 = 0;
         h_tile_prefix[i] = tp;
         tp += tiles[i];
         for (uint64_t p = bases[i] / kPartSlotsHost; p < (bases[i] + caps[i]) / kPartSlotsHost; ++p)
