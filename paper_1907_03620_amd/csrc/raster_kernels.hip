@@ -896,6 +896,9 @@ __device__ __forceinline__ void aggregate_partition(const PartLists<NL>& L, Slot
     }
 }
 
+// At least 6 waves per SIMD: the LDS slice allows three workgroups of 8 waves
+// per CU, and this holds the registers (the next batch's keys included) to
+// what three need.
 __global__ __launch_bounds__(AGG_THREADS, 6) void k_aggregate(const uint64_t* __restrict__ bin2, uint64_t cap2,
                                                            const uint32_t* cursor2, Slot* tab, SpillBuf sp,
                                                            unsigned long long* ctr) {
