@@ -651,7 +651,7 @@ raster_status TableRun::flush() {
                 "bin keys");
         if ((st = span_end(1, a)) != RASTER_OK) return st;
         if ((st = span_begin(2, &a)) != RASTER_OK) return st;
-        HIP_TRY(launch_aggregate(bin2, c2, cursor2, cursor1, tab, cap, sp, ctr, stream, dims == 3), "aggregate");
+        HIP_TRY(launch_aggregate(bin2, c2, cursor2, cursor1, tab, cap, sp, ctr, stream), "aggregate");
         if ((st = span_end(2, a)) != RASTER_OK) return st;
     }
     flushes += 1;

@@ -218,7 +218,7 @@ hipError_t launch_bin_keys(const uint64_t* bin1, uint64_t cap1, const uint32_t* 
 // Binned contraction, update: one workgroup per partition adds that
 // partition's keys to the table in LDS; then clears cursor1 for the next group.
 hipError_t launch_aggregate(const uint64_t* bin2, uint64_t cap2, const uint32_t* cursor2, uint32_t* cursor1,
-                            Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream, bool d3 = false);
+                            Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream);
 // Direct insertion of everything held in the coarse buckets (used when the
 // table is outside the binned geometry).  Clears cursor1.
 hipError_t launch_drain_bins(uint64_t* bin1, uint64_t cap1, uint32_t* cursor1, Slot* tab, uint64_t cap,

@@ -2450,8 +2450,8 @@ hipError_t launch_bin_keys(const uint64_t* bin1, uint64_t cap1, const uint32_t* 
 }
 
 hipError_t launch_aggregate(const uint64_t* bin2, uint64_t cap2, const uint32_t* cursor2, uint32_t* cursor1,
-                            Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream, bool d3) {
-    const Geo g = make_geo(cap, d3);
+                            Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream) {
+    const Geo g = make_geo(cap);  // the update only needs the partition count
     if (!binned_geometry(g)) return hipErrorInvalidValue;
     const uint64_t parts = 1ull << g.p_log2;
     hipLaunchKernelGGL(k_snapshot_keys, dim3(1), dim3(64), 0, stream, ctr);
