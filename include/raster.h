@@ -288,6 +288,14 @@ typedef struct raster_job {
  * alone.  On failure every outs[i] is NULL. */
 raster_status raster_cluster_batch(const raster_job* jobs, int32_t n_jobs, hipStream_t stream,
                                    raster_result** outs);
+/* Same, with a neighbourhood per job (Section 3.2): opts[i] (n_jobs entries,
+ * or NULL for the defaults everywhere) gives job i's metric and delta, and
+ * outs[i] is identical to raster_cluster_opts on that job alone.  Jobs that
+ * share a neighbourhood run as one fused batch; the groups run one after
+ * another, in order of first appearance.  E_INVAL for invalid options and for
+ * square_step = 1 or dims = 3, which batches do not take. */
+raster_status raster_cluster_batch_opts(const raster_job* jobs, const raster_options* opts, int32_t n_jobs,
+                                        hipStream_t stream, raster_result** outs);
 
 /* ---- served form ------------------------------------------------------------- */
 

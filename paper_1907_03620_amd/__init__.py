@@ -112,6 +112,7 @@ def load():
         "raster_stream_tiles": (st, [vp, vp, vp, i64, ctypes.POINTER(i64)]),
         "raster_stream_destroy": (None, [vp]),
         "raster_cluster_batch": (st, [ctypes.POINTER(_Job), i32, vp, pp]),
+        "raster_cluster_batch_opts": (st, [ctypes.POINTER(_Job), ctypes.POINTER(_Options), i32, vp, pp]),
         "raster_server_create": (st, [ctypes.c_size_t, i32, pp]),
         "raster_server_submit": (st, [vp, ctypes.POINTER(_Job), ctypes.POINTER(ctypes.c_uint64)]),
         "raster_server_wait": (st, [vp, ctypes.c_uint64, pp, ctypes.POINTER(dbl)]),
@@ -400,12 +401,24 @@ def _job(points, precision=None, tau=5, mu=4, scale=None) -> _Job:
 
 
 def cluster_batch(jobs, stream=None) -> list:
-    """jobs: iterable of dicts with keys points, tau, mu and precision or scale."""
+    """jobs: iterable of dicts with keys points, tau, mu and precision or
+    scale, and optionally metric and delta (the job's neighbourhood,
+    Section 3.2; jobs with other neighbourhoods than the default go through
+    raster_cluster_batch_opts)."""
     lib = load()
-    jobs = list(jobs)
+    jobs = [dict(j) for j in jobs]
+    nbhd = [(j.pop("metric", "chebyshev"), int(j.pop("delta", 1))) for j in jobs]
     arr = (_Job * max(1, len(jobs)))(*[_job(**j) for j in jobs])
     outs = (ctypes.c_void_p * max(1, len(jobs)))()
-    _check(lib.raster_cluster_batch(arr, len(jobs), _stream_handle(stream), outs), "raster_cluster_batch")
+    if all(m == "chebyshev" and d == 1 for m, d in nbhd):
+        _check(lib.raster_cluster_batch(arr, len(jobs), _stream_handle(stream), outs), "raster_cluster_batch")
+    else:
+        for m, _ in nbhd:
+            if m not in METRICS:
+                raise RasterError(E_INVAL, "cluster_batch", f"unknown metric {m!r}")
+        opts = (_Options * len(jobs))(*[_Options(METRICS[m], d, 0, 2) for m, d in nbhd])
+        _check(lib.raster_cluster_batch_opts(arr, opts, len(jobs), _stream_handle(stream), outs),
+               "raster_cluster_batch_opts")
     return [Result(ctypes.c_void_p(outs[i]), stream) for i in range(len(jobs))]
 
 

@@ -84,6 +84,13 @@ struct BatchEngine {
     hipGraphExec_t exec = nullptr;
     raster_tuning graph_tuning{};
     bool graph_valid = false;
+    // neighbourhood of the agglomeration (Section 3.2): that of the current
+    // run and that the captured graph was recorded with (its link launches
+    // carry the offsets as arguments)
+    uint32_t metric = RASTER_CHEBYSHEV, delta = 1;
+    uint32_t graph_metric = RASTER_CHEBYSHEV, graph_delta = 1;
+    std::vector<NbrRound> rounds;
+    uint64_t nbr_cap_words = 4;  // neighbour-list words per tile the buffer holds
     std::mutex mu;
     float last_us = 0.f;  // device time of the last replay
 
@@ -212,9 +219,10 @@ struct BatchEngine {
 
     // Grows every buffer to hold the given totals (with headroom), dropping
     // the captured graph when anything moves.
-    raster_status reserve(uint64_t slots, uint64_t s_need, uint32_t njobs, uint64_t ncoarse, uint64_t b1, uint64_t b2) {
+    raster_status reserve(uint64_t slots, uint64_t s_need, uint32_t njobs, uint64_t ncoarse, uint64_t b1, uint64_t b2,
+                          uint64_t words) {
         const bool ok = slots <= arena_cap && s_need <= s_cap && njobs <= jobs_cap && ncoarse <= coarse_cap &&
-                        b1 <= bin1_cap && b2 <= bin2_cap;
+                        b1 <= bin1_cap && b2 <= bin2_cap && words <= nbr_cap_words;
         if (ok) return RASTER_OK;
         (void)hipStreamSynchronize(bs);
         drop_graph();
@@ -228,6 +236,7 @@ struct BatchEngine {
         coarse_cap = std::max<uint64_t>((ncoarse + ncoarse / 4 + 9) & ~1ull, coarse_cap);
         bin1_cap = std::max<uint64_t>(b1 + b1 / 4, bin1_cap);
         bin2_cap = std::max<uint64_t>(b2 + b2 / 4, bin2_cap);
+        nbr_cap_words = std::max<uint64_t>(words, nbr_cap_words);
         auto take = [&](void** p, size_t bytes, const char* what) -> raster_status {
             hipError_t e = bufs.take(p, bytes);
             return e == hipSuccess ? RASTER_OK : hip_fail(e, what);
@@ -246,7 +255,7 @@ struct BatchEngine {
         TAKE(s_count, s_cap * sizeof(uint32_t), "S counts");
         TAKE(s_job, s_cap * sizeof(uint32_t), "S jobs");
         TAKE(parent, s_cap * sizeof(uint32_t), "parents");
-        TAKE(nbr, s_cap * 4 * sizeof(uint32_t), "neighbour lists");
+        TAKE(nbr, s_cap * nbr_cap_words * sizeof(uint32_t), "neighbour lists");
         TAKE(size, s_cap * sizeof(uint32_t), "sizes");
         TAKE(o_kx, s_cap * sizeof(int32_t), "rows");
         TAKE(o_ky, s_cap * sizeof(int32_t), "rows");
@@ -294,7 +303,9 @@ struct BatchEngine {
             if (e == hipSuccess) e = launch_batch_count(jv, tile_prefix, arena, kernel_tuning(tu), 4096, bs);
         }
         if (e == hipSuccess) e = launch_threshold(arena, jv, s_key, s_count, size, partials, ctr, bs);
-        if (e == hipSuccess) e = launch_agglomerate(arena, arena_cap, jv, s_key, parent, nbr, size, s_cap, ctr, bs);
+        if (e == hipSuccess)
+            e = launch_agglomerate(arena, arena_cap, jv, s_key, parent, nbr, size, s_cap, ctr, bs, rounds.data(),
+                                   (int)rounds.size());
         if (e == hipSuccess)
             e = launch_filter(jv, s_key, s_count, nbr, size, o_kx, o_ky, o_count, o_label, o_job, partials, ctr, bs);
         uint32_t* s_start = bounds;
@@ -308,15 +319,18 @@ struct BatchEngine {
     }
 
     raster_status run(const raster_job* jobs, int32_t n_jobs, hipStream_t user, raster_result** outs,
-                      std::vector<int32_t>* redo);
+                      std::vector<int32_t>* redo, uint32_t metric_ = RASTER_CHEBYSHEV, uint32_t delta_ = 1);
 
     static constexpr uint64_t kPartSlotsHost = 4096;
 };
 
 raster_status BatchEngine::run(const raster_job* jobs, int32_t n_jobs, hipStream_t user, raster_result** outs,
-                               std::vector<int32_t>* redo) {
+                               std::vector<int32_t>* redo, uint32_t metric_, uint32_t delta_) {
     raster_status st = init();
     if (st != RASTER_OK) return st;
+    metric = metric_;
+    delta = delta_;
+    rounds = neighbourhood_rounds(metric, delta);
     const raster_tuning tu = current_tuning();
     // every job's table sized from its estimated distinct tiles (a job that
     // still overflows is redone alone); the sketch reads the points in tiles
@@ -391,7 +405,7 @@ raster_status BatchEngine::run(const raster_job* jobs, int32_t n_jobs, hipStream
     cap1 = (cap1 + 255) / 256 * 256;
     const uint64_t s_need = std::max<uint64_t>(1, std::min<uint64_t>(slots, pts_total));
     st = reserve(slots, s_need, (uint32_t)n_jobs, binned ? ncoarse : 0, binned ? ncoarse * cap1 : 0,
-                 binned ? b2_total : 0);
+                 binned ? b2_total : 0, nbr_words((int)rounds.size()));
     if (st != RASTER_OK) return st;
     // host mirrors
     uint32_t tp = 0;
@@ -439,7 +453,8 @@ raster_status BatchEngine::run(const raster_job* jobs, int32_t n_jobs, hipStream
         e = hipMemcpyAsync(cjob, h_cjob, ncoarse * sizeof(uint32_t), hipMemcpyHostToDevice, bs);
     if (e != hipSuccess) return hip_fail(e, "batch upload");
     const bool same_tuning = graph_tuning.block == tu.block && graph_tuning.items == tu.items &&
-                             graph_tuning.preagg_slots == tu.preagg_slots && graph_binned == binned;
+                             graph_tuning.preagg_slots == tu.preagg_slots && graph_binned == binned &&
+                             graph_metric == metric && graph_delta == delta;
     if (!graph_valid || !same_tuning) {
         drop_graph();
         e = hipStreamBeginCapture(bs, hipStreamCaptureModeThreadLocal);
@@ -457,6 +472,8 @@ raster_status BatchEngine::run(const raster_job* jobs, int32_t n_jobs, hipStream
         graph_valid = true;
         graph_tuning = tu;
         graph_binned = binned;
+        graph_metric = metric;
+        graph_delta = delta;
     }
     hipEvent_t t0 = nullptr, t1 = nullptr;
     (void)hipEventCreate(&t0);
@@ -559,25 +576,62 @@ raster_status validate_job(const raster_job& j, int32_t i) {
     return st;
 }
 
-raster_status run_batch(BatchEngine& eng, const raster_job* jobs, int32_t n_jobs, hipStream_t stream,
-                        raster_result** outs) {
-    for (int32_t i = 0; i < n_jobs; ++i) outs[i] = nullptr;
-    for (int32_t i = 0; i < n_jobs; ++i) {
-        raster_status st = validate_job(jobs[i], i);
-        if (st != RASTER_OK) return st;
-    }
-    if (n_jobs == 0) return RASTER_OK;
+// One batch of jobs that share a neighbourhood; a job that spilled is redone
+// alone through the plain path with the same neighbourhood.
+static raster_status run_group(BatchEngine& eng, const raster_job* jobs, int32_t n_jobs, hipStream_t stream,
+                               raster_result** outs, uint32_t metric, uint32_t delta) {
     std::vector<int32_t> redo;
     raster_status st;
     {
         std::lock_guard<std::mutex> g(eng.mu);
-        st = eng.run(jobs, n_jobs, stream, outs, &redo);
+        st = eng.run(jobs, n_jobs, stream, outs, &redo, metric, delta);
     }
+    const raster_options o{(raster_metric)metric, delta, 0u, 2u};
     for (size_t k = 0; st == RASTER_OK && k < redo.size(); ++k) {
         const raster_job& j = jobs[redo[k]];
         double sc = j.scale;
         if (!(sc > 0.0)) scale_for_precision(j.precision, &sc);
-        st = raster_cluster_scaled(j.d_points, j.n, j.dt, sc, j.tau, j.mu, stream, &outs[redo[k]]);
+        st = raster_cluster_opts(j.d_points, j.n, j.dt, sc, j.tau, j.mu, &o, stream, &outs[redo[k]]);
+    }
+    return st;
+}
+
+raster_status run_batch(BatchEngine& eng, const raster_job* jobs, int32_t n_jobs, hipStream_t stream,
+                        raster_result** outs, const raster_options* opts) {
+    for (int32_t i = 0; i < n_jobs; ++i) outs[i] = nullptr;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        raster_status st = validate_job(jobs[i], i);
+        if (st == RASTER_OK && opts) st = check_options(&opts[i]);
+        if (st == RASTER_OK && opts && (opts[i].square_step || opts[i].dims == 3))
+            st = fail(RASTER_E_INVAL, "job %d: batches take neighbourhood options only (no 2x2 step, no 3-D)", i);
+        if (st != RASTER_OK) return st;
+    }
+    if (n_jobs == 0) return RASTER_OK;
+    // jobs grouped by neighbourhood, each group one batch, in first-seen order
+    std::vector<std::pair<uint32_t, uint32_t>> keys;
+    std::vector<std::vector<int32_t>> members;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        const std::pair<uint32_t, uint32_t> k =
+            opts ? std::make_pair((uint32_t)opts[i].metric, opts[i].delta) : std::make_pair(0u, 1u);
+        size_t g = 0;
+        while (g < keys.size() && keys[g] != k) ++g;
+        if (g == keys.size()) {
+            keys.push_back(k);
+            members.emplace_back();
+        }
+        members[g].push_back(i);
+    }
+    raster_status st = RASTER_OK;
+    if (keys.size() == 1) {
+        st = run_group(eng, jobs, n_jobs, stream, outs, keys[0].first, keys[0].second);
+    } else {
+        for (size_t g = 0; st == RASTER_OK && g < keys.size(); ++g) {
+            std::vector<raster_job> sub;
+            for (int32_t i : members[g]) sub.push_back(jobs[i]);
+            std::vector<raster_result*> res(sub.size(), nullptr);
+            st = run_group(eng, sub.data(), (int32_t)sub.size(), stream, res.data(), keys[g].first, keys[g].second);
+            for (size_t k = 0; k < sub.size(); ++k) outs[members[g][k]] = res[k];
+        }
     }
     if (st != RASTER_OK) {
         for (int32_t k = 0; k < n_jobs; ++k) {
@@ -593,7 +647,13 @@ raster_status run_batch(BatchEngine& eng, const raster_job* jobs, int32_t n_jobs
 extern "C" raster_status raster_cluster_batch(const raster_job* jobs, int32_t n_jobs, hipStream_t stream,
                                               raster_result** outs) {
     if (n_jobs < 0 || (n_jobs > 0 && (!jobs || !outs))) return fail(RASTER_E_INVAL, "bad batch arguments");
-    return run_batch(default_engine(), jobs, n_jobs, stream, outs);
+    return run_batch(default_engine(), jobs, n_jobs, stream, outs, nullptr);
+}
+
+extern "C" raster_status raster_cluster_batch_opts(const raster_job* jobs, const raster_options* opts, int32_t n_jobs,
+                                                   hipStream_t stream, raster_result** outs) {
+    if (n_jobs < 0 || (n_jobs > 0 && (!jobs || !outs))) return fail(RASTER_E_INVAL, "bad batch arguments");
+    return run_batch(default_engine(), jobs, n_jobs, stream, outs, opts);
 }
 
 // ---------------------------------------------------------------- server ---
@@ -691,14 +751,14 @@ static void server_worker(raster_server* s, int slot) {
             if (!(sc > 0.0)) scale_for_precision(j.precision, &sc);
             st = raster_cluster_scaled(j.d_points, j.n, j.dt, sc, j.tau, j.mu, eng.bs, &outs[0]);
         } else {
-            st = run_batch(eng, jv.data(), (int32_t)jv.size(), eng.bs, outs.data());
+            st = run_batch(eng, jv.data(), (int32_t)jv.size(), eng.bs, outs.data(), nullptr);
         }
         std::string err = st == RASTER_OK ? std::string() : g_last_error;
         if (st != RASTER_OK && batch.size() > 1) {
             // isolate the failing job(s): redo each job alone
             st = RASTER_OK;
             for (size_t i = 0; i < batch.size(); ++i) {
-                raster_status si = run_batch(eng, &jv[i], 1, eng.bs, &outs[i]);
+                raster_status si = run_batch(eng, &jv[i], 1, eng.bs, &outs[i], nullptr);
                 if (si != RASTER_OK) batch[i]->error = g_last_error;
                 batch[i]->status = si;
             }

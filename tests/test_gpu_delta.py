@@ -137,3 +137,78 @@ def test_invalid_neighbourhoods(raster, torch):
     out = ctypes.c_void_p()
     rc = lib.raster_cluster_delta(ctypes.c_void_p(pts.data_ptr()), 1, 2, 10.0, 1, 1, 2, 1, None, ctypes.byref(out))
     assert rc == raster.E_INVAL and not out.value
+
+
+# ---- neighbourhoods per job in a batch --------------------------------------
+
+BATCH_NBHDS = [("chebyshev", 1), ("manhattan", 2), ("chebyshev", 2), ("manhattan", 1), ("chebyshev", 3),
+               ("manhattan", 4)]
+
+
+def _batch(seed, n_jobs, torch, shift=0):
+    specs = synth.batch_jobs(seed=seed, n_jobs=n_jobs, size_scale=0.02)
+    jobs = [(sp, synth.job_points(sp), BATCH_NBHDS[(k + shift) % len(BATCH_NBHDS)]) for k, sp in enumerate(specs)]
+    args = [dict(points=dev(p, torch), precision=sp.precision, tau=sp.tau, mu=sp.mu, metric=m, delta=d)
+            for sp, p, (m, d) in jobs]
+    return jobs, args
+
+
+def test_batch_neighbourhood_per_job(raster, torch):
+    # jobs of six neighbourhoods in one call: each group is one fused batch;
+    # every job equals the oracle and the same job clustered alone
+    for seed, n_jobs, shift in ((11, 14, 0), (12, 9, 3), (13, 6, 1)):
+        jobs, args = _batch(seed, n_jobs, torch, shift)
+        res = raster.cluster_batch(args)
+        _say(f"batch of {n_jobs} jobs over {len({nb for _, _, nb in jobs})} neighbourhoods")
+        for k, ((sp, p, (m, d)), a, g) in enumerate(zip(jobs, args, res)):
+            o = oracle.cluster(p, tau=sp.tau, mu=sp.mu, precision=sp.precision, metric=m, delta=d)
+            assert_same(g, o, f"batch seed {seed} job {k} {m} {d}")
+            alone = raster.cluster(a["points"], precision=sp.precision, tau=sp.tau, mu=sp.mu, metric=m, delta=d)
+            assert alone.num_clusters == g.num_clusters and alone.num_tiles == g.num_tiles
+    # a default batch afterwards still takes the fixed neighbourhood
+    specs = synth.batch_jobs(seed=14, n_jobs=5, size_scale=0.02)
+    pts = [synth.job_points(sp) for sp in specs]
+    res = raster.cluster_batch([dict(points=dev(p, torch), precision=sp.precision, tau=sp.tau, mu=sp.mu)
+                                for sp, p in zip(specs, pts)])
+    for k, (sp, p, g) in enumerate(zip(specs, pts, res)):
+        assert_same(g, oracle.cluster(p, tau=sp.tau, mu=sp.mu, precision=sp.precision), f"default batch job {k}")
+
+
+def test_batch_options_rejected(raster, torch):
+    import ctypes
+    lib = raster.load()
+    pts = dev(np.array([[0.5, 0.5]] * 3), torch)
+    job = raster._job(pts, 1, 1, 1)
+    arr = (raster._Job * 1)(job)
+    outs = (ctypes.c_void_p * 1)()
+    for o in (raster._Options(0, 1, 1, 0), raster._Options(0, 1, 0, 3), raster._Options(0, 0, 0, 0),
+              raster._Options(2, 1, 0, 0), raster._Options(1, 9, 0, 0)):
+        opts = (raster._Options * 1)(o)
+        assert lib.raster_cluster_batch_opts(arr, opts, 1, None, outs) == raster.E_INVAL and not outs[0]
+    # NULL options are the defaults
+    assert lib.raster_cluster_batch_opts(arr, None, 1, None, outs) == 0 and outs[0]
+    lib.raster_result_free(outs[0])
+    with pytest.raises(raster.RasterError):
+        raster.cluster_batch([dict(points=pts, precision=1, tau=1, mu=1, metric="euclid", delta=1)])
+
+
+def test_batch_neighbourhoods_with_noise_job(raster, torch):
+    # a uniform-noise job (nearly every point its own tile) beside clustered
+    # ones, under other neighbourhoods, on both counting paths
+    rng = np.random.default_rng(9)
+    noise = rng.uniform(0.0, 1000.0, size=(400_000, 2))
+    small = synth.plain_small(1)[:50_000]
+    d1, d2 = dev(noise, torch), dev(small, torch)
+    for mode in (0, 1):
+        raster.set_tuning(mode=mode)
+        try:
+            res = raster.cluster_batch([dict(points=d1, precision=2, tau=1, mu=2, metric="manhattan", delta=2),
+                                        dict(points=d2, precision=1, tau=5, mu=4, metric="chebyshev", delta=2),
+                                        dict(points=d2, precision=1, tau=5, mu=4)])
+        finally:
+            raster.set_tuning(None)
+        assert_same(res[0], oracle.cluster(noise, tau=1, mu=2, precision=2, metric="manhattan", delta=2),
+                    f"noise job, manhattan 2, mode {mode}")
+        assert_same(res[1], oracle.cluster(small, tau=5, mu=4, precision=1, metric="chebyshev", delta=2),
+                    f"clustered job, chebyshev 2, mode {mode}")
+        assert_same(res[2], oracle.cluster(small, tau=5, mu=4, precision=1), f"clustered job, default, mode {mode}")
