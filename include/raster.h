@@ -307,6 +307,12 @@ raster_status raster_server_create(size_t budget_bytes, int32_t max_slots, raste
 /* Queue a job.  Its points are borrowed until raster_server_wait returns it.
  * Returns RASTER_E_BUDGET for a job that cannot fit the budget even alone. */
 raster_status raster_server_submit(raster_server* srv, const raster_job* job, uint64_t* ticket);
+/* Same, with the job's neighbourhood (Section 3.2; NULL: the defaults): its
+ * result is identical to raster_cluster_opts on the job alone.  Jobs that
+ * share a batch are grouped by neighbourhood as in raster_cluster_batch_opts.
+ * E_INVAL for invalid options and for square_step = 1 or dims = 3. */
+raster_status raster_server_submit_opts(raster_server* srv, const raster_job* job, const raster_options* opts,
+                                        uint64_t* ticket);
 /* Block until the job behind ticket is done; *latency_s receives submit-to-
  * completion wall time.  Each ticket may be waited on once. */
 raster_status raster_server_wait(raster_server* srv, uint64_t ticket, raster_result** out,

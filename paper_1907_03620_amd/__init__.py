@@ -115,6 +115,8 @@ def load():
         "raster_cluster_batch_opts": (st, [ctypes.POINTER(_Job), ctypes.POINTER(_Options), i32, vp, pp]),
         "raster_server_create": (st, [ctypes.c_size_t, i32, pp]),
         "raster_server_submit": (st, [vp, ctypes.POINTER(_Job), ctypes.POINTER(ctypes.c_uint64)]),
+        "raster_server_submit_opts": (st, [vp, ctypes.POINTER(_Job), ctypes.POINTER(_Options),
+                                           ctypes.POINTER(ctypes.c_uint64)]),
         "raster_server_wait": (st, [vp, ctypes.c_uint64, pp, ctypes.POINTER(dbl)]),
         "raster_server_destroy": (None, [vp]),
         "raster_set_tuning": (st, [ctypes.POINTER(_Tuning)]),
@@ -432,10 +434,16 @@ class Server:
         _check(self._lib.raster_server_create(int(budget_bytes), int(max_slots), ctypes.byref(self._h)),
                "raster_server_create")
 
-    def submit(self, points, tau: int, mu: int, precision: int | None = None, scale: float | None = None) -> int:
+    def submit(self, points, tau: int, mu: int, precision: int | None = None, scale: float | None = None,
+               metric: str = "chebyshev", delta: int = 1) -> int:
         job = _job(points, precision, tau, mu, scale)
         t = ctypes.c_uint64()
-        _check(self._lib.raster_server_submit(self._h, ctypes.byref(job), ctypes.byref(t)), "raster_server_submit")
+        opts = _options(metric, delta, False)
+        if opts is None:
+            _check(self._lib.raster_server_submit(self._h, ctypes.byref(job), ctypes.byref(t)), "raster_server_submit")
+        else:
+            _check(self._lib.raster_server_submit_opts(self._h, ctypes.byref(job), ctypes.byref(opts), ctypes.byref(t)),
+                   "raster_server_submit_opts")
         self._keep[t.value] = points
         return t.value
 

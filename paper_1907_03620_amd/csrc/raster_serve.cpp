@@ -668,6 +668,7 @@ extern "C" raster_status raster_cluster_batch_opts(const raster_job* jobs, const
 struct ServerJob {
     uint64_t ticket = 0;
     raster_job job{};
+    raster_options opts{RASTER_CHEBYSHEV, 1u, 0u, 2u};  // the job's neighbourhood
     size_t bytes = 0;
     std::chrono::steady_clock::time_point submitted;
     bool done = false;
@@ -740,8 +741,12 @@ static void server_worker(raster_server* s, int slot) {
         }
         s->cv_work.notify_all();  // another worker may take what is left
         std::vector<raster_job> jv(batch.size());
+        std::vector<raster_options> ov(batch.size());
         std::vector<raster_result*> outs(batch.size(), nullptr);
-        for (size_t i = 0; i < batch.size(); ++i) jv[i] = batch[i]->job;
+        for (size_t i = 0; i < batch.size(); ++i) {
+            jv[i] = batch[i]->job;
+            ov[i] = batch[i]->opts;
+        }
         raster_status st = RASTER_OK;
         (void)eng.init();
         if (batch.size() == 1) {
@@ -749,16 +754,16 @@ static void server_worker(raster_server* s, int slot) {
             const raster_job& j = jv[0];
             double sc = j.scale;
             if (!(sc > 0.0)) scale_for_precision(j.precision, &sc);
-            st = raster_cluster_scaled(j.d_points, j.n, j.dt, sc, j.tau, j.mu, eng.bs, &outs[0]);
+            st = raster_cluster_opts(j.d_points, j.n, j.dt, sc, j.tau, j.mu, &ov[0], eng.bs, &outs[0]);
         } else {
-            st = run_batch(eng, jv.data(), (int32_t)jv.size(), eng.bs, outs.data(), nullptr);
+            st = run_batch(eng, jv.data(), (int32_t)jv.size(), eng.bs, outs.data(), ov.data());
         }
         std::string err = st == RASTER_OK ? std::string() : g_last_error;
         if (st != RASTER_OK && batch.size() > 1) {
             // isolate the failing job(s): redo each job alone
             st = RASTER_OK;
             for (size_t i = 0; i < batch.size(); ++i) {
-                raster_status si = run_batch(eng, &jv[i], 1, eng.bs, &outs[i], nullptr);
+                raster_status si = run_batch(eng, &jv[i], 1, eng.bs, &outs[i], &ov[i]);
                 if (si != RASTER_OK) batch[i]->error = g_last_error;
                 batch[i]->status = si;
             }
@@ -811,8 +816,16 @@ extern "C" raster_status raster_server_create(size_t budget_bytes, int32_t max_s
 }
 
 extern "C" raster_status raster_server_submit(raster_server* s, const raster_job* job, uint64_t* ticket) {
+    return raster_server_submit_opts(s, job, nullptr, ticket);
+}
+
+extern "C" raster_status raster_server_submit_opts(raster_server* s, const raster_job* job,
+                                                   const raster_options* opts, uint64_t* ticket) {
     if (!s || !job || !ticket) return fail(RASTER_E_INVAL, "NULL argument");
     raster_status st = validate_job(*job, 0);
+    if (st == RASTER_OK) st = check_options(opts);
+    if (st == RASTER_OK && opts && (opts->square_step || opts->dims == 3))
+        st = fail(RASTER_E_INVAL, "server jobs take neighbourhood options only (no 2x2 step, no 3-D)");
     if (st != RASTER_OK) return st;
     const size_t bytes = job_bytes(*job);
     if (bytes > s->budget)
@@ -820,6 +833,7 @@ extern "C" raster_status raster_server_submit(raster_server* s, const raster_job
                     s->budget);
     ServerJob* j = new ServerJob();
     j->job = *job;
+    if (opts) j->opts = raster_options{opts->metric, opts->delta, 0u, 2u};
     j->bytes = bytes;
     j->submitted = std::chrono::steady_clock::now();
     {

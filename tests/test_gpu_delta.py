@@ -212,3 +212,27 @@ def test_batch_neighbourhoods_with_noise_job(raster, torch):
         assert_same(res[1], oracle.cluster(small, tau=5, mu=4, precision=1, metric="chebyshev", delta=2),
                     f"clustered job, chebyshev 2, mode {mode}")
         assert_same(res[2], oracle.cluster(small, tau=5, mu=4, precision=1), f"clustered job, default, mode {mode}")
+
+
+def test_server_neighbourhood_per_job(raster, torch):
+    # jobs of several neighbourhoods submitted together: the server fuses what
+    # has arrived, grouped by neighbourhood, and every job equals the oracle
+    jobs, args = _batch(21, 12, torch)
+    srv = raster.Server(budget_bytes=8 << 30, max_slots=3)
+    try:
+        tickets = [srv.submit(a["points"], a["tau"], a["mu"], precision=a["precision"], metric=a["metric"],
+                              delta=a["delta"]) for a in args]
+        for k, (t, (sp, p, (m, d))) in enumerate(zip(tickets, jobs)):
+            g, lat = srv.wait(t)
+            assert lat >= 0.0
+            assert_same(g, oracle.cluster(p, tau=sp.tau, mu=sp.mu, precision=sp.precision, metric=m, delta=d),
+                        f"served job {k} {m} {d}")
+        import ctypes
+        lib = raster.load()
+        job = raster._job(args[0]["points"], 1, 1, 1)
+        t = ctypes.c_uint64()
+        for o in (raster._Options(0, 1, 1, 0), raster._Options(0, 1, 0, 3), raster._Options(1, 0, 0, 0)):
+            assert lib.raster_server_submit_opts(srv._h, ctypes.byref(job), ctypes.byref(o),
+                                                 ctypes.byref(t)) == raster.E_INVAL
+    finally:
+        srv.close()
