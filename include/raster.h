@@ -288,12 +288,12 @@ typedef struct raster_job {
  * alone.  On failure every outs[i] is NULL. */
 raster_status raster_cluster_batch(const raster_job* jobs, int32_t n_jobs, hipStream_t stream,
                                    raster_result** outs);
-/* Same, with a neighbourhood per job (Section 3.2): opts[i] (n_jobs entries,
- * or NULL for the defaults everywhere) gives job i's metric and delta, and
+/* Same, with options per job: opts[i] (n_jobs entries, or NULL for the
+ * defaults everywhere) gives job i's metric, delta and square_step, and
  * outs[i] is identical to raster_cluster_opts on that job alone.  Jobs that
- * share a neighbourhood run as one fused batch; the groups run one after
+ * share their options run as one fused batch; the groups run one after
  * another, in order of first appearance.  E_INVAL for invalid options and for
- * square_step = 1 or dims = 3, which batches do not take. */
+ * dims = 3 (batches take two-dimensional points). */
 raster_status raster_cluster_batch_opts(const raster_job* jobs, const raster_options* opts, int32_t n_jobs,
                                         hipStream_t stream, raster_result** outs);
 
@@ -307,10 +307,10 @@ raster_status raster_server_create(size_t budget_bytes, int32_t max_slots, raste
 /* Queue a job.  Its points are borrowed until raster_server_wait returns it.
  * Returns RASTER_E_BUDGET for a job that cannot fit the budget even alone. */
 raster_status raster_server_submit(raster_server* srv, const raster_job* job, uint64_t* ticket);
-/* Same, with the job's neighbourhood (Section 3.2; NULL: the defaults): its
- * result is identical to raster_cluster_opts on the job alone.  Jobs that
- * share a batch are grouped by neighbourhood as in raster_cluster_batch_opts.
- * E_INVAL for invalid options and for square_step = 1 or dims = 3. */
+/* Same, with the job's options (metric, delta, square_step; NULL: the
+ * defaults): its result is identical to raster_cluster_opts on the job alone.
+ * Jobs that share a batch are grouped by options as in
+ * raster_cluster_batch_opts.  E_INVAL for invalid options and for dims = 3. */
 raster_status raster_server_submit_opts(raster_server* srv, const raster_job* job, const raster_options* opts,
                                         uint64_t* ticket);
 /* Block until the job behind ticket is done; *latency_s receives submit-to-

@@ -404,21 +404,21 @@ def _job(points, precision=None, tau=5, mu=4, scale=None) -> _Job:
 
 def cluster_batch(jobs, stream=None) -> list:
     """jobs: iterable of dicts with keys points, tau, mu and precision or
-    scale, and optionally metric and delta (the job's neighbourhood,
-    Section 3.2; jobs with other neighbourhoods than the default go through
-    raster_cluster_batch_opts)."""
+    scale, and optionally metric, delta (the job's neighbourhood, Section 3.2)
+    and square (the 2x2 post-step of Section 3.6); jobs with other options
+    than the defaults go through raster_cluster_batch_opts."""
     lib = load()
     jobs = [dict(j) for j in jobs]
-    nbhd = [(j.pop("metric", "chebyshev"), int(j.pop("delta", 1))) for j in jobs]
+    var = [(j.pop("metric", "chebyshev"), int(j.pop("delta", 1)), bool(j.pop("square", False))) for j in jobs]
     arr = (_Job * max(1, len(jobs)))(*[_job(**j) for j in jobs])
     outs = (ctypes.c_void_p * max(1, len(jobs)))()
-    if all(m == "chebyshev" and d == 1 for m, d in nbhd):
+    if all(m == "chebyshev" and d == 1 and not q for m, d, q in var):
         _check(lib.raster_cluster_batch(arr, len(jobs), _stream_handle(stream), outs), "raster_cluster_batch")
     else:
-        for m, _ in nbhd:
+        for m, _, _ in var:
             if m not in METRICS:
                 raise RasterError(E_INVAL, "cluster_batch", f"unknown metric {m!r}")
-        opts = (_Options * len(jobs))(*[_Options(METRICS[m], d, 0, 2) for m, d in nbhd])
+        opts = (_Options * len(jobs))(*[_Options(METRICS[m], d, int(q), 2) for m, d, q in var])
         _check(lib.raster_cluster_batch_opts(arr, opts, len(jobs), _stream_handle(stream), outs),
                "raster_cluster_batch_opts")
     return [Result(ctypes.c_void_p(outs[i]), stream) for i in range(len(jobs))]
@@ -435,10 +435,10 @@ class Server:
                "raster_server_create")
 
     def submit(self, points, tau: int, mu: int, precision: int | None = None, scale: float | None = None,
-               metric: str = "chebyshev", delta: int = 1) -> int:
+               metric: str = "chebyshev", delta: int = 1, square: bool = False) -> int:
         job = _job(points, precision, tau, mu, scale)
         t = ctypes.c_uint64()
-        opts = _options(metric, delta, False)
+        opts = _options(metric, delta, square)
         if opts is None:
             _check(self._lib.raster_server_submit(self._h, ctypes.byref(job), ctypes.byref(t)), "raster_server_submit")
         else:

@@ -1468,7 +1468,8 @@ __device__ __forceinline__ void uf_unite(uint32_t* parent, const uint64_t* key, 
 // slice's keys and counts in LDS; the counts of the eight surrounding tiles are
 // read there when they share the partition, else from the device table.  Only
 // counts are read, and only aux is written, so the order of the partitions
-// does not matter.  Single job.
+// does not matter.  In a batch each partition belongs to the job part_job
+// names, whose table starts at its slot_base.
 constexpr int SQUARE_THREADS = 512;
 
 __global__ __launch_bounds__(SQUARE_THREADS) void k_square_part(Slot* tab, JobView jv) {
@@ -1476,17 +1477,22 @@ __global__ __launch_bounds__(SQUARE_THREADS) void k_square_part(Slot* tab, JobVi
     __shared__ uint32_t lcnt[kPartSlots];
     __shared__ uint16_t list[kPartSlots];
     __shared__ uint32_t nlist;
-    const JobInfo& J = jv.jobs[0];
-    const uint32_t tau = J.tau;
-    const Geo g = make_geo(J.cap, false);  // the step is two-dimensional
-    const uint32_t psize = (uint32_t)min<uint64_t>(J.cap, kPartSlots);
-    const uint64_t parts = (J.cap + kPartSlots - 1) >> kPartLog2;
+    const bool multi = jv.part_job != nullptr;
+    const uint64_t parts = multi ? jv.dims->slots >> kPartLog2 : (jv.jobs[0].cap + kPartSlots - 1) >> kPartLog2;
     for (uint64_t p = blockIdx.x; p < parts; p += gridDim.x) {
-        const uint64_t base = p << kPartLog2;
+        // the partition's job: its table starts at slot_base (a whole number
+        // of partitions), so job-local partition jp holds slots base.. of it
+        const JobInfo& J = jv.jobs[multi ? jv.part_job[p] : 0u];
+        const uint32_t tau = J.tau;
+        const Geo g = make_geo(J.cap, false);  // the step is two-dimensional
+        const uint32_t psize = (uint32_t)min<uint64_t>(J.cap, kPartSlots);
+        Slot* jt = tab + J.slot_base;
+        const uint64_t jp = p - (J.slot_base >> kPartLog2);
+        const uint64_t base = jp << kPartLog2;
         if (threadIdx.x == 0) nlist = 0;
         __syncthreads();
         for (uint32_t u = threadIdx.x; u < psize; u += SQUARE_THREADS) {
-            const Slot v = tab[base + u];
+            const Slot v = jt[base + u];
             lkey[u] = v.key;
             lcnt[u] = v.count;
         }
@@ -1518,7 +1524,7 @@ __global__ __launch_bounds__(SQUARE_THREADS) void k_square_part(Slot* tab, JobVi
                     } else if (x >= 2 && x <= 0xFFFFFFFEll && y >= 2 && y <= 0xFFFFFFFEll) {
                         const uint64_t nk = ((uint64_t)(uint32_t)x << 32) | (uint32_t)y;
                         const uint64_t pos = home_slot(nk, g);
-                        if ((pos >> kPartLog2) == p) {
+                        if ((pos >> kPartLog2) == jp) {
                             uint32_t lp = (uint32_t)(pos - base);
                             for (uint32_t step = 0; step < kMaxProbe; ++step) {
                                 const uint64_t cur = lkey[lp];
@@ -1530,8 +1536,8 @@ __global__ __launch_bounds__(SQUARE_THREADS) void k_square_part(Slot* tab, JobVi
                                 lp = (lp + 1) & (psize - 1);
                             }
                         } else {
-                            const uint64_t at = table_find(tab, g, nk);
-                            if (at != ~0ull) n_cnt = tab[at].count;
+                            const uint64_t at = table_find(jt, g, nk);
+                            if (at != ~0ull) n_cnt = jt[at].count;
                         }
                     }
                     c[dx + 1][dy + 1] = n_cnt;
@@ -1542,7 +1548,7 @@ __global__ __launch_bounds__(SQUARE_THREADS) void k_square_part(Slot* tab, JobVi
 #pragma unroll
                 for (int b = 0; b <= 1; ++b)
                     keep |= c[a][b] + c[a + 1][b] + c[a][b + 1] + c[a + 1][b + 1] >= (uint64_t)tau;
-            if (keep) tab[base + u].aux = kSquareKeep;
+            if (keep) jt[base + u].aux = kSquareKeep;
         }
         __syncthreads();  // the slice is overwritten by the next partition
     }

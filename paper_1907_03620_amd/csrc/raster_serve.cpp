@@ -89,6 +89,7 @@ struct BatchEngine {
     // carry the offsets as arguments)
     uint32_t metric = RASTER_CHEBYSHEV, delta = 1;
     uint32_t graph_metric = RASTER_CHEBYSHEV, graph_delta = 1;
+    bool square = false, graph_square = false;  // the 2x2 post-step (Section 3.6)
     std::vector<NbrRound> rounds;
     uint64_t nbr_cap_words = 4;  // neighbour-list words per tile the buffer holds
     std::mutex mu;
@@ -302,7 +303,8 @@ struct BatchEngine {
         } else {
             if (e == hipSuccess) e = launch_batch_count(jv, tile_prefix, arena, kernel_tuning(tu), 4096, bs);
         }
-        if (e == hipSuccess) e = launch_threshold(arena, jv, s_key, s_count, size, partials, ctr, bs);
+        if (e == hipSuccess)
+            e = launch_threshold(arena, jv, s_key, s_count, size, partials, ctr, bs, square ? arena_cap : 0);
         if (e == hipSuccess)
             e = launch_agglomerate(arena, arena_cap, jv, s_key, parent, nbr, size, s_cap, ctr, bs, rounds.data(),
                                    (int)rounds.size());
@@ -319,17 +321,19 @@ struct BatchEngine {
     }
 
     raster_status run(const raster_job* jobs, int32_t n_jobs, hipStream_t user, raster_result** outs,
-                      std::vector<int32_t>* redo, uint32_t metric_ = RASTER_CHEBYSHEV, uint32_t delta_ = 1);
+                      std::vector<int32_t>* redo, uint32_t metric_ = RASTER_CHEBYSHEV, uint32_t delta_ = 1,
+                      bool square_ = false);
 
     static constexpr uint64_t kPartSlotsHost = 4096;
 };
 
 raster_status BatchEngine::run(const raster_job* jobs, int32_t n_jobs, hipStream_t user, raster_result** outs,
-                               std::vector<int32_t>* redo, uint32_t metric_, uint32_t delta_) {
+                               std::vector<int32_t>* redo, uint32_t metric_, uint32_t delta_, bool square_) {
     raster_status st = init();
     if (st != RASTER_OK) return st;
     metric = metric_;
     delta = delta_;
+    square = square_;
     rounds = neighbourhood_rounds(metric, delta);
     const raster_tuning tu = current_tuning();
     // every job's table sized from its estimated distinct tiles (a job that
@@ -454,7 +458,7 @@ raster_status BatchEngine::run(const raster_job* jobs, int32_t n_jobs, hipStream
     if (e != hipSuccess) return hip_fail(e, "batch upload");
     const bool same_tuning = graph_tuning.block == tu.block && graph_tuning.items == tu.items &&
                              graph_tuning.preagg_slots == tu.preagg_slots && graph_binned == binned &&
-                             graph_metric == metric && graph_delta == delta;
+                             graph_metric == metric && graph_delta == delta && graph_square == square;
     if (!graph_valid || !same_tuning) {
         drop_graph();
         e = hipStreamBeginCapture(bs, hipStreamCaptureModeThreadLocal);
@@ -474,6 +478,7 @@ raster_status BatchEngine::run(const raster_job* jobs, int32_t n_jobs, hipStream
         graph_binned = binned;
         graph_metric = metric;
         graph_delta = delta;
+        graph_square = square;
     }
     hipEvent_t t0 = nullptr, t1 = nullptr;
     (void)hipEventCreate(&t0);
@@ -576,17 +581,16 @@ raster_status validate_job(const raster_job& j, int32_t i) {
     return st;
 }
 
-// One batch of jobs that share a neighbourhood; a job that spilled is redone
-// alone through the plain path with the same neighbourhood.
+// One batch of jobs that share their options; a job that spilled is redone
+// alone through the plain path with the same options.
 static raster_status run_group(BatchEngine& eng, const raster_job* jobs, int32_t n_jobs, hipStream_t stream,
-                               raster_result** outs, uint32_t metric, uint32_t delta) {
+                               raster_result** outs, const raster_options& o) {
     std::vector<int32_t> redo;
     raster_status st;
     {
         std::lock_guard<std::mutex> g(eng.mu);
-        st = eng.run(jobs, n_jobs, stream, outs, &redo, metric, delta);
+        st = eng.run(jobs, n_jobs, stream, outs, &redo, (uint32_t)o.metric, o.delta, o.square_step != 0);
     }
-    const raster_options o{(raster_metric)metric, delta, 0u, 2u};
     for (size_t k = 0; st == RASTER_OK && k < redo.size(); ++k) {
         const raster_job& j = jobs[redo[k]];
         double sc = j.scale;
@@ -602,19 +606,22 @@ raster_status run_batch(BatchEngine& eng, const raster_job* jobs, int32_t n_jobs
     for (int32_t i = 0; i < n_jobs; ++i) {
         raster_status st = validate_job(jobs[i], i);
         if (st == RASTER_OK && opts) st = check_options(&opts[i]);
-        if (st == RASTER_OK && opts && (opts[i].square_step || opts[i].dims == 3))
-            st = fail(RASTER_E_INVAL, "job %d: batches take neighbourhood options only (no 2x2 step, no 3-D)", i);
+        if (st == RASTER_OK && opts && opts[i].dims == 3)
+            st = fail(RASTER_E_INVAL, "job %d: batches take two-dimensional points only", i);
         if (st != RASTER_OK) return st;
     }
     if (n_jobs == 0) return RASTER_OK;
-    // jobs grouped by neighbourhood, each group one batch, in first-seen order
-    std::vector<std::pair<uint32_t, uint32_t>> keys;
+    // jobs grouped by options, each group one batch, in first-seen order
+    auto same = [](const raster_options& a, const raster_options& b) {
+        return a.metric == b.metric && a.delta == b.delta && (a.square_step != 0) == (b.square_step != 0);
+    };
+    std::vector<raster_options> keys;
     std::vector<std::vector<int32_t>> members;
     for (int32_t i = 0; i < n_jobs; ++i) {
-        const std::pair<uint32_t, uint32_t> k =
-            opts ? std::make_pair((uint32_t)opts[i].metric, opts[i].delta) : std::make_pair(0u, 1u);
+        const raster_options k = opts ? raster_options{opts[i].metric, opts[i].delta, opts[i].square_step ? 1u : 0u, 2u}
+                                      : raster_options{RASTER_CHEBYSHEV, 1u, 0u, 2u};
         size_t g = 0;
-        while (g < keys.size() && keys[g] != k) ++g;
+        while (g < keys.size() && !same(keys[g], k)) ++g;
         if (g == keys.size()) {
             keys.push_back(k);
             members.emplace_back();
@@ -623,13 +630,13 @@ raster_status run_batch(BatchEngine& eng, const raster_job* jobs, int32_t n_jobs
     }
     raster_status st = RASTER_OK;
     if (keys.size() == 1) {
-        st = run_group(eng, jobs, n_jobs, stream, outs, keys[0].first, keys[0].second);
+        st = run_group(eng, jobs, n_jobs, stream, outs, keys[0]);
     } else {
         for (size_t g = 0; st == RASTER_OK && g < keys.size(); ++g) {
             std::vector<raster_job> sub;
             for (int32_t i : members[g]) sub.push_back(jobs[i]);
             std::vector<raster_result*> res(sub.size(), nullptr);
-            st = run_group(eng, sub.data(), (int32_t)sub.size(), stream, res.data(), keys[g].first, keys[g].second);
+            st = run_group(eng, sub.data(), (int32_t)sub.size(), stream, res.data(), keys[g]);
             for (size_t k = 0; k < sub.size(); ++k) outs[members[g][k]] = res[k];
         }
     }
@@ -824,8 +831,8 @@ extern "C" raster_status raster_server_submit_opts(raster_server* s, const raste
     if (!s || !job || !ticket) return fail(RASTER_E_INVAL, "NULL argument");
     raster_status st = validate_job(*job, 0);
     if (st == RASTER_OK) st = check_options(opts);
-    if (st == RASTER_OK && opts && (opts->square_step || opts->dims == 3))
-        st = fail(RASTER_E_INVAL, "server jobs take neighbourhood options only (no 2x2 step, no 3-D)");
+    if (st == RASTER_OK && opts && opts->dims == 3)
+        st = fail(RASTER_E_INVAL, "server jobs take two-dimensional points only");
     if (st != RASTER_OK) return st;
     const size_t bytes = job_bytes(*job);
     if (bytes > s->budget)
@@ -833,7 +840,7 @@ extern "C" raster_status raster_server_submit_opts(raster_server* s, const raste
                     s->budget);
     ServerJob* j = new ServerJob();
     j->job = *job;
-    if (opts) j->opts = raster_options{opts->metric, opts->delta, 0u, 2u};
+    if (opts) j->opts = raster_options{opts->metric, opts->delta, opts->square_step ? 1u : 0u, 2u};
     j->bytes = bytes;
     j->submitted = std::chrono::steady_clock::now();
     {

@@ -181,7 +181,7 @@ def test_batch_options_rejected(raster, torch):
     job = raster._job(pts, 1, 1, 1)
     arr = (raster._Job * 1)(job)
     outs = (ctypes.c_void_p * 1)()
-    for o in (raster._Options(0, 1, 1, 0), raster._Options(0, 1, 0, 3), raster._Options(0, 0, 0, 0),
+    for o in (raster._Options(0, 1, 2, 0), raster._Options(0, 1, 0, 3), raster._Options(0, 0, 0, 0),
               raster._Options(2, 1, 0, 0), raster._Options(1, 9, 0, 0)):
         opts = (raster._Options * 1)(o)
         assert lib.raster_cluster_batch_opts(arr, opts, 1, None, outs) == raster.E_INVAL and not outs[0]
@@ -231,7 +231,7 @@ def test_server_neighbourhood_per_job(raster, torch):
         lib = raster.load()
         job = raster._job(args[0]["points"], 1, 1, 1)
         t = ctypes.c_uint64()
-        for o in (raster._Options(0, 1, 1, 0), raster._Options(0, 1, 0, 3), raster._Options(1, 0, 0, 0)):
+        for o in (raster._Options(0, 1, 2, 0), raster._Options(0, 1, 0, 3), raster._Options(1, 0, 0, 0)):
             assert lib.raster_server_submit_opts(srv._h, ctypes.byref(job), ctypes.byref(o),
                                                  ctypes.byref(t)) == raster.E_INVAL
     finally:

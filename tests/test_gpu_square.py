@@ -135,3 +135,38 @@ def test_invalid_options(raster, torch):
     rc = lib.raster_cluster_opts(ctypes.c_void_p(pts.data_ptr()), 1, 2, 10.0, 1, 1, None, None, ctypes.byref(out))
     assert rc == 0 and out.value
     lib.raster_result_free(out)
+
+
+def test_batch_and_server_with_the_step(raster, torch):
+    # jobs with and without the step (and with another neighbourhood) in one
+    # batch call and through the server; each equals the oracle
+    specs = synth.batch_jobs(seed=31, n_jobs=10, size_scale=0.02)
+    variants = [dict(), dict(square=True), dict(square=True, metric="manhattan", delta=2), dict(metric="chebyshev",
+                                                                                               delta=2)]
+    jobs = [(sp, synth.job_points(sp), variants[k % len(variants)]) for k, sp in enumerate(specs)]
+    args = [dict(points=dev(p, torch), precision=sp.precision, tau=sp.tau, mu=sp.mu, **v) for sp, p, v in jobs]
+
+    def want(sp, p, v):
+        return oracle.cluster(p, tau=sp.tau, mu=sp.mu, precision=sp.precision, metric=v.get("metric", "chebyshev"),
+                              delta=v.get("delta", 1), window=v.get("square", False))
+
+    res = raster.cluster_batch(args)
+    for k, ((sp, p, v), g) in enumerate(zip(jobs, res)):
+        assert_same(g, want(sp, p, v), f"batch job {k} {v}")
+    # a larger job with the step: the square pass runs over a whole batch arena
+    fig = np.array(json.load(open(os.path.join(GOLDEN, "fig4_grid_corner.json")))["points"])
+    res = raster.cluster_batch([dict(points=dev(fig, torch), precision=0, tau=4, mu=1, square=True),
+                                dict(points=args[0]["points"], precision=jobs[0][0].precision, tau=jobs[0][0].tau,
+                                     mu=jobs[0][0].mu, square=True)])
+    assert res[0].num_clusters == 1 and res[0].num_tiles == 4
+    assert_same(res[1], want(jobs[0][0], jobs[0][1], dict(square=True)), "second job of a square batch")
+    srv = raster.Server(budget_bytes=8 << 30, max_slots=2)
+    try:
+        tickets = [srv.submit(a["points"], a["tau"], a["mu"], precision=a["precision"],
+                              metric=a.get("metric", "chebyshev"), delta=a.get("delta", 1),
+                              square=a.get("square", False)) for a in args]
+        for k, (t, (sp, p, v)) in enumerate(zip(tickets, jobs)):
+            g, _ = srv.wait(t)
+            assert_same(g, want(sp, p, v), f"served job {k} {v}")
+    finally:
+        srv.close()
