@@ -15,7 +15,8 @@
  * Conventions shared by every call:
  *   - Points are caller-owned DEVICE memory, row-major (n, 2): x then y of
  *     each point, RASTER_F64 (16 bytes per point, 16-byte aligned) or
- *     RASTER_F32 (8 bytes per point, 8-byte aligned).  FP32 coordinates are
+ *     RASTER_F32 (8 bytes per point, 8-byte aligned); (n, 3) with
+ *     raster_options.dims = 3 (three-dimensional points, below).  FP32 coordinates are
  *     widened to FP64 exactly before the product, so an FP32 point and its
  *     FP64 widening land on the same tile.
  *   - Tile of a point: kx = trunc(fl64(x * s)), ky = trunc(fl64(y * s)), one
@@ -57,7 +58,9 @@ typedef enum raster_dtype { RASTER_F32 = 1, RASTER_F64 = 2 } raster_dtype;
 typedef enum raster_metric { RASTER_CHEBYSHEV = 0, RASTER_MANHATTAN = 1 } raster_metric;
 #define RASTER_MAX_DELTA 8
 
-/* Variants of the method, for raster_cluster_opts and raster_begin_opts.
+/* Variants of the method, for raster_cluster_opts and raster_begin_opts (and,
+ * without dims = 3, per job in raster_cluster_batch_opts and
+ * raster_server_submit_opts).
  * NULL options mean {RASTER_CHEBYSHEV, 1, 0, 2}: Algorithm 1 as the paper's
  * code runs it. */
 typedef struct raster_options {
