@@ -110,6 +110,8 @@ typedef struct raster_stats {
     float us_bin_keys;         /* binned path: second-level binning, summed       */
     float us_aggregate;        /* binned path: LDS partition updates, summed      */
     int32_t flushes;           /* binned path: groups of keys applied to the table */
+    int32_t redone;            /* batched and served jobs: 1 when the job overflowed its
+                                  batch table and was redone alone by the plain path */
 } raster_stats;
 
 /* Launch knobs of the contraction kernels.  Any value gives the same result;
@@ -173,6 +175,13 @@ raster_status raster_cluster_delta(const void* d_points, int64_t n, raster_dtype
 raster_status raster_cluster_opts(const void* d_points, int64_t n, raster_dtype dt, double scale,
                                   uint32_t tau, uint32_t mu, const raster_options* opts, hipStream_t stream,
                                   raster_result** out);
+
+/* raster_cluster_opts with an integer precision p in [0, 15] (s = 10^p,
+ * computed exactly by the library) instead of a scale; E_INVAL for p outside
+ * [0, 15]. */
+raster_status raster_cluster_p_opts(const void* d_points, int64_t n, raster_dtype dt, int32_t precision,
+                                    uint32_t tau, uint32_t mu, const raster_options* opts, hipStream_t stream,
+                                    raster_result** out);
 
 /* ---- results --------------------------------------------------------------- */
 
@@ -253,6 +262,10 @@ raster_status raster_begin_delta(double scale, uint32_t tau, uint32_t mu, raster
 /* A stream with every variant in `opts`, as in raster_cluster_opts. */
 raster_status raster_begin_opts(double scale, uint32_t tau, uint32_t mu, const raster_options* opts,
                                 int64_t tile_hint, hipStream_t stream, raster_stream** st);
+/* raster_begin_opts with an integer precision p in [0, 15] (s = 10^p), as in
+ * raster_begin. */
+raster_status raster_begin_p_opts(int32_t precision, uint32_t tau, uint32_t mu, const raster_options* opts,
+                                  int64_t tile_hint, hipStream_t stream, raster_stream** st);
 /* Count one chunk.  d_points is borrowed until the stream has passed the
  * enqueued work (the next raster_* call on this stream object, or a
  * synchronisation of its HIP stream).  Returns without waiting for this chunk;
@@ -307,24 +320,50 @@ raster_status raster_cluster_batch_opts(const raster_job* jobs, const raster_opt
  * to max_slots HIP streams at once, so that new jobs overlap jobs already on
  * the GPU.  Tables stay resident and are reused across jobs. */
 raster_status raster_server_create(size_t budget_bytes, int32_t max_slots, raster_server** srv);
-/* Queue a job.  Its points are borrowed until raster_server_wait returns it.
- * Returns RASTER_E_BUDGET for a job that cannot fit the budget even alone. */
+/* Queue a job whose points were produced by work on `stream` (0: the null
+ * stream).  Submission records an event on `stream` and returns at once; the
+ * job's device work waits for that event, so points written by kernels or
+ * copies enqueued on `stream` before the call are read only once they are
+ * complete.  Its points are borrowed until raster_server_wait returns it.
+ * At submission the server enqueues a distinct-tile sketch of the points (one
+ * read of them, on its own stream); when the job reaches the head of the
+ * queue, its device footprint is computed from that estimate -- the table
+ * sized from it with room for one growth step, the binning and spill scratch
+ * of its points, the compact arrays and the rows -- and the job is admitted
+ * once the running batches, the buffers the idle engines keep and the job
+ * fit the budget (an idle engine gives its buffers back to make room).  So the
+ * library's in-use device memory stays within budget_bytes while the server
+ * runs (raster_memory_stats).  Returns RASTER_E_BUDGET when even the smallest
+ * footprint of the job (one distinct tile) exceeds the budget; a job whose
+ * estimated footprint exceeds it fails with RASTER_E_BUDGET at
+ * raster_server_wait.  E_INVAL for invalid options and for dims = 3. */
+raster_status raster_server_submit_stream(raster_server* srv, const raster_job* job, const raster_options* opts,
+                                          hipStream_t stream, uint64_t* ticket);
+/* raster_server_submit_stream on the null stream with the default options. */
 raster_status raster_server_submit(raster_server* srv, const raster_job* job, uint64_t* ticket);
 /* Same, with the job's options (metric, delta, square_step; NULL: the
- * defaults): its result is identical to raster_cluster_opts on the job alone.
- * Jobs that share a batch are grouped by options as in
- * raster_cluster_batch_opts.  E_INVAL for invalid options and for dims = 3. */
+ * defaults), on the null stream: its result is identical to
+ * raster_cluster_opts on the job alone.  Jobs that share a batch are grouped
+ * by options as in raster_cluster_batch_opts. */
 raster_status raster_server_submit_opts(raster_server* srv, const raster_job* job, const raster_options* opts,
                                         uint64_t* ticket);
 /* Block until the job behind ticket is done; *latency_s receives submit-to-
  * completion wall time.  Each ticket may be waited on once. */
 raster_status raster_server_wait(raster_server* srv, uint64_t ticket, raster_result** out,
                                  double* latency_s);
+/* The server's budget and the largest device footprint it has charged at
+ * once (running batches plus the buffers idle engines keep). */
+raster_status raster_server_memory(raster_server* srv, size_t* budget, size_t* peak_charged);
 /* Drain queued work, stop the loop and release the server's memory. */
 void raster_server_destroy(raster_server* srv);
 
 /* ---- misc ------------------------------------------------------------------- */
 
+/* Device memory held by the library on the calling thread's current device:
+ * bytes in use (tables, scratch, results not yet freed, buffers the batch
+ * engines keep), bytes cached for reuse, and the largest in-use figure since
+ * the last reset (reset_peak != 0 starts a new window at the current use). */
+raster_status raster_memory_stats(size_t* used, size_t* cached, size_t* peak_used, int32_t reset_peak);
 raster_status raster_set_tuning(const raster_tuning* t); /* NULL restores defaults */
 raster_status raster_get_tuning(raster_tuning* t);
 const char* raster_status_string(raster_status s);

@@ -19,7 +19,7 @@ from dataclasses import dataclass
 
 __all__ = [
     "cluster", "Stream", "cluster_batch", "Server", "Result", "RasterError", "RasterNotBuilt",
-    "set_tuning", "get_tuning", "library_path", "load", "biased_key", "F32", "F64",
+    "set_tuning", "get_tuning", "library_path", "load", "memory_stats", "F32", "F64",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -55,7 +55,7 @@ class _Stats(ctypes.Structure):
                 ("us_agglomerate", ctypes.c_float), ("us_filter", ctypes.c_float),
                 ("count_launches", ctypes.c_int64), ("us_count_kernel", ctypes.c_float),
                 ("us_bin_keys", ctypes.c_float), ("us_aggregate", ctypes.c_float),
-                ("flushes", ctypes.c_int32)]
+                ("flushes", ctypes.c_int32), ("redone", ctypes.c_int32)]
 
 
 class _Tuning(ctypes.Structure):
@@ -104,6 +104,8 @@ def load():
         "raster_begin_delta": (st, [dbl, u32, u32, ctypes.c_int, u32, i64, vp, pp]),
         "raster_cluster_delta": (st, [vp, i64, ctypes.c_int, dbl, u32, u32, ctypes.c_int, u32, vp, pp]),
         "raster_cluster_opts": (st, [vp, i64, ctypes.c_int, dbl, u32, u32, ctypes.POINTER(_Options), vp, pp]),
+        "raster_cluster_p_opts": (st, [vp, i64, ctypes.c_int, i32, u32, u32, ctypes.POINTER(_Options), vp, pp]),
+        "raster_begin_p_opts": (st, [i32, u32, u32, ctypes.POINTER(_Options), i64, vp, pp]),
         "raster_result_kz": (st, [vp, ctypes.POINTER(vp)]),
         "raster_result_copy_kz": (st, [vp, vp, vp]),
         "raster_begin_opts": (st, [dbl, u32, u32, ctypes.POINTER(_Options), i64, vp, pp]),
@@ -117,7 +119,12 @@ def load():
         "raster_server_submit": (st, [vp, ctypes.POINTER(_Job), ctypes.POINTER(ctypes.c_uint64)]),
         "raster_server_submit_opts": (st, [vp, ctypes.POINTER(_Job), ctypes.POINTER(_Options),
                                            ctypes.POINTER(ctypes.c_uint64)]),
+        "raster_server_submit_stream": (st, [vp, ctypes.POINTER(_Job), ctypes.POINTER(_Options), vp,
+                                             ctypes.POINTER(ctypes.c_uint64)]),
         "raster_server_wait": (st, [vp, ctypes.c_uint64, pp, ctypes.POINTER(dbl)]),
+        "raster_server_memory": (st, [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+        "raster_memory_stats": (st, [ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                     ctypes.POINTER(ctypes.c_size_t), i32]),
         "raster_server_destroy": (None, [vp]),
         "raster_set_tuning": (st, [ctypes.POINTER(_Tuning)]),
         "raster_get_tuning": (st, [ctypes.POINTER(_Tuning)]),
@@ -169,14 +176,6 @@ def _points(points, dims: int = 2):
     else:
         raise ValueError("points must be float32 or float64")
     return ctypes.c_void_p(points.data_ptr()), int(points.shape[0]), dt
-
-
-def biased_key(kx, ky):
-    """Biased 64-bit tile key of integer arrays kx, ky (numpy): (kx + 2^31) << 32 | (ky + 2^31)."""
-    import numpy as np
-    kx = np.asarray(kx, dtype=np.int64)
-    ky = np.asarray(ky, dtype=np.int64)
-    return (((kx + (1 << 31)).astype(np.uint64) << np.uint64(32)) | (ky + (1 << 31)).astype(np.uint64))
 
 
 class Result:
@@ -285,14 +284,6 @@ class Result:
 METRICS = {"chebyshev": 0, "manhattan": 1}
 
 
-def _scale_of(precision, scale) -> float:
-    if scale is not None:
-        return float(scale)
-    if precision is None:
-        raise ValueError("give precision or scale")
-    return float(10 ** int(precision))
-
-
 def _options(metric: str, delta: int, square: bool, dims: int = 2):
     """The options struct, or None for the defaults."""
     if metric == "chebyshev" and delta == 1 and not square and dims == 2:
@@ -306,10 +297,9 @@ def _dims_of(points) -> int:
     return 3 if points.dim() == 2 and points.shape[1] == 3 else 2
 
 
-def _variant_scale(precision, scale, what) -> float:
-    if scale is None and not (precision is not None and 0 <= int(precision) <= 15):
-        raise RasterError(E_INVAL, what, f"precision {precision} outside [0, 15]")
-    return _scale_of(precision, scale)
+def _need_precision(precision, scale, what):
+    if scale is None and precision is None:
+        raise RasterError(E_INVAL, what, "give precision or scale")
 
 
 def cluster(points, tau: int, mu: int, precision: int | None = None, scale: float | None = None,
@@ -325,9 +315,13 @@ def cluster(points, tau: int, mu: int, precision: int | None = None, scale: floa
     out = ctypes.c_void_p()
     st = _stream_handle(stream)
     opts = _options(metric, delta, square, dims)
-    if opts is not None:
-        rc = lib.raster_cluster_opts(p, n, dt, _variant_scale(precision, scale, "raster_cluster_opts"), int(tau),
-                                     int(mu), ctypes.byref(opts), st, ctypes.byref(out))
+    _need_precision(precision, scale, "raster_cluster")
+    if opts is not None and scale is not None:
+        rc = lib.raster_cluster_opts(p, n, dt, float(scale), int(tau), int(mu), ctypes.byref(opts), st,
+                                     ctypes.byref(out))
+    elif opts is not None:
+        rc = lib.raster_cluster_p_opts(p, n, dt, int(precision), int(tau), int(mu), ctypes.byref(opts), st,
+                                       ctypes.byref(out))
     elif scale is not None:
         rc = lib.raster_cluster_scaled(p, n, dt, float(scale), int(tau), int(mu), st, ctypes.byref(out))
     else:
@@ -349,9 +343,13 @@ class Stream:
         self._keep = []  # chunks stay referenced until the stream has consumed them
         st = _stream_handle(stream)
         opts = _options(metric, delta, square, self._dims)
-        if opts is not None:
-            rc = self._lib.raster_begin_opts(_variant_scale(precision, scale, "raster_begin_opts"), int(tau), int(mu),
-                                             ctypes.byref(opts), int(tile_hint), st, ctypes.byref(self._h))
+        _need_precision(precision, scale, "raster_begin")
+        if opts is not None and scale is not None:
+            rc = self._lib.raster_begin_opts(float(scale), int(tau), int(mu), ctypes.byref(opts), int(tile_hint), st,
+                                             ctypes.byref(self._h))
+        elif opts is not None:
+            rc = self._lib.raster_begin_p_opts(int(precision), int(tau), int(mu), ctypes.byref(opts),
+                                               int(tile_hint), st, ctypes.byref(self._h))
         elif scale is not None:
             rc = self._lib.raster_begin_scaled(float(scale), int(tau), int(mu), int(tile_hint), st,
                                                ctypes.byref(self._h))
@@ -435,17 +433,25 @@ class Server:
                "raster_server_create")
 
     def submit(self, points, tau: int, mu: int, precision: int | None = None, scale: float | None = None,
-               metric: str = "chebyshev", delta: int = 1, square: bool = False) -> int:
+               metric: str = "chebyshev", delta: int = 1, square: bool = False, stream=None) -> int:
+        """Queue a job; its device work is ordered after the work already
+        enqueued on ``stream`` (default: the current torch stream), which may
+        still be producing the points."""
         job = _job(points, precision, tau, mu, scale)
         t = ctypes.c_uint64()
         opts = _options(metric, delta, square)
-        if opts is None:
-            _check(self._lib.raster_server_submit(self._h, ctypes.byref(job), ctypes.byref(t)), "raster_server_submit")
-        else:
-            _check(self._lib.raster_server_submit_opts(self._h, ctypes.byref(job), ctypes.byref(opts), ctypes.byref(t)),
-                   "raster_server_submit_opts")
+        _check(self._lib.raster_server_submit_stream(self._h, ctypes.byref(job),
+                                                     ctypes.byref(opts) if opts is not None else None,
+                                                     _stream_handle(stream), ctypes.byref(t)),
+               "raster_server_submit_stream")
         self._keep[t.value] = points
         return t.value
+
+    def memory(self):
+        """(budget, largest footprint charged at once) in bytes."""
+        b, p = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(self._lib.raster_server_memory(self._h, ctypes.byref(b), ctypes.byref(p)), "raster_server_memory")
+        return b.value, p.value
 
     def wait(self, ticket: int):
         out = ctypes.c_void_p()
@@ -489,6 +495,15 @@ def set_tuning(t: Tuning | None = None, **kw) -> None:
     c = _Tuning(int(t.block), int(t.items), int(t.preagg_slots), float(t.load_factor), int(t.mode),
                 int(t.group_mpoints))
     _check(lib.raster_set_tuning(ctypes.byref(c)), "raster_set_tuning")
+
+
+def memory_stats(reset_peak: bool = False):
+    """(used, cached, peak_used) device bytes of the library's pool on the
+    current device; ``reset_peak`` starts a new peak window."""
+    u, c, p = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load().raster_memory_stats(ctypes.byref(u), ctypes.byref(c), ctypes.byref(p), int(bool(reset_peak))),
+           "raster_memory_stats")
+    return u.value, c.value, p.value
 
 
 def get_tuning() -> Tuning:

@@ -105,6 +105,7 @@ hipError_t DevicePool::alloc(void** out, size_t bytes) {
             *out = it->second;
             cached_ -= it->first;
             used_ += it->first;
+            peak_ = std::max(peak_, used_);
             free_.erase(it);
             return hipSuccess;
         }
@@ -123,6 +124,7 @@ hipError_t DevicePool::alloc(void** out, size_t bytes) {
     std::lock_guard<std::mutex> g(mu_);
     sizes_[*out] = c;
     used_ += c;
+    peak_ = std::max(peak_, used_);
     return hipSuccess;
 }
 
@@ -152,6 +154,24 @@ size_t DevicePool::used_bytes() {
     return used_;
 }
 
+size_t DevicePool::cached_bytes() {
+    std::lock_guard<std::mutex> g(mu_);
+    return cached_;
+}
+
+size_t DevicePool::block_bytes(void* p) {
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = sizes_.find(p);
+    return it == sizes_.end() ? 0 : it->second;
+}
+
+size_t DevicePool::peak_used(bool reset) {
+    std::lock_guard<std::mutex> g(mu_);
+    const size_t p = peak_;
+    if (reset) peak_ = used_;
+    return p;
+}
+
 // A set of pool blocks released together.
 Buffers::~Buffers() { release_all(); }
 
@@ -165,6 +185,13 @@ hipError_t Buffers::take(void** out, size_t bytes) {
     hipError_t e = pool->alloc(out, bytes);
     if (e == hipSuccess) blocks.push_back(*out);
     return e;
+}
+
+size_t Buffers::bytes() const {
+    size_t b = 0;
+    if (pool)
+        for (void* p : blocks) b += pool->block_bytes(p);
+    return b;
 }
 
 void Buffers::give_back(void* p) {
@@ -930,6 +957,15 @@ raster_status raster_cluster_opts(const void* d_points, int64_t n, raster_dtype 
     return run.finish(out);
 }
 
+raster_status raster_cluster_p_opts(const void* d_points, int64_t n, raster_dtype dt, int32_t precision,
+                                    uint32_t tau, uint32_t mu, const raster_options* opts, hipStream_t stream,
+                                    raster_result** out) {
+    double s;
+    if (out) *out = nullptr;
+    if (!scale_for_precision(precision, &s)) return fail(RASTER_E_INVAL, "precision %d outside [0, 15]", precision);
+    return raster_cluster_opts(d_points, n, dt, s, tau, mu, opts, stream, out);
+}
+
 raster_status raster_cluster_delta(const void* d_points, int64_t n, raster_dtype dt, double scale, uint32_t tau,
                                    uint32_t mu, raster_metric metric, uint32_t delta, hipStream_t stream,
                                    raster_result** out) {
@@ -948,6 +984,17 @@ raster_status raster_cluster(const void* d_points, int64_t n, raster_dtype dt, i
     if (out) *out = nullptr;
     if (!scale_for_precision(precision, &s)) return fail(RASTER_E_INVAL, "precision %d outside [0, 15]", precision);
     return raster_cluster_scaled(d_points, n, dt, s, tau, mu, stream, out);
+}
+
+raster_status raster_memory_stats(size_t* used, size_t* cached, size_t* peak_used, int32_t reset_peak) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    DevicePool& p = DevicePool::get(dev);
+    if (used) *used = p.used_bytes();
+    if (cached) *cached = p.cached_bytes();
+    const size_t pk = p.peak_used(reset_peak != 0);
+    if (peak_used) *peak_used = pk;
+    return RASTER_OK;
 }
 
 int64_t raster_result_num_tiles(const raster_result* r) { return r ? r->tiles : -1; }
@@ -1149,6 +1196,14 @@ raster_status raster_begin_opts(double scale, uint32_t tau, uint32_t mu, const r
     }
     *st = h;
     return RASTER_OK;
+}
+
+raster_status raster_begin_p_opts(int32_t precision, uint32_t tau, uint32_t mu, const raster_options* opts,
+                                  int64_t tile_hint, hipStream_t stream, raster_stream** st) {
+    double s;
+    if (st) *st = nullptr;
+    if (!scale_for_precision(precision, &s)) return fail(RASTER_E_INVAL, "precision %d outside [0, 15]", precision);
+    return raster_begin_opts(s, tau, mu, opts, tile_hint, stream, st);
 }
 
 raster_status raster_begin_delta(double scale, uint32_t tau, uint32_t mu, raster_metric metric, uint32_t delta,

@@ -70,12 +70,15 @@ class DevicePool {
     void release(void* p);
     void trim();
     size_t used_bytes();
+    size_t cached_bytes();
+    size_t block_bytes(void* p);   // size class of a block handed out by alloc
+    size_t peak_used(bool reset);  // largest used_bytes() since the last reset
 
   private:
     std::mutex mu_;
     std::multimap<size_t, void*> free_;
     std::unordered_map<void*, size_t> sizes_;
-    size_t cached_ = 0, used_ = 0;
+    size_t cached_ = 0, used_ = 0, peak_ = 0;
     int device_ = 0;
 };
 
@@ -86,6 +89,7 @@ struct Buffers {
     hipError_t take(void** out, size_t bytes);
     void give_back(void* p);
     void release_all();
+    size_t bytes() const;  // device bytes of the blocks held
 };
 
 // Device image of a one-job view.

@@ -18,6 +18,12 @@
 
 using namespace rst;
 
+#define HIP_TRY_S(expr, what)                              \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) return hip_fail(e_, what);   \
+    } while (0)
+
 // ----------------------------------------------------------------- batch ---
 //
 // A batch is clustered by one pipeline over all its jobs: one fused counting
@@ -596,6 +602,7 @@ static raster_status run_group(BatchEngine& eng, const raster_job* jobs, int32_t
         double sc = j.scale;
         if (!(sc > 0.0)) scale_for_precision(j.precision, &sc);
         st = raster_cluster_opts(j.d_points, j.n, j.dt, sc, j.tau, j.mu, &o, stream, &outs[redo[k]]);
+        if (st == RASTER_OK) outs[redo[k]]->stats.redone = 1;
     }
     return st;
 }
@@ -671,12 +678,36 @@ extern "C" raster_status raster_cluster_batch_opts(const raster_job* jobs, const
 // batches already running, runs them as one batch, and hands out the results.
 // Jobs arriving while batches are on the GPU are picked up by the next free
 // worker, so their work overlaps the running batches.
+//
+// Ordering: a job's points may still be in production on the submitter's
+// stream.  Submission records an event there; the job's sketch and its run
+// wait for that event on the device.
+//
+// Admission: at submission a distinct-tile sketch of the job's points is
+// enqueued on the server's sketch stream (one read of the points).  When the
+// job reaches the head of the queue its device footprint is computed from
+// that estimate: the table the run will size from it (with one growth step
+// in reserve), the binning and spill scratch its point count needs, the
+// compact arrays and its rows.  A worker admits jobs while the footprints of
+// the running batches, plus the buffers other idle engines keep, plus the new
+// jobs fit the budget; a worker that cannot admit the head job releases its
+// own engine's buffers first.  The library's in-use device bytes therefore
+// stay within the budget while the server runs.
+
+struct SketchBuf {
+    uint32_t* dev = nullptr;   // kHllReps << kHllLog2 registers
+    uint32_t* host = nullptr;  // pinned copy
+};
 
 struct ServerJob {
     uint64_t ticket = 0;
     raster_job job{};
     raster_options opts{RASTER_CHEBYSHEV, 1u, 0u, 2u};  // the job's neighbourhood
-    size_t bytes = 0;
+    size_t bytes = 0;        // device footprint, once charged
+    bool charged = false;
+    hipEvent_t ready = nullptr;     // recorded on the submitter's stream
+    hipEvent_t sketched = nullptr;  // recorded after the sketch's copy
+    SketchBuf sk;
     std::chrono::steady_clock::time_point submitted;
     bool done = false;
     raster_status status = RASTER_OK;
@@ -694,21 +725,43 @@ struct raster_server {
     std::deque<ServerJob*> queue;
     std::unordered_map<uint64_t, ServerJob*> jobs;
     uint64_t next_ticket = 1;
-    size_t in_flight = 0;  // bytes held by running batches
+    size_t in_flight = 0;         // footprints of running batches
+    std::vector<size_t> resident; // buffers each idle engine keeps
+    size_t peak_charged = 0;      // largest in_flight + resident seen
     bool stop = false;
     std::vector<std::thread> workers;
     std::vector<BatchEngine*> engines;
+    hipStream_t sk_stream = nullptr;  // sketches of submitted jobs
+    std::vector<hipEvent_t> free_events;
+    std::vector<SketchBuf> free_sketches;
+    Buffers sk_bufs;
 };
 
-// Device working set of one job in a batch: its table (16 B per slot), the
-// compact arrays and rows (sized by its points or table, whichever is
-// smaller, about 60 B each), and its share of the job tables.
-static size_t job_bytes(const raster_job& j) {
+static size_t table_bytes(double distinct, double lf) {
+    return (size_t)next_pow2(std::max<uint64_t>(4096, (uint64_t)(distinct / lf) + 1)) * sizeof(Slot);
+}
+
+// Device footprint of one job of n points with about d distinct tiles, as
+// the larger of what a plain run takes (first table from the n/8 guess, the
+// sketch-sized table and a growth step, binning and spill scratch, compact
+// arrays, neighbour lists and rows) and what the job adds to a batch engine
+// (arena share, coarse and partition buckets, per-slot compact arrays, rows;
+// the engine keeps a quarter of headroom on each).
+static size_t job_footprint(int64_t n_, double est) {
     const raster_tuning tu = current_tuning();
-    const double est = std::max<double>((double)j.n / 8.0, 1.0) / tu.load_factor;
-    const uint64_t cap = next_pow2(std::max<uint64_t>(4096, (uint64_t)est));
-    const uint64_t s = std::min<uint64_t>(cap, (uint64_t)std::max<int64_t>(j.n, 1));
-    return (size_t)(cap * 16 * 5 / 4 + s * 60 * 5 / 4 + 4096);
+    const double lf = tu.load_factor;
+    const double n = (double)std::max<int64_t>(n_, 1);
+    const double d = std::min(1.25 * est + 1024.0, n);
+    const size_t t0 = table_bytes(std::max(n / 8.0, 1024.0), lf);
+    const size_t t1 = table_bytes(d, lf);
+    // binned counting (tables of at least 2^19 slots) adds two levels of key
+    // buckets, at least 8 MiB for the first; the direct path a 64 KiB sketch
+    const bool binned = t0 / sizeof(Slot) >= (1u << 19) || tu.mode == 2;
+    const double bins = binned ? 19.5 * n + (double)(10u << 20) : (double)(64u << 10);
+    const double solo = (double)t0 + 3.0 * (double)t1 + bins + 12.0 * n + 56.0 * d + (double)(1u << 20);
+    const double cap = (double)t1 / sizeof(Slot);
+    const double batch = 1.25 * ((double)t1 + 18.0 * n + 100.0 * std::min(cap, n)) + (double)(1u << 20);
+    return (size_t)std::max(solo, batch);
 }
 
 static constexpr size_t kMaxBatchJobs = 128;
@@ -717,46 +770,115 @@ static constexpr uint64_t kMaxBatchPoints = 256ull * 1000 * 1000;
 // GPU, and fusing them would hold small jobs queued behind them.
 static constexpr uint64_t kSoloPoints = 2ull * 1000 * 1000;
 
+// Turns the job's sketch into its footprint (waits for the sketch if it is
+// still running) and returns the sketch buffers.  Called with s->mu held.
+static void charge(raster_server* s, ServerJob* j) {
+    if (j->charged) return;
+    double est = (double)j->job.n;
+    if (j->sketched && hipEventSynchronize(j->sketched) == hipSuccess) {
+        std::vector<uint32_t> M(1u << kHllLog2, 0);
+        for (uint32_t r = 0; r < kHllReps; ++r)
+            for (uint32_t k = 0; k < (1u << kHllLog2); ++k)
+                M[k] = std::max(M[k], j->sk.host[((size_t)r << kHllLog2) + k]);
+        est = hll_estimate(M.data());
+    }
+    j->bytes = job_footprint(j->job.n, est);
+    j->charged = true;
+    if (j->sk.dev) s->free_sketches.push_back(j->sk);
+    j->sk = SketchBuf{};
+    if (j->sketched) s->free_events.push_back(j->sketched);
+    j->sketched = nullptr;
+}
+
+static size_t others_resident(const raster_server* s, int slot) {
+    size_t r = 0;
+    for (int k = 0; k < (int)s->resident.size(); ++k)
+        if (k != slot) r += s->resident[k];
+    return r;
+}
+
 static void server_worker(raster_server* s, int slot) {
     (void)hipSetDevice(s->device);
     BatchEngine& eng = *s->engines[slot];
     while (true) {
         std::vector<ServerJob*> batch;
         size_t bytes = 0;
+        bool release_own = false;
         {
             std::unique_lock<std::mutex> g(s->mu);
-            s->cv_work.wait(g, [&] {
-                return (!s->queue.empty() && s->queue.front()->bytes <= s->budget - s->in_flight) ||
-                       (s->stop && s->queue.empty());
-            });
+            s->cv_work.wait(g, [&] { return !s->queue.empty() || s->stop; });
             if (s->queue.empty()) return;  // stopping and drained
-            // a large job runs alone; small jobs waiting together share one
-            // fused batch
-            uint64_t pts = 0;
-            while (!s->queue.empty() && batch.size() < kMaxBatchJobs) {
-                ServerJob* j = s->queue.front();
-                if (j->bytes > s->budget - s->in_flight - bytes) break;
-                const bool large = (uint64_t)j->job.n >= kSoloPoints;
-                if (!batch.empty() && (large || pts + (uint64_t)j->job.n > kMaxBatchPoints)) break;
-                batch.push_back(j);
-                bytes += j->bytes;
-                pts += (uint64_t)j->job.n;
+            ServerJob* head = s->queue.front();
+            charge(s, head);
+            if (head->bytes > s->budget) {
                 s->queue.pop_front();
-                if (large) break;
+                head->status = RASTER_E_BUDGET;
+                head->error = "the job's device footprint (" + std::to_string(head->bytes) +
+                              " bytes) exceeds the server's budget";
+                head->latency = std::chrono::duration<double>(std::chrono::steady_clock::now() - head->submitted).count();
+                head->done = true;
+                if (head->ready) s->free_events.push_back(head->ready);
+                head->ready = nullptr;
+                g.unlock();
+                s->cv_done.notify_all();
+                continue;
             }
-            s->in_flight += bytes;
+            // this engine's own buffers are reused by its next batch
+            const size_t avail_all = s->budget - std::min(s->budget, s->in_flight + others_resident(s, slot));
+            if (head->bytes > avail_all) {
+                if (s->resident[slot] > 0) {
+                    release_own = true;  // make room: drop this idle engine's buffers
+                    s->resident[slot] = 0;
+                } else {
+                    s->cv_work.wait(g);  // a batch ending or an engine releasing its buffers wakes us
+                    continue;
+                }
+            } else {
+                // a large job runs alone; small jobs waiting together share
+                // one fused batch
+                uint64_t pts = 0;
+                while (!s->queue.empty() && batch.size() < kMaxBatchJobs) {
+                    ServerJob* j = s->queue.front();
+                    charge(s, j);
+                    if (j->bytes > avail_all - bytes) break;
+                    const bool large = (uint64_t)j->job.n >= kSoloPoints;
+                    if (!batch.empty() && (large || pts + (uint64_t)j->job.n > kMaxBatchPoints)) break;
+                    batch.push_back(j);
+                    bytes += j->bytes;
+                    pts += (uint64_t)j->job.n;
+                    s->queue.pop_front();
+                    if (large) break;
+                }
+                // the engine keeps its buffers while it runs: a fused batch
+                // reuses them (it is charged at least what they hold); a job
+                // alone takes the plain path, which allocates beside them
+                bytes = batch.size() == 1 ? bytes + s->resident[slot] : std::max(bytes, s->resident[slot]);
+                s->resident[slot] = 0;
+                s->in_flight += bytes;
+                s->peak_charged = std::max(s->peak_charged, s->in_flight + others_resident(s, slot));
+            }
+        }
+        if (release_own) {
+            eng.release();
+            s->cv_work.notify_all();
+            continue;
         }
         s->cv_work.notify_all();  // another worker may take what is left
         std::vector<raster_job> jv(batch.size());
         std::vector<raster_options> ov(batch.size());
         std::vector<raster_result*> outs(batch.size(), nullptr);
+        raster_status st = eng.init();
         for (size_t i = 0; i < batch.size(); ++i) {
             jv[i] = batch[i]->job;
             ov[i] = batch[i]->opts;
+            // the points are ready once the submitter's stream has passed
+            // the event recorded at submission
+            if (st == RASTER_OK && batch[i]->ready && hipStreamWaitEvent(eng.bs, batch[i]->ready, 0) != hipSuccess)
+                st = fail(RASTER_E_DEVICE, "stream order of a served job");
         }
-        raster_status st = RASTER_OK;
-        (void)eng.init();
-        if (batch.size() == 1) {
+        if (st != RASTER_OK) {
+            // nothing ran
+        } else if (batch.size() == 1) {
             // nothing to fuse with: the plain path has the least fixed cost
             const raster_job& j = jv[0];
             double sc = j.scale;
@@ -780,6 +902,10 @@ static void server_worker(raster_server* s, int slot) {
                 batch[i]->error = err;
             }
         }
+        // cached pool blocks beyond the budget go back to the device
+        DevicePool& pool = DevicePool::get(s->device);
+        if (pool.used_bytes() + pool.cached_bytes() > s->budget) pool.trim();
+        const size_t kept = eng.bufs.bytes() + eng.sk_bufs.bytes();
         const auto t1 = std::chrono::steady_clock::now();
         {
             std::lock_guard<std::mutex> g(s->mu);
@@ -787,8 +913,11 @@ static void server_worker(raster_server* s, int slot) {
                 batch[i]->result = outs[i];
                 batch[i]->latency = std::chrono::duration<double>(t1 - batch[i]->submitted).count();
                 batch[i]->done = true;
+                if (batch[i]->ready) s->free_events.push_back(batch[i]->ready);
+                batch[i]->ready = nullptr;
             }
             s->in_flight -= bytes;
+            s->resident[slot] = kept;
         }
         s->cv_done.notify_all();
         s->cv_work.notify_all();
@@ -804,15 +933,19 @@ extern "C" raster_status raster_server_create(size_t budget_bytes, int32_t max_s
     s->budget = budget_bytes;
     s->slots = max_slots;
     hipError_t e = hipGetDevice(&s->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->sk_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete s;
-        return hip_fail(e, "hipGetDevice");
+        return hip_fail(e, "server setup");
     }
+    s->sk_bufs.pool = &DevicePool::get(s->device);
+    s->resident.assign(max_slots, 0);
     for (int i = 0; i < max_slots; ++i) {
         s->engines.push_back(new BatchEngine());
         raster_status st = s->engines.back()->init();
         if (st != RASTER_OK) {
             for (BatchEngine* b : s->engines) delete b;
+            (void)hipStreamDestroy(s->sk_stream);
             delete s;
             return st;
         }
@@ -823,29 +956,91 @@ extern "C" raster_status raster_server_create(size_t budget_bytes, int32_t max_s
 }
 
 extern "C" raster_status raster_server_submit(raster_server* s, const raster_job* job, uint64_t* ticket) {
-    return raster_server_submit_opts(s, job, nullptr, ticket);
+    return raster_server_submit_stream(s, job, nullptr, nullptr, ticket);
 }
 
 extern "C" raster_status raster_server_submit_opts(raster_server* s, const raster_job* job,
                                                    const raster_options* opts, uint64_t* ticket) {
+    return raster_server_submit_stream(s, job, opts, nullptr, ticket);
+}
+
+// An event and a sketch buffer from the server's free lists (or new ones).
+static raster_status take_submit_resources(raster_server* s, hipEvent_t* ready, hipEvent_t* sketched,
+                                           SketchBuf* sk) {
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        for (hipEvent_t* e : {ready, sketched}) {
+            if (!s->free_events.empty()) {
+                *e = s->free_events.back();
+                s->free_events.pop_back();
+            }
+        }
+        if (!s->free_sketches.empty()) {
+            *sk = s->free_sketches.back();
+            s->free_sketches.pop_back();
+        }
+    }
+    for (hipEvent_t* e : {ready, sketched})
+        if (!*e) HIP_TRY_S(hipEventCreateWithFlags(e, hipEventDisableTiming), "server event");
+    if (!sk->dev) {
+        const size_t regs = (size_t)kHllReps << kHllLog2;
+        std::lock_guard<std::mutex> g(s->mu);
+        HIP_TRY_S(s->sk_bufs.take((void**)&sk->dev, regs * sizeof(uint32_t)), "server sketch");
+        HIP_TRY_S(hipHostMalloc((void**)&sk->host, regs * sizeof(uint32_t), hipHostMallocDefault), "server sketch");
+    }
+    return RASTER_OK;
+}
+
+extern "C" raster_status raster_server_submit_stream(raster_server* s, const raster_job* job,
+                                                     const raster_options* opts, hipStream_t stream,
+                                                     uint64_t* ticket) {
     if (!s || !job || !ticket) return fail(RASTER_E_INVAL, "NULL argument");
     raster_status st = validate_job(*job, 0);
     if (st == RASTER_OK) st = check_options(opts);
     if (st == RASTER_OK && opts && opts->dims == 3)
         st = fail(RASTER_E_INVAL, "server jobs take two-dimensional points only");
     if (st != RASTER_OK) return st;
-    const size_t bytes = job_bytes(*job);
-    if (bytes > s->budget)
-        return fail(RASTER_E_BUDGET, "job needs about %zu bytes of device memory, more than the budget %zu", bytes,
+    // the smallest footprint the job can have (a single distinct tile)
+    const size_t least = job_footprint(job->n, 1.0);
+    if (least > s->budget)
+        return fail(RASTER_E_BUDGET, "job needs at least %zu bytes of device memory, more than the budget %zu", least,
                     s->budget);
     ServerJob* j = new ServerJob();
     j->job = *job;
     if (opts) j->opts = raster_options{opts->metric, opts->delta, opts->square_step ? 1u : 0u, 2u};
-    j->bytes = bytes;
+    st = take_submit_resources(s, &j->ready, &j->sketched, &j->sk);
+    if (st != RASTER_OK) {
+        delete j;
+        return st;
+    }
+    double sc = job->scale;
+    if (!(sc > 0.0)) scale_for_precision(job->precision, &sc);
+    hipError_t e = hipEventRecord(j->ready, stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s->sk_stream, j->ready, 0);
+    if (e == hipSuccess) e = launch_zero_u64((uint64_t*)j->sk.dev, ((size_t)kHllReps << kHllLog2) / 2, s->sk_stream);
+    if (e == hipSuccess && job->n > 0)
+        e = launch_points_hll(job->d_points, job->n, (int)job->dt, sc, j->sk.dev, s->sk_stream, 2);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(j->sk.host, j->sk.dev, ((size_t)kHllReps << kHllLog2) * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, s->sk_stream);
+    if (e == hipSuccess) e = hipEventRecord(j->sketched, s->sk_stream);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(s->sk_stream);
+        std::lock_guard<std::mutex> g(s->mu);
+        s->free_events.push_back(j->ready);
+        s->free_events.push_back(j->sketched);
+        s->free_sketches.push_back(j->sk);
+        delete j;
+        return hip_fail(e, "served job sketch");
+    }
     j->submitted = std::chrono::steady_clock::now();
     {
         std::lock_guard<std::mutex> g(s->mu);
         if (s->stop) {
+            (void)hipEventSynchronize(j->sketched);
+            s->free_events.push_back(j->ready);
+            s->free_events.push_back(j->sketched);
+            s->free_sketches.push_back(j->sk);
             delete j;
             return fail(RASTER_E_STATE, "server is stopping");
         }
@@ -880,6 +1075,14 @@ extern "C" raster_status raster_server_wait(raster_server* s, uint64_t ticket, r
     return RASTER_OK;
 }
 
+extern "C" raster_status raster_server_memory(raster_server* s, size_t* budget, size_t* peak_charged) {
+    if (!s) return fail(RASTER_E_INVAL, "server is NULL");
+    std::lock_guard<std::mutex> g(s->mu);
+    if (budget) *budget = s->budget;
+    if (peak_charged) *peak_charged = s->peak_charged;
+    return RASTER_OK;
+}
+
 extern "C" void raster_server_destroy(raster_server* s) {
     if (!s) return;
     {
@@ -889,10 +1092,19 @@ extern "C" void raster_server_destroy(raster_server* s) {
     s->cv_work.notify_all();
     for (std::thread& t : s->workers)
         if (t.joinable()) t.join();
+    if (s->sk_stream) (void)hipStreamSynchronize(s->sk_stream);
     for (auto& kv : s->jobs) {
         raster_result_free(kv.second->result);
+        if (kv.second->ready) s->free_events.push_back(kv.second->ready);
+        if (kv.second->sketched) s->free_events.push_back(kv.second->sketched);
+        if (kv.second->sk.dev) s->free_sketches.push_back(kv.second->sk);
         delete kv.second;
     }
     for (BatchEngine* b : s->engines) delete b;
+    for (hipEvent_t e : s->free_events) (void)hipEventDestroy(e);
+    for (SketchBuf& b : s->free_sketches)
+        if (b.host) (void)hipHostFree(b.host);
+    s->sk_bufs.release_all();
+    if (s->sk_stream) (void)hipStreamDestroy(s->sk_stream);
     delete s;
 }

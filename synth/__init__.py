@@ -23,7 +23,7 @@ import numpy as np
 
 __all__ = [
     "rng_for", "blobs", "blobs3d", "plain_small", "zipf_hot", "paper_scale_chunk",
-    "paper_scale_centres", "batch_jobs", "served_trace", "JobSpec",
+    "paper_scale_centres", "batch_jobs", "served_trace", "served_parity_slice", "JobSpec",
     "PLAIN_SMALL", "ZIPF_HOT", "PAPER_SCALE",
 ]
 
@@ -221,3 +221,13 @@ def served_trace(seed: int = 5, rate: float = 200.0, duration_s: float = 30.0,
                     precision=int(p[j]), tau=int(tau[j]), mu=int(mu[j]),
                     dtype="f32" if dts[j] else "f64", arrival_s=float(arrivals[j]))
             for j in range(k)]
+
+
+def served_parity_slice(seed: int = 5, head_s: float = 0.5) -> list[JobSpec]:
+    """Jobs of the served workload (200 jobs/s for 30 s) used for full-size
+    parity: every job arriving in the first ``head_s`` seconds, plus the
+    largest job of the whole trace, each at its full size and dtype."""
+    trace = served_trace(seed=seed, rate=200.0, duration_s=30.0)
+    head = [s for s in trace if s.arrival_s < head_s]
+    big = max(trace, key=lambda s: s.n)
+    return head + ([big] if big not in head else [])

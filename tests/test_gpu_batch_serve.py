@@ -94,11 +94,35 @@ def test_batch_graph_replay_and_recapture(raster, torch, batch24):
             same_result(first[k], other[k], f"tuning {tuning} job {k}")
 
 
+def _lowbias32(x):
+    """C. Wellons' 32-bit mixer, as the library hashes tiles (test-local)."""
+    x = np.asarray(x, dtype=np.uint32)
+    x = x ^ (x >> np.uint32(16))
+    x = x * np.uint32(0x7FEB352D)
+    x = x ^ (x >> np.uint32(15))
+    x = x * np.uint32(0x846CA68B)
+    return x ^ (x >> np.uint32(16))
+
+
+def _unsketched_noise(n, precision, seed):
+    """Uniform noise with every point removed whose tile falls in the fixed
+    1/64 hash sample that the batch's distinct-tile sketch reads: the sketch
+    sees almost no tile, the job's batch table gets its smallest size and
+    overflows, and the job must be redone alone."""
+    rng = np.random.default_rng(seed)
+    pts = rng.uniform(0.0, 1000.0, size=(3 * n // 2, 2))
+    s = 10.0 ** precision
+    kx = np.trunc(pts[:, 0] * s).astype(np.int64)
+    ky = np.trunc(pts[:, 1] * s).astype(np.int64)
+    bx = (kx + (1 << 31)).astype(np.uint64).astype(np.uint32)
+    by = (ky + (1 << 31)).astype(np.uint64).astype(np.uint32)
+    with np.errstate(over="ignore"):
+        h = _lowbias32(bx * np.uint32(0x9E3779B9) + by)
+    return np.ascontiguousarray(pts[(h & np.uint32(63)) != 0][:n])
+
+
 def test_batch_spilled_job_is_redone(raster, torch):
-    # uniform noise: nearly every point its own tile, far more than the table
-    # sized for n/8 tiles can hold, so the job spills and is redone alone
-    rng = np.random.default_rng(9)
-    noise = rng.uniform(0.0, 1000.0, size=(400_000, 2))
+    noise = _unsketched_noise(400_000, 2, seed=9)
     small = synth.plain_small(1)[:50_000]
     d1, d2 = dev(noise, torch), dev(small, torch)
     for mode in (0, 1):
@@ -108,6 +132,8 @@ def test_batch_spilled_job_is_redone(raster, torch):
                                         dict(points=d2, precision=1, tau=5, mu=4)])
         finally:
             raster.set_tuning(None)
+        assert res[0].stats["redone"] == 1, f"mode {mode}: the job fit its batch table"
+        assert res[1].stats["redone"] == 0
         assert_same(res[0], oracle.cluster(noise, tau=1, mu=1, precision=2), f"spilled job, mode {mode}")
         assert_same(res[1], oracle.cluster(small, tau=5, mu=4, precision=1), f"neighbour of spilled job, mode {mode}")
 
@@ -189,3 +215,52 @@ def test_autotuner_choice_gives_same_results(raster, torch, batch24, tmp_path, m
         raster.set_tuning(None)
     for k in range(len(batch24)):
         same_result(base[k], res[k], f"autotuned job {k}")
+
+
+def test_server_orders_after_producer(raster, torch):
+    """Points still being written on the submitter's stream are read only
+    once that stream has written them."""
+    pts = synth.plain_small(1)
+    base = dev(pts, torch)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        out = torch.full_like(base, 1.0e6)   # until the copy lands: every point on one far tile
+        torch.cuda._sleep(20_000_000)        # the producer is still busy when the job is submitted
+        out.copy_(base)
+        srv = raster.Server(budget_bytes=1 << 30, max_slots=2)
+        try:
+            t = srv.submit(out, tau=5, mu=4, precision=1)
+            r, _ = srv.wait(t)
+        finally:
+            srv.close()
+    torch.cuda.synchronize()
+    same_result(r, raster.cluster(base, precision=1, tau=5, mu=4), "job submitted behind its producer")
+    assert_same(r, oracle.cluster(pts, tau=5, mu=4, precision=1), "job submitted behind its producer")
+
+
+def test_server_budget_bounds_device_memory(raster, torch):
+    """Noise-heavy jobs (p=3: almost every point its own tile, tables many
+    times an n/8 guess) under a budget that holds about two of them: the
+    library's in-use device bytes stay within the budget."""
+    specs = [synth.JobSpec(seed=7000 + k, n=300_000 + 60_000 * k, precision=3, tau=3, mu=2) for k in range(8)]
+    host = [synth.job_points(sp) for sp in specs]
+    devs = [dev(h, torch) for h in host]
+    plain = [raster.cluster(d, precision=sp.precision, tau=sp.tau, mu=sp.mu) for sp, d in zip(specs, devs)]
+    budget = 192 << 20
+    torch.cuda.synchronize()
+    srv = raster.Server(budget_bytes=budget, max_slots=3)
+    try:
+        used0, _, _ = raster.memory_stats(reset_peak=True)
+        tickets = [srv.submit(d, tau=sp.tau, mu=sp.mu, precision=sp.precision) for sp, d in zip(specs, devs)]
+        results = [srv.wait(t)[0] for t in tickets]
+        _, _, peak = raster.memory_stats()
+        _, charged = srv.memory()
+    finally:
+        srv.close()
+    _say(f"budget {budget >> 20} MiB: peak in-use {(peak - used0) >> 20} MiB above the start, "
+         f"largest charge {charged >> 20} MiB")
+    assert charged <= budget
+    assert peak - used0 <= budget, f"in-use device bytes rose by {peak - used0}, budget {budget}"
+    for k, (r, p) in enumerate(zip(results, plain)):
+        same_result(r, p, f"budgeted job {k}")

@@ -15,6 +15,7 @@ import pytest
 
 import oracle
 import synth
+from digest import biased
 from gpu_util import assert_same, dev
 
 pytestmark = pytest.mark.gpu
@@ -113,7 +114,7 @@ def test_paper_stream_full_size_sampled(raster, torch):
     assert kx.shape[0] == stats["tiles"] and stats["clusters"] > 900_000
     # every output tile meets tau; clusters meet mu and carry their min key
     assert cnt.min() >= tau
-    keys = raster.biased_key(kx, ky)
+    keys = biased(kx, ky)
     order = np.argsort(lab, kind="stable")
     lab_s, keys_s = lab[order], keys[order]
     starts = np.r_[0, np.nonzero(np.diff(lab_s))[0] + 1]
@@ -150,7 +151,7 @@ def test_paper_stream_full_size_sampled(raster, torch):
         ring = {(x + dx, y + dy) for x, y in tiles for dx in (-1, 0, 1) for dy in (-1, 0, 1)} - tiles
         assert all(exact[t] < tau for t in ring), label
         assert len(_components(tiles)) == 1, label
-        assert int(raster.biased_key([min(tiles)[0]], [min(tiles)[1]])[0]) == label
+        assert int(biased([min(tiles)[0]], [min(tiles)[1]])[0]) == label
     # per-point labels over all 500M points: each cluster holds exactly the
     # points its tiles counted, the rest are noise, and sampled points carry
     # the label of their tile as the oracle projects and looks it up
