@@ -183,6 +183,38 @@ raster_status raster_cluster_p_opts(const void* d_points, int64_t n, raster_dtyp
                                     uint32_t tau, uint32_t mu, const raster_options* opts, hipStream_t stream,
                                     raster_result** out);
 
+/* ---- plain form without device allocation ------------------------------------ */
+
+/* For callers that cannot allocate device memory: code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * raster_cluster (precision p in [0, 15], Chebyshev 1, two dimensions) on at
+ * most RASTER_NOALLOC_MAX_POINTS points, with every scratch buffer (tile
+ * table, compact arrays, union-find words, counters) in one fixed device
+ * array of RASTER_NOALLOC_SCRATCH_BYTES that the library holds on each device
+ * it runs on until the process ends; the call itself allocates nothing.
+ * The kept rows are written to the caller's device arrays d_kx, d_ky (int32),
+ * d_count (uint32) and d_label (uint64, the biased key of the cluster's
+ * smallest tile), each of at least max_rows elements, in no particular
+ * order; *rows (host) receives the number of rows t.  The rows, as a set,
+ * are those of raster_cluster on the same points.  stats, if not NULL,
+ * receives the counters (the phase times are 0).  Synchronises `stream`.
+ * Errors: E_INVAL for the argument errors of raster_cluster, for n above
+ * RASTER_NOALLOC_MAX_POINTS, for rows NULL, and when t > max_rows (then *rows
+ * is t and no row is written: max_rows = n always suffices); E_RANGE as for
+ * raster_cluster; E_NOMEM if the fixed table (at least four slots per point)
+ * overflows, which takes an adversarial point set.
+ * The array is shared by every call on the device and keeps the last call's
+ * contents; each call clears what must start empty.  Calls on one device are
+ * serialised by the library (a call holds the device's array until it has
+ * synchronised its stream); calls from another process use that process's
+ * own array. */
+#define RASTER_NOALLOC_MAX_POINTS (1 << 19)
+#define RASTER_NOALLOC_SCRATCH_BYTES 52634368u
+raster_status raster_cluster_noalloc(const void* d_points, int64_t n, raster_dtype dt, int32_t precision,
+                                     uint32_t tau, uint32_t mu, hipStream_t stream, int32_t* d_kx,
+                                     int32_t* d_ky, uint32_t* d_count, uint64_t* d_label, int64_t max_rows,
+                                     int64_t* rows, raster_stats* stats);
+
 /* ---- results --------------------------------------------------------------- */
 
 int64_t raster_result_num_tiles(const raster_result* r);    /* rows t, or -1 if r is NULL */

@@ -19,7 +19,7 @@ from dataclasses import dataclass
 
 __all__ = [
     "cluster", "Stream", "cluster_batch", "Server", "Result", "RasterError", "RasterNotBuilt",
-    "set_tuning", "get_tuning", "library_path", "load", "memory_stats", "F32", "F64",
+    "set_tuning", "get_tuning", "library_path", "load", "memory_stats", "F32", "F64", "cluster_noalloc",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -91,6 +91,8 @@ def load():
     sig = {
         "raster_cluster": (st, [vp, i64, ctypes.c_int, i32, u32, u32, vp, pp]),
         "raster_cluster_scaled": (st, [vp, i64, ctypes.c_int, dbl, u32, u32, vp, pp]),
+        "raster_cluster_noalloc": (st, [vp, i64, ctypes.c_int, i32, u32, u32, vp, vp, vp, vp, vp, i64,
+                                        ctypes.POINTER(i64), ctypes.POINTER(_Stats)]),
         "raster_result_num_tiles": (i64, [vp]),
         "raster_result_num_clusters": (i64, [vp]),
         "raster_result_arrays": (st, [vp, pp, pp, pp, pp]),
@@ -328,6 +330,41 @@ def cluster(points, tau: int, mu: int, precision: int | None = None, scale: floa
         rc = lib.raster_cluster(p, n, dt, int(precision), int(tau), int(mu), st, ctypes.byref(out))
     _check(rc, "raster_cluster")
     return Result(out, stream)
+
+
+NOALLOC_MAX_POINTS = 1 << 19
+
+
+def cluster_noalloc(points, tau: int, mu: int, precision: int, max_rows: int | None = None, stream=None):
+    """raster_cluster_noalloc: Algorithm 1 (eight neighbours) on at most
+    NOALLOC_MAX_POINTS points with the library's fixed scratch, so that the
+    library allocates no device memory.  The output rows go to device tensors
+    allocated here, on the caller's side of the boundary, with room for
+    ``max_rows`` rows (default: one per point).  Returns ``(kx, ky, count,
+    label, stats)``: int32, int32, uint32 and uint64 tensors of the t rows (in
+    no particular order) and the counters as a dict."""
+    torch = _torch()
+    lib = load()
+    p, n, dt = _points(points, 2)
+    cap = n if max_rows is None else int(max_rows)
+    dev = points.device
+    kx = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    ky = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    cnt = torch.empty(max(cap, 1), dtype=torch.uint32, device=dev)
+    lab = torch.empty(max(cap, 1), dtype=torch.uint64, device=dev)
+    rows = ctypes.c_int64()
+    s = _Stats()
+    rc = lib.raster_cluster_noalloc(p, n, dt, int(precision), int(tau), int(mu), _stream_handle(stream),
+                                    ctypes.c_void_p(kx.data_ptr()), ctypes.c_void_p(ky.data_ptr()),
+                                    ctypes.c_void_p(cnt.data_ptr()), ctypes.c_void_p(lab.data_ptr()), cap,
+                                    ctypes.byref(rows), ctypes.byref(s))
+    if rc != 0:
+        err = RasterError(rc, "raster_cluster_noalloc", (lib.raster_last_error() or b"").decode())
+        err.rows = int(rows.value)
+        raise err
+    t = int(rows.value)
+    stats = {name: getattr(s, name) for name, _ in _Stats._fields_}
+    return kx[:t], ky[:t], cnt[:t], lab[:t], stats
 
 
 class Stream:

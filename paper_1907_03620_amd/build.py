@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libraster.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["raster_kernels.hip", "raster_host.cpp", "raster_serve.cpp"]
+SOURCES = ["raster_kernels.hip", "raster_host.cpp", "raster_serve.cpp", "raster_noalloc.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",

@@ -265,6 +265,19 @@ hipError_t launch_filter(const JobView& jv, const uint64_t* s_key, const uint32_
                          uint64_t* out_label, uint32_t* out_job, uint32_t* partials, unsigned long long* ctr,
                          hipStream_t stream, int32_t* out_kz = nullptr);
 
+// The two halves of launch_filter: the kept-row count (ctr[C_TILES], and the
+// per-block offsets in partials), then the scatter of the rows.
+hipError_t launch_filter_count(const JobView& jv, const uint32_t* root, const uint32_t* size, uint32_t* partials,
+                               unsigned long long* ctr, hipStream_t stream);
+hipError_t launch_filter_scatter(const JobView& jv, const uint64_t* s_key, const uint32_t* s_count,
+                                 const uint32_t* root, const uint32_t* size, int32_t* out_kx, int32_t* out_ky,
+                                 uint32_t* out_count, uint64_t* out_label, uint32_t* out_job,
+                                 const uint32_t* partials, const unsigned long long* ctr, hipStream_t stream,
+                                 int32_t* out_kz = nullptr);
+
+// Stores a one-job view's descriptor (d, j) at d_dims / d_job on the device.
+hipError_t launch_store_job(const Dims& d, const JobInfo& j, Dims* d_dims, JobInfo* d_job, hipStream_t stream);
+
 // Batched counting: one launch over the point tiles of every job, each point
 // added to its job's table with device atomics (LDS pre-aggregation per tile
 // when tu.preagg_slots > 0).  A key that finds no room raises its job's

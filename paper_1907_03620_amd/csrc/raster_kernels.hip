@@ -1916,6 +1916,13 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_filter_scatter(JobView jv, con
     }
 }
 
+// Writes a one-job descriptor (passed by value with the launch) to device
+// memory, so that a caller needs no host-to-device copy for it.
+__global__ void k_store_job(Dims d, JobInfo j, Dims* d_dims, JobInfo* d_job) {
+    *d_dims = d;
+    *d_job = j;
+}
+
 // ---- distinct-tile sketch of one point set -------------------------------------
 //
 // The hll_sample sketch of n points into kHllReps register replicas (one per
@@ -2555,15 +2562,36 @@ hipError_t launch_agglomerate(const Slot* tab, uint64_t slots_max, const JobView
     return hipGetLastError();
 }
 
+hipError_t launch_filter_count(const JobView& jv, const uint32_t* root, const uint32_t* size, uint32_t* partials,
+                               unsigned long long* ctr, hipStream_t stream) {
+    hipLaunchKernelGGL(k_filter_count, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, jv, root, size, partials,
+                       ctr);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, stream, partials, ctr + C_TILES);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter_scatter(const JobView& jv, const uint64_t* s_key, const uint32_t* s_count,
+                                 const uint32_t* root, const uint32_t* size, int32_t* out_kx, int32_t* out_ky,
+                                 uint32_t* out_count, uint64_t* out_label, uint32_t* out_job,
+                                 const uint32_t* partials, const unsigned long long* ctr, hipStream_t stream,
+                                 int32_t* out_kz) {
+    hipLaunchKernelGGL(k_filter_scatter, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, jv, s_key, s_count, root,
+                       size, partials, ctr, out_kx, out_ky, out_kz, out_count, out_label, out_job);
+    return hipGetLastError();
+}
+
 hipError_t launch_filter(const JobView& jv, const uint64_t* s_key, const uint32_t* s_count, const uint32_t* root,
                          const uint32_t* size, int32_t* out_kx, int32_t* out_ky, uint32_t* out_count,
                          uint64_t* out_label, uint32_t* out_job, uint32_t* partials, unsigned long long* ctr,
                          hipStream_t stream, int32_t* out_kz) {
-    hipLaunchKernelGGL(k_filter_count, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, jv, root, size, partials,
-                       ctr);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, stream, partials, ctr + C_TILES);
-    hipLaunchKernelGGL(k_filter_scatter, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, jv, s_key, s_count, root,
-                       size, partials, ctr, out_kx, out_ky, out_kz, out_count, out_label, out_job);
+    hipError_t e = launch_filter_count(jv, root, size, partials, ctr, stream);
+    if (e != hipSuccess) return e;
+    return launch_filter_scatter(jv, s_key, s_count, root, size, out_kx, out_ky, out_count, out_label, out_job,
+                                 partials, ctr, stream, out_kz);
+}
+
+hipError_t launch_store_job(const Dims& d, const JobInfo& j, Dims* d_dims, JobInfo* d_job, hipStream_t stream) {
+    hipLaunchKernelGGL(k_store_job, dim3(1), dim3(1), 0, stream, d, j, d_dims, d_job);
     return hipGetLastError();
 }
 
