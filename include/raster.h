@@ -112,6 +112,9 @@ typedef struct raster_stats {
     int32_t flushes;           /* binned path: groups of keys applied to the table */
     int32_t redone;            /* batched and served jobs: 1 when the job overflowed its
                                   batch table and was redone alone by the plain path */
+    int32_t key_frame;         /* 1 when the table placed keys by a key frame and the
+                                  binned contraction moved 4-byte entries         */
+    int32_t reserved_;         /* 0                                                */
 } raster_stats;
 
 /* Launch knobs of the contraction kernels.  Any value gives the same result;
@@ -126,7 +129,10 @@ typedef struct raster_tuning {
     int32_t mode;         /* counting path: 0 auto, 1 direct (one device atomic per point),
                              2 binned (keys binned by table partition, then each partition
                              updated in LDS by one workgroup; used when the table has
-                             128..65536 partitions of 4096 slots, else direct)            */
+                             128..65536 partitions of 4096 slots, else direct), 3 binned
+                             with 8-byte bin entries only (2 and 0 move 4-byte entries
+                             when a sample of the first chunk shows the tiles of a
+                             two-dimensional input within a window of 2^20 x 2^20)     */
     int32_t group_mpoints; /* binned path: millions of points binned before the table is
                               updated (1..4096); bounds the binning and spill buffers      */
 } raster_tuning;

@@ -55,7 +55,8 @@ class _Stats(ctypes.Structure):
                 ("us_agglomerate", ctypes.c_float), ("us_filter", ctypes.c_float),
                 ("count_launches", ctypes.c_int64), ("us_count_kernel", ctypes.c_float),
                 ("us_bin_keys", ctypes.c_float), ("us_aggregate", ctypes.c_float),
-                ("flushes", ctypes.c_int32), ("redone", ctypes.c_int32)]
+                ("flushes", ctypes.c_int32), ("redone", ctypes.c_int32),
+                ("key_frame", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
 class _Tuning(ctypes.Structure):

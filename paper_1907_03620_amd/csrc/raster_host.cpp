@@ -491,6 +491,42 @@ raster_status TableRun::alloc_table(uint64_t c, Slot** t, uint64_t* c_out) {
     return RASTER_OK;
 }
 
+// Points whose tile box decides the key frame: a sample from the start of the
+// first chunk (the frame only has to hold most keys; the others go to the
+// table directly).
+static constexpr int64_t kFrameSample = 1 << 20;
+
+// Chooses the key frame from the tile box of the sample: the frame is centred
+// on the box when the box, with a margin of 1/64 of its size plus 64 tiles on
+// each side, fits into 2^20 tiles per axis; otherwise the table stays
+// unframed.  Tuning mode 3 asks for the unframed binning.
+raster_status TableRun::decide_frame(const void* pts, int64_t n, raster_dtype dt) {
+    frame = Frame{0, 0, 0};
+    if (dims != 2 || tuning.mode == 3 || n <= 0) return RASTER_OK;
+    uint32_t* d = nullptr;
+    HIP_TRY(bufs.take((void**)&d, kBboxWords * sizeof(uint32_t)), "frame box");
+    HIP_TRY(launch_key_bbox(pts, std::min<int64_t>(n, kFrameSample), (int)dt, scale, d, stream), "frame box");
+    uint32_t bb[4] = {1, 0, 1, 0};
+    HIP_TRY(hipMemcpyAsync(bb, d, sizeof bb, hipMemcpyDeviceToHost, stream), "frame box copy");
+    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    bufs.give_back(d);
+    if (bb[0] > bb[1] || bb[2] > bb[3]) return RASTER_OK;
+    const int64_t side = (int64_t)1 << kFrameLog2;
+    auto origin = [&](uint32_t lo, uint32_t hi, uint32_t* o) {
+        const int64_t w = (int64_t)hi - (int64_t)lo + 1;
+        const int64_t margin = w / 64 + 64;
+        if (w + 2 * margin > side) return false;
+        int64_t f = (int64_t)lo - (side - w) / 2;
+        f = std::max<int64_t>(f, 0);
+        f = std::min<int64_t>(f, ((int64_t)1 << 32) - side);
+        *o = (uint32_t)f;
+        return true;
+    };
+    uint32_t fx = 0, fy = 0;
+    if (origin(bb[0], bb[1], &fx) && origin(bb[2], bb[3], &fy)) frame = Frame{1, fx, fy};
+    return RASTER_OK;
+}
+
 // Makes spill buffer b hold at least `need` records.  Only that buffer is
 // replaced, so records still waiting in the other one survive.
 raster_status TableRun::ensure_spill(int b, uint64_t need) {
@@ -571,8 +607,9 @@ raster_status TableRun::grow(uint64_t new_cap, uint64_t pending, int src) {
         if (st != RASTER_OK) return st;
         HIP_TRY(launch_zero_u64((uint64_t*)ctr + C_INSERTED, 2, stream), "reset counters");
         SpillBuf sp{spill_keys[dst], spill_counts[dst], spill_cap[dst]};
-        HIP_TRY(launch_rehash(tab, cap, nt, nc, sp, ctr, stream, dims == 3), "rehash");
-        HIP_TRY(launch_insert_records(spill_keys[src], spill_counts[src], pending, nt, nc, sp, ctr, stream, dims == 3),
+        HIP_TRY(launch_rehash(tab, cap, nt, nc, sp, ctr, stream, dims == 3, frame), "rehash");
+        HIP_TRY(launch_insert_records(spill_keys[src], spill_counts[src], pending, nt, nc, sp, ctr, stream, dims == 3,
+                                      frame),
                 "reinsert");
         raster_status ps = pull_counters();
         if (ps != RASTER_OK) return ps;
@@ -634,13 +671,15 @@ raster_status TableRun::ensure_bins(uint64_t want_points) {
     bin1 = nullptr;
     // a coarse list receives about want_points / (128 kBinRep) keys; the slack
     // is far beyond the binomial spread, and overflow only costs direct inserts
-    const uint64_t lists = (uint64_t)kBinRep * kCoarse;
+    const uint64_t lists = (uint64_t)kBinRep * coarse_buckets();
     const uint64_t per = want_points / lists;
     cap1 = (per + per / 50 + 1024 + 255) / 256 * 256;
-    HIP_TRY(bufs.take((void**)&bin1, lists * cap1 * sizeof(uint64_t)), "coarse buckets");
+    HIP_TRY(bufs.take((void**)&bin1, lists * cap1 * bin_entry_bytes()), "coarse buckets");
     if (!cursor1) {
-        HIP_TRY(bufs.take((void**)&cursor1, lists * sizeof(uint32_t)), "coarse cursors");
-        HIP_TRY(launch_zero_u64((uint64_t*)cursor1, lists / 2, stream), "zero cursors");
+        // room for the framed layout's lists, so that either layout can use it
+        const uint64_t n_cursors = (uint64_t)kBinRep * kFrameCoarse;
+        HIP_TRY(bufs.take((void**)&cursor1, n_cursors * sizeof(uint32_t)), "coarse cursors");
+        HIP_TRY(launch_zero_u64((uint64_t*)cursor1, n_cursors / 2, stream), "zero cursors");
     }
     bin_points = want_points;
     return RASTER_OK;
@@ -652,9 +691,13 @@ raster_status TableRun::flush() {
     raster_status st = settle();
     if (st != RASTER_OK) return st;
     if (sketch && (st = size_from_sketch(group_points)) != RASTER_OK) return st;
-    const Geo g = make_geo(cap, dims == 3);
+    const Geo g = geo();
     SpillBuf sp{spill_keys[0], spill_counts[0], spill_cap[0]};
-    if (!binned_geometry(g)) {
+    if (frame.on && !framed_binned_geometry(g)) {
+        HIP_TRY(launch_drain_bins_framed(reinterpret_cast<uint32_t*>(bin1), cap1, cursor1, tab, cap, frame, sp, ctr,
+                                         stream),
+                "drain bins");
+    } else if (!frame.on && !binned_geometry(g)) {
         HIP_TRY(launch_drain_bins(bin1, cap1, cursor1, tab, cap, sp, ctr, stream, dims == 3), "drain bins");
     } else {
         const uint64_t lists = (uint64_t)kBinRep << g.p_log2;  // kBinRep lists per partition
@@ -668,17 +711,28 @@ raster_status TableRun::flush() {
             cursor2 = nullptr;
             bin2_slots = lists * c2 + lists * c2 / 4;  // headroom for later groups
             cursor2_n = lists;
-            HIP_TRY(bufs.take((void**)&bin2, bin2_slots * sizeof(uint64_t)), "partition buckets");
+            HIP_TRY(bufs.take((void**)&bin2, bin2_slots * bin_entry_bytes()), "partition buckets");
             HIP_TRY(bufs.take((void**)&cursor2, cursor2_n * sizeof(uint32_t)), "partition cursors");
         }
         c2 = bin2_slots / lists;
         hipEvent_t a = nullptr;
         if ((st = span_begin(1, &a)) != RASTER_OK) return st;
-        HIP_TRY(launch_bin_keys(bin1, cap1, cursor1, bin2, c2, cursor2, tab, cap, sp, ctr, stream, dims == 3),
-                "bin keys");
+        if (frame.on)
+            HIP_TRY(launch_bin_keys_framed(reinterpret_cast<uint32_t*>(bin1), cap1, cursor1,
+                                           reinterpret_cast<uint32_t*>(bin2), c2, cursor2, tab, cap, frame, sp, ctr,
+                                           stream),
+                    "bin keys");
+        else
+            HIP_TRY(launch_bin_keys(bin1, cap1, cursor1, bin2, c2, cursor2, tab, cap, sp, ctr, stream, dims == 3),
+                    "bin keys");
         if ((st = span_end(1, a)) != RASTER_OK) return st;
         if ((st = span_begin(2, &a)) != RASTER_OK) return st;
-        HIP_TRY(launch_aggregate(bin2, c2, cursor2, cursor1, tab, cap, sp, ctr, stream), "aggregate");
+        if (frame.on)
+            HIP_TRY(launch_aggregate_framed(reinterpret_cast<uint32_t*>(bin2), c2, cursor2, cursor1, tab, cap, frame,
+                                            sp, ctr, stream),
+                    "aggregate");
+        else
+            HIP_TRY(launch_aggregate(bin2, c2, cursor2, cursor1, tab, cap, sp, ctr, stream), "aggregate");
         if ((st = span_end(2, a)) != RASTER_OK) return st;
     }
     flushes += 1;
@@ -696,8 +750,8 @@ raster_status TableRun::flush() {
 // are.  Errors of the earlier chunks are then reported by a later call.
 bool TableRun::can_bin_unsettled(int64_t n) const {
     if (!chunk_pending || !last_binned || single_shot || n <= 0 || (uint64_t)n > group_budget) return false;
-    const Geo g = make_geo(cap, dims == 3);
-    const bool binned = (tuning.mode == 2 || (tuning.mode == 0 && (uint64_t)n >= cap / 8)) && binned_geometry(g);
+    const Geo g = geo();
+    const bool binned = (tuning.mode >= 2 || (tuning.mode == 0 && (uint64_t)n >= cap / 8)) && binned_geometry(g);
     if (!binned || !bin1 || group_points == 0 || group_points + (uint64_t)n > bin_points) return false;
     return spill_cap[0] >= std::min<uint64_t>(group_budget, group_points + (uint64_t)n);
 }
@@ -747,12 +801,19 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
     for (int64_t off = 0; off < n;) {
         const int64_t piece = std::min<int64_t>(n - off, (int64_t)group_budget);
         const void* p = (const char*)pts + (size_t)off * point_bytes;
-        const Geo g = make_geo(cap, dims == 3);
-        const bool binned = (tuning.mode == 2 || (tuning.mode == 0 && (uint64_t)piece >= cap / 8)) &&
+        const Geo g = geo();
+        const bool binned = (tuning.mode >= 2 || (tuning.mode == 0 && (uint64_t)piece >= cap / 8)) &&
                             binned_geometry(g);
         SpillBuf sp{spill_keys[0], spill_counts[0], spill_cap[0]};
         hipEvent_t a = nullptr;
         if (binned) {
+            // the key frame comes from the first binned chunk of an empty
+            // table; a table that already holds keys keeps its placement
+            if (!frame_decided) {
+                st = n_points == 0 ? decide_frame(p, piece, dt) : RASTER_OK;
+                frame_decided = true;
+                if (st != RASTER_OK) return st;
+            }
             // a one-shot call bins exactly its points; a stream expects more
             // chunks like this one and bins several before updating the table
             st = ensure_bins(single_shot ? (uint64_t)piece : 16 * (uint64_t)piece);
@@ -766,9 +827,14 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
             if ((st = span_begin(0, &a)) != RASTER_OK) return st;
             // the sketch of the binned keys sizes the table before the flush
             if ((st = ensure_sketch()) != RASTER_OK) return st;
-            HIP_TRY(launch_bin_points(p, piece, (int)dt, scale, bin1, cap1, cursor1, tab, cap, sp, ctr, sketch, stream,
-                                      (int)dims),
-                    "bin points");
+            if (frame.on)
+                HIP_TRY(launch_bin_points_framed(p, piece, (int)dt, scale, reinterpret_cast<uint32_t*>(bin1), cap1,
+                                                 cursor1, tab, cap, frame, sp, ctr, sketch, stream),
+                        "bin points");
+            else
+                HIP_TRY(launch_bin_points(p, piece, (int)dt, scale, bin1, cap1, cursor1, tab, cap, sp, ctr, sketch,
+                                          stream, (int)dims),
+                        "bin points");
             if ((st = span_end(0, a)) != RASTER_OK) return st;
             group_points += (uint64_t)piece;
         } else {
@@ -782,7 +848,7 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
             }
             if ((st = span_begin(0, &a)) != RASTER_OK) return st;
             HIP_TRY(launch_project_count(p, piece, (int)dt, scale, tab, cap, sp, ctr, kernel_tuning(tuning), stream,
-                                         (int)dims),
+                                         (int)dims, frame),
                     "project_count");
             if ((st = span_end(0, a)) != RASTER_OK) return st;
         }
@@ -844,6 +910,9 @@ raster_status TableRun::finish(raster_result** out) {
     single.job.mu = mu;
     single.job.dtype = 0;
     single.job.first_tile = 0;
+    single.job.framed = frame.on;
+    single.job.fx = frame.fx;
+    single.job.fy = frame.fy;
     single.dims.slots = cap;
     single.dims.njobs = 1;
     single.dims.tiles = 0;
@@ -890,6 +959,7 @@ raster_status TableRun::finish(raster_result** out) {
     S.us_bin_keys = (float)span_us[1];
     S.us_aggregate = (float)span_us[2];
     S.flushes = flushes;
+    S.key_frame = frame.on ? 1 : 0;
     r->tiles = S.tiles;
     r->clusters = S.clusters;
     if (h_ctr[C_ERROR] & kErrInternal) return drop(fail(RASTER_E_DEVICE, "agglomeration state inconsistent"));
@@ -1281,7 +1351,7 @@ raster_status raster_set_tuning(const raster_tuning* t) {
             (v.preagg_slots < 256 || v.preagg_slots > 4096 || (v.preagg_slots & (v.preagg_slots - 1))))
             return fail(RASTER_E_INVAL, "preagg_slots must be 0 or a power of two in [256, 4096]");
         if (!(v.load_factor > 0.05f && v.load_factor <= 0.9f)) return fail(RASTER_E_INVAL, "load_factor in (0.05, 0.9]");
-        if (v.mode < 0 || v.mode > 2) return fail(RASTER_E_INVAL, "mode must be 0, 1 or 2");
+        if (v.mode < 0 || v.mode > 3) return fail(RASTER_E_INVAL, "mode must be 0, 1, 2 or 3");
         if (v.group_mpoints < 1 || v.group_mpoints > 4096) return fail(RASTER_E_INVAL, "group_mpoints in [1, 4096]");
     }
     std::lock_guard<std::mutex> g(g_tuning_mu);

@@ -35,19 +35,44 @@ constexpr uint32_t kPartLog2 = 12;
 // which bounds how unevenly keys spread over partitions.
 constexpr uint32_t kSuperLog2 = 3;
 constexpr uint64_t kSuperMask = ~((((1ull << kSuperLog2) - 1) << 32) | ((1ull << kSuperLog2) - 1));
+// Key frame of a two-dimensional table: a window of 2^kFrameLog2 x
+// 2^kFrameLog2 tiles whose smallest biased coordinates are (fx, fy).  A key
+// inside the frame is placed by a bijective 34-bit mix h of its super-tile's
+// position in the frame: its partition is the top bits of h, its home slot the
+// hash of its 32-bit "entry" (the low 26 bits of h and the key's position in
+// its super-tile).  The top kFrameCoarseLog2 bits of h pick the key's coarse
+// bucket in the binned contraction, so the coarse bucket and the entry give
+// the key back exactly, and the binning moves 4-byte entries instead of
+// 8-byte keys.  A key outside the frame is placed as in an unframed table.
+// on = 0: no frame.
+constexpr uint32_t kFrameLog2 = 20;
+constexpr uint32_t kFrameStBits = 2 * (kFrameLog2 - 3);  // bits of a super-tile's position (8 x 8 super-tiles)
+constexpr uint32_t kFrameCoarseLog2 = 8;
+constexpr uint32_t kFrameCoarse = 1u << kFrameCoarseLog2;
+constexpr uint32_t kFrameHLow = kFrameStBits - kFrameCoarseLog2;  // h bits held by an entry (26)
+struct Frame {
+    uint32_t on;
+    uint32_t fx, fy;  // biased coordinates of the frame's first tile
+};
+
 struct Geo {
     uint64_t cap;      // slots, a power of two
     uint32_t cp_log2;  // log2 slots per partition
     uint32_t p_log2;   // log2 partitions
     uint32_t d3;       // 1: three-dimensional keys (placed by 4x4x4 super-cubes)
+    uint32_t framed;   // 1: keys inside the frame (fx, fy) are placed by their frame position
+    uint32_t fx, fy;
 };
-__host__ __device__ inline Geo make_geo(uint64_t cap, bool d3 = false) {
+__host__ __device__ inline Geo make_geo(uint64_t cap, bool d3 = false, Frame f = Frame{0, 0, 0}) {
     const uint32_t l = (uint32_t)__builtin_ctzll(cap);  // cap is a power of two
     Geo g;
     g.cap = cap;
     g.cp_log2 = l < kPartLog2 ? l : kPartLog2;
     g.p_log2 = l - g.cp_log2;
     g.d3 = d3 ? 1u : 0u;
+    g.framed = (f.on && !d3) ? 1u : 0u;
+    g.fx = f.fx;
+    g.fy = f.fy;
     return g;
 }
 
@@ -72,6 +97,11 @@ constexpr uint32_t kHllReps = 64;
 
 inline bool binned_geometry(const Geo& g) {
     return g.cp_log2 == kPartLog2 && g.p_log2 >= kCoarseLog2 && (1ull << (g.p_log2 - kCoarseLog2)) <= kMaxFine;
+}
+// The same for the framed binning (kFrameCoarse coarse buckets of entries).
+inline bool framed_binned_geometry(const Geo& g) {
+    return g.framed && g.cp_log2 == kPartLog2 && g.p_log2 >= kFrameCoarseLog2 &&
+           (1ull << (g.p_log2 - kFrameCoarseLog2)) <= kMaxFine;
 }
 
 // One table slot: 16 bytes, so a probe and the count update touch one line.
@@ -119,7 +149,13 @@ struct JobInfo {
     uint32_t cshift;      // binned batches: log2 partitions per coarse bucket
     uint32_t cap2;        // binned batches: keys per partition list of the job
     uint64_t bin2_base;   // binned batches: first key of the job's partition lists
+    uint32_t framed;      // single tables: the table's key frame (Geo::framed, fx, fy)
+    uint32_t fx, fy;
+    uint32_t pad_;
 };
+__host__ __device__ inline Geo job_geo(const JobInfo& J, bool d3 = false) {
+    return make_geo(J.cap, d3, Frame{J.framed, J.fx, J.fy});
+}
 
 // One round of the link pass for a neighbourhood other than the eight
 // adjacent tiles: up to four backward offsets (the neighbour's key is smaller,
@@ -200,7 +236,36 @@ hipError_t launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t stream);
 // Projection + counting of n points into the table (dtype 1 = f32, 2 = f64).
 hipError_t launch_project_count(const void* pts, int64_t n, int dtype, double scale, Slot* tab,
                                  uint64_t cap, SpillBuf spill, unsigned long long* ctr,
-                                 const KernelTuning& tu, hipStream_t stream, int dims = 2);
+                                 const KernelTuning& tu, hipStream_t stream, int dims = 2, Frame frame = Frame{});
+
+// Tile bounding box of the first n points (two dimensions): out[0..3] =
+// smallest and largest biased x, smallest and largest biased y over the
+// points with a valid tile (out[0] > out[1] when there is none).  out holds
+// kBboxWords words (the rest is scratch).
+constexpr int kBboxWords = 4 + 4 * 256;
+hipError_t launch_key_bbox(const void* pts, int64_t n, int dtype, double scale, uint32_t* out, hipStream_t stream);
+
+// Framed binned contraction (two dimensions): level 1 appends the entry of
+// each point's key to coarse list (replica, h >> kFrameHLow) of bin1
+// (kBinRep * kFrameCoarse lists of cap1 entries, counts in cursor1); keys
+// outside the frame, and keys past a full list, go straight into the table.
+hipError_t launch_bin_points_framed(const void* pts, int64_t n, int dtype, double scale, uint32_t* bin1,
+                                   uint64_t cap1, uint32_t* cursor1, Slot* tab, uint64_t cap, Frame frame,
+                                   SpillBuf spill, unsigned long long* ctr, uint32_t* hll, hipStream_t stream);
+// Level 2: every coarse list into its partitions' lists (bin2, cap2 entries
+// per list; counts in cursor2, cleared here).
+hipError_t launch_bin_keys_framed(const uint32_t* bin1, uint64_t cap1, const uint32_t* cursor1, uint32_t* bin2,
+                                 uint64_t cap2, uint32_t* cursor2, Slot* tab, uint64_t cap, Frame frame,
+                                 SpillBuf spill, unsigned long long* ctr, hipStream_t stream);
+// Update: one workgroup per partition adds its entries to the table in LDS;
+// then clears cursor1.
+hipError_t launch_aggregate_framed(const uint32_t* bin2, uint64_t cap2, const uint32_t* cursor2, uint32_t* cursor1,
+                                  Slot* tab, uint64_t cap, Frame frame, SpillBuf spill, unsigned long long* ctr,
+                                  hipStream_t stream);
+// Direct insertion of every entry held in the coarse lists (tables outside
+// the framed binned geometry).  Clears cursor1.
+hipError_t launch_drain_bins_framed(const uint32_t* bin1, uint64_t cap1, uint32_t* cursor1, Slot* tab, uint64_t cap,
+                                   Frame frame, SpillBuf spill, unsigned long long* ctr, hipStream_t stream);
 
 // Binned contraction, level 1: project n points and append each key to its
 // coarse bucket: bucket b holds keys at bin1[b * cap1 + i], i < cursor1[b].
@@ -227,11 +292,12 @@ hipError_t launch_drain_bins(uint64_t* bin1, uint64_t cap1, uint32_t* cursor1, S
 // Insert n (key, count) records (spilled keys, or a rehash source).
 hipError_t launch_insert_records(const uint64_t* keys, const uint32_t* counts, uint64_t n,
                                  Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr,
-                                 hipStream_t stream, bool d3 = false);
+                                 hipStream_t stream, bool d3 = false, Frame frame = Frame{});
 
 // Move every occupied slot of `from` into `to` (a larger table).
 hipError_t launch_rehash(const Slot* from, uint64_t from_cap, Slot* to, uint64_t to_cap,
-                         SpillBuf spill, unsigned long long* ctr, hipStream_t stream, bool d3 = false);
+                         SpillBuf spill, unsigned long long* ctr, hipStream_t stream, bool d3 = false,
+                         Frame frame = Frame{});
 
 // Export every occupied (key, count) pair, compacted; writes at most cap rows,
 // and the number of occupied slots to ctr[C_DISTINCT].

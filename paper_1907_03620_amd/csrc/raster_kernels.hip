@@ -281,7 +281,63 @@ enum AddResult : int { ADD_FOUND = 0, ADD_NEW = 1, ADD_FULL = 2 };
 // its probe window if it is not there yet.  Keys are only ever written once
 // (empty -> key), so a stale read can only show a slot as empty; the
 // compare-and-swap then returns the true occupant.
+// ---- key frame of a two-dimensional table ----------------------------------
+//
+// A key inside the table's frame (a window of 2^20 x 2^20 tiles) is described
+// by h, a bijective mix of its super-tile's 34-bit position in the frame, and
+// its 32-bit entry: the low 26 bits of h and the key's 6-bit position inside
+// the super-tile.  The top 8 bits of h (the coarse bucket) and the entry give
+// the key back.  The mix is multiplications by odd constants and xor-shifts,
+// each invertible modulo 2^34.
+constexpr uint64_t kFrameStMask = (1ull << kFrameStBits) - 1;
+constexpr uint64_t kFrameMul1 = 0x2c1b3c6d5ull, kFrameMul1Inv = 0x1eea1427dull;
+constexpr uint64_t kFrameMul2 = 0x297a2d39bull, kFrameMul2Inv = 0x165145a93ull;
+constexpr uint32_t kFrameSide = 1u << kFrameLog2;
+constexpr uint32_t kFrameStSide = kFrameLog2 - 3;  // bits of one super-tile coordinate
+
+__device__ __forceinline__ uint64_t frame_mix(uint64_t v) {
+    v = (v * kFrameMul1) & kFrameStMask;
+    v ^= v >> 17;
+    v = (v * kFrameMul2) & kFrameStMask;
+    v ^= v >> 15;
+    return v;
+}
+
+__device__ __forceinline__ uint64_t frame_unmix(uint64_t h) {
+    h ^= (h >> 15) ^ (h >> 30);
+    h = (h * kFrameMul2Inv) & kFrameStMask;
+    h ^= h >> 17;
+    h = (h * kFrameMul1Inv) & kFrameStMask;
+    return h;
+}
+
+// h and entry of a key; false for a key outside the frame.
+__device__ __forceinline__ bool frame_code(uint64_t key, uint32_t fx, uint32_t fy, uint64_t& h, uint32_t& e) {
+    const uint32_t rx = (uint32_t)(key >> 32) - fx, ry = (uint32_t)key - fy;
+    if ((rx | ry) >= kFrameSide) return false;
+    h = frame_mix(((uint64_t)(rx >> 3) << kFrameStSide) | (ry >> 3));
+    e = ((uint32_t)(h & ((1u << kFrameHLow) - 1)) << 6) | ((rx & 7u) << 3) | (ry & 7u);
+    return true;
+}
+
+// The key of entry e in coarse bucket cb.
+__device__ __forceinline__ uint64_t frame_key(uint32_t cb, uint32_t e, uint32_t fx, uint32_t fy) {
+    const uint64_t st = frame_unmix(((uint64_t)cb << kFrameHLow) | (e >> 6));
+    const uint32_t rx = ((uint32_t)(st >> kFrameStSide) << 3) | ((e >> 3) & 7u);
+    const uint32_t ry = ((uint32_t)(st & ((1u << kFrameStSide) - 1)) << 3) | (e & 7u);
+    return ((uint64_t)(fx + rx) << 32) | (uint32_t)(fy + ry);
+}
+
+// Home slot of a key: partition from the placement hash of its super-tile
+// (or from h inside a frame), slot inside the partition from the key's own
+// hash (or the entry's).
 __device__ __forceinline__ uint64_t home_slot(uint64_t key, const Geo& g) {
+    uint64_t h;
+    uint32_t e;
+    if (g.framed && frame_code(key, g.fx, g.fy, h, e)) {
+        const uint64_t part = g.p_log2 ? (h >> (kFrameStBits - g.p_log2)) : 0;
+        return (part << g.cp_log2) | (mix32(e) & ((1u << g.cp_log2) - 1));
+    }
     const uint64_t part = g.p_log2 ? (place_of(key, g.d3) >> (32 - g.p_log2)) : 0;
     return (part << g.cp_log2) | (slot_hash(key) & ((1u << g.cp_log2) - 1));
 }
@@ -913,6 +969,445 @@ __global__ __launch_bounds__(AGG_THREADS, 6) void k_aggregate(const uint64_t* __
     add_fresh(ctr, fresh);
 }
 
+// ---- framed binned contraction (two-dimensional tables with a key frame) -----
+//
+// The same two binning levels and LDS update as above, moving 4-byte entries
+// (frame_code) instead of 8-byte keys.  Level 1 uses kFrameCoarse coarse
+// buckets (the top 8 bits of h) and work tiles of kFBinTile points; level 2
+// splits each coarse list by the next bits of h, which are the top bits of
+// the entry, so it needs no hashing.  Keys outside the frame, and entries past
+// a full list, go straight into the table.
+
+constexpr uint32_t kFBinTile = 8192;
+constexpr int FBIN_ITEMS = (int)kFBinTile / BIN_THREADS;  // 16
+
+struct FBinCommon {
+    uint32_t ent[kFBinTile];
+    uint32_t hist[kMaxFine];
+    uint32_t off[kMaxFine];
+    uint32_t base[kMaxFine];
+    uint32_t total;
+};
+struct FBinScratch1 : FBinCommon {
+    uint8_t bkt[kFBinTile];  // level 1: the coarse bucket of each staged entry
+};
+
+// Scatters this tile's valid entries into nb buckets, as bin_tile does for
+// keys.  Level 1 (L1) buckets are coarse buckets, taken from S.bkt on the way
+// out; level-2 buckets are (e >> 6) >> sub_shift, inside coarse bucket cb.
+template <bool L1, typename Scratch>
+__device__ void fbin_tile(Scratch& S, const uint32_t (&ent)[FBIN_ITEMS], const uint16_t (&bucket)[FBIN_ITEMS],
+                          uint32_t valid, uint32_t nb, uint32_t sub_shift, uint32_t cb, uint32_t* out,
+                          uint64_t stride, uint64_t cap, uint32_t* cursor, Slot* tab, const Geo& g,
+                          const SpillBuf& sp, unsigned long long* ctr, uint32_t& fresh) {
+    uint32_t rank[FBIN_ITEMS];
+#pragma unroll
+    for (int j = 0; j < FBIN_ITEMS; ++j) {
+        rank[j] = 0;
+        if (valid & (1u << j)) rank[j] = atomicAdd(&S.hist[bucket[j]], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const uint32_t per = (nb + 63) / 64;
+        const uint32_t lo = threadIdx.x * per;
+        uint32_t sum = 0;
+        for (uint32_t q = 0; q < per; ++q)
+            if (lo + q < nb) sum += S.hist[lo + q];
+        uint32_t inc = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t v = __shfl_up(inc, o);
+            if (lane_id() >= o) inc += v;
+        }
+        uint32_t ex = inc - sum;
+        for (uint32_t q = 0; q < per; ++q)
+            if (lo + q < nb) {
+                S.off[lo + q] = ex;
+                ex += S.hist[lo + q];
+            }
+        if (threadIdx.x == 63) S.total = inc;
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < nb; b += BIN_THREADS)
+        S.base[b] = S.hist[b] ? atomicAdd(&cursor[b], S.hist[b]) : 0u;
+#pragma unroll
+    for (int j = 0; j < FBIN_ITEMS; ++j) {
+        if (valid & (1u << j)) {
+            const uint32_t p = S.off[bucket[j]] + rank[j];
+            S.ent[p] = ent[j];
+            if constexpr (L1) S.bkt[p] = (uint8_t)bucket[j];
+        }
+    }
+    __syncthreads();
+    const uint32_t total = S.total;
+    for (uint32_t q0 = 0; q0 < total; q0 += BIN_THREADS) {
+        const uint32_t q = q0 + threadIdx.x;
+        int r = ADD_FOUND;
+        uint64_t k = 0;
+        if (q < total) {
+            const uint32_t e = S.ent[q];
+            uint32_t b;
+            if constexpr (L1) b = S.bkt[q];
+            else b = (e >> 6) >> sub_shift;
+            const uint64_t dst = (uint64_t)S.base[b] + (q - S.off[b]);
+            if (dst < cap) {
+                out[(uint64_t)b * stride + dst] = e;
+            } else {
+                k = frame_key(L1 ? b : cb, e, g.fx, g.fy);
+                r = table_add(tab, g, k, 1u);
+                fresh += (r == ADD_NEW);
+            }
+        }
+        spill_push(sp, ctr, r == ADD_FULL, k, 1u);
+    }
+}
+
+template <typename T, bool SKETCH>
+__global__ __launch_bounds__(BIN_THREADS) void k_bin_points_f(const T* __restrict__ pts, int64_t n, double scale,
+                                                              uint32_t* bin1, uint64_t cap1, uint32_t* cursor1,
+                                                              Slot* tab, const Geo g, SpillBuf sp,
+                                                              unsigned long long* ctr, uint32_t* hll) {
+    __shared__ FBinScratch1 S;
+    __shared__ uint32_t sk[SKETCH ? (1u << kHllLog2) : 1u];
+    for (uint32_t b = threadIdx.x; b < kFrameCoarse; b += BIN_THREADS) S.hist[b] = 0;
+    if (SKETCH)
+        for (uint32_t b = threadIdx.x; b < (1u << kHllLog2); b += BIN_THREADS) sk[b] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kFBinTile + threadIdx.x;
+    uint32_t ent[FBIN_ITEMS];
+    uint16_t bucket[FBIN_ITEMS];
+    uint32_t valid = 0, fresh = 0;
+    bool bad = false;
+    constexpr int HALF = FBIN_ITEMS / 2;
+#pragma unroll
+    for (int h0 = 0; h0 < FBIN_ITEMS; h0 += HALF) {
+        // the loads of half the items first, so that they are in flight together
+        double x[HALF], y[HALF];
+#pragma unroll
+        for (int j = 0; j < HALF; ++j) {
+            const int64_t i = base + (int64_t)(h0 + j) * BIN_THREADS;
+            x[j] = 0.0;
+            y[j] = 0.0;
+            if (i < n) load_point(pts, i, x[j], y[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < HALF; ++j) {
+            const int jj = h0 + j;
+            const int64_t i = base + (int64_t)jj * BIN_THREADS;
+            ent[jj] = 0;
+            bucket[jj] = 0;
+            int r = ADD_FOUND;
+            uint64_t key = 0;
+            if (i < n) {
+                if (tile_key(x[j], y[j], scale, key)) {
+                    uint32_t reg, rank;
+                    if (SKETCH && hll_sample(key, reg, rank)) atomicMax(&sk[reg], rank);
+                    uint64_t h;
+                    uint32_t e;
+                    if (frame_code(key, g.fx, g.fy, h, e)) {
+                        ent[jj] = e;
+                        bucket[jj] = (uint16_t)(h >> kFrameHLow);
+                        valid |= 1u << jj;
+                    } else {
+                        // outside the frame: straight into the table
+                        r = table_add(tab, g, key, 1u);
+                        fresh += (r == ADD_NEW);
+                    }
+                } else {
+                    bad = true;
+                }
+            }
+            spill_push(sp, ctr, r == ADD_FULL, key, 1u);
+        }
+    }
+    if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrRange);
+    const uint32_t rep = blockIdx.x % kBinRep;
+    fbin_tile<true>(S, ent, bucket, valid, kFrameCoarse, 0u, 0u, bin1 + (uint64_t)rep * kFrameCoarse * cap1, cap1,
+                    cap1, cursor1 + rep * kFrameCoarse, tab, g, sp, ctr, fresh);
+    add_fresh(ctr, fresh);
+    if (SKETCH) {
+        __syncthreads();  // every sampled key is registered
+        uint32_t* rp = hll + ((uint64_t)(blockIdx.x % kHllReps) << kHllLog2);
+        for (uint32_t b = threadIdx.x; b < (1u << kHllLog2); b += BIN_THREADS)
+            if (sk[b]) atomicMax(rp + b, sk[b]);
+    }
+}
+
+// Level 2: workgroup (l1, seg) splits entries [seg * kFBinTile, ...) of
+// coarse list l1 = (replica r, bucket b1) into replica r of that bucket's
+// partition lists (stored as in the unframed binning).
+__global__ __launch_bounds__(BIN_THREADS) void k_bin_keys_f(const uint32_t* __restrict__ bin1, uint64_t cap1,
+                                                            const uint32_t* cursor1, uint32_t segs, uint32_t* bin2,
+                                                            uint64_t cap2, uint32_t* cursor2, Slot* tab, const Geo g,
+                                                            SpillBuf sp, unsigned long long* ctr) {
+    __shared__ FBinCommon S;
+    const uint32_t l1 = blockIdx.x / segs;
+    const uint32_t seg = blockIdx.x % segs;
+    const uint32_t r = l1 / kFrameCoarse, b1 = l1 % kFrameCoarse;
+    const uint64_t cnt = min((uint64_t)cursor1[l1], cap1);
+    const uint64_t start = (uint64_t)seg * kFBinTile;
+    if (start >= cnt) return;  // uniform across the workgroup
+    const uint32_t fine_log2 = g.p_log2 - kFrameCoarseLog2;
+    const uint32_t nb = 1u << fine_log2;
+    const uint32_t sub_shift = kFrameHLow - fine_log2;
+    for (uint32_t b = threadIdx.x; b < nb; b += BIN_THREADS) S.hist[b] = 0;
+    __syncthreads();
+    uint32_t ent[FBIN_ITEMS];
+    uint16_t bucket[FBIN_ITEMS];
+    uint32_t valid = 0;
+    const uint32_t* src = bin1 + (uint64_t)l1 * cap1;
+    // all loads first, so that they are in flight together
+#pragma unroll
+    for (int j = 0; j < FBIN_ITEMS; ++j) {
+        const uint64_t i = start + (uint64_t)j * BIN_THREADS + threadIdx.x;
+        ent[j] = 0;
+        if (i < cnt) ent[j] = __builtin_nontemporal_load(src + i);
+    }
+#pragma unroll
+    for (int j = 0; j < FBIN_ITEMS; ++j) {
+        const uint64_t i = start + (uint64_t)j * BIN_THREADS + threadIdx.x;
+        bucket[j] = (uint16_t)((ent[j] >> 6) >> sub_shift);
+        if (i < cnt) valid |= 1u << j;
+    }
+    uint32_t fresh = 0;
+    const uint64_t first = (uint64_t)b1 << fine_log2;
+    fbin_tile<false>(S, ent, bucket, valid, nb, sub_shift, b1, bin2 + (first * kBinRep + r) * cap2, kBinRep * cap2,
+                     cap2, cursor2 + ((uint64_t)r << g.p_log2) + first, tab, g, sp, ctr, fresh);
+    add_fresh(ctr, fresh);
+}
+
+// One workgroup per partition adds its entries to the slice in LDS.  A slot
+// is claimed by a 64-bit word, 1 << 32 | entry (0: empty), and counted in its
+// own 32-bit word, so that the count updates spread over all LDS banks.  When
+// the table already held keys the slice is read first; a slot holding a key
+// outside the frame gets the word 2 << 32, which no entry matches, and is not
+// written back.
+constexpr int FAGG_BATCH = 8;
+
+template <int NL>
+struct PartEntries {
+    const uint32_t* src;
+    uint64_t lstride;
+    uint32_t size[NL];
+    uint32_t total;
+    __device__ PartEntries(const uint32_t* s, uint64_t ls, const uint32_t* count, uint64_t cstride, uint64_t cap)
+        : src(s), lstride(ls), total(0) {
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            size[i] = (uint32_t)min((uint64_t)count[i * cstride], cap);
+            total += size[i];
+        }
+    }
+    __device__ uint32_t size_of(uint32_t li) const {
+        uint32_t v = 0;
+#pragma unroll
+        for (int i = 0; i < NL; ++i)
+            if ((uint32_t)i == li) v = size[i];
+        return v;
+    }
+};
+
+struct FAggLds {
+    uint64_t word[kPartSlots];
+    uint32_t cnt[kPartSlots];
+};
+constexpr uint64_t kClaimed = 1ull << 32, kForeign = 2ull << 32;
+
+__device__ __forceinline__ void aggregate_entries(const PartEntries<kBinRep>& L, Slot* part, uint32_t cb, const Geo& g,
+                                                  bool load, FAggLds& A, const SpillBuf& sp, unsigned long long* ctr,
+                                                  uint32_t& fresh) {
+    constexpr int PER = (int)kPartSlots / AGG_THREADS;
+    if (load) {
+        Slot v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) v[u] = part[u * AGG_THREADS + threadIdx.x];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const uint32_t sl = u * AGG_THREADS + threadIdx.x;
+            uint64_t w = 0, h;
+            uint32_t e, c = 0;
+            if (v[u].key != kEmptyKey) {
+                c = v[u].count;
+                w = frame_code(v[u].key, g.fx, g.fy, h, e) ? (kClaimed | e) : kForeign;
+            }
+            A.word[sl] = w;
+            A.cnt[sl] = c;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            A.word[u * AGG_THREADS + threadIdx.x] = 0;
+            A.cnt[u * AGG_THREADS + threadIdx.x] = 0;
+        }
+    }
+    __syncthreads();
+    const uint32_t cnt = L.total;
+    uint32_t li = 0, lo = 0, hi = L.size[0];
+    constexpr uint32_t STEP = AGG_THREADS * FAGG_BATCH;
+    auto fetch = [&](uint32_t q0, uint32_t (&k)[FAGG_BATCH]) {
+        const uint32_t* at[FAGG_BATCH];
+#pragma unroll
+        for (int u = 0; u < FAGG_BATCH; ++u) {
+            const uint32_t q = min(q0 + u * AGG_THREADS + threadIdx.x, cnt - 1);
+            while (q >= hi) {
+                ++li;
+                lo = hi;
+                hi += L.size_of(li);
+            }
+            at[u] = L.src + li * L.lstride + (q - lo);
+        }
+#pragma unroll
+        for (int u = 0; u < FAGG_BATCH; ++u) k[u] = __builtin_nontemporal_load(at[u]);
+    };
+    uint32_t k[FAGG_BATCH], next[FAGG_BATCH];
+    fetch(0, next);
+    for (uint32_t q0 = 0; q0 < cnt; q0 += STEP) {
+#pragma unroll
+        for (int u = 0; u < FAGG_BATCH; ++u) k[u] = next[u];
+        if (q0 + STEP < cnt) fetch(q0 + STEP, next);  // uniform across the workgroup
+        // home-slot reads of all entries together; most entries find
+        // themselves there, and only the others walk the probe sequence
+        uint32_t pos[FAGG_BATCH];
+        uint64_t cur[FAGG_BATCH];
+#pragma unroll
+        for (int u = 0; u < FAGG_BATCH; ++u) {
+            pos[u] = mix32(k[u]) & (kPartSlots - 1);
+            cur[u] = q0 + u * AGG_THREADS + threadIdx.x < cnt ? lds_load_relaxed(&A.word[pos[u]]) : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < FAGG_BATCH; ++u) {
+            const bool have = q0 + u * AGG_THREADS + threadIdx.x < cnt;
+            int r = ADD_FOUND;
+            if (have) {
+                const uint64_t want = kClaimed | k[u];
+                uint32_t ps = pos[u];
+                uint64_t c = cur[u];
+                r = ADD_FULL;
+                for (uint32_t step = 0; step < kMaxProbe; ++step) {
+                    if (step) c = lds_load_relaxed(&A.word[ps]);
+                    if (c == 0) {
+                        c = atomicCAS(reinterpret_cast<unsigned long long*>(&A.word[ps]), 0ull,
+                                      (unsigned long long)want);
+                        if (c == 0) {
+                            atomicAdd(&A.cnt[ps], 1u);
+                            r = ADD_NEW;
+                            break;
+                        }
+                    }
+                    if (c == want) {
+                        atomicAdd(&A.cnt[ps], 1u);
+                        r = ADD_FOUND;
+                        break;
+                    }
+                    ps = (ps + 1) & (kPartSlots - 1);
+                }
+                fresh += (r == ADD_NEW);
+            }
+            const uint64_t key = r == ADD_FULL ? frame_key(cb, k[u], g.fx, g.fy) : 0;
+            spill_push(sp, ctr, r == ADD_FULL, key, 1u);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const uint32_t sl = u * AGG_THREADS + threadIdx.x;
+        const uint64_t w = A.word[sl];
+        if ((w >> 32) == 1) {
+            Slot v;
+            v.key = frame_key(cb, (uint32_t)w, g.fx, g.fy);
+            v.count = A.cnt[sl];
+            v.aux = kNotSignificant;
+            part[sl] = v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(AGG_THREADS, 6) void k_aggregate_f(const uint32_t* __restrict__ bin2, uint64_t cap2,
+                                                                const uint32_t* cursor2, Slot* tab, const Geo g,
+                                                                SpillBuf sp, unsigned long long* ctr) {
+    __shared__ FAggLds A;
+    const uint64_t p = blockIdx.x;
+    const uint64_t parts = gridDim.x;
+    const PartEntries<kBinRep> L(bin2 + p * kBinRep * cap2, cap2, cursor2 + p, parts, cap2);
+    if (L.total == 0) return;  // uniform across the workgroup
+    Slot* part = tab + (p << kPartLog2);
+    const uint32_t cb = (uint32_t)(p >> (g.p_log2 - kFrameCoarseLog2));
+    uint32_t fresh = 0;
+    aggregate_entries(L, part, cb, g, ctr[C_TABLE_KEYS] != 0, A, sp, ctr, fresh);
+    add_fresh(ctr, fresh);
+}
+
+// Fallback: every entry held in the coarse lists goes straight to the table.
+__global__ void k_drain_bins_f(const uint32_t* bin1, uint64_t cap1, const uint32_t* cursor1, Slot* tab, const Geo g,
+                               SpillBuf sp, unsigned long long* ctr) {
+    const uint64_t total = (uint64_t)kBinRep * kFrameCoarse * cap1;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t n_round = (total + 63) / 64 * 64;
+    uint32_t fresh = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_round; i += stride) {
+        int r = ADD_FOUND;
+        uint64_t k = 0;
+        if (i < total) {
+            const uint64_t b = i / cap1, q = i % cap1;
+            if (q < min((uint64_t)cursor1[b], cap1)) {
+                k = frame_key((uint32_t)(b % kFrameCoarse), bin1[i], g.fx, g.fy);
+                r = table_add(tab, g, k, 1u);
+                fresh += (r == ADD_NEW);
+            }
+        }
+        spill_push(sp, ctr, r == ADD_FULL, k, 1u);
+    }
+    add_fresh(ctr, fresh);
+}
+
+// Tile bounding box of points [0, n) over the points with a valid tile: each
+// workgroup writes {min bx, max bx, min by, max by} (biased) of its points to
+// part[4 * blockIdx.x ...], then k_bbox_merge folds the parts into out.
+constexpr int kBboxBlocks = 256;
+static_assert(kBboxWords == 4 + 4 * kBboxBlocks, "box scratch holds one part per workgroup");
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_key_bbox(const T* __restrict__ pts, int64_t n, double scale, uint32_t* part) {
+    __shared__ uint32_t red[4][4];
+    uint32_t v[4] = {~0u, 0u, ~0u, 0u};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double x, y;
+        load_point(pts, i, x, y);
+        uint64_t key;
+        if (tile_key(x, y, scale, key)) {
+            const uint32_t bx = (uint32_t)(key >> 32), by = (uint32_t)key;
+            v[0] = min(v[0], bx);
+            v[1] = max(v[1], bx);
+            v[2] = min(v[2], by);
+            v[3] = max(v[3], by);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        v[0] = min(v[0], (uint32_t)__shfl_xor((int)v[0], o));
+        v[1] = max(v[1], (uint32_t)__shfl_xor((int)v[1], o));
+        v[2] = min(v[2], (uint32_t)__shfl_xor((int)v[2], o));
+        v[3] = max(v[3], (uint32_t)__shfl_xor((int)v[3], o));
+    }
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0)
+        for (int c = 0; c < 4; ++c) red[w][c] = v[c];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int c = threadIdx.x;
+        uint32_t r = red[0][c];
+        for (int q = 1; q < 4; ++q) r = (c & 1) ? max(r, red[q][c]) : min(r, red[q][c]);
+        part[4 * blockIdx.x + c] = r;
+    }
+}
+
+__global__ void k_bbox_merge(const uint32_t* part, int parts, uint32_t* out) {
+    if (threadIdx.x < 4) {
+        const int c = threadIdx.x;
+        uint32_t r = (c & 1) ? 0u : ~0u;
+        for (int b = 0; b < parts; ++b) r = (c & 1) ? max(r, part[4 * b + c]) : min(r, part[4 * b + c]);
+        out[c] = r;
+    }
+}
+
 // ---- binned counting for batches ----------------------------------------------
 //
 // The same two binning levels and LDS update, over every job of a batch at
@@ -931,7 +1426,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bbin_points(JobView jv, const u
     for (uint32_t t = tr.lo; t < tr.hi; ++t) {
         job = advance_job(tile_prefix, job, t);
         const JobInfo& J = jv.jobs[job];
-        const Geo g = make_geo(J.cap, false);  // batch jobs are two-dimensional
+        const Geo g = job_geo(J);  // batch jobs are two-dimensional
         const uint32_t top = g.p_log2 - J.cshift;  // coarse bits of the hash
         const uint32_t nb = 1u << top;
         for (uint32_t b = threadIdx.x; b < nb; b += BIN_THREADS) S.hist[b] = 0;
@@ -996,7 +1491,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bbin_keys(JobView jv, const uin
         if (start >= cnt) continue;  // uniform across the workgroup
         const uint32_t job = cjob[c];
         const JobInfo& J = jv.jobs[job];
-        const Geo g = make_geo(J.cap, false);  // batch jobs are two-dimensional
+        const Geo g = job_geo(J);  // batch jobs are two-dimensional
         const uint32_t nb = 1u << J.cshift;
         for (uint32_t b = threadIdx.x; b < nb; b += BIN_THREADS) S.hist[b] = 0;
         __syncthreads();
@@ -1484,7 +1979,7 @@ __global__ __launch_bounds__(SQUARE_THREADS) void k_square_part(Slot* tab, JobVi
         // of partitions), so job-local partition jp holds slots base.. of it
         const JobInfo& J = jv.jobs[multi ? jv.part_job[p] : 0u];
         const uint32_t tau = J.tau;
-        const Geo g = make_geo(J.cap, false);  // the step is two-dimensional
+        const Geo g = job_geo(J);  // the step is two-dimensional
         const uint32_t psize = (uint32_t)min<uint64_t>(J.cap, kPartSlots);
         Slot* jt = tab + J.slot_base;
         const uint64_t jp = p - (J.slot_base >> kPartLog2);
@@ -1583,7 +2078,7 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_part(const Slot* tab, Job
     bool bad = false;
     for (uint64_t p = blockIdx.x; p < parts; p += gridDim.x) {
         const JobInfo& J = jv.jobs[multi ? jv.part_job[p] : 0u];
-        const Geo g = make_geo(J.cap, D3);
+        const Geo g = job_geo(J, D3);
         const uint32_t psize = (uint32_t)min<uint64_t>(J.cap, kPartSlots);  // a power of two
         const uint64_t base = p << kPartLog2;
         if (threadIdx.x == 0) nlist = 0;
@@ -2280,7 +2775,7 @@ __global__ void k_batch_count(JobView jv, const uint32_t* tile_prefix, Slot* tab
         const uint32_t job = job_of_tile(tile_prefix, njobs, t);
         const JobInfo& J = jv.jobs[job];
         Slot* jt = tab + J.slot_base;
-        const Geo g = make_geo(J.cap, false);  // batch jobs are two-dimensional
+        const Geo g = job_geo(J);  // batch jobs are two-dimensional
         unsigned long long* jc = jv.job_ctr + (uint64_t)job * kCounterWords;
         const int64_t base = (int64_t)(t - J.first_tile) * blockDim.x * ITEMS;
         if (L) {
@@ -2397,9 +2892,9 @@ hipError_t launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t stream) {
 
 hipError_t launch_project_count(const void* pts, int64_t n, int dtype, double scale, Slot* tab, uint64_t cap,
                                  SpillBuf spill, unsigned long long* ctr, const KernelTuning& tu,
-                                 hipStream_t stream, int dims) {
+                                 hipStream_t stream, int dims, Frame frame) {
     if (n <= 0) return hipSuccess;
-    const Geo g = make_geo(cap, dims == 3);
+    const Geo g = make_geo(cap, dims == 3, frame);
     if (dims == 3) {
         if (dtype == 1)
             return launch_count_items(static_cast<const Pt3<float>*>(pts), n, scale, tab, g, spill, ctr, tu, stream);
@@ -2483,17 +2978,90 @@ hipError_t launch_drain_bins(uint64_t* bin1, uint64_t cap1, uint32_t* cursor1, S
 }
 
 hipError_t launch_insert_records(const uint64_t* keys, const uint32_t* counts, uint64_t n, Slot* tab,
-                                 uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream, bool d3) {
+                                 uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream, bool d3,
+                                 Frame frame) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_insert_records, dim3(grid_for(n, 256, kPersistBlocks)), dim3(256), 0, stream, keys,
-                       counts, n, tab, make_geo(cap, d3), spill, ctr);
+                       counts, n, tab, make_geo(cap, d3, frame), spill, ctr);
     return hipGetLastError();
 }
 
 hipError_t launch_rehash(const Slot* from, uint64_t from_cap, Slot* to, uint64_t to_cap, SpillBuf spill,
-                         unsigned long long* ctr, hipStream_t stream, bool d3) {
+                         unsigned long long* ctr, hipStream_t stream, bool d3, Frame frame) {
     hipLaunchKernelGGL(k_rehash, dim3(grid_for(from_cap, 256, kPersistBlocks)), dim3(256), 0, stream, from,
-                       from_cap, to, make_geo(to_cap, d3), spill, ctr);
+                       from_cap, to, make_geo(to_cap, d3, frame), spill, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_key_bbox(const void* pts, int64_t n, int dtype, double scale, uint32_t* out, hipStream_t stream) {
+    uint32_t* part = out + 4;
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_key_bbox<float>, dim3(kBboxBlocks), dim3(256), 0, stream, static_cast<const float*>(pts),
+                           n, scale, part);
+    else
+        hipLaunchKernelGGL(k_key_bbox<double>, dim3(kBboxBlocks), dim3(256), 0, stream,
+                           static_cast<const double*>(pts), n, scale, part);
+    hipLaunchKernelGGL(k_bbox_merge, dim3(1), dim3(64), 0, stream, part, kBboxBlocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_points_framed(const void* pts, int64_t n, int dtype, double scale, uint32_t* bin1,
+                                   uint64_t cap1, uint32_t* cursor1, Slot* tab, uint64_t cap, Frame frame,
+                                   SpillBuf spill, unsigned long long* ctr, uint32_t* hll, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const Geo g = make_geo(cap, false, frame);
+    if (!g.framed) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((n + kFBinTile - 1) / kFBinTile));
+    auto go = [&](auto kernel, const auto* p) {
+        hipLaunchKernelGGL(kernel, grid, dim3(BIN_THREADS), 0, stream, p, n, scale, bin1, cap1, cursor1, tab, g, spill,
+                           ctr, hll);
+    };
+    const float* pf = static_cast<const float*>(pts);
+    const double* pd = static_cast<const double*>(pts);
+    if (dtype == 1) {
+        if (hll) go(k_bin_points_f<float, true>, pf);
+        else go(k_bin_points_f<float, false>, pf);
+    } else {
+        if (hll) go(k_bin_points_f<double, true>, pd);
+        else go(k_bin_points_f<double, false>, pd);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_keys_framed(const uint32_t* bin1, uint64_t cap1, const uint32_t* cursor1, uint32_t* bin2,
+                                 uint64_t cap2, uint32_t* cursor2, Slot* tab, uint64_t cap, Frame frame,
+                                 SpillBuf spill, unsigned long long* ctr, hipStream_t stream) {
+    const Geo g = make_geo(cap, false, frame);
+    if (!framed_binned_geometry(g)) return hipErrorInvalidValue;
+    const uint64_t lists2 = (uint64_t)kBinRep << g.p_log2;
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(lists2, 256, 4096)), dim3(256), 0, stream, cursor2, lists2);
+    const uint32_t segs = (uint32_t)((cap1 + kFBinTile - 1) / kFBinTile);
+    const dim3 grid(kBinRep * kFrameCoarse * segs);
+    hipLaunchKernelGGL(k_bin_keys_f, grid, dim3(BIN_THREADS), 0, stream, bin1, cap1, cursor1, segs, bin2, cap2,
+                       cursor2, tab, g, spill, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_aggregate_framed(const uint32_t* bin2, uint64_t cap2, const uint32_t* cursor2, uint32_t* cursor1,
+                                  Slot* tab, uint64_t cap, Frame frame, SpillBuf spill, unsigned long long* ctr,
+                                  hipStream_t stream) {
+    const Geo g = make_geo(cap, false, frame);
+    if (!framed_binned_geometry(g)) return hipErrorInvalidValue;
+    const uint64_t parts = 1ull << g.p_log2;
+    hipLaunchKernelGGL(k_snapshot_keys, dim3(1), dim3(64), 0, stream, ctr);
+    hipLaunchKernelGGL(k_aggregate_f, dim3((unsigned)parts), dim3(AGG_THREADS), 0, stream, bin2, cap2, cursor2, tab,
+                       g, spill, ctr);
+    hipLaunchKernelGGL(k_zero_u32, dim3(8), dim3(256), 0, stream, cursor1, (uint64_t)kBinRep * kFrameCoarse);
+    return hipGetLastError();
+}
+
+hipError_t launch_drain_bins_framed(const uint32_t* bin1, uint64_t cap1, uint32_t* cursor1, Slot* tab, uint64_t cap,
+                                   Frame frame, SpillBuf spill, unsigned long long* ctr, hipStream_t stream) {
+    const Geo g = make_geo(cap, false, frame);
+    if (!g.framed) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_drain_bins_f, dim3(grid_for((uint64_t)kBinRep * kFrameCoarse * cap1, 256, kPersistBlocks)),
+                       dim3(256), 0, stream, bin1, cap1, cursor1, tab, g, spill, ctr);
+    hipLaunchKernelGGL(k_zero_u32, dim3(8), dim3(256), 0, stream, cursor1, (uint64_t)kBinRep * kFrameCoarse);
     return hipGetLastError();
 }
 

@@ -135,7 +135,12 @@ struct TableRun {
     std::vector<hipEvent_t> ev_free;
     double span_us[3] = {0, 0, 0};
     int64_t span_n[3] = {0, 0, 0};
-    // binned contraction
+    // Key frame of the table (two dimensions): decided from the first binned
+    // chunk while the table is empty, then fixed for the table's life.
+    Frame frame{};
+    bool frame_decided = false;
+    // binned contraction: coarse and partition lists of 8-byte keys, or of
+    // 4-byte entries in a framed table
     uint64_t* bin1 = nullptr;
     uint64_t cap1 = 0;
     uint32_t* cursor1 = nullptr;
@@ -166,6 +171,10 @@ struct TableRun {
     raster_status export_tiles(uint64_t* keys, uint32_t* counts, int64_t cap_rows, int64_t* m);
 
     raster_status alloc_table(uint64_t c, Slot** t, uint64_t* c_out);
+    raster_status decide_frame(const void* pts, int64_t n, raster_dtype dt);
+    size_t bin_entry_bytes() const { return frame.on ? sizeof(uint32_t) : sizeof(uint64_t); }
+    uint32_t coarse_buckets() const { return frame.on ? kFrameCoarse : kCoarse; }
+    Geo geo() const { return make_geo(cap, dims == 3, frame); }
     raster_status size_from_sketch(uint64_t points);
     raster_status ensure_sketch();
     raster_status ensure_spill(int b, uint64_t need);

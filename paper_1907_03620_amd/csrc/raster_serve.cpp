@@ -437,6 +437,9 @@ raster_status BatchEngine::run(const raster_job* jobs, int32_t n_jobs, hipStream
         J.cshift = shifts[i];
         J.cap2 = cap2s[i];
         J.bin2_base = b2base[i];
+        J.framed = 0;  // batch tables are unframed
+        J.fx = 0;
+        J.fy = 0;
         h_tile_prefix[i] = tp;
         tp += tiles[i];
         for (uint64_t p = bases[i] / kPartSlotsHost; p < (bases[i] + caps[i]) / kPartSlotsHost; ++p)

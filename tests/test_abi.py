@@ -92,7 +92,7 @@ def test_tuning_validation(lib):
     lib.raster_set_tuning.argtypes = [ctypes.POINTER(T)]
     lib.raster_get_tuning.argtypes = [ctypes.POINTER(T)]
     for bad in [T(100, 4, 0, 0.5, 0, 256), T(256, 3, 0, 0.5, 0, 256), T(256, 4, 300, 0.5, 0, 256),
-                T(256, 4, 0, 0.95, 0, 256), T(2048, 4, 0, 0.5, 0, 256), T(256, 4, 0, 0.5, 3, 256),
+                T(256, 4, 0, 0.95, 0, 256), T(2048, 4, 0, 0.5, 0, 256), T(256, 4, 0, 0.5, 4, 256),
                 T(256, 4, 0, 0.5, 0, 0), T(256, 4, 0, 0.5, 0, 5000)]:
         assert lib.raster_set_tuning(ctypes.byref(bad)) == -1
     good = T(512, 8, 2048, 0.4, 2, 64)
