@@ -146,3 +146,19 @@ def test_too_wide_for_a_frame(raster, torch):
     res = raster.cluster(dev(framed_size, torch), precision=3, tau=5, mu=4)
     assert res.stats["key_frame"] == 1
     assert_same(res, oracle.cluster(framed_size, tau=5, mu=4, precision=3), "framed plain call")
+
+
+def test_partition_overflow_at_high_load(raster, torch):
+    """A stream kept at about 80% table load (a stream keeps its table until
+    the sketch shows it 85% full): partitions overflow in the LDS update,
+    whose spilled entries make the table grow and are inserted again.
+    Results must not change."""
+    rng = synth.rng_for(7700)
+    # about 800K distinct tiles of 1 x 1 (p=0) in a 2^20-slot table
+    pts = rng.uniform(0.0, 2000.0, size=(900_000, 2))
+    chunks = [np.ascontiguousarray(pts[i::3]) for i in range(3)]
+    _say("frame: final update at high load")
+    res = run_stream(raster, torch, chunks, 0, 2, 2, tile_hint=600_000, mode=2)
+    assert res.stats["key_frame"] == 1
+    assert res.stats["distinct_tiles"] > 700_000
+    assert_same(res, oracle.cluster_chunks(chunks, tau=2, mu=2, precision=0), "high-load final update")
