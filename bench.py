@@ -8,8 +8,10 @@ chunks, finish (significance scan, union-find agglomeration, mu filter).
 
 Prints one JSON line with points/s, the counting kernel's roofline (HIP-event
 duration per launch against the 8 TB/s HBM peak, algorithmic bytes = 16 bytes
-of FP64 coordinates per point) and the CPU oracle timed on a bounded sample
-of the same workload on this host.  After the timed steps it also times the
+of FP64 coordinates per point), the whole step's algorithmic bandwidth
+against the same peak, the step's kernels from the committed rocprofv3
+summary, and the CPU oracle timed on the whole workload on this host (one
+core), with whether its rows equal the GPU step's.  After the timed steps it also times the
 per-point label pass over all 500M resident points (Section 4.1), the 256-job
 batch against plain calls, and the server on a Poisson trace.
 """
@@ -68,6 +70,68 @@ def measured_traffic(per_launch_points: int, key: str = "hbm_bytes_per_launch"):
     return float(kv[key])
 
 
+STEP_KERNELS_FILE = os.path.join(ROOT, "profiles", "paper500M_step_kernels.txt")
+
+# Algorithmic bytes of each kernel of the step, per unit of the workload (n
+# points, m distinct tiles, s significant tiles, t output rows): what the
+# method itself must move, without probe amplification or binning scratch.
+# Their sum is the step's 16 n + 24 m + 20 s + 20 t.
+KERNEL_ALG_BYTES = {
+    "k_bin_points": ("16 B per point (FP64 coordinates, read once)", lambda n, m, s, t: 16.0 * n),
+    "k_bin_keys": ("0 (binning scratch only)", lambda n, m, s, t: 0.0),
+    "k_aggregate": ("12 B per distinct tile (key and count written once)", lambda n, m, s, t: 12.0 * m),
+    "k_threshold": ("12 B per distinct tile (key and count read once)", lambda n, m, s, t: 12.0 * m),
+    "k_link_part": ("8 B per significant tile (its key)", lambda n, m, s, t: 8.0 * s),
+    "union-find": ("12 B per significant tile (parent traffic)", lambda n, m, s, t: 12.0 * s),
+    "k_filter": ("20 B per output row", lambda n, m, s, t: 20.0 * t),
+}
+
+
+def kernel_group(name: str):
+    """The algorithmic-bytes group of a kernel name from the profile."""
+    for g in ("k_bin_points", "k_bin_keys", "k_aggregate", "k_threshold", "k_link_part", "k_filter"):
+        if name.startswith(g):
+            return g
+    if name.startswith(("k_jump", "k_merge", "k_compress")):
+        return "union-find"
+    return None
+
+
+def step_kernels(n: int, m: int, s: int, t: int):
+    """Per-kernel figures of one step from the committed rocprofv3 summary
+    (average launch time, launches per step, HBM traffic and L2 atomic
+    requests per launch), with each kernel's algorithmic bytes for this run's
+    n, m, s and t.  None unless the summary was taken on the current kernel
+    source."""
+    if not os.path.exists(STEP_KERNELS_FILE):
+        return None
+    kv, rows = {}, []
+    for line in open(STEP_KERNELS_FILE):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        if line.startswith("kernel="):
+            rows.append(dict(f.split("=", 1) for f in line.split(";")))
+        elif "=" in line:
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    out = []
+    for r in rows:
+        g = kernel_group(r["kernel"])
+        calls = float(r["calls_per_step"])
+        alg = KERNEL_ALG_BYTES[g][1](n, m, s, t) if g else None
+        out.append({"kernel": r["kernel"], "launches_per_step": calls, "avg_launch_us": float(r["avg_us"]),
+                    "ms_per_step": calls * float(r["avg_us"]) / 1000.0,
+                    "algorithmic_bytes_per_step": alg,
+                    "algorithmic_bytes": KERNEL_ALG_BYTES[g][0] if g else None,
+                    "hbm_bytes_per_step": calls * (float(r["fetch_bytes"]) + float(r["write_bytes"])),
+                    "l2_atomic_requests_per_step": calls * float(r["tcc_atomic"]),
+                    "memory_atomic_requests_per_step": calls * float(r["ea_atomic"])})
+    return out
+
+
 def gen_paper_scale(n_chunks: int, chunk: int):
     import synth
     centres = synth.paper_scale_centres(3)
@@ -110,6 +174,45 @@ def cpu_baseline(sample, strip: float, precision: int, tau: int, mu: int):
                 sample=(f"x in [0, {strip:g}) strip of all chunks: {sample.shape[0]} points "
                         f"({res.stats['clusters']} clusters), full Algorithm 1, {dt:.1f} s"),
                 seconds=dt, points=int(sample.shape[0]), clusters=int(res.stats["clusters"]))
+
+
+def cpu_baseline_full(host_chunks, gpu_rows, precision: int, tau: int, mu: int):
+    """Times the oracle, single-threaded and pinned to one core, on the whole
+    workload (every chunk of the stream, fed as chunks), and checks that its
+    rows equal those of the last timed GPU step."""
+    import numpy as np
+    import oracle
+    try:
+        cpu = sorted(os.sched_getaffinity(0))[0]
+        os.sched_setaffinity(0, {cpu})
+    except (AttributeError, OSError):
+        pass
+    t0 = time.perf_counter()
+    res = oracle.cluster_chunks(host_chunks, tau=tau, mu=mu, precision=precision)
+    dt = time.perf_counter() - t0
+    try:
+        os.sched_setaffinity(0, set(range(os.cpu_count() or 1)))
+    except (AttributeError, OSError):
+        pass
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
+    kx, ky, cnt, lab = gpu_rows
+    lab = lab.astype(np.uint64)
+    lx = (lab >> np.uint64(32)).astype(np.int64) - (1 << 31)
+    ly = (lab & np.uint64(0xFFFFFFFF)).astype(np.int64) - (1 << 31)
+    same = (kx.shape[0] == res.kx.shape[0] and np.array_equal(kx.astype(np.int64), res.kx)
+            and np.array_equal(ky.astype(np.int64), res.ky) and np.array_equal(cnt.astype(np.uint64), res.count)
+            and np.array_equal(lx, res.label_x) and np.array_equal(ly, res.label_y))
+    n = sum(int(h.shape[0]) for h in host_chunks)
+    return dict(value=n / dt, unit="points/s", cores=1, kind="oracle", cpu=model, host_cpus=os.cpu_count(),
+                sample=(f"the whole workload: all {len(host_chunks)} chunks ({n} points) fed to the oracle as one "
+                        f"stream, full Algorithm 1, {dt:.1f} s"),
+                seconds=dt, points=n, clusters=int(res.stats["clusters"]), tiles=int(res.stats["tiles"]),
+                same_rows_as_gpu_step=bool(same))
 
 
 def cpu_p_raster(sample, precision: int, tau: int, mu: int):
@@ -579,6 +682,7 @@ def main():
     traffic = measured_traffic(int(points_per_launch))
     m, s, t = st["distinct_tiles"], st["significant_tiles"], st["tiles"]
     alg_bytes = 16.0 * n_total + 2 * 12.0 * m + 20.0 * s + 20.0 * t
+    step_gbps = alg_bytes / (ms_per_step * 1e-3) / 1e9
     phases = {k: round(float(np.mean([r.stats[k] for r in results])), 1)
               for k in ("us_contract", "us_threshold", "us_agglomerate", "us_filter",
                         "us_count_kernel", "us_bin_keys", "us_aggregate")}
@@ -605,7 +709,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_bin_points (projection + level-1 binning)" if binned
+            "kernel": ("k_bin_points_f (projection + level-1 binning of 4-byte entries)" if st["key_frame"]
+                       else "k_bin_points (projection + level-1 binning)") if binned
                       else "k_count_direct (projection + device-table count)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBPS,
@@ -615,13 +720,20 @@ def main():
             "avg_launch_us": avg_us,
             "bytes_per_launch": bytes_per_launch,
             "algorithmic_bytes": "16 B of FP64 coordinates per point, read once",
+            "step_achieved": step_gbps,
+            "step_frac": step_gbps / HBM_PEAK_GBPS,
+            "step_algorithmic_bytes": alg_bytes,
+            "step_algorithmic_bytes_formula": "16 n + 24 m + 20 s + 20 t (n points, m distinct tiles, "
+                                              "s significant tiles, t output rows)",
         },
-        "hbm_gbps_algorithmic_step": alg_bytes / (ms_per_step * 1e-3) / 1e9,
+        "kernels": step_kernels(n_total, m, s, t),
+        "hbm_gbps_algorithmic_step": step_gbps,
         "phases_us": phases,
         "result": {"distinct_tiles": m, "significant_tiles": s, "clusters": st["clusters"], "tiles": t,
                    "table_capacity": st["table_capacity"], "grow_events": st["grow_events"]},
         "cpu_baseline": None,
     }
+    gpu_rows = results[-1].numpy(sort=True) if not args.no_cpu_baseline else None
     line["point_labels"] = None if args.no_point_labels else bench_point_labels(raster, torch, results[-1], dev)
     line["tile_points"] = None if args.no_point_labels else bench_tile_points(raster, torch, results[-1], dev)
     line["neighbourhoods"] = None
@@ -649,13 +761,15 @@ def main():
                                                               args.served_slots, args.served_stress_rate)
     line["cpu_p_raster"] = None
     if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, one core, the whole stream)")
+        line["cpu_baseline"] = cpu_baseline_full(host, gpu_rows, precision, tau, mu)
+        del gpu_rows
         sample = strip_sample(host, args.cpu_strip)
-        log("cpu baseline (oracle, one core)")
-        line["cpu_baseline"] = cpu_baseline(sample, args.cpu_strip, precision, tau, mu)
-        log("cpu P-RASTER (host threads)")
+        log("cpu P-RASTER (host threads) and the oracle on a strip")
+        strip = cpu_baseline(sample, args.cpu_strip, precision, tau, mu)
         line["cpu_p_raster"] = cpu_p_raster(sample, precision, tau, mu)
-        line["cpu_p_raster"]["same_clusters_as_oracle"] = (line["cpu_p_raster"]["clusters"]
-                                                           == line["cpu_baseline"]["clusters"])
+        line["cpu_p_raster"]["oracle_on_the_strip"] = strip
+        line["cpu_p_raster"]["same_clusters_as_oracle"] = line["cpu_p_raster"]["clusters"] == strip["clusters"]
     print(json.dumps(line), flush=True)
 
 
