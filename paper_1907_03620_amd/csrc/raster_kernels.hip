@@ -978,7 +978,11 @@ __global__ __launch_bounds__(AGG_THREADS, 6) void k_aggregate(const uint64_t* __
 // the entry, so it needs no hashing.  Keys outside the frame, and entries past
 // a full list, go straight into the table.
 
-constexpr uint32_t kFBinTile = 8192;
+// Points per thread of the framed level 1.  16 (an 8192-point tile, three
+// workgroups per CU) and 8 (a 4096-point tile, four per CU) measure the same;
+// the larger tile takes half the cursor atomics.
+constexpr int kFBinItems1 = 16;
+constexpr uint32_t kFBinTile = 8192;  // level 2's work tile
 constexpr int FBIN_ITEMS = (int)kFBinTile / BIN_THREADS;  // 16
 
 struct FBinCommon {
@@ -988,21 +992,28 @@ struct FBinCommon {
     uint32_t base[kMaxFine];
     uint32_t total;
 };
-struct FBinScratch1 : FBinCommon {
-    uint8_t bkt[kFBinTile];  // level 1: the coarse bucket of each staged entry
+// Level 1: ITEMS points per thread, kFrameCoarse buckets.
+template <int ITEMS>
+struct FBinScratch1 {
+    uint32_t ent[BIN_THREADS * ITEMS];
+    uint8_t bkt[BIN_THREADS * ITEMS];  // the coarse bucket of each staged entry
+    uint32_t hist[kFrameCoarse];
+    uint32_t off[kFrameCoarse];
+    uint32_t base[kFrameCoarse];
+    uint32_t total;
 };
 
 // Scatters this tile's valid entries into nb buckets, as bin_tile does for
 // keys.  Level 1 (L1) buckets are coarse buckets, taken from S.bkt on the way
 // out; level-2 buckets are (e >> 6) >> sub_shift, inside coarse bucket cb.
-template <bool L1, typename Scratch>
-__device__ void fbin_tile(Scratch& S, const uint32_t (&ent)[FBIN_ITEMS], const uint16_t (&bucket)[FBIN_ITEMS],
+template <bool L1, int ITEMS, typename Scratch>
+__device__ void fbin_tile(Scratch& S, const uint32_t (&ent)[ITEMS], const uint16_t (&bucket)[ITEMS],
                           uint32_t valid, uint32_t nb, uint32_t sub_shift, uint32_t cb, uint32_t* out,
                           uint64_t stride, uint64_t cap, uint32_t* cursor, Slot* tab, const Geo& g,
                           const SpillBuf& sp, unsigned long long* ctr, uint32_t& fresh) {
-    uint32_t rank[FBIN_ITEMS];
+    uint32_t rank[ITEMS];
 #pragma unroll
-    for (int j = 0; j < FBIN_ITEMS; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         rank[j] = 0;
         if (valid & (1u << j)) rank[j] = atomicAdd(&S.hist[bucket[j]], 1u);
     }
@@ -1030,7 +1041,7 @@ __device__ void fbin_tile(Scratch& S, const uint32_t (&ent)[FBIN_ITEMS], const u
     for (uint32_t b = threadIdx.x; b < nb; b += BIN_THREADS)
         S.base[b] = S.hist[b] ? atomicAdd(&cursor[b], S.hist[b]) : 0u;
 #pragma unroll
-    for (int j = 0; j < FBIN_ITEMS; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         if (valid & (1u << j)) {
             const uint32_t p = S.off[bucket[j]] + rank[j];
             S.ent[p] = ent[j];
@@ -1061,25 +1072,26 @@ __device__ void fbin_tile(Scratch& S, const uint32_t (&ent)[FBIN_ITEMS], const u
     }
 }
 
-template <typename T, bool SKETCH>
+template <typename T, bool SKETCH, int ITEMS>
 __global__ __launch_bounds__(BIN_THREADS) void k_bin_points_f(const T* __restrict__ pts, int64_t n, double scale,
                                                               uint32_t* bin1, uint64_t cap1, uint32_t* cursor1,
                                                               Slot* tab, const Geo g, SpillBuf sp,
                                                               unsigned long long* ctr, uint32_t* hll) {
-    __shared__ FBinScratch1 S;
+    constexpr uint32_t TILE = BIN_THREADS * ITEMS;
+    __shared__ FBinScratch1<ITEMS> S;
     __shared__ uint32_t sk[SKETCH ? (1u << kHllLog2) : 1u];
     for (uint32_t b = threadIdx.x; b < kFrameCoarse; b += BIN_THREADS) S.hist[b] = 0;
     if (SKETCH)
         for (uint32_t b = threadIdx.x; b < (1u << kHllLog2); b += BIN_THREADS) sk[b] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kFBinTile + threadIdx.x;
-    uint32_t ent[FBIN_ITEMS];
-    uint16_t bucket[FBIN_ITEMS];
+    const int64_t base = (int64_t)blockIdx.x * TILE + threadIdx.x;
+    uint32_t ent[ITEMS];
+    uint16_t bucket[ITEMS];
     uint32_t valid = 0, fresh = 0;
     bool bad = false;
-    constexpr int HALF = FBIN_ITEMS / 2;
+    constexpr int HALF = ITEMS > 8 ? ITEMS / 2 : ITEMS;
 #pragma unroll
-    for (int h0 = 0; h0 < FBIN_ITEMS; h0 += HALF) {
+    for (int h0 = 0; h0 < ITEMS; h0 += HALF) {
         // the loads of half the items first, so that they are in flight together
         double x[HALF], y[HALF];
 #pragma unroll
@@ -1121,8 +1133,8 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_points_f(const T* __restric
     }
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrRange);
     const uint32_t rep = blockIdx.x % kBinRep;
-    fbin_tile<true>(S, ent, bucket, valid, kFrameCoarse, 0u, 0u, bin1 + (uint64_t)rep * kFrameCoarse * cap1, cap1,
-                    cap1, cursor1 + rep * kFrameCoarse, tab, g, sp, ctr, fresh);
+    fbin_tile<true, ITEMS>(S, ent, bucket, valid, kFrameCoarse, 0u, 0u, bin1 + (uint64_t)rep * kFrameCoarse * cap1,
+                           cap1, cap1, cursor1 + rep * kFrameCoarse, tab, g, sp, ctr, fresh);
     add_fresh(ctr, fresh);
     if (SKETCH) {
         __syncthreads();  // every sampled key is registered
@@ -1170,8 +1182,9 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_keys_f(const uint32_t* __re
     }
     uint32_t fresh = 0;
     const uint64_t first = (uint64_t)b1 << fine_log2;
-    fbin_tile<false>(S, ent, bucket, valid, nb, sub_shift, b1, bin2 + (first * kBinRep + r) * cap2, kBinRep * cap2,
-                     cap2, cursor2 + ((uint64_t)r << g.p_log2) + first, tab, g, sp, ctr, fresh);
+    fbin_tile<false, FBIN_ITEMS>(S, ent, bucket, valid, nb, sub_shift, b1, bin2 + (first * kBinRep + r) * cap2,
+                                 kBinRep * cap2, cap2, cursor2 + ((uint64_t)r << g.p_log2) + first, tab, g, sp, ctr,
+                                 fresh);
     add_fresh(ctr, fresh);
 }
 
@@ -1333,6 +1346,137 @@ __global__ __launch_bounds__(AGG_THREADS, 6) void k_aggregate_f(const uint32_t* 
     const uint32_t cb = (uint32_t)(p >> (g.p_log2 - kFrameCoarseLog2));
     uint32_t fresh = 0;
     aggregate_entries(L, part, cb, g, ctr[C_TABLE_KEYS] != 0, A, sp, ctr, fresh);
+    add_fresh(ctr, fresh);
+}
+
+// The same update with 4-byte claim words, for tables with at least 512
+// partitions: a partition's entries then share their top p_log2 - 8 bits
+// (the partition's bits below its coarse bucket), so an entry whose top bit
+// differs from theirs marks an empty slot and another one a slot holding a
+// key outside the frame.  The slice takes 32 KB of LDS instead of 48, which
+// lets four workgroups share a CU.
+struct FAggLds32 {
+    uint32_t ent[kPartSlots];
+    uint32_t cnt[kPartSlots];
+};
+
+__global__ __launch_bounds__(AGG_THREADS, 8) void k_aggregate_f32(const uint32_t* __restrict__ bin2, uint64_t cap2,
+                                                                  const uint32_t* cursor2, Slot* tab, const Geo g,
+                                                                  SpillBuf sp, unsigned long long* ctr) {
+    __shared__ FAggLds32 A;
+    const uint64_t p = blockIdx.x;
+    const uint64_t parts = gridDim.x;
+    const PartEntries<kBinRep> L(bin2 + p * kBinRep * cap2, cap2, cursor2 + p, parts, cap2);
+    if (L.total == 0) return;  // uniform across the workgroup
+    const bool load = ctr[C_TABLE_KEYS] != 0;
+    Slot* part = tab + (p << kPartLog2);
+    const uint32_t fine = g.p_log2 - kFrameCoarseLog2;  // >= 1 here
+    const uint32_t cb = (uint32_t)(p >> fine);
+    const uint32_t top = (uint32_t)(p & ((1u << fine) - 1)) << (32 - fine);
+    const uint32_t kEmpty = top ^ 0x80000000u, kAlien = kEmpty ^ 1u;  // never an entry of this partition
+    constexpr int PER = (int)kPartSlots / AGG_THREADS;
+    if (load) {
+        Slot v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) v[u] = part[u * AGG_THREADS + threadIdx.x];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const uint32_t sl = u * AGG_THREADS + threadIdx.x;
+            uint64_t h;
+            uint32_t e = kEmpty, c = 0;
+            if (v[u].key != kEmptyKey) {
+                c = v[u].count;
+                if (!frame_code(v[u].key, g.fx, g.fy, h, e)) e = kAlien;
+            }
+            A.ent[sl] = e;
+            A.cnt[sl] = c;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            A.ent[u * AGG_THREADS + threadIdx.x] = kEmpty;
+            A.cnt[u * AGG_THREADS + threadIdx.x] = 0;
+        }
+    }
+    __syncthreads();
+    const uint32_t cnt = L.total;
+    uint32_t li = 0, lo = 0, hi = L.size[0];
+    constexpr uint32_t STEP = AGG_THREADS * FAGG_BATCH;
+    auto fetch = [&](uint32_t q0, uint32_t (&k)[FAGG_BATCH]) {
+        const uint32_t* at[FAGG_BATCH];
+#pragma unroll
+        for (int u = 0; u < FAGG_BATCH; ++u) {
+            const uint32_t q = min(q0 + u * AGG_THREADS + threadIdx.x, cnt - 1);
+            while (q >= hi) {
+                ++li;
+                lo = hi;
+                hi += L.size_of(li);
+            }
+            at[u] = L.src + li * L.lstride + (q - lo);
+        }
+#pragma unroll
+        for (int u = 0; u < FAGG_BATCH; ++u) k[u] = __builtin_nontemporal_load(at[u]);
+    };
+    uint32_t fresh = 0;
+    uint32_t k[FAGG_BATCH], next[FAGG_BATCH];
+    fetch(0, next);
+    for (uint32_t q0 = 0; q0 < cnt; q0 += STEP) {
+#pragma unroll
+        for (int u = 0; u < FAGG_BATCH; ++u) k[u] = next[u];
+        if (q0 + STEP < cnt) fetch(q0 + STEP, next);  // uniform across the workgroup
+        // home-slot reads of all entries together
+        uint32_t pos[FAGG_BATCH], cur[FAGG_BATCH];
+#pragma unroll
+        for (int u = 0; u < FAGG_BATCH; ++u) {
+            pos[u] = mix32(k[u]) & (kPartSlots - 1);
+            cur[u] = q0 + u * AGG_THREADS + threadIdx.x < cnt
+                         ? __hip_atomic_load(&A.ent[pos[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+                         : kEmpty;
+        }
+#pragma unroll
+        for (int u = 0; u < FAGG_BATCH; ++u) {
+            const bool have = q0 + u * AGG_THREADS + threadIdx.x < cnt;
+            int r = ADD_FOUND;
+            if (have) {
+                const uint32_t e = k[u];
+                uint32_t ps = pos[u], c = cur[u];
+                r = ADD_FULL;
+                for (uint32_t step = 0; step < kMaxProbe; ++step) {
+                    if (step) c = __hip_atomic_load(&A.ent[ps], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (c == kEmpty) {
+                        c = atomicCAS(&A.ent[ps], kEmpty, e);
+                        if (c == kEmpty) {
+                            atomicAdd(&A.cnt[ps], 1u);
+                            r = ADD_NEW;
+                            break;
+                        }
+                    }
+                    if (c == e) {
+                        atomicAdd(&A.cnt[ps], 1u);
+                        r = ADD_FOUND;
+                        break;
+                    }
+                    ps = (ps + 1) & (kPartSlots - 1);
+                }
+                fresh += (r == ADD_NEW);
+            }
+            const uint64_t key = r == ADD_FULL ? frame_key(cb, k[u], g.fx, g.fy) : 0;
+            spill_push(sp, ctr, r == ADD_FULL, key, 1u);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const uint32_t sl = u * AGG_THREADS + threadIdx.x;
+        const uint32_t e = A.ent[sl];
+        if (e != kEmpty && e != kAlien) {
+            Slot v;
+            v.key = frame_key(cb, e, g.fx, g.fy);
+            v.count = A.cnt[sl];
+            v.aux = kNotSignificant;
+            part[sl] = v;
+        }
+    }
     add_fresh(ctr, fresh);
 }
 
@@ -3011,7 +3155,8 @@ hipError_t launch_bin_points_framed(const void* pts, int64_t n, int dtype, doubl
     if (n <= 0) return hipSuccess;
     const Geo g = make_geo(cap, false, frame);
     if (!g.framed) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((n + kFBinTile - 1) / kFBinTile));
+    const uint32_t tile = BIN_THREADS * kFBinItems1;
+    const dim3 grid((unsigned)((n + tile - 1) / tile));
     auto go = [&](auto kernel, const auto* p) {
         hipLaunchKernelGGL(kernel, grid, dim3(BIN_THREADS), 0, stream, p, n, scale, bin1, cap1, cursor1, tab, g, spill,
                            ctr, hll);
@@ -3019,11 +3164,11 @@ hipError_t launch_bin_points_framed(const void* pts, int64_t n, int dtype, doubl
     const float* pf = static_cast<const float*>(pts);
     const double* pd = static_cast<const double*>(pts);
     if (dtype == 1) {
-        if (hll) go(k_bin_points_f<float, true>, pf);
-        else go(k_bin_points_f<float, false>, pf);
+        if (hll) go(k_bin_points_f<float, true, kFBinItems1>, pf);
+        else go(k_bin_points_f<float, false, kFBinItems1>, pf);
     } else {
-        if (hll) go(k_bin_points_f<double, true>, pd);
-        else go(k_bin_points_f<double, false>, pd);
+        if (hll) go(k_bin_points_f<double, true, kFBinItems1>, pd);
+        else go(k_bin_points_f<double, false, kFBinItems1>, pd);
     }
     return hipGetLastError();
 }
@@ -3049,8 +3194,12 @@ hipError_t launch_aggregate_framed(const uint32_t* bin2, uint64_t cap2, const ui
     if (!framed_binned_geometry(g)) return hipErrorInvalidValue;
     const uint64_t parts = 1ull << g.p_log2;
     hipLaunchKernelGGL(k_snapshot_keys, dim3(1), dim3(64), 0, stream, ctr);
-    hipLaunchKernelGGL(k_aggregate_f, dim3((unsigned)parts), dim3(AGG_THREADS), 0, stream, bin2, cap2, cursor2, tab,
-                       g, spill, ctr);
+    if (g.p_log2 > kFrameCoarseLog2)
+        hipLaunchKernelGGL(k_aggregate_f32, dim3((unsigned)parts), dim3(AGG_THREADS), 0, stream, bin2, cap2, cursor2,
+                           tab, g, spill, ctr);
+    else
+        hipLaunchKernelGGL(k_aggregate_f, dim3((unsigned)parts), dim3(AGG_THREADS), 0, stream, bin2, cap2, cursor2,
+                           tab, g, spill, ctr);
     hipLaunchKernelGGL(k_zero_u32, dim3(8), dim3(256), 0, stream, cursor1, (uint64_t)kBinRep * kFrameCoarse);
     return hipGetLastError();
 }
