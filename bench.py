@@ -473,7 +473,7 @@ def bench_batched(raster, torch, n_jobs: int, reps: int):
 
 
 def bench_served(raster, torch, duration_s: float, rate: float, slots: int, stress_rate: float = 0.0,
-                 stress_s: float = 4.0):
+                 stress_s: float = 2.0):
     """Poisson arrivals replayed in real time: the continuous-batching server
     against a plain FIFO worker issuing one call per job; at the workload's
     rate and, if stress_rate > 0, at a rate that queues jobs."""
@@ -546,6 +546,8 @@ def served_run(raster, torch, pool64, pool32, duration_s: float, rate: float, sl
         srv.close()
         return lat, done_at[0] - t0
 
+    service = []  # plain per-job call times, without waiting
+
     def run_fifo():
         import queue
         q = queue.Queue()
@@ -559,10 +561,12 @@ def served_run(raster, torch, pool64, pool32, duration_s: float, rate: float, sl
                     return
                 j, arrived = item
                 sp = trace[j]
+                start = time.perf_counter()
                 r = raster.cluster(views[j], precision=sp.precision, tau=sp.tau, mu=sp.mu)
                 r.free()
                 now = time.perf_counter()
                 lat.append(now - arrived)
+                service.append(now - start)
                 done_at[0] = now
 
         th = threading.Thread(target=worker)
@@ -578,16 +582,26 @@ def served_run(raster, torch, pool64, pool32, duration_s: float, rate: float, sl
         return lat, done_at[0] - t0
 
     out = {}
+    big = np.array([sp.n >= 2_000_000 for sp in trace])
     for name, fn in (("server", run_server), ("plain_fifo", run_fifo)):
         lat, span = fn()
         out[name] = {"p50_ms": 1e3 * pct(lat, 50), "p99_ms": 1e3 * pct(lat, 99), "mean_ms": 1e3 * float(np.mean(lat)),
                      "points_per_s": total / span, "makespan_s": span}
+        # both record latencies in arrival order: split by job size
+        lat_a = np.asarray(lat)
+        out[name]["p99_ms_jobs_below_2M"] = 1e3 * pct(lat_a[~big], 99)
+        out[name]["p99_ms_jobs_2M_up"] = 1e3 * pct(lat_a[big], 99)
+    svc = np.asarray(service)
+    service_stats = {"p50_ms": 1e3 * pct(svc, 50), "p99_ms": 1e3 * pct(svc, 99),
+                     "p99_ms_jobs_below_2M": 1e3 * pct(svc[~big], 99), "p99_ms_jobs_2M_up": 1e3 * pct(svc[big], 99),
+                     "busy_fraction": float(svc.sum()) / duration_s}
     del views
     return {"workload": f"Poisson {rate:g} jobs/s for {duration_s:g} s ({len(trace)} jobs), n log-uniform in "
                         "[1e3, 2e7] (windows of one 20M-point set shaped like workload 1), FP32/FP64 per job, "
                         "p/tau/mu drawn per job, budget 64 GiB",
             "jobs": len(trace), "points": total, "offered_points_per_s": total / duration_s, "slots": slots,
-            "server": out["server"], "plain_fifo": out["plain_fifo"]}
+            "server": out["server"], "plain_fifo": out["plain_fifo"],
+            "plain_call_time": service_stats}
 
 
 def main():
@@ -610,7 +624,7 @@ def main():
     ap.add_argument("--no-point-labels", action="store_true",
                     help="skip the per-point label pass and the per-tile point lists")
     ap.add_argument("--no-served", action="store_true", help="skip the served (Poisson trace) comparison")
-    ap.add_argument("--served-seconds", type=float, default=10.0)
+    ap.add_argument("--served-seconds", type=float, default=30.0)
     ap.add_argument("--served-rate", type=float, default=200.0)
     ap.add_argument("--served-slots", type=int, default=4)
     ap.add_argument("--served-stress-rate", type=float, default=2000.0,

@@ -926,7 +926,7 @@ raster_status TableRun::finish(raster_result** out) {
     if (e == hipSuccess) e = hipEventRecord(ev[2], stream);
     if (e == hipSuccess)
         e = launch_agglomerate(tab, cap, jv, s_key, parent, nbr, size, m, ctr, stream, rounds.data(),
-                               (int)rounds.size(), dims == 3);
+                               (int)rounds.size(), dims == 3, frame);
     if (e == hipSuccess) e = hipEventRecord(ev[3], stream);
     if (e == hipSuccess)
         e = launch_filter(jv, s_key, s_count, nbr, size, r->kx, r->ky, r->count, r->label, nullptr, partials, ctr,

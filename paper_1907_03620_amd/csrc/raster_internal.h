@@ -322,7 +322,7 @@ hipError_t launch_agglomerate(const Slot* tab, uint64_t slots_max, const JobView
                               uint32_t* parent, uint32_t* nbr, uint32_t* size, uint64_t s_max,
                               unsigned long long* ctr, hipStream_t stream,
                               const NbrRound* rounds = nullptr, int nrounds = 0,
-                              bool d3 = false);
+                              bool d3 = false, Frame frame = Frame{});
 
 // mu filter and output compaction: rows of kept components in compact order
 // (out_job gets each row's job for several jobs).

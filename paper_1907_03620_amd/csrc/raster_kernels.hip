@@ -2379,6 +2379,145 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_part(const Slot* tab, Job
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
 }
 
+// The eight-neighbour link pass of a framed single table of at least 512
+// partitions (as k_link_part<false, false>): the slice is held in LDS as
+// 4-byte entries (with the empty and foreign markers of k_aggregate_f32), 40
+// KB instead of 56, so that more workgroups share a CU and hide the latency
+// of the probes into other partitions.
+__global__ __launch_bounds__(LINK_THREADS) void k_link_framed(const Slot* tab, const Geo g, uint32_t* parent,
+                                                              uint32_t* nbr, unsigned long long* ctr) {
+    __shared__ uint32_t lent[kPartSlots];
+    __shared__ uint32_t laux[kPartSlots];
+    __shared__ uint16_t list[kPartSlots];
+    __shared__ uint32_t nlist;
+    const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
+    const uint64_t parts = 1ull << g.p_log2;
+    const uint32_t fine = g.p_log2 - kFrameCoarseLog2;  // >= 1 here
+    bool bad = false;
+    for (uint64_t p = blockIdx.x; p < parts; p += gridDim.x) {
+        const uint64_t base = p << kPartLog2;
+        const uint32_t cb = (uint32_t)(p >> fine);
+        const uint32_t top = (uint32_t)(p & ((1u << fine) - 1)) << (32 - fine);
+        const uint32_t kEmpty = top ^ 0x80000000u, kAlien = kEmpty ^ 1u;  // never an entry of this partition
+        if (threadIdx.x == 0) nlist = 0;
+        __syncthreads();  // also orders the previous partition's LDS reads before the overwrite
+        constexpr int PER = (int)kPartSlots / LINK_THREADS;
+        {
+            Slot v[PER];
+#pragma unroll
+            for (int k = 0; k < PER; ++k) v[k] = tab[base + k * LINK_THREADS + threadIdx.x];
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const uint32_t u = k * LINK_THREADS + threadIdx.x;
+                uint64_t h;
+                uint32_t e = kEmpty;
+                if (v[k].key != kEmptyKey && !frame_code(v[k].key, g.fx, g.fy, h, e)) e = kAlien;
+                lent[u] = e;
+                laux[u] = v[k].key != kEmptyKey ? v[k].aux : kNotSignificant;
+            }
+        }
+        for (uint32_t u0 = 0; u0 < kPartSlots; u0 += LINK_THREADS) {
+            const uint32_t u = u0 + threadIdx.x;
+            const bool sig = laux[u] != kNotSignificant;
+            const uint64_t b = __ballot(sig);
+            uint32_t wbase = 0;
+            if (lane_id() == 0 && b) wbase = atomicAdd(&nlist, (uint32_t)__popcll(b));
+            wbase = __shfl(wbase, 0);
+            if (sig) list[wbase + __popcll(b & lanemask_lt())] = (uint16_t)u;
+        }
+        __syncthreads();
+        const uint32_t nl = nlist;
+        for (uint32_t t = threadIdx.x; t < nl; t += LINK_THREADS) {
+            const uint32_t u = list[t];
+            const uint32_t i = laux[u];
+            if (i >= s) {
+                bad = true;
+                continue;
+            }
+            const uint32_t eu = lent[u];
+            const uint64_t key = eu != kAlien ? frame_key(cb, eu, g.fx, g.fy) : tab[base + u].key;
+            const uint32_t bx = (uint32_t)(key >> 32), by = (uint32_t)key;
+            // valid biased coordinates lie in [2, 2^32 - 2]
+            const bool left = bx > 2u, down = by > 2u, up = by < 0xFFFFFFFEu;
+            uint64_t nk[4];
+            bool want[4];
+            nk[0] = ((uint64_t)(bx - 1) << 32) | (uint32_t)(by - 1);
+            want[0] = left && down;
+            nk[1] = ((uint64_t)(bx - 1) << 32) | by;
+            want[1] = left;
+            nk[2] = ((uint64_t)(bx - 1) << 32) | (uint32_t)(by + 1);
+            want[2] = left && up;
+            nk[3] = ((uint64_t)bx << 32) | (uint32_t)(by - 1);
+            want[3] = down;
+            // device-table loads for the other partitions issued together
+            // (home slot and the next one); LDS probes need no wait
+            uint64_t pos[4];
+            uint32_t e[4];
+            bool local[4];
+            Slot v[4], w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint64_t h;
+                local[q] = frame_code(nk[q], g.fx, g.fy, h, e[q]) && (h >> (kFrameStBits - g.p_log2)) == p;
+                pos[q] = home_slot(nk[q], g);
+                if (want[q] && !local[q]) {
+                    v[q] = tab[pos[q]];
+                    w[q] = tab[next_slot(pos[q], g)];
+                }
+            }
+            uint32_t j[4];
+            uint32_t best = i;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                j[q] = kNoNeighbour;
+                if (!want[q]) continue;
+                uint32_t aux = kNotSignificant;
+                if (local[q]) {
+                    uint32_t lp = (uint32_t)(pos[q] - base);
+                    for (uint32_t step = 0; step < kMaxProbe; ++step) {
+                        const uint32_t cur = lent[lp];
+                        if (cur == e[q]) {
+                            aux = laux[lp];
+                            break;
+                        }
+                        if (cur == kEmpty) break;
+                        lp = (lp + 1) & (kPartSlots - 1);
+                    }
+                } else {
+                    if (v[q].key != nk[q] && v[q].key != kEmptyKey) {
+                        // second probe already loaded
+                        pos[q] = next_slot(pos[q], g);
+                        v[q] = w[q];
+                        uint32_t steps = 2;
+                        while (v[q].key != nk[q] && v[q].key != kEmptyKey && steps < kMaxProbe) {
+                            pos[q] = next_slot(pos[q], g);
+                            v[q] = tab[pos[q]];
+                            ++steps;
+                        }
+                    }
+                    if (v[q].key == nk[q]) aux = v[q].aux;
+                }
+                if (aux != kNotSignificant) {
+                    if (aux >= s) {
+                        bad = true;
+                    } else {
+                        j[q] = aux;
+                        if (best == i) best = aux;  // backward neighbours come in increasing key order
+                    }
+                }
+            }
+            uint4 rec;
+            rec.x = j[0];
+            rec.y = j[1];
+            rec.z = j[2];
+            rec.w = j[3];
+            reinterpret_cast<uint4*>(nbr)[i] = rec;
+            parent[i] = best;
+        }
+    }
+    if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
+}
+
 // Parents after this pass are roots or, where a concurrent path-halving write
 // lands after the root is stored, ancestors; merge and compress only need
 // ancestors.
@@ -3246,10 +3385,15 @@ hipError_t launch_threshold(Slot* tab, const JobView& jv, uint64_t* s_key, uint3
 hipError_t launch_agglomerate(const Slot* tab, uint64_t slots_max, const JobView& jv, const uint64_t* s_key,
                               uint32_t* parent, uint32_t* nbr, uint32_t* size, uint64_t s_max,
                               unsigned long long* ctr, hipStream_t stream, const NbrRound* rounds, int nrounds,
-                              bool d3) {
+                              bool d3, Frame frame) {
     const int grid = (grid_for(s_max, 256, kPersistBlocks) + kXcds - 1) / kXcds * kXcds;
     const int link_grid = grid_for((slots_max + kPartSlots - 1) >> kPartLog2, 1, 8192);
-    if (nrounds <= 0) {
+    const Geo fg = make_geo(slots_max, d3, frame);
+    if (nrounds <= 0 && fg.framed && fg.cp_log2 == kPartLog2 && fg.p_log2 > kFrameCoarseLog2) {
+        hipLaunchKernelGGL(k_link_framed, dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, fg, parent, nbr, ctr);
+        hipLaunchKernelGGL(k_jump, dim3(grid), dim3(256), 0, stream, parent, ctr);
+        hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, stream, nbr, 1u, s_key, parent, ctr);
+    } else if (nrounds <= 0) {
         hipLaunchKernelGGL((k_link_part<false, false>), dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, jv,
                            parent, nbr, ctr, NbrGroup{});
         hipLaunchKernelGGL(k_jump, dim3(grid), dim3(256), 0, stream, parent, ctr);
