@@ -92,6 +92,8 @@ def kernel_group(name: str):
     for g in ("k_bin_points", "k_bin_keys", "k_aggregate", "k_threshold", "k_link_part", "k_filter"):
         if name.startswith(g):
             return g
+    if name.startswith("k_link_framed"):
+        return "k_link_part"
     if name.startswith(("k_jump", "k_merge", "k_compress")):
         return "union-find"
     return None
@@ -264,11 +266,16 @@ def bench_point_labels(raster, torch, res, dev, reps: int = 3):
     avg_call_us = 1000.0 * float(np.mean(per_call))
     per_launch = n / len(dev)
     gbps = 40.0 * per_launch / (avg_call_us * 1e-6) / 1e9
+    traffic = measured_traffic(int(per_launch), "labels_hbm_bytes_per_launch")
+    # the lookup of each point's tile is one random table line: the kernel is
+    # bound by that line traffic, reported beside the algorithmic rate
+    traffic_gbps = traffic / (avg_call_us * 1e-6) / 1e9 if traffic else None
     return {"points": n, "ms_per_pass": ms, "points_per_s": n / (ms * 1e-3),
             "avg_launch_us": avg_call_us, "launches_per_pass": len(dev),
             "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
             "algorithmic_bytes": "40 B per point: 16 of coordinates in, one 16-byte slot, 8 of label out",
-            "traffic": measured_traffic(int(per_launch), "labels_hbm_bytes_per_launch"),
+            "traffic": traffic, "traffic_bytes_per_point": traffic / per_launch if traffic else None,
+            "traffic_gbps": traffic_gbps, "traffic_frac": traffic_gbps / HBM_PEAK_GBPS if traffic else None,
             "noise_points": noise}
 
 
