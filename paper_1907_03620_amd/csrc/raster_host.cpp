@@ -374,9 +374,6 @@ struct HostCache {
 
 TableRun::~TableRun() {
     HostCache& hc = HostCache::get();
-    // a counter copy may still be in flight into h_ctr: wait before another
-    // stream can receive the mirror
-    if (chunk_pending && ev_chunk) (void)hipEventSynchronize(ev_chunk);
     for (hipEvent_t& e : ev) if (e) hc.give_event(device, true, e);
     if (ev_chunk) hc.give_event(device, false, ev_chunk);
     for (const Span& sp : spans) {
@@ -419,14 +416,17 @@ raster_status TableRun::ensure_sketch() {
     return RASTER_OK;
 }
 
-// Reads the sketch registers (one copy and wait) and sizes the table from
-// them.  A single-shot call may replace an empty table by one of the
+// Reads the sketch registers (one copy and wait, unless the caller has
+// fetched them already) and sizes the table from them.  A single-shot call may replace an empty table by one of the
 // estimated size; a stream grows its table only when the estimate shows it
 // too full to work in.
-raster_status TableRun::size_from_sketch(uint64_t points) {
+raster_status TableRun::size_from_sketch(uint64_t points, bool fetched) {
     const size_t regs = (size_t)kHllReps << kHllLog2;
-    HIP_TRY(hipMemcpyAsync(h_sketch, sketch, regs * sizeof(uint32_t), hipMemcpyDeviceToHost, stream), "sketch copy");
-    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    if (!fetched) {
+        HIP_TRY(hipMemcpyAsync(h_sketch, sketch, regs * sizeof(uint32_t), hipMemcpyDeviceToHost, stream),
+                "sketch copy");
+        HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    }
     const uint32_t* h = h_sketch;
     std::vector<uint32_t> M(1u << kHllLog2, 0);
     for (uint32_t r = 0; r < kHllReps; ++r)
@@ -630,6 +630,11 @@ raster_status TableRun::grow(uint64_t new_cap, uint64_t pending, int src) {
 raster_status TableRun::settle() {
     if (!chunk_pending) return RASTER_OK;
     chunk_pending = false;
+    // the counters are copied only now, once for all the work enqueued
+    // since the last settle: a copy after every chunk stalls the stream
+    HIP_TRY(hipMemcpyAsync(h_ctr, ctr, kCounterWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream),
+            "counter copy");
+    HIP_TRY(hipEventRecord(ev_chunk, stream), "hipEventRecord");
     HIP_TRY(hipEventSynchronize(ev_chunk), "hipEventSynchronize");
     resolve_spans();
     if (h_ctr[C_ERROR] & kErrRange) {
@@ -653,11 +658,8 @@ raster_status TableRun::settle() {
     return RASTER_OK;
 }
 
+// Marks work whose counters the next settle() reads.
 raster_status TableRun::mark_pending() {
-    HIP_TRY(hipMemcpyAsync(h_ctr, ctr, kCounterWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream),
-            "counter copy");
-
-    HIP_TRY(hipEventRecord(ev_chunk, stream), "hipEventRecord");
     chunk_pending = true;
     return RASTER_OK;
 }
@@ -688,9 +690,16 @@ raster_status TableRun::ensure_bins(uint64_t want_points) {
 // Applies the keys waiting in the coarse buckets to the table.
 raster_status TableRun::flush() {
     if (group_points == 0) return RASTER_OK;
+    // the sketch registers come back with the counters, in one wait
+    if (sketch) {
+        HIP_TRY(hipMemcpyAsync(h_sketch, sketch, ((size_t)kHllReps << kHllLog2) * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, stream),
+                "sketch copy");
+        chunk_pending = true;
+    }
     raster_status st = settle();
     if (st != RASTER_OK) return st;
-    if (sketch && (st = size_from_sketch(group_points)) != RASTER_OK) return st;
+    if (sketch && (st = size_from_sketch(group_points, true)) != RASTER_OK) return st;
     const Geo g = geo();
     SpillBuf sp{spill_keys[0], spill_counts[0], spill_cap[0]};
     if (frame.on && !framed_binned_geometry(g)) {
@@ -776,7 +785,16 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
         // previous chunks already filled it past the target
         want = next_pow2((uint64_t)(2.0 * (double)h_ctr[C_INSERTED] / lf));
     }
-    if (want > cap) {
+    if (want > cap && n_points == 0) {
+        // nothing inserted yet: a fresh table instead of a rehash and its
+        // wait.  The starter table stays held until the run ends, since its
+        // fill may still be running.
+        Slot* nt = nullptr;
+        uint64_t nc = 0;
+        if ((st = alloc_table(want, &nt, &nc)) != RASTER_OK) return st;
+        tab = nt;
+        cap = nc;
+    } else if (want > cap) {
         st = grow(want, 0, 0);
         if (st != RASTER_OK) {
             failed = st;

@@ -175,7 +175,7 @@ struct TableRun {
     size_t bin_entry_bytes() const { return frame.on ? sizeof(uint32_t) : sizeof(uint64_t); }
     uint32_t coarse_buckets() const { return frame.on ? kFrameCoarse : kCoarse; }
     Geo geo() const { return make_geo(cap, dims == 3, frame); }
-    raster_status size_from_sketch(uint64_t points);
+    raster_status size_from_sketch(uint64_t points, bool fetched = false);
     raster_status ensure_sketch();
     raster_status ensure_spill(int b, uint64_t need);
     raster_status pull_counters();
