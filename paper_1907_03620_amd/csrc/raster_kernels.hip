@@ -1353,11 +1353,19 @@ __global__ __launch_bounds__(AGG_THREADS, 6) void k_aggregate_f(const uint32_t* 
 // partitions: a partition's entries then share their top p_log2 - 8 bits
 // (the partition's bits below its coarse bucket), so an entry whose top bit
 // differs from theirs marks an empty slot and another one a slot holding a
-// key outside the frame.  The slice takes 32 KB of LDS instead of 48, which
+// key outside the frame.
+//
+// Each entry looks at its home slot and the next one, which hold about 90%
+// of the entries of a partition filled to half its slots.  The others are
+// deferred to a ring of the wave's own in LDS and walk their probe sequences
+// 64 at a time, one per lane, so that a wave does not run the longest walk
+// of each of its entries.  The slice and the rings take 36 KB of LDS, which
 // lets four workgroups share a CU.
+constexpr uint32_t AGG_RING = 128;  // deferred entries per wave (at most 127 wait)
 struct FAggLds32 {
     uint32_t ent[kPartSlots];
     uint32_t cnt[kPartSlots];
+    uint32_t ring[AGG_THREADS / 64][AGG_RING];
 };
 
 __global__ __launch_bounds__(AGG_THREADS, 8) void k_aggregate_f32(const uint32_t* __restrict__ bin2, uint64_t cap2,
@@ -1399,71 +1407,110 @@ __global__ __launch_bounds__(AGG_THREADS, 8) void k_aggregate_f32(const uint32_t
         }
     }
     __syncthreads();
-    const uint32_t cnt = L.total;
-    uint32_t li = 0, lo = 0, hi = L.size[0];
+    uint32_t* ring = A.ring[threadIdx.x >> 6];
+    const uint32_t lane = lane_id();
+    const uint64_t lt = lanemask_lt();
+    uint32_t head = 0, tail = 0;  // the wave's ring (uniform across the wave)
+    uint32_t fresh = 0;
+    // Up to 64 deferred entries, one per lane, walk their probe sequences from
+    // the home slot (a lost claim may have filled the first two slots with
+    // other keys since they were read).
+    auto drain = [&]() {
+        const uint32_t n = min(tail - head, 64u);
+        bool act = lane < n;
+        const uint32_t e = act ? ring[(head + lane) & (AGG_RING - 1)] : 0u;
+        head += n;
+        uint32_t ps = mix32(e) & (kPartSlots - 1);
+        for (uint32_t step = 0; act && step < kMaxProbe; ++step) {
+            uint32_t c = __hip_atomic_load(&A.ent[ps], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (c == kEmpty) {
+                c = atomicCAS(&A.ent[ps], kEmpty, e);
+                fresh += (c == kEmpty);
+            }
+            if (c == kEmpty || c == e) {
+                atomicAdd(&A.cnt[ps], 1u);
+                act = false;
+            } else {
+                ps = (ps + 1) & (kPartSlots - 1);
+            }
+        }
+        // still active: no slot within the probe limit
+        spill_push(sp, ctr, act, act ? frame_key(cb, e, g.fx, g.fy) : 0, 1u);
+    };
+    // One entry at its first two slots; true when it has to walk further.
+    auto first_two = [&](uint32_t e, uint32_t h, uint32_t c0, uint32_t c1) {
+        uint32_t s = h, c = c0;
+        if (c != e && c != kEmpty) {
+            s = (h + 1) & (kPartSlots - 1);
+            c = c1;
+        }
+        if (c != e && c != kEmpty) return true;
+        if (c == kEmpty) {
+            c = atomicCAS(&A.ent[s], kEmpty, e);
+            if (c == kEmpty) {
+                ++fresh;
+                c = e;
+            }
+        }
+        if (c != e) return true;
+        atomicAdd(&A.cnt[s], 1u);
+        return false;
+    };
+    // Batches of STEP entries, list by list: (li, q0) is uniform across the
+    // workgroup, and the next batch's loads are in flight while this one is
+    // added.
     constexpr uint32_t STEP = AGG_THREADS * FAGG_BATCH;
-    auto fetch = [&](uint32_t q0, uint32_t (&k)[FAGG_BATCH]) {
-        const uint32_t* at[FAGG_BATCH];
+    uint32_t li = 0, q0 = 0;
+    while (li < kBinRep && L.size_of(li) == 0) ++li;
+    auto fetch = [&](uint32_t bl, uint32_t bq, uint32_t (&k)[FAGG_BATCH]) {
+        const uint32_t n_l = L.size_of(bl);
+        const uint32_t* src = L.src + bl * L.lstride;
 #pragma unroll
         for (int u = 0; u < FAGG_BATCH; ++u) {
-            const uint32_t q = min(q0 + u * AGG_THREADS + threadIdx.x, cnt - 1);
-            while (q >= hi) {
-                ++li;
-                lo = hi;
-                hi += L.size_of(li);
-            }
-            at[u] = L.src + li * L.lstride + (q - lo);
+            const uint32_t q = bq + u * AGG_THREADS + threadIdx.x;
+            k[u] = __builtin_nontemporal_load(src + min(q, n_l - 1));
         }
-#pragma unroll
-        for (int u = 0; u < FAGG_BATCH; ++u) k[u] = __builtin_nontemporal_load(at[u]);
     };
-    uint32_t fresh = 0;
     uint32_t k[FAGG_BATCH], next[FAGG_BATCH];
-    fetch(0, next);
-    for (uint32_t q0 = 0; q0 < cnt; q0 += STEP) {
+    if (li < kBinRep) fetch(li, q0, next);
+    while (li < kBinRep) {
+        const uint32_t n_l = L.size_of(li), bq = q0;
 #pragma unroll
         for (int u = 0; u < FAGG_BATCH; ++u) k[u] = next[u];
-        if (q0 + STEP < cnt) fetch(q0 + STEP, next);  // uniform across the workgroup
-        // home-slot reads of all entries together
-        uint32_t pos[FAGG_BATCH], cur[FAGG_BATCH];
+        q0 += STEP;
+        if (q0 >= n_l) {
+            q0 = 0;
+            do ++li;
+            while (li < kBinRep && L.size_of(li) == 0);
+        }
+        if (li < kBinRep) fetch(li, q0, next);
+        // the first two slots of every entry read together
+        uint32_t hs[FAGG_BATCH], c0[FAGG_BATCH], c1[FAGG_BATCH];
 #pragma unroll
         for (int u = 0; u < FAGG_BATCH; ++u) {
-            pos[u] = mix32(k[u]) & (kPartSlots - 1);
-            cur[u] = q0 + u * AGG_THREADS + threadIdx.x < cnt
-                         ? __hip_atomic_load(&A.ent[pos[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
-                         : kEmpty;
+            hs[u] = mix32(k[u]) & (kPartSlots - 1);
+            c0[u] = __hip_atomic_load(&A.ent[hs[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            c1[u] = __hip_atomic_load(&A.ent[(hs[u] + 1) & (kPartSlots - 1)], __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WORKGROUP);
         }
 #pragma unroll
         for (int u = 0; u < FAGG_BATCH; ++u) {
-            const bool have = q0 + u * AGG_THREADS + threadIdx.x < cnt;
-            int r = ADD_FOUND;
-            if (have) {
-                const uint32_t e = k[u];
-                uint32_t ps = pos[u], c = cur[u];
-                r = ADD_FULL;
-                for (uint32_t step = 0; step < kMaxProbe; ++step) {
-                    if (step) c = __hip_atomic_load(&A.ent[ps], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    if (c == kEmpty) {
-                        c = atomicCAS(&A.ent[ps], kEmpty, e);
-                        if (c == kEmpty) {
-                            atomicAdd(&A.cnt[ps], 1u);
-                            r = ADD_NEW;
-                            break;
-                        }
-                    }
-                    if (c == e) {
-                        atomicAdd(&A.cnt[ps], 1u);
-                        r = ADD_FOUND;
-                        break;
-                    }
-                    ps = (ps + 1) & (kPartSlots - 1);
+            const bool have = bq + u * AGG_THREADS + threadIdx.x < n_l;
+            const bool defer = have && first_two(k[u], hs[u], c0[u], c1[u]);
+            const uint64_t b = __ballot(defer);
+            if (b) {  // uniform across the wave
+                if (defer) ring[(tail + (uint32_t)__popcll(b & lt)) & (AGG_RING - 1)] = k[u];
+                tail += (uint32_t)__popcll(b);
+                if (tail - head >= 64) {
+                    // the ring's entries are written by other lanes of this wave
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    drain();
                 }
-                fresh += (r == ADD_NEW);
             }
-            const uint64_t key = r == ADD_FULL ? frame_key(cb, k[u], g.fx, g.fy) : 0;
-            spill_push(sp, ctr, r == ADD_FULL, key, 1u);
         }
     }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    while (tail != head) drain();
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
