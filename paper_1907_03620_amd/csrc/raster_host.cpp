@@ -899,6 +899,11 @@ raster_status TableRun::finish(raster_result** out) {
     uint32_t* nbr = nullptr;
     const std::vector<NbrRound> rounds = neighbourhood_rounds(metric, delta, dims);
     HIP_TRY(bufs.take((void**)&nbr, m * nbr_words((int)rounds.size()) * sizeof(uint32_t)), "neighbour lists");
+    // framed tables of 512+ partitions: significant slots found by a census
+    // instead of an index written into every significant slot
+    const bool census = dims == 2 && rounds.empty() && census_geometry(cap, frame);
+    uint32_t* c_words = nullptr;
+    if (census) HIP_TRY(bufs.take((void**)&c_words, census_words(cap) * sizeof(uint32_t)), "census");
 
     raster_result* r = new raster_result();
     r->pool = bufs.pool;
@@ -940,11 +945,15 @@ raster_status TableRun::finish(raster_result** out) {
     JobView jv{&sj_dev->dims, &sj_dev->job, nullptr, nullptr, nullptr};
 
     e = launch_zero_u64((uint64_t*)ctr + C_DISTINCT, C_COUNT_ - C_DISTINCT, stream);
-    if (e == hipSuccess) e = launch_threshold(tab, jv, s_key, s_count, size, partials, ctr, stream, square ? cap : 0);
+    if (e == hipSuccess)
+        e = census ? launch_census(tab, cap, frame, jv, tau, square, c_words, partials, ctr, stream)
+                   : launch_threshold(tab, jv, s_key, s_count, size, partials, ctr, stream, square ? cap : 0);
     if (e == hipSuccess) e = hipEventRecord(ev[2], stream);
     if (e == hipSuccess)
-        e = launch_agglomerate(tab, cap, jv, s_key, parent, nbr, size, m, ctr, stream, rounds.data(),
-                               (int)rounds.size(), dims == 3, frame);
+        e = census ? launch_link_census(tab, cap, frame, jv, tau, square, c_words, s_key, s_count, parent, nbr,
+                                        size, m, ctr, stream)
+                   : launch_agglomerate(tab, cap, jv, s_key, parent, nbr, size, m, ctr, stream, rounds.data(),
+                                        (int)rounds.size(), dims == 3, frame);
     if (e == hipSuccess) e = hipEventRecord(ev[3], stream);
     if (e == hipSuccess)
         e = launch_filter(jv, s_key, s_count, nbr, size, r->kx, r->ky, r->count, r->label, nullptr, partials, ctr,
@@ -990,6 +999,7 @@ raster_status TableRun::finish(raster_result** out) {
     bufs.give_back(size);
     bufs.give_back(nbr);
     bufs.give_back(sj_dev);
+    if (c_words) bufs.give_back(c_words);
     *out = r;
     return RASTER_OK;
 }

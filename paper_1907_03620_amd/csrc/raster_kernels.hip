@@ -2426,33 +2426,154 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_part(const Slot* tab, Job
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
 }
 
-// The eight-neighbour link pass of a framed single table of at least 512
-// partitions (as k_link_part<false, false>): the slice is held in LDS as
-// 4-byte entries (with the empty and foreign markers of k_aggregate_f32), 40
-// KB instead of 56, so that more workgroups share a CU and hide the latency
-// of the probes into other partitions.
-__global__ __launch_bounds__(LINK_THREADS) void k_link_framed(const Slot* tab, const Geo g, uint32_t* parent,
-                                                              uint32_t* nbr, unsigned long long* ctr) {
+// ---- framed tables: census of the significant slots, then the link pass ----
+//
+// For a framed single table of at least 512 partitions (Chebyshev distance 1,
+// two dimensions) the compact index of a significant tile -- its rank among
+// the significant slots in slot order (Algorithm 1: the tiles kept by the
+// tau test) -- is computed where it is needed instead of being written into
+// every slot.  The census gives every 32 slots of the table one 8-byte
+// record: their significance bits and the number of significant slots before
+// them.  It counts within census blocks (runs of whole partitions) first; a
+// scan of the block totals and a pass over the records make the counts
+// global.  The link pass then reads each slice once: it writes the compact
+// arrays of its partition and finds the neighbours, local ones through the
+// slice in LDS and the others through the table and one census record.
+
+constexpr int CENSUS_THREADS = 512;
+constexpr uint32_t kCensusRecLog2 = 5;                       // 32 slots per record
+constexpr uint32_t kCensusPartRecs = kPartSlots >> kCensusRecLog2;  // 128
+
+__host__ __device__ inline uint32_t census_blk_shift(uint32_t p_log2) {
+    constexpr uint32_t scan_log2 = 11;  // kScanBlocks == 2^11
+    static_assert((1u << scan_log2) == (uint32_t)kScanBlocks, "census blocks");
+    return p_log2 > scan_log2 ? p_log2 - scan_log2 : 0u;
+}
+
+template <bool SQUARE>
+__device__ __forceinline__ bool slot_significant(const Slot& v, uint32_t tau) {
+    return v.key != kEmptyKey && (v.count >= tau || (SQUARE && v.aux == kSquareKeep));
+}
+
+// rec[r] = (bits of slots 32 r .. 32 r + 31, significant slots before them
+// in their census block); boff[b] = the total of census block b.
+template <bool SQUARE>
+__global__ __launch_bounds__(CENSUS_THREADS) void k_census_framed(const Slot* tab, const Geo g, uint32_t tau,
+                                                                  uint2* rec, uint32_t* boff,
+                                                                  unsigned long long* ctr) {
+    __shared__ uint64_t wbits[64];
+    __shared__ uint32_t ptotal;
+    __shared__ unsigned long long red[CENSUS_THREADS / 64][2];
+    const uint64_t parts = 1ull << g.p_log2;
+    const uint64_t ppb = 1ull << census_blk_shift(g.p_log2);
+    const uint64_t p0 = (uint64_t)blockIdx.x * ppb;
+    const uint32_t w = threadIdx.x >> 6;
+    uint32_t run = 0;
+    unsigned long long occ = 0, sum = 0;
+    for (uint64_t p = p0; p < p0 + ppb && p < parts; ++p) {
+        constexpr int PER = (int)kPartSlots / CENSUS_THREADS;
+        const Slot* sl = tab + (p << kPartLog2);
+        Slot v[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) v[k] = sl[k * CENSUS_THREADS + threadIdx.x];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const bool o = v[k].key != kEmptyKey;
+            occ += o;
+            sum += o ? v[k].count : 0u;
+            // the wave's 64 slots k * CENSUS_THREADS + 64 w + lane form word 8 k + w
+            const uint64_t b = __ballot(slot_significant<SQUARE>(v[k], tau));
+            if (lane_id() == 0) wbits[k * (CENSUS_THREADS / 64) + w] = b;
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const uint64_t b = wbits[threadIdx.x];
+            const uint32_t lo = (uint32_t)__popc((uint32_t)b), c = (uint32_t)__popcll(b);
+            uint32_t inc = c;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t t = __shfl_up(inc, o);
+                if (lane_id() >= (uint32_t)o) inc += t;
+            }
+            const uint32_t before = run + inc - c;
+            uint2* r = rec + (p << 7) + 2 * threadIdx.x;
+            r[0] = make_uint2((uint32_t)b, before);
+            r[1] = make_uint2((uint32_t)(b >> 32), before + lo);
+            if (threadIdx.x == 63) ptotal = inc;
+        }
+        __syncthreads();
+        run += ptotal;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        occ += __shfl_xor(occ, o);
+        sum += __shfl_xor(sum, o);
+    }
+    if (lane_id() == 0) {
+        red[w][0] = occ;
+        red[w][1] = sum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long to = 0, ts = 0;
+        for (int i = 0; i < CENSUS_THREADS / 64; ++i) {
+            to += red[i][0];
+            ts += red[i][1];
+        }
+        boff[blockIdx.x] = run;
+        if (to) atomicAdd(&ctr[C_DISTINCT], to);
+        if (ts) atomicAdd(&ctr[C_SUM], ts);
+    }
+}
+
+// Adds each census block's offset (boff after the scan) to its records.
+__global__ void k_census_offsets(uint2* rec, uint64_t nrec, const uint32_t* boff, uint32_t blk_shift) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nrec;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        rec[i].y += boff[(i >> 7) >> blk_shift];
+}
+
+// Compact index of the significant slot at `pos` from its census record.
+__device__ __forceinline__ uint32_t census_index(uint2 r, uint64_t pos) {
+    return r.y + (uint32_t)__popc(r.x & ((1u << (pos & 31)) - 1u));
+}
+
+// The eight-neighbour link pass over the census (as k_link_part<false, false>
+// for the rest): the slice is held in LDS as 4-byte entries (with the empty
+// and foreign markers of k_aggregate_f32) and the local ranks of its
+// significant slots.
+template <bool SQUARE>
+__global__ __launch_bounds__(LINK_THREADS) void k_link_census(const Slot* tab, const Geo g, uint32_t tau,
+                                                              const uint2* rec, uint64_t* s_key, uint32_t* s_count,
+                                                              uint32_t* size, uint32_t* parent, uint32_t* nbr,
+                                                              unsigned long long* ctr) {
     __shared__ uint32_t lent[kPartSlots];
-    __shared__ uint32_t laux[kPartSlots];
-    __shared__ uint16_t list[kPartSlots];
-    __shared__ uint32_t nlist;
+    __shared__ uint16_t lrank[kPartSlots];  // rank among the partition's significant slots, kNoRank if none
+    __shared__ uint16_t list[kPartSlots];   // slot of each rank
+    constexpr uint16_t kNoRank = 0xFFFFu;
     const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
     const uint64_t parts = 1ull << g.p_log2;
     const uint32_t fine = g.p_log2 - kFrameCoarseLog2;  // >= 1 here
+    const uint32_t w = threadIdx.x >> 6;
+    const uint64_t lt = lanemask_lt();
     bool bad = false;
     for (uint64_t p = blockIdx.x; p < parts; p += gridDim.x) {
         const uint64_t base = p << kPartLog2;
         const uint32_t cb = (uint32_t)(p >> fine);
         const uint32_t top = (uint32_t)(p & ((1u << fine) - 1)) << (32 - fine);
         const uint32_t kEmpty = top ^ 0x80000000u, kAlien = kEmpty ^ 1u;  // never an entry of this partition
-        if (threadIdx.x == 0) nlist = 0;
-        __syncthreads();  // also orders the previous partition's LDS reads before the overwrite
+        const uint2 last = rec[(p << 7) + kCensusPartRecs - 1];
+        const uint32_t poff = rec[p << 7].y;
+        const uint32_t nl = last.y + (uint32_t)__popc(last.x) - poff;
+        __syncthreads();  // the previous partition's LDS reads are done
         constexpr int PER = (int)kPartSlots / LINK_THREADS;
         {
             Slot v[PER];
+            uint32_t wz[PER];  // census counts before this wave's words, loaded with the slice
 #pragma unroll
-            for (int k = 0; k < PER; ++k) v[k] = tab[base + k * LINK_THREADS + threadIdx.x];
+            for (int k = 0; k < PER; ++k) {
+                v[k] = tab[base + k * LINK_THREADS + threadIdx.x];
+                const uint32_t word = (uint32_t)__builtin_amdgcn_readfirstlane(k * (LINK_THREADS / 64) + w);
+                wz[k] = rec[(p << 7) + 2 * word].y;
+            }
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
                 const uint32_t u = k * LINK_THREADS + threadIdx.x;
@@ -2460,23 +2581,27 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_framed(const Slot* tab, c
                 uint32_t e = kEmpty;
                 if (v[k].key != kEmptyKey && !frame_code(v[k].key, g.fx, g.fy, h, e)) e = kAlien;
                 lent[u] = e;
-                laux[u] = v[k].key != kEmptyKey ? v[k].aux : kNotSignificant;
+                const bool sig = slot_significant<SQUARE>(v[k], tau);
+                const uint64_t b = __ballot(sig);
+                const uint32_t r = wz[k] - poff + (uint32_t)__popcll(b & lt);
+                lrank[u] = sig ? (uint16_t)r : kNoRank;
+                if (sig) {
+                    list[r] = (uint16_t)u;
+                    const uint64_t i = (uint64_t)poff + r;
+                    if (i < s) {
+                        s_key[i] = v[k].key;
+                        s_count[i] = v[k].count;
+                        size[i] = 0;
+                    } else {
+                        bad = true;
+                    }
+                }
             }
         }
-        for (uint32_t u0 = 0; u0 < kPartSlots; u0 += LINK_THREADS) {
-            const uint32_t u = u0 + threadIdx.x;
-            const bool sig = laux[u] != kNotSignificant;
-            const uint64_t b = __ballot(sig);
-            uint32_t wbase = 0;
-            if (lane_id() == 0 && b) wbase = atomicAdd(&nlist, (uint32_t)__popcll(b));
-            wbase = __shfl(wbase, 0);
-            if (sig) list[wbase + __popcll(b & lanemask_lt())] = (uint16_t)u;
-        }
         __syncthreads();
-        const uint32_t nl = nlist;
         for (uint32_t t = threadIdx.x; t < nl; t += LINK_THREADS) {
             const uint32_t u = list[t];
-            const uint32_t i = laux[u];
+            const uint32_t i = poff + t;
             if (i >= s) {
                 bad = true;
                 continue;
@@ -2497,11 +2622,13 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_framed(const Slot* tab, c
             nk[3] = ((uint64_t)bx << 32) | (uint32_t)(by - 1);
             want[3] = down;
             // device-table loads for the other partitions issued together
-            // (home slot and the next one); LDS probes need no wait
+            // (home slot, the next one and the census record of the home
+            // slot); LDS probes need no wait
             uint64_t pos[4];
             uint32_t e[4];
             bool local[4];
-            Slot v[4], w[4];
+            Slot v[4], nx[4];
+            uint2 cr[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 uint64_t h;
@@ -2509,7 +2636,8 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_framed(const Slot* tab, c
                 pos[q] = home_slot(nk[q], g);
                 if (want[q] && !local[q]) {
                     v[q] = tab[pos[q]];
-                    w[q] = tab[next_slot(pos[q], g)];
+                    nx[q] = tab[next_slot(pos[q], g)];
+                    cr[q] = rec[pos[q] >> kCensusRecLog2];
                 }
             }
             uint32_t j[4];
@@ -2518,23 +2646,24 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_framed(const Slot* tab, c
             for (int q = 0; q < 4; ++q) {
                 j[q] = kNoNeighbour;
                 if (!want[q]) continue;
-                uint32_t aux = kNotSignificant;
                 if (local[q]) {
                     uint32_t lp = (uint32_t)(pos[q] - base);
                     for (uint32_t step = 0; step < kMaxProbe; ++step) {
                         const uint32_t cur = lent[lp];
                         if (cur == e[q]) {
-                            aux = laux[lp];
+                            const uint16_t r = lrank[lp];
+                            if (r != kNoRank) j[q] = poff + r;
                             break;
                         }
                         if (cur == kEmpty) break;
                         lp = (lp + 1) & (kPartSlots - 1);
                     }
                 } else {
+                    const uint64_t home = pos[q];
                     if (v[q].key != nk[q] && v[q].key != kEmptyKey) {
                         // second probe already loaded
                         pos[q] = next_slot(pos[q], g);
-                        v[q] = w[q];
+                        v[q] = nx[q];
                         uint32_t steps = 2;
                         while (v[q].key != nk[q] && v[q].key != kEmptyKey && steps < kMaxProbe) {
                             pos[q] = next_slot(pos[q], g);
@@ -2542,23 +2671,26 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_framed(const Slot* tab, c
                             ++steps;
                         }
                     }
-                    if (v[q].key == nk[q]) aux = v[q].aux;
+                    if (v[q].key == nk[q] && slot_significant<SQUARE>(v[q], tau)) {
+                        if ((pos[q] >> kCensusRecLog2) != (home >> kCensusRecLog2)) cr[q] = rec[pos[q] >> kCensusRecLog2];
+                        j[q] = census_index(cr[q], pos[q]);
+                    }
                 }
-                if (aux != kNotSignificant) {
-                    if (aux >= s) {
+                if (j[q] != kNoNeighbour) {
+                    if (j[q] >= s) {
                         bad = true;
-                    } else {
-                        j[q] = aux;
-                        if (best == i) best = aux;  // backward neighbours come in increasing key order
+                        j[q] = kNoNeighbour;
+                    } else if (best == i) {
+                        best = j[q];  // backward neighbours come in increasing key order
                     }
                 }
             }
-            uint4 rec;
-            rec.x = j[0];
-            rec.y = j[1];
-            rec.z = j[2];
-            rec.w = j[3];
-            reinterpret_cast<uint4*>(nbr)[i] = rec;
+            uint4 out;
+            out.x = j[0];
+            out.y = j[1];
+            out.z = j[2];
+            out.w = j[3];
+            reinterpret_cast<uint4*>(nbr)[i] = out;
             parent[i] = best;
         }
     }
@@ -3435,12 +3567,9 @@ hipError_t launch_agglomerate(const Slot* tab, uint64_t slots_max, const JobView
                               bool d3, Frame frame) {
     const int grid = (grid_for(s_max, 256, kPersistBlocks) + kXcds - 1) / kXcds * kXcds;
     const int link_grid = grid_for((slots_max + kPartSlots - 1) >> kPartLog2, 1, 8192);
-    const Geo fg = make_geo(slots_max, d3, frame);
-    if (nrounds <= 0 && fg.framed && fg.cp_log2 == kPartLog2 && fg.p_log2 > kFrameCoarseLog2) {
-        hipLaunchKernelGGL(k_link_framed, dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, fg, parent, nbr, ctr);
-        hipLaunchKernelGGL(k_jump, dim3(grid), dim3(256), 0, stream, parent, ctr);
-        hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, stream, nbr, 1u, s_key, parent, ctr);
-    } else if (nrounds <= 0) {
+    (void)d3;
+    (void)frame;
+    if (nrounds <= 0) {
         hipLaunchKernelGGL((k_link_part<false, false>), dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, jv,
                            parent, nbr, ctr, NbrGroup{});
         hipLaunchKernelGGL(k_jump, dim3(grid), dim3(256), 0, stream, parent, ctr);
@@ -3464,6 +3593,55 @@ hipError_t launch_agglomerate(const Slot* tab, uint64_t slots_max, const JobView
             hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, stream, nbr, grp.nrounds, s_key, parent, ctr);
         }
     }
+    // the neighbour lists are dead after the merge pass; their first s words
+    // take the final roots
+    hipLaunchKernelGGL(k_compress, dim3(grid), dim3(256), 0, stream, jv, parent, nbr, size, ctr);
+    return hipGetLastError();
+}
+
+bool census_geometry(uint64_t cap, Frame frame) {
+    const Geo g = make_geo(cap, false, frame);
+    return g.framed && g.cp_log2 == kPartLog2 && g.p_log2 > kFrameCoarseLog2;
+}
+
+uint64_t census_words(uint64_t cap) { return (cap >> 5) * 2; }
+
+hipError_t launch_census(Slot* tab, uint64_t cap, Frame frame, const JobView& jv, uint32_t tau, bool square,
+                         uint32_t* words, uint32_t* partials, unsigned long long* ctr, hipStream_t stream) {
+    const Geo g = make_geo(cap, false, frame);
+    uint2* rec = reinterpret_cast<uint2*>(words);
+    if (square) {
+        const int grid = grid_for((cap + kPartSlots - 1) >> kPartLog2, 1, 8192);
+        hipLaunchKernelGGL(k_square_part, dim3(grid), dim3(SQUARE_THREADS), 0, stream, tab, jv);
+        hipLaunchKernelGGL(k_census_framed<true>, dim3(kScanBlocks), dim3(CENSUS_THREADS), 0, stream, tab, g, tau,
+                           rec, partials, ctr);
+    } else {
+        hipLaunchKernelGGL(k_census_framed<false>, dim3(kScanBlocks), dim3(CENSUS_THREADS), 0, stream, tab, g, tau,
+                           rec, partials, ctr);
+    }
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, stream, partials, ctr + C_SIGNIFICANT);
+    const uint64_t nrec = cap >> kCensusRecLog2;
+    hipLaunchKernelGGL(k_census_offsets, dim3(grid_for(nrec, 256, 4096)), dim3(256), 0, stream, rec, nrec, partials,
+                       census_blk_shift(g.p_log2));
+    return hipGetLastError();
+}
+
+hipError_t launch_link_census(const Slot* tab, uint64_t cap, Frame frame, const JobView& jv, uint32_t tau,
+                              bool square, const uint32_t* words, uint64_t* s_key, uint32_t* s_count,
+                              uint32_t* parent, uint32_t* nbr, uint32_t* size, uint64_t s_max,
+                              unsigned long long* ctr, hipStream_t stream) {
+    const Geo g = make_geo(cap, false, frame);
+    const uint2* rec = reinterpret_cast<const uint2*>(words);
+    const int grid = (grid_for(s_max, 256, kPersistBlocks) + kXcds - 1) / kXcds * kXcds;
+    const int link_grid = grid_for(cap >> kPartLog2, 1, 8192);
+    if (square)
+        hipLaunchKernelGGL(k_link_census<true>, dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, g, tau, rec,
+                           s_key, s_count, size, parent, nbr, ctr);
+    else
+        hipLaunchKernelGGL(k_link_census<false>, dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, g, tau, rec,
+                           s_key, s_count, size, parent, nbr, ctr);
+    hipLaunchKernelGGL(k_jump, dim3(grid), dim3(256), 0, stream, parent, ctr);
+    hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, stream, nbr, 1u, s_key, parent, ctr);
     // the neighbour lists are dead after the merge pass; their first s words
     // take the final roots
     hipLaunchKernelGGL(k_compress, dim3(grid), dim3(256), 0, stream, jv, parent, nbr, size, ctr);

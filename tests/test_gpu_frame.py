@@ -15,7 +15,9 @@ Section 3.6: chunks in any order give the same clusters):
 * frames clamped at both ends of the tile range;
 * FP32 chunks;
 * framed and unframed (tuning mode 3) binning on the same input;
-* inputs too wide for a frame.
+* inputs too wide for a frame;
+* the census of significant tiles at table sizes below, at and above one
+  partition per census block.
 """
 import numpy as np
 import pytest
@@ -162,3 +164,29 @@ def test_partition_overflow_at_high_load(raster, torch):
     assert res.stats["key_frame"] == 1
     assert res.stats["distinct_tiles"] > 700_000
     assert_same(res, oracle.cluster_chunks(chunks, tau=2, mu=2, precision=0), "high-load final update")
+
+
+@pytest.mark.parametrize("square", [False, True])
+def test_census_table_sizes(raster, torch, square):
+    """Framed tables of 512 partitions and more find their significant tiles
+    by a census counted in blocks of whole partitions (one partition or
+    fewer per block below 2048 partitions, several above).  Tables of 2^21,
+    2^23 and 2^24 slots hold the same points; every result must equal the
+    oracle's (Algorithm 1; with the 2x2 post-step of Section 3.3 too)."""
+    pts = blob_box(7800, 400_000, 0.0, 80.0, n_centres=150, sigma=0.03, noise=0.1)
+    chunks = [pts[:250_000], pts[250_000:]]
+    ref = oracle.cluster_chunks(chunks, tau=4, mu=3, precision=2, window=square)
+    for hint in (1_000_000, 4_000_000, 9_000_000):
+        _say(f"frame: census, tile hint {hint}, square {square}")
+        raster.set_tuning(mode=2)  # binned chunks (the frame is chosen by the first one)
+        try:
+            st = raster.Stream(tau=4, mu=3, precision=2, tile_hint=hint, square=square)
+            for c in chunks:
+                st.feed(dev(c, torch))
+            res = st.finish()
+            st.close()
+        finally:
+            raster.set_tuning(None)
+        assert res.stats["key_frame"] == 1
+        assert res.stats["table_capacity"] >= 1 << 21
+        assert_same(res, ref, f"census, {res.stats['table_capacity']} slots, square {square}")
