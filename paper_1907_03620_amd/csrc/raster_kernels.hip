@@ -277,39 +277,36 @@ __device__ __forceinline__ bool job_point_key(const JobInfo& J, int64_t i, uint6
 
 enum AddResult : int { ADD_FOUND = 0, ADD_NEW = 1, ADD_FULL = 2 };
 
-// Adds `inc` to the count of `key`, inserting the key into an empty slot of
-// its probe window if it is not there yet.  Keys are only ever written once
-// (empty -> key), so a stale read can only show a slot as empty; the
-// compare-and-swap then returns the true occupant.
 // ---- key frame of a two-dimensional table ----------------------------------
 //
 // A key inside the table's frame (a window of 2^20 x 2^20 tiles) is described
 // by h, a bijective mix of its super-tile's 34-bit position in the frame, and
 // its 32-bit entry: the low 26 bits of h and the key's 6-bit position inside
 // the super-tile.  The top 8 bits of h (the coarse bucket) and the entry give
-// the key back.  The mix is multiplications by odd constants and xor-shifts,
-// each invertible modulo 2^34.
+// the key back.  The mix is a multiplication by an odd constant, whose top
+// bits (partition and coarse bucket) depend on every bit of the position,
+// then a xor-shift that brings them down into the entry; both are
+// invertible modulo 2^34.
 constexpr uint64_t kFrameStMask = (1ull << kFrameStBits) - 1;
-constexpr uint64_t kFrameMul1 = 0x2c1b3c6d5ull, kFrameMul1Inv = 0x1eea1427dull;
-constexpr uint64_t kFrameMul2 = 0x297a2d39bull, kFrameMul2Inv = 0x165145a93ull;
+constexpr uint64_t kFrameMul = 0x2c1b3c6d5ull, kFrameMulInv = 0x1eea1427dull;
+static_assert(((kFrameMul * kFrameMulInv) & ((1ull << 34) - 1)) == 1, "inverse modulo 2^34");
 constexpr uint32_t kFrameSide = 1u << kFrameLog2;
 constexpr uint32_t kFrameStSide = kFrameLog2 - 3;  // bits of one super-tile coordinate
 
 __device__ __forceinline__ uint64_t frame_mix(uint64_t v) {
-    v = (v * kFrameMul1) & kFrameStMask;
-    v ^= v >> 17;
-    v = (v * kFrameMul2) & kFrameStMask;
-    v ^= v >> 15;
-    return v;
+    v = (v * kFrameMul) & kFrameStMask;
+    return v ^ (v >> 17);
 }
 
 __device__ __forceinline__ uint64_t frame_unmix(uint64_t h) {
-    h ^= (h >> 15) ^ (h >> 30);
-    h = (h * kFrameMul2Inv) & kFrameStMask;
-    h ^= h >> 17;
-    h = (h * kFrameMul1Inv) & kFrameStMask;
-    return h;
+    h ^= h >> 17;  // its own inverse on 34 bits
+    return (h * kFrameMulInv) & kFrameStMask;
 }
+
+// Home slot of entry e inside its partition (before masking to the partition
+// size): 12 bits of h, with the 64 positions inside the super-tile spread
+// over the partition by a step of 65.
+__device__ __forceinline__ uint32_t frame_home(uint32_t e) { return (e >> 6) ^ ((e & 63u) * 65u); }
 
 // h and entry of a key; false for a key outside the frame.
 __device__ __forceinline__ bool frame_code(uint64_t key, uint32_t fx, uint32_t fy, uint64_t& h, uint32_t& e) {
@@ -336,7 +333,7 @@ __device__ __forceinline__ uint64_t home_slot(uint64_t key, const Geo& g) {
     uint32_t e;
     if (g.framed && frame_code(key, g.fx, g.fy, h, e)) {
         const uint64_t part = g.p_log2 ? (h >> (kFrameStBits - g.p_log2)) : 0;
-        return (part << g.cp_log2) | (mix32(e) & ((1u << g.cp_log2) - 1));
+        return (part << g.cp_log2) | (frame_home(e) & ((1u << g.cp_log2) - 1));
     }
     const uint64_t part = g.p_log2 ? (place_of(key, g.d3) >> (32 - g.p_log2)) : 0;
     return (part << g.cp_log2) | (slot_hash(key) & ((1u << g.cp_log2) - 1));
@@ -348,6 +345,10 @@ __device__ __forceinline__ uint64_t next_slot(uint64_t s, const Geo& g) {
     return (s & ~m) | ((s + 1) & m);
 }
 
+// Adds `inc` to the count of `key`, inserting the key into an empty slot of
+// its probe window if it is not there yet.  Keys are only ever written once
+// (empty -> key), so a stale read can only show a slot as empty; the
+// compare-and-swap then returns the true occupant.
 __device__ __forceinline__ int table_add(Slot* tab, const Geo& g, uint64_t key, uint32_t inc) {
     uint64_t pos = home_slot(key, g);
     for (uint32_t p = 0; p < kMaxProbe; ++p) {
@@ -1283,7 +1284,7 @@ __device__ __forceinline__ void aggregate_entries(const PartEntries<kBinRep>& L,
         uint64_t cur[FAGG_BATCH];
 #pragma unroll
         for (int u = 0; u < FAGG_BATCH; ++u) {
-            pos[u] = mix32(k[u]) & (kPartSlots - 1);
+            pos[u] = frame_home(k[u]) & (kPartSlots - 1);
             cur[u] = q0 + u * AGG_THREADS + threadIdx.x < cnt ? lds_load_relaxed(&A.word[pos[u]]) : 0;
         }
 #pragma unroll
@@ -1420,7 +1421,7 @@ __global__ __launch_bounds__(AGG_THREADS, 8) void k_aggregate_f32(const uint32_t
         bool act = lane < n;
         const uint32_t e = act ? ring[(head + lane) & (AGG_RING - 1)] : 0u;
         head += n;
-        uint32_t ps = mix32(e) & (kPartSlots - 1);
+        uint32_t ps = frame_home(e) & (kPartSlots - 1);
         for (uint32_t step = 0; act && step < kMaxProbe; ++step) {
             uint32_t c = __hip_atomic_load(&A.ent[ps], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (c == kEmpty) {
@@ -1488,7 +1489,7 @@ __global__ __launch_bounds__(AGG_THREADS, 8) void k_aggregate_f32(const uint32_t
         uint32_t hs[FAGG_BATCH], c0[FAGG_BATCH], c1[FAGG_BATCH];
 #pragma unroll
         for (int u = 0; u < FAGG_BATCH; ++u) {
-            hs[u] = mix32(k[u]) & (kPartSlots - 1);
+            hs[u] = frame_home(k[u]) & (kPartSlots - 1);
             c0[u] = __hip_atomic_load(&A.ent[hs[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             c1[u] = __hip_atomic_load(&A.ent[(hs[u] + 1) & (kPartSlots - 1)], __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_WORKGROUP);
