@@ -14,6 +14,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -417,15 +418,16 @@ raster_status TableRun::ensure_sketch() {
 }
 
 // Reads the sketch registers (one copy and wait, unless the caller has
-// fetched them already) and sizes the table from them.  A single-shot call may replace an empty table by one of the
-// estimated size; a stream grows its table only when the estimate shows it
-// too full to work in.
+// fetched them already) and sizes the table from them.  A single-shot call
+// may replace an empty table by one of the estimated size; a stream grows its
+// table only when the estimate shows it too full to work in.
 raster_status TableRun::size_from_sketch(uint64_t points, bool fetched) {
     const size_t regs = (size_t)kHllReps << kHllLog2;
     if (!fetched) {
         HIP_TRY(hipMemcpyAsync(h_sketch, sketch, regs * sizeof(uint32_t), hipMemcpyDeviceToHost, stream),
                 "sketch copy");
-        HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+        raster_status ws = wait_stream();
+        if (ws != RASTER_OK) return ws;
     }
     const uint32_t* h = h_sketch;
     std::vector<uint32_t> M(1u << kHllLog2, 0);
@@ -508,7 +510,8 @@ raster_status TableRun::decide_frame(const void* pts, int64_t n, raster_dtype dt
     HIP_TRY(launch_key_bbox(pts, std::min<int64_t>(n, kFrameSample), (int)dt, scale, d, stream), "frame box");
     uint32_t bb[4] = {1, 0, 1, 0};
     HIP_TRY(hipMemcpyAsync(bb, d, sizeof bb, hipMemcpyDeviceToHost, stream), "frame box copy");
-    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    raster_status ws = wait_stream();
+    if (ws != RASTER_OK) return ws;
     bufs.give_back(d);
     if (bb[0] > bb[1] || bb[2] > bb[3]) return RASTER_OK;
     const int64_t side = (int64_t)1 << kFrameLog2;
@@ -543,40 +546,45 @@ raster_status TableRun::ensure_spill(int b, uint64_t need) {
     return RASTER_OK;
 }
 
+// Waits for everything enqueued on the stream so far.  The host polls an
+// event instead of sleeping in the runtime: the next launches depend on what
+// the wait returns, and a sleeping wait adds its wake-up to the time the
+// device stands idle.
+raster_status TableRun::wait_stream() {
+    HIP_TRY(hipEventRecord(ev_chunk, stream), "hipEventRecord");
+    hipError_t e;
+    while ((e = hipEventQuery(ev_chunk)) == hipErrorNotReady) std::this_thread::yield();
+    if (e != hipSuccess) return hip_fail(e, "hipEventQuery");
+    return RASTER_OK;
+}
+
 raster_status TableRun::pull_counters() {
     HIP_TRY(hipMemcpyAsync(h_ctr, ctr, kCounterWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream),
             "counter copy");
-    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    raster_status ws = wait_stream();
+    if (ws != RASTER_OK) return ws;
     resolve_spans();
     return RASTER_OK;
 }
 
 // ---- per-kernel device timing: events around launches, read after a sync ----
 
-raster_status TableRun::span_begin(int kind, hipEvent_t* a) {
-    (void)kind;
-    if (!ev_free.empty()) {
-        *a = ev_free.back();
-        ev_free.pop_back();
-    } else {
-        HIP_TRY(HostCache::get().take_event(device, true, a), "hipEventCreate");
+// Two events for a timed launch (recorded by the launch itself).
+raster_status TableRun::span_events(KernelSpan* sp) {
+    hipEvent_t* e[2] = {&sp->a, &sp->b};
+    for (hipEvent_t* x : e) {
+        if (!ev_free.empty()) {
+            *x = ev_free.back();
+            ev_free.pop_back();
+        } else {
+            HIP_TRY(HostCache::get().take_event(device, true, x), "hipEventCreate");
+        }
     }
-    HIP_TRY(hipEventRecord(*a, stream), "hipEventRecord");
     return RASTER_OK;
 }
 
-raster_status TableRun::span_end(int kind, hipEvent_t a) {
-    hipEvent_t b;
-    if (!ev_free.empty()) {
-        b = ev_free.back();
-        ev_free.pop_back();
-    } else {
-        HIP_TRY(HostCache::get().take_event(device, true, &b), "hipEventCreate");
-    }
-    HIP_TRY(hipEventRecord(b, stream), "hipEventRecord");
-    spans.push_back(Span{kind, a, b});
-    return RASTER_OK;
-}
+// The span's events now follow an enqueued launch: read after the next wait.
+void TableRun::span_done(int kind, const KernelSpan& sp) { spans.push_back(Span{kind, sp.a, sp.b}); }
 
 void TableRun::resolve_spans() {
     for (const Span& sp : spans) {
@@ -634,8 +642,8 @@ raster_status TableRun::settle() {
     // since the last settle: a copy after every chunk stalls the stream
     HIP_TRY(hipMemcpyAsync(h_ctr, ctr, kCounterWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream),
             "counter copy");
-    HIP_TRY(hipEventRecord(ev_chunk, stream), "hipEventRecord");
-    HIP_TRY(hipEventSynchronize(ev_chunk), "hipEventSynchronize");
+    raster_status ws = wait_stream();
+    if (ws != RASTER_OK) return ws;
     resolve_spans();
     if (h_ctr[C_ERROR] & kErrRange) {
         failed = RASTER_E_RANGE;
@@ -724,25 +732,24 @@ raster_status TableRun::flush() {
             HIP_TRY(bufs.take((void**)&cursor2, cursor2_n * sizeof(uint32_t)), "partition cursors");
         }
         c2 = bin2_slots / lists;
-        hipEvent_t a = nullptr;
-        if ((st = span_begin(1, &a)) != RASTER_OK) return st;
+        KernelSpan t1, t2;
+        if ((st = span_events(&t1)) != RASTER_OK || (st = span_events(&t2)) != RASTER_OK) return st;
         if (frame.on)
             HIP_TRY(launch_bin_keys_framed(reinterpret_cast<uint32_t*>(bin1), cap1, cursor1,
                                            reinterpret_cast<uint32_t*>(bin2), c2, cursor2, tab, cap, frame, sp, ctr,
-                                           stream),
+                                           stream, t1),
                     "bin keys");
         else
-            HIP_TRY(launch_bin_keys(bin1, cap1, cursor1, bin2, c2, cursor2, tab, cap, sp, ctr, stream, dims == 3),
+            HIP_TRY(launch_bin_keys(bin1, cap1, cursor1, bin2, c2, cursor2, tab, cap, sp, ctr, stream, dims == 3, t1),
                     "bin keys");
-        if ((st = span_end(1, a)) != RASTER_OK) return st;
-        if ((st = span_begin(2, &a)) != RASTER_OK) return st;
+        span_done(1, t1);
         if (frame.on)
             HIP_TRY(launch_aggregate_framed(reinterpret_cast<uint32_t*>(bin2), c2, cursor2, cursor1, tab, cap, frame,
-                                            sp, ctr, stream),
+                                            sp, ctr, stream, t2),
                     "aggregate");
         else
-            HIP_TRY(launch_aggregate(bin2, c2, cursor2, cursor1, tab, cap, sp, ctr, stream), "aggregate");
-        if ((st = span_end(2, a)) != RASTER_OK) return st;
+            HIP_TRY(launch_aggregate(bin2, c2, cursor2, cursor1, tab, cap, sp, ctr, stream, t2), "aggregate");
+        span_done(2, t2);
     }
     flushes += 1;
     group_points = 0;
@@ -812,7 +819,12 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
     // A stream sizes the buffer for its whole bin group (which it reaches by
     // the group's end anyway), so that later chunks need no resize and can go
     // in without waiting (can_bin_unsettled).
-    const uint64_t spill_want = group_points + (uint64_t)n + (single_shot ? 0 : bin_points);
+    // (before a stream's first binned chunk the bins are not sized yet: take
+    // the size they will get, so that the next chunk need not wait for this
+    // one to resize the buffer)
+    const uint64_t bins_expected =
+        bin1 ? bin_points : std::min<uint64_t>(group_budget, std::max<uint64_t>(16 * (uint64_t)n, 1u << 20));
+    const uint64_t spill_want = group_points + (uint64_t)n + (single_shot ? 0 : bins_expected);
     st = ensure_spill(0, std::min<uint64_t>(group_budget, spill_want));
     if (st != RASTER_OK) return st;
     bool all_binned = true;
@@ -823,7 +835,7 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
         const bool binned = (tuning.mode >= 2 || (tuning.mode == 0 && (uint64_t)piece >= cap / 8)) &&
                             binned_geometry(g);
         SpillBuf sp{spill_keys[0], spill_counts[0], spill_cap[0]};
-        hipEvent_t a = nullptr;
+        KernelSpan t0;
         if (binned) {
             // the key frame comes from the first binned chunk of an empty
             // table; a table that already holds keys keeps its placement
@@ -842,18 +854,18 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
                 st = ensure_bins(single_shot ? (uint64_t)piece : 16 * (uint64_t)piece);
                 if (st != RASTER_OK) return st;
             }
-            if ((st = span_begin(0, &a)) != RASTER_OK) return st;
+            if ((st = span_events(&t0)) != RASTER_OK) return st;
             // the sketch of the binned keys sizes the table before the flush
             if ((st = ensure_sketch()) != RASTER_OK) return st;
             if (frame.on)
                 HIP_TRY(launch_bin_points_framed(p, piece, (int)dt, scale, reinterpret_cast<uint32_t*>(bin1), cap1,
-                                                 cursor1, tab, cap, frame, sp, ctr, sketch, stream),
+                                                 cursor1, tab, cap, frame, sp, ctr, sketch, stream, t0),
                         "bin points");
             else
                 HIP_TRY(launch_bin_points(p, piece, (int)dt, scale, bin1, cap1, cursor1, tab, cap, sp, ctr, sketch,
-                                          stream, (int)dims),
+                                          stream, (int)dims, t0),
                         "bin points");
-            if ((st = span_end(0, a)) != RASTER_OK) return st;
+            span_done(0, t0);
             group_points += (uint64_t)piece;
         } else {
             all_binned = false;
@@ -864,11 +876,11 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
                 if ((st = size_from_sketch((uint64_t)piece)) != RASTER_OK) return st;
                 sp = SpillBuf{spill_keys[0], spill_counts[0], spill_cap[0]};
             }
-            if ((st = span_begin(0, &a)) != RASTER_OK) return st;
+            if ((st = span_events(&t0)) != RASTER_OK) return st;
             HIP_TRY(launch_project_count(p, piece, (int)dt, scale, tab, cap, sp, ctr, kernel_tuning(tuning), stream,
-                                         (int)dims, frame),
+                                         (int)dims, frame, t0),
                     "project_count");
-            if ((st = span_end(0, a)) != RASTER_OK) return st;
+            span_done(0, t0);
         }
         n_points += piece;
         off += piece;
@@ -880,9 +892,8 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
 }
 
 raster_status TableRun::finish(raster_result** out) {
-    raster_status st = settle();
-    if (st != RASTER_OK) return st;
-    st = flush();
+    // a flush waits for the work before it itself
+    raster_status st = group_points > 0 ? flush() : settle();
     if (st != RASTER_OK) return st;
     if (!timing_started) {
         HIP_TRY(hipEventRecord(ev[0], stream), "hipEventRecord");
@@ -941,7 +952,8 @@ raster_status TableRun::finish(raster_result** out) {
     single.dims.tiles = 0;
     SingleJob* sj_dev = nullptr;
     HIP_TRY(bufs.take((void**)&sj_dev, sizeof(SingleJob)), "job descriptor");
-    HIP_TRY(hipMemcpyAsync(sj_dev, &single, sizeof(SingleJob), hipMemcpyHostToDevice, stream), "job descriptor");
+    // written by a kernel from its arguments: no copy from pageable memory
+    HIP_TRY(launch_store_job(single.dims, single.job, &sj_dev->dims, &sj_dev->job, stream), "job descriptor");
     JobView jv{&sj_dev->dims, &sj_dev->job, nullptr, nullptr, nullptr};
 
     e = launch_zero_u64((uint64_t*)ctr + C_DISTINCT, C_COUNT_ - C_DISTINCT, stream);

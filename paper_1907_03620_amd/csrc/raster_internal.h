@@ -234,9 +234,17 @@ hipError_t launch_zero_u64(uint64_t* p, uint64_t n, hipStream_t stream);
 hipError_t launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t stream);
 
 // Projection + counting of n points into the table (dtype 1 = f32, 2 = f64).
+// Events that a timed launch records around its main kernel (taken from
+// the kernel's own dispatch, so that timing adds no commands between
+// launches); both null: untimed.
+struct KernelSpan {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+
 hipError_t launch_project_count(const void* pts, int64_t n, int dtype, double scale, Slot* tab,
                                  uint64_t cap, SpillBuf spill, unsigned long long* ctr,
-                                 const KernelTuning& tu, hipStream_t stream, int dims = 2, Frame frame = Frame{});
+                                 const KernelTuning& tu, hipStream_t stream, int dims = 2, Frame frame = Frame{},
+                                 const KernelSpan& span = KernelSpan{});
 
 // Tile bounding box of the first n points (two dimensions): out[0..3] =
 // smallest and largest biased x, smallest and largest biased y over the
@@ -251,17 +259,19 @@ hipError_t launch_key_bbox(const void* pts, int64_t n, int dtype, double scale, 
 // outside the frame, and keys past a full list, go straight into the table.
 hipError_t launch_bin_points_framed(const void* pts, int64_t n, int dtype, double scale, uint32_t* bin1,
                                    uint64_t cap1, uint32_t* cursor1, Slot* tab, uint64_t cap, Frame frame,
-                                   SpillBuf spill, unsigned long long* ctr, uint32_t* hll, hipStream_t stream);
+                                   SpillBuf spill, unsigned long long* ctr, uint32_t* hll, hipStream_t stream,
+                                   const KernelSpan& span = KernelSpan{});
 // Level 2: every coarse list into its partitions' lists (bin2, cap2 entries
 // per list; counts in cursor2, cleared here).
 hipError_t launch_bin_keys_framed(const uint32_t* bin1, uint64_t cap1, const uint32_t* cursor1, uint32_t* bin2,
                                  uint64_t cap2, uint32_t* cursor2, Slot* tab, uint64_t cap, Frame frame,
-                                 SpillBuf spill, unsigned long long* ctr, hipStream_t stream);
+                                 SpillBuf spill, unsigned long long* ctr, hipStream_t stream,
+                                 const KernelSpan& span = KernelSpan{});
 // Update: one workgroup per partition adds its entries to the table in LDS;
 // then clears cursor1.
 hipError_t launch_aggregate_framed(const uint32_t* bin2, uint64_t cap2, const uint32_t* cursor2, uint32_t* cursor1,
                                   Slot* tab, uint64_t cap, Frame frame, SpillBuf spill, unsigned long long* ctr,
-                                  hipStream_t stream);
+                                  hipStream_t stream, const KernelSpan& span = KernelSpan{});
 // Direct insertion of every entry held in the coarse lists (tables outside
 // the framed binned geometry).  Clears cursor1.
 hipError_t launch_drain_bins_framed(const uint32_t* bin1, uint64_t cap1, uint32_t* cursor1, Slot* tab, uint64_t cap,
@@ -274,16 +284,18 @@ hipError_t launch_drain_bins_framed(const uint32_t* bin1, uint64_t cap1, uint32_
 // replicas of 2^kHllLog2 registers; merge them by maximum).
 hipError_t launch_bin_points(const void* pts, int64_t n, int dtype, double scale, uint64_t* bin1, uint64_t cap1,
                              uint32_t* cursor1, Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr,
-                             uint32_t* hll, hipStream_t stream, int dims = 2);
+                             uint32_t* hll, hipStream_t stream, int dims = 2, const KernelSpan& span = KernelSpan{});
 // Binned contraction, level 2: split every coarse bucket into its partitions
 // (bin2, cap2 keys per partition, counts in cursor2, which this clears first).
 hipError_t launch_bin_keys(const uint64_t* bin1, uint64_t cap1, const uint32_t* cursor1, uint64_t* bin2,
                            uint64_t cap2, uint32_t* cursor2, Slot* tab, uint64_t cap, SpillBuf spill,
-                           unsigned long long* ctr, hipStream_t stream, bool d3 = false);
+                           unsigned long long* ctr, hipStream_t stream, bool d3 = false,
+                           const KernelSpan& span = KernelSpan{});
 // Binned contraction, update: one workgroup per partition adds that
 // partition's keys to the table in LDS; then clears cursor1 for the next group.
 hipError_t launch_aggregate(const uint64_t* bin2, uint64_t cap2, const uint32_t* cursor2, uint32_t* cursor1,
-                            Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream);
+                            Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream,
+                            const KernelSpan& span = KernelSpan{});
 // Direct insertion of everything held in the coarse buckets (used when the
 // table is outside the binned geometry).  Clears cursor1.
 hipError_t launch_drain_bins(uint64_t* bin1, uint64_t cap1, uint32_t* cursor1, Slot* tab, uint64_t cap,

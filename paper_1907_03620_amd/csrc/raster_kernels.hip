@@ -13,6 +13,8 @@
 // Wavefront size is 64.  Counters that many lanes bump are aggregated per
 // wave with a ballot before the single global atomic.
 
+#include <hip/hip_ext.h>
+
 #include "raster_internal.h"
 
 namespace rst {
@@ -3300,9 +3302,21 @@ int grid_for(uint64_t work, int block, int max_blocks) {
 // CUs several times over.
 constexpr int kPersistBlocks = 256 * 8;
 
+// A launch timed by the events of `span` (recorded from the kernel's own
+// dispatch) or untimed.
+template <typename F, typename... Args>
+void launch_k(F kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t stream, const KernelSpan& span,
+              Args... args) {
+    if (span.a)
+        hipExtLaunchKernelGGL(kernel, grid, block, lds, stream, span.a, span.b, 0u, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, lds, stream, args...);
+}
+
 template <typename T, int ITEMS>
 hipError_t launch_count_t(const T* pts, int64_t n, double scale, Slot* tab, const Geo g, SpillBuf sp,
-                          unsigned long long* ctr, const KernelTuning& tu, hipStream_t stream) {
+                          unsigned long long* ctr, const KernelTuning& tu, hipStream_t stream,
+                          const KernelSpan& span) {
     const int block = tu.block;
     if (tu.preagg_slots > 0) {
         int lds_log2 = 0;
@@ -3311,26 +3325,27 @@ hipError_t launch_count_t(const T* pts, int64_t n, double scale, Slot* tab, cons
         const int64_t per_block = (int64_t)block * ITEMS * sweeps;
         const int64_t grid = (n + per_block - 1) / per_block;
         const size_t lds = (size_t)(1u << lds_log2) * (sizeof(uint64_t) + sizeof(uint32_t));
-        hipLaunchKernelGGL((k_count_preagg<T, ITEMS>), dim3((unsigned)grid), dim3(block), lds, stream, pts, n,
-                           scale, tab, g, sp, ctr, lds_log2, sweeps);
+        launch_k(k_count_preagg<T, ITEMS>, dim3((unsigned)grid), dim3(block), (uint32_t)lds, stream, span, pts, n,
+                 scale, tab, g, sp, ctr, lds_log2, sweeps);
     } else {
         const int64_t per_block = (int64_t)block * ITEMS;
         const int64_t grid = (n + per_block - 1) / per_block;
-        hipLaunchKernelGGL((k_count_direct<T, ITEMS>), dim3((unsigned)grid), dim3(block), 0, stream, pts, n, scale,
-                           tab, g, sp, ctr);
+        launch_k(k_count_direct<T, ITEMS>, dim3((unsigned)grid), dim3(block), 0u, stream, span, pts, n, scale, tab, g,
+                 sp, ctr);
     }
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_count_items(const T* pts, int64_t n, double scale, Slot* tab, const Geo g, SpillBuf sp,
-                              unsigned long long* ctr, const KernelTuning& tu, hipStream_t stream) {
+                              unsigned long long* ctr, const KernelTuning& tu, hipStream_t stream,
+                              const KernelSpan& span) {
     switch (tu.items) {
-        case 1: return launch_count_t<T, 1>(pts, n, scale, tab, g, sp, ctr, tu, stream);
-        case 2: return launch_count_t<T, 2>(pts, n, scale, tab, g, sp, ctr, tu, stream);
-        case 4: return launch_count_t<T, 4>(pts, n, scale, tab, g, sp, ctr, tu, stream);
-        case 8: return launch_count_t<T, 8>(pts, n, scale, tab, g, sp, ctr, tu, stream);
-        default: return launch_count_t<T, 16>(pts, n, scale, tab, g, sp, ctr, tu, stream);
+        case 1: return launch_count_t<T, 1>(pts, n, scale, tab, g, sp, ctr, tu, stream, span);
+        case 2: return launch_count_t<T, 2>(pts, n, scale, tab, g, sp, ctr, tu, stream, span);
+        case 4: return launch_count_t<T, 4>(pts, n, scale, tab, g, sp, ctr, tu, stream, span);
+        case 8: return launch_count_t<T, 8>(pts, n, scale, tab, g, sp, ctr, tu, stream, span);
+        default: return launch_count_t<T, 16>(pts, n, scale, tab, g, sp, ctr, tu, stream, span);
     }
 }
 
@@ -3355,28 +3370,30 @@ hipError_t launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t stream) {
 
 hipError_t launch_project_count(const void* pts, int64_t n, int dtype, double scale, Slot* tab, uint64_t cap,
                                  SpillBuf spill, unsigned long long* ctr, const KernelTuning& tu,
-                                 hipStream_t stream, int dims, Frame frame) {
+                                 hipStream_t stream, int dims, Frame frame, const KernelSpan& span) {
     if (n <= 0) return hipSuccess;
     const Geo g = make_geo(cap, dims == 3, frame);
     if (dims == 3) {
         if (dtype == 1)
-            return launch_count_items(static_cast<const Pt3<float>*>(pts), n, scale, tab, g, spill, ctr, tu, stream);
-        return launch_count_items(static_cast<const Pt3<double>*>(pts), n, scale, tab, g, spill, ctr, tu, stream);
+            return launch_count_items(static_cast<const Pt3<float>*>(pts), n, scale, tab, g, spill, ctr, tu, stream,
+                                      span);
+        return launch_count_items(static_cast<const Pt3<double>*>(pts), n, scale, tab, g, spill, ctr, tu, stream,
+                                  span);
     }
     if (dtype == 1)
-        return launch_count_items(static_cast<const float*>(pts), n, scale, tab, g, spill, ctr, tu, stream);
-    return launch_count_items(static_cast<const double*>(pts), n, scale, tab, g, spill, ctr, tu, stream);
+        return launch_count_items(static_cast<const float*>(pts), n, scale, tab, g, spill, ctr, tu, stream, span);
+    return launch_count_items(static_cast<const double*>(pts), n, scale, tab, g, spill, ctr, tu, stream, span);
 }
 
 hipError_t launch_bin_points(const void* pts, int64_t n, int dtype, double scale, uint64_t* bin1, uint64_t cap1,
                              uint32_t* cursor1, Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr,
-                             uint32_t* hll, hipStream_t stream, int dims) {
+                             uint32_t* hll, hipStream_t stream, int dims, const KernelSpan& span) {
     if (n <= 0) return hipSuccess;
     const Geo g = make_geo(cap, dims == 3);
     const unsigned grid = (unsigned)((n + kBinTile - 1) / kBinTile);
     auto go = [&](auto kernel, const auto* p) {
-        hipLaunchKernelGGL(kernel, dim3(grid), dim3(BIN_THREADS), 0, stream, p, n, scale, bin1, cap1, cursor1, tab, g,
-                           spill, ctr, hll);
+        launch_k(kernel, dim3(grid), dim3(BIN_THREADS), 0u, stream, span, p, n, scale, bin1, cap1, cursor1, tab, g,
+                 spill, ctr, hll);
     };
     if (dims == 3) {
         const Pt3<float>* pf = static_cast<const Pt3<float>*>(pts);
@@ -3404,7 +3421,7 @@ hipError_t launch_bin_points(const void* pts, int64_t n, int dtype, double scale
 
 hipError_t launch_bin_keys(const uint64_t* bin1, uint64_t cap1, const uint32_t* cursor1, uint64_t* bin2,
                            uint64_t cap2, uint32_t* cursor2, Slot* tab, uint64_t cap, SpillBuf spill,
-                           unsigned long long* ctr, hipStream_t stream, bool d3) {
+                           unsigned long long* ctr, hipStream_t stream, bool d3, const KernelSpan& span) {
     const Geo g = make_geo(cap, d3);
     if (!binned_geometry(g)) return hipErrorInvalidValue;
     const uint64_t lists2 = (uint64_t)kBinRep << g.p_log2;
@@ -3412,22 +3429,23 @@ hipError_t launch_bin_keys(const uint64_t* bin1, uint64_t cap1, const uint32_t* 
     const uint32_t segs = (uint32_t)((cap1 + kBinTile - 1) / kBinTile);
     const dim3 grid(kBinRep * kCoarse * segs);
     if (d3)
-        hipLaunchKernelGGL(k_bin_keys<true>, grid, dim3(BIN_THREADS), 0, stream, bin1, cap1, cursor1, segs, bin2, cap2,
-                           cursor2, tab, g, spill, ctr);
+        launch_k(k_bin_keys<true>, grid, dim3(BIN_THREADS), 0u, stream, span, bin1, cap1, cursor1, segs, bin2, cap2,
+                 cursor2, tab, g, spill, ctr);
     else
-        hipLaunchKernelGGL(k_bin_keys<false>, grid, dim3(BIN_THREADS), 0, stream, bin1, cap1, cursor1, segs, bin2, cap2,
-                           cursor2, tab, g, spill, ctr);
+        launch_k(k_bin_keys<false>, grid, dim3(BIN_THREADS), 0u, stream, span, bin1, cap1, cursor1, segs, bin2, cap2,
+                 cursor2, tab, g, spill, ctr);
     return hipGetLastError();
 }
 
 hipError_t launch_aggregate(const uint64_t* bin2, uint64_t cap2, const uint32_t* cursor2, uint32_t* cursor1,
-                            Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream) {
+                            Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream,
+                            const KernelSpan& span) {
     const Geo g = make_geo(cap);  // the update only needs the partition count
     if (!binned_geometry(g)) return hipErrorInvalidValue;
     const uint64_t parts = 1ull << g.p_log2;
     hipLaunchKernelGGL(k_snapshot_keys, dim3(1), dim3(64), 0, stream, ctr);
-    hipLaunchKernelGGL(k_aggregate, dim3((unsigned)parts), dim3(AGG_THREADS), 0, stream, bin2, cap2, cursor2, tab,
-                       spill, ctr);
+    launch_k(k_aggregate, dim3((unsigned)parts), dim3(AGG_THREADS), 0u, stream, span, bin2, cap2, cursor2, tab, spill,
+             ctr);
     hipLaunchKernelGGL(k_zero_u32, dim3(4), dim3(256), 0, stream, cursor1, (uint64_t)kBinRep * kCoarse);
     return hipGetLastError();
 }
@@ -3470,15 +3488,16 @@ hipError_t launch_key_bbox(const void* pts, int64_t n, int dtype, double scale, 
 
 hipError_t launch_bin_points_framed(const void* pts, int64_t n, int dtype, double scale, uint32_t* bin1,
                                    uint64_t cap1, uint32_t* cursor1, Slot* tab, uint64_t cap, Frame frame,
-                                   SpillBuf spill, unsigned long long* ctr, uint32_t* hll, hipStream_t stream) {
+                                   SpillBuf spill, unsigned long long* ctr, uint32_t* hll, hipStream_t stream,
+                                   const KernelSpan& span) {
     if (n <= 0) return hipSuccess;
     const Geo g = make_geo(cap, false, frame);
     if (!g.framed) return hipErrorInvalidValue;
     const uint32_t tile = BIN_THREADS * kFBinItems1;
     const dim3 grid((unsigned)((n + tile - 1) / tile));
     auto go = [&](auto kernel, const auto* p) {
-        hipLaunchKernelGGL(kernel, grid, dim3(BIN_THREADS), 0, stream, p, n, scale, bin1, cap1, cursor1, tab, g, spill,
-                           ctr, hll);
+        launch_k(kernel, grid, dim3(BIN_THREADS), 0u, stream, span, p, n, scale, bin1, cap1, cursor1, tab, g, spill,
+                 ctr, hll);
     };
     const float* pf = static_cast<const float*>(pts);
     const double* pd = static_cast<const double*>(pts);
@@ -3494,31 +3513,32 @@ hipError_t launch_bin_points_framed(const void* pts, int64_t n, int dtype, doubl
 
 hipError_t launch_bin_keys_framed(const uint32_t* bin1, uint64_t cap1, const uint32_t* cursor1, uint32_t* bin2,
                                  uint64_t cap2, uint32_t* cursor2, Slot* tab, uint64_t cap, Frame frame,
-                                 SpillBuf spill, unsigned long long* ctr, hipStream_t stream) {
+                                 SpillBuf spill, unsigned long long* ctr, hipStream_t stream,
+                                 const KernelSpan& span) {
     const Geo g = make_geo(cap, false, frame);
     if (!framed_binned_geometry(g)) return hipErrorInvalidValue;
     const uint64_t lists2 = (uint64_t)kBinRep << g.p_log2;
     hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(lists2, 256, 4096)), dim3(256), 0, stream, cursor2, lists2);
     const uint32_t segs = (uint32_t)((cap1 + kFBinTile - 1) / kFBinTile);
     const dim3 grid(kBinRep * kFrameCoarse * segs);
-    hipLaunchKernelGGL(k_bin_keys_f, grid, dim3(BIN_THREADS), 0, stream, bin1, cap1, cursor1, segs, bin2, cap2,
-                       cursor2, tab, g, spill, ctr);
+    launch_k(k_bin_keys_f, grid, dim3(BIN_THREADS), 0u, stream, span, bin1, cap1, cursor1, segs, bin2, cap2, cursor2,
+             tab, g, spill, ctr);
     return hipGetLastError();
 }
 
 hipError_t launch_aggregate_framed(const uint32_t* bin2, uint64_t cap2, const uint32_t* cursor2, uint32_t* cursor1,
                                   Slot* tab, uint64_t cap, Frame frame, SpillBuf spill, unsigned long long* ctr,
-                                  hipStream_t stream) {
+                                  hipStream_t stream, const KernelSpan& span) {
     const Geo g = make_geo(cap, false, frame);
     if (!framed_binned_geometry(g)) return hipErrorInvalidValue;
     const uint64_t parts = 1ull << g.p_log2;
     hipLaunchKernelGGL(k_snapshot_keys, dim3(1), dim3(64), 0, stream, ctr);
     if (g.p_log2 > kFrameCoarseLog2)
-        hipLaunchKernelGGL(k_aggregate_f32, dim3((unsigned)parts), dim3(AGG_THREADS), 0, stream, bin2, cap2, cursor2,
-                           tab, g, spill, ctr);
+        launch_k(k_aggregate_f32, dim3((unsigned)parts), dim3(AGG_THREADS), 0u, stream, span, bin2, cap2, cursor2, tab,
+                 g, spill, ctr);
     else
-        hipLaunchKernelGGL(k_aggregate_f, dim3((unsigned)parts), dim3(AGG_THREADS), 0, stream, bin2, cap2, cursor2,
-                           tab, g, spill, ctr);
+        launch_k(k_aggregate_f, dim3((unsigned)parts), dim3(AGG_THREADS), 0u, stream, span, bin2, cap2, cursor2, tab, g,
+                 spill, ctr);
     hipLaunchKernelGGL(k_zero_u32, dim3(8), dim3(256), 0, stream, cursor1, (uint64_t)kBinRep * kFrameCoarse);
     return hipGetLastError();
 }

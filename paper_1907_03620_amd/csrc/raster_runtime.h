@@ -184,8 +184,9 @@ struct TableRun {
     raster_status flush();
     raster_status ensure_bins(uint64_t want_points);
     raster_status mark_pending();
-    raster_status span_begin(int kind, hipEvent_t* a);
-    raster_status span_end(int kind, hipEvent_t a);
+    raster_status wait_stream();
+    raster_status span_events(KernelSpan* sp);
+    void span_done(int kind, const KernelSpan& sp);
     void resolve_spans();
 };
 
