@@ -92,7 +92,9 @@ def kernel_group(name: str):
     for g in ("k_bin_points", "k_bin_keys", "k_aggregate", "k_threshold", "k_link_part", "k_filter"):
         if name.startswith(g):
             return g
-    if name.startswith("k_link_framed"):
+    if name.startswith("k_census_framed"):  # the significance scan of framed tables
+        return "k_threshold"
+    if name.startswith("k_link_census"):
         return "k_link_part"
     if name.startswith(("k_jump", "k_merge", "k_compress")):
         return "union-find"
