@@ -696,7 +696,25 @@ raster_status TableRun::ensure_bins(uint64_t want_points) {
 }
 
 // Applies the keys waiting in the coarse buckets to the table.
-raster_status TableRun::flush() {
+// Census buffers for a table of `c` slots (kept across calls when large enough).
+raster_status TableRun::ensure_census(uint64_t c) {
+    if (c_words && c_words_cap >= c) return RASTER_OK;
+    if (c_words) bufs.give_back(c_words);
+    if (c_ptot) bufs.give_back(c_ptot);
+    c_words = nullptr;
+    c_ptot = nullptr;
+    c_words_cap = 0;
+    HIP_TRY(bufs.take((void**)&c_words, census_words(c) * sizeof(uint32_t)), "census");
+    HIP_TRY(bufs.take((void**)&c_ptot, (c >> kPartLog2) * sizeof(uint32_t)), "census totals");
+    c_words_cap = c;
+    return RASTER_OK;
+}
+
+// Updates the table with the binned group.  With `census`, a final update
+// of a table of 512+ partitions also takes the census of the significant
+// slots (valid while the table keeps its size: census_cap).
+raster_status TableRun::flush(bool census) {
+    census_cap = 0;
     if (group_points == 0) return RASTER_OK;
     // the sketch registers come back with the counters, in one wait
     if (sketch) {
@@ -743,9 +761,17 @@ raster_status TableRun::flush() {
             HIP_TRY(launch_bin_keys(bin1, cap1, cursor1, bin2, c2, cursor2, tab, cap, sp, ctr, stream, dims == 3, t1),
                     "bin keys");
         span_done(1, t1);
+        AggCensus cen;
+        if (census && frame.on && census_geometry(cap, frame)) {
+            if ((st = ensure_census(cap)) != RASTER_OK) return st;
+            cen.rec = reinterpret_cast<uint2*>(c_words);
+            cen.ptotal = c_ptot;
+            cen.tau = tau;
+            census_cap = cap;
+        }
         if (frame.on)
             HIP_TRY(launch_aggregate_framed(reinterpret_cast<uint32_t*>(bin2), c2, cursor2, cursor1, tab, cap, frame,
-                                            sp, ctr, stream, t2),
+                                            sp, ctr, stream, t2, cen),
                     "aggregate");
         else
             HIP_TRY(launch_aggregate(bin2, c2, cursor2, cursor1, tab, cap, sp, ctr, stream, t2), "aggregate");
@@ -892,9 +918,15 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
 }
 
 raster_status TableRun::finish(raster_result** out) {
-    // a flush waits for the work before it itself
-    raster_status st = group_points > 0 ? flush() : settle();
+    const std::vector<NbrRound> rounds = neighbourhood_rounds(metric, delta, dims);
+    const bool census_path = dims == 2 && rounds.empty();
+    // a flush waits for the work before it itself; the final update takes
+    // the census with it unless the 2x2 post-step changes significance after
+    raster_status st = group_points > 0 ? flush(census_path && !square) : settle();
     if (st != RASTER_OK) return st;
+    // a growth after the update (spilled entries) leaves its census stale
+    const bool census = census_path && census_geometry(cap, frame);
+    const bool fused = census && census_cap == cap;
     if (!timing_started) {
         HIP_TRY(hipEventRecord(ev[0], stream), "hipEventRecord");
         timing_started = true;
@@ -908,13 +940,10 @@ raster_status TableRun::finish(raster_result** out) {
     HIP_TRY(bufs.take((void**)&parent, m * sizeof(uint32_t)), "parent");
     HIP_TRY(bufs.take((void**)&size, m * sizeof(uint32_t)), "sizes");
     uint32_t* nbr = nullptr;
-    const std::vector<NbrRound> rounds = neighbourhood_rounds(metric, delta, dims);
     HIP_TRY(bufs.take((void**)&nbr, m * nbr_words((int)rounds.size()) * sizeof(uint32_t)), "neighbour lists");
     // framed tables of 512+ partitions: significant slots found by a census
     // instead of an index written into every significant slot
-    const bool census = dims == 2 && rounds.empty() && census_geometry(cap, frame);
-    uint32_t* c_words = nullptr;
-    if (census) HIP_TRY(bufs.take((void**)&c_words, census_words(cap) * sizeof(uint32_t)), "census");
+    if (census && (st = ensure_census(cap)) != RASTER_OK) return st;
 
     raster_result* r = new raster_result();
     r->pool = bufs.pool;
@@ -956,10 +985,15 @@ raster_status TableRun::finish(raster_result** out) {
     HIP_TRY(launch_store_job(single.dims, single.job, &sj_dev->dims, &sj_dev->job, stream), "job descriptor");
     JobView jv{&sj_dev->dims, &sj_dev->job, nullptr, nullptr, nullptr};
 
-    e = launch_zero_u64((uint64_t*)ctr + C_DISTINCT, C_COUNT_ - C_DISTINCT, stream);
+    // (the fused census has counted the occupied slots and their sum already)
+    e = fused ? launch_zero_u64((uint64_t*)ctr + C_SIGNIFICANT, 1, stream)
+              : launch_zero_u64((uint64_t*)ctr + C_DISTINCT, C_COUNT_ - C_DISTINCT, stream);
+    if (e == hipSuccess && fused)
+        e = launch_zero_u64((uint64_t*)ctr + C_COMPONENTS, C_COUNT_ - C_COMPONENTS, stream);
     if (e == hipSuccess)
-        e = census ? launch_census(tab, cap, frame, jv, tau, square, c_words, partials, ctr, stream)
-                   : launch_threshold(tab, jv, s_key, s_count, size, partials, ctr, stream, square ? cap : 0);
+        e = fused    ? launch_census_offsets(cap, c_words, c_ptot, ctr, stream)
+            : census ? launch_census(tab, cap, frame, jv, tau, square, c_words, partials, ctr, stream)
+                     : launch_threshold(tab, jv, s_key, s_count, size, partials, ctr, stream, square ? cap : 0);
     if (e == hipSuccess) e = hipEventRecord(ev[2], stream);
     if (e == hipSuccess)
         e = census ? launch_link_census(tab, cap, frame, jv, tau, square, c_words, s_key, s_count, parent, nbr,
@@ -1011,7 +1045,6 @@ raster_status TableRun::finish(raster_result** out) {
     bufs.give_back(size);
     bufs.give_back(nbr);
     bufs.give_back(sj_dev);
-    if (c_words) bufs.give_back(c_words);
     *out = r;
     return RASTER_OK;
 }

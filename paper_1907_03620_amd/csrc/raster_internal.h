@@ -267,11 +267,26 @@ hipError_t launch_bin_keys_framed(const uint32_t* bin1, uint64_t cap1, const uin
                                  uint64_t cap2, uint32_t* cursor2, Slot* tab, uint64_t cap, Frame frame,
                                  SpillBuf spill, unsigned long long* ctr, hipStream_t stream,
                                  const KernelSpan& span = KernelSpan{});
+// Census of the final update (rec null: none): with the table's final
+// slices in LDS, the update of a table of 512+ partitions also writes the
+// census records of every partition (counts before each 32 slots within the
+// partition; rec: 2 words per 32 slots), each partition's significant count
+// (ptotal), and the occupied slots and count sum (ctr[C_DISTINCT],
+// ctr[C_SUM], cleared first).  launch_census_offsets then makes the counts
+// global, as launch_census leaves them.
+struct AggCensus {
+    uint2* rec = nullptr;
+    uint32_t* ptotal = nullptr;
+    uint32_t tau = 0;
+};
 // Update: one workgroup per partition adds its entries to the table in LDS;
 // then clears cursor1.
 hipError_t launch_aggregate_framed(const uint32_t* bin2, uint64_t cap2, const uint32_t* cursor2, uint32_t* cursor1,
                                   Slot* tab, uint64_t cap, Frame frame, SpillBuf spill, unsigned long long* ctr,
-                                  hipStream_t stream, const KernelSpan& span = KernelSpan{});
+                                  hipStream_t stream, const KernelSpan& span = KernelSpan{},
+                                  const AggCensus& census = AggCensus{});
+hipError_t launch_census_offsets(uint64_t cap, uint32_t* words, uint32_t* ptotal, unsigned long long* ctr,
+                                 hipStream_t stream);
 // Direct insertion of every entry held in the coarse lists (tables outside
 // the framed binned geometry).  Clears cursor1.
 hipError_t launch_drain_bins_framed(const uint32_t* bin1, uint64_t cap1, uint32_t* cursor1, Slot* tab, uint64_t cap,

@@ -136,6 +136,20 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
 // counter word hit once per wave would serialise hundreds of thousands of
 // same-address atomics).  Every thread of the workgroup must call it, once,
 // at a point all of them reach.
+__device__ __forceinline__ void block_count_add64(unsigned long long* ctr, unsigned long long v) {
+    __shared__ unsigned long long part64[16];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane_id() == 0) part64[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int i = 0; i < (int)((blockDim.x + 63) >> 6); ++i) t += part64[i];
+        if (t) atomicAdd(ctr, t);
+    }
+}
+
 __device__ __forceinline__ void block_count_add(unsigned long long* ctr, uint32_t v) {
     __shared__ uint32_t part[16];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -1365,6 +1379,7 @@ __global__ __launch_bounds__(AGG_THREADS, 6) void k_aggregate_f(const uint32_t* 
 // of each of its entries.  The slice and the rings take 36 KB of LDS, which
 // lets four workgroups share a CU.
 constexpr uint32_t AGG_RING = 128;  // deferred entries per wave (at most 127 wait)
+static_assert(AGG_RING * (AGG_THREADS / 64) * 4 >= 64 * 8, "the rings hold the census bits afterwards");
 struct FAggLds32 {
     uint32_t ent[kPartSlots];
     uint32_t cnt[kPartSlots];
@@ -1373,12 +1388,13 @@ struct FAggLds32 {
 
 __global__ __launch_bounds__(AGG_THREADS, 8) void k_aggregate_f32(const uint32_t* __restrict__ bin2, uint64_t cap2,
                                                                   const uint32_t* cursor2, Slot* tab, const Geo g,
-                                                                  SpillBuf sp, unsigned long long* ctr) {
+                                                                  SpillBuf sp, unsigned long long* ctr,
+                                                                  AggCensus cen) {
     __shared__ FAggLds32 A;
     const uint64_t p = blockIdx.x;
     const uint64_t parts = gridDim.x;
     const PartEntries<kBinRep> L(bin2 + p * kBinRep * cap2, cap2, cursor2 + p, parts, cap2);
-    if (L.total == 0) return;  // uniform across the workgroup
+    if (L.total == 0 && !cen.rec) return;  // uniform across the workgroup
     const bool load = ctr[C_TABLE_KEYS] != 0;
     Slot* part = tab + (p << kPartLog2);
     const uint32_t fine = g.p_log2 - kFrameCoarseLog2;  // >= 1 here
@@ -1515,19 +1531,48 @@ __global__ __launch_bounds__(AGG_THREADS, 8) void k_aggregate_f32(const uint32_t
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     while (tail != head) drain();
     __syncthreads();
+    // the rings are free now: their first 512 bytes take the census bits
+    uint64_t* wbits = reinterpret_cast<uint64_t*>(&A.ring[0][0]);
+    uint32_t occ = 0;
+    unsigned long long sum = 0;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const uint32_t sl = u * AGG_THREADS + threadIdx.x;
-        const uint32_t e = A.ent[sl];
-        if (e != kEmpty && e != kAlien) {
+        const uint32_t e = A.ent[sl], c = A.cnt[sl];
+        if (L.total && e != kEmpty && e != kAlien) {
             Slot v;
             v.key = frame_key(cb, e, g.fx, g.fy);
-            v.count = A.cnt[sl];
+            v.count = c;
             v.aux = kNotSignificant;
             part[sl] = v;
         }
+        if (cen.rec) {
+            // the wave's 64 slots u * AGG_THREADS + 64 w + lane form word 8 u + w
+            occ += e != kEmpty;
+            sum += e != kEmpty ? c : 0u;
+            const uint64_t b = __ballot(e != kEmpty && c >= cen.tau);
+            if (lane_id() == 0) wbits[u * (AGG_THREADS / 64) + (threadIdx.x >> 6)] = b;
+        }
     }
     add_fresh(ctr, fresh);
+    if (cen.rec) {
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const uint64_t b = wbits[threadIdx.x];
+            const uint32_t lo = (uint32_t)__popc((uint32_t)b), c = (uint32_t)__popcll(b);
+            uint32_t inc = c;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t t = __shfl_up(inc, o);
+                if (lane_id() >= (uint32_t)o) inc += t;
+            }
+            uint2* r = cen.rec + (p << 7) + 2 * threadIdx.x;
+            r[0] = make_uint2((uint32_t)b, inc - c);
+            r[1] = make_uint2((uint32_t)(b >> 32), inc - c + lo);
+            if (threadIdx.x == 63) cen.ptotal[p] = inc;
+        }
+        block_count_add(&ctr[C_DISTINCT], occ);
+        block_count_add64(&ctr[C_SUM], sum);
+    }
 }
 
 // Fallback: every entry held in the coarse lists goes straight to the table.
@@ -2527,6 +2572,40 @@ __global__ __launch_bounds__(CENSUS_THREADS) void k_census_framed(const Slot* ta
     }
 }
 
+// Exclusive scan of n words in place by one workgroup of 1024 threads (each
+// takes a run of ceil(n / 1024)); the total goes to *total_out.
+__global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* v, uint32_t n, unsigned long long* total_out) {
+    __shared__ uint32_t wsum[16];
+    const uint32_t per = (n + 1023) / 1024;
+    const uint32_t lo = min(threadIdx.x * per, n), hi = min(lo + per, n);
+    uint32_t local = 0;
+    for (uint32_t i = lo; i < hi; ++i) local += v[i];
+    uint32_t inc = local;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(inc, off);
+        if (lane_id() >= (uint32_t)off) inc += o;
+    }
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 63) wsum[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int i = 0; i < 16; ++i) {
+            const uint32_t c = wsum[i];
+            wsum[i] = run;
+            run += c;
+        }
+        *total_out = run;
+    }
+    __syncthreads();
+    uint32_t ex = wsum[w] + inc - local;
+    for (uint32_t i = lo; i < hi; ++i) {
+        const uint32_t c = v[i];
+        v[i] = ex;
+        ex += c;
+    }
+}
+
 // Adds each census block's offset (boff after the scan) to its records.
 __global__ void k_census_offsets(uint2* rec, uint64_t nrec, const uint32_t* boff, uint32_t blk_shift) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nrec;
@@ -2624,36 +2703,24 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_census(const Slot* tab, c
             want[2] = left && up;
             nk[3] = ((uint64_t)bx << 32) | (uint32_t)(by - 1);
             want[3] = down;
-            // device-table loads for the other partitions issued together
-            // (home slot, the next one and the census record of the home
-            // slot); LDS probes need no wait
-            uint64_t pos[4];
-            uint32_t e[4];
-            bool local[4];
-            Slot v[4], nx[4];
-            uint2 cr[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                uint64_t h;
-                local[q] = frame_code(nk[q], g.fx, g.fy, h, e[q]) && (h >> (kFrameStBits - g.p_log2)) == p;
-                pos[q] = home_slot(nk[q], g);
-                if (want[q] && !local[q]) {
-                    v[q] = tab[pos[q]];
-                    nx[q] = tab[next_slot(pos[q], g)];
-                    cr[q] = rec[pos[q] >> kCensusRecLog2];
-                }
-            }
+            // local neighbours through the slice in LDS, the others through
+            // the table and one census record, one at a time (few live
+            // registers, so that many waves hide the table's latency)
             uint32_t j[4];
             uint32_t best = i;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 j[q] = kNoNeighbour;
                 if (!want[q]) continue;
-                if (local[q]) {
-                    uint32_t lp = (uint32_t)(pos[q] - base);
+                uint64_t h;
+                uint32_t e;
+                const bool local = frame_code(nk[q], g.fx, g.fy, h, e) && (h >> (kFrameStBits - g.p_log2)) == p;
+                uint64_t pos = home_slot(nk[q], g);
+                if (local) {
+                    uint32_t lp = (uint32_t)(pos - base);
                     for (uint32_t step = 0; step < kMaxProbe; ++step) {
                         const uint32_t cur = lent[lp];
-                        if (cur == e[q]) {
+                        if (cur == e) {
                             const uint16_t r = lrank[lp];
                             if (r != kNoRank) j[q] = poff + r;
                             break;
@@ -2662,21 +2729,24 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_census(const Slot* tab, c
                         lp = (lp + 1) & (kPartSlots - 1);
                     }
                 } else {
-                    const uint64_t home = pos[q];
-                    if (v[q].key != nk[q] && v[q].key != kEmptyKey) {
-                        // second probe already loaded
-                        pos[q] = next_slot(pos[q], g);
-                        v[q] = nx[q];
+                    // home slot, the next one and the home slot's census record together
+                    Slot v = tab[pos];
+                    const Slot nx = tab[next_slot(pos, g)];
+                    uint2 cr = rec[pos >> kCensusRecLog2];
+                    const uint64_t home = pos;
+                    if (v.key != nk[q] && v.key != kEmptyKey) {
+                        pos = next_slot(pos, g);
+                        v = nx;
                         uint32_t steps = 2;
-                        while (v[q].key != nk[q] && v[q].key != kEmptyKey && steps < kMaxProbe) {
-                            pos[q] = next_slot(pos[q], g);
-                            v[q] = tab[pos[q]];
+                        while (v.key != nk[q] && v.key != kEmptyKey && steps < kMaxProbe) {
+                            pos = next_slot(pos, g);
+                            v = tab[pos];
                             ++steps;
                         }
                     }
-                    if (v[q].key == nk[q] && slot_significant<SQUARE>(v[q], tau)) {
-                        if ((pos[q] >> kCensusRecLog2) != (home >> kCensusRecLog2)) cr[q] = rec[pos[q] >> kCensusRecLog2];
-                        j[q] = census_index(cr[q], pos[q]);
+                    if (v.key == nk[q] && slot_significant<SQUARE>(v, tau)) {
+                        if ((pos >> kCensusRecLog2) != (home >> kCensusRecLog2)) cr = rec[pos >> kCensusRecLog2];
+                        j[q] = census_index(cr, pos);
                     }
                 }
                 if (j[q] != kNoNeighbour) {
@@ -3528,14 +3598,16 @@ hipError_t launch_bin_keys_framed(const uint32_t* bin1, uint64_t cap1, const uin
 
 hipError_t launch_aggregate_framed(const uint32_t* bin2, uint64_t cap2, const uint32_t* cursor2, uint32_t* cursor1,
                                   Slot* tab, uint64_t cap, Frame frame, SpillBuf spill, unsigned long long* ctr,
-                                  hipStream_t stream, const KernelSpan& span) {
+                                  hipStream_t stream, const KernelSpan& span, const AggCensus& census) {
     const Geo g = make_geo(cap, false, frame);
     if (!framed_binned_geometry(g)) return hipErrorInvalidValue;
+    if (census.rec && g.p_log2 <= kFrameCoarseLog2) return hipErrorInvalidValue;
     const uint64_t parts = 1ull << g.p_log2;
     hipLaunchKernelGGL(k_snapshot_keys, dim3(1), dim3(64), 0, stream, ctr);
+    if (census.rec) (void)launch_zero_u64(reinterpret_cast<uint64_t*>(ctr) + C_DISTINCT, C_SUM - C_DISTINCT + 1, stream);
     if (g.p_log2 > kFrameCoarseLog2)
         launch_k(k_aggregate_f32, dim3((unsigned)parts), dim3(AGG_THREADS), 0u, stream, span, bin2, cap2, cursor2, tab,
-                 g, spill, ctr);
+                 g, spill, ctr, census);
     else
         launch_k(k_aggregate_f, dim3((unsigned)parts), dim3(AGG_THREADS), 0u, stream, span, bin2, cap2, cursor2, tab, g,
                  spill, ctr);
@@ -3644,6 +3716,15 @@ hipError_t launch_census(Slot* tab, uint64_t cap, Frame frame, const JobView& jv
     const uint64_t nrec = cap >> kCensusRecLog2;
     hipLaunchKernelGGL(k_census_offsets, dim3(grid_for(nrec, 256, 4096)), dim3(256), 0, stream, rec, nrec, partials,
                        census_blk_shift(g.p_log2));
+    return hipGetLastError();
+}
+
+hipError_t launch_census_offsets(uint64_t cap, uint32_t* words, uint32_t* ptotal, unsigned long long* ctr,
+                                 hipStream_t stream) {
+    const uint64_t parts = cap >> kPartLog2, nrec = cap >> kCensusRecLog2;
+    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, stream, ptotal, (uint32_t)parts, ctr + C_SIGNIFICANT);
+    hipLaunchKernelGGL(k_census_offsets, dim3(grid_for(nrec, 256, 4096)), dim3(256), 0, stream,
+                       reinterpret_cast<uint2*>(words), nrec, ptotal, 0u);
     return hipGetLastError();
 }
 

@@ -107,6 +107,12 @@ struct TableRun {
     uint32_t tau = 1, mu = 1;
     uint32_t metric = RASTER_CHEBYSHEV, delta = 1;  // neighbourhood of the agglomeration
     bool square = false;                            // the 2x2 post-step before the threshold
+    // census of the significant slots taken by the final update (valid while
+    // census_cap == cap)
+    uint32_t* c_words = nullptr;
+    uint32_t* c_ptot = nullptr;
+    uint64_t c_words_cap = 0;  // table size the census buffers are sized for
+    uint64_t census_cap = 0;
     uint32_t dims = 2;                              // coordinates per point: 2 or 3
     // Occupancy the table is sized for.  Three-dimensional keys are placed
     // in partitions by 4x4x4 blocks, which dense clusters fill completely, so
@@ -181,7 +187,8 @@ struct TableRun {
     raster_status pull_counters();
     raster_status grow(uint64_t new_cap, uint64_t pending, int src);
     raster_status settle();
-    raster_status flush();
+    raster_status flush(bool census = false);
+    raster_status ensure_census(uint64_t c);
     raster_status ensure_bins(uint64_t want_points);
     raster_status mark_pending();
     raster_status wait_stream();
