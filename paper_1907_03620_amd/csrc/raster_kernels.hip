@@ -2754,7 +2754,11 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_census(const Slot* tab, c
                         bad = true;
                         j[q] = kNoNeighbour;
                     } else if (best == i) {
-                        best = j[q];  // backward neighbours come in increasing key order
+                        // backward neighbours come in increasing key order; the
+                        // parent edge is in the forest already, so the merge
+                        // pass need not see it
+                        best = j[q];
+                        j[q] = kNoNeighbour;
                     }
                 }
             }
