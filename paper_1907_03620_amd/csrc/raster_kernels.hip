@@ -2621,9 +2621,10 @@ __device__ __forceinline__ uint32_t census_index(uint2 r, uint64_t pos) {
 // The eight-neighbour link pass over the census (as k_link_part<false, false>
 // for the rest): the slice is held in LDS as 4-byte entries (with the empty
 // and foreign markers of k_aggregate_f32) and the local ranks of its
-// significant slots.
+// significant slots.  At most 80 VGPRs, so that six waves per SIMD hide the
+// device-table probes.
 template <bool SQUARE>
-__global__ __launch_bounds__(LINK_THREADS) void k_link_census(const Slot* tab, const Geo g, uint32_t tau,
+__global__ __launch_bounds__(LINK_THREADS, 6) void k_link_census(const Slot* tab, const Geo g, uint32_t tau,
                                                               const uint2* rec, uint64_t* s_key, uint32_t* s_count,
                                                               uint32_t* size, uint32_t* parent, uint32_t* nbr,
                                                               unsigned long long* ctr) {
@@ -2703,24 +2704,36 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_census(const Slot* tab, c
             want[2] = left && up;
             nk[3] = ((uint64_t)bx << 32) | (uint32_t)(by - 1);
             want[3] = down;
-            // local neighbours through the slice in LDS, the others through
-            // the table and one census record, one at a time (few live
-            // registers, so that many waves hide the table's latency)
+            // Loads for the neighbours in other partitions issued together:
+            // the keys of the home slot and the next one, and the home slot's
+            // census record, whose bit tells significance (no counts read).
+            // Neighbours in this partition are probed in LDS meanwhile.
+            uint64_t pos[4], k0[4], k1[4];
+            uint32_t e[4];
+            uint2 cr[4];
+            bool local[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint64_t h;
+                local[q] = frame_code(nk[q], g.fx, g.fy, h, e[q]) && (h >> (kFrameStBits - g.p_log2)) == p;
+                pos[q] = home_slot(nk[q], g);
+                if (want[q] && !local[q]) {
+                    k0[q] = tab[pos[q]].key;
+                    k1[q] = tab[next_slot(pos[q], g)].key;
+                    cr[q] = rec[pos[q] >> kCensusRecLog2];
+                }
+            }
             uint32_t j[4];
             uint32_t best = i;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 j[q] = kNoNeighbour;
                 if (!want[q]) continue;
-                uint64_t h;
-                uint32_t e;
-                const bool local = frame_code(nk[q], g.fx, g.fy, h, e) && (h >> (kFrameStBits - g.p_log2)) == p;
-                uint64_t pos = home_slot(nk[q], g);
-                if (local) {
-                    uint32_t lp = (uint32_t)(pos - base);
+                if (local[q]) {
+                    uint32_t lp = (uint32_t)(pos[q] - base);
                     for (uint32_t step = 0; step < kMaxProbe; ++step) {
                         const uint32_t cur = lent[lp];
-                        if (cur == e) {
+                        if (cur == e[q]) {
                             const uint16_t r = lrank[lp];
                             if (r != kNoRank) j[q] = poff + r;
                             break;
@@ -2729,24 +2742,22 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_census(const Slot* tab, c
                         lp = (lp + 1) & (kPartSlots - 1);
                     }
                 } else {
-                    // home slot, the next one and the home slot's census record together
-                    Slot v = tab[pos];
-                    const Slot nx = tab[next_slot(pos, g)];
-                    uint2 cr = rec[pos >> kCensusRecLog2];
-                    const uint64_t home = pos;
-                    if (v.key != nk[q] && v.key != kEmptyKey) {
-                        pos = next_slot(pos, g);
-                        v = nx;
+                    const uint64_t home = pos[q];
+                    uint64_t ck = k0[q];
+                    if (ck != nk[q] && ck != kEmptyKey) {
+                        pos[q] = next_slot(pos[q], g);
+                        ck = k1[q];
                         uint32_t steps = 2;
-                        while (v.key != nk[q] && v.key != kEmptyKey && steps < kMaxProbe) {
-                            pos = next_slot(pos, g);
-                            v = tab[pos];
+                        while (ck != nk[q] && ck != kEmptyKey && steps < kMaxProbe) {
+                            pos[q] = next_slot(pos[q], g);
+                            ck = tab[pos[q]].key;
                             ++steps;
                         }
                     }
-                    if (v.key == nk[q] && slot_significant<SQUARE>(v, tau)) {
-                        if ((pos >> kCensusRecLog2) != (home >> kCensusRecLog2)) cr = rec[pos >> kCensusRecLog2];
-                        j[q] = census_index(cr, pos);
+                    if (ck == nk[q]) {
+                        uint2 r = cr[q];
+                        if ((pos[q] >> kCensusRecLog2) != (home >> kCensusRecLog2)) r = rec[pos[q] >> kCensusRecLog2];
+                        if ((r.x >> (pos[q] & 31)) & 1u) j[q] = census_index(r, pos[q]);
                     }
                 }
                 if (j[q] != kNoNeighbour) {
