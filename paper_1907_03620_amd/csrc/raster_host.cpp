@@ -996,7 +996,7 @@ raster_status TableRun::finish(raster_result** out) {
                      : launch_threshold(tab, jv, s_key, s_count, size, partials, ctr, stream, square ? cap : 0);
     if (e == hipSuccess) e = hipEventRecord(ev[2], stream);
     if (e == hipSuccess)
-        e = census ? launch_link_census(tab, cap, frame, jv, tau, square, c_words, s_key, s_count, parent, nbr,
+        e = census ? launch_link_census(tab, cap, frame, mu, tau, square, c_words, s_key, s_count, parent, nbr,
                                         size, m, ctr, stream)
                    : launch_agglomerate(tab, cap, jv, s_key, parent, nbr, size, m, ctr, stream, rounds.data(),
                                         (int)rounds.size(), dims == 3, frame);

@@ -363,7 +363,7 @@ bool census_geometry(uint64_t cap, Frame frame);
 uint64_t census_words(uint64_t cap);
 hipError_t launch_census(Slot* tab, uint64_t cap, Frame frame, const JobView& jv, uint32_t tau, bool square,
                          uint32_t* words, uint32_t* partials, unsigned long long* ctr, hipStream_t stream);
-hipError_t launch_link_census(const Slot* tab, uint64_t cap, Frame frame, const JobView& jv, uint32_t tau,
+hipError_t launch_link_census(const Slot* tab, uint64_t cap, Frame frame, uint32_t mu, uint32_t tau,
                               bool square, const uint32_t* words, uint64_t* s_key, uint32_t* s_count,
                               uint32_t* parent, uint32_t* nbr, uint32_t* size, uint64_t s_max,
                               unsigned long long* ctr, hipStream_t stream);

@@ -2853,6 +2853,60 @@ __global__ void k_compress(JobView jv, uint32_t* parent, uint32_t* root, uint32_
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
 }
 
+// The same for the census path, one workgroup per partition: the roots of
+// the partition's significant tiles are counted in LDS first, so that a
+// component's size takes one memory-side atomic per partition it touches
+// instead of one per tile (the partition's compact range comes from the
+// census records).
+__global__ __launch_bounds__(512) void k_compress_census(const uint2* rec, uint64_t parts, uint32_t mu,
+                                                         uint32_t* parent, uint32_t* root, uint32_t* size,
+                                                         unsigned long long* ctr) {
+    __shared__ uint32_t hroot[kPartSlots];  // a partition has at most kPartSlots tiles, so as many roots
+    __shared__ uint32_t hcnt[kPartSlots];
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
+    bool bad = false;
+    uint32_t roots = 0;
+    for (uint64_t p = blockIdx.x; p < parts; p += gridDim.x) {
+        const uint2 last = rec[(p << 7) + kCensusPartRecs - 1];
+        const uint32_t poff = rec[p << 7].y;
+        const uint32_t nl = last.y + (uint32_t)__popc(last.x) - poff;
+        __syncthreads();  // the previous partition's counts are out
+        for (uint32_t u = threadIdx.x; u < kPartSlots; u += blockDim.x) {
+            hroot[u] = kNone;
+            hcnt[u] = 0;
+        }
+        __syncthreads();
+        for (uint32_t t = threadIdx.x; t < nl; t += blockDim.x) {
+            const uint32_t i = poff + t;
+            if (i >= s) {
+                bad = true;
+                continue;
+            }
+            const uint32_t r = uf_root_cached(parent, i, s, bad);
+            root[i] = r;
+            roots += (r == i);
+            uint32_t h = mix32(r) & (kPartSlots - 1);
+            for (uint32_t step = 0; step < kPartSlots; ++step) {
+                uint32_t cur = __hip_atomic_load(&hroot[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (cur == kNone) cur = atomicCAS(&hroot[h], kNone, r);
+                if (cur == kNone || cur == r) {
+                    atomicAdd(&hcnt[h], 1u);
+                    break;
+                }
+                h = (h + 1) & (kPartSlots - 1);
+            }
+        }
+        __syncthreads();
+        for (uint32_t u = threadIdx.x; u < kPartSlots; u += blockDim.x) {
+            const uint32_t r = hroot[u];
+            if (r != kNone && ld_relaxed(size + r) < mu) atomicAdd(size + r, hcnt[u]);
+        }
+    }
+    block_count_add(&ctr[C_COMPONENTS], roots);
+    if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
+}
+
 // ---- mu filter (Algorithm 1: keep clusters of at least mu tiles) -----------
 
 // Root, mu and root size of the items of one scan tile (t0 < hi <= s).  Each
@@ -3743,7 +3797,7 @@ hipError_t launch_census_offsets(uint64_t cap, uint32_t* words, uint32_t* ptotal
     return hipGetLastError();
 }
 
-hipError_t launch_link_census(const Slot* tab, uint64_t cap, Frame frame, const JobView& jv, uint32_t tau,
+hipError_t launch_link_census(const Slot* tab, uint64_t cap, Frame frame, uint32_t mu, uint32_t tau,
                               bool square, const uint32_t* words, uint64_t* s_key, uint32_t* s_count,
                               uint32_t* parent, uint32_t* nbr, uint32_t* size, uint64_t s_max,
                               unsigned long long* ctr, hipStream_t stream) {
@@ -3761,7 +3815,8 @@ hipError_t launch_link_census(const Slot* tab, uint64_t cap, Frame frame, const 
     hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, stream, nbr, 1u, s_key, parent, ctr);
     // the neighbour lists are dead after the merge pass; their first s words
     // take the final roots
-    hipLaunchKernelGGL(k_compress, dim3(grid), dim3(256), 0, stream, jv, parent, nbr, size, ctr);
+    hipLaunchKernelGGL(k_compress_census, dim3(link_grid), dim3(512), 0, stream, rec, cap >> kPartLog2, mu,
+                       parent, nbr, size, ctr);
     return hipGetLastError();
 }
 
