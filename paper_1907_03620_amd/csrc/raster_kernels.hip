@@ -70,14 +70,16 @@ __device__ __forceinline__ uint32_t slot_hash(uint64_t key) {
 // low 6 bits zero.  Register = the top kHllLog2 hash bits, rank = 1 + the
 // leading zeros of hash bits [6, 32 - kHllLog2).  Returns false for a tile
 // outside the sample.
-__device__ __forceinline__ bool hll_sample(uint64_t key, uint32_t& reg, uint32_t& rank) {
+__device__ __forceinline__ bool hll_from_hash(uint32_t h, uint32_t& reg, uint32_t& rank) {
     constexpr uint32_t rank_bits = 26 - kHllLog2;
-    const uint32_t h = slot_hash(key);
     if (h & 63u) return false;
     const uint32_t rest = (h >> 6) & ((1u << rank_bits) - 1);
     rank = rest ? (uint32_t)__clz(rest) - (32 - rank_bits) + 1 : rank_bits + 1;
     reg = h >> (32 - kHllLog2);
     return true;
+}
+__device__ __forceinline__ bool hll_sample(uint64_t key, uint32_t& reg, uint32_t& rank) {
+    return hll_from_hash(slot_hash(key), reg, rank);
 }
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -1129,15 +1131,19 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_points_f(const T* __restric
             if (i < n) {
                 if (tile_key(x[j], y[j], scale, key)) {
                     uint32_t reg, rank;
-                    if (SKETCH && hll_sample(key, reg, rank)) atomicMax(&sk[reg], rank);
                     uint64_t h;
                     uint32_t e;
                     if (frame_code(key, g.fx, g.fy, h, e)) {
+                        // the sketch takes the mixed h with the position in the
+                        // super-tile spread over 32 bits: no second hash
+                        if (SKETCH && hll_from_hash((uint32_t)h ^ ((e & 63u) * kGolden32), reg, rank))
+                            atomicMax(&sk[reg], rank);
                         ent[jj] = e;
                         bucket[jj] = (uint16_t)(h >> kFrameHLow);
                         valid |= 1u << jj;
                     } else {
                         // outside the frame: straight into the table
+                        if (SKETCH && hll_sample(key, reg, rank)) atomicMax(&sk[reg], rank);
                         r = table_add(tab, g, key, 1u);
                         fresh += (r == ADD_NEW);
                     }
