@@ -654,6 +654,12 @@ raster_status TableRun::settle() {
         return fail(RASTER_E_DEVICE, "spill buffer overflow");
     }
     const uint64_t spilled = h_ctr[C_SPILLED];
+    if (spilled > 0 && image_cap == cap) {
+        // the last update wrote only its slice image: the table takes the
+        // keys before it grows
+        HIP_TRY(launch_image_to_table(img, tab, cap, frame, stream), "image to table");
+        image_cap = 0;
+    }
     if (spilled > 0) {
         const double lf = target_load();
         const uint64_t want = next_pow2((uint64_t)((double)(h_ctr[C_INSERTED] + spilled) / lf) + 1);
@@ -707,6 +713,11 @@ raster_status TableRun::ensure_census(uint64_t c) {
     HIP_TRY(bufs.take((void**)&c_words, census_words(c) * sizeof(uint32_t)), "census");
     HIP_TRY(bufs.take((void**)&c_ptot, (c >> kPartLog2) * sizeof(uint32_t)), "census totals");
     c_words_cap = c;
+    if (img) bufs.give_back(img);
+    img = nullptr;
+    img_cap = 0;
+    HIP_TRY(bufs.take((void**)&img, c * sizeof(uint2)), "slice image");
+    img_cap = c;
     return RASTER_OK;
 }
 
@@ -716,6 +727,11 @@ raster_status TableRun::ensure_census(uint64_t c) {
 raster_status TableRun::flush(bool census) {
     census_cap = 0;
     if (group_points == 0) return RASTER_OK;
+    if (image_cap == cap) {
+        // an earlier update wrote only its slice image
+        HIP_TRY(launch_image_to_table(img, tab, cap, frame, stream), "image to table");
+        image_cap = 0;
+    }
     // the sketch registers come back with the counters, in one wait
     if (sketch) {
         HIP_TRY(hipMemcpyAsync(h_sketch, sketch, ((size_t)kHllReps << kHllLog2) * sizeof(uint32_t),
@@ -767,7 +783,9 @@ raster_status TableRun::flush(bool census) {
             cen.rec = reinterpret_cast<uint2*>(c_words);
             cen.ptotal = c_ptot;
             cen.tau = tau;
+            cen.img = img;
             census_cap = cap;
+            image_cap = cap;
         }
         if (frame.on)
             HIP_TRY(launch_aggregate_framed(reinterpret_cast<uint32_t*>(bin2), c2, cursor2, cursor1, tab, cap, frame,
@@ -996,7 +1014,8 @@ raster_status TableRun::finish(raster_result** out) {
                      : launch_threshold(tab, jv, s_key, s_count, size, partials, ctr, stream, square ? cap : 0);
     if (e == hipSuccess) e = hipEventRecord(ev[2], stream);
     if (e == hipSuccess)
-        e = census ? launch_link_census(tab, cap, frame, mu, tau, square, c_words, s_key, s_count, parent, nbr,
+        e = census ? launch_link_census(tab, fused && image_cap == cap ? img : nullptr, cap, frame, mu, tau, square,
+                                        c_words, s_key, s_count, parent, nbr,
                                         size, m, ctr, stream)
                    : launch_agglomerate(tab, cap, jv, s_key, parent, nbr, size, m, ctr, stream, rounds.data(),
                                         (int)rounds.size(), dims == 3, frame);

@@ -278,6 +278,10 @@ struct AggCensus {
     uint2* rec = nullptr;
     uint32_t* ptotal = nullptr;
     uint32_t tau = 0;
+    // non-null: the update writes each slice's image (entry and count per
+    // slot, cap pairs) instead of the table; launch_image_to_table writes the
+    // keys into the table when it has to grow afterwards
+    uint2* img = nullptr;
 };
 // Update: one workgroup per partition adds its entries to the table in LDS;
 // then clears cursor1.
@@ -363,7 +367,9 @@ bool census_geometry(uint64_t cap, Frame frame);
 uint64_t census_words(uint64_t cap);
 hipError_t launch_census(Slot* tab, uint64_t cap, Frame frame, const JobView& jv, uint32_t tau, bool square,
                          uint32_t* words, uint32_t* partials, unsigned long long* ctr, hipStream_t stream);
-hipError_t launch_link_census(const Slot* tab, uint64_t cap, Frame frame, uint32_t mu, uint32_t tau,
+hipError_t launch_image_to_table(const uint2* img, Slot* tab, uint64_t cap, Frame frame, hipStream_t stream);
+// img: the slice image of the final update, or null (read the table).
+hipError_t launch_link_census(const Slot* tab, const uint2* img, uint64_t cap, Frame frame, uint32_t mu, uint32_t tau,
                               bool square, const uint32_t* words, uint64_t* s_key, uint32_t* s_count,
                               uint32_t* parent, uint32_t* nbr, uint32_t* size, uint64_t s_max,
                               unsigned long long* ctr, hipStream_t stream);

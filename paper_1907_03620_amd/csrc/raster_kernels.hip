@@ -1547,7 +1547,11 @@ __global__ __launch_bounds__(AGG_THREADS, 8) void k_aggregate_f32(const uint32_t
     for (int u = 0; u < PER; ++u) {
         const uint32_t sl = u * AGG_THREADS + threadIdx.x;
         const uint32_t e = A.ent[sl], c = A.cnt[sl];
-        if (L.total && e != kEmpty && e != kAlien) {
+        if (cen.img) {
+            // the final update writes the slice image (the table itself only
+            // if keys spill afterwards: k_image_to_table)
+            cen.img[(p << kPartLog2) + sl] = make_uint2(e, c);
+        } else if (L.total && e != kEmpty && e != kAlien) {
             Slot v;
             v.key = frame_key(cb, e, g.fx, g.fy);
             v.count = c;
@@ -2587,7 +2591,16 @@ __global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* v, uint32_t n, unsi
     const uint32_t per = (n + 1023) / 1024;
     const uint32_t lo = min(threadIdx.x * per, n), hi = min(lo + per, n);
     uint32_t local = 0;
-    for (uint32_t i = lo; i < hi; ++i) local += v[i];
+    constexpr uint32_t kRun = 16;  // runs up to this long are loaded all at once
+    uint32_t run[kRun];
+    if (per <= kRun) {
+#pragma unroll
+        for (uint32_t k = 0; k < kRun; ++k) run[k] = lo + k < hi ? v[lo + k] : 0u;
+#pragma unroll
+        for (uint32_t k = 0; k < kRun; ++k) local += run[k];
+    } else {
+        for (uint32_t i = lo; i < hi; ++i) local += v[i];
+    }
     uint32_t inc = local;
     for (int off = 1; off < 64; off <<= 1) {
         const uint32_t o = __shfl_up(inc, off);
@@ -2607,10 +2620,19 @@ __global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* v, uint32_t n, unsi
     }
     __syncthreads();
     uint32_t ex = wsum[w] + inc - local;
-    for (uint32_t i = lo; i < hi; ++i) {
-        const uint32_t c = v[i];
-        v[i] = ex;
-        ex += c;
+    if (per <= kRun) {
+#pragma unroll
+        for (uint32_t k = 0; k < kRun; ++k)
+            if (lo + k < hi) {
+                v[lo + k] = ex;
+                ex += run[k];
+            }
+    } else {
+        for (uint32_t i = lo; i < hi; ++i) {
+            const uint32_t c = v[i];
+            v[i] = ex;
+            ex += c;
+        }
     }
 }
 
@@ -2630,12 +2652,15 @@ __device__ __forceinline__ uint32_t census_index(uint2 r, uint64_t pos) {
 // for the rest): the slice is held in LDS as 4-byte entries (with the empty
 // and foreign markers of k_aggregate_f32) and the local ranks of its
 // significant slots.  At most 80 VGPRs, so that six waves per SIMD hide the
-// device-table probes.
-template <bool SQUARE>
-__global__ __launch_bounds__(LINK_THREADS, 6) void k_link_census(const Slot* tab, const Geo g, uint32_t tau,
-                                                              const uint2* rec, uint64_t* s_key, uint32_t* s_count,
-                                                              uint32_t* size, uint32_t* parent, uint32_t* nbr,
-                                                              unsigned long long* ctr) {
+// device-table probes.  With IMG the slices come from the image the final
+// update wrote (entry and count per slot, 8 bytes instead of 16), and so do
+// the probes for neighbours inside the frame; keys outside the frame are
+// still found in the table.
+template <bool SQUARE, bool IMG>
+__global__ __launch_bounds__(LINK_THREADS, 6) void k_link_census(const Slot* tab, const uint2* img, const Geo g,
+                                                              uint32_t tau, const uint2* rec, uint64_t* s_key,
+                                                              uint32_t* s_count, uint32_t* size, uint32_t* parent,
+                                                              uint32_t* nbr, unsigned long long* ctr) {
     __shared__ uint32_t lent[kPartSlots];
     __shared__ uint16_t lrank[kPartSlots];  // rank among the partition's significant slots, kNoRank if none
     __shared__ uint16_t list[kPartSlots];   // slot of each rank
@@ -2657,22 +2682,32 @@ __global__ __launch_bounds__(LINK_THREADS, 6) void k_link_census(const Slot* tab
         __syncthreads();  // the previous partition's LDS reads are done
         constexpr int PER = (int)kPartSlots / LINK_THREADS;
         {
-            Slot v[PER];
+            Slot v[IMG ? 1 : PER];
+            uint2 iv[IMG ? PER : 1];
             uint32_t wz[PER];  // census counts before this wave's words, loaded with the slice
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
-                v[k] = tab[base + k * LINK_THREADS + threadIdx.x];
+                if constexpr (IMG) iv[k] = img[base + k * LINK_THREADS + threadIdx.x];
+                else v[k] = tab[base + k * LINK_THREADS + threadIdx.x];
                 const uint32_t word = (uint32_t)__builtin_amdgcn_readfirstlane(k * (LINK_THREADS / 64) + w);
                 wz[k] = rec[(p << 7) + 2 * word].y;
             }
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
                 const uint32_t u = k * LINK_THREADS + threadIdx.x;
-                uint64_t h;
-                uint32_t e = kEmpty;
-                if (v[k].key != kEmptyKey && !frame_code(v[k].key, g.fx, g.fy, h, e)) e = kAlien;
+                uint32_t e = kEmpty, cnt;
+                bool sig;
+                if constexpr (IMG) {
+                    e = iv[k].x;
+                    cnt = iv[k].y;
+                    sig = e != kEmpty && cnt >= tau;
+                } else {
+                    uint64_t h;
+                    if (v[k].key != kEmptyKey && !frame_code(v[k].key, g.fx, g.fy, h, e)) e = kAlien;
+                    cnt = v[k].count;
+                    sig = slot_significant<SQUARE>(v[k], tau);
+                }
                 lent[u] = e;
-                const bool sig = slot_significant<SQUARE>(v[k], tau);
                 const uint64_t b = __ballot(sig);
                 const uint32_t r = wz[k] - poff + (uint32_t)__popcll(b & lt);
                 lrank[u] = sig ? (uint16_t)r : kNoRank;
@@ -2680,8 +2715,11 @@ __global__ __launch_bounds__(LINK_THREADS, 6) void k_link_census(const Slot* tab
                     list[r] = (uint16_t)u;
                     const uint64_t i = (uint64_t)poff + r;
                     if (i < s) {
-                        s_key[i] = v[k].key;
-                        s_count[i] = v[k].count;
+                        if constexpr (IMG)
+                            s_key[i] = e != kAlien ? frame_key(cb, e, g.fx, g.fy) : tab[base + u].key;
+                        else
+                            s_key[i] = v[k].key;
+                        s_count[i] = cnt;
                         size[i] = 0;
                     } else {
                         bad = true;
@@ -2716,19 +2754,34 @@ __global__ __launch_bounds__(LINK_THREADS, 6) void k_link_census(const Slot* tab
             // the keys of the home slot and the next one, and the home slot's
             // census record, whose bit tells significance (no counts read).
             // Neighbours in this partition are probed in LDS meanwhile.
-            uint64_t pos[4], k0[4], k1[4];
+            uint64_t pos[4];
             uint32_t e[4];
             uint2 cr[4];
-            bool local[4];
+            bool local[4], framed[4];
+            // IMG: a0/a1 hold entries (4 bytes) and pq the neighbour's
+            // partition; otherwise k0/k1 hold keys
+            uint32_t a0[IMG ? 4 : 1], a1[IMG ? 4 : 1], pq[IMG ? 4 : 1];
+            uint64_t k0[IMG ? 1 : 4], k1[IMG ? 1 : 4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 uint64_t h;
-                local[q] = frame_code(nk[q], g.fx, g.fy, h, e[q]) && (h >> (kFrameStBits - g.p_log2)) == p;
+                framed[q] = frame_code(nk[q], g.fx, g.fy, h, e[q]);
+                const uint64_t part_q = h >> (kFrameStBits - g.p_log2);
+                local[q] = framed[q] && part_q == p;
                 pos[q] = home_slot(nk[q], g);
-                if (want[q] && !local[q]) {
-                    k0[q] = tab[pos[q]].key;
-                    k1[q] = tab[next_slot(pos[q], g)].key;
-                    cr[q] = rec[pos[q] >> kCensusRecLog2];
+                if constexpr (IMG) {
+                    pq[q] = (uint32_t)part_q;
+                    if (want[q] && !local[q] && framed[q]) {
+                        a0[q] = img[pos[q]].x;
+                        a1[q] = img[next_slot(pos[q], g)].x;
+                        cr[q] = rec[pos[q] >> kCensusRecLog2];
+                    }
+                } else {
+                    if (want[q] && !local[q]) {
+                        k0[q] = tab[pos[q]].key;
+                        k1[q] = tab[next_slot(pos[q], g)].key;
+                        cr[q] = rec[pos[q] >> kCensusRecLog2];
+                    }
                 }
             }
             uint32_t j[4];
@@ -2749,12 +2802,33 @@ __global__ __launch_bounds__(LINK_THREADS, 6) void k_link_census(const Slot* tab
                         if (cur == kEmpty) break;
                         lp = (lp + 1) & (kPartSlots - 1);
                     }
-                } else {
+                } else if (IMG && framed[q]) {
+                    // the neighbour's partition marks its empty slots by its own value
+                    const uint32_t none = ((pq[IMG ? q : 0] & ((1u << fine) - 1)) << (32 - fine)) ^ 0x80000000u;
                     const uint64_t home = pos[q];
-                    uint64_t ck = k0[q];
+                    uint32_t ce = a0[IMG ? q : 0];
+                    if (ce != e[q] && ce != none) {
+                        pos[q] = next_slot(pos[q], g);
+                        ce = a1[IMG ? q : 0];
+                        uint32_t steps = 2;
+                        while (ce != e[q] && ce != none && steps < kMaxProbe) {
+                            pos[q] = next_slot(pos[q], g);
+                            ce = img[pos[q]].x;
+                            ++steps;
+                        }
+                    }
+                    if (ce == e[q]) {
+                        uint2 r = cr[q];
+                        if ((pos[q] >> kCensusRecLog2) != (home >> kCensusRecLog2)) r = rec[pos[q] >> kCensusRecLog2];
+                        if ((r.x >> (pos[q] & 31)) & 1u) j[q] = census_index(r, pos[q]);
+                    }
+                } else {
+                    // keys outside the frame (IMG: not loaded ahead) are in the table
+                    const uint64_t home = pos[q];
+                    uint64_t ck = IMG ? tab[pos[q]].key : k0[IMG ? 0 : q];
                     if (ck != nk[q] && ck != kEmptyKey) {
                         pos[q] = next_slot(pos[q], g);
-                        ck = k1[q];
+                        ck = IMG ? tab[pos[q]].key : k1[IMG ? 0 : q];
                         uint32_t steps = 2;
                         while (ck != nk[q] && ck != kEmptyKey && steps < kMaxProbe) {
                             pos[q] = next_slot(pos[q], g);
@@ -2763,7 +2837,7 @@ __global__ __launch_bounds__(LINK_THREADS, 6) void k_link_census(const Slot* tab
                         }
                     }
                     if (ck == nk[q]) {
-                        uint2 r = cr[q];
+                        uint2 r = IMG ? rec[pos[q] >> kCensusRecLog2] : cr[q];
                         if ((pos[q] >> kCensusRecLog2) != (home >> kCensusRecLog2)) r = rec[pos[q] >> kCensusRecLog2];
                         if ((r.x >> (pos[q] & 31)) & 1u) j[q] = census_index(r, pos[q]);
                     }
@@ -2913,6 +2987,26 @@ __global__ __launch_bounds__(512) void k_compress_census(const uint2* rec, uint6
     }
     block_count_add(&ctr[C_COMPONENTS], roots);
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
+}
+
+// Writes the keys of a slice image back into the table (for a table that
+// has to grow after an update that wrote only the image).
+__global__ void k_image_to_table(const uint2* img, Slot* tab, const Geo g) {
+    const uint32_t fine = g.p_log2 - kFrameCoarseLog2;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < g.cap;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t p = i >> kPartLog2;
+        const uint32_t top = (uint32_t)(p & ((1u << fine) - 1)) << (32 - fine);
+        const uint32_t kEmpty = top ^ 0x80000000u, kAlien = kEmpty ^ 1u;
+        const uint2 v = img[i];
+        if (v.x != kEmpty && v.x != kAlien) {
+            Slot sl;
+            sl.key = frame_key((uint32_t)(p >> fine), v.x, g.fx, g.fy);
+            sl.count = v.y;
+            sl.aux = kNotSignificant;
+            tab[i] = sl;
+        }
+    }
 }
 
 // ---- mu filter (Algorithm 1: keep clusters of at least mu tiles) -----------
@@ -3805,7 +3899,13 @@ hipError_t launch_census_offsets(uint64_t cap, uint32_t* words, uint32_t* ptotal
     return hipGetLastError();
 }
 
-hipError_t launch_link_census(const Slot* tab, uint64_t cap, Frame frame, uint32_t mu, uint32_t tau,
+hipError_t launch_image_to_table(const uint2* img, Slot* tab, uint64_t cap, Frame frame, hipStream_t stream) {
+    hipLaunchKernelGGL(k_image_to_table, dim3(grid_for(cap, 256, 65536)), dim3(256), 0, stream, img, tab,
+                       make_geo(cap, false, frame));
+    return hipGetLastError();
+}
+
+hipError_t launch_link_census(const Slot* tab, const uint2* img, uint64_t cap, Frame frame, uint32_t mu, uint32_t tau,
                               bool square, const uint32_t* words, uint64_t* s_key, uint32_t* s_count,
                               uint32_t* parent, uint32_t* nbr, uint32_t* size, uint64_t s_max,
                               unsigned long long* ctr, hipStream_t stream) {
@@ -3813,12 +3913,16 @@ hipError_t launch_link_census(const Slot* tab, uint64_t cap, Frame frame, uint32
     const uint2* rec = reinterpret_cast<const uint2*>(words);
     const int grid = (grid_for(s_max, 256, kPersistBlocks) + kXcds - 1) / kXcds * kXcds;
     const int link_grid = grid_for(cap >> kPartLog2, 1, 8192);
+    if (square && img) return hipErrorInvalidValue;  // the 2x2 marks are in the table only
     if (square)
-        hipLaunchKernelGGL(k_link_census<true>, dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, g, tau, rec,
-                           s_key, s_count, size, parent, nbr, ctr);
+        hipLaunchKernelGGL((k_link_census<true, false>), dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, img, g,
+                           tau, rec, s_key, s_count, size, parent, nbr, ctr);
+    else if (img)
+        hipLaunchKernelGGL((k_link_census<false, true>), dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, img, g,
+                           tau, rec, s_key, s_count, size, parent, nbr, ctr);
     else
-        hipLaunchKernelGGL(k_link_census<false>, dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, g, tau, rec,
-                           s_key, s_count, size, parent, nbr, ctr);
+        hipLaunchKernelGGL((k_link_census<false, false>), dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, img, g,
+                           tau, rec, s_key, s_count, size, parent, nbr, ctr);
     hipLaunchKernelGGL(k_jump, dim3(grid), dim3(256), 0, stream, parent, ctr);
     hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, stream, nbr, 1u, s_key, parent, ctr);
     // the neighbour lists are dead after the merge pass; their first s words

@@ -113,6 +113,10 @@ struct TableRun {
     uint32_t* c_ptot = nullptr;
     uint64_t c_words_cap = 0;  // table size the census buffers are sized for
     uint64_t census_cap = 0;
+    // slice image written by the final update instead of the table (the
+    // table is stale while image_cap == cap)
+    uint2* img = nullptr;
+    uint64_t img_cap = 0, image_cap = 0;
     uint32_t dims = 2;                              // coordinates per point: 2 or 3
     // Occupancy the table is sized for.  Three-dimensional keys are placed
     // in partitions by 4x4x4 blocks, which dense clusters fill completely, so
