@@ -190,3 +190,18 @@ def test_census_table_sizes(raster, torch, square):
         assert res.stats["key_frame"] == 1
         assert res.stats["table_capacity"] >= 1 << 21
         assert_same(res, ref, f"census, {res.stats['table_capacity']} slots, square {square}")
+
+
+def test_final_update_image_then_growth(raster, torch):
+    """The final update of a table of 512+ partitions writes a slice image
+    instead of the table.  When it spills at high load, the table is rebuilt
+    from the image before it grows; results must not change (Algorithm 1)."""
+    rng = synth.rng_for(7900)
+    # about 1.6M distinct tiles of 1 x 1 (p=0) in a table of 2^21 slots
+    pts = rng.uniform(0.0, 2200.0, size=(1_900_000, 2))
+    chunks = [np.ascontiguousarray(pts[i::3]) for i in range(3)]
+    _say("frame: final update image, then growth")
+    res = run_stream(raster, torch, chunks, 0, 2, 2, tile_hint=1_200_000, mode=2)
+    assert res.stats["key_frame"] == 1
+    assert res.stats["grow_events"] >= 1, "the final update did not spill"
+    assert_same(res, oracle.cluster_chunks(chunks, tau=2, mu=2, precision=0), "image, then growth")
