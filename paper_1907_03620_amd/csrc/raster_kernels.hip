@@ -1106,7 +1106,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_points_f(const T* __restric
     const int64_t base = (int64_t)blockIdx.x * TILE + threadIdx.x;
     uint32_t ent[ITEMS];
     uint16_t bucket[ITEMS];
-    uint32_t valid = 0, fresh = 0;
+    uint32_t valid = 0, rare = 0, fresh = 0;
     bool bad = false;
     constexpr int HALF = ITEMS > 8 ? ITEMS / 2 : ITEMS;
 #pragma unroll
@@ -1120,36 +1120,49 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_points_f(const T* __restric
             y[j] = 0.0;
             if (i < n) load_point(pts, i, x[j], y[j]);
         }
+        // Keys inside the frame without branches (the projection of
+        // tile_key, then frame_code); points outside the frame wait for the
+        // pass below, and range errors only raise the flag.
 #pragma unroll
         for (int j = 0; j < HALF; ++j) {
             const int jj = h0 + j;
-            const int64_t i = base + (int64_t)jj * BIN_THREADS;
-            ent[jj] = 0;
-            bucket[jj] = 0;
+            const bool in = base + (int64_t)jj * BIN_THREADS < n;
+            const double px = x[j] * scale, py = y[j] * scale;
+            const bool ok = fabs(px) < 2147483647.0 && fabs(py) < 2147483647.0;
+            const uint32_t bx = (uint32_t)(int32_t)(ok ? px : 0.0) + 0x80000000u;
+            const uint32_t by = (uint32_t)(int32_t)(ok ? py : 0.0) + 0x80000000u;
+            const uint32_t rx = bx - g.fx, ry = by - g.fy;
+            const bool inside = ok && (rx | ry) < kFrameSide;
+            const uint64_t h = frame_mix(((uint64_t)((rx >> 3) & ((1u << kFrameStSide) - 1)) << kFrameStSide) |
+                                         ((ry >> 3) & ((1u << kFrameStSide) - 1)));
+            const uint32_t e = ((uint32_t)(h & ((1u << kFrameHLow) - 1)) << 6) | ((rx & 7u) << 3) | (ry & 7u);
+            ent[jj] = e;
+            bucket[jj] = (uint16_t)(h >> kFrameHLow);
+            valid |= (in && inside ? 1u : 0u) << jj;
+            rare |= (in && ok && !inside ? 1u : 0u) << jj;
+            bad |= in && !ok;
+            // the sketch takes the mixed h with the position in the
+            // super-tile spread over 32 bits: no second hash
+            uint32_t reg, rank;
+            if (SKETCH && in && inside && hll_from_hash((uint32_t)h ^ ((e & 63u) * kGolden32), reg, rank))
+                atomicMax(&sk[reg], rank);
+        }
+    }
+    // Points whose tiles lie outside the frame: read again and put straight
+    // into the table (with the key's own sketch hash).
+    if (__ballot(rare != 0)) {  // uniform across the wave
+#pragma unroll 1
+        for (int jj = 0; jj < ITEMS; ++jj) {
             int r = ADD_FOUND;
             uint64_t key = 0;
-            if (i < n) {
-                if (tile_key(x[j], y[j], scale, key)) {
-                    uint32_t reg, rank;
-                    uint64_t h;
-                    uint32_t e;
-                    if (frame_code(key, g.fx, g.fy, h, e)) {
-                        // the sketch takes the mixed h with the position in the
-                        // super-tile spread over 32 bits: no second hash
-                        if (SKETCH && hll_from_hash((uint32_t)h ^ ((e & 63u) * kGolden32), reg, rank))
-                            atomicMax(&sk[reg], rank);
-                        ent[jj] = e;
-                        bucket[jj] = (uint16_t)(h >> kFrameHLow);
-                        valid |= 1u << jj;
-                    } else {
-                        // outside the frame: straight into the table
-                        if (SKETCH && hll_sample(key, reg, rank)) atomicMax(&sk[reg], rank);
-                        r = table_add(tab, g, key, 1u);
-                        fresh += (r == ADD_NEW);
-                    }
-                } else {
-                    bad = true;
-                }
+            if ((rare >> jj) & 1u) {
+                double x, y;
+                load_point(pts, base + (int64_t)jj * BIN_THREADS, x, y);
+                (void)tile_key(x, y, scale, key);  // in range: checked above
+                uint32_t reg, rank;
+                if (SKETCH && hll_sample(key, reg, rank)) atomicMax(&sk[reg], rank);
+                r = table_add(tab, g, key, 1u);
+                fresh += (r == ADD_NEW);
             }
             spill_push(sp, ctr, r == ADD_FULL, key, 1u);
         }
