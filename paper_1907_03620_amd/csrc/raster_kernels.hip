@@ -2677,11 +2677,19 @@ __global__ __launch_bounds__(LINK_THREADS, 6) void k_link_census(const Slot* tab
     __shared__ uint32_t lent[kPartSlots];
     __shared__ uint16_t lrank[kPartSlots];  // rank among the partition's significant slots, kNoRank if none
     __shared__ uint16_t list[kPartSlots];   // slot of each rank
+    // parent of each rank: itself (no backward neighbour), the rank of a
+    // parent in this partition, or kFar | the compact index of one outside
+    __shared__ uint32_t lpar[kPartSlots];
+    constexpr uint32_t kFar = 0x80000000u;
     constexpr uint16_t kNoRank = 0xFFFFu;
     const uint32_t s = (uint32_t)ctr[C_SIGNIFICANT];
     const uint64_t parts = 1ull << g.p_log2;
     const uint32_t fine = g.p_log2 - kFrameCoarseLog2;  // >= 1 here
     const uint32_t w = threadIdx.x >> 6;
+    if (ctr[C_SIGNIFICANT] >= kFar) {  // compact indices need 31 bits here; uniform across the grid
+        if (threadIdx.x == 0) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
+        return;
+    }
     const uint64_t lt = lanemask_lt();
     bool bad = false;
     for (uint64_t p = blockIdx.x; p < parts; p += gridDim.x) {
@@ -2726,6 +2734,7 @@ __global__ __launch_bounds__(LINK_THREADS, 6) void k_link_census(const Slot* tab
                 lrank[u] = sig ? (uint16_t)r : kNoRank;
                 if (sig) {
                     list[r] = (uint16_t)u;
+                    lpar[r] = r;
                     const uint64_t i = (uint64_t)poff + r;
                     if (i < s) {
                         if constexpr (IMG)
@@ -2874,7 +2883,25 @@ __global__ __launch_bounds__(LINK_THREADS, 6) void k_link_census(const Slot* tab
             out.z = j[2];
             out.w = j[3];
             reinterpret_cast<uint4*>(nbr)[i] = out;
-            parent[i] = best;
+            lpar[t] = best == i ? t : best - poff < nl ? best - poff : kFar | best;
+        }
+        __syncthreads();
+        // parent = the end of the tile's chain of parents inside the partition
+        // (its root, or the first parent outside), so that the jump pass
+        // only follows the links between partitions
+        for (uint32_t t = threadIdx.x; t < nl; t += LINK_THREADS) {
+            const uint32_t i = poff + t;
+            if (i >= s) continue;
+            uint32_t x = t, v = lpar[t];
+            for (uint32_t step = 0; step < nl && !(v & kFar) && v != x; ++step) {
+                if (v >= nl) {  // never a rank of this partition
+                    bad = true;
+                    break;
+                }
+                x = v;
+                v = lpar[x];
+            }
+            parent[i] = v & kFar ? v & ~kFar : poff + x;
         }
     }
     if (bad) atomicOr(&ctr[C_ERROR], (unsigned long long)kErrInternal);
