@@ -503,16 +503,37 @@ static constexpr int64_t kFrameSample = 1 << 20;
 // each side, fits into 2^20 tiles per axis; otherwise the table stays
 // unframed.  Tuning mode 3 asks for the unframed binning.
 raster_status TableRun::decide_frame(const void* pts, int64_t n, raster_dtype dt) {
+    raster_status st = frame_begin(pts, n, dt);
+    return st != RASTER_OK ? st : frame_end();
+}
+
+// The tile box of the frame sample, copied into the pinned sketch mirror;
+// frame_end waits for it, so that work enqueued in between (a table fill)
+// runs meanwhile.
+raster_status TableRun::frame_begin(const void* pts, int64_t n, raster_dtype dt) {
     frame = Frame{0, 0, 0};
+    frame_box = nullptr;
     if (dims != 2 || tuning.mode == 3 || n <= 0) return RASTER_OK;
-    uint32_t* d = nullptr;
-    HIP_TRY(bufs.take((void**)&d, kBboxWords * sizeof(uint32_t)), "frame box");
-    HIP_TRY(launch_key_bbox(pts, std::min<int64_t>(n, kFrameSample), (int)dt, scale, d, stream), "frame box");
-    uint32_t bb[4] = {1, 0, 1, 0};
-    HIP_TRY(hipMemcpyAsync(bb, d, sizeof bb, hipMemcpyDeviceToHost, stream), "frame box copy");
-    raster_status ws = wait_stream();
-    if (ws != RASTER_OK) return ws;
-    bufs.give_back(d);
+    raster_status st = ensure_sketch();
+    if (st != RASTER_OK) return st;
+    HIP_TRY(bufs.take((void**)&frame_box, kBboxWords * sizeof(uint32_t)), "frame box");
+    HIP_TRY(launch_key_bbox(pts, std::min<int64_t>(n, kFrameSample), (int)dt, scale, frame_box, stream),
+            "frame box");
+    HIP_TRY(hipMemcpyAsync(h_sketch, frame_box, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, stream),
+            "frame box copy");
+    HIP_TRY(hipEventRecord(ev_chunk, stream), "hipEventRecord");
+    return RASTER_OK;
+}
+
+raster_status TableRun::frame_end() {
+    if (!frame_box) return RASTER_OK;
+    hipError_t e;
+    while ((e = hipEventQuery(ev_chunk)) == hipErrorNotReady) std::this_thread::yield();
+    if (e != hipSuccess) return hip_fail(e, "hipEventQuery");
+    uint32_t bb[4];
+    std::memcpy(bb, h_sketch, sizeof bb);
+    bufs.give_back(frame_box);
+    frame_box = nullptr;
     if (bb[0] > bb[1] || bb[2] > bb[3]) return RASTER_OK;
     const int64_t side = (int64_t)1 << kFrameLog2;
     auto origin = [&](uint32_t lo, uint32_t hi, uint32_t* o) {
@@ -839,12 +860,21 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
     if (want > cap && n_points == 0) {
         // nothing inserted yet: a fresh table instead of a rehash and its
         // wait.  The starter table stays held until the run ends, since its
-        // fill may still be running.
+        // fill may still be running.  When the first piece will be binned,
+        // its frame box is taken first and read while the fill runs.
+        const int64_t first = std::min<int64_t>(n, (int64_t)group_budget);
+        const bool first_binned = (tuning.mode >= 2 || (tuning.mode == 0 && (uint64_t)first >= next_pow2(want) / 8)) &&
+                                  binned_geometry(make_geo(next_pow2(want), dims == 3));
+        if (first_binned && !frame_decided && (st = frame_begin(pts, first, dt)) != RASTER_OK) return st;
         Slot* nt = nullptr;
         uint64_t nc = 0;
         if ((st = alloc_table(want, &nt, &nc)) != RASTER_OK) return st;
         tab = nt;
         cap = nc;
+        if (first_binned && !frame_decided) {
+            if ((st = frame_end()) != RASTER_OK) return st;
+            frame_decided = true;
+        }
     } else if (want > cap) {
         st = grow(want, 0, 0);
         if (st != RASTER_OK) {

@@ -149,6 +149,7 @@ struct TableRun {
     // chunk while the table is empty, then fixed for the table's life.
     Frame frame{};
     bool frame_decided = false;
+    uint32_t* frame_box = nullptr;  // tile box of the frame sample, while it is being read
     // binned contraction: coarse and partition lists of 8-byte keys, or of
     // 4-byte entries in a framed table
     uint64_t* bin1 = nullptr;
@@ -182,6 +183,8 @@ struct TableRun {
 
     raster_status alloc_table(uint64_t c, Slot** t, uint64_t* c_out);
     raster_status decide_frame(const void* pts, int64_t n, raster_dtype dt);
+    raster_status frame_begin(const void* pts, int64_t n, raster_dtype dt);
+    raster_status frame_end();
     size_t bin_entry_bytes() const { return frame.on ? sizeof(uint32_t) : sizeof(uint64_t); }
     uint32_t coarse_buckets() const { return frame.on ? kFrameCoarse : kCoarse; }
     Geo geo() const { return make_geo(cap, dims == 3, frame); }
