@@ -451,7 +451,7 @@ raster_status TableRun::size_from_sketch(uint64_t points, bool fetched) {
         // nothing inserted yet: a fresh table, no rehash
         Slot* nt = nullptr;
         uint64_t nc = 0;
-        raster_status st = alloc_table(want, &nt, &nc);
+        raster_status st = alloc_table(want, &nt, &nc, !tab_unfilled);
         if (st != RASTER_OK) return st;
         bufs.give_back(tab);
         tab = nt;
@@ -482,14 +482,52 @@ raster_status TableRun::init(double scale_, uint32_t tau_, uint32_t mu_, int64_t
     hinted = tile_hint > 0;
     const double lf = target_load();
     const uint64_t want = (uint64_t)std::max<double>(4096.0, (double)std::max<int64_t>(tile_hint, 1) / lf);
-    return alloc_table(next_pow2(want), &tab, &cap);
+    // filled when first needed (ensure_filled): the framed binning and a final
+    // update that writes its slice image do without
+    tab_unfilled = true;
+    return alloc_table(next_pow2(want), &tab, &cap, false);
 }
 
-raster_status TableRun::alloc_table(uint64_t c, Slot** t, uint64_t* c_out) {
+raster_status TableRun::alloc_table(uint64_t c, Slot** t, uint64_t* c_out, bool fill) {
     if (c > ((uint64_t)1 << 31)) return fail(RASTER_E_NOMEM, "table of %llu slots is too large", (unsigned long long)c);
     HIP_TRY(bufs.take((void**)t, c * sizeof(Slot)), "tile table");
-    HIP_TRY(launch_fill_table(*t, c, stream), "fill table");
+    if (fill) HIP_TRY(launch_fill_table(*t, c, stream), "fill table");
     *c_out = c;
+    return RASTER_OK;
+}
+
+// Fills a table left unfilled; called before anything reads or writes its
+// slots other than the framed binning (which then gets no table) and a final
+// update that writes its slice image.
+raster_status TableRun::ensure_filled() {
+    if (!tab_unfilled) return RASTER_OK;
+    HIP_TRY(launch_fill_table(tab, cap, stream), "fill table");
+    tab_unfilled = false;
+    return RASTER_OK;
+}
+
+// Keys held in spill buffer 0 while the table was unfilled (tiles outside the
+// key frame, entries past a full list): the table is filled and takes them;
+// what does not fit is left in spill buffer 1 (*src = 1) for a growth.  Its
+// census and slice image, if any, no longer cover every key.
+raster_status TableRun::insert_held(uint64_t* spilled, int* src) {
+    raster_status st = ensure_filled();
+    if (st != RASTER_OK) return st;
+    if (image_cap == cap) {
+        HIP_TRY(launch_image_to_table(img, tab, cap, frame, stream), "image to table");
+        image_cap = 0;
+    }
+    census_cap = 0;
+    if ((st = ensure_spill(1, *spilled)) != RASTER_OK) return st;
+    HIP_TRY(launch_zero_u64((uint64_t*)ctr + C_SPILLED, 1, stream), "reset spill counter");
+    SpillBuf sp{spill_keys[1], spill_counts[1], spill_cap[1]};
+    HIP_TRY(launch_insert_records(spill_keys[0], spill_counts[0], *spilled, tab, cap, sp, ctr, stream, dims == 3,
+                                  frame),
+            "insert held keys");
+    if ((st = pull_counters()) != RASTER_OK) return st;
+    if (h_ctr[C_ERROR] & kErrSpillOverflow) return fail(RASTER_E_DEVICE, "spill buffer overflow");
+    *spilled = h_ctr[C_SPILLED];
+    *src = 1;
     return RASTER_OK;
 }
 
@@ -625,6 +663,8 @@ void TableRun::resolve_spans() {
 // in the (unlikely) case the new table spills again.  Keys waiting in the
 // coarse buckets stay valid: their bucket depends on the key alone.
 raster_status TableRun::grow(uint64_t new_cap, uint64_t pending, int src) {
+    raster_status fs = ensure_filled();
+    if (fs != RASTER_OK) return fs;
     while (true) {
         Slot* nt = nullptr;
         uint64_t nc = 0;
@@ -674,7 +714,15 @@ raster_status TableRun::settle() {
         failed = RASTER_E_DEVICE;
         return fail(RASTER_E_DEVICE, "spill buffer overflow");
     }
-    const uint64_t spilled = h_ctr[C_SPILLED];
+    uint64_t spilled = h_ctr[C_SPILLED];
+    int src = 0;
+    if (spilled > 0 && tab_unfilled) {
+        raster_status st = insert_held(&spilled, &src);
+        if (st != RASTER_OK) {
+            failed = st;
+            return st;
+        }
+    }
     if (spilled > 0 && image_cap == cap) {
         // the last update wrote only its slice image: the table takes the
         // keys before it grows
@@ -684,7 +732,7 @@ raster_status TableRun::settle() {
     if (spilled > 0) {
         const double lf = target_load();
         const uint64_t want = next_pow2((uint64_t)((double)(h_ctr[C_INSERTED] + spilled) / lf) + 1);
-        raster_status st = grow(std::max<uint64_t>(want, cap * 2), spilled, 0);
+        raster_status st = grow(std::max<uint64_t>(want, cap * 2), spilled, src);
         if (st != RASTER_OK) {
             failed = st;
             return st;
@@ -750,6 +798,8 @@ raster_status TableRun::flush(bool census) {
     if (group_points == 0) return RASTER_OK;
     if (image_cap == cap) {
         // an earlier update wrote only its slice image
+        raster_status fs = ensure_filled();
+        if (fs != RASTER_OK) return fs;
         HIP_TRY(launch_image_to_table(img, tab, cap, frame, stream), "image to table");
         image_cap = 0;
     }
@@ -765,6 +815,7 @@ raster_status TableRun::flush(bool census) {
     if (sketch && (st = size_from_sketch(group_points, true)) != RASTER_OK) return st;
     const Geo g = geo();
     SpillBuf sp{spill_keys[0], spill_counts[0], spill_cap[0]};
+    if (((frame.on && !framed_binned_geometry(g)) || !frame.on) && (st = ensure_filled()) != RASTER_OK) return st;
     if (frame.on && !framed_binned_geometry(g)) {
         HIP_TRY(launch_drain_bins_framed(reinterpret_cast<uint32_t*>(bin1), cap1, cursor1, tab, cap, frame, sp, ctr,
                                          stream),
@@ -791,8 +842,8 @@ raster_status TableRun::flush(bool census) {
         if ((st = span_events(&t1)) != RASTER_OK || (st = span_events(&t2)) != RASTER_OK) return st;
         if (frame.on)
             HIP_TRY(launch_bin_keys_framed(reinterpret_cast<uint32_t*>(bin1), cap1, cursor1,
-                                           reinterpret_cast<uint32_t*>(bin2), c2, cursor2, tab, cap, frame, sp, ctr,
-                                           stream, t1),
+                                           reinterpret_cast<uint32_t*>(bin2), c2, cursor2, bin_tab(), cap, frame, sp,
+                                           ctr, stream, t1),
                     "bin keys");
         else
             HIP_TRY(launch_bin_keys(bin1, cap1, cursor1, bin2, c2, cursor2, tab, cap, sp, ctr, stream, dims == 3, t1),
@@ -808,6 +859,8 @@ raster_status TableRun::flush(bool census) {
             census_cap = cap;
             image_cap = cap;
         }
+        // an update that writes the table back needs its empty slots
+        if (!cen.img && (st = ensure_filled()) != RASTER_OK) return st;
         if (frame.on)
             HIP_TRY(launch_aggregate_framed(reinterpret_cast<uint32_t*>(bin2), c2, cursor2, cursor1, tab, cap, frame,
                                             sp, ctr, stream, t2, cen),
@@ -825,7 +878,8 @@ raster_status TableRun::flush(bool census) {
 
 // Whether a chunk of n points can be binned without first waiting for the
 // previous chunk's counters.  Binning writes the table only for keys past a
-// full bucket (spilled into a buffer that holds the whole group), so the
+// full bucket or outside the key frame (or, while the table is unfilled,
+// holds them in the spill buffer, which has room for the whole group), so the
 // counters can only ask for a flush, a growth or a resize, none of which this
 // chunk needs when it fits the group, the bins and the spill buffer as they
 // are.  Errors of the earlier chunks are then reported by a later call.
@@ -868,13 +922,16 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
         if (first_binned && !frame_decided && (st = frame_begin(pts, first, dt)) != RASTER_OK) return st;
         Slot* nt = nullptr;
         uint64_t nc = 0;
-        if ((st = alloc_table(want, &nt, &nc)) != RASTER_OK) return st;
+        if ((st = alloc_table(want, &nt, &nc, false)) != RASTER_OK) return st;
         tab = nt;
         cap = nc;
+        tab_unfilled = true;
         if (first_binned && !frame_decided) {
             if ((st = frame_end()) != RASTER_OK) return st;
             frame_decided = true;
         }
+        // only the framed binning works without the table's slots
+        if (!(first_binned && frame.on) && (st = ensure_filled()) != RASTER_OK) return st;
     } else if (want > cap) {
         st = grow(want, 0, 0);
         if (st != RASTER_OK) {
@@ -899,8 +956,9 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
     const uint64_t bins_expected =
         bin1 ? bin_points : std::min<uint64_t>(group_budget, std::max<uint64_t>(16 * (uint64_t)n, 1u << 20));
     const uint64_t spill_want = group_points + (uint64_t)n + (single_shot ? 0 : bins_expected);
-    st = ensure_spill(0, std::min<uint64_t>(group_budget, spill_want));
-    if (st != RASTER_OK) return st;
+    // a chunk binned without a settle keeps the buffer as it is: it may hold
+    // records of the chunks before it (and has room for this one's)
+    if (!unsettled && (st = ensure_spill(0, std::min<uint64_t>(group_budget, spill_want))) != RASTER_OK) return st;
     bool all_binned = true;
     for (int64_t off = 0; off < n;) {
         const int64_t piece = std::min<int64_t>(n - off, (int64_t)group_budget);
@@ -931,9 +989,10 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
             if ((st = span_events(&t0)) != RASTER_OK) return st;
             // the sketch of the binned keys sizes the table before the flush
             if ((st = ensure_sketch()) != RASTER_OK) return st;
+            if (!frame.on && (st = ensure_filled()) != RASTER_OK) return st;
             if (frame.on)
                 HIP_TRY(launch_bin_points_framed(p, piece, (int)dt, scale, reinterpret_cast<uint32_t*>(bin1), cap1,
-                                                 cursor1, tab, cap, frame, sp, ctr, sketch, stream, t0),
+                                                 cursor1, bin_tab(), cap, frame, sp, ctr, sketch, stream, t0),
                         "bin points");
             else
                 HIP_TRY(launch_bin_points(p, piece, (int)dt, scale, bin1, cap1, cursor1, tab, cap, sp, ctr, sketch,
@@ -950,7 +1009,7 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
                 if ((st = size_from_sketch((uint64_t)piece)) != RASTER_OK) return st;
                 sp = SpillBuf{spill_keys[0], spill_counts[0], spill_cap[0]};
             }
-            if ((st = span_events(&t0)) != RASTER_OK) return st;
+            if ((st = span_events(&t0)) != RASTER_OK || (st = ensure_filled()) != RASTER_OK) return st;
             HIP_TRY(launch_project_count(p, piece, (int)dt, scale, tab, cap, sp, ctr, kernel_tuning(tuning), stream,
                                          (int)dims, frame, t0),
                     "project_count");
@@ -1038,13 +1097,17 @@ raster_status TableRun::finish(raster_result** out) {
               : launch_zero_u64((uint64_t*)ctr + C_DISTINCT, C_COUNT_ - C_DISTINCT, stream);
     if (e == hipSuccess && fused)
         e = launch_zero_u64((uint64_t*)ctr + C_COMPONENTS, C_COUNT_ - C_COMPONENTS, stream);
+    // the link pass reads the slice image when the final update wrote one,
+    // else the table
+    const bool use_img = fused && image_cap == cap;
+    if (!use_img && (st = ensure_filled()) != RASTER_OK) return drop(st);
     if (e == hipSuccess)
         e = fused    ? launch_census_offsets(cap, c_words, c_ptot, ctr, stream)
             : census ? launch_census(tab, cap, frame, jv, tau, square, c_words, partials, ctr, stream)
                      : launch_threshold(tab, jv, s_key, s_count, size, partials, ctr, stream, square ? cap : 0);
     if (e == hipSuccess) e = hipEventRecord(ev[2], stream);
     if (e == hipSuccess)
-        e = census ? launch_link_census(tab, fused && image_cap == cap ? img : nullptr, cap, frame, mu, tau, square,
+        e = census ? launch_link_census(bin_tab(), use_img ? img : nullptr, cap, frame, mu, tau, square,
                                         c_words, s_key, s_count, parent, nbr,
                                         size, m, ctr, stream)
                    : launch_agglomerate(tab, cap, jv, s_key, parent, nbr, size, m, ctr, stream, rounds.data(),
@@ -1103,6 +1166,13 @@ raster_status TableRun::export_tiles(uint64_t* keys, uint32_t* counts, int64_t c
     if (st != RASTER_OK) return st;
     st = flush();
     if (st != RASTER_OK) return st;
+    if (image_cap == cap) {
+        // the last update wrote only its slice image
+        if ((st = ensure_filled()) != RASTER_OK) return st;
+        HIP_TRY(launch_image_to_table(img, tab, cap, frame, stream), "image to table");
+        image_cap = 0;
+    }
+    if ((st = ensure_filled()) != RASTER_OK) return st;
     HIP_TRY(launch_zero_u64((uint64_t*)ctr + C_DISTINCT, 1, stream), "zero counter");
     HIP_TRY(launch_export_tiles(tab, cap, keys, counts, (uint64_t)std::max<int64_t>(cap_rows, 0), partials, ctr,
                                 stream),

@@ -995,7 +995,8 @@ __global__ __launch_bounds__(AGG_THREADS, 6) void k_aggregate(const uint64_t* __
 // buckets (the top 8 bits of h) and work tiles of kFBinTile points; level 2
 // splits each coarse list by the next bits of h, which are the top bits of
 // the entry, so it needs no hashing.  Keys outside the frame, and entries past
-// a full list, go straight into the table.
+// a full list, go straight into the table, or into the spill buffer while the
+// table is not filled yet (tab == nullptr).
 
 // Points per thread of the framed level 1.  16 (an 8192-point tile, three
 // workgroups per CU) and 8 (a 4096-point tile, four per CU) measure the same;
@@ -1083,7 +1084,7 @@ __device__ void fbin_tile(Scratch& S, const uint32_t (&ent)[ITEMS], const uint16
                 out[(uint64_t)b * stride + dst] = e;
             } else {
                 k = frame_key(L1 ? b : cb, e, g.fx, g.fy);
-                r = table_add(tab, g, k, 1u);
+                r = tab ? table_add(tab, g, k, 1u) : ADD_FULL;
                 fresh += (r == ADD_NEW);
             }
         }
@@ -1161,7 +1162,8 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_points_f(const T* __restric
                 (void)tile_key(x, y, scale, key);  // in range: checked above
                 uint32_t reg, rank;
                 if (SKETCH && hll_sample(key, reg, rank)) atomicMax(&sk[reg], rank);
-                r = table_add(tab, g, key, 1u);
+                // no table yet (not filled): the key waits in the spill buffer
+                r = tab ? table_add(tab, g, key, 1u) : ADD_FULL;
                 fresh += (r == ADD_NEW);
             }
             spill_push(sp, ctr, r == ADD_FULL, key, 1u);
@@ -2668,7 +2670,8 @@ __device__ __forceinline__ uint32_t census_index(uint2 r, uint64_t pos) {
 // device-table probes.  With IMG the slices come from the image the final
 // update wrote (entry and count per slot, 8 bytes instead of 16), and so do
 // the probes for neighbours inside the frame; keys outside the frame are
-// still found in the table.
+// still found in the table.  A null table (never filled: every key went
+// through the binning into the image) holds no such keys.
 template <bool SQUARE, bool IMG>
 __global__ __launch_bounds__(LINK_THREADS, 6) void k_link_census(const Slot* tab, const uint2* img, const Geo g,
                                                               uint32_t tau, const uint2* rec, uint64_t* s_key,
@@ -2844,8 +2847,10 @@ __global__ __launch_bounds__(LINK_THREADS, 6) void k_link_census(const Slot* tab
                         if ((pos[q] >> kCensusRecLog2) != (home >> kCensusRecLog2)) r = rec[pos[q] >> kCensusRecLog2];
                         if ((r.x >> (pos[q] & 31)) & 1u) j[q] = census_index(r, pos[q]);
                     }
-                } else {
-                    // keys outside the frame (IMG: not loaded ahead) are in the table
+                } else if (!IMG || tab) {
+                    // keys outside the frame (IMG: not loaded ahead) are in the
+                    // table; with the image and no table (never filled) there
+                    // are none
                     const uint64_t home = pos[q];
                     uint64_t ck = IMG ? tab[pos[q]].key : k0[IMG ? 0 : q];
                     if (ck != nk[q] && ck != kEmptyKey) {

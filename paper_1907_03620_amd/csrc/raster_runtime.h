@@ -127,6 +127,11 @@ struct TableRun {
     Buffers bufs;
     Slot* tab = nullptr;
     uint64_t cap = 0;
+    // A stream's first table is filled only when something needs its slots:
+    // until then the framed binning hands it no table (keys it would insert
+    // directly wait in the spill buffer), and a final update that writes its
+    // slice image leaves it untouched.
+    bool tab_unfilled = false;
     unsigned long long* ctr = nullptr;    // device counters
     unsigned long long* h_ctr = nullptr;  // pinned host mirror
     uint32_t* partials = nullptr;
@@ -181,7 +186,10 @@ struct TableRun {
     raster_status finish(raster_result** out);
     raster_status export_tiles(uint64_t* keys, uint32_t* counts, int64_t cap_rows, int64_t* m);
 
-    raster_status alloc_table(uint64_t c, Slot** t, uint64_t* c_out);
+    raster_status alloc_table(uint64_t c, Slot** t, uint64_t* c_out, bool fill = true);
+    raster_status ensure_filled();
+    Slot* bin_tab() const { return tab_unfilled ? nullptr : tab; }
+    raster_status insert_held(uint64_t* spilled, int* src);
     raster_status decide_frame(const void* pts, int64_t n, raster_dtype dt);
     raster_status frame_begin(const void* pts, int64_t n, raster_dtype dt);
     raster_status frame_end();
