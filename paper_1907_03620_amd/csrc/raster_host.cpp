@@ -482,8 +482,9 @@ raster_status TableRun::init(double scale_, uint32_t tau_, uint32_t mu_, int64_t
     hinted = tile_hint > 0;
     const double lf = target_load();
     const uint64_t want = (uint64_t)std::max<double>(4096.0, (double)std::max<int64_t>(tile_hint, 1) / lf);
-    // filled when first needed (ensure_filled): the framed binning and a final
-    // update that writes its slice image do without
+    // not filled here: the binning does without, and the first update fills
+    // it by writing whole slices (or leaves it alone when it writes its slice
+    // image); anything else calls ensure_filled first
     tab_unfilled = true;
     return alloc_table(next_pow2(want), &tab, &cap, false);
 }
@@ -497,8 +498,8 @@ raster_status TableRun::alloc_table(uint64_t c, Slot** t, uint64_t* c_out, bool 
 }
 
 // Fills a table left unfilled; called before anything reads or writes its
-// slots other than the framed binning (which then gets no table) and a final
-// update that writes its slice image.
+// slots other than the binning (which then gets no table) and the update
+// (which writes whole slices, or only its slice image).
 raster_status TableRun::ensure_filled() {
     if (!tab_unfilled) return RASTER_OK;
     HIP_TRY(launch_fill_table(tab, cap, stream), "fill table");
@@ -815,7 +816,10 @@ raster_status TableRun::flush(bool census) {
     if (sketch && (st = size_from_sketch(group_points, true)) != RASTER_OK) return st;
     const Geo g = geo();
     SpillBuf sp{spill_keys[0], spill_counts[0], spill_cap[0]};
-    if (((frame.on && !framed_binned_geometry(g)) || !frame.on) && (st = ensure_filled()) != RASTER_OK) return st;
+    // the drains insert straight into the table
+    if (((frame.on && !framed_binned_geometry(g)) || (!frame.on && !binned_geometry(g))) &&
+        (st = ensure_filled()) != RASTER_OK)
+        return st;
     if (frame.on && !framed_binned_geometry(g)) {
         HIP_TRY(launch_drain_bins_framed(reinterpret_cast<uint32_t*>(bin1), cap1, cursor1, tab, cap, frame, sp, ctr,
                                          stream),
@@ -846,7 +850,8 @@ raster_status TableRun::flush(bool census) {
                                            ctr, stream, t1),
                     "bin keys");
         else
-            HIP_TRY(launch_bin_keys(bin1, cap1, cursor1, bin2, c2, cursor2, tab, cap, sp, ctr, stream, dims == 3, t1),
+            HIP_TRY(launch_bin_keys(bin1, cap1, cursor1, bin2, c2, cursor2, bin_tab(), cap, sp, ctr, stream, dims == 3,
+                                    t1),
                     "bin keys");
         span_done(1, t1);
         AggCensus cen;
@@ -859,14 +864,16 @@ raster_status TableRun::flush(bool census) {
             census_cap = cap;
             image_cap = cap;
         }
-        // an update that writes the table back needs its empty slots
-        if (!cen.img && (st = ensure_filled()) != RASTER_OK) return st;
+        // an update that writes the table back into a table not filled yet
+        // writes whole slices, which fills it
+        const bool whole = tab_unfilled && !cen.img;
         if (frame.on)
             HIP_TRY(launch_aggregate_framed(reinterpret_cast<uint32_t*>(bin2), c2, cursor2, cursor1, tab, cap, frame,
-                                            sp, ctr, stream, t2, cen),
+                                            sp, ctr, stream, t2, cen, whole),
                     "aggregate");
         else
-            HIP_TRY(launch_aggregate(bin2, c2, cursor2, cursor1, tab, cap, sp, ctr, stream, t2), "aggregate");
+            HIP_TRY(launch_aggregate(bin2, c2, cursor2, cursor1, tab, cap, sp, ctr, stream, t2, whole), "aggregate");
+        if (whole) tab_unfilled = false;
         span_done(2, t2);
     }
     flushes += 1;
@@ -930,8 +937,6 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
             if ((st = frame_end()) != RASTER_OK) return st;
             frame_decided = true;
         }
-        // only the framed binning works without the table's slots
-        if (!(first_binned && frame.on) && (st = ensure_filled()) != RASTER_OK) return st;
     } else if (want > cap) {
         st = grow(want, 0, 0);
         if (st != RASTER_OK) {
@@ -989,14 +994,13 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
             if ((st = span_events(&t0)) != RASTER_OK) return st;
             // the sketch of the binned keys sizes the table before the flush
             if ((st = ensure_sketch()) != RASTER_OK) return st;
-            if (!frame.on && (st = ensure_filled()) != RASTER_OK) return st;
             if (frame.on)
                 HIP_TRY(launch_bin_points_framed(p, piece, (int)dt, scale, reinterpret_cast<uint32_t*>(bin1), cap1,
                                                  cursor1, bin_tab(), cap, frame, sp, ctr, sketch, stream, t0),
                         "bin points");
             else
-                HIP_TRY(launch_bin_points(p, piece, (int)dt, scale, bin1, cap1, cursor1, tab, cap, sp, ctr, sketch,
-                                          stream, (int)dims, t0),
+                HIP_TRY(launch_bin_points(p, piece, (int)dt, scale, bin1, cap1, cursor1, bin_tab(), cap, sp, ctr,
+                                          sketch, stream, (int)dims, t0),
                         "bin points");
             span_done(0, t0);
             group_points += (uint64_t)piece;

@@ -284,11 +284,12 @@ struct AggCensus {
     uint2* img = nullptr;
 };
 // Update: one workgroup per partition adds its entries to the table in LDS;
-// then clears cursor1.
+// then clears cursor1.  With `whole` (a table not filled yet, holding no key)
+// every slot is written, the empty ones too, which fills the table.
 hipError_t launch_aggregate_framed(const uint32_t* bin2, uint64_t cap2, const uint32_t* cursor2, uint32_t* cursor1,
                                   Slot* tab, uint64_t cap, Frame frame, SpillBuf spill, unsigned long long* ctr,
                                   hipStream_t stream, const KernelSpan& span = KernelSpan{},
-                                  const AggCensus& census = AggCensus{});
+                                  const AggCensus& census = AggCensus{}, bool whole = false);
 hipError_t launch_census_offsets(uint64_t cap, uint32_t* words, uint32_t* ptotal, unsigned long long* ctr,
                                  hipStream_t stream);
 // Direct insertion of every entry held in the coarse lists (tables outside
@@ -298,7 +299,8 @@ hipError_t launch_drain_bins_framed(const uint32_t* bin1, uint64_t cap1, uint32_
 
 // Binned contraction, level 1: project n points and append each key to its
 // coarse bucket: bucket b holds keys at bin1[b * cap1 + i], i < cursor1[b].
-// Keys past a bucket's capacity go straight into the table.
+// Keys past a bucket's capacity go straight into the table, or into the
+// spill buffer when tab is null (a table not filled yet); so in level 2.
 // hll, if not null, gets the distinct-tile sketch of the keys (kHllReps
 // replicas of 2^kHllLog2 registers; merge them by maximum).
 hipError_t launch_bin_points(const void* pts, int64_t n, int dtype, double scale, uint64_t* bin1, uint64_t cap1,
@@ -312,9 +314,10 @@ hipError_t launch_bin_keys(const uint64_t* bin1, uint64_t cap1, const uint32_t* 
                            const KernelSpan& span = KernelSpan{});
 // Binned contraction, update: one workgroup per partition adds that
 // partition's keys to the table in LDS; then clears cursor1 for the next group.
+// `whole` as for launch_aggregate_framed.
 hipError_t launch_aggregate(const uint64_t* bin2, uint64_t cap2, const uint32_t* cursor2, uint32_t* cursor1,
                             Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream,
-                            const KernelSpan& span = KernelSpan{});
+                            const KernelSpan& span = KernelSpan{}, bool whole = false);
 // Direct insertion of everything held in the coarse buckets (used when the
 // table is outside the binned geometry).  Clears cursor1.
 hipError_t launch_drain_bins(uint64_t* bin1, uint64_t cap1, uint32_t* cursor1, Slot* tab, uint64_t cap,

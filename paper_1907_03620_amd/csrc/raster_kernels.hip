@@ -689,7 +689,8 @@ __device__ void bin_tile(BinScratch& S, const uint64_t (&key)[BIN_ITEMS], const 
             if (dst < cap) {
                 out[(uint64_t)b * stride + dst] = k;
             } else {
-                r = table_add(tab, g, k, 1u);
+                // no table yet (not filled): the key waits in the spill buffer
+                r = tab ? table_add(tab, g, k, 1u) : ADD_FULL;
                 fresh += (r == ADD_NEW);
             }
         }
@@ -876,11 +877,13 @@ struct PartLists {
 
 // Adds the L.total keys of the lists L to one 4096-slot partition through LDS.
 // With load false the table holds no key yet, and the slice starts empty
-// without being read.
+// without being read.  With whole (a table not filled yet) every slot of the
+// slice is written, the empty ones too.
 template <int NL>
 __device__ __forceinline__ void aggregate_partition(const PartLists<NL>& L, Slot* part, bool load, uint64_t* lkey,
                                                     uint32_t* lcnt, const SpillBuf& sp,
-                                                    unsigned long long* spill_ctr, uint32_t& fresh) {
+                                                    unsigned long long* spill_ctr, uint32_t& fresh,
+                                                    bool whole = false) {
     constexpr int PER = (int)kPartSlots / AGG_THREADS;
     const uint32_t cnt = L.total;
     if (load) {
@@ -961,10 +964,10 @@ __device__ __forceinline__ void aggregate_partition(const PartLists<NL>& L, Slot
     for (int u = 0; u < PER; ++u) {
         const uint32_t s = u * AGG_THREADS + threadIdx.x;
         const uint64_t k = lkey[s];
-        if (k != kEmptyKey) {
+        if (whole || k != kEmptyKey) {
             Slot v;
             v.key = k;
-            v.count = lcnt[s];
+            v.count = lcnt[s];  // 0 in an empty slot
             v.aux = kNotSignificant;
             part[s] = v;
         }
@@ -974,17 +977,20 @@ __device__ __forceinline__ void aggregate_partition(const PartLists<NL>& L, Slot
 // At least 6 waves per SIMD: the LDS slice allows three workgroups of 8 waves
 // per CU, and this holds the registers (the next batch's keys included) to
 // what three need.
+// With whole (a table not filled yet: no key in it) every workgroup writes
+// its whole slice, which fills the table.
 __global__ __launch_bounds__(AGG_THREADS, 6) void k_aggregate(const uint64_t* __restrict__ bin2, uint64_t cap2,
                                                            const uint32_t* cursor2, Slot* tab, SpillBuf sp,
-                                                           unsigned long long* ctr) {
+                                                           unsigned long long* ctr, bool whole) {
     __shared__ uint64_t lkey[kPartSlots];
     __shared__ uint32_t lcnt[kPartSlots];
     const uint64_t p = blockIdx.x;
     const uint64_t parts = gridDim.x;
     const PartLists<kBinRep> L(bin2 + p * kBinRep * cap2, cap2, cursor2 + p, parts, cap2);
-    if (L.total == 0) return;  // uniform across the workgroup
+    if (L.total == 0 && !whole) return;  // uniform across the workgroup
     uint32_t fresh = 0;
-    aggregate_partition(L, tab + (p << kPartLog2), ctr[C_TABLE_KEYS] != 0, lkey, lcnt, sp, ctr, fresh);
+    aggregate_partition(L, tab + (p << kPartLog2), !whole && ctr[C_TABLE_KEYS] != 0, lkey, lcnt, sp, ctr, fresh,
+                        whole);
     add_fresh(ctr, fresh);
 }
 
@@ -1267,7 +1273,7 @@ constexpr uint64_t kClaimed = 1ull << 32, kForeign = 2ull << 32;
 
 __device__ __forceinline__ void aggregate_entries(const PartEntries<kBinRep>& L, Slot* part, uint32_t cb, const Geo& g,
                                                   bool load, FAggLds& A, const SpillBuf& sp, unsigned long long* ctr,
-                                                  uint32_t& fresh) {
+                                                  uint32_t& fresh, bool whole) {
     constexpr int PER = (int)kPartSlots / AGG_THREADS;
     if (load) {
         Slot v[PER];
@@ -1364,10 +1370,10 @@ __device__ __forceinline__ void aggregate_entries(const PartEntries<kBinRep>& L,
     for (int u = 0; u < PER; ++u) {
         const uint32_t sl = u * AGG_THREADS + threadIdx.x;
         const uint64_t w = A.word[sl];
-        if ((w >> 32) == 1) {
+        if ((w >> 32) == 1 || (whole && w == 0)) {
             Slot v;
-            v.key = frame_key(cb, (uint32_t)w, g.fx, g.fy);
-            v.count = A.cnt[sl];
+            v.key = w ? frame_key(cb, (uint32_t)w, g.fx, g.fy) : kEmptyKey;
+            v.count = A.cnt[sl];  // 0 in an empty slot
             v.aux = kNotSignificant;
             part[sl] = v;
         }
@@ -1376,16 +1382,16 @@ __device__ __forceinline__ void aggregate_entries(const PartEntries<kBinRep>& L,
 
 __global__ __launch_bounds__(AGG_THREADS, 6) void k_aggregate_f(const uint32_t* __restrict__ bin2, uint64_t cap2,
                                                                 const uint32_t* cursor2, Slot* tab, const Geo g,
-                                                                SpillBuf sp, unsigned long long* ctr) {
+                                                                SpillBuf sp, unsigned long long* ctr, bool whole) {
     __shared__ FAggLds A;
     const uint64_t p = blockIdx.x;
     const uint64_t parts = gridDim.x;
     const PartEntries<kBinRep> L(bin2 + p * kBinRep * cap2, cap2, cursor2 + p, parts, cap2);
-    if (L.total == 0) return;  // uniform across the workgroup
+    if (L.total == 0 && !whole) return;  // uniform across the workgroup
     Slot* part = tab + (p << kPartLog2);
     const uint32_t cb = (uint32_t)(p >> (g.p_log2 - kFrameCoarseLog2));
     uint32_t fresh = 0;
-    aggregate_entries(L, part, cb, g, ctr[C_TABLE_KEYS] != 0, A, sp, ctr, fresh);
+    aggregate_entries(L, part, cb, g, !whole && ctr[C_TABLE_KEYS] != 0, A, sp, ctr, fresh, whole);
     add_fresh(ctr, fresh);
 }
 
@@ -1412,13 +1418,13 @@ struct FAggLds32 {
 __global__ __launch_bounds__(AGG_THREADS, 8) void k_aggregate_f32(const uint32_t* __restrict__ bin2, uint64_t cap2,
                                                                   const uint32_t* cursor2, Slot* tab, const Geo g,
                                                                   SpillBuf sp, unsigned long long* ctr,
-                                                                  AggCensus cen) {
+                                                                  AggCensus cen, bool whole) {
     __shared__ FAggLds32 A;
     const uint64_t p = blockIdx.x;
     const uint64_t parts = gridDim.x;
     const PartEntries<kBinRep> L(bin2 + p * kBinRep * cap2, cap2, cursor2 + p, parts, cap2);
-    if (L.total == 0 && !cen.rec) return;  // uniform across the workgroup
-    const bool load = ctr[C_TABLE_KEYS] != 0;
+    if (L.total == 0 && !cen.rec && !whole) return;  // uniform across the workgroup
+    const bool load = !whole && ctr[C_TABLE_KEYS] != 0;
     Slot* part = tab + (p << kPartLog2);
     const uint32_t fine = g.p_log2 - kFrameCoarseLog2;  // >= 1 here
     const uint32_t cb = (uint32_t)(p >> fine);
@@ -1566,9 +1572,10 @@ __global__ __launch_bounds__(AGG_THREADS, 8) void k_aggregate_f32(const uint32_t
             // the final update writes the slice image (the table itself only
             // if keys spill afterwards: k_image_to_table)
             cen.img[(p << kPartLog2) + sl] = make_uint2(e, c);
-        } else if (L.total && e != kEmpty && e != kAlien) {
+        } else if ((L.total && e != kEmpty && e != kAlien) || (whole && e == kEmpty)) {
+            // (whole: a table not filled yet takes every slot, the empty ones too)
             Slot v;
-            v.key = frame_key(cb, e, g.fx, g.fy);
+            v.key = e != kEmpty ? frame_key(cb, e, g.fx, g.fy) : kEmptyKey;
             v.count = c;
             v.aux = kNotSignificant;
             part[sl] = v;
@@ -3725,13 +3732,13 @@ hipError_t launch_bin_keys(const uint64_t* bin1, uint64_t cap1, const uint32_t* 
 
 hipError_t launch_aggregate(const uint64_t* bin2, uint64_t cap2, const uint32_t* cursor2, uint32_t* cursor1,
                             Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream,
-                            const KernelSpan& span) {
+                            const KernelSpan& span, bool whole) {
     const Geo g = make_geo(cap);  // the update only needs the partition count
     if (!binned_geometry(g)) return hipErrorInvalidValue;
     const uint64_t parts = 1ull << g.p_log2;
     hipLaunchKernelGGL(k_snapshot_keys, dim3(1), dim3(64), 0, stream, ctr);
     launch_k(k_aggregate, dim3((unsigned)parts), dim3(AGG_THREADS), 0u, stream, span, bin2, cap2, cursor2, tab, spill,
-             ctr);
+             ctr, whole);
     hipLaunchKernelGGL(k_zero_u32, dim3(4), dim3(256), 0, stream, cursor1, (uint64_t)kBinRep * kCoarse);
     return hipGetLastError();
 }
@@ -3814,19 +3821,20 @@ hipError_t launch_bin_keys_framed(const uint32_t* bin1, uint64_t cap1, const uin
 
 hipError_t launch_aggregate_framed(const uint32_t* bin2, uint64_t cap2, const uint32_t* cursor2, uint32_t* cursor1,
                                   Slot* tab, uint64_t cap, Frame frame, SpillBuf spill, unsigned long long* ctr,
-                                  hipStream_t stream, const KernelSpan& span, const AggCensus& census) {
+                                  hipStream_t stream, const KernelSpan& span, const AggCensus& census, bool whole) {
     const Geo g = make_geo(cap, false, frame);
     if (!framed_binned_geometry(g)) return hipErrorInvalidValue;
     if (census.rec && g.p_log2 <= kFrameCoarseLog2) return hipErrorInvalidValue;
+    if (whole && census.img) return hipErrorInvalidValue;  // the image form does not write the table
     const uint64_t parts = 1ull << g.p_log2;
     hipLaunchKernelGGL(k_snapshot_keys, dim3(1), dim3(64), 0, stream, ctr);
     if (census.rec) (void)launch_zero_u64(reinterpret_cast<uint64_t*>(ctr) + C_DISTINCT, C_SUM - C_DISTINCT + 1, stream);
     if (g.p_log2 > kFrameCoarseLog2)
         launch_k(k_aggregate_f32, dim3((unsigned)parts), dim3(AGG_THREADS), 0u, stream, span, bin2, cap2, cursor2, tab,
-                 g, spill, ctr, census);
+                 g, spill, ctr, census, whole);
     else
         launch_k(k_aggregate_f, dim3((unsigned)parts), dim3(AGG_THREADS), 0u, stream, span, bin2, cap2, cursor2, tab, g,
-                 spill, ctr);
+                 spill, ctr, whole);
     hipLaunchKernelGGL(k_zero_u32, dim3(8), dim3(256), 0, stream, cursor1, (uint64_t)kBinRep * kFrameCoarse);
     return hipGetLastError();
 }

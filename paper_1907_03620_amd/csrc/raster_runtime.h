@@ -127,10 +127,10 @@ struct TableRun {
     Buffers bufs;
     Slot* tab = nullptr;
     uint64_t cap = 0;
-    // A stream's first table is filled only when something needs its slots:
-    // until then the framed binning hands it no table (keys it would insert
-    // directly wait in the spill buffer), and a final update that writes its
-    // slice image leaves it untouched.
+    // A new table is filled only when something needs its slots: until then
+    // the binning gets no table (keys it would insert directly wait in the
+    // spill buffer), the first update writes whole slices, which fills it, and
+    // a final update that writes its slice image leaves it untouched.
     bool tab_unfilled = false;
     unsigned long long* ctr = nullptr;    // device counters
     unsigned long long* h_ctr = nullptr;  // pinned host mirror
