@@ -547,8 +547,8 @@ raster_status TableRun::decide_frame(const void* pts, int64_t n, raster_dtype dt
 }
 
 // The tile box of the frame sample, copied into the pinned sketch mirror;
-// frame_end waits for it, so that work enqueued in between (a table fill)
-// runs meanwhile.
+// frame_end waits for it, so that host work in between (the table's
+// allocation) overlaps the copy.
 raster_status TableRun::frame_begin(const void* pts, int64_t n, raster_dtype dt) {
     frame = Frame{0, 0, 0};
     frame_box = nullptr;
@@ -919,10 +919,10 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
         want = next_pow2((uint64_t)(2.0 * (double)h_ctr[C_INSERTED] / lf));
     }
     if (want > cap && n_points == 0) {
-        // nothing inserted yet: a fresh table instead of a rehash and its
-        // wait.  The starter table stays held until the run ends, since its
-        // fill may still be running.  When the first piece will be binned,
-        // its frame box is taken first and read while the fill runs.
+        // nothing inserted yet: a fresh table (not filled: see tab_unfilled)
+        // instead of a rehash and its wait.  The starter table stays held
+        // until the run ends.  When the first piece will be binned, its frame
+        // box is taken first and read after the allocation.
         const int64_t first = std::min<int64_t>(n, (int64_t)group_budget);
         const bool first_binned = (tuning.mode >= 2 || (tuning.mode == 0 && (uint64_t)first >= next_pow2(want) / 8)) &&
                                   binned_geometry(make_geo(next_pow2(want), dims == 3));
