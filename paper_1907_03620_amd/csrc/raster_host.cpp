@@ -519,6 +519,7 @@ raster_status TableRun::insert_held(uint64_t* spilled, int* src) {
         image_cap = 0;
     }
     census_cap = 0;
+    counted_cap = 0;
     if ((st = ensure_spill(1, *spilled)) != RASTER_OK) return st;
     HIP_TRY(launch_zero_u64((uint64_t*)ctr + C_SPILLED, 1, stream), "reset spill counter");
     SpillBuf sp{spill_keys[1], spill_counts[1], spill_cap[1]};
@@ -793,9 +794,12 @@ raster_status TableRun::ensure_census(uint64_t c) {
 
 // Updates the table with the binned group.  With `census`, a final update
 // of a table of 512+ partitions also takes the census of the significant
-// slots (valid while the table keeps its size: census_cap).
-raster_status TableRun::flush(bool census) {
+// slots (valid while the table keeps its size: census_cap); with `count`, a
+// final update of an unframed table does the significance scan's counting
+// pass (counted_cap).
+raster_status TableRun::flush(bool census, bool count) {
     census_cap = 0;
+    counted_cap = 0;
     if (group_points == 0) return RASTER_OK;
     if (image_cap == cap) {
         // an earlier update wrote only its slice image
@@ -871,8 +875,17 @@ raster_status TableRun::flush(bool census) {
             HIP_TRY(launch_aggregate_framed(reinterpret_cast<uint32_t*>(bin2), c2, cursor2, cursor1, tab, cap, frame,
                                             sp, ctr, stream, t2, cen, whole),
                     "aggregate");
-        else
-            HIP_TRY(launch_aggregate(bin2, c2, cursor2, cursor1, tab, cap, sp, ctr, stream, t2, whole), "aggregate");
+        else {
+            AggCount cnt;
+            if (count) {
+                cnt.partials = partials;
+                cnt.tau = tau;
+                cnt.blk_shift = scan_block_shift(cap);
+                counted_cap = cap;
+            }
+            HIP_TRY(launch_aggregate(bin2, c2, cursor2, cursor1, tab, cap, sp, ctr, stream, t2, whole, cnt),
+                    "aggregate");
+        }
         if (whole) tab_unfilled = false;
         span_done(2, t2);
     }
@@ -1033,11 +1046,13 @@ raster_status TableRun::finish(raster_result** out) {
     const bool census_path = dims == 2 && rounds.empty();
     // a flush waits for the work before it itself; the final update takes
     // the census with it unless the 2x2 post-step changes significance after
-    raster_status st = group_points > 0 ? flush(census_path && !square) : settle();
+    raster_status st = group_points > 0 ? flush(census_path && !square, !square) : settle();
     if (st != RASTER_OK) return st;
     // a growth after the update (spilled entries) leaves its census stale
     const bool census = census_path && census_geometry(cap, frame);
     const bool fused = census && census_cap == cap;
+    // (or, unframed, its counting pass)
+    const bool counted = !census && !square && counted_cap == cap;
     if (!timing_started) {
         HIP_TRY(hipEventRecord(ev[0], stream), "hipEventRecord");
         timing_started = true;
@@ -1108,7 +1123,7 @@ raster_status TableRun::finish(raster_result** out) {
     if (e == hipSuccess)
         e = fused    ? launch_census_offsets(cap, c_words, c_ptot, ctr, stream)
             : census ? launch_census(tab, cap, frame, jv, tau, square, c_words, partials, ctr, stream)
-                     : launch_threshold(tab, jv, s_key, s_count, size, partials, ctr, stream, square ? cap : 0);
+                     : launch_threshold(tab, jv, s_key, s_count, size, partials, ctr, stream, square ? cap : 0, counted);
     if (e == hipSuccess) e = hipEventRecord(ev[2], stream);
     if (e == hipSuccess)
         e = census ? launch_link_census(bin_tab(), use_img ? img : nullptr, cap, frame, mu, tau, square,

@@ -274,6 +274,18 @@ hipError_t launch_bin_keys_framed(const uint32_t* bin1, uint64_t cap1, const uin
 // (ptotal), and the occupied slots and count sum (ctr[C_DISTINCT],
 // ctr[C_SUM], cleared first).  launch_census_offsets then makes the counts
 // global, as launch_census leaves them.
+// The final update of an unframed table can do the significance scan's
+// counting pass: each workgroup adds its partition's slots with count >= tau
+// to partials[p >> blk_shift] (the scan block holding the partition: blocks
+// are whole partitions for any table of 4096 * 2^k slots; cleared first).
+// The scatter pass then totals the occupied slots and their counts.
+struct AggCount {
+    uint32_t* partials = nullptr;  // kScanBlocks words; null: no counting
+    uint32_t tau = 0;
+    uint32_t blk_shift = 0;
+};
+uint32_t scan_block_shift(uint64_t cap);
+
 struct AggCensus {
     uint2* rec = nullptr;
     uint32_t* ptotal = nullptr;
@@ -317,7 +329,8 @@ hipError_t launch_bin_keys(const uint64_t* bin1, uint64_t cap1, const uint32_t* 
 // `whole` as for launch_aggregate_framed.
 hipError_t launch_aggregate(const uint64_t* bin2, uint64_t cap2, const uint32_t* cursor2, uint32_t* cursor1,
                             Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream,
-                            const KernelSpan& span = KernelSpan{}, bool whole = false);
+                            const KernelSpan& span = KernelSpan{}, bool whole = false,
+                            const AggCount& count = AggCount{});
 // Direct insertion of everything held in the coarse buckets (used when the
 // table is outside the binned geometry).  Clears cursor1.
 hipError_t launch_drain_bins(uint64_t* bin1, uint64_t cap1, uint32_t* cursor1, Slot* tab, uint64_t cap,
@@ -342,9 +355,13 @@ hipError_t launch_export_tiles(const Slot* tab, uint64_t tcap, uint64_t* keys, u
 // Significance scan: flags count >= tau (per job), writes the compact arrays
 // S_key, S_count (and S_job for several jobs), sets slot.aux, zeroes size[i],
 // and fills ctr[C_DISTINCT], ctr[C_SIGNIFICANT], ctr[C_SUM] (per job too).
+// With `counted` (one job, no 2x2 step) the final update has already counted
+// the significant slots per scan block into partials (AggCount): the
+// counting pass is skipped, and the scatter pass fills ctr[C_DISTINCT] and
+// ctr[C_SUM] (cleared by the caller).
 hipError_t launch_threshold(Slot* tab, const JobView& jv, uint64_t* s_key, uint32_t* s_count, uint32_t* size,
                             uint32_t* partials, unsigned long long* ctr, hipStream_t stream,
-                            uint64_t square_cap = 0);
+                            uint64_t square_cap = 0, bool counted = false);
 
 // Connected components of the significant tiles (8-adjacency).  On return
 // nbr[i] (its first s words) holds the compact index of the smallest tile of

@@ -152,6 +152,21 @@ __device__ __forceinline__ void block_count_add64(unsigned long long* ctr, unsig
     }
 }
 
+// The same for a 32-bit word.
+__device__ __forceinline__ void block_count_add32(uint32_t* dst, uint32_t v) {
+    __shared__ uint32_t part32[16];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane_id() == 0) part32[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int i = 0; i < (int)((blockDim.x + 63) >> 6); ++i) t += part32[i];
+        if (t) atomicAdd(dst, t);
+    }
+}
+
 __device__ __forceinline__ void block_count_add(unsigned long long* ctr, uint32_t v) {
     __shared__ uint32_t part[16];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -878,12 +893,13 @@ struct PartLists {
 // Adds the L.total keys of the lists L to one 4096-slot partition through LDS.
 // With load false the table holds no key yet, and the slice starts empty
 // without being read.  With whole (a table not filled yet) every slot of the
-// slice is written, the empty ones too.
+// slice is written, the empty ones too; with write false (no entries: the
+// slice was read only to be counted) none is.
 template <int NL>
 __device__ __forceinline__ void aggregate_partition(const PartLists<NL>& L, Slot* part, bool load, uint64_t* lkey,
                                                     uint32_t* lcnt, const SpillBuf& sp,
                                                     unsigned long long* spill_ctr, uint32_t& fresh,
-                                                    bool whole = false) {
+                                                    bool whole = false, bool write = true) {
     constexpr int PER = (int)kPartSlots / AGG_THREADS;
     const uint32_t cnt = L.total;
     if (load) {
@@ -964,7 +980,7 @@ __device__ __forceinline__ void aggregate_partition(const PartLists<NL>& L, Slot
     for (int u = 0; u < PER; ++u) {
         const uint32_t s = u * AGG_THREADS + threadIdx.x;
         const uint64_t k = lkey[s];
-        if (whole || k != kEmptyKey) {
+        if (write && (whole || k != kEmptyKey)) {
             Slot v;
             v.key = k;
             v.count = lcnt[s];  // 0 in an empty slot
@@ -978,20 +994,35 @@ __device__ __forceinline__ void aggregate_partition(const PartLists<NL>& L, Slot
 // per CU, and this holds the registers (the next batch's keys included) to
 // what three need.
 // With whole (a table not filled yet: no key in it) every workgroup writes
-// its whole slice, which fills the table.
+// its whole slice, which fills the table.  With cn.partials (the final
+// update) every workgroup also counts its partition for the significance
+// scan (AggCount), reading the slice even when it got no entries.
 __global__ __launch_bounds__(AGG_THREADS, 6) void k_aggregate(const uint64_t* __restrict__ bin2, uint64_t cap2,
                                                            const uint32_t* cursor2, Slot* tab, SpillBuf sp,
-                                                           unsigned long long* ctr, bool whole) {
+                                                           unsigned long long* ctr, bool whole, AggCount cn) {
     __shared__ uint64_t lkey[kPartSlots];
     __shared__ uint32_t lcnt[kPartSlots];
     const uint64_t p = blockIdx.x;
     const uint64_t parts = gridDim.x;
     const PartLists<kBinRep> L(bin2 + p * kBinRep * cap2, cap2, cursor2 + p, parts, cap2);
-    if (L.total == 0 && !whole) return;  // uniform across the workgroup
+    if (L.total == 0 && !whole && !cn.partials) return;  // uniform across the workgroup
     uint32_t fresh = 0;
     aggregate_partition(L, tab + (p << kPartLog2), !whole && ctr[C_TABLE_KEYS] != 0, lkey, lcnt, sp, ctr, fresh,
-                        whole);
+                        whole, whole || L.total != 0);
     add_fresh(ctr, fresh);
+    if (cn.partials) {
+        // the slice in LDS is final: each thread counts the slots it wrote
+        constexpr int PER = (int)kPartSlots / AGG_THREADS;
+        uint32_t sig = 0;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const uint32_t sl = u * AGG_THREADS + threadIdx.x;
+            sig += lkey[sl] != kEmptyKey && lcnt[sl] >= cn.tau;
+        }
+        // (the occupied slots and their sum are totalled by the scatter pass:
+        // one atomic per workgroup here would meet on two words 2^16 times)
+        block_count_add32(cn.partials + (p >> cn.blk_shift), sig);
+    }
 }
 
 // ---- framed binned contraction (two-dimensional tables with a key frame) -----
@@ -2050,16 +2081,20 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_threshold_count(const Slot* ta
     }
 }
 
-template <bool SQUARE>
-__global__ __launch_bounds__(SCAN_THREADS) void k_threshold_scatter(Slot* tab, JobView jv, const uint32_t* offsets,
+// TOTALS (one job whose final update did the counting pass): the occupied
+// slots and their count sum go to ctr[C_DISTINCT] and ctr[C_SUM] here.
+template <bool SQUARE, bool TOTALS = false>
+__global__ __launch_bounds__(SCAN_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_threshold_scatter(Slot* tab, JobView jv, const uint32_t* offsets,
                                                                     uint64_t* s_key, uint32_t* s_count,
-                                                                    uint32_t* size) {
+                                                                    uint32_t* size, unsigned long long* ctr) {
     __shared__ TileScratch ts;
+    __shared__ unsigned long long red[SCAN_WAVES];
     const uint64_t N = jv.dims->slots;
     const bool multi = jv.part_job != nullptr;
     uint64_t lo, hi;
     block_range(N, lo, hi);
     uint64_t run = offsets[blockIdx.x];
+    uint32_t occ = 0, sum = 0;  // (a table holds fewer than 2^32 points)
     for (uint64_t t0 = lo; t0 < hi; t0 += SCAN_TILE) {
         const uint32_t job = job_of_slot(jv, multi, t0);
         const uint32_t tau = jv.jobs[job].tau;
@@ -2070,8 +2105,13 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_threshold_scatter(Slot* tab, J
         load_slots(tab, t0, hi, key, cnt);
         if (SQUARE) load_square_marks(tab, t0, hi, mark);
 #pragma unroll
-        for (int j = 0; j < SCAN_ITEMS; ++j)
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
             if (key[j] != kEmptyKey && (cnt[j] >= tau || mark[j])) bits |= 1u << j;
+            if (TOTALS && key[j] != kEmptyKey) {
+                occ += 1;
+                sum += cnt[j];
+            }
+        }
         uint32_t pos[SCAN_ITEMS];
         const uint32_t total = tile_positions(bits, pos, ts);
 #pragma unroll
@@ -2089,6 +2129,14 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_threshold_scatter(Slot* tab, J
                // slots that become significant here)
         }
         run += total;
+    }
+    if (TOTALS) {
+        const unsigned long long o = block_sum((unsigned long long)occ, red);
+        const unsigned long long c = block_sum((unsigned long long)sum, red);
+        if (threadIdx.x == 0) {
+            if (o) atomicAdd(&ctr[C_DISTINCT], o);
+            if (c) atomicAdd(&ctr[C_SUM], c);
+        }
     }
 }
 
@@ -3732,13 +3780,17 @@ hipError_t launch_bin_keys(const uint64_t* bin1, uint64_t cap1, const uint32_t* 
 
 hipError_t launch_aggregate(const uint64_t* bin2, uint64_t cap2, const uint32_t* cursor2, uint32_t* cursor1,
                             Slot* tab, uint64_t cap, SpillBuf spill, unsigned long long* ctr, hipStream_t stream,
-                            const KernelSpan& span, bool whole) {
+                            const KernelSpan& span, bool whole, const AggCount& count) {
     const Geo g = make_geo(cap);  // the update only needs the partition count
     if (!binned_geometry(g)) return hipErrorInvalidValue;
+    if (count.partials && count.blk_shift != scan_block_shift(cap)) return hipErrorInvalidValue;
     const uint64_t parts = 1ull << g.p_log2;
     hipLaunchKernelGGL(k_snapshot_keys, dim3(1), dim3(64), 0, stream, ctr);
+    if (count.partials)
+        hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(kScanBlocks, 256, 64)), dim3(256), 0, stream, count.partials,
+                           (uint64_t)kScanBlocks);
     launch_k(k_aggregate, dim3((unsigned)parts), dim3(AGG_THREADS), 0u, stream, span, bin2, cap2, cursor2, tab, spill,
-             ctr, whole);
+             ctr, whole, count);
     hipLaunchKernelGGL(k_zero_u32, dim3(4), dim3(256), 0, stream, cursor1, (uint64_t)kBinRep * kCoarse);
     return hipGetLastError();
 }
@@ -3858,22 +3910,39 @@ hipError_t launch_export_tiles(const Slot* tab, uint64_t tcap, uint64_t* keys, u
     return hipGetLastError();
 }
 
+// Scan block of a partition for tables of 4096 * 2^k slots: block_range gives
+// every block max(cap / kScanBlocks, 4096) slots, whole partitions.
+uint32_t scan_block_shift(uint64_t cap) {
+    const uint64_t parts = std::max<uint64_t>(cap >> kPartLog2, 1);
+    uint32_t p_log2 = 0, s_log2 = 0;
+    while ((1ull << p_log2) < parts) ++p_log2;
+    while ((1ull << s_log2) < (uint64_t)kScanBlocks) ++s_log2;
+    return p_log2 > s_log2 ? p_log2 - s_log2 : 0;
+}
+
 hipError_t launch_threshold(Slot* tab, const JobView& jv, uint64_t* s_key, uint32_t* s_count, uint32_t* size,
-                            uint32_t* partials, unsigned long long* ctr, hipStream_t stream, uint64_t square_cap) {
+                            uint32_t* partials, unsigned long long* ctr, hipStream_t stream, uint64_t square_cap,
+                            bool counted) {
+    if (counted && square_cap) return hipErrorInvalidValue;  // the 2x2 marks change significance after the update
     if (square_cap) {
         const int grid = grid_for((square_cap + kPartSlots - 1) >> kPartLog2, 1, 8192);
         hipLaunchKernelGGL(k_square_part, dim3(grid), dim3(SQUARE_THREADS), 0, stream, tab, jv);
         hipLaunchKernelGGL(k_threshold_count<true>, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, tab, jv,
                            partials, ctr);
         hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, stream, partials, ctr + C_SIGNIFICANT);
-        hipLaunchKernelGGL(k_threshold_scatter<true>, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, tab, jv,
-                           partials, s_key, s_count, size);
+        hipLaunchKernelGGL((k_threshold_scatter<true, false>), dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, tab,
+                           jv, partials, s_key, s_count, size, ctr);
     } else {
-        hipLaunchKernelGGL(k_threshold_count<false>, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, tab, jv,
-                           partials, ctr);
+        if (!counted)
+            hipLaunchKernelGGL(k_threshold_count<false>, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, tab, jv,
+                               partials, ctr);
         hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, stream, partials, ctr + C_SIGNIFICANT);
-        hipLaunchKernelGGL(k_threshold_scatter<false>, dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream, tab, jv,
-                           partials, s_key, s_count, size);
+        if (counted)
+            hipLaunchKernelGGL((k_threshold_scatter<false, true>), dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream,
+                               tab, jv, partials, s_key, s_count, size, ctr);
+        else
+            hipLaunchKernelGGL((k_threshold_scatter<false, false>), dim3(kScanBlocks), dim3(SCAN_THREADS), 0, stream,
+                               tab, jv, partials, s_key, s_count, size, ctr);
     }
     return hipGetLastError();
 }

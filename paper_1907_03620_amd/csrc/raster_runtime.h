@@ -113,6 +113,9 @@ struct TableRun {
     uint32_t* c_ptot = nullptr;
     uint64_t c_words_cap = 0;  // table size the census buffers are sized for
     uint64_t census_cap = 0;
+    // an unframed table's final update counted its significant slots per
+    // scan block into `partials` (valid while counted_cap == cap)
+    uint64_t counted_cap = 0;
     // slice image written by the final update instead of the table (the
     // table is stale while image_cap == cap)
     uint2* img = nullptr;
@@ -202,7 +205,7 @@ struct TableRun {
     raster_status pull_counters();
     raster_status grow(uint64_t new_cap, uint64_t pending, int src);
     raster_status settle();
-    raster_status flush(bool census = false);
+    raster_status flush(bool census = false, bool count = false);
     raster_status ensure_census(uint64_t c);
     raster_status ensure_bins(uint64_t want_points);
     raster_status mark_pending();
