@@ -782,7 +782,8 @@ raster_status TableRun::ensure_census(uint64_t c) {
     c_ptot = nullptr;
     c_words_cap = 0;
     HIP_TRY(bufs.take((void**)&c_words, census_words(c) * sizeof(uint32_t)), "census");
-    HIP_TRY(bufs.take((void**)&c_ptot, (c >> kPartLog2) * sizeof(uint32_t)), "census totals");
+    // per partition: significant slots, occupied slots, count sum
+    HIP_TRY(bufs.take((void**)&c_ptot, 3 * (c >> kPartLog2) * sizeof(uint32_t)), "census totals");
     c_words_cap = c;
     if (img) bufs.give_back(img);
     img = nullptr;

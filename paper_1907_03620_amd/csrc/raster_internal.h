@@ -267,13 +267,6 @@ hipError_t launch_bin_keys_framed(const uint32_t* bin1, uint64_t cap1, const uin
                                  uint64_t cap2, uint32_t* cursor2, Slot* tab, uint64_t cap, Frame frame,
                                  SpillBuf spill, unsigned long long* ctr, hipStream_t stream,
                                  const KernelSpan& span = KernelSpan{});
-// Census of the final update (rec null: none): with the table's final
-// slices in LDS, the update of a table of 512+ partitions also writes the
-// census records of every partition (counts before each 32 slots within the
-// partition; rec: 2 words per 32 slots), each partition's significant count
-// (ptotal), and the occupied slots and count sum (ctr[C_DISTINCT],
-// ctr[C_SUM], cleared first).  launch_census_offsets then makes the counts
-// global, as launch_census leaves them.
 // The final update of an unframed table can do the significance scan's
 // counting pass: each workgroup adds its partition's slots with count >= tau
 // to partials[p >> blk_shift] (the scan block holding the partition: blocks
@@ -286,6 +279,14 @@ struct AggCount {
 };
 uint32_t scan_block_shift(uint64_t cap);
 
+// Census of the final update (rec null: none): with the table's final
+// slices in LDS, the update of a table of 512+ partitions also writes the
+// census records of every partition (counts before each 32 slots within the
+// partition; rec: 2 words per 32 slots) and, in ptotal (3 words per
+// partition), each partition's significant count, then its occupied slots,
+// then its count sum.  launch_census_offsets then makes the counts global, as
+// launch_census leaves them, and totals the occupied slots and counts in
+// ctr[C_DISTINCT] and ctr[C_SUM].
 struct AggCensus {
     uint2* rec = nullptr;
     uint32_t* ptotal = nullptr;

@@ -152,6 +152,20 @@ __device__ __forceinline__ void block_count_add64(unsigned long long* ctr, unsig
     }
 }
 
+// Sum of v over the workgroup, valid in thread 0.
+__device__ __forceinline__ uint32_t block_total32(uint32_t v) {
+    __shared__ uint32_t tot32[16];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane_id() == 0) tot32[w] = v;
+    __syncthreads();
+    uint32_t t = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)((blockDim.x + 63) >> 6); ++i) t += tot32[i];
+    return t;
+}
+
 // The same for a 32-bit word.
 __device__ __forceinline__ void block_count_add32(uint32_t* dst, uint32_t v) {
     __shared__ uint32_t part32[16];
@@ -1593,8 +1607,7 @@ __global__ __launch_bounds__(AGG_THREADS, 8) void k_aggregate_f32(const uint32_t
     __syncthreads();
     // the rings are free now: their first 512 bytes take the census bits
     uint64_t* wbits = reinterpret_cast<uint64_t*>(&A.ring[0][0]);
-    uint32_t occ = 0;
-    unsigned long long sum = 0;
+    uint32_t occ = 0, sum = 0;  // (a table holds fewer than 2^32 points)
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const uint32_t sl = u * AGG_THREADS + threadIdx.x;
@@ -1635,8 +1648,14 @@ __global__ __launch_bounds__(AGG_THREADS, 8) void k_aggregate_f32(const uint32_t
             r[1] = make_uint2((uint32_t)(b >> 32), inc - c + lo);
             if (threadIdx.x == 63) cen.ptotal[p] = inc;
         }
-        block_count_add(&ctr[C_DISTINCT], occ);
-        block_count_add64(&ctr[C_SUM], sum);
+        // the partition's occupied slots and count sum beside its total (one
+        // atomic per workgroup on two counter words would serialise): the
+        // scan of the totals adds them up
+        const uint32_t o = block_total32(occ), c = block_total32(sum);
+        if (threadIdx.x == 0) {
+            cen.ptotal[parts + p] = o;
+            cen.ptotal[2 * parts + p] = c;
+        }
     }
 }
 
@@ -2656,8 +2675,24 @@ __global__ __launch_bounds__(CENSUS_THREADS) void k_census_framed(const Slot* ta
 
 // Exclusive scan of n words in place by one workgroup of 1024 threads (each
 // takes a run of ceil(n / 1024)); the total goes to *total_out.
-__global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* v, uint32_t n, unsigned long long* total_out) {
+// With ctr, also the sums of stat[0, n) and stat[n, 2n) (a census's occupied
+// slots and count sums per partition) go to ctr[C_DISTINCT] and ctr[C_SUM].
+__global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* v, uint32_t n, unsigned long long* total_out,
+                                                   const uint32_t* stat, unsigned long long* ctr) {
     __shared__ uint32_t wsum[16];
+    if (ctr) {
+        uint32_t o = 0, c = 0;
+        for (uint32_t i = threadIdx.x; i < n; i += 1024) {
+            o += stat[i];
+            c += stat[n + i];
+        }
+        o = block_total32(o);
+        c = block_total32(c);
+        if (threadIdx.x == 0) {
+            ctr[C_DISTINCT] = o;
+            ctr[C_SUM] = c;
+        }
+    }
     const uint32_t per = (n + 1023) / 1024;
     const uint32_t lo = min(threadIdx.x * per, n), hi = min(lo + per, n);
     uint32_t local = 0;
@@ -4015,7 +4050,8 @@ hipError_t launch_census(Slot* tab, uint64_t cap, Frame frame, const JobView& jv
 hipError_t launch_census_offsets(uint64_t cap, uint32_t* words, uint32_t* ptotal, unsigned long long* ctr,
                                  hipStream_t stream) {
     const uint64_t parts = cap >> kPartLog2, nrec = cap >> kCensusRecLog2;
-    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, stream, ptotal, (uint32_t)parts, ctr + C_SIGNIFICANT);
+    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, stream, ptotal, (uint32_t)parts, ctr + C_SIGNIFICANT,
+                       ptotal + parts, ctr);
     hipLaunchKernelGGL(k_census_offsets, dim3(grid_for(nrec, 256, 4096)), dim3(256), 0, stream,
                        reinterpret_cast<uint2*>(words), nrec, ptotal, 0u);
     return hipGetLastError();
