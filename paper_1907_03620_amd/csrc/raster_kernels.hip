@@ -1034,7 +1034,7 @@ __global__ __launch_bounds__(AGG_THREADS, 6) void k_aggregate(const uint64_t* __
             sig += lkey[sl] != kEmptyKey && lcnt[sl] >= cn.tau;
         }
         // (the occupied slots and their sum are totalled by the scatter pass:
-        // one atomic per workgroup here would meet on two words 2^16 times)
+        // totalling them here as well made this kernel much slower)
         block_count_add32(cn.partials + (p >> cn.blk_shift), sig);
     }
 }
@@ -1648,9 +1648,9 @@ __global__ __launch_bounds__(AGG_THREADS, 8) void k_aggregate_f32(const uint32_t
             r[1] = make_uint2((uint32_t)(b >> 32), inc - c + lo);
             if (threadIdx.x == 63) cen.ptotal[p] = inc;
         }
-        // the partition's occupied slots and count sum beside its total (one
-        // atomic per workgroup on two counter words would serialise): the
-        // scan of the totals adds them up
+        // the partition's occupied slots and count sum beside its total: the
+        // scan of the totals adds them up (atomics per workgroup on two
+        // counter words made this kernel slower)
         const uint32_t o = block_total32(occ), c = block_total32(sum);
         if (threadIdx.x == 0) {
             cen.ptotal[parts + p] = o;
