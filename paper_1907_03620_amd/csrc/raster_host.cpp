@@ -796,8 +796,8 @@ raster_status TableRun::ensure_census(uint64_t c) {
 // Updates the table with the binned group.  With `census`, a final update
 // of a table of 512+ partitions also takes the census of the significant
 // slots (valid while the table keeps its size: census_cap); with `count`, a
-// final update of an unframed table does the significance scan's counting
-// pass (counted_cap).
+// final update without a census does the significance scan's counting pass
+// (counted_cap).
 raster_status TableRun::flush(bool census, bool count) {
     census_cap = 0;
     counted_cap = 0;
@@ -872,21 +872,22 @@ raster_status TableRun::flush(bool census, bool count) {
         // an update that writes the table back into a table not filled yet
         // writes whole slices, which fills it
         const bool whole = tab_unfilled && !cen.img;
+        // the threshold's counting pass, in an update without a census (the
+        // framed one with 4-byte claim words only: 512+ partitions)
+        AggCount cnt;
+        if (count && !cen.rec && (!frame.on || geo().p_log2 > kFrameCoarseLog2)) {
+            cnt.partials = partials;
+            cnt.tau = tau;
+            cnt.blk_shift = scan_block_shift(cap);
+            counted_cap = cap;
+        }
         if (frame.on)
             HIP_TRY(launch_aggregate_framed(reinterpret_cast<uint32_t*>(bin2), c2, cursor2, cursor1, tab, cap, frame,
-                                            sp, ctr, stream, t2, cen, whole),
+                                            sp, ctr, stream, t2, cen, whole, cnt),
                     "aggregate");
-        else {
-            AggCount cnt;
-            if (count) {
-                cnt.partials = partials;
-                cnt.tau = tau;
-                cnt.blk_shift = scan_block_shift(cap);
-                counted_cap = cap;
-            }
+        else
             HIP_TRY(launch_aggregate(bin2, c2, cursor2, cursor1, tab, cap, sp, ctr, stream, t2, whole, cnt),
                     "aggregate");
-        }
         if (whole) tab_unfilled = false;
         span_done(2, t2);
     }

@@ -267,10 +267,11 @@ hipError_t launch_bin_keys_framed(const uint32_t* bin1, uint64_t cap1, const uin
                                  uint64_t cap2, uint32_t* cursor2, Slot* tab, uint64_t cap, Frame frame,
                                  SpillBuf spill, unsigned long long* ctr, hipStream_t stream,
                                  const KernelSpan& span = KernelSpan{});
-// The final update of an unframed table can do the significance scan's
-// counting pass: each workgroup adds its partition's slots with count >= tau
-// to partials[p >> blk_shift] (the scan block holding the partition: blocks
-// are whole partitions for any table of 4096 * 2^k slots; cleared first).
+// The final update of an unframed table, or of a framed one of 512+
+// partitions without a census, can do the significance scan's counting
+// pass: each workgroup adds its partition's slots with count >= tau to
+// partials[p >> blk_shift] (the scan block holding the partition: blocks are
+// whole partitions for any table of 4096 * 2^k slots; cleared first).
 // The scatter pass then totals the occupied slots and their counts.
 struct AggCount {
     uint32_t* partials = nullptr;  // kScanBlocks words; null: no counting
@@ -302,7 +303,8 @@ struct AggCensus {
 hipError_t launch_aggregate_framed(const uint32_t* bin2, uint64_t cap2, const uint32_t* cursor2, uint32_t* cursor1,
                                   Slot* tab, uint64_t cap, Frame frame, SpillBuf spill, unsigned long long* ctr,
                                   hipStream_t stream, const KernelSpan& span = KernelSpan{},
-                                  const AggCensus& census = AggCensus{}, bool whole = false);
+                                  const AggCensus& census = AggCensus{}, bool whole = false,
+                                  const AggCount& count = AggCount{});
 hipError_t launch_census_offsets(uint64_t cap, uint32_t* words, uint32_t* ptotal, unsigned long long* ctr,
                                  hipStream_t stream);
 // Direct insertion of every entry held in the coarse lists (tables outside

@@ -1463,12 +1463,12 @@ struct FAggLds32 {
 __global__ __launch_bounds__(AGG_THREADS, 8) void k_aggregate_f32(const uint32_t* __restrict__ bin2, uint64_t cap2,
                                                                   const uint32_t* cursor2, Slot* tab, const Geo g,
                                                                   SpillBuf sp, unsigned long long* ctr,
-                                                                  AggCensus cen, bool whole) {
+                                                                  AggCensus cen, bool whole, AggCount cn) {
     __shared__ FAggLds32 A;
     const uint64_t p = blockIdx.x;
     const uint64_t parts = gridDim.x;
     const PartEntries<kBinRep> L(bin2 + p * kBinRep * cap2, cap2, cursor2 + p, parts, cap2);
-    if (L.total == 0 && !cen.rec && !whole) return;  // uniform across the workgroup
+    if (L.total == 0 && !cen.rec && !whole && !cn.partials) return;  // uniform across the workgroup
     const bool load = !whole && ctr[C_TABLE_KEYS] != 0;
     Slot* part = tab + (p << kPartLog2);
     const uint32_t fine = g.p_log2 - kFrameCoarseLog2;  // >= 1 here
@@ -1608,6 +1608,7 @@ __global__ __launch_bounds__(AGG_THREADS, 8) void k_aggregate_f32(const uint32_t
     // the rings are free now: their first 512 bytes take the census bits
     uint64_t* wbits = reinterpret_cast<uint64_t*>(&A.ring[0][0]);
     uint32_t occ = 0, sum = 0;  // (a table holds fewer than 2^32 points)
+    uint32_t sig = 0;           // significant slots, for the threshold's scan (cn)
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const uint32_t sl = u * AGG_THREADS + threadIdx.x;
@@ -1624,6 +1625,7 @@ __global__ __launch_bounds__(AGG_THREADS, 8) void k_aggregate_f32(const uint32_t
             v.aux = kNotSignificant;
             part[sl] = v;
         }
+        if (cn.partials) sig += e != kEmpty && c >= cn.tau;  // (keys outside the frame too)
         if (cen.rec) {
             // the wave's 64 slots u * AGG_THREADS + 64 w + lane form word 8 u + w
             occ += e != kEmpty;
@@ -1657,6 +1659,8 @@ __global__ __launch_bounds__(AGG_THREADS, 8) void k_aggregate_f32(const uint32_t
             cen.ptotal[2 * parts + p] = c;
         }
     }
+    // the threshold's counting pass (AggCount), as in k_aggregate
+    if (cn.partials) block_count_add32(cn.partials + (p >> cn.blk_shift), sig);
 }
 
 // Fallback: every entry held in the coarse lists goes straight to the table.
@@ -3908,17 +3912,24 @@ hipError_t launch_bin_keys_framed(const uint32_t* bin1, uint64_t cap1, const uin
 
 hipError_t launch_aggregate_framed(const uint32_t* bin2, uint64_t cap2, const uint32_t* cursor2, uint32_t* cursor1,
                                   Slot* tab, uint64_t cap, Frame frame, SpillBuf spill, unsigned long long* ctr,
-                                  hipStream_t stream, const KernelSpan& span, const AggCensus& census, bool whole) {
+                                  hipStream_t stream, const KernelSpan& span, const AggCensus& census, bool whole,
+                                  const AggCount& count) {
     const Geo g = make_geo(cap, false, frame);
     if (!framed_binned_geometry(g)) return hipErrorInvalidValue;
     if (census.rec && g.p_log2 <= kFrameCoarseLog2) return hipErrorInvalidValue;
     if (whole && census.img) return hipErrorInvalidValue;  // the image form does not write the table
+    // the counting pass: the 4-byte claim-word update only, and never with a census
+    if (count.partials && (census.rec || g.p_log2 <= kFrameCoarseLog2 || count.blk_shift != scan_block_shift(cap)))
+        return hipErrorInvalidValue;
     const uint64_t parts = 1ull << g.p_log2;
     hipLaunchKernelGGL(k_snapshot_keys, dim3(1), dim3(64), 0, stream, ctr);
     if (census.rec) (void)launch_zero_u64(reinterpret_cast<uint64_t*>(ctr) + C_DISTINCT, C_SUM - C_DISTINCT + 1, stream);
+    if (count.partials)
+        hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(kScanBlocks, 256, 64)), dim3(256), 0, stream, count.partials,
+                           (uint64_t)kScanBlocks);
     if (g.p_log2 > kFrameCoarseLog2)
         launch_k(k_aggregate_f32, dim3((unsigned)parts), dim3(AGG_THREADS), 0u, stream, span, bin2, cap2, cursor2, tab,
-                 g, spill, ctr, census, whole);
+                 g, spill, ctr, census, whole, count);
     else
         launch_k(k_aggregate_f, dim3((unsigned)parts), dim3(AGG_THREADS), 0u, stream, span, bin2, cap2, cursor2, tab, g,
                  spill, ctr, whole);
