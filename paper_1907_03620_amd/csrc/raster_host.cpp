@@ -1045,7 +1045,10 @@ raster_status TableRun::feed(const void* pts, int64_t n, raster_dtype dt) {
 
 raster_status TableRun::finish(raster_result** out) {
     const std::vector<NbrRound> rounds = neighbourhood_rounds(metric, delta, dims);
-    const bool census_path = dims == 2 && rounds.empty();
+    // (Manhattan distance 1 looks up two of the census link pass's four
+    // backward neighbours)
+    const bool manhattan1 = metric == RASTER_MANHATTAN && delta == 1;
+    const bool census_path = dims == 2 && (rounds.empty() || manhattan1);
     // a flush waits for the work before it itself; the final update takes
     // the census with it unless the 2x2 post-step changes significance after
     raster_status st = group_points > 0 ? flush(census_path && !square, !square) : settle();
@@ -1130,7 +1133,7 @@ raster_status TableRun::finish(raster_result** out) {
     if (e == hipSuccess)
         e = census ? launch_link_census(bin_tab(), use_img ? img : nullptr, cap, frame, mu, tau, square,
                                         c_words, s_key, s_count, parent, nbr,
-                                        size, m, ctr, stream)
+                                        size, m, ctr, stream, manhattan1)
                    : launch_agglomerate(tab, cap, jv, s_key, parent, nbr, size, m, ctr, stream, rounds.data(),
                                         (int)rounds.size(), dims == 3, frame);
     if (e == hipSuccess) e = hipEventRecord(ev[3], stream);

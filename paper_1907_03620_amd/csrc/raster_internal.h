@@ -379,13 +379,14 @@ hipError_t launch_agglomerate(const Slot* tab, uint64_t slots_max, const JobView
                               bool d3 = false, Frame frame = Frame{});
 
 // Framed single tables of at least 512 partitions (two dimensions, Chebyshev
-// distance 1) take the census path instead of launch_threshold and
+// or Manhattan distance 1) take the census path instead of launch_threshold and
 // launch_agglomerate: launch_census records which slots are significant
 // (words: census_words(cap) 32-bit words, 8-byte aligned; partials:
 // kScanBlocks words, scanned in place), fills ctr[C_DISTINCT], ctr[C_SUM]
 // and ctr[C_SIGNIFICANT], and with `square` runs the 2x2 post-step first.
 // launch_link_census then writes S_key, S_count and size[i] = 0 and leaves
-// the roots and sizes as launch_agglomerate does.
+// the roots and sizes as launch_agglomerate does (`manhattan`: the two
+// edge-sharing neighbours only).
 bool census_geometry(uint64_t cap, Frame frame);
 uint64_t census_words(uint64_t cap);
 hipError_t launch_census(Slot* tab, uint64_t cap, Frame frame, const JobView& jv, uint32_t tau, bool square,
@@ -395,7 +396,7 @@ hipError_t launch_image_to_table(const uint2* img, Slot* tab, uint64_t cap, Fram
 hipError_t launch_link_census(const Slot* tab, const uint2* img, uint64_t cap, Frame frame, uint32_t mu, uint32_t tau,
                               bool square, const uint32_t* words, uint64_t* s_key, uint32_t* s_count,
                               uint32_t* parent, uint32_t* nbr, uint32_t* size, uint64_t s_max,
-                              unsigned long long* ctr, hipStream_t stream);
+                              unsigned long long* ctr, hipStream_t stream, bool manhattan = false);
 
 // mu filter and output compaction: rows of kept components in compact order
 // (out_job gets each row's job for several jobs).

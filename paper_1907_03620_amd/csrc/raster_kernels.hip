@@ -2766,9 +2766,12 @@ __device__ __forceinline__ uint32_t census_index(uint2 r, uint64_t pos) {
 // the probes for neighbours inside the frame; keys outside the frame are
 // still found in the table.  A null table (never filled: every key went
 // through the binning into the image) holds no such keys.
+//
+// With manh (Manhattan distance 1) only the two backward neighbours that
+// share an edge with the tile are looked up, (-1, 0) and (0, -1).
 template <bool SQUARE, bool IMG>
 __global__ __launch_bounds__(LINK_THREADS, 6) void k_link_census(const Slot* tab, const uint2* img, const Geo g,
-                                                              uint32_t tau, const uint2* rec, uint64_t* s_key,
+                                                              uint32_t tau, bool manh, const uint2* rec, uint64_t* s_key,
                                                               uint32_t* s_count, uint32_t* size, uint32_t* parent,
                                                               uint32_t* nbr, unsigned long long* ctr) {
     __shared__ uint32_t lent[kPartSlots];
@@ -2862,11 +2865,11 @@ __global__ __launch_bounds__(LINK_THREADS, 6) void k_link_census(const Slot* tab
             uint64_t nk[4];
             bool want[4];
             nk[0] = ((uint64_t)(bx - 1) << 32) | (uint32_t)(by - 1);
-            want[0] = left && down;
+            want[0] = left && down && !manh;
             nk[1] = ((uint64_t)(bx - 1) << 32) | by;
             want[1] = left;
             nk[2] = ((uint64_t)(bx - 1) << 32) | (uint32_t)(by + 1);
-            want[2] = left && up;
+            want[2] = left && up && !manh;
             nk[3] = ((uint64_t)bx << 32) | (uint32_t)(by - 1);
             want[3] = down;
             // Loads for the neighbours in other partitions issued together:
@@ -4077,7 +4080,7 @@ hipError_t launch_image_to_table(const uint2* img, Slot* tab, uint64_t cap, Fram
 hipError_t launch_link_census(const Slot* tab, const uint2* img, uint64_t cap, Frame frame, uint32_t mu, uint32_t tau,
                               bool square, const uint32_t* words, uint64_t* s_key, uint32_t* s_count,
                               uint32_t* parent, uint32_t* nbr, uint32_t* size, uint64_t s_max,
-                              unsigned long long* ctr, hipStream_t stream) {
+                              unsigned long long* ctr, hipStream_t stream, bool manhattan) {
     const Geo g = make_geo(cap, false, frame);
     const uint2* rec = reinterpret_cast<const uint2*>(words);
     const int grid = (grid_for(s_max, 256, kPersistBlocks) + kXcds - 1) / kXcds * kXcds;
@@ -4085,13 +4088,13 @@ hipError_t launch_link_census(const Slot* tab, const uint2* img, uint64_t cap, F
     if (square && img) return hipErrorInvalidValue;  // the 2x2 marks are in the table only
     if (square)
         hipLaunchKernelGGL((k_link_census<true, false>), dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, img, g,
-                           tau, rec, s_key, s_count, size, parent, nbr, ctr);
+                           tau, manhattan, rec, s_key, s_count, size, parent, nbr, ctr);
     else if (img)
         hipLaunchKernelGGL((k_link_census<false, true>), dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, img, g,
-                           tau, rec, s_key, s_count, size, parent, nbr, ctr);
+                           tau, manhattan, rec, s_key, s_count, size, parent, nbr, ctr);
     else
         hipLaunchKernelGGL((k_link_census<false, false>), dim3(link_grid), dim3(LINK_THREADS), 0, stream, tab, img, g,
-                           tau, rec, s_key, s_count, size, parent, nbr, ctr);
+                           tau, manhattan, rec, s_key, s_count, size, parent, nbr, ctr);
     hipLaunchKernelGGL(k_jump, dim3(grid), dim3(256), 0, stream, parent, ctr);
     hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, stream, nbr, 1u, s_key, parent, ctr);
     // the neighbour lists are dead after the merge pass; their first s words

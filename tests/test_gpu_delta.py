@@ -236,3 +236,28 @@ def test_server_neighbourhood_per_job(raster, torch):
                                                  ctypes.byref(t)) == raster.E_INVAL
     finally:
         srv.close()
+
+
+@pytest.mark.parametrize("square", [False, True])
+def test_manhattan_1_census_tables(raster, torch, square):
+    """Manhattan distance 1 on framed tables of 512+ partitions takes the
+    census link pass with two of its four backward neighbours (the ones that
+    share an edge with the tile); with and without the 2x2 post-step, every
+    row must equal the oracle's (Section 3.2; Section 3.6 for the 2x2 step)."""
+    centres = synth.paper_scale_centres(3)
+    chunks = [synth.paper_scale_chunk(c, centres=centres, chunk=1_000_000) for c in range(5)]
+    ref = oracle.cluster_chunks(chunks, tau=4, mu=3, precision=2, metric="manhattan", delta=1, window=square)
+    for hint in (0, 2_000_000):
+        _say(f"manhattan 1 census tables, tile hint {hint}, square {square}")
+        raster.set_tuning(mode=2)
+        try:
+            st = raster.Stream(tau=4, mu=3, precision=2, tile_hint=hint, metric="manhattan", delta=1, square=square)
+            for c in chunks:
+                st.feed(dev(c, torch))
+            g = st.finish()
+            st.close()
+        finally:
+            raster.set_tuning(None)
+        assert g.stats["key_frame"] == 1
+        assert g.stats["table_capacity"] >= 1 << 21
+        assert_same(g, ref, f"manhattan 1, {g.stats['table_capacity']} slots, square {square}")
