@@ -2351,36 +2351,58 @@ __global__ __launch_bounds__(SQUARE_THREADS) void k_square_part(Slot* tab, JobVi
             const uint32_t u = list[t];
             const uint32_t bx = (uint32_t)(lkey[u] >> 32);
             const uint32_t by = (uint32_t)lkey[u];
+            // the eight surrounding tiles, q = 3 (dx + 1) + (dy + 1) without
+            // the centre: the home slots of those in other partitions are
+            // loaded together first (key and count in one 16-byte load), and
+            // only a key that is neither there nor an empty slot walks on
+            uint64_t nk[9], pos[9];
+            bool in[9], remote[9];
+            Slot hv[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const int64_t x = (int64_t)bx + (q / 3 - 1), y = (int64_t)by + (q % 3 - 1);
+                in[q] = q != 4 && x >= 2 && x <= 0xFFFFFFFEll && y >= 2 && y <= 0xFFFFFFFEll;
+                nk[q] = ((uint64_t)(uint32_t)x << 32) | (uint32_t)y;
+                pos[q] = in[q] ? home_slot(nk[q], g) : 0;
+                remote[q] = in[q] && (pos[q] >> kPartLog2) != jp;
+                if (remote[q]) hv[q] = jt[pos[q]];
+            }
             uint64_t c[3][3];  // counts of the tiles (bx + dx, by + dy), [dx + 1][dy + 1]
 #pragma unroll
-            for (int dx = -1; dx <= 1; ++dx)
-#pragma unroll
-                for (int dy = -1; dy <= 1; ++dy) {
-                    uint64_t n_cnt = 0;
-                    const int64_t x = (int64_t)bx + dx, y = (int64_t)by + dy;
-                    if (dx == 0 && dy == 0) {
-                        n_cnt = lcnt[u];
-                    } else if (x >= 2 && x <= 0xFFFFFFFEll && y >= 2 && y <= 0xFFFFFFFEll) {
-                        const uint64_t nk = ((uint64_t)(uint32_t)x << 32) | (uint32_t)y;
-                        const uint64_t pos = home_slot(nk, g);
-                        if ((pos >> kPartLog2) == jp) {
-                            uint32_t lp = (uint32_t)(pos - base);
-                            for (uint32_t step = 0; step < kMaxProbe; ++step) {
-                                const uint64_t cur = lkey[lp];
-                                if (cur == nk) {
-                                    n_cnt = lcnt[lp];
-                                    break;
-                                }
-                                if (cur == kEmptyKey) break;
-                                lp = (lp + 1) & (psize - 1);
+            for (int q = 0; q < 9; ++q) {
+                uint64_t n_cnt = 0;
+                if (q == 4) {
+                    n_cnt = lcnt[u];
+                } else if (in[q] && !remote[q]) {
+                    uint32_t lp = (uint32_t)(pos[q] - base);
+                    for (uint32_t step = 0; step < kMaxProbe; ++step) {
+                        const uint64_t cur = lkey[lp];
+                        if (cur == nk[q]) {
+                            n_cnt = lcnt[lp];
+                            break;
+                        }
+                        if (cur == kEmptyKey) break;
+                        lp = (lp + 1) & (psize - 1);
+                    }
+                } else if (remote[q]) {
+                    if (hv[q].key == nk[q]) {
+                        n_cnt = hv[q].count;
+                    } else if (hv[q].key != kEmptyKey) {
+                        // the rest of the probe sequence, as table_find walks it
+                        uint64_t at = pos[q];
+                        for (uint32_t step = 1; step < kMaxProbe; ++step) {
+                            at = next_slot(at, g);
+                            const Slot v = jt[at];
+                            if (v.key == nk[q]) {
+                                n_cnt = v.count;
+                                break;
                             }
-                        } else {
-                            const uint64_t at = table_find(jt, g, nk);
-                            if (at != ~0ull) n_cnt = jt[at].count;
+                            if (v.key == kEmptyKey) break;
                         }
                     }
-                    c[dx + 1][dy + 1] = n_cnt;
                 }
+                c[q / 3][q % 3] = n_cnt;
+            }
             bool keep = false;
 #pragma unroll
             for (int a = 0; a <= 1; ++a)
