@@ -2310,14 +2310,21 @@ __device__ __forceinline__ void uf_unite(uint32_t* parent, const uint64_t* key, 
 // does not matter.  In a batch each partition belongs to the job part_job
 // names, whose table starts at its slot_base.
 constexpr int SQUARE_THREADS = 512;
+constexpr uint32_t SQUARE_RING = 128;  // light slots queued per wave (at most 127 wait)
 
-__global__ __launch_bounds__(SQUARE_THREADS) void k_square_part(Slot* tab, JobView jv) {
+// The light tiles of a slice are queued in a ring of their wave's and
+// checked 64 at a time, one per lane (a slice-wide list would take 8 KB of
+// LDS and leave room for two workgroups per CU instead of three; six waves
+// per SIMD, so that three fit the registers too).
+__global__ __launch_bounds__(SQUARE_THREADS, 6) void k_square_part(Slot* tab, JobView jv) {
     __shared__ uint64_t lkey[kPartSlots];
     __shared__ uint32_t lcnt[kPartSlots];
-    __shared__ uint16_t list[kPartSlots];
-    __shared__ uint32_t nlist;
+    __shared__ uint16_t ring[SQUARE_THREADS / 64][SQUARE_RING];
     const bool multi = jv.part_job != nullptr;
     const uint64_t parts = multi ? jv.dims->slots >> kPartLog2 : (jv.jobs[0].cap + kPartSlots - 1) >> kPartLog2;
+    const uint32_t w = threadIdx.x >> 6, lane = lane_id();
+    const uint64_t lt = lanemask_lt();
+    uint16_t* rw = ring[w];
     for (uint64_t p = blockIdx.x; p < parts; p += gridDim.x) {
         // the partition's job: its table starts at slot_base (a whole number
         // of partitions), so job-local partition jp holds slots base.. of it
@@ -2328,27 +2335,15 @@ __global__ __launch_bounds__(SQUARE_THREADS) void k_square_part(Slot* tab, JobVi
         Slot* jt = tab + J.slot_base;
         const uint64_t jp = p - (J.slot_base >> kPartLog2);
         const uint64_t base = jp << kPartLog2;
-        if (threadIdx.x == 0) nlist = 0;
-        __syncthreads();
+        __syncthreads();  // the previous partition's slice is no longer read
         for (uint32_t u = threadIdx.x; u < psize; u += SQUARE_THREADS) {
             const Slot v = jt[base + u];
             lkey[u] = v.key;
             lcnt[u] = v.count;
         }
         __syncthreads();
-        for (uint32_t u0 = 0; u0 < psize; u0 += SQUARE_THREADS) {
-            const uint32_t u = u0 + threadIdx.x;
-            const bool light = u < psize && lkey[u] != kEmptyKey && lcnt[u] < tau;
-            const uint64_t b = __ballot(light);
-            uint32_t wbase = 0;
-            if (lane_id() == 0 && b) wbase = atomicAdd(&nlist, (uint32_t)__popcll(b));
-            wbase = __shfl(wbase, 0);
-            if (light) list[wbase + __popcll(b & lanemask_lt())] = (uint16_t)u;
-        }
-        __syncthreads();
-        const uint32_t nl = nlist;
-        for (uint32_t t = threadIdx.x; t < nl; t += SQUARE_THREADS) {
-            const uint32_t u = list[t];
+        // marks slot u when a 2x2 square holding its tile reaches tau
+        auto check = [&](uint32_t u) {
             const uint32_t bx = (uint32_t)(lkey[u] >> 32);
             const uint32_t by = (uint32_t)lkey[u];
             // the eight surrounding tiles, q = 3 (dx + 1) + (dy + 1) without
@@ -2410,8 +2405,25 @@ __global__ __launch_bounds__(SQUARE_THREADS) void k_square_part(Slot* tab, JobVi
                 for (int b = 0; b <= 1; ++b)
                     keep |= c[a][b] + c[a + 1][b] + c[a][b + 1] + c[a + 1][b + 1] >= (uint64_t)tau;
             if (keep) jt[base + u].aux = kSquareKeep;
+        };
+        // the wave's chunks of 64 slots, every eighth chunk of the slice
+        // (uniform across the wave, as are head and tail)
+        uint32_t head = 0, tail = 0;
+        for (uint32_t u0 = w * 64; u0 < psize; u0 += SQUARE_THREADS) {
+            const uint32_t u = u0 + lane;
+            const bool light = u < psize && lkey[u] != kEmptyKey && lcnt[u] < tau;
+            const uint64_t b = __ballot(light);
+            if (light) rw[(tail + (uint32_t)__popcll(b & lt)) & (SQUARE_RING - 1)] = (uint16_t)u;
+            tail += (uint32_t)__popcll(b);
+            if (tail - head >= 64) {
+                // the ring's entries are written by other lanes of this wave
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                check(rw[(head + lane) & (SQUARE_RING - 1)]);
+                head += 64;
+            }
         }
-        __syncthreads();  // the slice is overwritten by the next partition
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (tail != head && lane < tail - head) check(rw[(head + lane) & (SQUARE_RING - 1)]);
     }
 }
 
